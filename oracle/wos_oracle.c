@@ -1,0 +1,440 @@
+/*
+ * wos_oracle.c -- plain FP64 CPU reference of the walk-on-ellipsoids (WoE) Monte Carlo estimator
+ * of the discretised elliptic measure.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP path is compared against.
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header, table or constant generator with the
+ * HIP library: it is written from the paper and from the published Philox definition.
+ *
+ * What it computes (paper, Section 3 and Algorithm "MC-REM"):
+ *   For observation point x_i and walk k:
+ *     X_0 = x_i;  X_{n+1} = X_n + r(X_n) * S * U_n,  U_n uniform on the unit sphere,
+ *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
+ *   generality; the walk-on-ellipsoids chain, Section 3.2 eq. "wos chain"), and r(x) is the step
+ *   radius: r = dist(x, dD) ("WoE bound") or, for boxes, the largest r with x + r S B(0,1) inside D
+ *   ("mapped exact").  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
+ *   epsilon x"), tested before each step.  The stop point is projected onto dD and the element
+ *   that contains the projection receives one count (intrinsic Voronoi weights, Appendix
+ *   Ex. A.3; for equally spaced arcs this equals the extrinsic Voronoi cells of Ex. A.2).  So
+ *   counts[i, j] / N is the Monte Carlo estimate A_{omega, eps, N} of eq. "WoE_matrix_MC".
+ *
+ * Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = (seed_lo, seed_hi),
+ * counter = (block b, walk k, point i, instance).  The q-th FP64 uniform of a walk is the top 53
+ * bits of words (2(q&1), 2(q&1)+1) of block q>>1, u = m * 2^-53 + 2^-54.  In 2D step s uses
+ * uniform q = s (angle 2*pi*u); in 3D step s uses q = 2s (z = 1 - 2u) and q = 2s+1 (azimuth).
+ *
+ * Everything is FP64, compiled with -ffp-contract=off, no blocking or reordering beyond the
+ * definition.  Rows (points) are split over threads; results do not depend on the thread count.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OG_DISK 0
+#define OG_ANNULUS 1
+#define OG_ELLIPSE 2
+#define OG_POLYGON 3
+#define OG_BALL 4
+#define OG_BOX 5
+
+#define OG_TWO_PI 6.283185307179586
+
+typedef struct {
+    int32_t dim;
+    int32_t kind;
+    double p[8];          /* shape parameters, see the geometry table in the docs */
+    int32_t layout[4];    /* element layout */
+    const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise */
+    int32_t n_verts;
+} og_geom;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): ten rounds of two 32x32->64 multiplies and xors with a Weyl key.      */
+/* ------------------------------------------------------------------------------------------ */
+void oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* u in (0,1) from two 32-bit words: the top 53 bits of (hi:lo), centred in its 2^-53 cell. */
+double oracle_u53(uint32_t hi, uint32_t lo)
+{
+    uint64_t m = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+    return (double)m * (1.0 / 9007199254740992.0) + (1.0 / 18014398509481984.0);
+}
+
+/* The q-th uniform of walk (k, i) of instance inst. */
+static double walk_uniform(uint32_t q, uint32_t k, uint32_t i, uint32_t inst,
+                           uint32_t key0, uint32_t key1)
+{
+    uint32_t ctr[4] = { q >> 1, k, i, inst };
+    uint32_t key[2] = { key0, key1 };
+    uint32_t w[4];
+    oracle_philox(ctr, key, w);
+    if ((q & 1u) == 0) return oracle_u53(w[0], w[1]);
+    return oracle_u53(w[2], w[3]);
+}
+
+/* Uniform direction on S^{d-1} for step s (paper: U_n i.i.d. uniform on the unit sphere). */
+void oracle_direction(int dim, uint32_t s, uint32_t k, uint32_t i, uint32_t inst,
+                      uint32_t key0, uint32_t key1, double *U)
+{
+    if (dim == 2) {
+        double th = OG_TWO_PI * walk_uniform(s, k, i, inst, key0, key1);
+        U[0] = cos(th);
+        U[1] = sin(th);
+    } else {
+        /* Archimedes: z uniform on [-1,1] and an independent uniform azimuth. */
+        double z = 1.0 - 2.0 * walk_uniform(2u * s, k, i, inst, key0, key1);
+        double ph = OG_TWO_PI * walk_uniform(2u * s + 1u, k, i, inst, key0, key1);
+        double rho = sqrt((1.0 - z) * (1.0 + z));
+        U[0] = rho * cos(ph);
+        U[1] = rho * sin(ph);
+        U[2] = z;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Geometry: signed Euclidean distance to dD (positive inside), projection -> element index.     */
+/* ------------------------------------------------------------------------------------------ */
+static double seg_dist(const double *a, const double *b, const double *x, double *t_out)
+{
+    double ex = b[0] - a[0], ey = b[1] - a[1];
+    double wx = x[0] - a[0], wy = x[1] - a[1];
+    double ll = ex * ex + ey * ey;
+    double t = (wx * ex + wy * ey) / ll;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double dx = wx - t * ex, dy = wy - t * ey;
+    *t_out = t;
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* Lower bound of the distance to the ellipse (x/a)^2 + (y/b)^2 = 1 from the gauge
+ * f(x) = |diag(1/a,1/b) x|, which is Lipschitz with constant 1/min(a,b): dist >= min(a,b)(1-f). */
+static double ellipse_lb(const og_geom *g, const double *x)
+{
+    double u = (x[0] - g->p[0]) / g->p[2], v = (x[1] - g->p[1]) / g->p[3];
+    double f = sqrt(u * u + v * v);
+    double m = g->p[2] < g->p[3] ? g->p[2] : g->p[3];
+    return m * (1.0 - f);
+}
+
+double oracle_dist(const og_geom *g, const double *x)
+{
+    switch (g->kind) {
+    case OG_DISK: {
+        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
+        return g->p[2] - sqrt(dx * dx + dy * dy);
+    }
+    case OG_ANNULUS: {
+        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
+        double rho = sqrt(dx * dx + dy * dy);
+        double d_out = g->p[3] - rho, d_in = rho - g->p[2];
+        return d_out < d_in ? d_out : d_in;
+    }
+    case OG_ELLIPSE:
+        return ellipse_lb(g, x);
+    case OG_POLYGON: {
+        double best = INFINITY, t;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e;
+            const double *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            double d = seg_dist(a, b, x, &t);
+            if (d < best) best = d;
+        }
+        return best;
+    }
+    case OG_BALL: {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) s += (x[a] - g->p[a]) * (x[a] - g->p[a]);
+        return g->p[3] - sqrt(s);
+    }
+    case OG_BOX: {
+        int d = g->dim;
+        double best = INFINITY;
+        for (int a = 0; a < d; ++a) {
+            double lo = x[a] - g->p[a], hi = g->p[d + a] - x[a];
+            if (lo < best) best = lo;
+            if (hi < best) best = hi;
+        }
+        return best;
+    }
+    }
+    return -INFINITY;
+}
+
+static int clampi(long v, int n)
+{
+    if (v < 0) return 0;
+    if (v > n - 1) return n - 1;
+    return (int)v;
+}
+
+/* Arc index of angle theta (in (-pi, pi]) among M equal arcs counted from angle 0. */
+static int arc_index(double theta, int M)
+{
+    if (theta < 0.0) theta += OG_TWO_PI;
+    return clampi((long)floor(theta * (double)M / OG_TWO_PI), M);
+}
+
+/* Element index of the projection pi(x) of x onto dD (intrinsic Voronoi cells; ties go to the
+ * lowest index, matching the disjoint partition of the paper's Appendix). */
+int oracle_element(const og_geom *g, const double *x)
+{
+    switch (g->kind) {
+    case OG_DISK:
+        return arc_index(atan2(x[1] - g->p[1], x[0] - g->p[0]), g->layout[0]);
+    case OG_ANNULUS: {
+        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
+        double rho = sqrt(dx * dx + dy * dy);
+        double th = atan2(dy, dx);
+        if (g->p[3] - rho <= rho - g->p[2]) return arc_index(th, g->layout[0]);
+        return g->layout[0] + arc_index(th, g->layout[1]);
+    }
+    case OG_ELLIPSE: {
+        /* eccentric angle of the gauge projection x / f(x) */
+        double u = (x[0] - g->p[0]) / g->p[2], v = (x[1] - g->p[1]) / g->p[3];
+        return arc_index(atan2(v, u), g->layout[0]);
+    }
+    case OG_POLYGON: {
+        double best = INFINITY, tb = 0.0, t, perim = 0.0, s_at = 0.0;
+        int eb = 0;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e;
+            const double *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            double d = seg_dist(a, b, x, &t);
+            if (d < best) { best = d; eb = e; tb = t; }
+        }
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e;
+            const double *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            double len = sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]));
+            if (e == eb) s_at = perim + tb * len;
+            perim += len;
+        }
+        int M = g->layout[0];
+        return clampi((long)floor(s_at * (double)M / perim), M);
+    }
+    case OG_BALL: {
+        double v[3], s = 0.0;
+        for (int a = 0; a < 3; ++a) { v[a] = x[a] - g->p[a]; s += v[a] * v[a]; }
+        double n = sqrt(s);
+        int nz = g->layout[0], nphi = g->layout[1];
+        double zc = v[2] / n;
+        int iz = clampi((long)floor((1.0 - zc) * 0.5 * (double)nz), nz);
+        int ip = arc_index(atan2(v[1], v[0]), nphi);
+        return iz * nphi + ip;
+    }
+    case OG_BOX: {
+        int d = g->dim, n = g->layout[0];
+        double best = INFINITY;
+        int fb = 0;
+        for (int f = 0; f < 2 * d; ++f) {
+            int a = f / 2;
+            double df = (f % 2 == 0) ? x[a] - g->p[a] : g->p[d + a] - x[a];
+            if (df < best) { best = df; fb = f; }
+        }
+        int a = fb / 2, idx = 0;
+        for (int b = 0; b < d; ++b) {
+            if (b == a) continue;
+            double lo = g->p[b], hi = g->p[d + b];
+            int ib = clampi((long)floor((x[b] - lo) / (hi - lo) * (double)n), n);
+            idx = idx * n + ib;
+        }
+        int per_face = (d == 2) ? n : n * n;
+        return fb * per_face + idx;
+    }
+    }
+    return -1;
+}
+
+/* Step radius.  mode 0: r = dist (the ellipsoid x + r S B(0,1) lies in the Euclidean ball of
+ * radius r because |S| <= 1).  mode 1 (boxes): r = min over faces of (face distance)/|S e_a|,
+ * the largest r whose ellipsoid stays inside the box. */
+static double step_radius(const og_geom *g, int mode, const double *S, const double *x, double d)
+{
+    if (mode == 0) return d;
+    int dim = g->dim;
+    double best = INFINITY;
+    for (int a = 0; a < dim; ++a) {
+        double cn = 0.0;
+        for (int r = 0; r < dim; ++r) cn += S[r * 3 + a] * S[r * 3 + a];
+        cn = sqrt(cn);
+        double lo = (x[a] - g->p[a]) / cn, hi = (g->p[dim + a] - x[a]) / cn;
+        if (lo < best) best = lo;
+        if (hi < best) best = hi;
+    }
+    return best;
+}
+
+typedef struct {
+    const og_geom *g;
+    const double *S;
+    double eps;
+    int radius_mode;
+    uint32_t key0, key1, inst, max_steps;
+    const double *x_obs;
+    int32_t n_obs;
+    uint64_t wb, we;
+    uint32_t *counts;
+    int32_t *trace;
+    int n_elem;
+    int tid, nthr;
+    uint64_t stats[5]; /* walks, steps, max_steps_seen, cap_hits, escapes */
+} og_job;
+
+static void *run_rows(void *arg)
+{
+    og_job *J = (og_job *)arg;
+    const og_geom *g = J->g;
+    int dim = g->dim;
+    for (int i = J->tid; i < J->n_obs; i += J->nthr) {
+        for (uint64_t k = J->wb; k < J->we; ++k) {
+            double x[3] = { 0.0, 0.0, 0.0 }, U[3], y[3];
+            for (int a = 0; a < dim; ++a) x[a] = J->x_obs[(size_t)i * dim + a];
+            uint32_t s = 0;
+            int capped = 0;
+            double d;
+            for (;;) {
+                d = oracle_dist(g, x);
+                if (d <= J->eps) break;
+                if (s >= J->max_steps) { capped = 1; break; }
+                double r = step_radius(g, J->radius_mode, J->S, x, d);
+                oracle_direction(dim, s, (uint32_t)k, (uint32_t)i, J->inst, J->key0, J->key1, U);
+                for (int rr = 0; rr < dim; ++rr) {
+                    double acc = 0.0;
+                    for (int c = 0; c < dim; ++c) acc += J->S[rr * 3 + c] * U[c];
+                    y[rr] = acc;
+                }
+                for (int a = 0; a < dim; ++a) x[a] = x[a] + r * y[a];
+                s += 1;
+            }
+            int j = oracle_element(g, x);
+            J->counts[(size_t)i * J->n_elem + j] += 1u;
+            J->stats[0] += 1;
+            J->stats[1] += s;
+            if (s > J->stats[2]) J->stats[2] = s;
+            J->stats[3] += (uint64_t)capped;
+            J->stats[4] += (uint64_t)(d < 0.0);
+            if (J->trace) {
+                size_t t = ((size_t)i * (size_t)(J->we - J->wb) + (size_t)(k - J->wb)) * 2;
+                J->trace[t] = j;
+                J->trace[t + 1] = (int32_t)s;
+            }
+        }
+    }
+    return NULL;
+}
+
+/*
+ * Accumulates counts[i * n_elem + j] (row-major, caller-zeroed) for walks k in [walk_begin,
+ * walk_end) of every point.  S is the 3x3 row-major symmetric root of K/lambda_max (only the
+ * leading dim x dim block is read).  stats_out[5] = walks, steps, max steps, cap hits, escapes.
+ * trace (optional) receives (element, steps) per walk, row-major over (point, walk - walk_begin).
+ * Returns 0 on success, -1 on invalid arguments.
+ */
+int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, double eps,
+                         int radius_mode, uint32_t seed_lo, uint32_t seed_hi, uint32_t inst,
+                         uint32_t max_steps, const double *x_obs, int32_t n_obs,
+                         uint64_t walk_begin, uint64_t walk_end, uint32_t *counts,
+                         uint64_t *stats_out, int32_t *trace, int n_threads)
+{
+    if (!g || !S || !counts || n_obs < 0 || walk_end < walk_begin || eps <= 0.0) return -1;
+    if (radius_mode == 1 && g->kind != OG_BOX) return -1;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    og_job *jobs = (og_job *)calloc((size_t)n_threads, sizeof(og_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    for (int t = 0; t < n_threads; ++t) {
+        og_job *J = &jobs[t];
+        J->g = g; J->S = S; J->eps = eps; J->radius_mode = radius_mode;
+        J->key0 = seed_lo; J->key1 = seed_hi; J->inst = inst; J->max_steps = max_steps;
+        J->x_obs = x_obs; J->n_obs = n_obs; J->wb = walk_begin; J->we = walk_end;
+        J->counts = counts; J->trace = trace; J->n_elem = n_elem;
+        J->tid = t; J->nthr = n_threads;
+        pthread_create(&th[t], NULL, run_rows, J);
+    }
+    uint64_t st[5] = { 0, 0, 0, 0, 0 };
+    for (int t = 0; t < n_threads; ++t) {
+        pthread_join(th[t], NULL);
+        st[0] += jobs[t].stats[0];
+        st[1] += jobs[t].stats[1];
+        if (jobs[t].stats[2] > st[2]) st[2] = jobs[t].stats[2];
+        st[3] += jobs[t].stats[3];
+        st[4] += jobs[t].stats[4];
+    }
+    if (stats_out) memcpy(stats_out, st, sizeof(st));
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* Geometry probe for tests: distance and element of each of n points. */
+void oracle_geom_eval(const og_geom *g, const double *x, int32_t n, double *d_out, int32_t *e_out)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        const double *p = x + (size_t)i * g->dim;
+        if (d_out) d_out[i] = oracle_dist(g, p);
+        if (e_out) e_out[i] = oracle_element(g, p);
+    }
+}
+
+/* Direction probe for tests: U for steps s in [0, n) of walk (k, i, inst). */
+void oracle_directions(int dim, uint32_t n, uint32_t k, uint32_t i, uint32_t inst,
+                       uint32_t key0, uint32_t key1, double *U_out)
+{
+    for (uint32_t s = 0; s < n; ++s) oracle_direction(dim, s, k, i, inst, key0, key1, U_out + (size_t)s * dim);
+}
+
+/* Stop positions of walks k in [kb, ke) from point x0 (row index i of its instance): the chain of
+ * the estimator without the binning, for tests of E[u(X_{N_eps})] = u(x0) on K-harmonic u. */
+int oracle_walk_exits(const og_geom *g, const double *S, double eps, int radius_mode,
+                      uint32_t seed_lo, uint32_t seed_hi, uint32_t inst, uint32_t max_steps,
+                      const double *x0, uint32_t i, uint64_t kb, uint64_t ke, double *pos_out)
+{
+    if (!g || !S || !x0 || !pos_out || ke < kb || eps <= 0.0) return -1;
+    if (radius_mode == 1 && g->kind != OG_BOX) return -1;
+    int dim = g->dim;
+    for (uint64_t k = kb; k < ke; ++k) {
+        double x[3] = { 0.0, 0.0, 0.0 }, U[3], y[3];
+        for (int a = 0; a < dim; ++a) x[a] = x0[a];
+        uint32_t s = 0;
+        for (;;) {
+            double d = oracle_dist(g, x);
+            if (d <= eps || s >= max_steps) break;
+            double r = step_radius(g, radius_mode, S, x, d);
+            oracle_direction(dim, s, (uint32_t)k, i, inst, seed_lo, seed_hi, U);
+            for (int rr = 0; rr < dim; ++rr) {
+                double acc = 0.0;
+                for (int c = 0; c < dim; ++c) acc += S[rr * 3 + c] * U[c];
+                y[rr] = acc;
+            }
+            for (int a = 0; a < dim; ++a) x[a] = x[a] + r * y[a];
+            s += 1;
+        }
+        for (int a = 0; a < dim; ++a) pos_out[(size_t)(k - kb) * dim + a] = x[a];
+    }
+    return 0;
+}

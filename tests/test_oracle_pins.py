@@ -1,0 +1,407 @@
+"""Pins of the CPU oracle against facts fixed outside it: published known answers, closed forms
+from the paper's introduction, textbook special cases, brute force and exact invariants.
+
+Every check here would fail for a plausible slip in the oracle (wrong Philox round, wrong uniform
+conversion, a non-uniform direction, a wrong square root of K, a wrong distance or element index,
+a dropped count, an unnormalised K)."""
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import wos_inputs as wi
+from oracle import closed_forms as cf
+from oracle import walks
+from tests import statutil
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- Philox and uniforms
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        assert walks.philox(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_u53_range_and_resolution():
+    assert walks.u53(0, 0) == 2.0 ** -54
+    assert walks.u53(0, 1 << 11) == 2.0 ** -53 + 2.0 ** -54
+    # the low 11 bits are dropped
+    assert walks.u53(0x12345678, 0x9ABCDEF0) == walks.u53(0x12345678, 0x9ABCD800)
+    top = walks.u53(0xFFFFFFFF, 0xFFFFFFFF)
+    assert 1 - 2.0 ** -52 < top <= 1.0
+
+
+def test_philox_uniformity_chi2():
+    # 40 000 blocks, 160 000 words, top byte histogram
+    words = np.array([walks.philox((b, 7, 3, 1), (11, 22)) for b in range(40000)], np.uint64).ravel()
+    hist = np.bincount((words >> np.uint64(24)).astype(np.int64), minlength=256)
+    chi = ((hist - hist.mean()) ** 2 / hist.mean()).sum()
+    assert stats.chi2.sf(chi, 255) > 1e-4
+
+
+# ---------------------------------------------------------------- sphere sampler
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_direction_moments(dim):
+    n = 200_000
+    U = np.concatenate([walks.directions(dim, n // 4, k=k, i=5, inst=2, seed=9) for k in range(4)])
+    assert np.allclose(np.linalg.norm(U, axis=1), 1.0, atol=1e-15)
+    m = U.mean(0)
+    assert np.all(np.abs(m) < 5 * np.sqrt(1.0 / dim / n))
+    C = U.T @ U / n
+    # Var(U_a^2) <= 1, Var(U_a U_b) <= 1/4 ... use a generous 5-sigma bound
+    assert np.all(np.abs(C - np.eye(dim) / dim) < 5 * np.sqrt(0.5 / n))
+    if dim == 3:
+        assert stats.kstest((U[:, 2] + 1) / 2, "uniform").pvalue > 1e-4
+        ph = np.mod(np.arctan2(U[:, 1], U[:, 0]), 2 * np.pi) / (2 * np.pi)
+        assert stats.kstest(ph, "uniform").pvalue > 1e-4
+    else:
+        th = np.mod(np.arctan2(U[:, 1], U[:, 0]), 2 * np.pi) / (2 * np.pi)
+        assert stats.kstest(th, "uniform").pvalue > 1e-4
+
+
+# ---------------------------------------------------------------- geometry vs brute force
+
+def _boundary_samples(g, n):
+    """Dense boundary samples with their element index, built from the element definitions."""
+    M = g.n_elem
+    if g.kind == wi.DISK:
+        t = (np.arange(n) + 0.5) * 2 * np.pi / n
+        return np.stack([np.cos(t), np.sin(t)], 1) * g.params[2], (t * M / (2 * np.pi)).astype(int)
+    if g.kind == wi.ANNULUS:
+        mo, mi = g.layout
+        t = (np.arange(n) + 0.5) * 2 * np.pi / n
+        po = np.stack([np.cos(t), np.sin(t)], 1) * g.params[3]
+        pi_ = np.stack([np.cos(t), np.sin(t)], 1) * g.params[2]
+        return (np.concatenate([po, pi_]),
+                np.concatenate([(t * mo / (2 * np.pi)).astype(int), mo + (t * mi / (2 * np.pi)).astype(int)]))
+    if g.kind == wi.POLYGON:
+        v = np.asarray(g.verts)
+        seg = np.roll(v, -1, 0) - v
+        ln = np.sqrt((seg ** 2).sum(1))
+        cum = np.concatenate([[0], np.cumsum(ln)])
+        s = (np.arange(n) + 0.5) * cum[-1] / n
+        e = np.searchsorted(cum, s, side="right") - 1
+        p = v[e] + ((s - cum[e]) / ln[e])[:, None] * seg[e]
+        return p, (s * M / cum[-1]).astype(int)
+    if g.kind == wi.BOX:
+        d, nn = g.dim, g.layout[0]
+        m = int(round(n ** (1.0 / (d - 1))))
+        pts, el = [], []
+        for f in range(2 * d):
+            a, side = f // 2, f % 2
+            others = [b for b in range(d) if b != a]
+            grid = np.stack(np.meshgrid(*[(np.arange(m) + 0.5) / m] * (d - 1), indexing="ij"), -1).reshape(-1, d - 1)
+            p = np.zeros((grid.shape[0], d))
+            p[:, a] = float(side)
+            idx = np.zeros(grid.shape[0], int)
+            for c, b in enumerate(others):
+                p[:, b] = grid[:, c]
+                idx = idx * nn + (grid[:, c] * nn).astype(int)
+            pts.append(p)
+            el.append(f * nn ** (d - 1) + idx)
+        return np.concatenate(pts), np.concatenate(el)
+    if g.kind == wi.BALL:
+        nz, nphi = g.layout
+        m = int(np.sqrt(n))
+        z = 1 - 2 * (np.arange(m) + 0.5) / m
+        ph = (np.arange(2 * m) + 0.5) * np.pi / m
+        Z, P = np.meshgrid(z, ph, indexing="ij")
+        r = np.sqrt(1 - Z ** 2)
+        p = np.stack([r * np.cos(P), r * np.sin(P), Z], -1).reshape(-1, 3)
+        iz = ((1 - Z) / 2 * nz).astype(int).ravel()
+        ip = (P * nphi / (2 * np.pi)).astype(int).ravel()
+        return p, iz * nphi + ip
+    raise ValueError(g.kind)
+
+
+@pytest.mark.parametrize("case", ["disk", "annulus", "lshape", "square", "cube", "ball"])
+def test_distance_and_element_vs_brute_force(case):
+    rng = np.random.default_rng(1)
+    if case == "disk":
+        g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (37,))
+    elif case == "annulus":
+        g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.3, 1.0), (29, 13))
+    elif case == "lshape":
+        g = wi.Geometry(2, wi.POLYGON, (), (50,), verts=wi.L_SHAPE)
+    elif case == "square":
+        g = wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 1.0), (7,))
+    elif case == "cube":
+        g = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (5,))
+    else:
+        g = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (6, 11))
+    bp, be = _boundary_samples(g, 400_000 if g.dim == 2 else 360_000)
+    pts = wi.sample_points(g, 300, rng)
+    d, e = walks.geom_eval(g, pts)
+    spacing = 2e-5 if g.dim == 2 else 6e-3
+    for k in range(len(pts)):
+        dd = np.sqrt(((bp - pts[k]) ** 2).sum(1))
+        j = int(np.argmin(dd))
+        assert abs(d[k] - dd[j]) <= spacing, (k, d[k], dd[j])
+        # the element of the nearest boundary sample, unless the point is close to a cell edge
+        # or equidistant between two parts of the boundary
+        near = be[dd <= dd[j] + 2 * spacing]
+        assert e[k] in set(near.tolist()) or len(set(near.tolist())) > 1, (k, e[k], be[j])
+        assert e[k] == be[j] or len(set(near.tolist())) > 1
+
+
+def test_ellipse_lower_bound_and_angle():
+    g = wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.4), (40,))
+    rng = np.random.default_rng(2)
+    pts = wi.sample_points(g, 300, rng)
+    d, e = walks.geom_eval(g, pts)
+    t = (np.arange(400_000) + 0.5) * 2 * np.pi / 400_000
+    bp = np.stack([np.cos(t), 0.4 * np.sin(t)], 1)
+    for k in range(len(pts)):
+        exact = np.sqrt(((bp - pts[k]) ** 2).sum(1)).min()
+        assert d[k] <= exact + 1e-5
+        f = np.hypot(pts[k, 0], pts[k, 1] / 0.4)
+        assert exact <= (1 - f) / f * np.hypot(*pts[k]) / 1.0 + 1e-5  # radial point bound
+        ecc = np.mod(np.arctan2(pts[k, 1] / 0.4, pts[k, 0]), 2 * np.pi)
+        assert e[k] == min(int(ecc * 40 / (2 * np.pi)), 39)
+
+
+# ---------------------------------------------------------------- closed forms vs quadrature
+
+def test_disk_arc_closed_form_vs_quadrature_of_poisson_kernel():
+    rng = np.random.default_rng(3)
+    for _ in range(12):
+        rho, phi = rng.uniform(0, 0.95), rng.uniform(0, 2 * np.pi)
+        x = rho * np.array([np.cos(phi), np.sin(phi)])
+        a = rng.uniform(0, 2 * np.pi)
+        b = a + rng.uniform(0, 2 * np.pi)
+        f = lambda t: cf.disk_density(x, np.array([np.cos(t), np.sin(t)]))
+        ref = integrate.quad(f, a, b, limit=400, epsabs=1e-14, epsrel=1e-13)[0]
+        assert abs(cf.disk_arc_measure(x, 1.0, a, b) - ref) < 1e-11
+    # total mass 1 for any pole
+    H = cf.disk_H(np.array([[0.3, -0.2], [0.0, 0.9]]), 1.0, 16)
+    assert np.allclose(H.sum(1), 1.0, atol=1e-14)
+
+
+def test_ball_band_closed_form_vs_quadrature():
+    for a in (0.0, 0.37, 0.8):
+        x = np.array([0, 0, a])
+        for c in (-1.0, -0.3, 0.2, 0.8):
+            f = lambda z, ph: cf.ball_density(x, np.array([np.sqrt(1 - z * z) * np.cos(ph),
+                                                           np.sqrt(1 - z * z) * np.sin(ph), z]))
+            ref = integrate.dblquad(f, 0, 2 * np.pi, c, 1.0, epsabs=1e-12, epsrel=1e-12)[0]
+            assert abs(cf.ball_band_above(a, c) - ref) < 1e-9
+
+
+def test_annulus_series_mass_and_log_term():
+    for rho in (0.35, 0.6, 0.95):
+        m = cf.annulus_arc_measures(np.array([rho * np.cos(1.0), rho * np.sin(1.0)]), 0.3, 1.0, 40, 24)
+        assert abs(m.sum() - 1) < 1e-12
+        assert abs(m[40:].sum() - cf.annulus_inner_mass(rho, 0.3, 1.0)) < 1e-12
+        assert m.min() > 0
+    # as the hole shrinks the Fourier modes of the outer density tend to those of the disk
+    # Poisson kernel (the constant mode, the log capacity term, converges only logarithmically)
+    x = np.array([0.2, 0.5])
+    m = cf.annulus_arc_measures(x, 1e-12, 1.0, 32, 4)[:32]
+    h = cf.disk_H(x[None], 1.0, 32)[0]
+    assert np.allclose(m - m.mean(), h - h.mean(), atol=1e-12)
+
+
+# ---------------------------------------------------------------- the estimator vs closed forms
+
+def _bias_2d(P, eps):
+    """O(eps) shell bias allowance per entry: the one-sided mass within eps*log(1/eps) of each arc
+    end (mass moved between neighbouring elements by stopping inside the eps-shell)."""
+    return 4 * eps * (1 + np.log(1 / eps)) * np.maximum(P, 1e-3) * P.shape[1] / (2 * np.pi)
+
+
+def test_oracle_disk_matches_poisson_kernel():
+    inst = wi.cfg1_disk()
+    counts, st, _ = walks.build_instance(inst, threads=8)
+    assert np.all(counts.sum(1) == inst.n_walks)
+    assert st["cap_hits"] == 0 and st["escapes"] == 0
+    P = cf.disk_H(inst.x_obs, 1.0, 64)
+    rep = statutil.vs_probabilities(counts, inst.n_walks, P, bias=_bias_2d(P, inst.eps))
+    assert rep["ok"], rep
+    chi = statutil.row_chi2(counts, inst.n_walks, P)
+    assert chi["ok"], chi
+    # mean number of steps for a start at radius 1/2 (O(log 1/eps), Section 3.2)
+    assert 10 < st["steps"] / st["walks"] < 16
+
+
+def test_oracle_annulus_matches_series():
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.3, 1.0), (24, 12))
+    x = np.array([[0.45, 0.1], [-0.2, 0.7], [0.0, -0.93], [0.31, 0.0]])
+    N = 40_000
+    counts, st, _ = walks.build_measure(g, np.eye(2), x, 1e-4, seed=3, walk_end=N, threads=8)
+    P = np.stack([cf.annulus_arc_measures(p, 0.3, 1.0, 24, 12) for p in x])
+    rep = statutil.vs_probabilities(counts, N, P, bias=_bias_2d(P, 1e-4))
+    assert rep["ok"], rep
+    inner = counts[:, 24:].sum(1) / N
+    mass = cf.annulus_inner_mass(np.hypot(x[:, 0], x[:, 1]), 0.3, 1.0)
+    assert np.all(np.abs(inner - mass) < 4.5 * np.sqrt(mass * (1 - mass) / N) + 1e-3)
+
+
+def test_oracle_ball_matches_poisson_kernel():
+    g = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (8, 6))
+    a_list = [0.0, 0.35, -0.6]
+    x = np.array([[0.0, 0.0, a] for a in a_list])
+    N = 40_000
+    counts, st, _ = walks.build_measure(g, np.eye(3), x, 1e-4, seed=5, walk_end=N, threads=8)
+    P = []
+    for a in a_list:
+        cells = cf.ball_cells_axis(abs(a), 8, 6).reshape(8, 6)
+        if a < 0:  # pole below the equator: bands mirror
+            cells = cells[::-1]
+        P.append(cells.ravel())
+    P = np.array(P)
+    rep = statutil.vs_probabilities(counts, N, P, bias=4e-4)
+    assert rep["ok"], rep
+
+
+def _sol4(K):
+    """2D-sol4 of the paper (Section 4): K-harmonic for the paper's K = [[1, .3], [.3, .4]]."""
+    def u(p):
+        x1, x2 = p[:, 0], p[:, 1]
+        return ((2 * K[1, 0] - K[1, 1]) / (3 * K[0, 0]) * x1 ** 3 - x1 ** 2 * x2 + x1 * x2 ** 2
+                - (2 * K[0, 1] - K[0, 0]) / (3 * K[1, 1]) * x2 ** 3)
+    return u
+
+
+def _exit_mean_z(geom, S, x, u, n, grad_bound, eps=1e-4, radius_mode=0, seed=11):
+    """z-scores of mean u(X_stop) - u(x): E[u(Y_tau)] = u(x) for K-harmonic u (eq.
+    probabilisticrepresentation); stopping in the eps-shell moves the mean by at most eps*|grad u|."""
+    z = []
+    for i, p in enumerate(x):
+        pos = walks.walk_exits(geom, S, p, eps, n, i=i, seed=seed, radius_mode=radius_mode)
+        v = u(pos)
+        dev = abs(v.mean() - u(p[None])[0])
+        z.append(max(dev - eps * grad_bound, 0.0) / (v.std() / np.sqrt(n)))
+    return np.array(z)
+
+
+def test_walk_reproduces_paper_anisotropic_solution():
+    """The WoE chain with S = Khat^{1/2} reproduces the paper's K-harmonic 2D-sol4; the plausible
+    slip S = Khat (forgetting the square root) does not."""
+    K = np.array([[1.0, 0.3], [0.3, 0.4]])
+    u = _sol4(K)
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.5, 1.0), (8, 8))
+    x = wi.sample_points(g, 10, np.random.default_rng(7))
+    _, Khat, S = walks.instance_setup(K, 2)
+    z = _exit_mean_z(g, S, x, u, 40_000, grad_bound=3.0)
+    assert np.all(z < 4.5), z
+    Sw = np.zeros((3, 3))
+    Sw[:2, :2] = Khat
+    zw = _exit_mean_z(g, Sw, x, u, 40_000, grad_bound=3.0)
+    assert zw.max() > 8, zw
+
+
+def test_walk_reproduces_isotropic_paper_solutions():
+    """2D-sol2 and 2D-sol3 (K = I) of the paper on the ex01-like square with a hole replaced by the
+    L-shape polygon; and 3D-sol1 in the unit ball."""
+    sol2 = lambda p: -p[:, 0] ** 3 / 3 - p[:, 0] ** 2 * p[:, 1] + p[:, 0] * p[:, 1] ** 2 + p[:, 1] ** 3 / 3
+    sol3 = lambda p: p[:, 0] ** 2 - p[:, 1] ** 2
+    g = wi.Geometry(2, wi.POLYGON, (), (16,), verts=wi.L_SHAPE)
+    x = wi.sample_points(g, 6, np.random.default_rng(9))
+    _, _, S = walks.instance_setup(np.eye(2), 2)
+    for u in (sol2, sol3):
+        assert np.all(_exit_mean_z(g, S, x, u, 30_000, grad_bound=4.0) < 4.5)
+    sol1_3d = lambda p: p[:, 0] * p[:, 1] + p[:, 1] ** 2 - p[:, 2] ** 2
+    gb = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (4, 4))
+    xb = wi.sample_points(gb, 6, np.random.default_rng(10))
+    _, _, S3 = walks.instance_setup(np.eye(3), 3)
+    assert np.all(_exit_mean_z(gb, S3, xb, sol1_3d, 30_000, grad_bound=4.0) < 4.5)
+
+
+@pytest.mark.parametrize("radius_mode", [0, 1])
+def test_walk_reproduces_harmonic_in_anisotropic_cube(radius_mode):
+    import scipy.stats as st_
+    Q = st_.special_ortho_group.rvs(3, random_state=1)
+    K = Q @ np.diag([1.0, 3.0, 10.0]) @ Q.T
+    g = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (4,))
+    Kis = wi.spd_inv_sqrt(K)
+    def u(p):  # 3D-sol1 of the paper composed with y = K^{-1/2} x: K-harmonic
+        y = p @ Kis.T
+        return y[:, 0] * y[:, 1] + y[:, 1] ** 2 - y[:, 2] ** 2
+    x = wi.sample_points(g, 6, np.random.default_rng(8), margin=0.05)
+    _, _, S = walks.instance_setup(K, 3)
+    z = _exit_mean_z(g, S, x, u, 30_000, grad_bound=6.0, radius_mode=radius_mode)
+    assert np.all(z < 4.5), z
+
+
+def test_element_level_reproduction_fine_arcs():
+    """sum_j H_ij u(c_j) ~ u(x_i): the binned measure integrates the K-harmonic 2D-sol4 (midpoint
+    rule on 3000 arcs: second-order error, below 2e-4 here)."""
+    K = np.array([[1.0, 0.3], [0.3, 0.4]])
+    u = _sol4(K)
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.5, 1.0), (2000, 1000))
+    x = wi.sample_points(g, 8, np.random.default_rng(7))
+    N = 60_000
+    counts, st, _ = walks.build_measure(g, K, x, 1e-4, seed=11, walk_end=N, threads=8)
+    H = counts / N
+    ur = u(wi.element_ref_points(g))
+    est = H @ ur
+    se = np.sqrt(np.maximum(H @ ur ** 2 - est ** 2, 0) / N)
+    assert np.all(np.abs(est - u(x)) <= 4.5 * se + 2e-4 + 3e-4), (est - u(x), se)
+
+
+def test_mapped_exact_radius_same_law_fewer_steps():
+    inst0 = wi.cfg3_cube(n_walks=4000, precision=wi.FP64, radius_mode=wi.RADIUS_WOE_BOUND, stride=512)
+    inst1 = wi.cfg3_cube(n_walks=4000, precision=wi.FP64, radius_mode=wi.RADIUS_MAPPED_EXACT, stride=512)
+    inst1.seed = 99
+    c0, s0, _ = walks.build_instance(inst0, threads=8)
+    c1, s1, _ = walks.build_instance(inst1, threads=8)
+    assert s1["steps"] < 0.6 * s0["steps"]
+    # merge 4x4 patch blocks to keep expected counts testable
+    def merge(c):
+        return c.reshape(c.shape[0], 6, 6, 4, 6, 4).sum((3, 5)).reshape(c.shape[0], -1)
+    rep = statutil.two_sample(merge(c0), 4000, merge(c1), 4000)
+    assert rep["ok"], rep
+
+
+# ---------------------------------------------------------------- exact invariants
+
+def test_row_sums_threads_and_resume_exact():
+    inst = wi.cfg2_annulus(n_walks=600, n_obs=64)
+    a, sa, _ = walks.build_instance(inst, threads=1)
+    b, sb, _ = walks.build_instance(inst, threads=7)
+    assert np.array_equal(a, b) and sa == sb
+    assert np.all(a.sum(1) == 600)
+    c, _, _ = walks.build_instance(inst, walk_begin=0, walk_end=217, threads=3)
+    walks.build_instance(inst, walk_begin=217, walk_end=600, threads=5, counts=c)
+    assert np.array_equal(a, c)
+
+
+def test_scale_invariance_of_K_is_exact():
+    """Only Khat = K / lambda_max enters the walk (Section 3.2), so scaling K by a power of two
+    changes nothing, bit for bit."""
+    inst = wi.cfg2_annulus(n_walks=500, n_obs=48)
+    a, _, _ = walks.build_instance(inst, threads=8)
+    inst.K = inst.K * 4.0
+    b, _, _ = walks.build_instance(inst, threads=8)
+    assert np.array_equal(a, b)
+
+
+def test_step_cap_and_boundary_start():
+    inst = wi.cfg1_disk(n_walks=300)
+    inst.max_steps = 1
+    c, st, _ = walks.build_instance(inst, threads=4)
+    assert np.all(c.sum(1) == 300)
+    # every walk takes exactly one step; it is capped unless that step landed in the eps-shell
+    assert st["walks"] == 64 * 300 and st["steps"] == st["walks"]
+    assert 0.95 * st["walks"] < st["cap_hits"] < st["walks"]
+    # a start inside the eps-shell stops with zero steps in the element of its projection
+    g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (8,))
+    x = np.array([[np.cos(0.3) * (1 - 5e-5), np.sin(0.3) * (1 - 5e-5)]])
+    c, st, tr = walks.build_measure(g, np.eye(2), x, 1e-4, walk_end=50, trace=True)
+    assert c[0, 0] == 50 and st["steps"] == 0 and np.all(tr[0, :, 1] == 0)
+
+
+def test_empty_inputs():
+    g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (8,))
+    c, st, _ = walks.build_measure(g, np.eye(2), np.zeros((0, 2)), 1e-4, walk_end=10)
+    assert c.shape == (0, 8) and st["walks"] == 0
+    c, st, _ = walks.build_measure(g, np.eye(2), np.zeros((3, 2)), 1e-4, walk_begin=5, walk_end=5)
+    assert c.sum() == 0 and st["walks"] == 0

@@ -1,0 +1,426 @@
+"""Seeded synthetic inputs shared by the oracle, the tests, the smoke check and the benchmark.
+
+This module only *describes* problem instances: domain shapes, boundary element layouts, the
+Gamma_0 / Gamma_1 split, conductivity matrices, observation points, walk budgets and boundary
+data.  It contains none of the estimator's arithmetic (no walks, no distances used by a walk,
+no binning, no linear algebra of the reconstruction), so both the HIP path and the CPU oracle
+can take the very same instance from here without sharing any of the method.
+
+Geometry kinds (codes shared by the C ABI and the oracle):
+
+  DISK     params (cx, cy, R)                      layout (M,)            M arcs, counter-clockwise from angle 0
+  ANNULUS  params (cx, cy, R_in, R_out)            layout (M_out, M_in)   outer arcs first, then inner arcs
+  ELLIPSE  params (cx, cy, a, b)                   layout (M,)            equal steps of the eccentric angle
+  POLYGON  verts  (n, 2), one counter-clockwise loop  layout (M,)         equal pieces of perimeter
+  BALL     params (cx, cy, cz, R)                  layout (n_z, n_phi)    equal-area (z, phi) cells
+  BOX      params (lo_0..lo_{d-1}, hi_0..hi_{d-1}) layout (n,)            n^(d-1) patches per face
+
+The paper's problem statement (Section 2, the discrete inverse problem with interior data) fixes
+what an instance holds: the domain D, its boundary split into an accessible part Gamma_0 and an
+inaccessible part Gamma_1, a constant SPD conductivity K, interior points x^D, and data u^D, u^0.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX = 0, 1, 2, 3, 4, 5
+KIND_NAMES = {DISK: "disk", ANNULUS: "annulus", ELLIPSE: "ellipse", POLYGON: "polygon",
+              BALL: "ball", BOX: "box"}
+
+FP64 = 0
+FP32_GEOM_FP64_EXIT = 1
+RADIUS_WOE_BOUND = 0
+RADIUS_MAPPED_EXACT = 1
+
+
+@dataclasses.dataclass
+class Geometry:
+    dim: int
+    kind: int
+    params: tuple = ()
+    layout: tuple = ()
+    verts: Optional[np.ndarray] = None
+    gamma1_mask: Optional[np.ndarray] = None  # uint8, length n_elem, 1 = Gamma_1
+
+    @property
+    def n_elem(self) -> int:
+        return element_count(self.dim, self.kind, self.layout)
+
+
+@dataclasses.dataclass
+class Instance:
+    """One measure-building problem: geometry + conductivity + points + walk budget."""
+    geom: Geometry
+    K: np.ndarray            # (dim, dim) SPD, as given (not normalised)
+    x_obs: np.ndarray        # (n_obs, dim) float64
+    n_walks: int
+    eps: float = 1e-4
+    seed: int = 0
+    instance_id: int = 0
+    precision: int = FP64
+    radius_mode: int = RADIUS_WOE_BOUND
+    max_steps: int = 10000
+    name: str = ""
+    uD: Optional[np.ndarray] = None   # interior data at x_obs
+    u0: Optional[np.ndarray] = None   # Gamma_0 data, one value per Gamma_0 element (index order)
+    u_exact_g1: Optional[np.ndarray] = None  # exact data at Gamma_1 element reference points
+    noise_delta: float = 0.0          # expected norm of nu * noise(b), for the discrepancy principle
+
+
+def element_count(dim: int, kind: int, layout) -> int:
+    layout = tuple(int(v) for v in layout)
+    if kind in (DISK, ELLIPSE, POLYGON):
+        return layout[0]
+    if kind == ANNULUS:
+        return layout[0] + layout[1]
+    if kind == BALL:
+        return layout[0] * layout[1]
+    if kind == BOX:
+        return 2 * dim * layout[0] ** (dim - 1)
+    raise ValueError(f"unknown geometry kind {kind}")
+
+
+# --------------------------------------------------------------------------------------------
+# Element reference points (where boundary data is sampled).  These are input definitions: the
+# point of each element at which the data u^0 / exact u is given (arc mid-angle, patch centre).
+# --------------------------------------------------------------------------------------------
+
+def element_ref_points(g: Geometry) -> np.ndarray:
+    M = g.n_elem
+    if g.kind == DISK:
+        cx, cy, R = g.params
+        t = (np.arange(M) + 0.5) * 2 * np.pi / M
+        return np.stack([cx + R * np.cos(t), cy + R * np.sin(t)], 1)
+    if g.kind == ANNULUS:
+        cx, cy, r_in, r_out = g.params
+        pts = []
+        for R, m in ((r_out, g.layout[0]), (r_in, g.layout[1])):
+            t = (np.arange(m) + 0.5) * 2 * np.pi / m
+            pts.append(np.stack([cx + R * np.cos(t), cy + R * np.sin(t)], 1))
+        return np.concatenate(pts, 0)
+    if g.kind == ELLIPSE:
+        cx, cy, a, b = g.params
+        t = (np.arange(M) + 0.5) * 2 * np.pi / M
+        return np.stack([cx + a * np.cos(t), cy + b * np.sin(t)], 1)
+    if g.kind == POLYGON:
+        v = np.asarray(g.verts, float)
+        seg = np.roll(v, -1, 0) - v
+        ln = np.sqrt((seg ** 2).sum(1))
+        cum = np.concatenate([[0.0], np.cumsum(ln)])
+        L = cum[-1]
+        s = (np.arange(M) + 0.5) * L / M
+        e = np.searchsorted(cum, s, side="right") - 1
+        t = (s - cum[e]) / ln[e]
+        return v[e] + t[:, None] * seg[e]
+    if g.kind == BALL:
+        cx, cy, cz, R = g.params
+        nz, nphi = g.layout
+        iz, ip = np.meshgrid(np.arange(nz), np.arange(nphi), indexing="ij")
+        z = 1 - 2 * (iz.ravel() + 0.5) / nz
+        ph = (ip.ravel() + 0.5) * 2 * np.pi / nphi
+        rr = np.sqrt(1 - z * z)
+        return np.stack([cx + R * rr * np.cos(ph), cy + R * rr * np.sin(ph), cz + R * z], 1)
+    if g.kind == BOX:
+        d = g.dim
+        lo = np.array(g.params[:d], float)
+        hi = np.array(g.params[d:2 * d], float)
+        n = g.layout[0]
+        out = []
+        for f in range(2 * d):
+            a, side = f // 2, f % 2
+            others = [b for b in range(d) if b != a]
+            idx = np.stack(np.meshgrid(*[np.arange(n)] * (d - 1), indexing="ij"), -1).reshape(-1, d - 1)
+            p = np.zeros((idx.shape[0], d))
+            p[:, a] = hi[a] if side else lo[a]
+            for c, b in enumerate(others):
+                p[:, b] = lo[b] + (idx[:, c] + 0.5) * (hi[b] - lo[b]) / n
+            out.append(p)
+        return np.concatenate(out, 0)
+    raise ValueError(g.kind)
+
+
+# --------------------------------------------------------------------------------------------
+# Conductivity helpers for the *data* (not used by either estimator)
+# --------------------------------------------------------------------------------------------
+
+def spd_inv_sqrt(K: np.ndarray) -> np.ndarray:
+    w, Q = np.linalg.eigh(np.asarray(K, float))
+    return (Q / np.sqrt(w)) @ Q.T
+
+
+def random_rotation(d: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-random rotation (QR of a Gaussian matrix with sign fix, det = +1)."""
+    A = rng.standard_normal((d, d))
+    Q, R = np.linalg.qr(A)
+    Q = Q * np.sign(np.diag(R))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def harmonic_re_z3(x: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """u(x) = Re((y1 + i y2)^3) with y = K^{-1/2} x: harmonic for div(K grad u) = 0 in 2D."""
+    y = x @ spd_inv_sqrt(K).T
+    z = y[:, 0] + 1j * y[:, 1]
+    return np.real(z ** 3)
+
+
+def random_harmonic_poly(d: int, K: np.ndarray, degree: int, rng: np.random.Generator):
+    """u(x) = Re sum_k alpha_k (c_k . y)^k, y = K^{-1/2} x, c_k = a + i b with a ⟂ b, |a| = |b|.
+
+    c_k . c_k = 0 makes every term harmonic in y in any dimension, so u is K-harmonic in x."""
+    Kis = spd_inv_sqrt(K)
+    terms = []
+    for k in range(degree + 1):
+        a = rng.standard_normal(d)
+        a /= np.linalg.norm(a)
+        b = rng.standard_normal(d)
+        b -= (b @ a) * a
+        b /= np.linalg.norm(b)
+        terms.append((rng.standard_normal(), a + 1j * b, k))
+
+    def u(x):
+        y = np.asarray(x, float) @ Kis.T
+        acc = np.zeros(y.shape[0], complex)
+        for alpha, c, k in terms:
+            acc += alpha * (y @ c) ** k
+        return np.real(acc)
+    return u
+
+
+def add_noise(uD, u0, eta, rng):
+    """Additive i.i.d. Gaussian noise of std eta * max|u| over u^D and u^0."""
+    scale = eta * max(np.abs(uD).max(initial=0.0), np.abs(u0).max(initial=0.0))
+    return (uD + scale * rng.standard_normal(uD.shape),
+            u0 + scale * rng.standard_normal(u0.shape), scale)
+
+
+# --------------------------------------------------------------------------------------------
+# The five workloads
+# --------------------------------------------------------------------------------------------
+
+def cfg1_disk(n_walks: int = 10_000) -> Instance:
+    """2D unit disk, K = I, 64 equal arcs (Gamma_0 = upper half), 64 points on radius 0.5."""
+    M = 64
+    g = Geometry(2, DISK, (0.0, 0.0, 1.0), (M,))
+    g.gamma1_mask = (np.arange(M) >= M // 2).astype(np.uint8)
+    t = 2 * np.pi * np.arange(64) / 64
+    x = 0.5 * np.stack([np.cos(t), np.sin(t)], 1)
+    return Instance(g, np.eye(2), x, n_walks, eps=1e-4, seed=0, precision=FP64,
+                    name="disk64_K=I_64pts")
+
+
+def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP32_GEOM_FP64_EXIT,
+                 eta: float = 0.01) -> Instance:
+    """2D annulus r in [0.3, 1], K = [[1, .5], [.5, 2]], 128 + 128 arcs, 1024 points uniform by area.
+
+    Gamma_0 = outer arcs with angle in [0, pi); Gamma_1 = the rest.  Data u = Re(z^3) in mapped
+    coordinates y = K^{-1/2} x, with 1 % Gaussian noise."""
+    g = Geometry(2, ANNULUS, (0.0, 0.0, 0.3, 1.0), (128, 128))
+    mask = np.ones(256, np.uint8)
+    mask[:64] = 0
+    g.gamma1_mask = mask
+    rng = np.random.default_rng(0)
+    r = np.sqrt(rng.uniform(0.3 ** 2, 1.0, n_obs))
+    th = rng.uniform(0, 2 * np.pi, n_obs)
+    x = np.stack([r * np.cos(th), r * np.sin(th)], 1)
+    K = np.array([[1.0, 0.5], [0.5, 2.0]])
+    inst = Instance(g, K, x, n_walks, eps=1e-4, seed=0, precision=precision,
+                    name="annulus256_Kaniso_1024pts")
+    ref = element_ref_points(g)
+    u_ref = harmonic_re_z3(ref, K)
+    uD = harmonic_re_z3(x, K)
+    u0 = u_ref[mask == 0]
+    nrng = np.random.default_rng(12)
+    inst.uD, inst.u0, scale = add_noise(uD, u0, eta, nrng)
+    inst.u_exact_g1 = u_ref[mask == 1]
+    inst.noise_delta = scale  # ||nu * noise|| ~ scale when nu = 1/sqrt(M_D)
+    return inst
+
+
+def cfg3_cube(n_walks: int = 100_000, precision: int = FP32_GEOM_FP64_EXIT,
+              radius_mode: int = RADIUS_MAPPED_EXACT, stride: int = 1) -> Instance:
+    """[0,1]^3, K = Q diag(1,3,10) Q^T (Q Haar-random, seed 1), 24x24 patches per face,
+    Gamma_0 = faces {x=0, y=0, z=0}; 4096 points on the 16^3 interior grid."""
+    import scipy.stats as st
+    n = 24
+    g = Geometry(3, BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (n,))
+    M = 6 * n * n
+    face = np.arange(M) // (n * n)
+    g.gamma1_mask = (face % 2 == 1).astype(np.uint8)  # faces 0,2,4 are the lo faces -> Gamma_0
+    Q = st.special_ortho_group.rvs(3, random_state=1)
+    K = Q @ np.diag([1.0, 3.0, 10.0]) @ Q.T
+    k = (np.arange(16) + 0.5) / 16
+    X, Y, Z = np.meshgrid(k, k, k, indexing="ij")
+    x = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)[::stride].copy()
+    inst = Instance(g, K, x, n_walks, eps=1e-4, seed=0, precision=precision,
+                    radius_mode=radius_mode, name="cube3456_Kaniso_4096pts")
+    ref = element_ref_points(g)
+    rng = np.random.default_rng(3)
+    u = random_harmonic_poly(3, K, 3, rng)
+    inst.uD = u(x)
+    inst.u0 = u(ref)[g.gamma1_mask == 0]
+    inst.u_exact_g1 = u(ref)[g.gamma1_mask == 1]
+    return inst
+
+
+L_SHAPE = np.array([[0, 0], [1, 0], [1, 0.5], [0.5, 0.5], [0.5, 1], [0, 1]], float)
+
+
+def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
+    """Membership of candidate points in the open domain (used to draw points by rejection)."""
+    if g.kind == DISK:
+        cx, cy, R = g.params
+        return (p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 < R * R
+    if g.kind == ANNULUS:
+        cx, cy, ri, ro = g.params
+        r2 = (p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2
+        return (r2 < ro * ro) & (r2 > ri * ri)
+    if g.kind == ELLIPSE:
+        cx, cy, a, b = g.params
+        return ((p[:, 0] - cx) / a) ** 2 + ((p[:, 1] - cy) / b) ** 2 < 1
+    if g.kind == POLYGON:
+        v = np.asarray(g.verts)
+        ins = np.zeros(p.shape[0], bool)
+        for k in range(len(v)):
+            a, b = v[k], v[(k + 1) % len(v)]
+            cond = (a[1] > p[:, 1]) != (b[1] > p[:, 1])
+            xint = a[0] + (p[:, 1] - a[1]) * (b[0] - a[0]) / np.where(b[1] != a[1], b[1] - a[1], 1)
+            ins ^= cond & (p[:, 0] < xint)
+        return ins
+    if g.kind == BALL:
+        c = np.array(g.params[:3])
+        return ((p - c) ** 2).sum(1) < g.params[3] ** 2
+    if g.kind == BOX:
+        d = g.dim
+        lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])
+        return np.all((p > lo) & (p < hi), 1)
+    raise ValueError(g.kind)
+
+
+def _bbox(g: Geometry):
+    if g.kind == DISK:
+        cx, cy, R = g.params
+        return np.array([cx - R, cy - R]), np.array([cx + R, cy + R])
+    if g.kind == ANNULUS:
+        cx, cy, _, R = g.params
+        return np.array([cx - R, cy - R]), np.array([cx + R, cy + R])
+    if g.kind == ELLIPSE:
+        cx, cy, a, b = g.params
+        return np.array([cx - a, cy - b]), np.array([cx + a, cy + b])
+    if g.kind == POLYGON:
+        v = np.asarray(g.verts)
+        return v.min(0), v.max(0)
+    if g.kind == BALL:
+        c = np.array(g.params[:3])
+        return c - g.params[3], c + g.params[3]
+    d = g.dim
+    return np.array(g.params[:d]), np.array(g.params[d:2 * d])
+
+
+def sample_points(g: Geometry, n: int, rng: np.random.Generator, margin: float = 0.0) -> np.ndarray:
+    lo, hi = _bbox(g)
+    out = []
+    while sum(len(o) for o in out) < n:
+        p = rng.uniform(lo, hi, (max(2 * n, 64), g.dim))
+        ok = _inside(g, p)
+        if margin > 0:
+            for dlt in np.eye(g.dim) * margin:
+                ok &= _inside(g, p + dlt) & _inside(g, p - dlt)
+        out.append(p[ok])
+    return np.concatenate(out, 0)[:n].copy()
+
+
+def _layout_for(kind: int, dim: int, M_target: int):
+    if kind in (DISK, ELLIPSE, POLYGON):
+        return (M_target,)
+    if kind == ANNULUS:
+        return (M_target - M_target // 2, M_target // 2)
+    if kind == BALL:
+        nphi = max(4, int(round(math.sqrt(2 * M_target))))
+        nz = max(2, M_target // nphi)
+        return (nz, nphi)
+    if kind == BOX:
+        if dim == 2:
+            return (max(1, M_target // 4),)
+        return (max(1, int(round(math.sqrt(M_target / 6)))),)
+    raise ValueError(kind)
+
+
+def random_instance(rng: np.random.Generator, instance_id: int, kind_name: Optional[str] = None,
+                    walk_scale: float = 1.0, precision: int = FP32_GEOM_FP64_EXIT,
+                    data_degree: int = 6, eta: Optional[float] = None) -> Instance:
+    """One instance of the heterogeneous batch: disk, ellipse (1 x 0.4), L-shape, annulus (0.3, 1),
+    unit ball or unit cube; random SPD K with condition number in [1, 20] (lambda_max = 1);
+    points per instance in [32, 2048]; elements in [64, 2048]; walks log-uniform in [1e3, 1e5];
+    Gamma_0 = elements whose reference point's last coordinate is >= the domain centre's."""
+    kinds = ["disk", "ellipse", "lshape", "annulus", "ball", "cube"]
+    kn = kind_name or kinds[int(rng.integers(len(kinds)))]
+    if kn == "disk":
+        g = Geometry(2, DISK, (0.0, 0.0, 1.0))
+    elif kn == "ellipse":
+        g = Geometry(2, ELLIPSE, (0.0, 0.0, 1.0, 0.4))
+    elif kn == "lshape":
+        g = Geometry(2, POLYGON, (), verts=L_SHAPE.copy())
+    elif kn == "annulus":
+        g = Geometry(2, ANNULUS, (0.0, 0.0, 0.3, 1.0))
+    elif kn == "ball":
+        g = Geometry(3, BALL, (0.0, 0.0, 0.0, 1.0))
+    else:
+        g = Geometry(3, BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0))
+    d = g.dim
+    M_target = int(rng.integers(64, 2049))
+    g.layout = _layout_for(g.kind, d, M_target)
+    ref = element_ref_points(g)
+    lo, hi = _bbox(g)
+    centre = 0.5 * (lo + hi)
+    if g.kind == POLYGON:
+        centre = np.asarray(g.verts).mean(0)
+    g.gamma1_mask = (ref[:, -1] < centre[-1]).astype(np.uint8)
+    cond = rng.uniform(1.0, 20.0)
+    if d == 2:
+        lam = np.array([1.0, 1.0 / cond])
+    else:
+        mid = math.exp(rng.uniform(math.log(1.0 / cond), 0.0))
+        lam = np.array([1.0, mid, 1.0 / cond])
+    Q = random_rotation(d, rng)
+    K = Q @ np.diag(lam) @ Q.T
+    K = 0.5 * (K + K.T)
+    n_obs = int(rng.integers(32, 2049))
+    x = sample_points(g, n_obs, rng, margin=1e-3)
+    N = int(round(10 ** rng.uniform(3, 5) * walk_scale))
+    N = max(N, 1)
+    inst = Instance(g, K, x, N, eps=1e-4, seed=instance_id + 1000, instance_id=instance_id,
+                    precision=precision,
+                    radius_mode=RADIUS_MAPPED_EXACT if g.kind == BOX else RADIUS_WOE_BOUND,
+                    name=f"{kn}{g.n_elem}")
+    u = random_harmonic_poly(d, K, data_degree, rng)
+    uref = u(ref)
+    eta_v = rng.uniform(0.01, 0.05) if eta is None else eta
+    uD, u0, scale = add_noise(u(x), uref[g.gamma1_mask == 0], eta_v, rng)
+    inst.uD, inst.u0 = uD, u0
+    inst.u_exact_g1 = uref[g.gamma1_mask == 1]
+    inst.noise_delta = scale
+    return inst
+
+
+def cfg4_batch(n_instances: int = 64, seed: int = 4, walk_scale: float = 1.0,
+               precision: int = FP32_GEOM_FP64_EXIT) -> list:
+    rng = np.random.default_rng(seed)
+    return [random_instance(rng, i, walk_scale=walk_scale, precision=precision)
+            for i in range(n_instances)]
+
+
+def cfg5_arrivals(rate: float = 200.0, duration_s: float = 60.0, seed: int = 5):
+    """Poisson arrival times (seconds) of the serving stream."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            return np.array(out)
+        out.append(t)
