@@ -1,0 +1,287 @@
+/*
+ * wos.h -- C ABI of libwos: walk-on-ellipsoids Monte Carlo estimation of the discretised elliptic
+ * measure on one AMD Instinct MI355X (gfx950), and the FP64 truncated-SVD / Tikhonov reconstruction
+ * of the inaccessible boundary data that consumes it.
+ *
+ * The method is that of Cimpean, Grecu and Marin, "Numerical spectral analysis of Cauchy-type
+ * inverse problems: a probabilistic approach" (arXiv 2409.03686):
+ *   - the walk-on-ellipsoids chain X_{n+1} = X_n + dist(X_n, dD) K^{1/2} U_n with lambda_max(K) = 1
+ *     (Section 3.2, eq. "wos chain"), stopped at the first n with dist(X_n, dD) <= eps
+ *     (eq. "N epsilon x");
+ *   - the Monte Carlo matrix A_{omega,eps,N}[i, j] = (1/N) #{walks from x_i stopping in cell j}
+ *     (Section 3.3, eq. "WoE_matrix_MC" and its Voronoi counting form; Algorithm "MC-REM");
+ *   - the scaled direct operator B = diag(nu) A_{Gamma_1} diag(sigma)^{-1/2}, its SVD, and the
+ *     TSVD solution u_1 = diag(sigma)^{-1/2} B_r^+ diag(nu) b, b = u^D - A_{Gamma_0} u^0
+ *     (Sections 2.3 and 3.3, eqs. "SVD", "u1r", "tsvd solution simulations"; Algorithm "Main").
+ *
+ * Conventions common to every entry point
+ *   - Every function returns a wos_status.  On any status other than WOS_OK, wos_last_error()
+ *     returns a message for the calling thread.  Argument checks run on the host before any device
+ *     work, so WOS_EINVAL never leaves partial device work behind.
+ *   - "_dev" pointers are device (HBM) pointers on the context's device; "_host" pointers are host
+ *     memory.  The caller owns every buffer it passes in; the library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is enqueued on it and the
+ *     call returns without waiting, unless stated otherwise.
+ *   - Matrices are row-major unless stated otherwise.  Element (boundary cell) indices follow the
+ *     per-kind layout documented at wos_geometry.
+ *   - A context is used by one host thread at a time, except the wos_serve* entry points which
+ *     synchronise internally.
+ */
+#ifndef WOS_H
+#define WOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WOS_OK = 0,
+    WOS_EINVAL = 1,     /* invalid argument (nothing was enqueued) */
+    WOS_ENOMEM = 2,     /* device or host allocation failed, or the HBM budget is exceeded */
+    WOS_EDEVICE = 3,    /* a HIP call failed; the context is unusable afterwards */
+    WOS_EBUSY = 4,      /* the serving queue is full */
+    WOS_ETIMEOUT = 5,   /* a serving request exceeded its time limit */
+    WOS_ENOTSUP = 6,    /* valid request outside what this build supports */
+    WOS_ECANCELLED = 7  /* a serving request was cancelled */
+} wos_status;
+
+typedef struct wos_ctx wos_ctx;
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device memory the
+ * library itself allocates (scratch, SVD workspaces, serving slots); 0 = no bound. */
+wos_status wos_create(wos_ctx **out, int device, size_t hbm_budget_bytes);
+/* Waits for the context's own streams and frees everything it allocated. */
+wos_status wos_destroy(wos_ctx *ctx);
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char *wos_last_error(void);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Geometry                                                                                      */
+/* ------------------------------------------------------------------------------------------- */
+/* Domain kinds and their parameters (all coordinates in the original, unmapped frame):
+ *   WOS_DISK     dim 2, params (cx, cy, R),           layout (M)            M equal arcs, counter-
+ *                clockwise from angle 0; arc j = [2 pi j / M, 2 pi (j+1) / M).
+ *   WOS_ANNULUS  dim 2, params (cx, cy, R_in, R_out), layout (M_out, M_in)  outer arcs 0..M_out-1,
+ *                then inner arcs; a point is assigned to the nearer circle (ties: outer).
+ *   WOS_ELLIPSE  dim 2, params (cx, cy, a, b),        layout (M)            M equal steps of the
+ *                eccentric angle t of (cx + a cos t, cy + b sin t).  The walk uses the Lipschitz
+ *                lower bound min(a,b) (1 - f(x)) of the distance, f the ellipse gauge (the paper's
+ *                remark on Lipschitz replacements of dist), and cells by the eccentric angle.
+ *   WOS_POLYGON  dim 2, verts = one counter-clockwise loop of n_verts (x, y) pairs (host), layout
+ *                (M): M equal pieces of the perimeter, counted from vertex 0.
+ *   WOS_BALL     dim 3, params (cx, cy, cz, R),       layout (n_z, n_phi)   equal-area cells:
+ *                band iz over z from the top, sector iphi over the azimuth; j = iz n_phi + iphi.
+ *   WOS_BOX      dim 2 or 3, params (lo_0..lo_{d-1}, hi_0..hi_{d-1}), layout (n): faces in the
+ *                order (x=lo, x=hi, y=lo, y=hi[, z=lo, z=hi]), n^(d-1) patches each, patch
+ *                indices along the remaining axes in increasing axis order; j = f n^(d-1) + idx.
+ * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
+ * weights of the paper's appendix, Ex. A.3); ties go to the lowest face/segment index. */
+typedef enum {
+    WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5
+} wos_geom_kind;
+
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t kind;         /* wos_geom_kind */
+    double params[8];
+    int32_t layout[4];
+    const double *verts;  /* host; polygon only (copied during the call) */
+    int32_t n_verts;      /* 3..WOS_MAX_POLY_VERTS */
+} wos_geometry;
+
+#define WOS_MAX_POLY_VERTS 64
+#define WOS_MAX_ELEMENTS 16384  /* one LDS histogram row must fit in 64 KiB */
+
+/* Number of boundary cells M of a geometry. */
+wos_status wos_element_count(const wos_geometry *geom, int32_t *n_elem);
+/* sigma_host[M] = surface measure of each cell (the sigma(omega_j) of eq. "boundary_weights"). */
+wos_status wos_element_measures(const wos_geometry *geom, double *sigma_host);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Measure building (Algorithm MC-REM)                                                           */
+/* ------------------------------------------------------------------------------------------- */
+typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
+typedef enum { WOS_RADIUS_WOE_BOUND = 0, WOS_RADIUS_MAPPED_EXACT = 1 } wos_radius_mode;
+
+typedef struct {
+    double K[9];          /* conductivity, row-major, leading dim x dim block; symmetric positive
+                             definite; only K / lambda_max(K) enters the walk (Section 3.2) */
+    double eps;           /* stopping shell width, > 0 */
+    uint64_t walk_begin;  /* walks k in [walk_begin, walk_end) are run for every point; */
+    uint64_t walk_end;    /* walk_end <= 2^32.  Splitting a range and summing is bit-exact. */
+    uint64_t seed;        /* Philox key (low word, high word) */
+    uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
+    int32_t precision;    /* wos_precision */
+    int32_t radius_mode;  /* wos_radius_mode; MAPPED_EXACT only for WOS_BOX */
+    uint32_t max_steps;   /* step cap S_max (0 -> 10000); capped walks are binned where they are */
+} wos_walk_params;
+
+/* Random numbers: Philox4x32-10 (Salmon et al., SC'11), key (seed lo, seed hi), counter
+ * (block b, walk k, point i, instance).  FP64: the q-th uniform of a walk is the top 53 bits of
+ * words (2(q&1), 2(q&1)+1) of block q>>1, u = m 2^-53 + 2^-54; step s uses q = s in 2D (angle
+ * 2 pi u) and q = 2s, 2s+1 in 3D (z = 1 - 2u, azimuth 2 pi u).  FP32 geometry: the q-th uniform
+ * is the top 24 bits of word q&3 of block q>>2, u = m 2^-24 + 2^-25, same q per step. */
+
+/* Statistics words accumulated into stats_dev (uint64[WOS_STATS_WORDS]). */
+enum {
+    WOS_STAT_WALKS = 0, WOS_STAT_STEPS = 1, WOS_STAT_MAX_STEPS = 2, WOS_STAT_CAP_HITS = 3,
+    WOS_STAT_ESCAPES = 4, WOS_STAT_FP64_EVALS = 5, WOS_STAT_LANE_SLOTS = 6, WOS_STATS_WORDS = 8
+};
+
+/* Runs walks [walk_begin, walk_end) from each of the n_obs points and ACCUMULATES
+ *   counts_dev[i * M + j] += #{walks from point i stopping in cell j}
+ * (uint32, row-major n_obs x M, caller-zeroed), so sub-ranges, resumed runs and shards sum
+ * bit-exactly.  x_obs_dev: double[n_obs * dim] row-major.  stats_dev (optional): accumulated
+ * statistics (walks, sphere steps, max steps (a maximum), cap hits, escapes = stop points with a
+ * negative distance, FP64 shell evaluations, lane-step slots issued).  trace_dev (optional):
+ * int32[n_obs * (walk_end - walk_begin) * 2] receiving (cell, steps) of every walk, for tests.
+ * Points outside D stop with zero steps and count as escapes.  Every row sums to exactly
+ * walk_end - walk_begin.  Asynchronous on `stream`. */
+wos_status wos_build_measure(wos_ctx *ctx, const wos_geometry *geom, const wos_walk_params *walk,
+                             const double *x_obs_dev, int32_t n_obs, uint32_t *counts_dev,
+                             uint64_t *stats_dev, int32_t *trace_dev, void *stream);
+
+/* One instance of a batched build. */
+typedef struct {
+    wos_geometry geom;
+    wos_walk_params walk;
+    const double *x_obs_dev;
+    int32_t n_obs;
+    uint32_t *counts_dev;
+    uint64_t *stats_dev;   /* optional, per instance */
+    int32_t *trace_dev;    /* optional, per instance */
+} wos_measure_job;
+
+/* Builds the measures of n_jobs heterogeneous instances with persistent kernels that pull
+ * (instance, point, walk-chunk) work items from one global queue per (precision, dimension)
+ * group; results are identical to n_jobs separate wos_build_measure calls. */
+wos_status wos_build_measure_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs,
+                                   void *stream);
+
+/* Launch shape of the walk kernel: threads per block and walks per lane per work item. */
+typedef struct {
+    int32_t block;          /* 64, 128, 256, 512 or 1024 */
+    int32_t walks_per_lane; /* >= 1 */
+} wos_tuning;
+
+/* Sets the launch shape used for (dim, kind, precision) from now on (kind < 0: all kinds). */
+wos_status wos_set_tuning(wos_ctx *ctx, int32_t dim, int32_t kind, int32_t precision,
+                          const wos_tuning *t);
+/* Times every candidate launch shape on a walk sub-range of `job` (results discarded), stores the
+ * fastest for the job's (dim, kind, precision) and returns it.  Blocking. */
+wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uint64_t sample_walks,
+                        wos_tuning *best, void *stream);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Spectral step: B = diag(nu) (counts / N)[:, Gamma_1] diag(sigma_1)^{-1/2} = U diag(s) V^T      */
+/* ------------------------------------------------------------------------------------------- */
+typedef struct wos_svd_t wos_svd_t;
+
+/* Allocates the device workspace of an SVD of an n_obs x n_elem count matrix.  gamma1_mask_host
+ * (uint8[n_elem], 1 = Gamma_1), sigma_host (double[n_elem]) and nu_host (double[n_obs] or NULL
+ * for 1/sqrt(n_obs)) are copied.  Sizes: m = n_obs, n = |Gamma_1|, k = min(m, n). */
+wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem,
+                          const uint8_t *gamma1_mask_host, const double *sigma_host,
+                          const double *nu_host, wos_svd_t **out);
+wos_status wos_svd_destroy(wos_ctx *ctx, wos_svd_t *h);
+
+/* Assembles B from counts_dev (n_walks walks per row) and computes its thin SVD in FP64 on the
+ * device (one-sided Jacobi, Hestenes; paper eq. "SVD").  Results stay in the handle:
+ *   U: double[m * k] column-major, s: double[k] descending, V: double[n * k] column-major.
+ * s^2 are the eigenvalues of Lambda^nu = B B^T (the spectrum the paper studies). */
+wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts_dev, uint64_t n_walks,
+                   void *stream);
+/* Device pointers and sizes of the factors (valid until the handle is destroyed). */
+wos_status wos_svd_factors(const wos_svd_t *h, const double **U_dev, const double **s_dev,
+                           const double **V_dev, int32_t *m, int32_t *n, int32_t *k);
+/* Number of Jacobi sweeps of the last completed wos_svd and its error flag (0 = converged). */
+wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, void *stream);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Reconstruction (Algorithm Main)                                                               */
+/* ------------------------------------------------------------------------------------------- */
+typedef enum { WOS_TSVD_RANK = 0, WOS_TSVD_DISCREPANCY = 1, WOS_TIKHONOV = 2 } wos_reg;
+
+typedef struct {
+    int32_t kind;        /* wos_reg */
+    int32_t rank;        /* WOS_TSVD_RANK: truncation r (clamped to the numerical rank) */
+    double alpha;        /* WOS_TIKHONOV: alpha > 0, or 0 to choose it by the discrepancy rule */
+    double noise_delta;  /* discrepancy rules: expected |nu * noise(b)| */
+    double tau;          /* discrepancy rules: safety factor (e.g. 1.1) */
+} wos_reg_params;
+
+/* With q = diag(nu) (uD - (counts/N)[:, Gamma_0] u0) and the factors of h:
+ *   u1 = diag(sigma_1)^{-1/2} V diag(phi) U^T q,  phi_i = 1/s_i (i <= r, TSVD) or
+ *        s_i / (s_i^2 + alpha^2) (Tikhonov),
+ *   pred = (counts/N)[:, Gamma_1] u1 + (counts/N)[:, Gamma_0] u0   (data predicted at x^D).
+ * Discrepancy rules: r = smallest r with |q - B w_r| <= tau delta; alpha solves
+ * |q - B w_alpha| = tau delta.  uD_dev: double[m]; u0_dev: double[|Gamma_0|] in cell order (may be
+ * NULL when Gamma_0 is empty); u1_dev: double[n]; pred_dev (optional): double[m];
+ * rank_used_dev (optional, int32), alpha_used_dev (optional, double). */
+wos_status wos_reconstruct(wos_ctx *ctx, const wos_svd_t *h, const uint32_t *counts_dev,
+                           uint64_t n_walks, const double *uD_dev, const double *u0_dev,
+                           const wos_reg_params *reg, double *u1_dev, double *pred_dev,
+                           int32_t *rank_used_dev, double *alpha_used_dev, void *stream);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Captured pipeline: the whole path of one instance as one HIP graph                            */
+/* ------------------------------------------------------------------------------------------- */
+typedef struct wos_plan wos_plan;
+
+/* Records zero-fill of counts, the walk kernel(s), the SVD and the reconstruction of one
+ * instance into a HIP graph.  All pointers are captured and must stay valid while the plan
+ * lives; svd and the reconstruction arguments may be NULL for a measure-only plan. */
+wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, wos_svd_t *svd,
+                           const double *uD_dev, const double *u0_dev, const wos_reg_params *reg,
+                           double *u1_dev, double *pred_dev, int32_t *rank_used_dev,
+                           double *alpha_used_dev, wos_plan **out);
+wos_status wos_plan_launch(wos_plan *plan, void *stream);
+wos_status wos_plan_destroy(wos_plan *plan);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Serving: continuous batching of build + SVD + reconstruct requests                            */
+/* ------------------------------------------------------------------------------------------- */
+typedef struct {
+    wos_geometry geom;
+    wos_walk_params walk;          /* walk_begin/walk_end: the walk budget N = end - begin */
+    const double *x_obs_host;      /* double[n_obs * dim] */
+    int32_t n_obs;
+    const uint8_t *gamma1_mask_host;
+    const double *uD_host;         /* double[n_obs] */
+    const double *u0_host;         /* double[|Gamma_0|] */
+    wos_reg_params reg;
+    double arrival_s;              /* offset from the start of wos_serve (open-loop replay) */
+} wos_request;
+
+typedef struct {
+    double *u1_host;               /* caller-allocated double[|Gamma_1|] */
+    double *pred_host;             /* caller-allocated double[n_obs] or NULL */
+    double *s_host;                /* caller-allocated double[min(n_obs, |Gamma_1|)] or NULL */
+    int32_t rank_used;
+    double alpha_used;
+    int32_t status;                /* wos_status of this request */
+    double t_arrive, t_admit, t_done;  /* seconds since the start of wos_serve */
+    uint64_t walks, steps;
+} wos_result;
+
+typedef struct {
+    size_t hbm_budget_bytes;       /* admission bound on the device memory of in-flight requests */
+    int32_t max_inflight;          /* concurrent requests on the device (streams) */
+    double timeout_s;              /* per request, from arrival; 0 = none */
+} wos_serve_opts;
+
+/* Blocking driver: replays the requests at their arrival times (open loop), admits each when a
+ * slot and enough HBM budget are free, runs admitted requests concurrently on separate streams
+ * (their walk kernels overlap on the device), and fills results[i].  Returns WOS_OK if the loop
+ * ran; per-request status is in results[i].status. */
+wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n, wos_result *results,
+                     const wos_serve_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WOS_H */

@@ -32,7 +32,7 @@ def lib():
             C.POINTER(OgGeom), C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int,
             C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.c_int32,
             C.c_uint64, C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
-            C.POINTER(C.c_int32), C.c_int]
+            C.POINTER(C.c_int32), C.POINTER(C.c_uint32), C.c_int]
         L.oracle_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.oracle_u53.restype = C.c_double
         L.oracle_u53.argtypes = [C.c_uint32, C.c_uint32]
@@ -118,7 +118,7 @@ def element_measures(g) -> np.ndarray:
 
 
 def build_measure(geom, K, x_obs, eps, seed=0, instance_id=0, radius_mode=0, max_steps=10000,
-                  walk_begin=0, walk_end=1000, threads=None, trace=False, counts=None):
+                  walk_begin=0, walk_end=1000, threads=None, trace=False, counts=None, point_ids=None):
     """counts[i, j] = #{k in [walk_begin, walk_end): walk (i, k) stops in element j}.
 
     Returns (counts uint32 [n_obs, M], stats dict, trace or None)."""
@@ -134,11 +134,16 @@ def build_measure(geom, K, x_obs, eps, seed=0, instance_id=0, radius_mode=0, max
     st = np.zeros(5, np.uint64)
     tr = np.zeros((n_obs, walk_end - walk_begin, 2), np.int32) if trace else None
     nthr = threads or len(os.sched_getaffinity(0))
+    pid = None
+    if point_ids is not None:
+        pid = np.ascontiguousarray(np.asarray(point_ids, np.uint32))
+        assert pid.shape == (n_obs,)
     rc = L.oracle_build_measure(C.byref(g), M, _ptr(S, C.c_double), float(eps), int(radius_mode),
                                 seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF, int(instance_id),
                                 int(max_steps), _ptr(x, C.c_double), n_obs, int(walk_begin),
                                 int(walk_end), _ptr(counts, C.c_uint32), _ptr(st, C.c_uint64),
-                                _ptr(tr, C.c_int32) if trace else None, int(nthr))
+                                _ptr(tr, C.c_int32) if trace else None,
+                                _ptr(pid, C.c_uint32) if pid is not None else None, int(nthr))
     if rc != 0:
         raise ValueError("oracle_build_measure rejected its arguments")
     stats = dict(walks=int(st[0]), steps=int(st[1]), max_steps=int(st[2]), cap_hits=int(st[3]),

@@ -300,6 +300,7 @@ typedef struct {
     uint64_t wb, we;
     uint32_t *counts;
     int32_t *trace;
+    const uint32_t *point_ids;
     int n_elem;
     int tid, nthr;
     uint64_t stats[5]; /* walks, steps, max_steps_seen, cap_hits, escapes */
@@ -322,7 +323,8 @@ static void *run_rows(void *arg)
                 if (d <= J->eps) break;
                 if (s >= J->max_steps) { capped = 1; break; }
                 double r = step_radius(g, J->radius_mode, J->S, x, d);
-                oracle_direction(dim, s, (uint32_t)k, (uint32_t)i, J->inst, J->key0, J->key1, U);
+                uint32_t pid = J->point_ids ? J->point_ids[i] : (uint32_t)i;
+                oracle_direction(dim, s, (uint32_t)k, pid, J->inst, J->key0, J->key1, U);
                 for (int rr = 0; rr < dim; ++rr) {
                     double acc = 0.0;
                     for (int c = 0; c < dim; ++c) acc += J->S[rr * 3 + c] * U[c];
@@ -353,13 +355,16 @@ static void *run_rows(void *arg)
  * walk_end) of every point.  S is the 3x3 row-major symmetric root of K/lambda_max (only the
  * leading dim x dim block is read).  stats_out[5] = walks, steps, max steps, cap hits, escapes.
  * trace (optional) receives (element, steps) per walk, row-major over (point, walk - walk_begin).
+ * point_ids (optional) gives the point index used in the random-number counter of each row (default:
+ * the row index), so single rows of a large problem can be recomputed on their own.
  * Returns 0 on success, -1 on invalid arguments.
  */
 int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, double eps,
                          int radius_mode, uint32_t seed_lo, uint32_t seed_hi, uint32_t inst,
                          uint32_t max_steps, const double *x_obs, int32_t n_obs,
                          uint64_t walk_begin, uint64_t walk_end, uint32_t *counts,
-                         uint64_t *stats_out, int32_t *trace, int n_threads)
+                         uint64_t *stats_out, int32_t *trace, const uint32_t *point_ids,
+                         int n_threads)
 {
     if (!g || !S || !counts || n_obs < 0 || walk_end < walk_begin || eps <= 0.0) return -1;
     if (radius_mode == 1 && g->kind != OG_BOX) return -1;
@@ -372,7 +377,7 @@ int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, doub
         J->g = g; J->S = S; J->eps = eps; J->radius_mode = radius_mode;
         J->key0 = seed_lo; J->key1 = seed_hi; J->inst = inst; J->max_steps = max_steps;
         J->x_obs = x_obs; J->n_obs = n_obs; J->wb = walk_begin; J->we = walk_end;
-        J->counts = counts; J->trace = trace; J->n_elem = n_elem;
+        J->counts = counts; J->trace = trace; J->point_ids = point_ids; J->n_elem = n_elem;
         J->tid = t; J->nthr = n_threads;
         pthread_create(&th[t], NULL, run_rows, J);
     }

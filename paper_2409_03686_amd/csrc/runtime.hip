@@ -1,0 +1,739 @@
+// runtime.hip -- host side of libwos: the C ABI declared in include/wos.h.
+//
+// Responsibilities: argument validation (before any device work), instance set-up (lambda_max(K),
+// Khat = K / lambda_max, S = Khat^{1/2} by a symmetric Jacobi eigensolver in FP64), cell measures,
+// device descriptors of batched builds staged through a ring of pinned buffers, launch shapes
+// (set or autotuned), SVD workspaces, reconstruction, and HIP-graph plans of the whole path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wos.h"
+#include "wos_internal.h"
+#include "wos_runtime.h"
+
+using namespace wos;
+
+// ---------------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+wos_status wos::set_error(wos_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+extern "C" const char *wos_last_error(void) { return g_last_error.c_str(); }
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            if (ctx) (ctx)->poisoned = true;                                                      \
+            return set_error(WOS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+        }                                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Device memory accounting
+// ---------------------------------------------------------------------------------------------
+wos_status wos::ctx_malloc(wos_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    size_t used = ctx->hbm_used.load();
+    if (ctx->hbm_budget && used + bytes > ctx->hbm_budget)
+        return set_error(WOS_ENOMEM, "HBM budget exceeded (%zu + %zu > %zu bytes)", used, bytes, ctx->hbm_budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return set_error(WOS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    ctx->hbm_used += bytes;
+    return WOS_OK;
+}
+
+void wos::ctx_free(wos_ctx *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    (void)hipFree(p);
+    ctx->hbm_used -= bytes;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------------------------
+extern "C" wos_status wos_create(wos_ctx **out, int device, size_t hbm_budget_bytes)
+{
+    if (!out) return set_error(WOS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return set_error(WOS_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return set_error(WOS_EINVAL, "device %d out of range [0, %d)", device, n);
+    wos_ctx *ctx = new wos_ctx();
+    ctx->device = device;
+    ctx->hbm_budget = hbm_budget_bytes;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&ctx->props, device) != hipSuccess) {
+        delete ctx;
+        return set_error(WOS_EDEVICE, "cannot open HIP device %d", device);
+    }
+    ctx->n_cu = ctx->props.multiProcessorCount;
+    for (auto &slot : ctx->ring) {
+        if (hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess) {
+            delete ctx;
+            return set_error(WOS_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    *out = ctx;
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_destroy(wos_ctx *ctx)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    (void)hipSetDevice(ctx->device);
+    for (auto &slot : ctx->ring) {
+        if (slot.used) (void)hipEventSynchronize(slot.done);
+        (void)hipEventDestroy(slot.done);
+        if (slot.host) (void)hipHostFree(slot.host);
+        ctx_free(ctx, slot.dev, slot.cap);
+    }
+    delete ctx;
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------------------------
+static int elements_of(const wos_geometry *g)
+{
+    switch (g->kind) {
+    case WOS_DISK: case WOS_ELLIPSE: case WOS_POLYGON: return g->layout[0];
+    case WOS_ANNULUS: return g->layout[0] + g->layout[1];
+    case WOS_BALL: return g->layout[0] * g->layout[1];
+    case WOS_BOX: return g->dim == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
+    }
+    return -1;
+}
+
+wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
+{
+    if (!g) return set_error(WOS_EINVAL, "geometry is NULL");
+    for (double v : g->params)
+        if (!std::isfinite(v)) return set_error(WOS_EINVAL, "geometry parameters must be finite");
+    const double *p = g->params;
+    switch (g->kind) {
+    case WOS_DISK:
+        if (g->dim != 2 || !(p[2] > 0)) return set_error(WOS_EINVAL, "disk needs dim 2 and R > 0");
+        break;
+    case WOS_ANNULUS:
+        if (g->dim != 2 || !(p[2] > 0) || !(p[3] > p[2]))
+            return set_error(WOS_EINVAL, "annulus needs dim 2 and 0 < R_in < R_out");
+        if (g->layout[1] < 1) return set_error(WOS_EINVAL, "annulus needs layout (M_out >= 1, M_in >= 1)");
+        break;
+    case WOS_ELLIPSE:
+        if (g->dim != 2 || !(p[2] > 0) || !(p[3] > 0)) return set_error(WOS_EINVAL, "ellipse needs dim 2, a, b > 0");
+        break;
+    case WOS_POLYGON: {
+        if (g->dim != 2) return set_error(WOS_EINVAL, "polygon needs dim 2");
+        if (!g->verts || g->n_verts < 3 || g->n_verts > WOS_MAX_POLY_VERTS)
+            return set_error(WOS_EINVAL, "polygon needs 3..%d vertices", WOS_MAX_POLY_VERTS);
+        double area2 = 0.0;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e, *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            if (!std::isfinite(a[0]) || !std::isfinite(a[1])) return set_error(WOS_EINVAL, "polygon vertex not finite");
+            if (a[0] == b[0] && a[1] == b[1]) return set_error(WOS_EINVAL, "polygon has a zero-length edge");
+            area2 += a[0] * b[1] - a[1] * b[0];
+        }
+        if (!(area2 > 0)) return set_error(WOS_EINVAL, "polygon loop must be counter-clockwise");
+        break;
+    }
+    case WOS_BALL:
+        if (g->dim != 3 || !(p[3] > 0)) return set_error(WOS_EINVAL, "ball needs dim 3 and R > 0");
+        if (g->layout[1] < 1) return set_error(WOS_EINVAL, "ball needs layout (n_z >= 1, n_phi >= 1)");
+        break;
+    case WOS_BOX:
+        if (g->dim != 2 && g->dim != 3) return set_error(WOS_EINVAL, "box needs dim 2 or 3");
+        for (int a = 0; a < g->dim; ++a)
+            if (!(p[g->dim + a] > p[a])) return set_error(WOS_EINVAL, "box needs lo < hi on every axis");
+        break;
+    default:
+        return set_error(WOS_EINVAL, "unknown geometry kind %d", g->kind);
+    }
+    if (g->layout[0] < 1) return set_error(WOS_EINVAL, "layout[0] must be >= 1");
+    const long long m = elements_of(g);
+    if (m < 1 || m > WOS_MAX_ELEMENTS)
+        return set_error(WOS_ENOTSUP, "%lld cells (supported: 1..%d)", m, WOS_MAX_ELEMENTS);
+    if (n_elem) *n_elem = static_cast<int>(m);
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_element_count(const wos_geometry *geom, int32_t *n_elem)
+{
+    if (!n_elem) return set_error(WOS_EINVAL, "n_elem is NULL");
+    int m = 0;
+    wos_status st = validate_geometry(geom, &m);
+    if (st != WOS_OK) return st;
+    *n_elem = m;
+    return WOS_OK;
+}
+
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n (for the ellipse arc lengths).
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            const double z1 = z;
+            z = z1 - p1 / pp;
+            if (std::fabs(z - z1) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
+{
+    int M = 0;
+    wos_status st = validate_geometry(g, &M);
+    if (st != WOS_OK) return st;
+    if (!sigma) return set_error(WOS_EINVAL, "sigma_host is NULL");
+    const double *p = g->params;
+    switch (g->kind) {
+    case WOS_DISK:
+        for (int j = 0; j < M; ++j) sigma[j] = 2.0 * M_PI * p[2] / M;
+        break;
+    case WOS_ANNULUS:
+        for (int j = 0; j < g->layout[0]; ++j) sigma[j] = 2.0 * M_PI * p[3] / g->layout[0];
+        for (int j = 0; j < g->layout[1]; ++j) sigma[g->layout[0] + j] = 2.0 * M_PI * p[2] / g->layout[1];
+        break;
+    case WOS_ELLIPSE: {
+        std::vector<double> xg, wg;
+        gauss_legendre(48, xg, wg);
+        for (int j = 0; j < M; ++j) {
+            const double t0 = 2.0 * M_PI * j / M, t1 = 2.0 * M_PI * (j + 1) / M;
+            double acc = 0.0;
+            for (size_t q = 0; q < xg.size(); ++q) {
+                const double t = 0.5 * (t1 - t0) * xg[q] + 0.5 * (t1 + t0);
+                acc += wg[q] * std::sqrt(p[2] * p[2] * std::sin(t) * std::sin(t) + p[3] * p[3] * std::cos(t) * std::cos(t));
+            }
+            sigma[j] = 0.5 * (t1 - t0) * acc;
+        }
+        break;
+    }
+    case WOS_POLYGON: {
+        double L = 0.0;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e, *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            L += std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]));
+        }
+        for (int j = 0; j < M; ++j) sigma[j] = L / M;
+        break;
+    }
+    case WOS_BALL:
+        for (int j = 0; j < M; ++j) sigma[j] = 4.0 * M_PI * p[3] * p[3] / M;
+        break;
+    case WOS_BOX: {
+        const int d = g->dim, n = g->layout[0];
+        const int per_face = d == 2 ? n : n * n;
+        for (int f = 0; f < 2 * d; ++f) {
+            double area = 1.0;
+            for (int b = 0; b < d; ++b)
+                if (b != f / 2) area *= (p[d + b] - p[b]) / n;
+            for (int j = 0; j < per_face; ++j) sigma[f * per_face + j] = area;
+        }
+        break;
+    }
+    }
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Instance set-up: lambda_max(K) and S = (K / lambda_max)^{1/2} (cyclic Jacobi eigensolver).
+// ---------------------------------------------------------------------------------------------
+wos_status wos::conductivity_root(const double *K, int d, double S[9], double *lam_max, double *lam_min)
+{
+    double A[3][3] = {}, V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double scale = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            const double v = K[i * 3 + j];
+            if (!std::isfinite(v)) return set_error(WOS_EINVAL, "K has a non-finite entry");
+            A[i][j] = v;
+            scale = std::max(scale, std::fabs(v));
+        }
+    for (int i = 0; i < d; ++i)
+        for (int j = i + 1; j < d; ++j)
+            if (std::fabs(A[i][j] - A[j][i]) > 1e-12 * scale) return set_error(WOS_EINVAL, "K is not symmetric");
+    if (!(scale > 0)) return set_error(WOS_EINVAL, "K is zero");
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = i + 1; j < d; ++j) off += A[i][j] * A[i][j];
+        if (off == 0.0) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < d; ++k) {  // A <- A J
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {  // A <- J^T A
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                A[p][q] = A[q][p] = 0.0;
+                for (int k = 0; k < d; ++k) {  // V <- V J
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    double lmax = -1e300, lmin = 1e300;
+    for (int i = 0; i < d; ++i) {
+        lmax = std::max(lmax, A[i][i]);
+        lmin = std::min(lmin, A[i][i]);
+    }
+    if (!(lmin > 0)) return set_error(WOS_EINVAL, "K is not positive definite (smallest eigenvalue %g)", lmin);
+    for (int i = 0; i < 9; ++i) S[i] = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < d; ++k) acc += V[i][k] * std::sqrt(A[k][k] / lmax) * V[j][k];
+            S[i * 3 + j] = acc;
+        }
+    if (lam_max) *lam_max = lmax;
+    if (lam_min) *lam_min = lmin;
+    return WOS_OK;
+}
+
+wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
+{
+    if (!w) return set_error(WOS_EINVAL, "walk params are NULL");
+    if (!(w->eps > 0) || !std::isfinite(w->eps)) return set_error(WOS_EINVAL, "eps must be finite and > 0");
+    if (w->walk_end < w->walk_begin) return set_error(WOS_EINVAL, "walk_end < walk_begin");
+    if (w->walk_end > (1ull << 32)) return set_error(WOS_EINVAL, "walk ids must be below 2^32");
+    if (w->precision != WOS_FP64 && w->precision != WOS_FP32_GEOM_FP64_EXIT)
+        return set_error(WOS_EINVAL, "unknown precision %d", w->precision);
+    if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT)
+        return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
+    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX)
+        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes only");
+    return WOS_OK;
+}
+
+// Domain scale for the FP32 error bound: the largest coordinate magnitude the walk can reach.
+static double domain_scale(const wos_geometry *g)
+{
+    const double *p = g->params;
+    double s = 0.0;
+    switch (g->kind) {
+    case WOS_DISK: s = std::fabs(p[0]) + std::fabs(p[1]) + p[2]; break;
+    case WOS_ANNULUS: s = std::fabs(p[0]) + std::fabs(p[1]) + p[3]; break;
+    case WOS_ELLIPSE: s = std::fabs(p[0]) + std::fabs(p[1]) + std::max(p[2], p[3]); break;
+    case WOS_POLYGON:
+        for (int e = 0; e < 2 * g->n_verts; ++e) s = std::max(s, std::fabs(g->verts[e]));
+        break;
+    case WOS_BALL: s = std::fabs(p[0]) + std::fabs(p[1]) + std::fabs(p[2]) + p[3]; break;
+    case WOS_BOX:
+        for (int a = 0; a < 2 * g->dim; ++a) s = std::max(s, std::fabs(p[a]));
+        break;
+    }
+    return std::max(s, 1e-30);
+}
+
+wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n_elem, DevInst &I,
+                          std::vector<PolySeg> &segs)
+{
+    std::memset(&I, 0, sizeof I);
+    I.dim = g->dim;
+    I.kind = g->kind;
+    I.radius_mode = w->radius_mode;
+    I.n_elem = n_elem;
+    for (int k = 0; k < 4; ++k) I.layout[k] = g->layout[k];
+    I.precision = w->precision;
+    for (int k = 0; k < 8; ++k) {
+        I.p[k] = g->params[k];
+        I.pf[k] = static_cast<float>(g->params[k]);
+    }
+    if (g->kind == WOS_ELLIPSE) {
+        I.pf[4] = static_cast<float>(1.0 / g->params[2]);
+        I.pf[5] = static_cast<float>(1.0 / g->params[3]);
+        I.pf[6] = static_cast<float>(std::min(g->params[2], g->params[3]));
+    }
+    double lmax = 0, lmin = 0;
+    wos_status st = conductivity_root(w->K, g->dim, I.S, &lmax, &lmin);
+    if (st != WOS_OK) return st;
+    for (int k = 0; k < 9; ++k) I.Sf[k] = static_cast<float>(I.S[k]);
+    for (int a = 0; a < 3; ++a) {
+        double cn = 0.0;
+        for (int r = 0; r < g->dim; ++r) cn += I.S[r * 3 + a] * I.S[r * 3 + a];
+        I.cn[a] = std::sqrt(cn);
+        I.icnf[a] = a < g->dim ? static_cast<float>(1.0 / I.cn[a]) : 0.0f;
+    }
+    I.eps = w->eps;
+    // FP32 distance error bound: a few dozen ulps of the coordinate scale (differences, squares,
+    // a hardware square root and one subtraction; derivation in the design notes).
+    const double delta = std::ldexp(domain_scale(g), -18);
+    I.delta = static_cast<float>(delta);
+    I.eps_lo = static_cast<float>(w->eps - delta);
+    I.eps_hi = static_cast<float>(w->eps + delta);
+    if (w->precision == WOS_FP32_GEOM_FP64_EXIT && !(w->eps > 8.0 * delta))
+        return set_error(WOS_ENOTSUP, "eps %g is too small for FP32 geometry at domain scale %g (needs eps > %g)",
+                         w->eps, domain_scale(g), 8.0 * delta);
+    I.key0 = static_cast<uint32_t>(w->seed & 0xFFFFFFFFu);
+    I.key1 = static_cast<uint32_t>(w->seed >> 32);
+    I.inst = w->instance;
+    I.max_steps = w->max_steps ? w->max_steps : 10000u;
+    I.walk_begin = w->walk_begin;
+    I.n_walks = static_cast<uint32_t>(w->walk_end - w->walk_begin);
+    segs.clear();
+    if (g->kind == WOS_POLYGON) {
+        I.n_verts = g->n_verts;
+        double cum = 0.0;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e, *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            PolySeg s{};
+            s.ax = a[0];
+            s.ay = a[1];
+            s.ex = b[0] - a[0];
+            s.ey = b[1] - a[1];
+            s.ll = s.ex * s.ex + s.ey * s.ey;
+            s.len = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]));
+            s.cum = cum;
+            cum += s.len;
+            s.fax = static_cast<float>(s.ax);
+            s.fay = static_cast<float>(s.ay);
+            s.fex = static_cast<float>(s.ex);
+            s.fey = static_cast<float>(s.ey);
+            s.finv_ll = static_cast<float>(1.0 / s.ll);
+            segs.push_back(s);
+        }
+        I.perim = cum;
+    }
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launch shapes
+// ---------------------------------------------------------------------------------------------
+static int tune_key(int dim, int kind, int precision) { return (precision * 4 + dim) * 16 + (kind + 1); }
+
+wos_tuning wos::get_tuning(wos_ctx *ctx, int dim, int kind, int precision)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tuning.find(tune_key(dim, kind, precision));
+    if (it != ctx->tuning.end()) return it->second;
+    it = ctx->tuning.find(tune_key(dim, -1, precision));
+    if (it != ctx->tuning.end()) return it->second;
+    return wos_tuning{256, 32};
+}
+
+static bool valid_tuning(const wos_tuning *t)
+{
+    return t && (t->block == 64 || t->block == 128 || t->block == 256 || t->block == 512 || t->block == 1024) &&
+           t->walks_per_lane >= 1 && t->walks_per_lane <= 4096;
+}
+
+extern "C" wos_status wos_set_tuning(wos_ctx *ctx, int32_t dim, int32_t kind, int32_t precision, const wos_tuning *t)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    if (!valid_tuning(t)) return set_error(WOS_EINVAL, "block must be 64..1024 (power of two), walks_per_lane >= 1");
+    if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > 5)
+        return set_error(WOS_EINVAL, "bad (dim, kind, precision)");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuning[tune_key(dim, kind, precision)] = *t;
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched measure build
+// ---------------------------------------------------------------------------------------------
+struct Group {
+    int precision, dim;
+    std::vector<int> jobs;
+};
+
+// Prepares the descriptors of one (precision, dim) group into host memory `buf` (DevInst array
+// followed by the polygon segments) and returns the launch shape.
+wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const std::vector<int> &idx,
+                              const wos_tuning *force, std::vector<uint8_t> &buf, GroupLaunch &gl)
+{
+    const int n = static_cast<int>(idx.size());
+    std::vector<DevInst> insts(n);
+    std::vector<std::vector<PolySeg>> segs(n);
+    gl = GroupLaunch{};
+    wos_tuning tn = force ? *force : get_tuning(ctx, jobs[idx[0]].geom.dim, jobs[idx[0]].geom.kind, jobs[idx[0]].walk.precision);
+    int max_elem = 1, seg_max = 0;
+    for (int q = 0; q < n; ++q) {
+        const wos_measure_job &J = jobs[idx[q]];
+        int M = 0;
+        wos_status st = validate_geometry(&J.geom, &M);
+        if (st != WOS_OK) return st;
+        st = fill_inst(&J.geom, &J.walk, M, insts[q], segs[q]);
+        if (st != WOS_OK) return st;
+        max_elem = std::max(max_elem, M);
+        seg_max = std::max(seg_max, static_cast<int>(segs[q].size()));
+    }
+    const uint32_t chunk = static_cast<uint32_t>(tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
+    uint64_t items = 0;
+    size_t seg_off = sizeof(DevInst) * n;
+    for (int q = 0; q < n; ++q) {
+        DevInst &I = insts[q];
+        const wos_measure_job &J = jobs[idx[q]];
+        I.chunk = chunk;
+        I.n_chunks = I.n_walks == 0 ? 0 : (I.n_walks + chunk - 1) / chunk;
+        I.n_obs = J.n_obs;
+        I.item_begin = items;
+        I.n_items = static_cast<uint64_t>(J.n_obs) * I.n_chunks;
+        items += I.n_items;
+        I.x_obs = J.x_obs_dev;
+        I.counts = J.counts_dev;
+        I.stats = reinterpret_cast<unsigned long long *>(J.stats_dev);
+        I.trace = J.trace_dev;
+        // segs pointer is patched with the device base address at upload time (offset stored)
+        I.segs = reinterpret_cast<const PolySeg *>(static_cast<uintptr_t>(seg_off));
+        seg_off += sizeof(PolySeg) * segs[q].size();
+    }
+    if (items >= (1ull << 32)) return set_error(WOS_ENOTSUP, "more than 2^32 work items in one launch");
+    buf.assign(seg_off, 0);
+    std::memcpy(buf.data(), insts.data(), sizeof(DevInst) * n);
+    size_t off = sizeof(DevInst) * n;
+    for (int q = 0; q < n; ++q) {
+        if (!segs[q].empty()) std::memcpy(buf.data() + off, segs[q].data(), sizeof(PolySeg) * segs[q].size());
+        off += sizeof(PolySeg) * segs[q].size();
+    }
+    gl.n_inst = n;
+    gl.items = items;
+    gl.block = tn.block;
+    gl.hist_words = (max_elem + 3) & ~3;
+    gl.seg_bytes = static_cast<int>(sizeof(PolySeg)) * seg_max;
+    gl.precision = jobs[idx[0]].walk.precision;
+    gl.dim = jobs[idx[0]].geom.dim;
+    const size_t lds = static_cast<size_t>(gl.hist_words) * 4 + gl.seg_bytes + walk_queue_bytes(gl.precision, gl.dim, gl.block);
+    if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);
+    int per_cu = 0;
+    if (hipFuncSetAttribute(walk_kernel_ptr(gl.precision, gl.dim), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds)) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(gl.precision, gl.dim), gl.block, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    uint64_t grid = static_cast<uint64_t>(per_cu) * ctx->n_cu;
+    grid = std::min<uint64_t>(grid, std::max<uint64_t>(items, 1));
+    gl.grid = static_cast<int>(grid);
+    return WOS_OK;
+}
+
+// Patches the segment offsets of a staged descriptor buffer to device addresses.
+static void patch_segs(std::vector<uint8_t> &buf, int n_inst, uintptr_t dev_base)
+{
+    DevInst *I = reinterpret_cast<DevInst *>(buf.data());
+    for (int q = 0; q < n_inst; ++q)
+        I[q].segs = reinterpret_cast<const PolySeg *>(dev_base + reinterpret_cast<uintptr_t>(I[q].segs));
+}
+
+wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const GroupLaunch &gl, hipStream_t stream)
+{
+    // ring slot: waits only if the launch that used it last has not finished
+    RingSlot &slot = ctx->ring[ctx->ring_next];
+    ctx->ring_next = (ctx->ring_next + 1) % ctx->ring.size();
+    if (slot.used) HIP_TRY(ctx, hipEventSynchronize(slot.done));
+    const size_t need = buf.size() + 64;
+    if (slot.cap < need) {
+        if (slot.host) (void)hipHostFree(slot.host);
+        ctx_free(ctx, slot.dev, slot.cap);
+        slot.host = nullptr;
+        slot.dev = nullptr;
+        slot.cap = 0;
+        size_t cap = 4096;
+        while (cap < need) cap *= 2;
+        wos_status st = ctx_malloc(ctx, &slot.dev, cap);
+        if (st != WOS_OK) return st;
+        if (hipHostMalloc(&slot.host, cap, hipHostMallocDefault) != hipSuccess) {
+            ctx_free(ctx, slot.dev, cap);
+            slot.dev = nullptr;
+            return set_error(WOS_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+        }
+        slot.cap = cap;
+    }
+    uint8_t *dev = static_cast<uint8_t *>(slot.dev);
+    patch_segs(buf, gl.n_inst, reinterpret_cast<uintptr_t>(dev));
+    std::memcpy(slot.host, buf.data(), buf.size());
+    uint32_t *cursor = reinterpret_cast<uint32_t *>(dev + ((buf.size() + 15) & ~size_t(15)));
+    HIP_TRY(ctx, hipMemcpyAsync(dev, slot.host, buf.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, reinterpret_cast<const DevInst *>(dev), gl.n_inst, gl.items,
+                              cursor, gl.hist_words, gl.seg_bytes, gl.block, gl.grid, stream));
+    HIP_TRY(ctx, hipEventRecord(slot.done, stream));
+    slot.used = true;
+    return WOS_OK;
+}
+
+static wos_status check_job(const wos_measure_job *J)
+{
+    int M = 0;
+    wos_status st = validate_geometry(&J->geom, &M);
+    if (st != WOS_OK) return st;
+    st = validate_walk(&J->geom, &J->walk);
+    if (st != WOS_OK) return st;
+    if (J->n_obs < 0) return set_error(WOS_EINVAL, "n_obs < 0");
+    if (J->n_obs > 0 && J->walk.walk_end > J->walk.walk_begin) {
+        if (!J->x_obs_dev) return set_error(WOS_EINVAL, "x_obs_dev is NULL");
+        if (!J->counts_dev) return set_error(WOS_EINVAL, "counts_dev is NULL");
+    }
+    return WOS_OK;
+}
+
+wos_status wos::group_jobs(const wos_measure_job *jobs, int n, std::vector<std::vector<int>> &groups)
+{
+    groups.clear();
+    std::map<int, std::vector<int>> by;
+    for (int q = 0; q < n; ++q) {
+        wos_status st = check_job(&jobs[q]);
+        if (st != WOS_OK) return set_error(st, "job %d: %s", q, wos_last_error());
+        if (jobs[q].n_obs == 0 || jobs[q].walk.walk_end == jobs[q].walk.walk_begin) continue;  // nothing to do
+        by[jobs[q].walk.precision * 4 + jobs[q].geom.dim].push_back(q);
+    }
+    for (auto &kv : by) groups.push_back(kv.second);
+    return WOS_OK;
+}
+
+wos_status wos::build_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs, hipStream_t stream,
+                            const wos_tuning *force)
+{
+    std::vector<std::vector<int>> groups;
+    wos_status st = group_jobs(jobs, n_jobs, groups);
+    if (st != WOS_OK) return st;
+    // validate every group before enqueuing anything
+    std::vector<std::vector<uint8_t>> bufs(groups.size());
+    std::vector<GroupLaunch> gls(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        st = prepare_group(ctx, jobs, groups[g], force, bufs[g], gls[g]);
+        if (st != WOS_OK) return st;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        st = stage_and_launch(ctx, bufs[g], gls[g], stream);
+        if (st != WOS_OK) return st;
+    }
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_build_measure_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs, void *stream)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return set_error(WOS_EINVAL, "bad job list");
+    std::lock_guard<std::recursive_mutex> lk(ctx->launch_mu);
+    return build_batch(ctx, jobs, n_jobs, static_cast<hipStream_t>(stream), nullptr);
+}
+
+extern "C" wos_status wos_build_measure(wos_ctx *ctx, const wos_geometry *geom, const wos_walk_params *walk,
+                                        const double *x_obs_dev, int32_t n_obs, uint32_t *counts_dev,
+                                        uint64_t *stats_dev, int32_t *trace_dev, void *stream)
+{
+    if (!geom || !walk) return set_error(WOS_EINVAL, "geometry or walk params NULL");
+    wos_measure_job J;
+    J.geom = *geom;
+    J.walk = *walk;
+    J.x_obs_dev = x_obs_dev;
+    J.n_obs = n_obs;
+    J.counts_dev = counts_dev;
+    J.stats_dev = stats_dev;
+    J.trace_dev = trace_dev;
+    return wos_build_measure_batch(ctx, &J, 1, stream);
+}
+
+extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uint64_t sample_walks, wos_tuning *best,
+                                   void *stream)
+{
+    if (!ctx || !job) return set_error(WOS_EINVAL, "ctx or job NULL");
+    wos_status st = check_job(job);
+    if (st != WOS_OK) return st;
+    if (job->n_obs == 0) return set_error(WOS_EINVAL, "autotune needs points");
+    std::lock_guard<std::recursive_mutex> lk(ctx->launch_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    wos_measure_job J = *job;
+    const uint64_t avail = J.walk.walk_end - J.walk.walk_begin;
+    J.walk.walk_end = J.walk.walk_begin + std::min<uint64_t>(avail, std::max<uint64_t>(sample_walks, 1));
+    J.stats_dev = nullptr;
+    J.trace_dev = nullptr;
+    int M = 0;
+    (void)validate_geometry(&J.geom, &M);
+    const size_t cbytes = static_cast<size_t>(J.n_obs) * M * sizeof(uint32_t);
+    void *scratch = nullptr;
+    st = ctx_malloc(ctx, &scratch, cbytes);
+    if (st != WOS_OK) return st;
+    J.counts_dev = static_cast<uint32_t *>(scratch);  // timing runs never touch the caller's counts
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    const int blocks[] = {128, 256, 512, 1024};
+    const int wpls[] = {4, 8, 16, 32, 64};
+    float best_ms = 1e30f;
+    wos_tuning bt{256, 32};
+    for (int b : blocks)
+        for (int w : wpls) {
+            wos_tuning t{b, w};
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_TRY(ctx, hipEventRecord(e0, s));
+                st = build_batch(ctx, &J, 1, s, &t);
+                if (st != WOS_OK) break;
+                HIP_TRY(ctx, hipEventRecord(e1, s));
+                HIP_TRY(ctx, hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+                ms_min = std::min(ms_min, ms);
+            }
+            if (st != WOS_OK) {  // e.g. LDS need too large for this block: skip the shape
+                st = WOS_OK;
+                continue;
+            }
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                bt = t;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    ctx_free(ctx, scratch, cbytes);
+    {
+        std::lock_guard<std::mutex> lk2(ctx->mu);
+        ctx->tuning[tune_key(job->geom.dim, job->geom.kind, job->walk.precision)] = bt;
+    }
+    if (best) *best = bt;
+    return WOS_OK;
+}

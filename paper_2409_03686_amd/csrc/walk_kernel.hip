@@ -1,0 +1,428 @@
+// walk_kernel.hip -- persistent walk-on-ellipsoids kernel for gfx950 (Algorithm MC-REM).
+//
+// Work decomposition: a work item is (instance, point i, chunk c of walk ids).  Blocks pull items
+// from one global atomic cursor until the queue is empty, so uneven instances and geometric-tailed
+// walk lengths share one launch.  Inside an item every wavefront keeps 64 walks in flight, one per
+// lane; a lane whose walk stops is refilled with the next walk id of the item through a wave ballot
+// and one LDS atomic for the whole wave (the paper's compaction of the active index vector).
+//
+// Randomness is counter-based (Philox4x32-10 keyed by instance seed; counter (block, walk, point,
+// instance)), so which lane runs which walk never changes a result.  One Philox block feeds
+// SPB consecutive steps of a walk (4 in 2D FP32, 2 in 3D FP32 and 2D FP64, 1 in 3D FP64); new
+// walks start only at wave iterations that are multiples of SPB, which keeps every live lane of a
+// wave on the same phase, so the generator runs wave-uniformly once per SPB steps.
+//
+// Stop points are appended to a per-wave LDS queue and binned 64 at a time (full-wave FP64
+// projection), then counted in an LDS histogram row of the item's point; at the end of the item
+// the non-zero bins are flushed to the count matrix in HBM with atomics.
+#include "wos_device.hpp"
+#include "wos_internal.h"
+
+namespace wos {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename R, int DIM> struct Spb;
+template <> struct Spb<float, 2> { static constexpr int v = 4; };
+template <> struct Spb<float, 3> { static constexpr int v = 2; };
+template <> struct Spb<double, 2> { static constexpr int v = 2; };
+template <> struct Spb<double, 3> { static constexpr int v = 1; };
+
+struct BlockShared {
+    uint32_t item_lo, item_hi;
+    uint32_t next;            // next walk offset of the current item
+    uint32_t pad;
+    unsigned long long st[8]; // per-item statistics
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Direction of step s (phase = s mod SPB) from the words of the walk's current Philox block.
+template <typename R, int DIM> struct Dir;
+
+template <> struct Dir<float, 2> {
+    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, float *U)
+    {
+        const uint32_t word = phase == 0 ? w[0] : phase == 1 ? w[1] : phase == 2 ? w[2] : w[3];
+        const float u = u24(word);
+        // v_sin/v_cos take revolutions: sin(2 pi u), cos(2 pi u) without range reduction
+        const float c = __builtin_amdgcn_cosf(u), s = __builtin_amdgcn_sinf(u);
+        const float inv = __builtin_amdgcn_rsqf(c * c + s * s);
+        U[0] = c * inv;
+        U[1] = s * inv;
+    }
+};
+template <> struct Dir<float, 3> {
+    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, float *U)
+    {
+        const float u1 = u24(phase == 0 ? w[0] : w[2]);
+        const float u2 = u24(phase == 0 ? w[1] : w[3]);
+        const float z = 1.0f - 2.0f * u1;
+        const float rho = __builtin_amdgcn_sqrtf(__builtin_fmaxf((1.0f - z) * (1.0f + z), 0.0f));
+        const float c = __builtin_amdgcn_cosf(u2), s = __builtin_amdgcn_sinf(u2);
+        const float inv = rho * __builtin_amdgcn_rsqf(c * c + s * s);
+        U[0] = c * inv;
+        U[1] = s * inv;
+        U[2] = z;
+    }
+};
+template <> struct Dir<double, 2> {
+    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, double *U)
+    {
+#pragma clang fp contract(off)
+        const double u = phase == 0 ? u53(w[0], w[1]) : u53(w[2], w[3]);
+        const double th = kTwoPi * u;
+        double s, c;
+        sincos(th, &s, &c);
+        U[0] = c;
+        U[1] = s;
+    }
+};
+template <> struct Dir<double, 3> {
+    static __device__ __forceinline__ void get(const uint32_t w[4], int, double *U)
+    {
+#pragma clang fp contract(off)
+        const double z = 1.0 - 2.0 * u53(w[0], w[1]);
+        const double ph = kTwoPi * u53(w[2], w[3]);
+        const double rho = __builtin_sqrt((1.0 - z) * (1.0 + z));
+        double s, c;
+        sincos(ph, &s, &c);
+        U[0] = rho * c;
+        U[1] = rho * s;
+        U[2] = z;
+    }
+};
+
+// x <- x + r S U  (FP64 keeps the order of the definition; FP32 uses fused multiply-adds)
+template <int DIM> __device__ __forceinline__ void step64(const DevInst &I, double *x, double r, const double *U)
+{
+#pragma clang fp contract(off)
+    double y[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc += I.S[a * 3 + c] * U[c];
+        y[a] = acc;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x[a] = x[a] + r * y[a];
+}
+template <int DIM> __device__ __forceinline__ void step32(const DevInst &I, float *x, float r, const float *U)
+{
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc = __builtin_fmaf(I.Sf[a * 3 + c], U[c], acc);
+        x[a] = __builtin_fmaf(r, acc, x[a]);
+    }
+}
+
+// Per-wave stop queue in LDS (structure of arrays).
+template <typename R, int DIM> struct StopQueue {
+    R *pos;          // [DIM][kWave]
+    uint32_t *koff;  // [kWave]
+    uint32_t *steps; // [kWave]
+};
+
+template <typename R, int DIM, int KIND>
+__device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R, DIM> &q, uint32_t n,
+                                            uint32_t point, uint32_t *hist, const PolySeg *segs,
+                                            uint32_t &escapes)
+{
+    const uint32_t lane = __lane_id();
+    if (lane < n) {
+        double x[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) x[a] = static_cast<double>(q.pos[a * kWave + lane]);
+        const int j = element64<KIND, DIM>(I, x, segs);
+        atomicAdd(&hist[j], 1u);
+        if (dist64<KIND, DIM>(I, x, segs) < 0.0) escapes += 1;
+        if (I.trace) {
+            const size_t t = (static_cast<size_t>(point) * I.n_walks + q.koff[lane]) * 2;
+            I.trace[t] = j;
+            I.trace[t + 1] = static_cast<int32_t>(q.steps[lane]);
+        }
+    }
+}
+
+template <typename R, int DIM, int KIND>
+__device__ void run_item(const DevInst &I, uint32_t point, uint32_t chunk_idx, uint32_t *hist,
+                         PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh)
+{
+    constexpr int SPB = Spb<R, DIM>::v;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int M = I.n_elem;
+    for (int j = tid; j < M; j += nthr) hist[j] = 0u;
+    const PolySeg *segs = I.segs;
+    if constexpr (KIND == kPolygon) {
+        for (int e = tid; e < I.n_verts; e += nthr) lds_segs[e] = I.segs[e];
+        segs = lds_segs;
+    }
+    if (tid < 8) sh.st[tid] = 0ull;
+    if (tid == 0) sh.next = 0u;
+    __syncthreads();
+
+    const uint32_t k0 = chunk_idx * I.chunk;
+    const uint32_t cnt = min(I.chunk, I.n_walks - k0);
+
+    double x0d[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x0d[a] = I.x_obs[static_cast<size_t>(point) * DIM + a];
+    const double d0d = dist64<KIND, DIM>(I, x0d, segs);
+
+    if (!(d0d > I.eps)) {
+        // The start point lies in the eps-shell (or outside D): every walk stops with zero steps
+        // in the cell of the start point's projection.
+        const int j0 = element64<KIND, DIM>(I, x0d, segs);
+        if (tid == 0) {
+            hist[j0] += cnt;
+            sh.st[0] = cnt;
+            if (d0d < 0.0) sh.st[4] = cnt;
+        }
+        if (I.trace) {
+            for (uint32_t w = tid; w < cnt; w += nthr) {
+                const size_t t = (static_cast<size_t>(point) * I.n_walks + k0 + w) * 2;
+                I.trace[t] = j0;
+                I.trace[t + 1] = 0;
+            }
+        }
+    } else {
+        const uint32_t lane = __lane_id();
+        const int wv = tid / kWave;
+        StopQueue<R, DIM> q;
+        {
+            uint8_t *b = qbase + static_cast<size_t>(wv) * kWave * (DIM * sizeof(R) + 8);
+            q.pos = reinterpret_cast<R *>(b);
+            q.koff = reinterpret_cast<uint32_t *>(b + kWave * DIM * sizeof(R));
+            q.steps = q.koff + kWave;
+        }
+        R x0[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) x0[a] = static_cast<R>(x0d[a]);
+        R d0;
+        if constexpr (sizeof(R) == 8) d0 = d0d; else d0 = dist32<KIND, DIM>(I, x0, segs);
+
+        bool live = false;
+        uint32_t koff = 0, s = 0;
+        R x[DIM];
+        R d = d0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        uint32_t qn = 0;  // wave-uniform queue length
+        uint32_t phase = 0;
+        uint32_t n_walks = 0, n_cap = 0, n_esc = 0, n_fp64 = 0, max_s = 0;
+        unsigned long long steps_sum = 0, wave_iters = 0;
+
+        for (;;) {
+            if (phase == 0) {
+                const uint64_t need = __ballot(!live);
+                if (need != 0ull) {
+                    const uint32_t nneed = __popcll(need);
+                    const uint32_t leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
+                    uint32_t base = 0;
+                    if (lane == leader) base = atomicAdd(&sh.next, nneed);
+                    base = __shfl(base, leader);
+                    const uint32_t mine = base + __popcll(need & lanemask_lt());
+                    if (!live && mine < cnt) {
+                        live = true;
+                        koff = k0 + mine;
+                        s = 0;
+                        d = d0;
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+                    }
+                }
+                if (!__any(live)) break;
+                if (live) {
+                    uint32_t c0 = s / SPB, c1 = I.walk_begin + koff, c2 = point, c3 = I.inst;
+                    philox4x32_10(c0, c1, c2, c3, I.key0, I.key1);
+                    w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+                }
+            } else if (!__any(live)) {
+                phase = 0;
+                continue;
+            }
+            ++wave_iters;
+            bool fin = false;
+            if (live) {
+                R U[DIM];
+                Dir<R, DIM>::get(w, static_cast<int>(phase), U);
+                if constexpr (sizeof(R) == 8) {
+                    const double r = radius64<KIND, DIM>(I, x, d);
+                    step64<DIM>(I, x, r, U);
+                    d = dist64<KIND, DIM>(I, x, segs);
+                    s += 1;
+                    fin = !(d > I.eps);
+                } else {
+                    // conservative radius: below the true distance by more than the FP32 error
+                    const float rr = radius32<KIND, DIM>(I, x, d);
+                    const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-20f, -2.0f * I.delta);
+                    step32<DIM>(I, x, r, U);
+                    d = dist32<KIND, DIM>(I, x, segs);
+                    s += 1;
+                    if (d <= I.eps_lo) {
+                        fin = true;
+                    } else if (d <= I.eps_hi) {
+                        // ambiguous band: decide in FP64 at the stored position
+                        double xd[DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) xd[a] = static_cast<double>(x[a]);
+                        fin = !(dist64<KIND, DIM>(I, xd, segs) > I.eps);
+                        ++n_fp64;
+                    }
+                }
+                if (!fin && s >= I.max_steps) {
+                    fin = true;
+                    ++n_cap;
+                }
+                if (fin) {
+                    ++n_walks;
+                    steps_sum += s;
+                    max_s = max(max_s, s);
+                }
+            }
+            const uint64_t fmask = __ballot(fin);
+            if (fmask != 0ull) {
+                const uint32_t nf = __popcll(fmask);
+                if (qn + nf > static_cast<uint32_t>(kWave)) {
+                    flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, n_esc);
+                    qn = 0;
+                }
+                if (fin) {
+                    const uint32_t slot = qn + __popcll(fmask & lanemask_lt());
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
+                    q.koff[slot] = koff;
+                    q.steps[slot] = s;
+                    live = false;
+                }
+                qn += nf;
+            }
+            phase = (phase + 1) & (SPB - 1);
+        }
+        if (qn) flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, n_esc);
+
+        if (n_walks) atomicAdd(&sh.st[0], static_cast<unsigned long long>(n_walks));
+        if (steps_sum) atomicAdd(&sh.st[1], steps_sum);
+        if (max_s) atomicMax(&sh.st[2], static_cast<unsigned long long>(max_s));
+        if (n_cap) atomicAdd(&sh.st[3], static_cast<unsigned long long>(n_cap));
+        if (n_esc) atomicAdd(&sh.st[4], static_cast<unsigned long long>(n_esc));
+        if (n_fp64) atomicAdd(&sh.st[5], static_cast<unsigned long long>(n_fp64));
+        if (lane == 0) atomicAdd(&sh.st[6], wave_iters * kWave);
+    }
+    __syncthreads();
+    uint32_t *row = I.counts + static_cast<size_t>(point) * M;
+    for (int j = tid; j < M; j += nthr) {
+        const uint32_t v = hist[j];
+        if (v) atomicAdd(&row[j], v);
+    }
+    if (I.stats && tid < 7) {
+        const unsigned long long v = sh.st[tid];
+        if (tid == 2) {
+            if (v) atomicMax(&I.stats[2], v);
+        } else if (v) {
+            atomicAdd(&I.stats[tid], v);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, int DIM>
+__global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
+                                                    uint64_t total_items, uint32_t *cursor,
+                                                    int hist_words, int seg_bytes)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ BlockShared sh;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
+    PolySeg *lds_segs = reinterpret_cast<PolySeg *>(smem + static_cast<size_t>(hist_words) * 4);
+    uint8_t *qbase = smem + static_cast<size_t>(hist_words) * 4 + seg_bytes;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(cursor, 1u);
+            sh.item_lo = it;
+        }
+        __syncthreads();
+        const uint64_t item = __builtin_amdgcn_readfirstlane(sh.item_lo);
+        __syncthreads();
+        if (item >= total_items) return;
+        // instance of this item (descriptors sorted by item_begin)
+        int lo = 0, hi = n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (insts[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const int idx = __builtin_amdgcn_readfirstlane(lo);
+        const DevInst &I = insts[idx];
+        const uint64_t local = item - I.item_begin;
+        const uint32_t point = static_cast<uint32_t>(local / I.n_chunks);
+        const uint32_t chunk = static_cast<uint32_t>(local % I.n_chunks);
+        if constexpr (DIM == 2) {
+            switch (I.kind) {
+            case kDisk: run_item<R, 2, kDisk>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            case kAnnulus: run_item<R, 2, kAnnulus>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            case kEllipse: run_item<R, 2, kEllipse>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            case kPolygon: run_item<R, 2, kPolygon>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            default: run_item<R, 2, kBox>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            }
+        } else {
+            switch (I.kind) {
+            case kBall: run_item<R, 3, kBall>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            default: run_item<R, 3, kBox>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            }
+        }
+    }
+}
+
+__global__ void reset_cursor_kernel(uint32_t *cursor) { *cursor = 0u; }
+
+}  // namespace
+
+size_t walk_queue_bytes(int precision, int dim, int block)
+{
+    const size_t rs = precision == 0 ? 8 : 4;
+    return static_cast<size_t>(block / kWave) * kWave * (dim * rs + 8);
+}
+
+const void *walk_kernel_ptr(int precision, int dim)
+{
+    if (precision == 0) return dim == 2 ? reinterpret_cast<const void *>(&walk_kernel<double, 2>)
+                                        : reinterpret_cast<const void *>(&walk_kernel<double, 3>);
+    return dim == 2 ? reinterpret_cast<const void *>(&walk_kernel<float, 2>)
+                    : reinterpret_cast<const void *>(&walk_kernel<float, 3>);
+}
+
+hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst, uint64_t total_items,
+                        uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
+                        hipStream_t stream)
+{
+    reset_cursor_kernel<<<1, 1, 0, stream>>>(cursor);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = static_cast<size_t>(hist_words) * 4 + seg_bytes + walk_queue_bytes(precision, dim, block);
+    if (precision == 0) {
+        if (dim == 2)
+            walk_kernel<double, 2><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
+        else
+            walk_kernel<double, 3><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
+    } else {
+        if (dim == 2)
+            walk_kernel<float, 2><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
+        else
+            walk_kernel<float, 3><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace wos

@@ -1,0 +1,323 @@
+// wos_device.hpp -- device-side building blocks of the walk-on-ellipsoids kernels (gfx950).
+//
+// Philox4x32-10 counter-based generator, uniform-direction samplers, signed distance functions,
+// step radii and the cell index of the projection onto the boundary.  All of it is written for
+// 64-wide wavefronts: per-walk state lives in VGPRs, per-instance constants are wave-uniform and
+// are read through scalar loads from the instance descriptor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wos {
+
+enum Kind : int32_t { kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5 };
+
+constexpr int kMaxPolyVerts = 64;
+constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
+
+// One polygon edge a -> b in FP64 (exit tests and cell indices) and FP32 (bulk distance).
+struct PolySeg {
+    double ax, ay, ex, ey, ll, cum, len, pad;
+    float fax, fay, fex, fey, finv_ll, fpad0, fpad1, fpad2;
+};
+
+// Device descriptor of one instance of a (batched) measure build.  Filled on the host.
+struct alignas(16) DevInst {
+    int32_t dim, kind, radius_mode, n_elem;
+    int32_t layout[4];
+    int32_t n_verts, precision;
+    double p[8];
+    double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
+    double cn[3];     // |S e_a|: the half-extent of the unit ellipsoid S B(0,1) along axis a
+    double eps;
+    double perim;     // polygon perimeter
+    float pf[8];
+    float Sf[9];
+    float icnf[3];    // 1 / |S e_a|
+    float eps_lo;     // FP32 distance <= eps_lo: certainly inside the eps-shell
+    float eps_hi;     // FP32 distance >  eps_hi: certainly outside it
+    float delta;      // bound on |dist_fp32 - dist| for this domain (absolute)
+    float pad0;
+    uint32_t key0, key1, inst, max_steps;
+    uint64_t walk_begin;  // first walk id of the range
+    uint32_t n_walks;     // walks per point in this call
+    uint32_t chunk;       // walks per work item
+    uint32_t n_chunks;    // work items per point
+    int32_t n_obs;
+    uint64_t item_begin;  // first global work item of this instance
+    uint64_t n_items;
+    const double *x_obs;
+    uint32_t *counts;
+    unsigned long long *stats;
+    int32_t *trace;
+    const PolySeg *segs;
+};
+
+// ------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The key schedule is wave-uniform, so the
+// key additions run on the scalar unit; each round is two 32x32->64 multiplies and two xors.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform in (0,1]: the top 53 bits of hi:lo at the centre of their 2^-53 cell.
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo)
+{
+    const uint64_t m = ((static_cast<uint64_t>(hi) << 32) | lo) >> 11;
+    return static_cast<double>(m) * 0x1.0p-53 + 0x1.0p-54;
+}
+
+// Uniform in (0,1]: the top 24 bits of w at the centre of their 2^-24 cell.
+__device__ __forceinline__ float u24(uint32_t w)
+{
+    return static_cast<float>(w >> 8) * 0x1.0p-24f + 0x1.0p-25f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Scalar-type helpers
+// ------------------------------------------------------------------------------------------
+template <typename R> struct RT;
+template <> struct RT<double> {
+    static __device__ __forceinline__ double p(const DevInst &I, int k) { return I.p[k]; }
+    static __device__ __forceinline__ double S(const DevInst &I, int k) { return I.S[k]; }
+    static __device__ __forceinline__ double sqrt_(double v) { return __builtin_sqrt(v); }
+};
+template <> struct RT<float> {
+    static __device__ __forceinline__ float p(const DevInst &I, int k) { return I.pf[k]; }
+    static __device__ __forceinline__ float S(const DevInst &I, int k) { return I.Sf[k]; }
+    static __device__ __forceinline__ float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
+};
+
+template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+
+// ------------------------------------------------------------------------------------------
+// Signed distance to dD, positive inside.  FP64 instantiations keep the evaluation order of the
+// plain definition (no contraction), FP32 ones are the bulk path of the FP32-geometry mode.
+// ------------------------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R seg_dist_sq(R ax, R ay, R ex, R ey, R ll, R x, R y,
+                                                               R *t_out);
+template <> __device__ __forceinline__ double seg_dist_sq<double>(double ax, double ay, double ex,
+                                                                   double ey, double ll, double x,
+                                                                   double y, double *t_out)
+{
+#pragma clang fp contract(off)
+    const double wx = x - ax, wy = y - ay;
+    double t = (wx * ex + wy * ey) / ll;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double dx = wx - t * ex, dy = wy - t * ey;
+    *t_out = t;
+    return dx * dx + dy * dy;
+}
+template <> __device__ __forceinline__ float seg_dist_sq<float>(float ax, float ay, float ex, float ey,
+                                                                 float inv_ll, float x, float y,
+                                                                 float *t_out)
+{
+    const float wx = x - ax, wy = y - ay;
+    float t = (wx * ex + wy * ey) * inv_ll;
+    t = __builtin_fminf(__builtin_fmaxf(t, 0.0f), 1.0f);
+    const float dx = wx - t * ex, dy = wy - t * ey;
+    *t_out = t;
+    return dx * dx + dy * dy;
+}
+
+template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevInst &I, const double *x,
+                                                                      const PolySeg *segs)
+{
+#pragma clang fp contract(off)
+    if constexpr (KIND == kDisk) {
+        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
+        return I.p[2] - __builtin_sqrt(dx * dx + dy * dy);
+    } else if constexpr (KIND == kAnnulus) {
+        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
+        const double rho = __builtin_sqrt(dx * dx + dy * dy);
+        const double a = I.p[3] - rho, b = rho - I.p[2];
+        return a < b ? a : b;
+    } else if constexpr (KIND == kEllipse) {
+        const double u = (x[0] - I.p[0]) / I.p[2], v = (x[1] - I.p[1]) / I.p[3];
+        const double f = __builtin_sqrt(u * u + v * v);
+        const double m = I.p[2] < I.p[3] ? I.p[2] : I.p[3];
+        return m * (1.0 - f);
+    } else if constexpr (KIND == kPolygon) {
+        double best = __builtin_inf();
+        for (int e = 0; e < I.n_verts; ++e) {
+            double t;
+            const double q = seg_dist_sq<double>(segs[e].ax, segs[e].ay, segs[e].ex, segs[e].ey,
+                                                 segs[e].ll, x[0], x[1], &t);
+            const double d = __builtin_sqrt(q);
+            best = d < best ? d : best;
+        }
+        return best;
+    } else if constexpr (KIND == kBall) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);
+        return I.p[3] - __builtin_sqrt(s);
+    } else {  // kBox
+        double best = __builtin_inf();
+        for (int a = 0; a < DIM; ++a) {
+            const double lo = x[a] - I.p[a], hi = I.p[DIM + a] - x[a];
+            best = lo < best ? lo : best;
+            best = hi < best ? hi : best;
+        }
+        return best;
+    }
+}
+
+template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevInst &I, const float *x,
+                                                                     const PolySeg *segs)
+{
+    if constexpr (KIND == kDisk) {
+        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1];
+        return I.pf[2] - __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+    } else if constexpr (KIND == kAnnulus) {
+        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1];
+        const float rho = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+        return __builtin_fminf(I.pf[3] - rho, rho - I.pf[2]);
+    } else if constexpr (KIND == kEllipse) {
+        // pf[4] = 1/a, pf[5] = 1/b, pf[6] = min(a, b)
+        const float u = (x[0] - I.pf[0]) * I.pf[4], v = (x[1] - I.pf[1]) * I.pf[5];
+        return I.pf[6] * (1.0f - __builtin_amdgcn_sqrtf(u * u + v * v));
+    } else if constexpr (KIND == kPolygon) {
+        float best = __builtin_inff();
+        for (int e = 0; e < I.n_verts; ++e) {
+            float t;
+            best = __builtin_fminf(best, seg_dist_sq<float>(segs[e].fax, segs[e].fay, segs[e].fex,
+                                                            segs[e].fey, segs[e].finv_ll, x[0], x[1], &t));
+        }
+        return __builtin_amdgcn_sqrtf(best);
+    } else if constexpr (KIND == kBall) {
+        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1], dz = x[2] - I.pf[2];
+        return I.pf[3] - __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+    } else {
+        float best = __builtin_inff();
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            best = __builtin_fminf(best, __builtin_fminf(x[a] - I.pf[a], I.pf[DIM + a] - x[a]));
+        return best;
+    }
+}
+
+// Step radius.  WoE bound: r = dist (the ellipsoid x + r S B(0,1) lies in B(x, r) since |S| <= 1).
+// Mapped exact (boxes): the largest r with x + r S B(0,1) inside the box, min_a gap_a / |S e_a|.
+template <int KIND, int DIM> __device__ __forceinline__ double radius64(const DevInst &I, const double *x,
+                                                                        double d)
+{
+#pragma clang fp contract(off)
+    if constexpr (KIND == kBox) {
+        if (I.radius_mode == 1) {
+            double best = __builtin_inf();
+            for (int a = 0; a < DIM; ++a) {
+                const double lo = (x[a] - I.p[a]) / I.cn[a], hi = (I.p[DIM + a] - x[a]) / I.cn[a];
+                best = lo < best ? lo : best;
+                best = hi < best ? hi : best;
+            }
+            return best;
+        }
+    }
+    return d;
+}
+
+template <int KIND, int DIM> __device__ __forceinline__ float radius32(const DevInst &I, const float *x,
+                                                                       float d)
+{
+    if constexpr (KIND == kBox) {
+        if (I.radius_mode == 1) {
+            float best = __builtin_inff();
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                best = __builtin_fminf(best, __builtin_fminf((x[a] - I.pf[a]) * I.icnf[a],
+                                                             (I.pf[DIM + a] - x[a]) * I.icnf[a]));
+            return best;
+        }
+    }
+    return d;
+}
+
+// ------------------------------------------------------------------------------------------
+// Cell index of the projection of a stop point onto dD (FP64).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int clamp_index(double v, int n)
+{
+    const double f = __builtin_floor(v);
+    if (!(f >= 0.0)) return 0;  // also catches NaN
+    if (f > static_cast<double>(n - 1)) return n - 1;
+    return static_cast<int>(f);
+}
+
+// Arc of angle theta in (-pi, pi] among n equal arcs counted counter-clockwise from angle 0.
+__device__ __forceinline__ int arc_of(double theta, int n)
+{
+#pragma clang fp contract(off)
+    if (theta < 0.0) theta += kTwoPi;
+    return clamp_index(theta * static_cast<double>(n) / kTwoPi, n);
+}
+
+template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevInst &I, const double *x,
+                                                                      const PolySeg *segs)
+{
+#pragma clang fp contract(off)
+    if constexpr (KIND == kDisk) {
+        return arc_of(atan2(x[1] - I.p[1], x[0] - I.p[0]), I.layout[0]);
+    } else if constexpr (KIND == kAnnulus) {
+        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
+        const double rho = __builtin_sqrt(dx * dx + dy * dy);
+        const double th = atan2(dy, dx);
+        if (I.p[3] - rho <= rho - I.p[2]) return arc_of(th, I.layout[0]);
+        return I.layout[0] + arc_of(th, I.layout[1]);
+    } else if constexpr (KIND == kEllipse) {
+        const double u = (x[0] - I.p[0]) / I.p[2], v = (x[1] - I.p[1]) / I.p[3];
+        return arc_of(atan2(v, u), I.layout[0]);
+    } else if constexpr (KIND == kPolygon) {
+        double best = __builtin_inf(), tb = 0.0;
+        int eb = 0;
+        for (int e = 0; e < I.n_verts; ++e) {
+            double t;
+            const double d = __builtin_sqrt(seg_dist_sq<double>(segs[e].ax, segs[e].ay, segs[e].ex,
+                                                                segs[e].ey, segs[e].ll, x[0], x[1], &t));
+            if (d < best) { best = d; eb = e; tb = t; }
+        }
+        const double s_at = segs[eb].cum + tb * segs[eb].len;
+        return clamp_index(s_at * static_cast<double>(I.layout[0]) / I.perim, I.layout[0]);
+    } else if constexpr (KIND == kBall) {
+        double v[3], s = 0.0;
+        for (int a = 0; a < 3; ++a) { v[a] = x[a] - I.p[a]; s += v[a] * v[a]; }
+        const double zc = v[2] / __builtin_sqrt(s);
+        const int nz = I.layout[0], nphi = I.layout[1];
+        const int iz = clamp_index((1.0 - zc) * 0.5 * static_cast<double>(nz), nz);
+        return iz * nphi + arc_of(atan2(v[1], v[0]), nphi);
+    } else {  // kBox
+        const int n = I.layout[0];
+        double best = __builtin_inf();
+        int fb = 0;
+        for (int f = 0; f < 2 * DIM; ++f) {
+            const int a = f >> 1;
+            const double df = (f & 1) == 0 ? x[a] - I.p[a] : I.p[DIM + a] - x[a];
+            if (df < best) { best = df; fb = f; }
+        }
+        const int a = fb >> 1;
+        int idx = 0;
+        for (int b = 0; b < DIM; ++b) {
+            if (b == a) continue;
+            const double lo = I.p[b], hi = I.p[DIM + b];
+            idx = idx * n + clamp_index((x[b] - lo) / (hi - lo) * static_cast<double>(n), n);
+        }
+        return fb * (DIM == 2 ? n : n * n) + idx;
+    }
+}
+
+}  // namespace wos

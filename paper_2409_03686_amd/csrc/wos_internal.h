@@ -1,0 +1,51 @@
+// wos_internal.h -- declarations shared by the libwos host runtime and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wos_device.hpp"
+
+namespace wos {
+
+constexpr int kMaxSweeps = 60;
+
+// View of an SVD workspace passed by value to the linear-algebra kernels.
+struct SvdDevView {
+    int m, n, k;            // B is m x n (m = points, n = |Gamma_1|), k = min(m, n)
+    int rows, cols, colsp;  // work matrix A (rows x colsp, column-major): B, or B^T when m < n
+    int trans;
+    int n_elem, n0;         // cells of the count matrix, |Gamma_0|
+    double tol;             // Jacobi rotation threshold on |a_p.a_q| / (|a_p| |a_q|)
+    double *A, *W;          // work matrix, accumulated rotations (colsp x colsp)
+    double *s, *U, *V;      // outputs
+    double *nu, *isig1;     // nu (m), sigma_1^{-1/2} (n)
+    int32_t *g1idx, *g0idx; // Gamma_1 / Gamma_0 cell indices
+    int32_t *emap;          // cell -> Gamma_1 index (>= 0) or -(Gamma_0 index) - 1
+    double *work;           // cols + 1
+    double *q, *cvec, *phic;
+    uint32_t *rot;          // rotations per sweep (kMaxSweeps)
+    uint32_t *ctrl;         // barrier counter, error flag
+    int32_t *info;          // sweeps, error
+};
+
+struct RegDev {
+    int kind, rank;
+    double alpha, delta, tau;
+};
+
+size_t walk_queue_bytes(int precision, int dim, int block);
+const void *walk_kernel_ptr(int precision, int dim);
+hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst, uint64_t total_items,
+                        uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
+                        hipStream_t stream);
+
+hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,
+                      hipStream_t stream);
+int svd_coop_grid(int colsp, int n_cu);
+hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
+                        const double *u0, const RegDev &reg, double *u1, double *pred, int32_t *rank_out,
+                        double *alpha_out, hipStream_t stream);
+hipError_t fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t stream);
+
+}  // namespace wos
