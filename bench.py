@@ -1,0 +1,229 @@
+"""Benchmark: whole hot path on one MI355X.
+
+Workload (the configuration the metric is quoted on): 2D annulus r in [0.3, 1], K = [[1, .5],
+[.5, 2]], 128 + 128 boundary arcs, 1024 observation points, N = 1e5 walks per point, eps = 1e-4,
+FP32 walk geometry with FP64 exit test / binning, then FP64 SVD of the 1024 x 192 Gamma_1 block and
+the TSVD reconstruction (discrepancy principle) of u_1.  One step = zero counts + walk kernel +
+assembly + SVD + reconstruction, replayed as one captured HIP graph; inputs are resident in HBM.
+
+Prints one JSON line (rank 0).  Extra fields: the walk kernel alone (HIP events on its stream), the
+FP64 walk path, the roofline of the walk kernel, the CPU oracle baseline and serving latency.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU operations per sphere step of the 2D FP32 annulus walk (counted from the
+# method: Philox4x32-10 = 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor) = 80 ops per block, one block
+# per 4 steps; uniform 3; direction sin, cos, renormalisation 7; radius 1; x += r S U 6; annulus
+# distance 8; exit / cap tests and step count 4) and per walk (projection + histogram 30).
+OPS_PER_STEP_2D_FP32 = 20 + 3 + 7 + 1 + 6 + 8 + 4
+OPS_PER_WALK = 30
+# MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--walks", type=int, default=100_000)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--serve", action="store_true", help="also run the serving latency measurement")
+    p.add_argument("--serve-seconds", type=float, default=3.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
+    return p.parse_args()
+
+
+def cpu_baseline(inst, target_s):
+    """The oracle (FP64 walks + LAPACK SVD + TSVD) on a sample of the same workload: every point,
+    the first n walks, n chosen so the walks take about target_s seconds on all host cores."""
+    from oracle import linalg as ol
+    from oracle import walks as ow
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ow.build_instance(inst, walk_end=64, threads=cores)
+    cal = time.perf_counter() - t0
+    n = int(max(64, min(inst.n_walks, 64 * target_s / max(cal, 1e-3))))
+    t0 = time.perf_counter()
+    counts, st, _ = ow.build_instance(inst, walk_end=n, threads=cores)
+    t_walk = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sigma = ow.element_measures(inst.geom)
+    out = ol.assemble(counts, n, inst.geom.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+    U, s, Vt = ol.svd(out["B"])
+    g1 = inst.geom.gamma1_mask.astype(bool)
+    ol.reconstruct(U, s, Vt, sigma[g1], out["q"], kind=ol.TSVD_DISCREPANCY, delta=inst.noise_delta, tau=1.1)
+    t_lin = time.perf_counter() - t0
+    walks = st["walks"]
+    return {"value": walks / (t_walk + t_lin), "unit": "walks/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {inst.x_obs.shape[0]} points x first {n} walks (of {inst.n_walks}), FP64 walks + "
+                      f"LAPACK SVD + TSVD; walks {t_walk:.2f} s, linear algebra {t_lin:.3f} s",
+            "steps_per_s": st["steps"] / t_walk}
+
+
+def serve_latency(ctx, wos, wi, seconds, rate=200.0):
+    """Poisson arrivals of requests from the heterogeneous-instance generator (1-5 % noise, random
+    harmonic data of degree <= 6): build H + FP64 SVD + TSVD reconstruction each."""
+    import ctypes as C
+    arr = wi.cfg5_arrivals(rate=rate, duration_s=seconds, seed=5)
+    rng = np.random.default_rng(5)
+    insts = [wi.random_instance(rng, i) for i in range(len(arr))]
+    reqs, res, keep = [], [], []
+    for inst, t in zip(insts, arr):
+        r = wos.WosRequest()
+        gs = wos.geometry(inst.geom)
+        r.geom = gs
+        r.walk = wos.walk_params_of(inst)
+        x = np.ascontiguousarray(inst.x_obs)
+        m = np.ascontiguousarray(inst.geom.gamma1_mask)
+        uD, u0 = np.ascontiguousarray(inst.uD), np.ascontiguousarray(inst.u0)
+        r.x_obs_host = x.ctypes.data_as(C.POINTER(C.c_double))
+        r.n_obs = x.shape[0]
+        r.gamma1_mask_host = m.ctypes.data_as(C.POINTER(C.c_uint8))
+        r.uD_host = uD.ctypes.data_as(C.POINTER(C.c_double))
+        r.u0_host = u0.ctypes.data_as(C.POINTER(C.c_double))
+        r.reg = wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1)
+        r.arrival_s = float(t)
+        u1 = np.zeros(int(m.sum()))
+        o = wos.WosResult()
+        o.u1_host = u1.ctypes.data_as(C.POINTER(C.c_double))
+        keep += [gs, x, m, uD, u0, u1]
+        reqs.append(r)
+        res.append(o)
+    t0 = time.perf_counter()
+    out = wos.wos_serve(ctx, reqs, res, hbm_budget_bytes=32 << 30, max_inflight=16)
+    wall = time.perf_counter() - t0
+    ok = [o for o in out if o.status == 0]
+    lat = np.array([o.t_done - o.t_arrive for o in ok])
+    walks = sum(o.walks for o in ok)
+    return {"requests": len(out), "completed": len(ok), "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": walks / wall, "wall_s": wall}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import wos_inputs as wi
+    from paper_2409_03686_amd import wos
+
+    torch.cuda.set_device(0)
+    inst = wi.cfg2_annulus(n_walks=a.walks, precision=wi.FP32_GEOM_FP64_EXIT)
+    g = inst.geom
+    M = g.n_elem
+    n_obs = inst.x_obs.shape[0]
+    n1 = int(g.gamma1_mask.sum())
+    ctx = wos.wos_create(0)
+    dev = "cuda"
+    x = wos.device_inputs(inst)
+    counts = torch.zeros((n_obs, M), dtype=torch.int32, device=dev)
+    stats = torch.zeros(wos.WOS_STATS_WORDS, dtype=torch.int64, device=dev)
+    uD = torch.as_tensor(inst.uD, device=dev)
+    u0 = torch.as_tensor(inst.u0, device=dev)
+    u1 = torch.zeros(n1, dtype=torch.float64, device=dev)
+    pred = torch.zeros(n_obs, dtype=torch.float64, device=dev)
+    rank = torch.zeros(1, dtype=torch.int32, device=dev)
+    sigma = wos.wos_element_measures(g)
+    h = wos.wos_svd_create(ctx, n_obs, M, g.gamma1_mask, sigma)
+    reg = wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1)
+    job = wos.measure_job(g, wos.walk_params_of(inst), x, n_obs, counts, stats)
+    plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred, rank)
+    stream = torch.cuda.current_stream()
+
+    log("plan captured; warmup")
+    for _ in range(a.warmup):
+        wos.wos_plan_launch(plan, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        wos.wos_plan_launch(plan, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = wos.stats_dict(stats)
+    walks_step = n_obs * inst.n_walks
+    steps_step = st["steps"]
+    assert st["walks"] == walks_step, st
+    ms_step = elapsed / a.steps * 1e3
+    u1_h = u1.cpu().numpy()
+    err = float(np.abs(u1_h - inst.u_exact_g1).max() / np.abs(inst.u_exact_g1).max())
+
+    # walk kernel alone: HIP events on the launch stream
+    def time_walks(precision, reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w = wos.walk_params_of(inst, precision=precision)
+        ms = []
+        for r in range(reps + 1):
+            counts.zero_()
+            stats.zero_()
+            ev0.record(stream)
+            wos.wos_build_measure(ctx, g, w, x, n_obs, counts, stats, None, stream)
+            ev1.record(stream)
+            ev1.synchronize()
+            if r:
+                ms.append(ev0.elapsed_time(ev1))
+        return float(np.mean(ms)), wos.stats_dict(stats)
+
+    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step; timing the walk kernel alone")
+    walk_ms, st32 = time_walks(wi.FP32_GEOM_FP64_EXIT, max(3, a.steps // 2))
+    walk64_ms, st64 = time_walks(wi.FP64, 3)
+    ops = st32["steps"] * OPS_PER_STEP_2D_FP32 + st32["walks"] * OPS_PER_WALK
+    achieved = ops / (walk_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+            "kernel": "walk_kernel<float,2> (annulus)", "avg_ms": walk_ms,
+            "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
+            "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1)}
+
+    out = {
+        "metric": "walks/s (whole path: walks + SVD + TSVD reconstruction)",
+        "value": walks_step * a.steps / elapsed,
+        "unit": "walks/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "dtype_detail": "f32 walk geometry; f64 exit test, binning, SVD and reconstruction",
+        "data": "synthetic",
+        "config": {"workload": "annulus r in [0.3,1], K=[[1,.5],[.5,2]], 128+128 arcs, 1024 points uniform "
+                               "by area, N=1e5 walks/point, eps=1e-4, FP32 geometry + FP64 exit; FP64 SVD of "
+                               "the 1024x192 Gamma_1 block; TSVD (discrepancy) reconstruction of u_1",
+                   "n_obs": n_obs, "n_walks": inst.n_walks, "n_elem": M, "eps": inst.eps},
+        "sphere_steps_per_s": steps_step * a.steps / elapsed,
+        "walk_kernel": {"fp32_ms": walk_ms, "fp32_walks_per_s": walks_step / (walk_ms * 1e-3),
+                        "fp32_steps_per_s": st32["steps"] / (walk_ms * 1e-3),
+                        "fp64_ms": walk64_ms, "fp64_walks_per_s": walks_step / (walk64_ms * 1e-3),
+                        "fp64_steps_per_s": st64["steps"] / (walk64_ms * 1e-3),
+                        "fp32_fp64_evals": st32["fp64_evals"], "escapes": st32["escapes"] + st64["escapes"]},
+        "reconstruction": {"rank": int(rank.item()), "max_rel_err_u1": err},
+        "roofline": roof,
+    }
+    if a.serve:
+        log("serving run")
+        out["serving"] = serve_latency(ctx, wos, wi, a.serve_seconds)
+    if not a.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
+    wos.wos_plan_destroy(plan)
+    wos.wos_svd_destroy(ctx, h)
+    wos.wos_destroy(ctx)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -9,6 +9,8 @@
 //                or Tikhonov), u_1 = sigma^{-1/2} V (phi c), predicted data H_1 u_1 + H_0 u^0.
 // Matrix work is small next to the walks (a 1024 x 192 B at the annulus workload), so every kernel
 // is written for latency: few launches, wave-level shuffles, no host round trips.
+#include <utility>
+
 #include "wos_internal.h"
 
 namespace wos {
@@ -114,76 +116,222 @@ __device__ __forceinline__ void grid_barrier(uint32_t *counter, uint32_t *err, u
     __syncthreads();
 }
 
-__device__ __forceinline__ void pair_of(int t, int i, int colsp, int &p, int &q)
+// Round-robin ("circle") ordering: in round t of n - 1 rounds, slot i of n / 2 pairs element a with
+// element b; over a sweep every unordered pair meets exactly once.
+__device__ __forceinline__ void pair_of(int t, int i, int n, int &p, int &q)
 {
-    const int m1 = colsp - 1;
-    int a, b;
-    if (i == 0) {
-        a = 0;
-    } else {
-        a = ((i - 1 + t) % m1) + 1;
-    }
-    b = ((colsp - 2 - i + t) % m1) + 1;
+    const int m1 = n - 1;
+    const int a = i == 0 ? 0 : ((i - 1 + t) % m1) + 1;
+    const int b = ((n - 2 - i + t) % m1) + 1;
     p = a < b ? a : b;
     q = a < b ? b : a;
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(SvdDevView v)
+
+// Round-robin pair K of inner round IR of an 8-column block pair, as compile-time constants.
+template <int IR, int K> struct P8 {
+    static constexpr int a = K == 0 ? 0 : ((K - 1 + IR) % 7) + 1;
+    static constexpr int b = ((6 - K + IR) % 7) + 1;
+    static constexpr int p = a < b ? a : b;
+    static constexpr int q = a < b ? b : a;
+};
+
+// DPP move of a double (both 32-bit halves); lanes outside row_mask receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp64(double v)
 {
-    __shared__ double scratch[3 * 16];
-    __shared__ double cs[2];
-    __shared__ int flag;
-    const int npairs = v.colsp / 2;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes with VALU data movement only: quad permutes, half-row and row mirrors,
+// then row broadcasts 15 and 31 accumulate rows into row 3; lane 63 holds the total.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp64<0xB1>(v);        // quad_perm (1, 0, 3, 2)
+    v += dpp64<0x4E>(v);        // quad_perm (2, 3, 0, 1)
+    v += dpp64<0x141>(v);       // row_half_mirror
+    v += dpp64<0x140>(v);       // row_mirror
+    v += dpp64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+template <int IR, int K, int R>
+__device__ __forceinline__ double pair_dot(const double (&x)[R][8])
+{
+    constexpr int p = P8<IR, K>::p, q = P8<IR, K>::q;
+    double sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) sg = __builtin_fma(x[i][p], x[i][q], sg);
+    return sg;
+}
+
+template <int IR, int K, int R, int RW>
+__device__ __forceinline__ void pair_rotate(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8], double c,
+                                            double sn, double t, double g)
+{
+    constexpr int p = P8<IR, K>::p, q = P8<IR, K>::q;
+    if (sn != 0.0) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const double xp = x[i][p], xq = x[i][q];
+            x[i][p] = c * xp - sn * xq;
+            x[i][q] = sn * xp + c * xq;
+        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const double wp = w[i][p], wq = w[i][q];
+            w[i][p] = c * wp - sn * wq;
+            w[i][q] = sn * wp + c * wq;
+        }
+        // column norms after the rotation that zeroes g (Hestenes): |x_p|^2 - t g, |x_q|^2 + t g
+        n2[p] = n2[p] - t * g;
+        n2[q] = n2[q] + t * g;
+    }
+}
+
+// Sums NV per-wave totals across the waves of the block: lane 0 of each wave writes its totals,
+// one barrier, then every thread adds the wave totals in a fixed order (identical in all waves).
+template <int NV>
+__device__ __forceinline__ void block_totals(double (&val)[NV], double (*buf)[16], int nw)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) val[e] = wave_total(val[e]);
+    if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) buf[wid][e] = val[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        double acc = 0.0;
+        for (int w2 = 0; w2 < nw; ++w2) acc += buf[w2][e];
+        val[e] = acc;
+    }
+}
+
+// One inner round IR of the 8-column sweep: the 4 dot products g = x_p . x_q from the thread's
+// rows, block totals (one barrier), rotation parameters from the tracked norms, two-term updates
+// of the A rows and W rows held in registers.
+template <int IR, int R, int RW>
+__device__ __forceinline__ void inner_round8(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8],
+                                             double (*part)[16][16], int &nrot, double tol2, int nw)
+{
+    double g[4] = {pair_dot<IR, 0, R>(x), pair_dot<IR, 1, R>(x), pair_dot<IR, 2, R>(x), pair_dot<IR, 3, R>(x)};
+    block_totals<4>(g, part[IR & 1], nw);
+    const double a[4] = {n2[P8<IR, 0>::p], n2[P8<IR, 1>::p], n2[P8<IR, 2>::p], n2[P8<IR, 3>::p]};
+    const double b[4] = {n2[P8<IR, 0>::q], n2[P8<IR, 1>::q], n2[P8<IR, 2>::q], n2[P8<IR, 3>::q]};
+    double c[4], sn[4], tt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = 1.0;
+        sn[k] = 0.0;
+        tt[k] = 0.0;
+        if (g[k] != 0.0 && g[k] * g[k] > tol2 * a[k] * b[k]) {
+            const double zeta = (b[k] - a[k]) / (2.0 * g[k]);
+            tt[k] = (zeta >= 0.0 ? 1.0 : -1.0) / (__builtin_fabs(zeta) + __builtin_sqrt(1.0 + zeta * zeta));
+            c[k] = 1.0 / __builtin_sqrt(1.0 + tt[k] * tt[k]);
+            sn[k] = c[k] * tt[k];
+            ++nrot;
+        }
+    }
+    pair_rotate<IR, 0, R, RW>(x, w, n2, c[0], sn[0], tt[0], g[0]);
+    pair_rotate<IR, 1, R, RW>(x, w, n2, c[1], sn[1], tt[1], g[1]);
+    pair_rotate<IR, 2, R, RW>(x, w, n2, c[2], sn[2], tt[2], g[2]);
+    pair_rotate<IR, 3, R, RW>(x, w, n2, c[3], sn[3], tt[3], g[3]);
+}
+
+template <int R, int RW, int... IR>
+__device__ __forceinline__ void inner_sweep8(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8],
+                                             double (*part)[16][16], int &nrot, double tol2, int nw,
+                                             std::integer_sequence<int, IR...>)
+{
+    (inner_round8<IR, R, RW>(x, w, n2, part, nrot, tol2, nw), ...);
+}
+
+// Blocked one-sided Jacobi (Hestenes) with register-resident block pairs.
+//
+// Columns are grouped in blocks of 4; the blocks meet pairwise in round-robin order, one block pair
+// per workgroup per round, with a device-wide barrier between rounds.  A workgroup loads the 8
+// columns of its pair, rows of A and rows of W alike, into registers (thread t holds rows t, t + T,
+// ...), computes the 8 column norms, then runs one cyclic sweep over the 8 columns: in each of 7
+// inner rounds, 4 disjoint pairs get g = x_p . x_q from a DPP + LDS reduction and a pair with
+// g^2 > tol^2 |x_p|^2 |x_q|^2 is rotated by the plane rotation that zeroes g, applied as two-term
+// updates (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) to its A and W rows; the norms follow the
+// rotation analytically and are recomputed from the columns at the next load.  Fresh dot products
+// and two-term updates keep small columns accurate relative to their own size.  All waves compute
+// the same sums in the same order, so every thread takes the same decisions.  A sweep without
+// rotations ends the iteration.
+template <int R, int RW, int T>
+__global__ __launch_bounds__(T) void bjacobi_kernel(SvdDevView v)
+{
+    __shared__ double part[2][16][16];
+    __shared__ int cols[8];
+    const int nblk = v.colsp / 4;
+    const int npairs = nblk / 2;
     const int ld = v.rows;
+    const int ldw = v.colsp;
+    constexpr int nw = T >> 6;
+    const double tol2 = v.tol * v.tol;
     uint32_t gen = 0;
     uint32_t *bar = v.ctrl;
     uint32_t *err = v.ctrl + 1;
     int sweep = 0;
     for (; sweep < kMaxSweeps; ++sweep) {
-        for (int t = 0; t < v.colsp - 1; ++t) {
+        for (int t = 0; t < nblk - 1; ++t) {
             for (int pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
-                int p, q;
-                pair_of(t, pi, v.colsp, p, q);
-                double *ap = v.A + static_cast<size_t>(p) * ld;
-                double *aq = v.A + static_cast<size_t>(q) * ld;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int r = threadIdx.x; r < v.rows; r += blockDim.x) {
-                    const double x = ap[r], y = aq[r];
-                    al = __builtin_fma(x, x, al);
-                    be = __builtin_fma(y, y, be);
-                    ga = __builtin_fma(x, y, ga);
-                }
-                block_sum3(al, be, ga, scratch);
-                if (threadIdx.x == 0) {
-                    int rot = 0;
-                    if (ga != 0.0 && __builtin_fabs(ga) > v.tol * __builtin_sqrt(al) * __builtin_sqrt(be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
-                                          (__builtin_fabs(zeta) + __builtin_sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / __builtin_sqrt(1.0 + tt * tt);
-                        cs[0] = c;
-                        cs[1] = c * tt;
-                        rot = 1;
-                        atomicAdd(&v.rot[sweep], 1u);
-                    }
-                    flag = rot;
-                }
+                int P, Qb;
+                pair_of(t, pi, nblk, P, Qb);
+                if (threadIdx.x < 8) cols[threadIdx.x] = threadIdx.x < 4 ? P * 4 + threadIdx.x : Qb * 4 + threadIdx.x - 4;
                 __syncthreads();
-                if (flag) {
-                    const double c = cs[0], s = cs[1];
-                    for (int r = threadIdx.x; r < v.rows; r += blockDim.x) {
-                        const double x = ap[r], y = aq[r];
-                        ap[r] = c * x - s * y;
-                        aq[r] = s * x + c * y;
+                double x[R][8], w[RW][8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const double *ca = v.A + static_cast<size_t>(cols[j]) * ld;
+                    const double *cw = v.W + static_cast<size_t>(cols[j]) * ldw;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const int r = threadIdx.x + i * T;
+                        x[i][j] = r < ld ? ca[r] : 0.0;
                     }
-                    double *wp = v.W + static_cast<size_t>(p) * v.colsp;
-                    double *wq = v.W + static_cast<size_t>(q) * v.colsp;
-                    for (int r = threadIdx.x; r < v.colsp; r += blockDim.x) {
-                        const double x = wp[r], y = wq[r];
-                        wp[r] = c * x - s * y;
-                        wq[r] = s * x + c * y;
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) {
+                        const int r = threadIdx.x + i * T;
+                        w[i][j] = r < ldw ? cw[r] : 0.0;
                     }
                 }
+                double n2[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) acc = __builtin_fma(x[i][j], x[i][j], acc);
+                    n2[j] = acc;
+                }
+                block_totals<8>(n2, part[1], nw);
+                int nrot = 0;
+                inner_sweep8<R, RW>(x, w, n2, part, nrot, tol2, nw, std::make_integer_sequence<int, 7>{});
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    double *ca = v.A + static_cast<size_t>(cols[j]) * ld;
+                    double *cw = v.W + static_cast<size_t>(cols[j]) * ldw;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const int r = threadIdx.x + i * T;
+                        if (r < ld) ca[r] = x[i][j];
+                    }
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) {
+                        const int r = threadIdx.x + i * T;
+                        if (r < ldw) cw[r] = w[i][j];
+                    }
+                }
+                if (threadIdx.x == 0 && nrot) atomicAdd(&v.rot[sweep], static_cast<uint32_t>(nrot));
                 __syncthreads();
             }
             grid_barrier(bar, err, gridDim.x, gen);
@@ -201,6 +349,28 @@ __global__ __launch_bounds__(256) void jacobi_kernel(SvdDevView v)
                     (sweep >= kMaxSweeps && v.rot[kMaxSweeps - 1] != 0u ? 2 : 0);
     }
 }
+
+// Launch shape by the size of the work matrix: T threads, R rows of A and RW rows of W each.
+struct JacobiShape {
+    const void *fn;
+    int threads;
+};
+#define WOS_BJ(R, RW, T) JacobiShape{reinterpret_cast<const void *>(&bjacobi_kernel<R, RW, T>), T}
+static JacobiShape bjacobi_shape(int rows, int colsp)
+{
+    // one workgroup per CU: 256 threads (one wave per SIMD, up to 512 VGPRs) with R rows each
+    if (rows <= 256) return WOS_BJ(1, 1, 256);
+    if (rows <= 1024) return colsp <= 256 ? WOS_BJ(4, 1, 256) : WOS_BJ(4, 4, 256);
+    if (rows <= 2048) return colsp <= 512 ? WOS_BJ(8, 2, 256) : WOS_BJ(8, 8, 256);
+    if (rows <= 4096) {
+        if (colsp <= 1024) return WOS_BJ(16, 4, 256);
+        if (colsp <= 2048) return WOS_BJ(16, 8, 256);
+        return WOS_BJ(8, 8, 512);
+    }
+    if (rows <= 8192) return WOS_BJ(8, 8, 1024);
+    return {nullptr, 0};
+}
+#undef WOS_BJ
 
 __global__ void norms_kernel(SvdDevView v)
 {
@@ -405,11 +575,12 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     assemble_kernel<<<g, 256, 0, stream>>>(v, counts, inv_n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (v.colsp >= 2) {
+    {
         SvdDevView vv = v;
         void *args[] = {&vv};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&jacobi_kernel), dim3(coop_grid),
-                                       dim3(256), args, 0, stream);
+        const JacobiShape sh = bjacobi_shape(v.rows, v.colsp);
+        if (!sh.fn) return hipErrorInvalidValue;
+        e = hipLaunchCooperativeKernel(sh.fn, dim3(coop_grid), dim3(sh.threads), args, 0, stream);
         if (e != hipSuccess) return e;
     }
     const int gc = v.cols < 1 ? 1 : (v.cols > 2048 ? 2048 : v.cols);
@@ -418,14 +589,14 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     return hipGetLastError();
 }
 
-int svd_coop_grid(int colsp, int n_cu)
+int svd_coop_grid(int rows, int colsp, int n_cu)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&jacobi_kernel), 256, 0) !=
-            hipSuccess || per_cu < 1)
+    const JacobiShape sh = bjacobi_shape(rows, colsp);
+    if (!sh.fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sh.fn, sh.threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    int maxres = per_cu * n_cu;
-    int npairs = colsp / 2;
+    const int maxres = per_cu * n_cu;
+    int npairs = colsp / 8;
     if (npairs < 1) npairs = 1;
     return npairs < maxres ? npairs : maxres;
 }

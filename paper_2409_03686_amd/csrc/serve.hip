@@ -239,7 +239,7 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
             if (st2 != WOS_OK) return st2;
         }
         const uint64_t nw = r.walk.walk_end - r.walk.walk_begin;
-        const int grid = svd_coop_grid(L.svd.v.colsp, ctx->n_cu);
+        const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx->n_cu);
         e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, s.stream);
         double *u1 = reinterpret_cast<double *>(base + L.off_u1);
         double *pred = reinterpret_cast<double *>(base + L.off_pred);

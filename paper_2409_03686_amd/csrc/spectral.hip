@@ -93,17 +93,17 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
     v.trans = v.m < v.n ? 1 : 0;
     v.rows = v.trans ? v.n : v.m;
     v.cols = v.trans ? v.m : v.n;
-    v.colsp = v.cols + (v.cols & 1);
+    v.colsp = (v.cols + 15) & ~15;  // blocks of 8 columns, an even number of blocks
     v.n_elem = n_elem;
     v.n0 = static_cast<int>(hs.g0.size());
-    v.tol = static_cast<double>(v.rows) * 0x1.0p-53;
+    v.tol = static_cast<double>(v.rows) * 0x1.0p-52;
     hs.bytes = 0;
     // device arrays, in carve order
     const size_t sz[] = {
         carve_size(size_t(v.rows) * v.colsp, 8), carve_size(size_t(v.colsp) * v.colsp, 8), carve_size(v.k, 8),
         carve_size(size_t(v.m) * v.k, 8), carve_size(size_t(v.n) * v.k, 8), carve_size(v.m, 8),
         carve_size(v.n, 8), carve_size(hs.g1.size(), 4), carve_size(std::max<size_t>(hs.g0.size(), 1), 4),
-        carve_size(n_elem, 4), carve_size(v.cols + 1, 8), carve_size(v.m, 8), carve_size(v.k, 8),
+        carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
         carve_size(v.k, 8), carve_size(kMaxSweeps, 4), carve_size(2, 4), carve_size(2, 4)};
     for (size_t s : sz) hs.bytes += s;
     return WOS_OK;
@@ -123,7 +123,7 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     v.g1idx = carve<int32_t>(cur, hs.g1.size());
     v.g0idx = carve<int32_t>(cur, std::max<size_t>(hs.g0.size(), 1));
     v.emap = carve<int32_t>(cur, v.n_elem);
-    v.work = carve<double>(cur, v.cols + 1);
+    v.work = carve<double>(cur, v.cols + 2);
     v.q = carve<double>(cur, v.m);
     v.cvec = carve<double>(cur, v.k);
     v.phic = carve<double>(cur, v.k);
@@ -189,7 +189,7 @@ extern "C" wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem
         return set_error(WOS_EDEVICE, "SVD workspace upload failed: %s", hipGetErrorString(e));
     }
     h->v = hs.v;
-    h->coop_grid = svd_coop_grid(h->v.colsp, ctx->n_cu);
+    h->coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, ctx->n_cu);
     *out = h;
     return WOS_OK;
 }

@@ -42,7 +42,7 @@ hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst
 
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,
                       hipStream_t stream);
-int svd_coop_grid(int colsp, int n_cu);
+int svd_coop_grid(int rows, int colsp, int n_cu);
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
                         const double *u0, const RegDev &reg, double *u1, double *pred, int32_t *rank_out,
                         double *alpha_out, hipStream_t stream);

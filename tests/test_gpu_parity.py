@@ -1,0 +1,553 @@
+"""GPU parity of libwos against the CPU oracle (run on an MI355X: pytest -m gpu).
+
+* FP64 walk geometry follows the oracle's arithmetic; walks are compared one by one through the
+  per-walk trace (cell, steps) and must agree at a rate >= 0.9999 (the only admitted differences
+  come from libm vs device sin/cos/atan2 rounding); every count row must sum to N exactly.
+* FP32 walk geometry draws its own uniforms (24-bit words), so it is compared statistically: the
+  exact-binomial rules of tests/statutil.py against the closed form or against oracle counts.
+* Counts must be bit-identical across launch shapes, walk-range splits, batching and serving.
+* The SVD must match LAPACK (|s - s_ref| <= 1e-10 s_1) and the reconstruction the oracle's.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import wos_inputs as wi
+from oracle import closed_forms as cf
+from oracle import linalg as ol
+from oracle import walks as ow
+from tests import statutil
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def wos():
+    from paper_2409_03686_amd import wos as w
+    w.lib()
+    return w
+
+
+@pytest.fixture(scope="module")
+def ctx(wos):
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = wos.wos_create(0)
+    yield c
+    wos.wos_destroy(c)
+
+
+def _np(t):
+    return t.cpu().numpy().view(np.uint32) if t.dtype == torch.int32 else t.cpu().numpy()
+
+
+def _gpu(wos, ctx, inst, **kw):
+    counts, stats, tr, _ = wos.run_measure(ctx, inst, **kw)
+    torch.cuda.synchronize()
+    return _np(counts), wos.stats_dict(stats), (None if tr is None else tr.cpu().numpy())
+
+
+def _agreement(tr_gpu, tr_ref):
+    return float(np.mean(np.all(tr_gpu == tr_ref, axis=2)))
+
+
+# -------------------------------------------------------------------------- FP64: walk for walk
+
+def test_fp64_disk_walk_for_walk(wos, ctx):
+    inst = wi.cfg1_disk()
+    c, st, tr = _gpu(wos, ctx, inst, trace=True, precision=wi.FP64)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    assert np.all(c.sum(1) == inst.n_walks)
+    agree = _agreement(tr, trr)
+    print(f"disk FP64 walk agreement {agree:.7f}")
+    assert agree >= 0.9999
+    n_dis = int(round((1 - agree) * tr.shape[0] * tr.shape[1]))
+    assert np.abs(c.astype(np.int64) - cr).sum() <= 2 * n_dis
+    assert st["walks"] == sr["walks"] and st["escapes"] == 0 and st["cap_hits"] == 0
+    if agree == 1.0:
+        assert np.array_equal(c, cr) and st["steps"] == sr["steps"] and st["max_steps"] == sr["max_steps"]
+
+
+def _kind_cases():
+    rng = np.random.default_rng(21)
+    Q3 = wi.random_rotation(3, rng)
+    K3 = Q3 @ np.diag([1.0, 0.4, 0.1]) @ Q3.T
+    K2 = np.array([[1.0, 0.5], [0.5, 2.0]])
+    cases = {
+        "annulus_aniso": (wi.Geometry(2, wi.ANNULUS, (0.1, -0.05, 0.3, 1.0), (40, 24)), K2, 0),
+        "ellipse_aniso": (wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.4), (50,)), K2, 0),
+        "lshape_aniso": (wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE), K2, 0),
+        "square_exact": (wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 2.0), (9,)), K2, 1),
+        "cube_woe": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 0),
+        "cube_exact": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 1),
+        "ball_aniso": (wi.Geometry(3, wi.BALL, (0.0, 0.1, 0.0, 1.0), (6, 10)), K3, 0),
+    }
+    return cases
+
+
+@pytest.mark.parametrize("case", list(_kind_cases().keys()))
+def test_fp64_every_kind_walk_for_walk(wos, ctx, case):
+    g, K, mode = _kind_cases()[case]
+    rng = np.random.default_rng(5)
+    x = wi.sample_points(g, 37, rng)  # 37 points: not a multiple of anything
+    inst = wi.Instance(g, K, x, 777, eps=1e-4, seed=123456789012, instance_id=3, precision=wi.FP64,
+                       radius_mode=mode)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    agree = _agreement(tr, trr)
+    print(f"{case} FP64 walk agreement {agree:.7f}")
+    assert np.all(c.sum(1) == 777)
+    assert agree >= 0.999
+    assert st["escapes"] == sr["escapes"] and st["cap_hits"] == 0
+
+
+def test_fp64_full_size_annulus_sampled_rows(wos, ctx):
+    """The 1024 x 1e5 annulus workload in FP64: sampled rows recomputed by the oracle alone."""
+    inst = wi.cfg2_annulus(precision=wi.FP64)
+    c, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c.sum(1) == inst.n_walks) and st["walks"] == 1024 * inst.n_walks
+    rows = [0, 517, 1023]
+    cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed,
+                                walk_end=inst.n_walks, point_ids=rows)
+    diff = np.abs(c[rows].astype(np.int64) - cr).sum()
+    print(f"annulus FP64 sampled rows: |count difference| = {diff} over {3 * inst.n_walks} walks")
+    assert diff <= 2e-4 * 3 * inst.n_walks
+
+
+def test_fp64_full_size_cube_sampled_rows(wos, ctx):
+    inst = wi.cfg3_cube(precision=wi.FP64)
+    c, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c.sum(1) == inst.n_walks)
+    rows = [0, 2730]
+    cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed,
+                                radius_mode=inst.radius_mode, walk_end=inst.n_walks, point_ids=rows)
+    diff = np.abs(c[rows].astype(np.int64) - cr).sum()
+    print(f"cube FP64 sampled rows: |count difference| = {diff}")
+    assert diff <= 2e-4 * 2 * inst.n_walks
+
+
+# -------------------------------------------------------------------------- FP32: statistics
+
+def _bias_2d(P, eps):
+    return 4 * eps * (1 + np.log(1 / eps)) * np.maximum(P, 1e-3) * P.shape[1] / (2 * np.pi)
+
+
+def test_fp32_disk_vs_poisson_kernel_and_oracle(wos, ctx):
+    inst = wi.cfg1_disk()
+    c, st, _ = _gpu(wos, ctx, inst, precision=wi.FP32_GEOM_FP64_EXIT)
+    assert np.all(c.sum(1) == inst.n_walks) and st["escapes"] == 0
+    P = cf.disk_H(inst.x_obs, 1.0, 64)
+    rep = statutil.vs_probabilities(c, inst.n_walks, P, bias=_bias_2d(P, inst.eps))
+    print("FP32 disk vs closed form", rep)
+    assert rep["ok"]
+    cr, _, _ = ow.build_instance(inst)
+    rep2 = statutil.two_sample(c, inst.n_walks, cr, inst.n_walks)
+    print("FP32 disk vs oracle", rep2)
+    assert rep2["ok"]
+
+
+def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
+    """The benchmark workload (1024 x 1e5, FP32 geometry) against the FP64 path on every entry
+    and against oracle rows."""
+    inst = wi.cfg2_annulus(precision=wi.FP32_GEOM_FP64_EXIT)
+    c32, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0 and st["cap_hits"] == 0
+    c64, _, _ = _gpu(wos, ctx, inst, precision=wi.FP64)
+    rep = statutil.two_sample(c32, inst.n_walks, c64, inst.n_walks)
+    print("FP32 vs FP64, 262144 entries", rep)
+    assert rep["ok"]
+    rows = [3, 700]
+    cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed + 1,
+                                walk_end=inst.n_walks, point_ids=rows)
+    rep2 = statutil.two_sample(c32[rows], inst.n_walks, cr, inst.n_walks)
+    print("FP32 vs independent oracle rows", rep2)
+    assert rep2["ok"]
+
+
+def test_fp32_cube_vs_fp64(wos, ctx):
+    inst = wi.cfg3_cube(n_walks=20_000, precision=wi.FP32_GEOM_FP64_EXIT, stride=4)
+    c32, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0
+    c64, _, _ = _gpu(wos, ctx, inst, precision=wi.FP64)
+    merge = lambda c: c.reshape(c.shape[0], 6, 6, 4, 6, 4).sum((3, 5)).reshape(c.shape[0], -1)
+    rep = statutil.two_sample(merge(c32), inst.n_walks, merge(c64), inst.n_walks)
+    print("FP32 vs FP64 cube (4x4 merged patches)", rep)
+    assert rep["ok"]
+
+
+# -------------------------------------------------------------------------- determinism
+
+@pytest.mark.parametrize("prec", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
+def test_counts_do_not_depend_on_launch_shape(wos, ctx, prec):
+    inst = wi.cfg2_annulus(n_walks=3001, n_obs=96, precision=prec)
+    outs = []
+    for block, wpl in [(256, 32), (64, 1), (1024, 3), (128, 17)]:
+        wos.wos_set_tuning(ctx, 2, -1, prec, block, wpl)
+        c, _, _ = _gpu(wos, ctx, inst)
+        outs.append(c)
+    wos.wos_set_tuning(ctx, 2, -1, prec, 256, 32)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+@pytest.mark.parametrize("prec", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
+def test_walk_range_splits_sum_exactly(wos, ctx, prec):
+    inst = wi.cfg3_cube(n_walks=2000, precision=prec, stride=16)
+    full, _, _ = _gpu(wos, ctx, inst)
+    counts, stats, _, x = wos.run_measure(ctx, inst, walk_begin=0, walk_end=613)
+    wos.run_measure(ctx, inst, walk_begin=613, walk_end=1999, counts=counts, stats=stats, x_dev=x)
+    wos.run_measure(ctx, inst, walk_begin=1999, walk_end=2000, counts=counts, stats=stats, x_dev=x)
+    torch.cuda.synchronize()
+    assert np.array_equal(full, _np(counts))
+
+
+def test_batch_equals_separate_and_oracle(wos, ctx):
+    insts = wi.cfg4_batch(n_instances=10, walk_scale=0.02, precision=wi.FP64)
+    for k, inst in enumerate(insts):  # keep the CPU side small
+        inst.x_obs = inst.x_obs[:24]
+        inst.n_walks = min(inst.n_walks, 400)
+    sep = [_gpu(wos, ctx, inst)[0] for inst in insts]
+    jobs, keep = [], []
+    for inst in insts:
+        M = wos.wos_element_count(inst.geom)
+        x = wos.device_inputs(inst)
+        cnt = torch.zeros((x.shape[0], M), dtype=torch.int32, device="cuda")
+        keep += [x, cnt]
+        jobs.append(wos.measure_job(inst.geom, wos.walk_params_of(inst), x, x.shape[0], cnt))
+    wos.wos_build_measure_batch(ctx, jobs)
+    torch.cuda.synchronize()
+    for k, inst in enumerate(insts):
+        got = _np(keep[2 * k + 1])
+        assert np.array_equal(got, sep[k]), inst.name
+        cr, _, _ = ow.build_instance(inst)
+        assert np.abs(got.astype(np.int64) - cr).sum() <= 2e-3 * got.sum() + 2, inst.name
+
+
+# -------------------------------------------------------------------------- edge cases
+
+def test_degenerate_inputs(wos, ctx):
+    g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16,))
+    x = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    cnt = torch.zeros((0, 16), dtype=torch.int32, device="cuda")
+    wos.wos_build_measure(ctx, g, wos.walk_params(np.eye(2), 1e-4, 0, 100), x, 0, cnt)  # no points
+    x1 = torch.tensor([[0.2, 0.1]], dtype=torch.float64, device="cuda")
+    c1 = torch.zeros((1, 16), dtype=torch.int32, device="cuda")
+    wos.wos_build_measure(ctx, g, wos.walk_params(np.eye(2), 1e-4, 50, 50), x1, 1, c1)  # no walks
+    torch.cuda.synchronize()
+    assert int(c1.sum()) == 0
+    # start inside the eps-shell: zero steps, all in the projection's cell; outside D: escapes
+    for prec in (wi.FP64, wi.FP32_GEOM_FP64_EXIT):
+        pts = np.array([[np.cos(0.3) * (1 - 5e-5), np.sin(0.3) * (1 - 5e-5)], [1.5, 0.0], [0.0, 0.3]])
+        inst = wi.Instance(g, np.eye(2), pts, 1001, precision=prec)
+        c, st, tr = _gpu(wos, ctx, inst, trace=True)
+        assert c[0, 0] == 1001 and c[1, 0] == 1001 and c[2].sum() == 1001
+        assert np.all(tr[0, :, 1] == 0) and np.all(tr[1, :, 1] == 0)
+        assert st["escapes"] == 1001 and st["walks"] == 3003
+    # step cap: every walk takes exactly one step
+    inst = wi.cfg1_disk(n_walks=300)
+    inst.max_steps = 1
+    c, st, _ = _gpu(wos, ctx, inst)
+    cr, sr, _ = ow.build_instance(inst)
+    assert np.all(c.sum(1) == 300) and st["steps"] == st["walks"] and st["cap_hits"] == sr["cap_hits"]
+    # the largest supported cell count
+    big = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16384,))
+    inst = wi.Instance(big, np.eye(2), np.array([[0.1, 0.2], [0.0, -0.9]]), 5000, precision=wi.FP64)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    _, _, trr = ow.build_instance(inst, trace=True)
+    assert np.all(c.sum(1) == 5000) and _agreement(tr, trr) >= 0.999
+
+
+def test_invalid_arguments_raise(wos, ctx):
+    g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16,))
+    x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
+    cnt = torch.zeros((4, 16), dtype=torch.int32, device="cuda")
+    bad = [
+        (g, wos.walk_params(np.eye(2), -1.0, 0, 10)),                      # eps <= 0
+        (g, wos.walk_params(np.array([[1, 2], [2, 1.0]]), 1e-4, 0, 10)),  # not SPD
+        (g, wos.walk_params(np.array([[1, 0.5], [0.0, 1.0]]), 1e-4, 0, 10)),  # not symmetric
+        (g, wos.walk_params(np.eye(2), 1e-4, 10, 5)),                       # empty range reversed
+        (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=1)),        # mapped-exact on a disk
+        (wi.Geometry(2, wi.ANNULUS, (0, 0, 1.0, 0.5), (4, 4)), wos.walk_params(np.eye(2), 1e-4, 0, 10)),
+        (g, wos.walk_params(np.eye(2), 1e-4, 0, (1 << 32) + 1)),
+    ]
+    for geom, w in bad:
+        with pytest.raises(wos.WosError):
+            wos.wos_build_measure(ctx, geom, w, x, 4, cnt)
+    with pytest.raises(wos.WosError):
+        wos.wos_build_measure(ctx, g, wos.walk_params(np.eye(2), 1e-4, 0, 10), x, 4, None)
+    # FP32 geometry refuses an eps below its error bound
+    with pytest.raises(wos.WosError):
+        wos.wos_build_measure(ctx, g, wos.walk_params(np.eye(2), 1e-7, 0, 10, precision=1), x, 4, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.sum()) == 0
+
+
+# -------------------------------------------------------------------------- SVD
+
+def _svd_case(wos, ctx, counts_np, n_walks, mask, sigma):
+    m, M = counts_np.shape
+    h = wos.wos_svd_create(ctx, m, M, mask, sigma)
+    ct = torch.as_tensor(counts_np.astype(np.int64).astype(np.int32), device="cuda")
+    wos.wos_svd(ctx, h, ct, n_walks)
+    sweeps, err = wos.wos_svd_info(h)
+    U, s, V = wos.svd_factors_numpy(h)
+    return h, ct, U, s, V, sweeps, err
+
+
+def _check_svd(B, U, s, V, tag):
+    Ur, sr, Vtr = ol.svd(B)
+    k = len(sr)
+    assert U.shape == (B.shape[0], k) and V.shape == (B.shape[1], k)
+    ds = np.abs(s - sr).max() / sr[0]
+    print(f"{tag}: max |s - s_lapack| / s1 = {ds:.2e}")
+    assert ds <= 1e-10
+    big = sr >= 5e-3 * sr[0]
+    assert np.all(np.abs(s[big] - sr[big]) <= 1e-10 * sr[big])
+    assert np.all(np.diff(s) <= 0)
+    # left vectors: the Jacobi iteration leaves Gram entries below 2^-44 |B|_F^2, so
+    # |u_i . u_j| <= 1e-11 + 2^-40 |B|_F^2 / (s_i s_j)
+    # the factor built from the rotated columns (U if m >= n, else V) is orthogonal up to the
+    # iteration's floor: |x_i . x_j| <= 1e-11 + 2^-40 |B|_F^2 / (s_i s_j); the other one is a product
+    # of rotations and orthogonal to rounding
+    nz = s > 1e-13 * s[0]
+    fro2 = np.sum(B * B)
+    tolX = 1e-11 + 2.0 ** -40 * fro2 / np.outer(s[nz], s[nz])
+    X, Y = (U, V) if B.shape[0] >= B.shape[1] else (V, U)
+    assert np.all(np.abs(X[:, nz].T @ X[:, nz] - np.eye(nz.sum())) <= tolX)
+    assert np.abs(Y.T @ Y - np.eye(k)).max() < 1e-11
+    assert np.abs((U * s) @ V.T - B).max() < 1e-12 * np.abs(B).max() * max(B.shape)
+    # leading singular vectors across clear gaps (sign-free)
+    gap = np.concatenate([[np.inf], -np.diff(sr)]) / sr[0]
+    for i in range(min(k - 1, 12)):
+        if gap[i] > 1e-3 and gap[i + 1] > 1e-3:
+            assert abs(abs(U[:, i] @ Ur[:, i]) - 1) < 1e-8
+            assert abs(abs(V[:, i] @ Vtr[i]) - 1) < 1e-8
+
+
+def test_svd_matches_lapack_on_annulus_counts(wos, ctx):
+    inst = wi.cfg2_annulus(n_walks=20_000)
+    c, _, _ = _gpu(wos, ctx, inst)
+    sigma = ow.element_measures(inst.geom)
+    h, ct, U, s, V, sweeps, err = _svd_case(wos, ctx, c, inst.n_walks, inst.geom.gamma1_mask, sigma)
+    assert err == 0
+    B = ol.assemble(c, inst.n_walks, inst.geom.gamma1_mask, sigma)["B"]
+    _check_svd(B, U, s, V, f"annulus 1024x192 ({sweeps} sweeps)")
+    wos.wos_svd_destroy(ctx, h)
+
+
+@pytest.mark.parametrize("shape", [(40, 101), (33, 7), (64, 64), (200, 63)])
+def test_svd_wide_tall_odd(wos, ctx, shape):
+    m, M = shape
+    rng = np.random.default_rng(m * 1000 + M)
+    counts = rng.integers(0, 50, size=(m, M)).astype(np.uint32)
+    counts[:, 3] = 0  # an empty column
+    mask = np.ones(M, np.uint8)
+    mask[: M // 5] = 0
+    sigma = rng.uniform(0.5, 2.0, M)
+    h, ct, U, s, V, sweeps, err = _svd_case(wos, ctx, counts, 50, mask, sigma)
+    assert err == 0
+    B = ol.assemble(counts, 50, mask, sigma)["B"]
+    _check_svd(B, U, s, V, f"random {m}x{int(mask.sum())}")
+    wos.wos_svd_destroy(ctx, h)
+
+
+def test_svd_circulant_matches_fft(wos, ctx):
+    M = 48
+    t = 2 * np.pi * np.arange(M) / M
+    x = 0.6 * np.stack([np.cos(t), np.sin(t)], 1)
+    H = cf.disk_H(x, 1.0, M)
+    N = 1 << 20
+    row = np.round(H[0] * N).astype(np.int64)
+    counts = np.stack([np.roll(row, i) for i in range(M)]).astype(np.uint32)
+    sigma = np.full(M, 2 * np.pi / M)
+    h, ct, U, s, V, _, err = _svd_case(wos, ctx, counts, N, np.ones(M, np.uint8), sigma)
+    ref = np.sort(np.abs(np.fft.fft(row / N)))[::-1] / np.sqrt(M) / np.sqrt(2 * np.pi / M)
+    assert np.abs(s - ref).max() <= 1e-12 * ref[0]
+    wos.wos_svd_destroy(ctx, h)
+
+
+# -------------------------------------------------------------------------- reconstruction
+
+def _recon(wos, ctx, h, ct, n_walks, uD, u0, reg, n1, m):
+    uD_d = torch.as_tensor(uD, dtype=torch.float64, device="cuda")
+    u0_d = torch.as_tensor(u0, dtype=torch.float64, device="cuda") if len(u0) else None
+    u1 = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    pred = torch.zeros(m, dtype=torch.float64, device="cuda")
+    r = torch.zeros(1, dtype=torch.int32, device="cuda")
+    a = torch.zeros(1, dtype=torch.float64, device="cuda")
+    wos.wos_reconstruct(ctx, h, ct, n_walks, uD_d, u0_d, reg, u1, pred, r, a)
+    torch.cuda.synchronize()
+    return u1.cpu().numpy(), pred.cpu().numpy(), int(r.item()), float(a.item())
+
+
+def test_reconstruction_matches_oracle(wos, ctx):
+    inst = wi.cfg2_annulus(n_walks=20_000)
+    c, _, _ = _gpu(wos, ctx, inst)
+    g = inst.geom
+    sigma = ow.element_measures(g)
+    g1 = g.gamma1_mask.astype(bool)
+    h, ct, U, s, V, _, _ = _svd_case(wos, ctx, c, inst.n_walks, g.gamma1_mask, sigma)
+    out = ol.assemble(c, inst.n_walks, g.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+    Ur, sr, Vtr = ol.svd(out["B"])
+    n1, m = int(g1.sum()), c.shape[0]
+    gaps = -np.diff(sr) / sr[0]
+    for reg, kind in [(wos.reg_params(wos.WOS_TSVD_RANK, rank=6), ol.TSVD_RANK),
+                      (wos.reg_params(wos.WOS_TIKHONOV, alpha=1e-3 * sr[0]), ol.TIKHONOV),
+                      (wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1),
+                       ol.TSVD_DISCREPANCY),
+                      (wos.reg_params(wos.WOS_TIKHONOV, alpha=0.0, noise_delta=inst.noise_delta, tau=1.1),
+                       ol.TIKHONOV)]:
+        u1, pred, r_used, a_used = _recon(wos, ctx, h, ct, inst.n_walks, inst.uD, inst.u0, reg, n1, m)
+        u1r, rr, ar = ol.reconstruct(Ur, sr, Vtr, sigma[g1], out["q"], kind=kind, rank=reg.rank,
+                                     alpha=reg.alpha, delta=reg.noise_delta, tau=reg.tau)
+        if kind in (ol.TSVD_RANK, ol.TSVD_DISCREPANCY):
+            assert r_used == rr
+            if rr > 0 and rr < len(sr) and gaps[rr - 1] < 1e-9:
+                continue  # truncation inside a numerically degenerate pair: subspace not unique
+        else:
+            assert abs(a_used - ar) <= 1e-8 * ar
+        rel = np.abs(u1 - u1r).max() / np.abs(u1r).max()
+        # both SVDs are backward stable (the device one to about 2^-42 |B|_F); the regularised
+        # solution amplifies that by its condition number s_1 / s_r (TSVD) or s_1 / alpha (Tikhonov)
+        kappa = sr[0] / (sr[rr - 1] if kind != ol.TIKHONOV else ar)
+        tol = max(1e-10, 2.0 ** -36 * np.linalg.norm(out["B"]) / sr[0] * kappa)
+        print(f"reconstruction kind {kind}: rank {r_used} alpha {a_used:.3e} rel err vs oracle {rel:.2e} "
+              f"(tolerance {tol:.1e})")
+        assert rel <= tol
+        pr = ol.predicted_data(out["H"], g.gamma1_mask, u1r, inst.u0)
+        assert np.abs(pred - pr).max() <= tol * np.abs(pr).max()
+    wos.wos_svd_destroy(ctx, h)
+
+
+def test_exact_data_is_recovered(wos, ctx):
+    """Counts = round(H 2^26) of the exact disk measure and data generated by them: the full-rank
+    TSVD must return the boundary values that generated the data."""
+    inst = wi.cfg1_disk()
+    g = inst.geom
+    N = 1 << 26
+    counts = np.round(cf.disk_H(inst.x_obs, 1.0, 64) * N).astype(np.uint32)
+    H = counts / N
+    sigma = ow.element_measures(g)
+    g1 = g.gamma1_mask.astype(bool)
+    ubar = np.random.default_rng(4).standard_normal(64)
+    uD = H @ ubar
+    h, ct, U, s, V, _, _ = _svd_case(wos, ctx, counts, N, g.gamma1_mask, sigma)
+    u1, pred, r, _ = _recon(wos, ctx, h, ct, N, uD, ubar[~g1], wos.reg_params(wos.WOS_TSVD_RANK, rank=32), 32, 64)
+    cond = s[0] / s[-1]
+    assert r == 32
+    assert np.abs(u1 - ubar[g1]).max() <= 1e-13 * cond
+    assert np.abs(pred - uD).max() <= 1e-12
+    wos.wos_svd_destroy(ctx, h)
+
+
+# -------------------------------------------------------------------------- plans and serving
+
+def test_plan_graph_replays_match_eager(wos, ctx):
+    inst = wi.cfg2_annulus(n_walks=4000, n_obs=256)
+    g = inst.geom
+    M = g.n_elem
+    x = wos.device_inputs(inst)
+    cnt = torch.zeros((256, M), dtype=torch.int32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    sigma = ow.element_measures(g)
+    h = wos.wos_svd_create(ctx, 256, M, g.gamma1_mask, sigma)
+    uD = torch.as_tensor(inst.uD[:256], device="cuda")
+    u0 = torch.as_tensor(inst.u0, device="cuda")
+    n1 = int(g.gamma1_mask.sum())
+    u1 = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    pred = torch.zeros(256, dtype=torch.float64, device="cuda")
+    reg = wos.reg_params(wos.WOS_TSVD_RANK, rank=5)
+    job = wos.measure_job(g, wos.walk_params_of(inst), x, 256, cnt, stats)
+    plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred)
+    # eager reference
+    c_ref, _, _, _ = wos.run_measure(ctx, inst, x_dev=x)
+    h2 = wos.wos_svd_create(ctx, 256, M, g.gamma1_mask, sigma)
+    wos.wos_svd(ctx, h2, c_ref, inst.n_walks)
+    u1_ref = torch.zeros_like(u1)
+    wos.wos_reconstruct(ctx, h2, c_ref, inst.n_walks, uD, u0, reg, u1_ref)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        wos.wos_plan_launch(plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(cnt), _np(c_ref)), rep
+        assert torch.equal(u1, u1_ref), rep
+        assert int(stats[0]) == 256 * inst.n_walks
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    wos.wos_plan_destroy(plan)
+    wos.wos_svd_destroy(ctx, h)
+    wos.wos_svd_destroy(ctx, h2)
+
+
+def _requests(wos, insts, arrivals):
+    reqs, res, keep = [], [], []
+    for inst, t in zip(insts, arrivals):
+        r = wos.WosRequest()
+        gs = wos.geometry(inst.geom)
+        r.geom = gs
+        r.walk = wos.walk_params_of(inst)
+        x = np.ascontiguousarray(inst.x_obs, np.float64)
+        mask = np.ascontiguousarray(inst.geom.gamma1_mask, np.uint8)
+        uD = np.ascontiguousarray(inst.uD, np.float64)
+        u0 = np.ascontiguousarray(inst.u0, np.float64)
+        r.x_obs_host = x.ctypes.data_as(C.POINTER(C.c_double))
+        r.n_obs = x.shape[0]
+        r.gamma1_mask_host = mask.ctypes.data_as(C.POINTER(C.c_uint8))
+        r.uD_host = uD.ctypes.data_as(C.POINTER(C.c_double))
+        r.u0_host = u0.ctypes.data_as(C.POINTER(C.c_double))
+        r.reg = wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1)
+        r.arrival_s = float(t)
+        u1 = np.zeros(int(mask.sum()))
+        o = wos.WosResult()
+        o.u1_host = u1.ctypes.data_as(C.POINTER(C.c_double))
+        keep += [gs, x, mask, uD, u0, u1]
+        reqs.append(r)
+        res.append(o)
+    return reqs, res, keep
+
+
+def test_serving_results_same_alone_and_in_mix(wos, ctx):
+    rng = np.random.default_rng(55)
+    insts = [wi.random_instance(rng, i, walk_scale=0.05) for i in range(6)]
+    for inst in insts:
+        inst.x_obs, inst.uD = inst.x_obs[:200], inst.uD[:200]
+    reqs, res, keep = _requests(wos, insts, np.linspace(0, 0.01, 6))
+    out = wos.wos_serve(ctx, reqs, res, max_inflight=4)
+    mix = [np.ctypeslib.as_array(o.u1_host, shape=(int(i.geom.gamma1_mask.sum()),)).copy() for o, i in zip(out, insts)]
+    for o in out:
+        assert o.status == 0 and o.t_done >= o.t_admit >= o.t_arrive - 1e-9
+    for k, inst in enumerate(insts):
+        r1, s1, keep1 = _requests(wos, [inst], [0.0])
+        o1 = wos.wos_serve(ctx, r1, s1, max_inflight=1)
+        alone = np.ctypeslib.as_array(o1[0].u1_host, shape=mix[k].shape).copy()
+        assert o1[0].status == 0 and o1[0].walks == out[k].walks
+        assert np.array_equal(alone, mix[k]), inst.name
+
+
+def test_serving_admission_by_memory(wos, ctx):
+    rng = np.random.default_rng(56)
+    insts = [wi.random_instance(rng, i, walk_scale=0.02) for i in range(5)]
+    reqs, res, keep = _requests(wos, insts, np.zeros(5))
+    # a budget that holds about one request at a time still completes everything in order
+    out = wos.wos_serve(ctx, reqs, res, hbm_budget_bytes=64 << 20, max_inflight=8)
+    assert all(o.status in (0,) for o in out)
+    # a budget smaller than a request rejects it with WOS_ENOMEM
+    out2 = wos.wos_serve(ctx, reqs[:1], res[:1], hbm_budget_bytes=4096, max_inflight=2)
+    assert out2[0].status == wos.WOS_ENOMEM
+
+
+def test_autotune_returns_valid_shape_and_keeps_results(wos, ctx):
+    inst = wi.cfg2_annulus(n_walks=2000, n_obs=128)
+    before, _, _ = _gpu(wos, ctx, inst)
+    x = wos.device_inputs(inst)
+    cnt = torch.zeros((128, 256), dtype=torch.int32, device="cuda")
+    job = wos.measure_job(inst.geom, wos.walk_params_of(inst), x, 128, cnt)
+    block, wpl = wos.wos_autotune(ctx, job, 2000)
+    assert block in (128, 256, 512, 1024) and wpl >= 1
+    assert int(cnt.sum()) == 0  # timing runs do not touch the caller's counts
+    after, _, _ = _gpu(wos, ctx, inst)
+    assert np.array_equal(before, after)
+    wos.wos_set_tuning(ctx, 2, -1, inst.precision, 256, 32)
