@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--serve", action="store_true", help="also run the serving latency measurement")
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
+    p.add_argument("--kernel-only", action="store_true",
+                   help="for counter collection: one 1 GiB device copy (calibration), then the FP32 walk "
+                        "kernel of the workload --steps times")
     return p.parse_args()
 
 
@@ -127,6 +130,19 @@ def main():
 
     torch.cuda.set_device(0)
     inst = wi.cfg2_annulus(n_walks=a.walks, precision=wi.FP32_GEOM_FP64_EXIT)
+    if a.kernel_only:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ctx = wos.wos_create(0)
+        x = wos.device_inputs(inst)
+        for _ in range(a.steps):
+            wos.run_measure(ctx, inst, x_dev=x)
+        torch.cuda.synchronize()
+        wos.wos_destroy(ctx)
+        print(json.dumps({"kernel_only": True, "steps": a.steps, "copy_bytes": 2 * src.numel() * 8}))
+        return
     g = inst.geom
     M = g.n_elem
     n_obs = inst.x_obs.shape[0]
@@ -145,6 +161,9 @@ def main():
     h = wos.wos_svd_create(ctx, n_obs, M, g.gamma1_mask, sigma)
     reg = wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1)
     job = wos.measure_job(g, wos.walk_params_of(inst), x, n_obs, counts, stats)
+    # launch shape (threads per block, walks per lane) chosen by the autotuner on a walk sub-range
+    tuned = wos.wos_autotune(ctx, job, max(1, inst.n_walks // 5))
+    log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}")
     plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred, rank)
     stream = torch.cuda.current_stream()
 
@@ -190,7 +209,8 @@ def main():
             "frac": achieved / VALU_PEAK_OPS, "traffic": None,
             "kernel": "walk_kernel<float,2> (annulus)", "avg_ms": walk_ms,
             "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
-            "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1)}
+            "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1),
+            "launch_shape": {"block": tuned[0], "walks_per_lane": tuned[1]}}
 
     out = {
         "metric": "walks/s (whole path: walks + SVD + TSVD reconstruction)",

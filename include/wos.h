@@ -116,7 +116,7 @@ typedef struct {
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */
     int32_t radius_mode;  /* wos_radius_mode; MAPPED_EXACT only for WOS_BOX */
-    uint32_t max_steps;   /* step cap S_max (0 -> 10000); capped walks are binned where they are */
+    uint32_t max_steps;   /* step cap S_max (0 -> 10000, must be < 2^31); capped walks are binned where they are */
 } wos_walk_params;
 
 /* Random numbers: Philox4x32-10 (Salmon et al., SC'11), key (seed lo, seed hi), counter

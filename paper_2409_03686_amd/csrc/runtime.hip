@@ -344,6 +344,7 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (!(w->eps > 0) || !std::isfinite(w->eps)) return set_error(WOS_EINVAL, "eps must be finite and > 0");
     if (w->walk_end < w->walk_begin) return set_error(WOS_EINVAL, "walk_end < walk_begin");
     if (w->walk_end > (1ull << 32)) return set_error(WOS_EINVAL, "walk ids must be below 2^32");
+    if (w->max_steps >= (1u << 31)) return set_error(WOS_EINVAL, "max_steps must be below 2^31");
     if (w->precision != WOS_FP64 && w->precision != WOS_FP32_GEOM_FP64_EXIT)
         return set_error(WOS_EINVAL, "unknown precision %d", w->precision);
     if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT)

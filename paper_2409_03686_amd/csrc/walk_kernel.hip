@@ -15,6 +15,8 @@
 // Stop points are appended to a per-wave LDS queue and binned 64 at a time (full-wave FP64
 // projection), then counted in an LDS histogram row of the item's point; at the end of the item
 // the non-zero bins are flushed to the count matrix in HBM with atomics.
+#include <type_traits>
+
 #include "wos_device.hpp"
 #include "wos_internal.h"
 
@@ -47,36 +49,32 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 template <typename R, int DIM> struct Dir;
 
 template <> struct Dir<float, 2> {
-    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, float *U)
+    template <int PH> static __device__ __forceinline__ void get(const uint32_t w[4], float *U)
     {
-        const uint32_t word = phase == 0 ? w[0] : phase == 1 ? w[1] : phase == 2 ? w[2] : w[3];
-        const float u = u24(word);
-        // v_sin/v_cos take revolutions: sin(2 pi u), cos(2 pi u) without range reduction
-        const float c = __builtin_amdgcn_cosf(u), s = __builtin_amdgcn_sinf(u);
-        const float inv = __builtin_amdgcn_rsqf(c * c + s * s);
-        U[0] = c * inv;
-        U[1] = s * inv;
+        const float u = u24(w[PH]);
+        // v_sin/v_cos take revolutions: sin(2 pi u), cos(2 pi u) without range reduction; their
+        // norm error (below 2^-20) is covered by the radius shrink of the FP32 step
+        U[0] = __builtin_amdgcn_cosf(u);
+        U[1] = __builtin_amdgcn_sinf(u);
     }
 };
 template <> struct Dir<float, 3> {
-    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, float *U)
+    template <int PH> static __device__ __forceinline__ void get(const uint32_t w[4], float *U)
     {
-        const float u1 = u24(phase == 0 ? w[0] : w[2]);
-        const float u2 = u24(phase == 0 ? w[1] : w[3]);
+        const float u1 = u24(w[2 * PH]);
+        const float u2 = u24(w[2 * PH + 1]);
         const float z = 1.0f - 2.0f * u1;
         const float rho = __builtin_amdgcn_sqrtf(__builtin_fmaxf((1.0f - z) * (1.0f + z), 0.0f));
-        const float c = __builtin_amdgcn_cosf(u2), s = __builtin_amdgcn_sinf(u2);
-        const float inv = rho * __builtin_amdgcn_rsqf(c * c + s * s);
-        U[0] = c * inv;
-        U[1] = s * inv;
+        U[0] = rho * __builtin_amdgcn_cosf(u2);
+        U[1] = rho * __builtin_amdgcn_sinf(u2);
         U[2] = z;
     }
 };
 template <> struct Dir<double, 2> {
-    static __device__ __forceinline__ void get(const uint32_t w[4], int phase, double *U)
+    template <int PH> static __device__ __forceinline__ void get(const uint32_t w[4], double *U)
     {
 #pragma clang fp contract(off)
-        const double u = phase == 0 ? u53(w[0], w[1]) : u53(w[2], w[3]);
+        const double u = u53(w[2 * PH], w[2 * PH + 1]);
         const double th = kTwoPi * u;
         double s, c;
         sincos(th, &s, &c);
@@ -85,7 +83,7 @@ template <> struct Dir<double, 2> {
     }
 };
 template <> struct Dir<double, 3> {
-    static __device__ __forceinline__ void get(const uint32_t w[4], int, double *U)
+    template <int PH> static __device__ __forceinline__ void get(const uint32_t w[4], double *U)
     {
 #pragma clang fp contract(off)
         const double z = 1.0 - 2.0 * u53(w[0], w[1]);
@@ -125,17 +123,26 @@ template <int DIM> __device__ __forceinline__ void step32(const DevInst &I, floa
     }
 }
 
-// Per-wave stop queue in LDS (structure of arrays).
+// Per-wave stop queue in LDS (structure of arrays): stop position, walk offset, and the step
+// count with the cap-hit flag in bit 31.
 template <typename R, int DIM> struct StopQueue {
     R *pos;          // [DIM][kWave]
     uint32_t *koff;  // [kWave]
     uint32_t *steps; // [kWave]
 };
 
+constexpr uint32_t kCapBit = 0x80000000u;
+
+// Per-lane statistics, accumulated 64 stops at a time when a queue is flushed.
+struct LaneStats {
+    uint32_t walks = 0, cap = 0, esc = 0, fp64 = 0, max_s = 0;
+    unsigned long long steps = 0;
+};
+
 template <typename R, int DIM, int KIND>
 __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R, DIM> &q, uint32_t n,
                                             uint32_t point, uint32_t *hist, const PolySeg *segs,
-                                            uint32_t &escapes)
+                                            LaneStats &ls)
 {
     const uint32_t lane = __lane_id();
     if (lane < n) {
@@ -144,13 +151,59 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
         for (int a = 0; a < DIM; ++a) x[a] = static_cast<double>(q.pos[a * kWave + lane]);
         const int j = element64<KIND, DIM>(I, x, segs);
         atomicAdd(&hist[j], 1u);
-        if (dist64<KIND, DIM>(I, x, segs) < 0.0) escapes += 1;
+        const uint32_t sw = q.steps[lane];
+        const uint32_t st = sw & ~kCapBit;
+        ls.walks += 1;
+        ls.steps += st;
+        ls.max_s = max(ls.max_s, st);
+        ls.cap += sw >> 31;
+        if (dist64<KIND, DIM>(I, x, segs) < 0.0) ls.esc += 1;
         if (I.trace) {
             const size_t t = (static_cast<size_t>(point) * I.n_walks + q.koff[lane]) * 2;
             I.trace[t] = j;
-            I.trace[t + 1] = static_cast<int32_t>(q.steps[lane]);
+            I.trace[t + 1] = static_cast<int32_t>(st);
         }
     }
+}
+
+// One sphere step of a live walk (phase PH of its Philox block).  Returns true when the walk
+// stops: inside the eps-shell, or at the step cap (then bit 31 of s is set).
+template <typename R, int DIM, int KIND, int PH>
+__device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], R *x, R &d,
+                                          uint32_t &s, uint32_t &n_fp64)
+{
+    R U[DIM];
+    Dir<R, DIM>::template get<PH>(w, U);
+    bool fin;
+    if constexpr (sizeof(R) == 8) {
+        const double r = radius64<KIND, DIM>(I, x, d);
+        step64<DIM>(I, x, r, U);
+        d = dist64<KIND, DIM>(I, x, segs);
+        s += 1;
+        fin = !(d > I.eps);
+    } else {
+        // conservative radius: below the true distance by more than the FP32 distance error
+        // (2 delta) and the direction's norm error (relative 2^-16)
+        const float rr = radius32<KIND, DIM>(I, x, d);
+        const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, -2.0f * I.delta);
+        step32<DIM>(I, x, r, U);
+        d = dist32<KIND, DIM>(I, x, segs);
+        s += 1;
+        fin = d <= I.eps_lo;
+        if (!fin && d <= I.eps_hi) {
+            // ambiguous band: decide in FP64 at the stored position
+            double xd[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) xd[a] = static_cast<double>(x[a]);
+            fin = !(dist64<KIND, DIM>(I, xd, segs) > I.eps);
+            ++n_fp64;
+        }
+    }
+    if (!fin && s >= I.max_steps) {
+        fin = true;
+        s |= kCapBit;
+    }
+    return fin;
 }
 
 template <typename R, int DIM, int KIND>
@@ -217,106 +270,74 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t chunk_idx, u
         R d = d0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
         uint32_t qn = 0;  // wave-uniform queue length
-        uint32_t phase = 0;
-        uint32_t n_walks = 0, n_cap = 0, n_esc = 0, n_fp64 = 0, max_s = 0;
-        unsigned long long steps_sum = 0, wave_iters = 0;
+        uint32_t n_fp64 = 0;
+        unsigned long long wave_iters = 0;
+        LaneStats ls;
 
+        // One outer iteration per Philox block: refill, draw the block, then SPB unrolled steps.
         for (;;) {
-            if (phase == 0) {
-                const uint64_t need = __ballot(!live);
-                if (need != 0ull) {
-                    const uint32_t nneed = __popcll(need);
-                    const uint32_t leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
-                    uint32_t base = 0;
-                    if (lane == leader) base = atomicAdd(&sh.next, nneed);
-                    base = __shfl(base, leader);
-                    const uint32_t mine = base + __popcll(need & lanemask_lt());
-                    if (!live && mine < cnt) {
-                        live = true;
-                        koff = k0 + mine;
-                        s = 0;
-                        d = d0;
+            const uint64_t need = __ballot(!live);
+            if (need != 0ull) {
+                const uint32_t nneed = __popcll(need);
+                const uint32_t leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&sh.next, nneed);
+                base = __shfl(base, leader);
+                const uint32_t mine = base + __popcll(need & lanemask_lt());
+                if (!live && mine < cnt) {
+                    live = true;
+                    koff = k0 + mine;
+                    s = 0;
+                    d = d0;
 #pragma unroll
-                        for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+                    for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+                }
+            }
+            if (!__any(live)) break;
+            uint32_t w[4];
+            {
+                uint32_t c0 = s / SPB, c1 = I.walk_begin + koff, c2 = point, c3 = I.inst;
+                philox4x32_10(c0, c1, c2, c3, I.key0, I.key1);
+                w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+            }
+            wave_iters += SPB;
+            auto phase = [&](auto ph_tag) {
+                constexpr int PH = decltype(ph_tag)::value;
+                bool fin = false;
+                if (live) fin = walk_step<R, DIM, KIND, PH>(I, segs, w, x, d, s, n_fp64);
+                const uint64_t fmask = __ballot(fin);
+                if (fmask != 0ull) {
+                    const uint32_t nf = __popcll(fmask);
+                    if (qn + nf > static_cast<uint32_t>(kWave)) {
+                        flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, ls);
+                        qn = 0;
                     }
-                }
-                if (!__any(live)) break;
-                if (live) {
-                    uint32_t c0 = s / SPB, c1 = I.walk_begin + koff, c2 = point, c3 = I.inst;
-                    philox4x32_10(c0, c1, c2, c3, I.key0, I.key1);
-                    w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
-                }
-            } else if (!__any(live)) {
-                phase = 0;
-                continue;
-            }
-            ++wave_iters;
-            bool fin = false;
-            if (live) {
-                R U[DIM];
-                Dir<R, DIM>::get(w, static_cast<int>(phase), U);
-                if constexpr (sizeof(R) == 8) {
-                    const double r = radius64<KIND, DIM>(I, x, d);
-                    step64<DIM>(I, x, r, U);
-                    d = dist64<KIND, DIM>(I, x, segs);
-                    s += 1;
-                    fin = !(d > I.eps);
-                } else {
-                    // conservative radius: below the true distance by more than the FP32 error
-                    const float rr = radius32<KIND, DIM>(I, x, d);
-                    const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-20f, -2.0f * I.delta);
-                    step32<DIM>(I, x, r, U);
-                    d = dist32<KIND, DIM>(I, x, segs);
-                    s += 1;
-                    if (d <= I.eps_lo) {
-                        fin = true;
-                    } else if (d <= I.eps_hi) {
-                        // ambiguous band: decide in FP64 at the stored position
-                        double xd[DIM];
+                    if (fin) {
+                        const uint32_t slot = qn + __popcll(fmask & lanemask_lt());
 #pragma unroll
-                        for (int a = 0; a < DIM; ++a) xd[a] = static_cast<double>(x[a]);
-                        fin = !(dist64<KIND, DIM>(I, xd, segs) > I.eps);
-                        ++n_fp64;
+                        for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
+                        q.koff[slot] = koff;
+                        q.steps[slot] = s;
+                        live = false;
                     }
+                    qn += nf;
                 }
-                if (!fin && s >= I.max_steps) {
-                    fin = true;
-                    ++n_cap;
-                }
-                if (fin) {
-                    ++n_walks;
-                    steps_sum += s;
-                    max_s = max(max_s, s);
-                }
+            };
+            phase(std::integral_constant<int, 0>{});
+            if constexpr (SPB > 1) phase(std::integral_constant<int, 1>{});
+            if constexpr (SPB > 2) {
+                phase(std::integral_constant<int, 2>{});
+                phase(std::integral_constant<int, 3>{});
             }
-            const uint64_t fmask = __ballot(fin);
-            if (fmask != 0ull) {
-                const uint32_t nf = __popcll(fmask);
-                if (qn + nf > static_cast<uint32_t>(kWave)) {
-                    flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, n_esc);
-                    qn = 0;
-                }
-                if (fin) {
-                    const uint32_t slot = qn + __popcll(fmask & lanemask_lt());
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
-                    q.koff[slot] = koff;
-                    q.steps[slot] = s;
-                    live = false;
-                }
-                qn += nf;
-            }
-            phase = (phase + 1) & (SPB - 1);
         }
-        if (qn) flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, n_esc);
+        if (qn) flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, ls);
 
-        if (n_walks) atomicAdd(&sh.st[0], static_cast<unsigned long long>(n_walks));
-        if (steps_sum) atomicAdd(&sh.st[1], steps_sum);
-        if (max_s) atomicMax(&sh.st[2], static_cast<unsigned long long>(max_s));
-        if (n_cap) atomicAdd(&sh.st[3], static_cast<unsigned long long>(n_cap));
-        if (n_esc) atomicAdd(&sh.st[4], static_cast<unsigned long long>(n_esc));
+        if (ls.walks) atomicAdd(&sh.st[0], static_cast<unsigned long long>(ls.walks));
+        if (ls.steps) atomicAdd(&sh.st[1], ls.steps);
+        if (ls.max_s) atomicMax(&sh.st[2], static_cast<unsigned long long>(ls.max_s));
+        if (ls.cap) atomicAdd(&sh.st[3], static_cast<unsigned long long>(ls.cap));
+        if (ls.esc) atomicAdd(&sh.st[4], static_cast<unsigned long long>(ls.esc));
         if (n_fp64) atomicAdd(&sh.st[5], static_cast<unsigned long long>(n_fp64));
         if (lane == 0) atomicAdd(&sh.st[6], wave_iters * kWave);
     }
