@@ -22,14 +22,52 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU operations per sphere step of the 2D FP32 annulus walk (counted from the
-# method: Philox4x32-10 = 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor) = 80 ops per block, one block
-# per 4 steps; uniform 3; direction sin, cos, renormalisation 7; radius 1; x += r S U 6; annulus
-# distance 8; exit / cap tests and step count 4) and per walk (projection + histogram 30).
-OPS_PER_STEP_2D_FP32 = 20 + 3 + 7 + 1 + 6 + 8 + 4
+# Algorithmic 32-bit VALU operations per sphere step of the 2D FP32 annulus walk, counted from the
+# method (an FMA counts once): Philox4x32-10 = 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor) = 80 ops
+# per block, one block per 4 steps -> 20; uniform from 24 bits 3; direction cos, sin 2; shrunken
+# radius 1; x += r S U 6; annulus distance 8; exit / band / cap tests and step count 4.  Per walk:
+# FP64 projection onto the boundary + arc index + histogram 30.
+OPS_PER_STEP_2D_FP32 = 20 + 3 + 2 + 1 + 6 + 8 + 4
 OPS_PER_WALK = 30
+# Algorithmic HBM bytes per launch of the workload: observation points (2 x f64 each) read once,
+# the 1024 x 256 uint32 count rows written once, 8 statistics words.
+ALGO_BYTES_PER_POINT = 16 + 256 * 4
+# HBM traffic measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE) for the walk kernel of this
+# workload, with the hash of the kernel sources it was measured on; reported only while they match.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel_f32_annulus_1024x1e5_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2409_03686_amd", "csrc", f) for f in ("walk_kernel.hip", "wos_device.hpp")]
 # MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(shape):
+    """(bytes per launch, detail) from the committed counter summary, or (None, reason)."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None, "no counter summary"
+    rec = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    try:
+        if rec.get("kernel_sources_sha256") != kernel_sources_hash():
+            return None, "kernel changed since the counters were taken"
+        if rec.get("launch_shape") != f"{shape[0]},{shape[1]}":
+            return None, "counters were taken at another launch shape"
+        f, w = float(rec["fetch_bytes_per_launch"]), float(rec["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None, "counter summary unreadable"
+    return f + w, {"fetch_bytes": f, "write_bytes": w}
 
 
 def log(msg):
@@ -43,6 +81,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--walks", type=int, default=100_000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--autotune", action="store_true",
+                   help="time every walk launch shape first (its launches then appear in kernel traces)")
     p.add_argument("--serve", action="store_true", help="also run the serving latency measurement")
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
@@ -161,9 +201,12 @@ def main():
     h = wos.wos_svd_create(ctx, n_obs, M, g.gamma1_mask, sigma)
     reg = wos.reg_params(wos.WOS_TSVD_DISCREPANCY, noise_delta=inst.noise_delta, tau=1.1)
     job = wos.measure_job(g, wos.walk_params_of(inst), x, n_obs, counts, stats)
-    # launch shape (threads per block, walks per lane) chosen by the autotuner on a walk sub-range
-    tuned = wos.wos_autotune(ctx, job, max(1, inst.n_walks // 5))
-    log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}")
+    # launch shape (threads per block, walks per lane): the library default, or the autotuner's
+    # choice on a walk sub-range
+    tuned = (256, 16)
+    if a.autotune:
+        tuned = tuple(wos.wos_autotune(ctx, job, max(1, inst.n_walks // 5)))
+        log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}")
     plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred, rank)
     stream = torch.cuda.current_stream()
 
@@ -205,8 +248,10 @@ def main():
     walk64_ms, st64 = time_walks(wi.FP64, 3)
     ops = st32["steps"] * OPS_PER_STEP_2D_FP32 + st32["walks"] * OPS_PER_WALK
     achieved = ops / (walk_ms * 1e-3)
+    traffic, traffic_detail = measured_traffic(tuned)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-            "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+            "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "traffic_detail": traffic_detail,
+            "algorithmic_bytes": n_obs * ALGO_BYTES_PER_POINT,
             "kernel": "walk_kernel<float,2> (annulus)", "avg_ms": walk_ms,
             "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
             "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1),

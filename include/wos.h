@@ -6,13 +6,13 @@
  * The method is that of Cimpean, Grecu and Marin, "Numerical spectral analysis of Cauchy-type
  * inverse problems: a probabilistic approach" (arXiv 2409.03686):
  *   - the walk-on-ellipsoids chain X_{n+1} = X_n + dist(X_n, dD) K^{1/2} U_n with lambda_max(K) = 1
- *     (Section 3.2, eq. "wos chain"), stopped at the first n with dist(X_n, dD) <= eps
+ *     (Section 4.2, eq. "wos chain"), stopped at the first n with dist(X_n, dD) <= eps
  *     (eq. "N epsilon x");
  *   - the Monte Carlo matrix A_{omega,eps,N}[i, j] = (1/N) #{walks from x_i stopping in cell j}
- *     (Section 3.3, eq. "WoE_matrix_MC" and its Voronoi counting form; Algorithm "MC-REM");
+ *     (Section 4.3.1, eq. "WoE_matrix_MC" and its Voronoi counting form; Algorithm "MC-REM");
  *   - the scaled direct operator B = diag(nu) A_{Gamma_1} diag(sigma)^{-1/2}, its SVD, and the
  *     TSVD solution u_1 = diag(sigma)^{-1/2} B_r^+ diag(nu) b, b = u^D - A_{Gamma_0} u^0
- *     (Sections 2.3 and 3.3, eqs. "SVD", "u1r", "tsvd solution simulations"; Algorithm "Main").
+ *     (Sections 3 and 5.1, eqs. "SVD", "u1r", "tsvd solution simulations"; Algorithm "Main").
  *
  * Conventions common to every entry point
  *   - Every function returns a wos_status.  On any status other than WOS_OK, wos_last_error()
@@ -108,7 +108,7 @@ typedef enum { WOS_RADIUS_WOE_BOUND = 0, WOS_RADIUS_MAPPED_EXACT = 1 } wos_radiu
 
 typedef struct {
     double K[9];          /* conductivity, row-major, leading dim x dim block; symmetric positive
-                             definite; only K / lambda_max(K) enters the walk (Section 3.2) */
+                             definite; only K / lambda_max(K) enters the walk (Section 4.2) */
     double eps;           /* stopping shell width, > 0 */
     uint64_t walk_begin;  /* walks k in [walk_begin, walk_end) are run for every point; */
     uint64_t walk_end;    /* walk_end <= 2^32.  Splitting a range and summing is bit-exact. */

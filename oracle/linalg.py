@@ -3,16 +3,16 @@ reconstruction and residual (FP64, numpy / scipy LAPACK).
 
 TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
 
-Definitions followed (paper, Sections 2.3-3.3 and Algorithm "Main"):
+Definitions followed (paper, Sections 3, 3.1, 4.3 and Algorithm "Main" of Section 5.1):
   H        = counts / N                                    (eq. WoE_matrix_MC, Voronoi counting form)
-  nu_i     = 1 / sqrt(M_D)                                 (Section 4, equal weights, sum nu^2 = 1)
+  nu_i     = 1 / sqrt(M_D)                                 (Section 5.2, equal weights, sum nu^2 = 1)
   B        = diag(nu) H[:, Gamma_1] diag(sigma_1)^{-1/2}   (the matrix inside A^{nu,dagger,r})
   b        = u^D - H[:, Gamma_0] u^0                        (remark on non-zero Gamma_0 data)
   B        = U Sigma V^T (thin), eigenvalues of Lambda^nu = B B^T are s^2   (eq. SVD)
   u_1      = diag(sigma_1)^{-1/2} V diag(phi(s)) U^T diag(nu) b
              TSVD: phi_i = 1/s_i for i <= r, else 0        (eq. u1r / A^{nu,dagger,r})
              Tikhonov: phi_i = s_i / (s_i^2 + alpha^2)
-  u_hat^D  = H[:, Gamma_1] u_1 + H[:, Gamma_0] u^0          (residual check of Section 4 (iv))
+  u_hat^D  = H[:, Gamma_1] u_1 + H[:, Gamma_0] u^0          (residual check, Section 5.2 item (iv))
 Truncation by the discrepancy principle: smallest r with |B w_r - nu b| <= tau * delta; Tikhonov
 alpha solves |B w_alpha - nu b| = tau * delta.
 """

@@ -67,7 +67,7 @@ def make_geom(g):
 def instance_setup(K, dim):
     """lambda_max(K), Khat = K / lambda_max and S = Khat^{1/2} (symmetric principal root).
 
-    Section 3.2 takes the largest eigenvalue of K to be 1 without loss of generality; the walk
+    Section 4.2 takes the largest eigenvalue of K to be 1 without loss of generality; the walk
     X + dist * Khat^{1/2} U stays in the Euclidean ball of radius dist only under that scaling."""
     K = np.asarray(K, np.float64)[:dim, :dim]
     w, Q = np.linalg.eigh(K)

@@ -7,11 +7,11 @@
  * product path never does.  It shares no code, header, table or constant generator with the
  * HIP library: it is written from the paper and from the published Philox definition.
  *
- * What it computes (paper, Section 3 and Algorithm "MC-REM"):
+ * What it computes (paper, Section 4 and Algorithm "MC-REM" of Section 5.1):
  *   For observation point x_i and walk k:
  *     X_0 = x_i;  X_{n+1} = X_n + r(X_n) * S * U_n,  U_n uniform on the unit sphere,
  *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
- *   generality; the walk-on-ellipsoids chain, Section 3.2 eq. "wos chain"), and r(x) is the step
+ *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
  *   radius: r = dist(x, dD) ("WoE bound") or, for boxes, the largest r with x + r S B(0,1) inside D
  *   ("mapped exact").  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  The stop point is projected onto dD and the element

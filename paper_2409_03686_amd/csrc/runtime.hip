@@ -458,7 +458,7 @@ wos_tuning wos::get_tuning(wos_ctx *ctx, int dim, int kind, int precision)
     if (it != ctx->tuning.end()) return it->second;
     it = ctx->tuning.find(tune_key(dim, -1, precision));
     if (it != ctx->tuning.end()) return it->second;
-    return wos_tuning{256, 32};
+    return wos_tuning{256, 16};
 }
 
 static bool valid_tuning(const wos_tuning *t)
@@ -703,7 +703,7 @@ extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uin
     const int blocks[] = {128, 256, 512, 1024};
     const int wpls[] = {4, 8, 16, 32, 64};
     float best_ms = 1e30f;
-    wos_tuning bt{256, 32};
+    wos_tuning bt{256, 16};
     for (int b : blocks)
         for (int w : wpls) {
             wos_tuning t{b, w};

@@ -227,7 +227,7 @@ def test_oracle_disk_matches_poisson_kernel():
     assert rep["ok"], rep
     chi = statutil.row_chi2(counts, inst.n_walks, P)
     assert chi["ok"], chi
-    # mean number of steps for a start at radius 1/2 (O(log 1/eps), Section 3.2)
+    # mean number of steps for a start at radius 1/2 (O(log 1/eps), Section 4.2.1)
     assert 10 < st["steps"] / st["walks"] < 16
 
 
@@ -262,7 +262,7 @@ def test_oracle_ball_matches_poisson_kernel():
 
 
 def _sol4(K):
-    """2D-sol4 of the paper (Section 4): K-harmonic for the paper's K = [[1, .3], [.3, .4]]."""
+    """2D-sol4 of the paper (Section 5.2): K-harmonic for the paper's K = [[1, .3], [.3, .4]]."""
     def u(p):
         x1, x2 = p[:, 0], p[:, 1]
         return ((2 * K[1, 0] - K[1, 1]) / (3 * K[0, 0]) * x1 ** 3 - x1 ** 2 * x2 + x1 * x2 ** 2
@@ -375,7 +375,7 @@ def test_row_sums_threads_and_resume_exact():
 
 
 def test_scale_invariance_of_K_is_exact():
-    """Only Khat = K / lambda_max enters the walk (Section 3.2), so scaling K by a power of two
+    """Only Khat = K / lambda_max enters the walk (Section 4.2), so scaling K by a power of two
     changes nothing, bit for bit."""
     inst = wi.cfg2_annulus(n_walks=500, n_obs=48)
     a, _, _ = walks.build_instance(inst, threads=8)

@@ -15,7 +15,7 @@ Geometry kinds (codes shared by the C ABI and the oracle):
   BALL     params (cx, cy, cz, R)                  layout (n_z, n_phi)    equal-area (z, phi) cells
   BOX      params (lo_0..lo_{d-1}, hi_0..hi_{d-1}) layout (n,)            n^(d-1) patches per face
 
-The paper's problem statement (Section 2, the discrete inverse problem with interior data) fixes
+The paper's problem statement (Section 1.1, the discrete inverse problem with interior data) fixes
 what an instance holds: the domain D, its boundary split into an accessible part Gamma_0 and an
 inaccessible part Gamma_1, a constant SPD conductivity K, interior points x^D, and data u^D, u^0.
 """
