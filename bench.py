@@ -243,7 +243,20 @@ def main():
                 ms.append(ev0.elapsed_time(ev1))
         return float(np.mean(ms)), wos.stats_dict(stats)
 
-    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step; timing the walk kernel alone")
+    # the spectral step alone (assemble + SVD) on the last step's counts, HIP events on the stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    svd_ms = []
+    for r in range(4):
+        ev0.record(stream)
+        wos.wos_svd(ctx, h, counts, inst.n_walks, stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        if r:
+            svd_ms.append(ev0.elapsed_time(ev1))
+    sweeps, svd_err, method = wos.wos_svd_info(h, stream)
+    svd_info = {"ms": float(np.mean(svd_ms)), "sweeps": sweeps, "error_flag": svd_err,
+                "method": "gram" if method == wos.WOS_SVD_GRAM else "hestenes"}
+    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step; svd {svd_info}; timing the walk kernel alone")
     walk_ms, st32 = time_walks(wi.FP32_GEOM_FP64_EXIT, max(3, a.steps // 2))
     walk64_ms, st64 = time_walks(wi.FP64, 3)
     ops = st32["steps"] * OPS_PER_STEP_2D_FP32 + st32["walks"] * OPS_PER_WALK
@@ -275,6 +288,7 @@ def main():
                         "fp64_ms": walk64_ms, "fp64_walks_per_s": walks_step / (walk64_ms * 1e-3),
                         "fp64_steps_per_s": st64["steps"] / (walk64_ms * 1e-3),
                         "fp32_fp64_evals": st32["fp64_evals"], "escapes": st32["escapes"] + st64["escapes"]},
+        "svd": svd_info,
         "reconstruction": {"rank": int(rank.item()), "max_rel_err_u1": err},
         "roofline": roof,
     }

@@ -189,16 +189,25 @@ wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem,
 wos_status wos_svd_destroy(wos_ctx *ctx, wos_svd_t *h);
 
 /* Assembles B from counts_dev (n_walks walks per row) and computes its thin SVD in FP64 on the
- * device (one-sided Jacobi, Hestenes; paper eq. "SVD").  Results stay in the handle:
+ * device (paper eq. "SVD").  Results stay in the handle:
  *   U: double[m * k] column-major, s: double[k] descending, V: double[n * k] column-major.
- * s^2 are the eigenvalues of Lambda^nu = B B^T (the spectrum the paper studies). */
+ * s^2 are the eigenvalues of Lambda^nu = B B^T (the spectrum the paper studies).
+ * Method: with A = B (or B^T when m < n) and c = min(m, n) <= 192, first the Gram path: G = A^T A,
+ * a pivoted Cholesky-type factor X (X X^T = G), one-sided Jacobi on X (right vectors and s), left
+ * vectors A v / s.  Its result is kept only if the left vectors pass an orthogonality check,
+ * max_ij |u_i.u_j - delta_ij| s_i s_j <= 2^-40 s_1^2, and s_min >= 1e-3 s_1; otherwise (and for
+ * c > 192) one-sided Jacobi (Hestenes) on A itself computes the result. */
 wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts_dev, uint64_t n_walks,
                    void *stream);
 /* Device pointers and sizes of the factors (valid until the handle is destroyed). */
 wos_status wos_svd_factors(const wos_svd_t *h, const double **U_dev, const double **s_dev,
                            const double **V_dev, int32_t *m, int32_t *n, int32_t *k);
-/* Number of Jacobi sweeps of the last completed wos_svd and its error flag (0 = converged). */
-wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, void *stream);
+typedef enum { WOS_SVD_HESTENES = 0, WOS_SVD_GRAM = 1 } wos_svd_method;
+/* Of the last completed wos_svd: Jacobi sweeps and error flags (0 = converged; 1 grid barrier time-
+ * out, 2 sweep limit) of the method whose result the handle holds, and that method (any of the
+ * out-pointers may be NULL).  Synchronises `stream`. */
+wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, int32_t *method,
+                        void *stream);
 
 /* ------------------------------------------------------------------------------------------- */
 /* Reconstruction (Algorithm Main)                                                               */

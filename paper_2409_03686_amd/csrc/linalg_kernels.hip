@@ -9,6 +9,7 @@
 //                or Tikhonov), u_1 = sigma^{-1/2} V (phi c), predicted data H_1 u_1 + H_0 u^0.
 // Matrix work is small next to the walks (a 1024 x 192 B at the annulus workload), so every kernel
 // is written for latency: few launches, wave-level shuffles, no host round trips.
+#include <type_traits>
 #include <utility>
 
 #include "wos_internal.h"
@@ -84,11 +85,12 @@ __global__ void assemble_kernel(SvdDevView v, const uint32_t *__restrict__ count
     for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < wtot;
          e += static_cast<size_t>(gridDim.x) * blockDim.x)
         v.W[e] = (e % v.colsp) == (e / v.colsp) ? 1.0 : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x < kMaxSweeps + 2) {
-        if (threadIdx.x < kMaxSweeps) v.rot[threadIdx.x] = 0u;
-        else v.ctrl[threadIdx.x - kMaxSweeps] = 0u;  // barrier counter, error flag
+    if (blockIdx.x == 0) {  // rotation counters, control words, info, acceptance statistic
+        for (int t = threadIdx.x; t < 2 * kMaxSweeps; t += blockDim.x) v.rot[t] = 0u;
+        if (threadIdx.x < kCtrlWords) v.ctrl[threadIdx.x] = 0u;
+        if (threadIdx.x < kInfoWords) v.info[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *v.crit = 0ull;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) v.info[0] = 0;
 }
 
 // Device-wide barrier for a cooperative grid: arrival counter with a generation target and a
@@ -127,14 +129,21 @@ __device__ __forceinline__ void pair_of(int t, int i, int n, int &p, int &q)
     q = a < b ? b : a;
 }
 
-
-// Round-robin pair K of inner round IR of an 8-column block pair, as compile-time constants.
-template <int IR, int K> struct P8 {
-    static constexpr int a = K == 0 ? 0 : ((K - 1 + IR) % 7) + 1;
-    static constexpr int b = ((6 - K + IR) % 7) + 1;
+// Pair K of round IR of the circle ordering of N elements, as compile-time constants.
+template <int N, int IR, int K> struct PairC {
+    static constexpr int a = K == 0 ? 0 : ((K - 1 + IR) % (N - 1)) + 1;
+    static constexpr int b = ((N - 2 - K + IR) % (N - 1)) + 1;
     static constexpr int p = a < b ? a : b;
     static constexpr int q = a < b ? b : a;
 };
+
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // DPP move of a double (both 32-bit halves); lanes outside row_mask receive 0.
 template <int CTRL, int ROW_MASK = 0xF>
@@ -145,218 +154,254 @@ __device__ __forceinline__ double dpp64(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes with VALU data movement only: quad permutes, half-row and row mirrors,
-// then row broadcasts 15 and 31 accumulate rows into row 3; lane 63 holds the total.
-__device__ __forceinline__ double wave_total(double v)
-{
-    v += dpp64<0xB1>(v);        // quad_perm (1, 0, 3, 2)
-    v += dpp64<0x4E>(v);        // quad_perm (2, 3, 0, 1)
-    v += dpp64<0x141>(v);       // row_half_mirror
-    v += dpp64<0x140>(v);       // row_mirror
-    v += dpp64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
-    v += dpp64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-
-template <int IR, int K, int R>
-__device__ __forceinline__ double pair_dot(const double (&x)[R][8])
-{
-    constexpr int p = P8<IR, K>::p, q = P8<IR, K>::q;
-    double sg = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) sg = __builtin_fma(x[i][p], x[i][q], sg);
-    return sg;
-}
-
-template <int IR, int K, int R, int RW>
-__device__ __forceinline__ void pair_rotate(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8], double c,
-                                            double sn, double t, double g)
-{
-    constexpr int p = P8<IR, K>::p, q = P8<IR, K>::q;
-    if (sn != 0.0) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const double xp = x[i][p], xq = x[i][q];
-            x[i][p] = c * xp - sn * xq;
-            x[i][q] = sn * xp + c * xq;
-        }
-#pragma unroll
-        for (int i = 0; i < RW; ++i) {
-            const double wp = w[i][p], wq = w[i][q];
-            w[i][p] = c * wp - sn * wq;
-            w[i][q] = sn * wp + c * wq;
-        }
-        // column norms after the rotation that zeroes g (Hestenes): |x_p|^2 - t g, |x_q|^2 + t g
-        n2[p] = n2[p] - t * g;
-        n2[q] = n2[q] + t * g;
-    }
-}
-
-// Sums NV per-wave totals across the waves of the block: lane 0 of each wave writes its totals,
-// one barrier, then every thread adds the wave totals in a fixed order (identical in all waves).
+// Sums over the 64 lanes with VALU data movement only: quad permutes, half-row and row mirrors,
+// then row broadcasts 15 and 31 accumulate rows into row 3; lane 63 holds the totals.  The NV
+// reductions advance step by step together, so their DPP latencies overlap.
 template <int NV>
-__device__ __forceinline__ void block_totals(double (&val)[NV], double (*buf)[16], int nw)
+__device__ __forceinline__ void wave_totals(double (&v)[NV])
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int e = 0; e < NV; ++e) val[e] = wave_total(val[e]);
-    if (lane == 0) {
-#pragma unroll
-        for (int e = 0; e < NV; ++e) buf[wid][e] = val[e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < NV; ++e) {
-        double acc = 0.0;
-        for (int w2 = 0; w2 < nw; ++w2) acc += buf[w2][e];
-        val[e] = acc;
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0xB1>(v[e]); });        // quad_perm (1, 0, 3, 2)
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0x4E>(v[e]); });        // quad_perm (2, 3, 0, 1)
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0x141>(v[e]); });       // row_half_mirror
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0x140>(v[e]); });       // row_mirror
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0x142, 0xA>(v[e]); });  // row_bcast15 into rows 1, 3
+    static_for<0, NV>([&](auto e) { v[e] += dpp64<0x143, 0xC>(v[e]); });  // row_bcast31 into rows 2, 3
+    static_for<0, NV>([&](auto e) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v[e]), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v[e]), 63);
+        v[e] = __hiloint2double(hi, lo);
+    });
+}
+
+// FP64 reciprocal and inverse square root: the hardware estimates refined by two Newton steps
+// (each step squares the relative error of the estimate).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+// Plane rotation that zeroes g = x_p . x_q for the squared norms a = |x_p|^2, b = |x_q|^2
+// (Rutishauser's form): zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = c t.  c comes from a refined inverse square root, so c^2 + s^2 = 1
+// to a few ulps, which keeps the rotation orthogonal.  Requires g != 0.
+__device__ __forceinline__ void rot_params(double a, double b, double g, double &c, double &s, double &t)
+{
+    const double zeta = (b - a) * rcp64(2.0 * g);
+    const double az = __builtin_fabs(zeta);
+    const double z2 = __builtin_fma(zeta, zeta, 1.0);
+    const double t_mid = rcp64(az + z2 * rsq64(z2));
+    const double t_big = 0.5 * rcp64(az);  // |zeta| >= 2^60: 1 / (2 |zeta|) to rounding
+    const double tt = az < 0x1.0p60 ? t_mid : t_big;
+    t = zeta >= 0.0 ? tt : -tt;
+    c = rsq64(__builtin_fma(t, t, 1.0));
+    s = c * t;
+}
+
+// Sums NV per-wave values over the NW waves of the block: lane 0 of each wave writes its totals,
+// one barrier, then every thread adds the wave totals in a fixed order (identical in all waves).
+template <int NV, int NW>
+__device__ __forceinline__ void block_totals(double (&val)[NV], double (*buf)[16])
+{
+    wave_totals<NV>(val);
+    if constexpr (NW > 1) {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) static_for<0, NV>([&](auto e) { buf[wid][e] = val[e]; });
+        __syncthreads();
+        static_for<0, NV>([&](auto e) {
+            double acc = 0.0;
+            for (int w2 = 0; w2 < NW; ++w2) acc += buf[w2][e];
+            val[e] = acc;
+        });
     }
 }
 
-// One inner round IR of the 8-column sweep: the 4 dot products g = x_p . x_q from the thread's
-// rows, block totals (one barrier), rotation parameters from the tracked norms, two-term updates
-// of the A rows and W rows held in registers.
-template <int IR, int R, int RW>
-__device__ __forceinline__ void inner_round8(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8],
-                                             double (*part)[16][16], int &nrot, double tol2, int nw)
+// One round IR of the cyclic sweep over the N columns held in registers: the N/2 dot products
+// g = x_p . x_q of disjoint pairs (their reductions interleaved), block totals, then for each pair
+// with g^2 > tol^2 |x_p|^2 |x_q|^2 the rotation parameters from the tracked norms and two-term
+// updates of the rows of the work matrix (and of the accumulated rotations when RW > 0).  The
+// decisions are uniform, so a pair that is already orthogonal costs only its dot product.
+template <int N, int IR, int R, int RW, int NW>
+__device__ __forceinline__ void inner_round(double (&x)[R][N], double (&w)[RW > 0 ? RW : 1][N], double (&n2)[N],
+                                            double (*part)[16][16], int &nrot, double tol2)
 {
-    double g[4] = {pair_dot<IR, 0, R>(x), pair_dot<IR, 1, R>(x), pair_dot<IR, 2, R>(x), pair_dot<IR, 3, R>(x)};
-    block_totals<4>(g, part[IR & 1], nw);
-    const double a[4] = {n2[P8<IR, 0>::p], n2[P8<IR, 1>::p], n2[P8<IR, 2>::p], n2[P8<IR, 3>::p]};
-    const double b[4] = {n2[P8<IR, 0>::q], n2[P8<IR, 1>::q], n2[P8<IR, 2>::q], n2[P8<IR, 3>::q]};
-    double c[4], sn[4], tt[4];
+    constexpr int NPR = N / 2;
+    double g[NPR];
+    static_for<0, NPR>([&](auto kk) {
+        constexpr int p = PairC<N, IR, decltype(kk)::value>::p, q = PairC<N, IR, decltype(kk)::value>::q;
+        double sg = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        c[k] = 1.0;
-        sn[k] = 0.0;
-        tt[k] = 0.0;
-        if (g[k] != 0.0 && g[k] * g[k] > tol2 * a[k] * b[k]) {
-            const double zeta = (b[k] - a[k]) / (2.0 * g[k]);
-            tt[k] = (zeta >= 0.0 ? 1.0 : -1.0) / (__builtin_fabs(zeta) + __builtin_sqrt(1.0 + zeta * zeta));
-            c[k] = 1.0 / __builtin_sqrt(1.0 + tt[k] * tt[k]);
-            sn[k] = c[k] * tt[k];
+        for (int i = 0; i < R; ++i) sg = __builtin_fma(x[i][p], x[i][q], sg);
+        g[kk] = sg;
+    });
+    block_totals<NPR, NW>(g, part[IR & 1]);
+    static_for<0, NPR>([&](auto kk) {
+        constexpr int p = PairC<N, IR, decltype(kk)::value>::p, q = PairC<N, IR, decltype(kk)::value>::q;
+        const double a = n2[p], b = n2[q], gg = g[kk];
+        if (gg != 0.0 && gg * gg > tol2 * a * b) {
+            double c, sn, t;
+            rot_params(a, b, gg, c, sn, t);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const double xp = x[i][p], xq = x[i][q];
+                x[i][p] = c * xp - sn * xq;
+                x[i][q] = sn * xp + c * xq;
+            }
+            if constexpr (RW > 0) {
+#pragma unroll
+                for (int i = 0; i < RW; ++i) {
+                    const double wp = w[i][p], wq = w[i][q];
+                    w[i][p] = c * wp - sn * wq;
+                    w[i][q] = sn * wp + c * wq;
+                }
+            }
+            // column norms after the rotation that zeroes g (Hestenes): |x_p|^2 - t g, |x_q|^2 + t g
+            n2[p] = a - t * gg;
+            n2[q] = b + t * gg;
             ++nrot;
         }
-    }
-    pair_rotate<IR, 0, R, RW>(x, w, n2, c[0], sn[0], tt[0], g[0]);
-    pair_rotate<IR, 1, R, RW>(x, w, n2, c[1], sn[1], tt[1], g[1]);
-    pair_rotate<IR, 2, R, RW>(x, w, n2, c[2], sn[2], tt[2], g[2]);
-    pair_rotate<IR, 3, R, RW>(x, w, n2, c[3], sn[3], tt[3], g[3]);
+    });
 }
 
-template <int R, int RW, int... IR>
-__device__ __forceinline__ void inner_sweep8(double (&x)[R][8], double (&w)[RW][8], double (&n2)[8],
-                                             double (*part)[16][16], int &nrot, double tol2, int nw,
-                                             std::integer_sequence<int, IR...>)
+template <int N, int R, int RW, int NW, int... IR>
+__device__ __forceinline__ void inner_sweep(double (&x)[R][N], double (&w)[RW > 0 ? RW : 1][N], double (&n2)[N],
+                                            double (*part)[16][16], int &nrot, double tol2,
+                                            std::integer_sequence<int, IR...>)
 {
-    (inner_round8<IR, R, RW>(x, w, n2, part, nrot, tol2, nw), ...);
+    (inner_round<N, IR, R, RW, NW>(x, w, n2, part, nrot, tol2), ...);
 }
+
+// Arguments of one blocked one-sided Jacobi run.
+struct JacobiArgs {
+    double *X;             // rows x colsp work matrix, column-major, leading dimension ldx
+    double *W;             // colsp x colsp accumulated rotations (leading dimension colsp), or null
+    int rows, ldx, colsp;
+    double tol;            // rotate while g^2 > tol^2 |x_p|^2 |x_q|^2
+    uint32_t *rot;         // kMaxSweeps rotation counters
+    uint32_t *bar, *err;   // grid barrier counter, barrier time-out flag
+    int32_t *info;         // [0] sweeps, [1] error flags (1 barrier time-out, 2 not converged)
+    const uint32_t *skip;  // when non-null and *skip != 0 the kernel returns at once
+};
 
 // Blocked one-sided Jacobi (Hestenes) with register-resident block pairs.
 //
-// Columns are grouped in blocks of 4; the blocks meet pairwise in round-robin order, one block pair
-// per workgroup per round, with a device-wide barrier between rounds.  A workgroup loads the 8
-// columns of its pair, rows of A and rows of W alike, into registers (thread t holds rows t, t + T,
-// ...), computes the 8 column norms, then runs one cyclic sweep over the 8 columns: in each of 7
-// inner rounds, 4 disjoint pairs get g = x_p . x_q from a DPP + LDS reduction and a pair with
-// g^2 > tol^2 |x_p|^2 |x_q|^2 is rotated by the plane rotation that zeroes g, applied as two-term
-// updates (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) to its A and W rows; the norms follow the
-// rotation analytically and are recomputed from the columns at the next load.  Fresh dot products
-// and two-term updates keep small columns accurate relative to their own size.  All waves compute
-// the same sums in the same order, so every thread takes the same decisions.  A sweep without
-// rotations ends the iteration.
-template <int R, int RW, int T>
-__global__ __launch_bounds__(T) void bjacobi_kernel(SvdDevView v)
+// Columns are grouped in blocks of BW; the blocks meet pairwise in round-robin order, one block
+// pair per workgroup per round, with a device-wide barrier between rounds.  A workgroup loads the
+// 2 BW columns of its pair, rows of X and (if kept) rows of W alike, into registers (thread t holds
+// rows t, t + T, ...), computes their norms, then runs one cyclic sweep over them: in each of
+// 2 BW - 1 rounds, BW disjoint pairs get g = x_p . x_q from a DPP (+ LDS when T > 64) reduction and
+// a pair with g^2 > tol^2 |x_p|^2 |x_q|^2 is rotated by the plane rotation that zeroes g, applied
+// as two-term updates to its rows; the norms follow the rotation analytically and are recomputed
+// from the columns at the next load.  Fresh dot products and two-term updates keep small columns
+// accurate relative to their own size.  All waves compute the same sums in the same order, so
+// every thread takes the same decisions.  A sweep without rotations ends the iteration.
+template <int R, int RW, int T, int BW>
+__global__ __launch_bounds__(T) void jacobi_kernel(JacobiArgs J)
 {
+    constexpr int N = 2 * BW;
+    constexpr int NW = T / 64;
     __shared__ double part[2][16][16];
-    __shared__ int cols[8];
-    const int nblk = v.colsp / 4;
+    __shared__ int cols[N];
+    if (J.skip && *J.skip != 0u) return;  // uniform over the grid: written by an earlier kernel
+    const int nblk = J.colsp / BW;
     const int npairs = nblk / 2;
-    const int ld = v.rows;
-    const int ldw = v.colsp;
-    constexpr int nw = T >> 6;
-    const double tol2 = v.tol * v.tol;
+    const int ld = J.ldx;
+    const int ldw = J.colsp;
+    const double tol2 = J.tol * J.tol;
     uint32_t gen = 0;
-    uint32_t *bar = v.ctrl;
-    uint32_t *err = v.ctrl + 1;
     int sweep = 0;
     for (; sweep < kMaxSweeps; ++sweep) {
         for (int t = 0; t < nblk - 1; ++t) {
             for (int pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
                 int P, Qb;
                 pair_of(t, pi, nblk, P, Qb);
-                if (threadIdx.x < 8) cols[threadIdx.x] = threadIdx.x < 4 ? P * 4 + threadIdx.x : Qb * 4 + threadIdx.x - 4;
+                if (threadIdx.x < N) cols[threadIdx.x] = threadIdx.x < BW ? P * BW + threadIdx.x : Qb * BW + threadIdx.x - BW;
                 __syncthreads();
-                double x[R][8], w[RW][8];
+                double x[R][N], w[RW > 0 ? RW : 1][N];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const double *ca = v.A + static_cast<size_t>(cols[j]) * ld;
-                    const double *cw = v.W + static_cast<size_t>(cols[j]) * ldw;
+                for (int j = 0; j < N; ++j) {
+                    const double *ca = J.X + static_cast<size_t>(cols[j]) * ld;
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
                         const int r = threadIdx.x + i * T;
-                        x[i][j] = r < ld ? ca[r] : 0.0;
+                        x[i][j] = r < J.rows ? ca[r] : 0.0;
                     }
+                    if constexpr (RW > 0) {
+                        const double *cw = J.W + static_cast<size_t>(cols[j]) * ldw;
 #pragma unroll
-                    for (int i = 0; i < RW; ++i) {
-                        const int r = threadIdx.x + i * T;
-                        w[i][j] = r < ldw ? cw[r] : 0.0;
+                        for (int i = 0; i < RW; ++i) {
+                            const int r = threadIdx.x + i * T;
+                            w[i][j] = r < ldw ? cw[r] : 0.0;
+                        }
                     }
                 }
-                double n2[8];
+                double n2[N];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
+                for (int j = 0; j < N; ++j) {
                     double acc = 0.0;
 #pragma unroll
                     for (int i = 0; i < R; ++i) acc = __builtin_fma(x[i][j], x[i][j], acc);
                     n2[j] = acc;
                 }
-                block_totals<8>(n2, part[1], nw);
+                block_totals<N, NW>(n2, part[1]);
                 int nrot = 0;
-                inner_sweep8<R, RW>(x, w, n2, part, nrot, tol2, nw, std::make_integer_sequence<int, 7>{});
+                inner_sweep<N, R, RW, NW>(x, w, n2, part, nrot, tol2, std::make_integer_sequence<int, N - 1>{});
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    double *ca = v.A + static_cast<size_t>(cols[j]) * ld;
-                    double *cw = v.W + static_cast<size_t>(cols[j]) * ldw;
+                for (int j = 0; j < N; ++j) {
+                    double *ca = J.X + static_cast<size_t>(cols[j]) * ld;
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
                         const int r = threadIdx.x + i * T;
-                        if (r < ld) ca[r] = x[i][j];
+                        if (r < J.rows) ca[r] = x[i][j];
                     }
+                    if constexpr (RW > 0) {
+                        double *cw = J.W + static_cast<size_t>(cols[j]) * ldw;
 #pragma unroll
-                    for (int i = 0; i < RW; ++i) {
-                        const int r = threadIdx.x + i * T;
-                        if (r < ldw) cw[r] = w[i][j];
+                        for (int i = 0; i < RW; ++i) {
+                            const int r = threadIdx.x + i * T;
+                            if (r < ldw) cw[r] = w[i][j];
+                        }
                     }
                 }
-                if (threadIdx.x == 0 && nrot) atomicAdd(&v.rot[sweep], static_cast<uint32_t>(nrot));
+                if (threadIdx.x == 0 && nrot) atomicAdd(&J.rot[sweep], static_cast<uint32_t>(nrot));
                 __syncthreads();
             }
-            grid_barrier(bar, err, gridDim.x, gen);
+            grid_barrier(J.bar, J.err, gridDim.x, gen);
         }
-        const uint32_t rotated = __hip_atomic_load(&v.rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t failed = __hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t rotated = __hip_atomic_load(&J.rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t failed = __hip_atomic_load(J.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (rotated == 0u || failed) {
             ++sweep;
             break;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        v.info[0] = sweep;
-        v.info[1] = static_cast<int32_t>(__hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) |
-                    (sweep >= kMaxSweeps && v.rot[kMaxSweeps - 1] != 0u ? 2 : 0);
+        J.info[0] = sweep;
+        J.info[1] = static_cast<int32_t>(__hip_atomic_load(J.err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) |
+                    (sweep >= kMaxSweeps && J.rot[kMaxSweeps - 1] != 0u ? 2 : 0);
     }
 }
 
-// Launch shape by the size of the work matrix: T threads, R rows of A and RW rows of W each.
+// Launch shape by the size of the work matrix: T threads, R rows of X and RW rows of W each.
 struct JacobiShape {
     const void *fn;
     int threads;
+    int bw;
 };
-#define WOS_BJ(R, RW, T) JacobiShape{reinterpret_cast<const void *>(&bjacobi_kernel<R, RW, T>), T}
-static JacobiShape bjacobi_shape(int rows, int colsp)
+#define WOS_BJ(R, RW, T) JacobiShape{reinterpret_cast<const void *>(&jacobi_kernel<R, RW, T, 4>), T, 4}
+static JacobiShape jacobi_shape(int rows, int colsp)
 {
     // one workgroup per CU: 256 threads (one wave per SIMD, up to 512 VGPRs) with R rows each
     if (rows <= 256) return WOS_BJ(1, 1, 256);
@@ -368,25 +413,38 @@ static JacobiShape bjacobi_shape(int rows, int colsp)
         return WOS_BJ(8, 8, 512);
     }
     if (rows <= 8192) return WOS_BJ(8, 8, 1024);
-    return {nullptr, 0};
+    return {nullptr, 0, 4};
 }
 #undef WOS_BJ
 
-__global__ void norms_kernel(SvdDevView v)
+// The Gram path's Jacobi runs on the np x np factor, one wave per block pair, without W.
+static JacobiShape gram_jacobi_shape(int np)
+{
+    if (np == 64) return {reinterpret_cast<const void *>(&jacobi_kernel<1, 0, 64, 4>), 64, 4};
+    if (np == 128) return {reinterpret_cast<const void *>(&jacobi_kernel<2, 0, 64, 4>), 64, 4};
+    if (np == 192) return {reinterpret_cast<const void *>(&jacobi_kernel<3, 0, 64, 4>), 64, 4};
+    return {nullptr, 0, 4};
+}
+
+// Column norms out[c] = |X[:, c]| for c < ncols (one block per column).
+__global__ void colnorm_kernel(const double *__restrict__ X, int rows, int ld, int ncols, double *__restrict__ out,
+                               const uint32_t *skip)
 {
     __shared__ double scratch[16];
-    for (int c = blockIdx.x; c < v.cols; c += gridDim.x) {
-        const double *a = v.A + static_cast<size_t>(c) * v.rows;
+    if (skip && *skip != 0u) return;
+    for (int c = blockIdx.x; c < ncols; c += gridDim.x) {
+        const double *a = X + static_cast<size_t>(c) * ld;
         double acc = 0.0;
-        for (int r = threadIdx.x; r < v.rows; r += blockDim.x) acc = __builtin_fma(a[r], a[r], acc);
+        for (int r = threadIdx.x; r < rows; r += blockDim.x) acc = __builtin_fma(a[r], a[r], acc);
         acc = block_sum(acc, scratch);
-        if (threadIdx.x == 0) v.work[c] = __builtin_sqrt(acc);
+        if (threadIdx.x == 0) out[c] = __builtin_sqrt(acc);
         __syncthreads();
     }
 }
 
-__global__ void scatter_kernel(SvdDevView v)
+__global__ void scatter_kernel(SvdDevView v, const uint32_t *skip)
 {
+    if (skip && *skip != 0u) return;
     for (int c = blockIdx.x; c < v.cols; c += gridDim.x) {
         const double sc = v.work[c];
         int rank = 0;
@@ -409,6 +467,256 @@ __global__ void scatter_kernel(SvdDevView v)
             double *vv = v.V + static_cast<size_t>(rank) * v.n;
             for (int r = threadIdx.x; r < v.n; r += blockDim.x) vv[r] = a[r] * inv;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Gram path for thin work matrices (cols <= kGramMaxCols)
+//
+//   G = A^T A (MFMA), a factor X with X X^T = G by outer-product elimination with diagonal
+//   pivoting (the Cholesky factor up to a permutation of its columns), one-sided Jacobi on X:
+//   X W = Z with orthogonal columns, so G = Z Z^T and the right singular vectors of A are Z's
+//   columns over their norms s; the left ones are A v / s (MFMA).  The result is accepted when
+//   the computed left vectors are orthogonal to max_ij |u_i.u_j - delta_ij| s_i s_j <= 2^-40 s_1^2
+//   and s_min >= 10^-3 s_1 -- then VᵀAᵀAV = diag(s^2) holds to 2^-40 s_1^2 entrywise, which bounds
+//   the singular value errors -- and otherwise the Hestenes path on A runs as before.
+// ---------------------------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 tile of G = A^T A per wave: v_mfma_f64_16x16x4f64 over the rows, 4 at a time.
+// Lane l supplies A-operand (i = l % 16, k = l / 16) and B-operand (k = l / 16, j = l % 16); it
+// receives D[4 v + l / 16][l % 16] in accumulator element v.
+__global__ __launch_bounds__(256) void gram_kernel(SvdDevView v)
+{
+    const int np = v.np, nt = np / 16;
+    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (wave >= nt * nt) return;  // whole waves
+    const int i0 = (wave % nt) * 16, j0 = (wave / nt) * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const bool va = i0 + li < v.colsp, vb = j0 + li < v.colsp;
+    const double *ca = v.A + static_cast<size_t>(va ? i0 + li : 0) * v.rows;
+    const double *cb = v.A + static_cast<size_t>(vb ? j0 + li : 0) * v.rows;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < v.rows; r0 += 4) {
+        const int r = r0 + lk;
+        const double a = (va && r < v.rows) ? ca[r] : 0.0;
+        const double b = (vb && r < v.rows) ? cb[r] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v.G[static_cast<size_t>(j0 + li) * np + i0 + 4 * e + lk] = acc[e];
+}
+
+__device__ __forceinline__ double readlane64(double x, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Outer-product elimination with diagonal pivoting, G = sum_k l_k l_k^T: step k takes the column
+// j of the remaining Schur complement with the largest diagonal d, l_k = S[:, j] / sqrt(d) (zero on
+// eliminated rows), S -= l_k l_k^T.  One workgroup of 1024 threads; S stays in registers (wave w
+// holds columns CPW w .. CPW w + CPW - 1, lane l rows l + 64 i); wave 0 keeps the diagonal and
+// picks the pivots.  Stops when no diagonal exceeds np 2^-52 times the first pivot; the remaining
+// columns of X are zero.
+template <int RPL>
+__global__ __launch_bounds__(1024) void gram_chol_kernel(SvdDevView v)
+{
+    constexpr int NPD = 64 * RPL, CPW = 4 * RPL;
+    __shared__ double lcol[NPD];
+    __shared__ double piv_d;
+    __shared__ int piv_j;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double x[RPL][CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) x[i][c] = v.G[static_cast<size_t>(w * CPW + c) * NPD + lane + 64 * i];
+    uint32_t live_cols = (1u << CPW) - 1u;  // wave-uniform
+    uint32_t live_rows = (1u << RPL) - 1u;  // per lane
+    double dg[RPL];                          // wave 0: Schur diagonal of index lane + 64 i (-1: eliminated)
+    auto pick = [&]() {
+        double bv = -1.0;
+        int bi = NPD;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            if (dg[i] > bv) {
+                bv = dg[i];
+                bi = lane + 64 * i;
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            piv_d = bv;
+            piv_j = bi;
+        }
+    };
+    if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int j = lane + 64 * i;
+            dg[i] = v.G[static_cast<size_t>(j) * NPD + j];
+        }
+        pick();
+    }
+    __syncthreads();
+    const double thresh = static_cast<double>(NPD) * 0x1.0p-52 * piv_d;
+    int k = 0;
+    for (; k < NPD; ++k) {
+        const double d = piv_d;
+        const int jp = piv_j;
+        if (!(d > thresh) || jp >= NPD) break;  // uniform
+        const int wp = jp / CPW, cp = jp - wp * CPW;
+        if (w == wp) {
+            const double inv = rsq64(d);
+            static_for<0, CPW>([&](auto cc) {
+                if (decltype(cc)::value == cp) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) {
+                        const int r = lane + 64 * i;
+                        const double val = ((live_rows >> i) & 1u) ? x[i][decltype(cc)::value] * inv : 0.0;
+                        lcol[r] = val;
+                        v.L[static_cast<size_t>(k) * NPD + r] = val;
+                    }
+                }
+            });
+            live_cols &= ~(1u << cp);
+        }
+        __syncthreads();
+        if (lane == (jp & 63)) live_rows &= ~(1u << (jp >> 6));
+        double lr[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) lr[i] = lcol[lane + 64 * i];
+        static_for<0, CPW>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if (live_cols & (1u << c)) {
+                const double lj = lcol[w * CPW + c];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][c] = __builtin_fma(-lr[i], lj, x[i][c]);
+            }
+        });
+        if (w == 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int j = lane + 64 * i;
+                dg[i] = j == jp ? -1.0 : (dg[i] < 0.0 ? dg[i] : __builtin_fma(-lr[i], lr[i], dg[i]));
+            }
+            pick();
+        }
+        __syncthreads();
+    }
+    for (size_t e = static_cast<size_t>(k) * NPD + threadIdx.x; e < static_cast<size_t>(NPD) * NPD; e += 1024)
+        v.L[e] = 0.0;
+}
+
+// Singular values in descending order and the eigenvector side: one block per factor column c;
+// s[rank] = zs[c], Vs[:, rank] = Z[:, c] / zs[c] (Vs = V, or U when the work matrix is B^T).
+__global__ void gram_vside_kernel(SvdDevView v)
+{
+    double *vs = v.trans ? v.U : v.V;
+    for (int c = blockIdx.x; c < v.np; c += gridDim.x) {
+        const double sc = v.zs[c];
+        int rank = 0;
+        for (int o = 0; o < v.np; ++o) {
+            const double so = v.zs[o];
+            rank += (so > sc || (so == sc && o < c)) ? 1 : 0;
+        }
+        if (rank >= v.k) continue;
+        if (threadIdx.x == 0) v.s[rank] = sc;
+        const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+        for (int r = threadIdx.x; r < v.cols; r += blockDim.x)
+            vs[static_cast<size_t>(rank) * v.cols + r] = v.L[static_cast<size_t>(c) * v.np + r] * inv;
+    }
+}
+
+// The other side: Y = A Vs diag(1/s), rows x k, one 16 x 16 tile per wave (MFMA over the columns).
+__global__ __launch_bounds__(256) void gram_yside_kernel(SvdDevView v)
+{
+    const double *vs = v.trans ? v.U : v.V;
+    double *ys = v.trans ? v.V : v.U;
+    const int tr = (v.rows + 15) / 16, tk = (v.k + 15) / 16;
+    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (wave >= tr * tk) return;
+    const int r0 = (wave % tr) * 16, l0 = (wave / tr) * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int r = r0 + li, l = l0 + li;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < v.cols; c0 += 4) {
+        const int c = c0 + lk;
+        const double a = (r < v.rows && c < v.cols) ? v.A[static_cast<size_t>(c) * v.rows + r] : 0.0;
+        const double b = (l < v.k && c < v.cols) ? vs[static_cast<size_t>(l) * v.cols + c] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (l < v.k) {
+        const double sl = v.s[l];
+        const double inv = sl > 0.0 ? 1.0 / sl : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int rr = r0 + 4 * e + lk;
+            if (rr < v.rows) ys[static_cast<size_t>(l) * v.rows + rr] = acc[e] * inv;
+        }
+    }
+}
+
+// Acceptance statistic max_ij |y_i . y_j - delta_ij| s_i s_j / s_1^2 over the k x k Gram matrix of
+// Y (MFMA over the rows), folded into crit with an atomic max on the bit pattern.
+__global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v)
+{
+    const double *ys = v.trans ? v.V : v.U;
+    const int tk = (v.k + 15) / 16;
+    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (wave >= tk * tk) return;
+    const int i0 = (wave % tk) * 16, j0 = (wave / tk) * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const bool va = i0 + li < v.k, vb = j0 + li < v.k;
+    const double *ya = ys + static_cast<size_t>(va ? i0 + li : 0) * v.rows;
+    const double *yb = ys + static_cast<size_t>(vb ? j0 + li : 0) * v.rows;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < v.rows; r0 += 4) {
+        const int r = r0 + lk;
+        const double a = (va && r < v.rows) ? ya[r] : 0.0;
+        const double b = (vb && r < v.rows) ? yb[r] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    const double s0 = v.s[0];
+    const double inv2 = s0 > 0.0 ? 1.0 / (s0 * s0) : 0.0;
+    double dev = 0.0;
+    const int j = j0 + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 4 * e + lk;
+        if (i < v.k && j < v.k) {
+            const double d = __builtin_fabs(acc[e] - (i == j ? 1.0 : 0.0)) * v.s[i] * v.s[j] * inv2;
+            dev = (d > dev || d != d) ? d : dev;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double od = __shfl_xor(dev, o);
+        dev = (od > dev || od != od) ? od : dev;
+    }
+    if (lane == 0) atomicMax(v.crit, static_cast<unsigned long long>(__double_as_longlong(dev)));
+}
+
+__global__ void gram_accept_kernel(SvdDevView v)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double s0 = v.s[0], sk = v.s[v.k - 1];
+    const double crit = __longlong_as_double(static_cast<long long>(*v.crit));
+    const bool ok = v.info[3] == 0 && s0 > 0.0 && sk >= 1e-3 * s0 && crit <= 0x1.0p-40;
+    v.ctrl[kCtrlGramOk] = ok ? 1u : 0u;
+    if (ok) {
+        v.info[0] = v.info[2];
+        v.info[1] = 0;
+        v.info[4] = 1;
     }
 }
 
@@ -566,6 +874,30 @@ __global__ void recon_pred_kernel(SvdDevView v, const uint32_t *__restrict__ cou
 
 }  // namespace
 
+int gram_order(int cols)
+{
+    if (cols < 1 || cols > kGramMaxCols) return 0;
+    return cols <= 64 ? 64 : (cols <= 128 ? 128 : 192);
+}
+
+static int coop_blocks(const JacobiShape &sh, int npairs, int n_cu)
+{
+    int per_cu = 0;
+    if (!sh.fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sh.fn, sh.threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int maxres = per_cu * n_cu;
+    npairs = npairs < 1 ? 1 : npairs;
+    return npairs < maxres ? npairs : maxres;
+}
+
+int svd_coop_grid(int rows, int colsp, int n_cu)
+{
+    const JacobiShape sh = jacobi_shape(rows, colsp);
+    return coop_blocks(sh, colsp / (2 * sh.bw), n_cu);
+}
+
+// assemble -> [Gram path: G, factor, Jacobi on the factor, norms, V side, U side, check, accept]
+// -> Hestenes path on A (skipped when the Gram result was accepted) -> norms -> scatter.
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,
                       hipStream_t stream)
 {
@@ -575,30 +907,45 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     assemble_kernel<<<g, 256, 0, stream>>>(v, counts, inv_n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const uint32_t *skip = nullptr;
+    if (v.np > 0) {
+        const int nt = v.np / 16;
+        gram_kernel<<<(nt * nt + 3) / 4, 256, 0, stream>>>(v);
+        if (v.np == 64) gram_chol_kernel<1><<<1, 1024, 0, stream>>>(v);
+        else if (v.np == 128) gram_chol_kernel<2><<<1, 1024, 0, stream>>>(v);
+        else gram_chol_kernel<3><<<1, 1024, 0, stream>>>(v);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const JacobiShape gs = gram_jacobi_shape(v.np);
+        if (!gs.fn) return hipErrorInvalidValue;
+        JacobiArgs J{v.L, nullptr, v.np, v.np, v.np, static_cast<double>(v.np) * 0x1.0p-52,
+                     v.rot + kMaxSweeps, v.ctrl + kCtrlGramBarrier, v.ctrl + kCtrlGramError, v.info + 2, nullptr};
+        void *args[] = {&J};
+        // the factor's Jacobi needs np / 8 co-resident one-wave blocks (at most 24)
+        e = hipLaunchCooperativeKernel(gs.fn, dim3(v.np / (2 * gs.bw)), dim3(gs.threads), args, 0, stream);
+        if (e != hipSuccess) return e;
+        colnorm_kernel<<<v.np, 64, 0, stream>>>(v.L, v.np, v.np, v.np, v.zs, nullptr);
+        gram_vside_kernel<<<v.np, 64, 0, stream>>>(v);
+        const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
+        gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
+        const int tk = (v.k + 15) / 16;
+        gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v);
+        gram_accept_kernel<<<1, 64, 0, stream>>>(v);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        skip = v.ctrl + kCtrlGramOk;
+    }
     {
-        SvdDevView vv = v;
-        void *args[] = {&vv};
-        const JacobiShape sh = bjacobi_shape(v.rows, v.colsp);
+        const JacobiShape sh = jacobi_shape(v.rows, v.colsp);
         if (!sh.fn) return hipErrorInvalidValue;
+        JacobiArgs J{v.A, v.W, v.rows, v.rows, v.colsp, v.tol, v.rot, v.ctrl + kCtrlBarrier, v.ctrl + kCtrlError,
+                     v.info, skip};
+        void *args[] = {&J};
         e = hipLaunchCooperativeKernel(sh.fn, dim3(coop_grid), dim3(sh.threads), args, 0, stream);
         if (e != hipSuccess) return e;
     }
     const int gc = v.cols < 1 ? 1 : (v.cols > 2048 ? 2048 : v.cols);
-    norms_kernel<<<gc, 256, 0, stream>>>(v);
-    scatter_kernel<<<gc, 256, 0, stream>>>(v);
+    colnorm_kernel<<<gc, 256, 0, stream>>>(v.A, v.rows, v.rows, v.cols, v.work, skip);
+    scatter_kernel<<<gc, 256, 0, stream>>>(v, skip);
     return hipGetLastError();
-}
-
-int svd_coop_grid(int rows, int colsp, int n_cu)
-{
-    int per_cu = 0;
-    const JacobiShape sh = bjacobi_shape(rows, colsp);
-    if (!sh.fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sh.fn, sh.threads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const int maxres = per_cu * n_cu;
-    int npairs = colsp / 8;
-    if (npairs < 1) npairs = 1;
-    return npairs < maxres ? npairs : maxres;
 }
 
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,

@@ -97,6 +97,8 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
     v.n_elem = n_elem;
     v.n0 = static_cast<int>(hs.g0.size());
     v.tol = static_cast<double>(v.rows) * 0x1.0p-52;
+    v.np = gram_order(v.cols);
+    const size_t npn = static_cast<size_t>(v.np);
     hs.bytes = 0;
     // device arrays, in carve order
     const size_t sz[] = {
@@ -104,7 +106,8 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
         carve_size(size_t(v.m) * v.k, 8), carve_size(size_t(v.n) * v.k, 8), carve_size(v.m, 8),
         carve_size(v.n, 8), carve_size(hs.g1.size(), 4), carve_size(std::max<size_t>(hs.g0.size(), 1), 4),
         carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
-        carve_size(v.k, 8), carve_size(kMaxSweeps, 4), carve_size(2, 4), carve_size(2, 4)};
+        carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
+        carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(1, 8)};
     for (size_t s : sz) hs.bytes += s;
     return WOS_OK;
 }
@@ -127,9 +130,14 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     v.q = carve<double>(cur, v.m);
     v.cvec = carve<double>(cur, v.k);
     v.phic = carve<double>(cur, v.k);
-    v.rot = carve<uint32_t>(cur, kMaxSweeps);
-    v.ctrl = carve<uint32_t>(cur, 2);
-    v.info = carve<int32_t>(cur, 2);
+    v.rot = carve<uint32_t>(cur, 2 * kMaxSweeps);
+    v.ctrl = carve<uint32_t>(cur, kCtrlWords);
+    v.info = carve<int32_t>(cur, kInfoWords);
+    const size_t npn = static_cast<size_t>(v.np);
+    v.G = carve<double>(cur, npn * npn);
+    v.L = carve<double>(cur, npn * npn);
+    v.zs = carve<double>(cur, npn);
+    v.crit = carve<unsigned long long>(cur, 1);
 }
 
 // Bytes of pinned staging svd_upload needs.
@@ -181,8 +189,8 @@ extern "C" wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem
     if (e == hipSuccess) e = hipMemcpy(v.g1idx, hs.g1.data(), 4 * hs.g1.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !hs.g0.empty()) e = hipMemcpy(v.g0idx, hs.g0.data(), 4 * hs.g0.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(v.emap, hs.emap.data(), 4 * hs.emap.size(), hipMemcpyHostToDevice);
-    int32_t zero2[2] = {0, 0};
-    if (e == hipSuccess) e = hipMemcpy(v.info, zero2, sizeof zero2, hipMemcpyHostToDevice);
+    int32_t zero_info[kInfoWords] = {};
+    if (e == hipSuccess) e = hipMemcpy(v.info, zero_info, sizeof zero_info, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         ctx_free(ctx, h->mem, h->bytes);
         delete h;
@@ -227,15 +235,17 @@ extern "C" wos_status wos_svd_factors(const wos_svd_t *h, const double **U, cons
     return WOS_OK;
 }
 
-extern "C" wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, void *stream)
+extern "C" wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, int32_t *method,
+                                   void *stream)
 {
     if (!h) return set_error(WOS_EINVAL, "handle NULL");
-    int32_t info[2] = {0, 0};
+    int32_t info[kInfoWords] = {};
     hipError_t e = hipMemcpyAsync(info, h->v.info, sizeof info, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return set_error(WOS_EDEVICE, "reading SVD info failed: %s", hipGetErrorString(e));
     if (sweeps) *sweeps = info[0];
     if (error_flag) *error_flag = info[1];
+    if (method) *method = info[4] ? WOS_SVD_GRAM : WOS_SVD_HESTENES;
     return WOS_OK;
 }
 

@@ -11,6 +11,23 @@ namespace wos {
 constexpr int kMaxSweeps = 60;
 
 // View of an SVD workspace passed by value to the linear-algebra kernels.
+// Largest column count (after transposing wide blocks) that the Gram path handles: its
+// factorisation keeps the whole Gram matrix in the registers of one 1024-thread workgroup.
+constexpr int kGramMaxCols = 192;
+
+// Control words of an SVD (device, zeroed by the assemble kernel).
+enum SvdCtrl : int {
+    kCtrlBarrier = 0,    // grid barrier counter, Hestenes path
+    kCtrlError = 1,      // barrier time-out, Hestenes path
+    kCtrlGramBarrier = 2,
+    kCtrlGramError = 3,
+    kCtrlGramOk = 4,     // 1: the Gram path's result was accepted, the Hestenes path is skipped
+    kCtrlWords = 8
+};
+// info words: [0] sweeps, [1] error flags of the result returned; [2], [3] the same for the
+// Gram path's Jacobi stage; [4] 1 if the result came from the Gram path.
+constexpr int kInfoWords = 8;
+
 struct SvdDevView {
     int m, n, k;            // B is m x n (m = points, n = |Gamma_1|), k = min(m, n)
     int rows, cols, colsp;  // work matrix A (rows x colsp, column-major): B, or B^T when m < n
@@ -24,9 +41,15 @@ struct SvdDevView {
     int32_t *emap;          // cell -> Gamma_1 index (>= 0) or -(Gamma_0 index) - 1
     double *work;           // cols + 1
     double *q, *cvec, *phic;
-    uint32_t *rot;          // rotations per sweep (kMaxSweeps)
-    uint32_t *ctrl;         // barrier counter, error flag
-    int32_t *info;          // sweeps, error
+    uint32_t *rot;          // rotations per sweep: [0, kMaxSweeps) Hestenes, [kMaxSweeps, 2 kMaxSweeps) Gram
+    uint32_t *ctrl;         // SvdCtrl words
+    int32_t *info;          // kInfoWords
+    // Gram path (np = 0: not used for this shape)
+    int np;                 // order of the padded Gram matrix, a multiple of 64, >= cols
+    double *G;              // np x np Gram matrix A^T A
+    double *L;              // np x np factor X with X X^T = G, then its Jacobi-rotated columns
+    double *zs;             // np column norms of the rotated factor
+    unsigned long long *crit;  // acceptance statistic (bit pattern of a non-negative double)
 };
 
 struct RegDev {
@@ -43,6 +66,7 @@ hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,
                       hipStream_t stream);
 int svd_coop_grid(int rows, int colsp, int n_cu);
+int gram_order(int cols);  // np of the Gram path for this column count, 0 if it does not apply
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
                         const double *u0, const RegDev &reg, double *u1, double *pred, int32_t *rank_out,
                         double *alpha_out, hipStream_t stream);

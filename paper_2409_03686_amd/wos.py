@@ -15,6 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwos.so")
 
+WOS_SVD_HESTENES, WOS_SVD_GRAM = 0, 1
 WOS_OK, WOS_EINVAL, WOS_ENOMEM, WOS_EDEVICE, WOS_EBUSY, WOS_ETIMEOUT, WOS_ENOTSUP, WOS_ECANCELLED = range(8)
 STATUS_NAMES = ["WOS_OK", "WOS_EINVAL", "WOS_ENOMEM", "WOS_EDEVICE", "WOS_EBUSY", "WOS_ETIMEOUT",
                 "WOS_ENOTSUP", "WOS_ECANCELLED"]
@@ -97,7 +98,7 @@ _SIGS = {
     "wos_svd": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP]),
     "wos_svd_factors": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    "wos_svd_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _VP]),
+    "wos_svd_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _VP]),
     "wos_reconstruct": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP, _VP,
                                   _VP, _VP]),
     "wos_plan_create": (C.c_int, [_VP, C.POINTER(WosMeasureJob), _VP, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP,
@@ -274,9 +275,10 @@ def wos_svd_factors(h):
 
 
 def wos_svd_info(h, stream=None):
-    sw, er = C.c_int32(), C.c_int32()
-    _check(lib().wos_svd_info(h, C.byref(sw), C.byref(er), _stream(stream)))
-    return sw.value, er.value
+    """(sweeps, error flags, method) of the last SVD; method is WOS_SVD_HESTENES or WOS_SVD_GRAM."""
+    sw, er, me = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().wos_svd_info(h, C.byref(sw), C.byref(er), C.byref(me), _stream(stream)))
+    return sw.value, er.value, me.value
 
 
 def wos_reconstruct(ctx, h, counts_dev, n_walks, uD_dev, u0_dev, reg: WosRegParams, u1_dev, pred_dev=None,

@@ -291,7 +291,8 @@ def _svd_case(wos, ctx, counts_np, n_walks, mask, sigma):
     h = wos.wos_svd_create(ctx, m, M, mask, sigma)
     ct = torch.as_tensor(counts_np.astype(np.int64).astype(np.int32), device="cuda")
     wos.wos_svd(ctx, h, ct, n_walks)
-    sweeps, err = wos.wos_svd_info(h)
+    sweeps, err, method = wos.wos_svd_info(h)
+    print(f"svd {m}x{M}: {sweeps} sweeps, method {'gram' if method == wos.WOS_SVD_GRAM else 'hestenes'}, err {err}")
     U, s, V = wos.svd_factors_numpy(h)
     return h, ct, U, s, V, sweeps, err
 
@@ -332,6 +333,7 @@ def test_svd_matches_lapack_on_annulus_counts(wos, ctx):
     sigma = ow.element_measures(inst.geom)
     h, ct, U, s, V, sweeps, err = _svd_case(wos, ctx, c, inst.n_walks, inst.geom.gamma1_mask, sigma)
     assert err == 0
+    assert wos.wos_svd_info(h)[2] == wos.WOS_SVD_GRAM  # well conditioned (s_min / s_1 ~ 5e-3)
     B = ol.assemble(c, inst.n_walks, inst.geom.gamma1_mask, sigma)["B"]
     _check_svd(B, U, s, V, f"annulus 1024x192 ({sweeps} sweeps)")
     wos.wos_svd_destroy(ctx, h)
@@ -350,6 +352,32 @@ def test_svd_wide_tall_odd(wos, ctx, shape):
     assert err == 0
     B = ol.assemble(counts, 50, mask, sigma)["B"]
     _check_svd(B, U, s, V, f"random {m}x{int(mask.sum())}")
+    wos.wos_svd_destroy(ctx, h)
+
+
+@pytest.mark.parametrize("case", ["tall_gram", "wide_gram", "rank_deficient", "ill_conditioned", "too_wide_for_gram"])
+def test_svd_method_selection(wos, ctx, case):
+    """The Gram path (Cholesky-type factor of A^T A, Jacobi on it) is kept only when its left vectors
+    pass the orthogonality check and s_min >= 1e-3 s_1; otherwise, or with more than 192 columns,
+    the Hestenes path on A runs.  Both must match LAPACK."""
+    rng = np.random.default_rng(7)
+    m, M, expect = {"tall_gram": (300, 150, wos.WOS_SVD_GRAM), "wide_gram": (90, 160, wos.WOS_SVD_GRAM),
+                    "rank_deficient": (200, 120, wos.WOS_SVD_HESTENES),
+                    "ill_conditioned": (256, 96, wos.WOS_SVD_HESTENES),
+                    "too_wide_for_gram": (400, 250, wos.WOS_SVD_HESTENES)}[case]
+    counts = rng.integers(20, 60, size=(m, M)).astype(np.uint32)
+    sigma = rng.uniform(0.5, 2.0, M)
+    if case == "rank_deficient":
+        counts[:, 7] = counts[:, 3]  # two equal columns
+    if case == "ill_conditioned":
+        sigma = np.logspace(0, 12, M)  # column scales sigma^{-1/2} over six decades
+    mask = np.ones(M, np.uint8)
+    h, ct, U, s, V, sweeps, err = _svd_case(wos, ctx, counts, 60, mask, sigma)
+    assert err == 0
+    _, _, method = wos.wos_svd_info(h)
+    assert method == expect, (case, method)
+    B = ol.assemble(counts, 60, mask, sigma)["B"]
+    _check_svd(B, U, s, V, f"{case} {m}x{M} ({sweeps} sweeps)")
     wos.wos_svd_destroy(ctx, h)
 
 
