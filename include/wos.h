@@ -111,7 +111,7 @@ typedef struct {
                              definite; only K / lambda_max(K) enters the walk (Section 4.2) */
     double eps;           /* stopping shell width, > 0 */
     uint64_t walk_begin;  /* walks k in [walk_begin, walk_end) are run for every point; */
-    uint64_t walk_end;    /* walk_end <= 2^32.  Splitting a range and summing is bit-exact. */
+    uint64_t walk_end;    /* walk_end <= 2^32, walk_end - walk_begin < 2^32.  Splitting a range and summing is bit-exact. */
     uint64_t seed;        /* Philox key (low word, high word) */
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */

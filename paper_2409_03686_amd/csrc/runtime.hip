@@ -344,6 +344,7 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (!(w->eps > 0) || !std::isfinite(w->eps)) return set_error(WOS_EINVAL, "eps must be finite and > 0");
     if (w->walk_end < w->walk_begin) return set_error(WOS_EINVAL, "walk_end < walk_begin");
     if (w->walk_end > (1ull << 32)) return set_error(WOS_EINVAL, "walk ids must be below 2^32");
+    if (w->walk_end - w->walk_begin >= (1ull << 32)) return set_error(WOS_EINVAL, "at most 2^32 - 1 walks per call");
     if (w->max_steps >= (1u << 31)) return set_error(WOS_EINVAL, "max_steps must be below 2^31");
     if (w->precision != WOS_FP64 && w->precision != WOS_FP32_GEOM_FP64_EXIT)
         return set_error(WOS_EINVAL, "unknown precision %d", w->precision);
@@ -513,11 +514,15 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     for (int q = 0; q < n; ++q) {
         DevInst &I = insts[q];
         const wos_measure_job &J = jobs[idx[q]];
+        // big items of 4 chunks first, then at least 3 chunks' worth of small items per point
         I.chunk = chunk;
-        I.n_chunks = I.n_walks == 0 ? 0 : (I.n_walks + chunk - 1) / chunk;
+        I.big_chunk = 4 * chunk;
+        I.n_big = I.n_walks >= 3 * chunk + I.big_chunk ? (I.n_walks - 3 * chunk) / I.big_chunk : 0;
+        const uint32_t rest = I.n_walks - I.n_big * I.big_chunk;
+        I.n_chunks = (rest + chunk - 1) / chunk;
         I.n_obs = J.n_obs;
         I.item_begin = items;
-        I.n_items = static_cast<uint64_t>(J.n_obs) * I.n_chunks;
+        I.n_items = static_cast<uint64_t>(J.n_obs) * (I.n_big + I.n_chunks);
         items += I.n_items;
         I.x_obs = J.x_obs_dev;
         I.counts = J.counts_dev;

@@ -207,7 +207,7 @@ __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs,
 }
 
 template <typename R, int DIM, int KIND>
-__device__ void run_item(const DevInst &I, uint32_t point, uint32_t chunk_idx, uint32_t *hist,
+__device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t cnt, uint32_t *hist,
                          PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh)
 {
     constexpr int SPB = Spb<R, DIM>::v;
@@ -223,9 +223,6 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t chunk_idx, u
     if (tid < 8) sh.st[tid] = 0ull;
     if (tid == 0) sh.next = 0u;
     __syncthreads();
-
-    const uint32_t k0 = chunk_idx * I.chunk;
-    const uint32_t cnt = min(I.chunk, I.n_walks - k0);
 
     double x0d[DIM];
 #pragma unroll
@@ -387,20 +384,30 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
         const int idx = __builtin_amdgcn_readfirstlane(lo);
         const DevInst &I = insts[idx];
         const uint64_t local = item - I.item_begin;
-        const uint32_t point = static_cast<uint32_t>(local / I.n_chunks);
-        const uint32_t chunk = static_cast<uint32_t>(local % I.n_chunks);
+        const uint64_t n_big_items = static_cast<uint64_t>(I.n_obs) * I.n_big;
+        uint32_t point, k0, cnt;
+        if (local < n_big_items) {
+            point = static_cast<uint32_t>(local / I.n_big);
+            k0 = static_cast<uint32_t>(local % I.n_big) * I.big_chunk;
+            cnt = I.big_chunk;
+        } else {
+            const uint64_t l2 = local - n_big_items;
+            point = static_cast<uint32_t>(l2 / I.n_chunks);
+            k0 = I.n_big * I.big_chunk + static_cast<uint32_t>(l2 % I.n_chunks) * I.chunk;
+            cnt = min(I.chunk, I.n_walks - k0);
+        }
         if constexpr (DIM == 2) {
             switch (I.kind) {
-            case kDisk: run_item<R, 2, kDisk>(I, point, chunk, hist, lds_segs, qbase, sh); break;
-            case kAnnulus: run_item<R, 2, kAnnulus>(I, point, chunk, hist, lds_segs, qbase, sh); break;
-            case kEllipse: run_item<R, 2, kEllipse>(I, point, chunk, hist, lds_segs, qbase, sh); break;
-            case kPolygon: run_item<R, 2, kPolygon>(I, point, chunk, hist, lds_segs, qbase, sh); break;
-            default: run_item<R, 2, kBox>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            case kDisk: run_item<R, 2, kDisk>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kAnnulus: run_item<R, 2, kAnnulus>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kEllipse: run_item<R, 2, kEllipse>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kPolygon: run_item<R, 2, kPolygon>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            default: run_item<R, 2, kBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             }
         } else {
             switch (I.kind) {
-            case kBall: run_item<R, 3, kBall>(I, point, chunk, hist, lds_segs, qbase, sh); break;
-            default: run_item<R, 3, kBox>(I, point, chunk, hist, lds_segs, qbase, sh); break;
+            case kBall: run_item<R, 3, kBall>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            default: run_item<R, 3, kBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             }
         }
     }

@@ -42,8 +42,13 @@ struct alignas(16) DevInst {
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call
-    uint32_t chunk;       // walks per work item
-    uint32_t n_chunks;    // work items per point
+    // Work items of a point: n_big items of big_chunk walks (walk offsets [0, n_big big_chunk)), then
+    // n_chunks items of chunk walks for the rest.  All big items (every point) come first in the
+    // cursor order, so the last items handed out are small and the blocks finish together.
+    uint32_t chunk;       // walks per small work item
+    uint32_t n_chunks;    // small work items per point
+    uint32_t big_chunk;   // walks per big work item
+    uint32_t n_big;       // big work items per point
     int32_t n_obs;
     uint64_t item_begin;  // first global work item of this instance
     uint64_t n_items;
