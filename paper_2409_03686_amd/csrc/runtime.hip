@@ -405,12 +405,20 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         I.icnf[a] = a < g->dim ? static_cast<float>(1.0 / I.cn[a]) : 0.0f;
     }
     I.eps = w->eps;
-    // FP32 distance error bound: a few dozen ulps of the coordinate scale (differences, squares,
-    // a hardware square root and one subtraction; derivation in the design notes).
-    const double delta = std::ldexp(domain_scale(g), -18);
+    // FP32 distance error bound delta = 16 (32 for the ellipse and polygon) units of 2^-24 times the
+    // largest coordinate magnitude: differences, squares, one hardware square root (2 ulps) and one
+    // subtraction cost at most about 5 such units for circles, spheres and boxes, about 8 for the
+    // ellipse gauge and the segment distances of a polygon.
+    const int dexp = (g->kind == WOS_ELLIPSE || g->kind == WOS_POLYGON) ? -19 : -20;
+    const double delta = std::ldexp(domain_scale(g), dexp);
     I.delta = static_cast<float>(delta);
-    I.eps_lo = static_cast<float>(w->eps - delta);
-    I.eps_hi = static_cast<float>(w->eps + delta);
+    I.neg2delta = -2.0f * I.delta;
+    // thresholds rounded outward so that the certain-exit test stays certain after rounding
+    float lo = static_cast<float>(w->eps - delta), hi = static_cast<float>(w->eps + delta);
+    if (static_cast<double>(lo) > w->eps - delta) lo = std::nextafter(lo, -INFINITY);
+    if (static_cast<double>(hi) < w->eps + delta) hi = std::nextafter(hi, INFINITY);
+    I.eps_lo = lo;
+    I.eps_hi = hi;
     if (w->precision == WOS_FP32_GEOM_FP64_EXIT && !(w->eps > 8.0 * delta))
         return set_error(WOS_ENOTSUP, "eps %g is too small for FP32 geometry at domain scale %g (needs eps > %g)",
                          w->eps, domain_scale(g), 8.0 * delta);
@@ -547,12 +555,15 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.seg_bytes = static_cast<int>(sizeof(PolySeg)) * seg_max;
     gl.precision = jobs[idx[0]].walk.precision;
     gl.dim = jobs[idx[0]].geom.dim;
+    gl.kind_sel = jobs[idx[0]].geom.kind;
+    for (int q = 1; q < n; ++q)
+        if (jobs[idx[q]].geom.kind != gl.kind_sel) gl.kind_sel = -1;
     const size_t lds = static_cast<size_t>(gl.hist_words) * 4 + gl.seg_bytes + walk_queue_bytes(gl.precision, gl.dim, gl.block);
     if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;
-    if (hipFuncSetAttribute(walk_kernel_ptr(gl.precision, gl.dim), hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute(walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             static_cast<int>(lds)) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(gl.precision, gl.dim), gl.block, lds) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel), gl.block, lds) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -599,7 +610,7 @@ wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const 
     std::memcpy(slot.host, buf.data(), buf.size());
     uint32_t *cursor = reinterpret_cast<uint32_t *>(dev + ((buf.size() + 15) & ~size_t(15)));
     HIP_TRY(ctx, hipMemcpyAsync(dev, slot.host, buf.size(), hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, reinterpret_cast<const DevInst *>(dev), gl.n_inst, gl.items,
+    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, reinterpret_cast<const DevInst *>(dev), gl.n_inst, gl.items,
                               cursor, gl.hist_words, gl.seg_bytes, gl.block, gl.grid, stream));
     HIP_TRY(ctx, hipEventRecord(slot.done, stream));
     slot.used = true;

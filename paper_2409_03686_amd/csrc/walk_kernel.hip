@@ -167,8 +167,9 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
 }
 
 // One sphere step of a live walk (phase PH of its Philox block).  Returns true when the walk
-// stops: inside the eps-shell, or at the step cap (then bit 31 of s is set).
-template <typename R, int DIM, int KIND, int PH>
+// stops: inside the eps-shell, or at the step cap (then bit 31 of s is set).  CAP = false when no
+// walk of the wave can reach the cap within this Philox block.
+template <typename R, int DIM, int KIND, int PH, bool CAP>
 __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], R *x, R &d,
                                           uint32_t &s, uint32_t &n_fp64)
 {
@@ -185,7 +186,7 @@ __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs,
         // conservative radius: below the true distance by more than the FP32 distance error
         // (2 delta) and the direction's norm error (relative 2^-16)
         const float rr = radius32<KIND, DIM>(I, x, d);
-        const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, -2.0f * I.delta);
+        const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, I.neg2delta);
         step32<DIM>(I, x, r, U);
         d = dist32<KIND, DIM>(I, x, segs);
         s += 1;
@@ -199,15 +200,17 @@ __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs,
             ++n_fp64;
         }
     }
-    if (!fin && s >= I.max_steps) {
-        fin = true;
-        s |= kCapBit;
+    if constexpr (CAP) {
+        if (!fin && s >= I.max_steps) {
+            fin = true;
+            s |= kCapBit;
+        }
     }
     return fin;
 }
 
 template <typename R, int DIM, int KIND>
-__device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t cnt, uint32_t *hist,
+__device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t cnt, uint32_t *hist,
                          PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh)
 {
     constexpr int SPB = Spb<R, DIM>::v;
@@ -280,7 +283,7 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t
                 const uint32_t leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
                 uint32_t base = 0;
                 if (lane == leader) base = atomicAdd(&sh.next, nneed);
-                base = __shfl(base, leader);
+                base = __builtin_amdgcn_readlane(base, leader);
                 const uint32_t mine = base + __popcll(need & lanemask_lt());
                 if (!live && mine < cnt) {
                     live = true;
@@ -299,10 +302,11 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t
                 w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
             }
             wave_iters += SPB;
-            auto phase = [&](auto ph_tag) {
+            auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
+                constexpr bool CAP = decltype(cap_tag)::value;
                 bool fin = false;
-                if (live) fin = walk_step<R, DIM, KIND, PH>(I, segs, w, x, d, s, n_fp64);
+                if (live) fin = walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, x, d, s, n_fp64);
                 const uint64_t fmask = __ballot(fin);
                 if (fmask != 0ull) {
                     const uint32_t nf = __popcll(fmask);
@@ -321,11 +325,21 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t
                     qn += nf;
                 }
             };
-            phase(std::integral_constant<int, 0>{});
-            if constexpr (SPB > 1) phase(std::integral_constant<int, 1>{});
-            if constexpr (SPB > 2) {
-                phase(std::integral_constant<int, 2>{});
-                phase(std::integral_constant<int, 3>{});
+            auto block = [&](auto cap_tag) {
+                phase(std::integral_constant<int, 0>{}, cap_tag);
+                if constexpr (SPB > 1) phase(std::integral_constant<int, 1>{}, cap_tag);
+                if constexpr (SPB > 2) {
+                    phase(std::integral_constant<int, 2>{}, cap_tag);
+                    phase(std::integral_constant<int, 3>{}, cap_tag);
+                }
+            };
+            // FP32: the step cap is tested only in blocks where some walk can reach it (the second copy
+            // of the block costs the FP64 variants more in registers than it saves)
+            if constexpr (sizeof(R) == 4) {
+                if (__any(live && s + SPB >= I.max_steps)) block(std::true_type{});
+                else block(std::false_type{});
+            } else {
+                block(std::true_type{});
             }
         }
         if (qn) flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, ls);
@@ -355,7 +369,9 @@ __device__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t
     __syncthreads();
 }
 
-template <typename R, int DIM>
+// KSEL: the domain kind of every instance of the launch (its own register allocation), or -1 for
+// launches that mix kinds (dispatch per item).
+template <typename R, int DIM, int KSEL>
 __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
                                                     uint64_t total_items, uint32_t *cursor,
                                                     int hist_words, int seg_bytes)
@@ -396,7 +412,9 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
             k0 = I.n_big * I.big_chunk + static_cast<uint32_t>(l2 % I.n_chunks) * I.chunk;
             cnt = min(I.chunk, I.n_walks - k0);
         }
-        if constexpr (DIM == 2) {
+        if constexpr (KSEL >= 0) {
+            run_item<R, DIM, KSEL>(I, point, k0, cnt, hist, lds_segs, qbase, sh);
+        } else if constexpr (DIM == 2) {
             switch (I.kind) {
             case kDisk: run_item<R, 2, kDisk>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             case kAnnulus: run_item<R, 2, kAnnulus>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
@@ -423,15 +441,36 @@ size_t walk_queue_bytes(int precision, int dim, int block)
     return static_cast<size_t>(block / kWave) * kWave * (dim * rs + 8);
 }
 
-const void *walk_kernel_ptr(int precision, int dim)
+template <typename R, int DIM, int KSEL> static const void *kptr()
 {
-    if (precision == 0) return dim == 2 ? reinterpret_cast<const void *>(&walk_kernel<double, 2>)
-                                        : reinterpret_cast<const void *>(&walk_kernel<double, 3>);
-    return dim == 2 ? reinterpret_cast<const void *>(&walk_kernel<float, 2>)
-                    : reinterpret_cast<const void *>(&walk_kernel<float, 3>);
+    return reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL>);
 }
 
-hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst, uint64_t total_items,
+template <typename R> static const void *kernel_of(int dim, int ksel)
+{
+    if (dim == 2) {
+        switch (ksel) {
+        case kDisk: return kptr<R, 2, kDisk>();
+        case kAnnulus: return kptr<R, 2, kAnnulus>();
+        case kEllipse: return kptr<R, 2, kEllipse>();
+        case kPolygon: return kptr<R, 2, kPolygon>();
+        case kBox: return kptr<R, 2, kBox>();
+        default: return kptr<R, 2, -1>();
+        }
+    }
+    switch (ksel) {
+    case kBall: return kptr<R, 3, kBall>();
+    case kBox: return kptr<R, 3, kBox>();
+    default: return kptr<R, 3, -1>();
+    }
+}
+
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel)
+{
+    return precision == 0 ? kernel_of<double>(dim, kind_sel) : kernel_of<float>(dim, kind_sel);
+}
+
+hipError_t launch_walks(int precision, int dim, int kind_sel, const DevInst *insts, int n_inst, uint64_t total_items,
                         uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream)
 {
@@ -439,18 +478,9 @@ hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = static_cast<size_t>(hist_words) * 4 + seg_bytes + walk_queue_bytes(precision, dim, block);
-    if (precision == 0) {
-        if (dim == 2)
-            walk_kernel<double, 2><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
-        else
-            walk_kernel<double, 3><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
-    } else {
-        if (dim == 2)
-            walk_kernel<float, 2><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
-        else
-            walk_kernel<float, 3><<<grid, block, lds, stream>>>(insts, n_inst, total_items, cursor, hist_words, seg_bytes);
-    }
-    return hipGetLastError();
+    const void *fn = walk_kernel_ptr(precision, dim, kind_sel);
+    void *args[] = {&insts, &n_inst, &total_items, &cursor, &hist_words, &seg_bytes};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
 
 }  // namespace wos

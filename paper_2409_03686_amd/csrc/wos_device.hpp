@@ -38,7 +38,7 @@ struct alignas(16) DevInst {
     float eps_lo;     // FP32 distance <= eps_lo: certainly inside the eps-shell
     float eps_hi;     // FP32 distance >  eps_hi: certainly outside it
     float delta;      // bound on |dist_fp32 - dist| for this domain (absolute)
-    float pad0;
+    float neg2delta;  // -2 delta (radius shrink)
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call

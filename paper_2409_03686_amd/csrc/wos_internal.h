@@ -58,8 +58,9 @@ struct RegDev {
 };
 
 size_t walk_queue_bytes(int precision, int dim, int block);
-const void *walk_kernel_ptr(int precision, int dim);
-hipError_t launch_walks(int precision, int dim, const DevInst *insts, int n_inst, uint64_t total_items,
+// kind_sel: the domain kind shared by all instances of the launch, or -1 when they differ
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel);
+hipError_t launch_walks(int precision, int dim, int kind_sel, const DevInst *insts, int n_inst, uint64_t total_items,
                         uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream);
 
