@@ -298,23 +298,33 @@ struct JacobiArgs {
 // Blocked one-sided Jacobi (Hestenes) with register-resident block pairs.
 //
 // Columns are grouped in blocks of BW; the blocks meet pairwise in round-robin order, one block
-// pair per workgroup per round, with a device-wide barrier between rounds.  A workgroup loads the
-// 2 BW columns of its pair, rows of X and (if kept) rows of W alike, into registers (thread t holds
-// rows t, t + T, ...), computes their norms, then runs one cyclic sweep over them: in each of
-// 2 BW - 1 rounds, BW disjoint pairs get g = x_p . x_q from a DPP (+ LDS when T > 64) reduction and
-// a pair with g^2 > tol^2 |x_p|^2 |x_q|^2 is rotated by the plane rotation that zeroes g, applied
-// as two-term updates to its rows; the norms follow the rotation analytically and are recomputed
-// from the columns at the next load.  Fresh dot products and two-term updates keep small columns
-// accurate relative to their own size.  All waves compute the same sums in the same order, so
-// every thread takes the same decisions.  A sweep without rotations ends the iteration.
-template <int R, int RW, int T, int BW>
-__global__ __launch_bounds__(T) void jacobi_kernel(JacobiArgs J)
+// pair per group of T threads per round, with a device-wide barrier between rounds.  A group loads
+// the 2 BW columns of its pair, rows of X and (if kept) rows of W alike, into registers (thread t
+// of the group holds rows t, t + T, ...), computes their norms, then runs one cyclic sweep over
+// them: in each of 2 BW - 1 rounds, BW disjoint pairs get g = x_p . x_q from a DPP (+ LDS when
+// T > 64) reduction and a pair with g^2 > tol^2 |x_p|^2 |x_q|^2 is rotated by the plane rotation
+// that zeroes g, applied as two-term updates to its rows; the norms follow the rotation
+// analytically and are recomputed from the columns at the next load.  Fresh dot products and
+// two-term updates keep small columns accurate relative to their own size.  All waves of a group
+// compute the same sums in the same order, so they take the same decisions.  A sweep without
+// rotations ends the iteration.  A workgroup holds GPB independent one-wave groups when T = 64
+// (fewer workgroups meet at the barrier), or one group of T threads.
+template <int R, int RW, int T, int BW, int GPB = 1>
+__global__ __launch_bounds__(T *GPB) void jacobi_kernel(JacobiArgs J)
 {
+    static_assert(GPB == 1 || T == 64, "several groups per workgroup need one-wave groups");
     constexpr int N = 2 * BW;
     constexpr int NW = T / 64;
     __shared__ double part[2][16][16];
-    __shared__ int cols[N];
+    __shared__ int cols_s[GPB][N];
     if (J.skip && *J.skip != 0u) return;  // uniform over the grid: written by an earlier kernel
+    const int grp = GPB > 1 ? static_cast<int>(threadIdx.x) / T : 0;
+    const int lt = GPB > 1 ? static_cast<int>(threadIdx.x) % T : static_cast<int>(threadIdx.x);
+    int *cols = cols_s[grp];
+    auto group_sync = [] {
+        if constexpr (GPB == 1) __syncthreads();
+        else __builtin_amdgcn_wave_barrier();
+    };
     const int nblk = J.colsp / BW;
     const int npairs = nblk / 2;
     const int ld = J.ldx;
@@ -324,25 +334,25 @@ __global__ __launch_bounds__(T) void jacobi_kernel(JacobiArgs J)
     int sweep = 0;
     for (; sweep < kMaxSweeps; ++sweep) {
         for (int t = 0; t < nblk - 1; ++t) {
-            for (int pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
+            for (int pi = blockIdx.x * GPB + grp; pi < npairs; pi += gridDim.x * GPB) {
                 int P, Qb;
                 pair_of(t, pi, nblk, P, Qb);
-                if (threadIdx.x < N) cols[threadIdx.x] = threadIdx.x < BW ? P * BW + threadIdx.x : Qb * BW + threadIdx.x - BW;
-                __syncthreads();
+                if (lt < N) cols[lt] = lt < BW ? P * BW + lt : Qb * BW + lt - BW;
+                group_sync();
                 double x[R][N], w[RW > 0 ? RW : 1][N];
 #pragma unroll
                 for (int j = 0; j < N; ++j) {
                     const double *ca = J.X + static_cast<size_t>(cols[j]) * ld;
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
-                        const int r = threadIdx.x + i * T;
+                        const int r = lt + i * T;
                         x[i][j] = r < J.rows ? ca[r] : 0.0;
                     }
                     if constexpr (RW > 0) {
                         const double *cw = J.W + static_cast<size_t>(cols[j]) * ldw;
 #pragma unroll
                         for (int i = 0; i < RW; ++i) {
-                            const int r = threadIdx.x + i * T;
+                            const int r = lt + i * T;
                             w[i][j] = r < ldw ? cw[r] : 0.0;
                         }
                     }
@@ -363,20 +373,20 @@ __global__ __launch_bounds__(T) void jacobi_kernel(JacobiArgs J)
                     double *ca = J.X + static_cast<size_t>(cols[j]) * ld;
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
-                        const int r = threadIdx.x + i * T;
+                        const int r = lt + i * T;
                         if (r < J.rows) ca[r] = x[i][j];
                     }
                     if constexpr (RW > 0) {
                         double *cw = J.W + static_cast<size_t>(cols[j]) * ldw;
 #pragma unroll
                         for (int i = 0; i < RW; ++i) {
-                            const int r = threadIdx.x + i * T;
+                            const int r = lt + i * T;
                             if (r < ldw) cw[r] = w[i][j];
                         }
                     }
                 }
-                if (threadIdx.x == 0 && nrot) atomicAdd(&J.rot[sweep], static_cast<uint32_t>(nrot));
-                __syncthreads();
+                if (lt == 0 && nrot) atomicAdd(&J.rot[sweep], static_cast<uint32_t>(nrot));
+                group_sync();
             }
             grid_barrier(J.bar, J.err, gridDim.x, gen);
         }
@@ -397,10 +407,11 @@ __global__ __launch_bounds__(T) void jacobi_kernel(JacobiArgs J)
 // Launch shape by the size of the work matrix: T threads, R rows of X and RW rows of W each.
 struct JacobiShape {
     const void *fn;
-    int threads;
-    int bw;
+    int threads;  // per workgroup
+    int bw;       // columns per block
+    int gpb;      // block pairs per workgroup
 };
-#define WOS_BJ(R, RW, T) JacobiShape{reinterpret_cast<const void *>(&jacobi_kernel<R, RW, T, 4>), T, 4}
+#define WOS_BJ(R, RW, T) JacobiShape{reinterpret_cast<const void *>(&jacobi_kernel<R, RW, T, 4>), T, 4, 1}
 static JacobiShape jacobi_shape(int rows, int colsp)
 {
     // one workgroup per CU: 256 threads (one wave per SIMD, up to 512 VGPRs) with R rows each
@@ -413,17 +424,18 @@ static JacobiShape jacobi_shape(int rows, int colsp)
         return WOS_BJ(8, 8, 512);
     }
     if (rows <= 8192) return WOS_BJ(8, 8, 1024);
-    return {nullptr, 0, 4};
+    return {nullptr, 0, 4, 1};
 }
 #undef WOS_BJ
 
-// The Gram path's Jacobi runs on the np x np factor, one wave per block pair, without W.
+// The Gram path's Jacobi runs on the np x np factor, one wave per block pair, four block pairs per
+// workgroup, without W.
 static JacobiShape gram_jacobi_shape(int np)
 {
-    if (np == 64) return {reinterpret_cast<const void *>(&jacobi_kernel<1, 0, 64, 4>), 64, 4};
-    if (np == 128) return {reinterpret_cast<const void *>(&jacobi_kernel<2, 0, 64, 4>), 64, 4};
-    if (np == 192) return {reinterpret_cast<const void *>(&jacobi_kernel<3, 0, 64, 4>), 64, 4};
-    return {nullptr, 0, 4};
+    if (np == 64) return {reinterpret_cast<const void *>(&jacobi_kernel<1, 0, 64, 4, 4>), 256, 4, 4};
+    if (np == 128) return {reinterpret_cast<const void *>(&jacobi_kernel<2, 0, 64, 4, 4>), 256, 4, 4};
+    if (np == 192) return {reinterpret_cast<const void *>(&jacobi_kernel<3, 0, 64, 4, 4>), 256, 4, 4};
+    return {nullptr, 0, 4, 1};
 }
 
 // Column norms out[c] = |X[:, c]| for c < ncols (one block per column).
@@ -893,7 +905,7 @@ static int coop_blocks(const JacobiShape &sh, int npairs, int n_cu)
 int svd_coop_grid(int rows, int colsp, int n_cu)
 {
     const JacobiShape sh = jacobi_shape(rows, colsp);
-    return coop_blocks(sh, colsp / (2 * sh.bw), n_cu);
+    return coop_blocks(sh, (colsp / (2 * sh.bw) + sh.gpb - 1) / sh.gpb, n_cu);
 }
 
 // assemble -> [Gram path: G, factor, Jacobi on the factor, norms, V side, U side, check, accept]
@@ -920,8 +932,9 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
         JacobiArgs J{v.L, nullptr, v.np, v.np, v.np, static_cast<double>(v.np) * 0x1.0p-52,
                      v.rot + kMaxSweeps, v.ctrl + kCtrlGramBarrier, v.ctrl + kCtrlGramError, v.info + 2, nullptr};
         void *args[] = {&J};
-        // the factor's Jacobi needs np / 8 co-resident one-wave blocks (at most 24)
-        e = hipLaunchCooperativeKernel(gs.fn, dim3(v.np / (2 * gs.bw)), dim3(gs.threads), args, 0, stream);
+        // the factor's Jacobi: np / 8 block pairs (at most 24), gpb per co-resident workgroup
+        const int gpairs = v.np / (2 * gs.bw);
+        e = hipLaunchCooperativeKernel(gs.fn, dim3((gpairs + gs.gpb - 1) / gs.gpb), dim3(gs.threads), args, 0, stream);
         if (e != hipSuccess) return e;
         colnorm_kernel<<<v.np, 64, 0, stream>>>(v.L, v.np, v.np, v.np, v.zs, nullptr);
         gram_vside_kernel<<<v.np, 64, 0, stream>>>(v);
