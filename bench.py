@@ -265,7 +265,7 @@ def main():
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "traffic_detail": traffic_detail,
             "algorithmic_bytes": n_obs * ALGO_BYTES_PER_POINT,
-            "kernel": "walk_kernel<float,2> (annulus)", "avg_ms": walk_ms,
+            "kernel": "walk_kernel<float,2,annulus>", "avg_ms": walk_ms,
             "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
             "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1),
             "launch_shape": {"block": tuned[0], "walks_per_lane": tuned[1]}}
