@@ -289,6 +289,24 @@ typedef struct {
 wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n, wos_result *results,
                      const wos_serve_opts *opts);
 
+/* Live form of the same engine: a serving thread owned by the context.
+ *   wos_serve_start  starts it with the given options (WOS_EBUSY if one is running);
+ *   wos_serve_submit validates a request, copies its host inputs (the caller may reuse them at
+ *                    once; arrival_s is ignored, the arrival is the submission time) and returns
+ *                    a ticket;
+ *   wos_serve_poll   waits up to wait_ms (0: no wait, < 0: until done) for the ticket; when done
+ *                    it copies u1 / pred / s into the buffers out points to (u1_host is required,
+ *                    pred_host and s_host may be NULL), fills the rest of *out, releases the
+ *                    ticket and returns WOS_OK (the request's own status is out->status);
+ *                    WOS_EBUSY if still running, WOS_EINVAL for an unknown ticket;
+ *   wos_serve_stop   finishes the requests in flight, then stops the thread (wos_destroy does
+ *                    this too).  Tickets not polled are released.
+ * These four entry points may be called from any host thread. */
+wos_status wos_serve_start(wos_ctx *ctx, const wos_serve_opts *opts);
+wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uint64_t *ticket);
+wos_status wos_serve_poll(wos_ctx *ctx, uint64_t ticket, wos_result *out, int32_t wait_ms);
+wos_status wos_serve_stop(wos_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

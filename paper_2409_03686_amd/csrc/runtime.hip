@@ -107,6 +107,7 @@ extern "C" wos_status wos_destroy(wos_ctx *ctx)
 {
     if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
     (void)hipSetDevice(ctx->device);
+    live_server_stop(ctx);  // drains requests in flight
     for (auto &slot : ctx->ring) {
         if (slot.used) (void)hipEventSynchronize(slot.done);
         (void)hipEventDestroy(slot.done);

@@ -1,6 +1,8 @@
 // serve.hip -- continuous batching of build + SVD + reconstruct requests (wos_serve).
 //
-// One host thread replays the arrival times (open loop).  A request is admitted when one of
+// The blocking driver (wos_serve) replays the arrival times (open loop) on the calling thread; the
+// live form (wos_serve_start / submit / poll / stop) runs the same engine on a thread owned by the
+// context.  A request is admitted when one of
 // max_inflight slots is free and its device footprint fits in the HBM budget; its buffers are
 // sub-allocated (first fit) from one arena allocated once, its inputs are staged through the
 // slot's pinned buffer, and its whole path is enqueued on the slot's stream.  Admitted requests
@@ -14,9 +16,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -128,83 +133,158 @@ struct Slot {
     hipEvent_t done{};
     void *pinned = nullptr;
     size_t pinned_cap = 0;
-    int req = -1;  // request index in flight
+    struct Job *job = nullptr;  // request in flight
     size_t mem_off = 0, mem_len = 0;
     size_t out_u1 = 0, out_pred = 0, out_s = 0, out_scal = 0, out_stats = 0;
 };
 
-}  // namespace
+// One request inside the engine.  The blocking driver points req/res at the caller's memory; the
+// live form owns copies of the inputs and of the outputs until they are polled.
+struct Job {
+    wos_request req{};
+    wos_result *res = nullptr;
+    ReqLayout L;
+    std::vector<double> x, uD, u0, u1, pred, sv;
+    std::vector<uint8_t> mask;
+    wos_result own{};
+    bool done = false;
+};
 
-extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n, wos_result *results,
-                                const wos_serve_opts *opts)
-{
-    using clock = std::chrono::steady_clock;
-    if (!ctx || (n > 0 && (!reqs || !results))) return set_error(WOS_EINVAL, "NULL argument");
-    if (n < 0) return set_error(WOS_EINVAL, "n < 0");
-    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
-    const int max_inflight = opts && opts->max_inflight > 0 ? std::min(opts->max_inflight, 64) : 4;
-    size_t budget = opts && opts->hbm_budget_bytes ? opts->hbm_budget_bytes : (size_t(4) << 30);
-    const double timeout = opts ? opts->timeout_s : 0.0;
-    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(WOS_EDEVICE, "hipSetDevice failed");
-
-    // validate and lay out every request up front
-    std::vector<ReqLayout> lay(n);
-    size_t max_stage = 0;
-    for (int i = 0; i < n; ++i) {
-        results[i].status = WOS_OK;
-        results[i].t_arrive = reqs[i].arrival_s;
-        results[i].t_admit = results[i].t_done = -1.0;
-        results[i].walks = results[i].steps = 0;
-        results[i].rank_used = 0;
-        results[i].alpha_used = 0.0;
-        wos_status st = layout_request(reqs[i], lay[i]);
-        if (st != WOS_OK) {
-            results[i].status = st;
-            continue;
-        }
-        if (lay[i].total > budget) {
-            results[i].status = set_error(WOS_ENOMEM, "request %d needs %zu bytes, budget %zu", i, lay[i].total, budget);
-            continue;
-        }
-        if (!results[i].u1_host) {
-            results[i].status = set_error(WOS_EINVAL, "request %d has no u1 output buffer", i);
-            continue;
-        }
-        max_stage = std::max(max_stage, staging_bytes(reqs[i], lay[i]));
+// Admission, launch and completion of requests on max_inflight slots (a stream, an event and a
+// pinned staging buffer each) with their device memory sub-allocated from one arena.
+class Engine {
+  public:
+    Engine(wos_ctx *ctx, const wos_serve_opts *opts) : ctx_(ctx)
+    {
+        max_inflight_ = opts && opts->max_inflight > 0 ? std::min(opts->max_inflight, 64) : 4;
+        budget_ = opts && opts->hbm_budget_bytes ? opts->hbm_budget_bytes : (size_t(4) << 30);
+        timeout_ = opts ? opts->timeout_s : 0.0;
     }
-    void *arena_mem = nullptr;
-    wos_status st = ctx_malloc(ctx, &arena_mem, budget);
-    if (st != WOS_OK) return st;
-    Arena arena;
-    arena.init(budget);
-    std::vector<Slot> slots(max_inflight);
-    for (auto &s : slots) {
-        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(&s.pinned, std::max<size_t>(max_stage, 4096), hipHostMallocDefault) != hipSuccess) {
-            ctx_free(ctx, arena_mem, budget);
-            return set_error(WOS_EDEVICE, "serving slot set-up failed");
+    ~Engine() { shutdown(); }
+
+    wos_status init(size_t stage_hint)
+    {
+        if (hipSetDevice(ctx_->device) != hipSuccess) return set_error(WOS_EDEVICE, "hipSetDevice failed");
+        wos_status st = ctx_malloc(ctx_, &arena_mem_, budget_);
+        if (st != WOS_OK) return st;
+        arena_.init(budget_);
+        slots_.resize(max_inflight_);
+        for (auto &s : slots_) {
+            if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+                return set_error(WOS_EDEVICE, "serving slot set-up failed");
+            if (!grow_pinned(s, std::max<size_t>(stage_hint, 4096))) return set_error(WOS_EDEVICE, "pinned staging allocation failed");
         }
-        s.pinned_cap = std::max<size_t>(max_stage, 4096);
+        return WOS_OK;
     }
-    // requests in arrival order
-    std::vector<int> order;
-    for (int i = 0; i < n; ++i)
-        if (results[i].status == WOS_OK) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
 
-    const auto t0 = clock::now();
-    auto now = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
-    std::deque<int> queue;
-    size_t next_arrival = 0;
-    int inflight = 0;
-    size_t done_count = 0;
-    wos_status fatal = WOS_OK;
+    // Validates and lays out a request; on failure the status is recorded in the job's result.
+    wos_status prepare(Job &j)
+    {
+        wos_status st = layout_request(j.req, j.L);
+        if (st == WOS_OK && j.L.total > budget_)
+            st = set_error(WOS_ENOMEM, "request needs %zu bytes, budget %zu", j.L.total, budget_);
+        if (st == WOS_OK && !j.res->u1_host) st = set_error(WOS_EINVAL, "request has no u1 output buffer");
+        j.res->status = st;
+        return st;
+    }
 
-    auto launch = [&](Slot &s, int i) -> wos_status {
-        const wos_request &r = reqs[i];
-        ReqLayout &L = lay[i];
-        uint8_t *base = static_cast<uint8_t *>(arena_mem) + s.mem_off;
+    double timeout() const { return timeout_; }
+    int inflight() const { return inflight_; }
+
+    // Admits queued jobs in order while a slot and memory are free.  Returns a fatal status.
+    wos_status admit(std::deque<Job *> &queue, double now)
+    {
+        while (!queue.empty() && inflight_ < max_inflight_) {
+            Job *j = queue.front();
+            size_t off = 0;
+            if (!arena_.alloc(j->L.total, off)) break;  // wait for memory
+            Slot *slot = nullptr;
+            for (auto &sl : slots_)
+                if (!sl.job) {
+                    slot = &sl;
+                    break;
+                }
+            slot->job = j;
+            slot->mem_off = off;
+            slot->mem_len = j->L.total;
+            queue.pop_front();
+            j->res->t_admit = now;
+            wos_status st = launch(*slot, *j);
+            if (st != WOS_OK) return st;
+            ++inflight_;
+        }
+        return WOS_OK;
+    }
+
+    // Harvests finished requests; returns how many finished (fatal device errors in *fatal).
+    int complete(double now, wos_status *fatal)
+    {
+        int n = 0;
+        for (auto &s : slots_) {
+            if (!s.job) continue;
+            hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            Job &j = *s.job;
+            wos_result &R = *j.res;
+            if (q != hipSuccess) {
+                R.status = WOS_EDEVICE;
+                *fatal = set_error(WOS_EDEVICE, "request failed on the device: %s", hipGetErrorString(q));
+            } else {
+                const uint8_t *pin = static_cast<const uint8_t *>(s.pinned);
+                std::memcpy(R.u1_host, pin + s.out_u1, 8ull * j.L.n1);
+                if (R.pred_host) std::memcpy(R.pred_host, pin + s.out_pred, 8ull * j.req.n_obs);
+                if (R.s_host) std::memcpy(R.s_host, pin + s.out_s, 8ull * j.L.k);
+                std::memcpy(&R.rank_used, pin + s.out_scal, 4);
+                std::memcpy(&R.alpha_used, pin + s.out_scal + 8, 8);
+                uint64_t stw[WOS_STATS_WORDS];
+                std::memcpy(stw, pin + s.out_stats, sizeof stw);
+                R.walks = stw[WOS_STAT_WALKS];
+                R.steps = stw[WOS_STAT_STEPS];
+                R.t_done = now;
+                if (timeout_ > 0 && R.t_done - R.t_arrive > timeout_) R.status = WOS_ETIMEOUT;
+            }
+            j.done = true;
+            arena_.release(s.mem_off, s.mem_len);
+            s.job = nullptr;
+            --inflight_;
+            ++n;
+        }
+        return n;
+    }
+
+    void shutdown()
+    {
+        for (auto &s : slots_) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.pinned) (void)hipHostFree(s.pinned);
+            s = Slot{};
+        }
+        slots_.clear();
+        if (arena_mem_) ctx_free(ctx_, arena_mem_, budget_);
+        arena_mem_ = nullptr;
+    }
+
+  private:
+    bool grow_pinned(Slot &s, size_t need)
+    {
+        if (s.pinned_cap >= need) return true;
+        if (s.pinned) (void)hipHostFree(s.pinned);
+        s.pinned = nullptr;
+        s.pinned_cap = 0;
+        if (hipHostMalloc(&s.pinned, need, hipHostMallocDefault) != hipSuccess) return false;
+        s.pinned_cap = need;
+        return true;
+    }
+
+    wos_status launch(Slot &s, Job &j)
+    {
+        const wos_request &r = j.req;
+        ReqLayout &L = j.L;
+        if (!grow_pinned(s, staging_bytes(r, L))) return set_error(WOS_EDEVICE, "pinned staging allocation failed");
+        uint8_t *base = static_cast<uint8_t *>(arena_mem_) + s.mem_off;
         uint8_t *pin = static_cast<uint8_t *>(s.pinned);
         size_t po = 0;
         auto stage_in = [&](size_t dev_off, const void *src, size_t bytes) -> hipError_t {
@@ -234,12 +314,12 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
         J.stats_dev = stats;
         J.trace_dev = nullptr;
         {
-            std::lock_guard<std::recursive_mutex> lk(ctx->launch_mu);
-            wos_status st2 = build_batch(ctx, &J, 1, s.stream, nullptr);
+            std::lock_guard<std::recursive_mutex> lk(ctx_->launch_mu);
+            wos_status st2 = build_batch(ctx_, &J, 1, s.stream, nullptr);
             if (st2 != WOS_OK) return st2;
         }
         const uint64_t nw = r.walk.walk_end - r.walk.walk_begin;
-        const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx->n_cu);
+        const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx_->n_cu);
         e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, s.stream);
         double *u1 = reinterpret_cast<double *>(base + L.off_u1);
         double *pred = reinterpret_cast<double *>(base + L.off_pred);
@@ -264,17 +344,63 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) return set_error(WOS_EDEVICE, "enqueue failed: %s", hipGetErrorString(e));
         return WOS_OK;
-    };
+    }
 
+    wos_ctx *ctx_;
+    int max_inflight_ = 4, inflight_ = 0;
+    size_t budget_ = 0;
+    double timeout_ = 0.0;
+    void *arena_mem_ = nullptr;
+    Arena arena_;
+    std::vector<Slot> slots_;
+};
+
+}  // namespace
+
+extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n, wos_result *results,
+                                const wos_serve_opts *opts)
+{
+    using clock = std::chrono::steady_clock;
+    if (!ctx || (n > 0 && (!reqs || !results))) return set_error(WOS_EINVAL, "NULL argument");
+    if (n < 0) return set_error(WOS_EINVAL, "n < 0");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    Engine eng(ctx, opts);
+    // validate and lay out every request up front
+    std::vector<Job> jobs(n);
+    size_t max_stage = 0;
+    for (int i = 0; i < n; ++i) {
+        Job &j = jobs[i];
+        j.req = reqs[i];
+        j.res = &results[i];
+        results[i].t_arrive = reqs[i].arrival_s;
+        results[i].t_admit = results[i].t_done = -1.0;
+        results[i].walks = results[i].steps = 0;
+        results[i].rank_used = 0;
+        results[i].alpha_used = 0.0;
+        if (eng.prepare(j) == WOS_OK) max_stage = std::max(max_stage, staging_bytes(reqs[i], j.L));
+    }
+    wos_status st = eng.init(max_stage);
+    if (st != WOS_OK) return st;
+    // requests in arrival order
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i)
+        if (results[i].status == WOS_OK) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+
+    const auto t0 = clock::now();
+    auto now = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    std::deque<Job *> queue;
+    size_t next_arrival = 0, done_count = 0;
+    wos_status fatal = WOS_OK;
+    const double timeout = eng.timeout();
     while (done_count < order.size() && fatal == WOS_OK) {
         const double t = now();
-        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= t) queue.push_back(order[next_arrival++]);
-        // time out queued requests
-        if (timeout > 0) {
+        while (next_arrival < order.size() && reqs[order[next_arrival]].arrival_s <= t) queue.push_back(&jobs[order[next_arrival++]]);
+        if (timeout > 0) {  // time out queued requests
             for (auto it = queue.begin(); it != queue.end();) {
-                if (t - reqs[*it].arrival_s > timeout) {
-                    results[*it].status = WOS_ETIMEOUT;
-                    results[*it].t_done = t;
+                if (t - (*it)->req.arrival_s > timeout) {
+                    (*it)->res->status = WOS_ETIMEOUT;
+                    (*it)->res->t_done = t;
                     ++done_count;
                     it = queue.erase(it);
                 } else {
@@ -282,78 +408,218 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
                 }
             }
         }
-        // admit in arrival order while a slot and memory are free
-        while (!queue.empty() && inflight < max_inflight) {
-            const int i = queue.front();
-            size_t off = 0;
-            if (!arena.alloc(lay[i].total, off)) break;  // wait for memory
-            Slot *slot = nullptr;
-            for (auto &s : slots)
-                if (s.req < 0) {
-                    slot = &s;
-                    break;
-                }
-            slot->req = i;
-            slot->mem_off = off;
-            slot->mem_len = lay[i].total;
-            queue.pop_front();
-            results[i].t_admit = now();
-            wos_status st2 = launch(*slot, i);
-            if (st2 != WOS_OK) {
-                fatal = st2;
-                break;
-            }
-            ++inflight;
-        }
-        // completions
-        bool any = false;
-        for (auto &s : slots) {
-            if (s.req < 0) continue;
-            hipError_t q = hipEventQuery(s.done);
-            if (q == hipErrorNotReady) continue;
-            const int i = s.req;
-            wos_result &R = results[i];
-            if (q != hipSuccess) {
-                R.status = WOS_EDEVICE;
-                fatal = set_error(WOS_EDEVICE, "request %d failed on the device: %s", i, hipGetErrorString(q));
-            } else {
-                const uint8_t *pin = static_cast<const uint8_t *>(s.pinned);
-                std::memcpy(R.u1_host, pin + s.out_u1, 8ull * lay[i].n1);
-                if (R.pred_host) std::memcpy(R.pred_host, pin + s.out_pred, 8ull * reqs[i].n_obs);
-                if (R.s_host) std::memcpy(R.s_host, pin + s.out_s, 8ull * lay[i].k);
-                std::memcpy(&R.rank_used, pin + s.out_scal, 4);
-                std::memcpy(&R.alpha_used, pin + s.out_scal + 8, 8);
-                uint64_t stw[WOS_STATS_WORDS];
-                std::memcpy(stw, pin + s.out_stats, sizeof stw);
-                R.walks = stw[WOS_STAT_WALKS];
-                R.steps = stw[WOS_STAT_STEPS];
-                R.t_done = now();
-                if (timeout > 0 && R.t_done - R.t_arrive > timeout) R.status = WOS_ETIMEOUT;
-            }
-            arena.release(s.mem_off, s.mem_len);
-            s.req = -1;
-            --inflight;
-            ++done_count;
-            any = true;
-        }
-        if (!any) {
+        fatal = eng.admit(queue, now());
+        if (fatal != WOS_OK) break;
+        const int fin = eng.complete(now(), &fatal);
+        done_count += static_cast<size_t>(fin);
+        if (fin == 0) {
             const double next_t = next_arrival < order.size() ? reqs[order[next_arrival]].arrival_s : 1e300;
-            if (inflight == 0 && queue.empty() && next_t > now())
+            if (eng.inflight() == 0 && queue.empty() && next_t > now())
                 std::this_thread::sleep_for(std::chrono::duration<double>(std::min(next_t - now(), 0.001)));
             else
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
-    for (auto &s : slots) {
-        (void)hipStreamSynchronize(s.stream);
-        (void)hipStreamDestroy(s.stream);
-        (void)hipEventDestroy(s.done);
-        (void)hipHostFree(s.pinned);
-    }
-    ctx_free(ctx, arena_mem, budget);
+    eng.shutdown();
     if (fatal != WOS_OK) {
         ctx->poisoned = fatal == WOS_EDEVICE;
         return fatal;
     }
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Live form: a serving thread owned by the context; requests are submitted and polled by ticket.
+// ---------------------------------------------------------------------------------------------
+struct LiveServer {
+    wos_ctx *ctx = nullptr;
+    std::unique_ptr<Engine> eng;
+    std::thread thr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job *> pending;                    // submitted, not yet seen by the thread
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;  // every ticket not yet polled
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    wos_status fatal = WOS_OK;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+
+    void run()
+    {
+        std::deque<Job *> queue;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (queue.empty() && eng->inflight() == 0 && pending.empty())
+                    cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] { return stop || !pending.empty(); });
+                if (stop && pending.empty() && queue.empty() && eng->inflight() == 0) return;
+                while (!pending.empty()) {
+                    queue.push_back(pending.front());
+                    pending.pop_front();
+                }
+            }
+            const double t = now();
+            const double timeout = eng->timeout();
+            int finished = 0;
+            if (timeout > 0) {
+                for (auto it = queue.begin(); it != queue.end();) {
+                    if (t - (*it)->res->t_arrive > timeout) {
+                        std::lock_guard<std::mutex> lk(mu);
+                        (*it)->res->status = WOS_ETIMEOUT;
+                        (*it)->res->t_done = t;
+                        (*it)->done = true;
+                        ++finished;
+                        it = queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            wos_status f = WOS_OK;
+            if (fatal == WOS_OK) f = eng->admit(queue, now());
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (f == WOS_OK) finished += eng->complete(now(), &f);
+                if (f != WOS_OK && fatal == WOS_OK) {
+                    fatal = f;
+                    ctx->poisoned = f == WOS_EDEVICE;
+                }
+                if (fatal != WOS_OK) {  // fail whatever is still queued
+                    for (Job *j : queue) {
+                        j->res->status = fatal;
+                        j->done = true;
+                    }
+                    finished += static_cast<int>(queue.size());
+                    queue.clear();
+                }
+            }
+            if (finished) cv_done.notify_all();
+            if (finished == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+};
+
+void wos::live_server_stop(wos_ctx *ctx)
+{
+    LiveServer *L = ctx->live;
+    if (!L) return;
+    {
+        std::lock_guard<std::mutex> lk(L->mu);
+        L->stop = true;
+    }
+    L->cv_work.notify_all();
+    if (L->thr.joinable()) L->thr.join();
+    L->eng->shutdown();
+    delete L;
+    ctx->live = nullptr;
+}
+
+extern "C" wos_status wos_serve_start(wos_ctx *ctx, const wos_serve_opts *opts)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    if (ctx->live) return set_error(WOS_EBUSY, "the live server of this context is already running");
+    auto *L = new LiveServer();
+    L->ctx = ctx;
+    L->eng = std::make_unique<Engine>(ctx, opts);
+    wos_status st = L->eng->init(4096);
+    if (st != WOS_OK) {
+        delete L;
+        return st;
+    }
+    L->t0 = std::chrono::steady_clock::now();
+    ctx->live = L;
+    L->thr = std::thread([L] {
+        (void)hipSetDevice(L->ctx->device);
+        L->run();
+    });
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_serve_stop(wos_ctx *ctx)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    if (!ctx->live) return set_error(WOS_EINVAL, "no live server is running");
+    live_server_stop(ctx);
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uint64_t *ticket)
+{
+    if (!ctx || !req || !ticket) return set_error(WOS_EINVAL, "NULL argument");
+    LiveServer *L = ctx->live;
+    if (!L) return set_error(WOS_EINVAL, "no live server is running (wos_serve_start)");
+    auto j = std::make_unique<Job>();
+    j->req = *req;
+    j->res = &j->own;
+    // own copies of the host inputs, so the caller may reuse its buffers after this call
+    int M = 0;
+    wos_status st = validate_geometry(&req->geom, &M);
+    if (st != WOS_OK) return st;
+    if (req->n_obs < 1 || !req->x_obs_host || !req->uD_host || !req->gamma1_mask_host)
+        return set_error(WOS_EINVAL, "request needs points, data and the Gamma_1 mask");
+    j->x.assign(req->x_obs_host, req->x_obs_host + static_cast<size_t>(req->n_obs) * req->geom.dim);
+    j->uD.assign(req->uD_host, req->uD_host + req->n_obs);
+    j->mask.assign(req->gamma1_mask_host, req->gamma1_mask_host + M);
+    int n0 = 0;
+    for (int e = 0; e < M; ++e) n0 += j->mask[e] ? 0 : 1;
+    if (n0 > 0) {
+        if (!req->u0_host) return set_error(WOS_EINVAL, "request needs u0 (Gamma_0 is not empty)");
+        j->u0.assign(req->u0_host, req->u0_host + n0);
+    }
+    j->req.x_obs_host = j->x.data();
+    j->req.uD_host = j->uD.data();
+    j->req.u0_host = n0 ? j->u0.data() : nullptr;
+    j->req.gamma1_mask_host = j->mask.data();
+    const int n1 = M - n0, k = std::min(req->n_obs, n1);
+    j->u1.assign(std::max(n1, 1), 0.0);
+    j->pred.assign(req->n_obs, 0.0);
+    j->sv.assign(std::max(k, 1), 0.0);
+    j->own.u1_host = j->u1.data();
+    j->own.pred_host = j->pred.data();
+    j->own.s_host = j->sv.data();
+    j->own.t_admit = j->own.t_done = -1.0;
+    st = L->eng->prepare(*j);
+    if (st != WOS_OK) return st;
+    std::lock_guard<std::mutex> lk(L->mu);
+    if (L->fatal != WOS_OK) return set_error(L->fatal, "the live server stopped after a device error");
+    j->own.t_arrive = L->now();
+    *ticket = L->next_ticket++;
+    L->pending.push_back(j.get());
+    L->jobs.emplace(*ticket, std::move(j));
+    L->cv_work.notify_one();
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_serve_poll(wos_ctx *ctx, uint64_t ticket, wos_result *out, int32_t wait_ms)
+{
+    if (!ctx || !out) return set_error(WOS_EINVAL, "NULL argument");
+    LiveServer *L = ctx->live;
+    if (!L) return set_error(WOS_EINVAL, "no live server is running");
+    std::unique_lock<std::mutex> lk(L->mu);
+    auto it = L->jobs.find(ticket);
+    if (it == L->jobs.end()) return set_error(WOS_EINVAL, "unknown ticket %llu", static_cast<unsigned long long>(ticket));
+    Job *j = it->second.get();
+    if (!j->done && wait_ms != 0) {
+        auto pred = [&] { return j->done; };
+        if (wait_ms < 0) L->cv_done.wait(lk, pred);
+        else L->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), pred);
+    }
+    if (!j->done) return WOS_EBUSY;
+    const wos_result &R = j->own;
+    if (out->u1_host) std::memcpy(out->u1_host, j->u1.data(), 8ull * j->L.n1);
+    if (out->pred_host) std::memcpy(out->pred_host, j->pred.data(), 8ull * j->req.n_obs);
+    if (out->s_host) std::memcpy(out->s_host, j->sv.data(), 8ull * j->L.k);
+    out->rank_used = R.rank_used;
+    out->alpha_used = R.alpha_used;
+    out->status = R.status;
+    out->t_arrive = R.t_arrive;
+    out->t_admit = R.t_admit;
+    out->t_done = R.t_done;
+    out->walks = R.walks;
+    out->steps = R.steps;
+    L->jobs.erase(it);
     return WOS_OK;
 }

@@ -39,10 +39,11 @@ struct BlockShared {
     unsigned long long st[8]; // per-item statistics
 };
 
-__device__ __forceinline__ uint64_t lanemask_lt()
+// Number of set bits of a wave mask below the calling lane (v_mbcnt_lo/hi).
+__device__ __forceinline__ uint32_t prefix_count(uint64_t mask)
 {
-    const uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
 // Direction of step s (phase = s mod SPB) from the words of the walk's current Philox block.
@@ -168,7 +169,8 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
 
 // One sphere step of a live walk (phase PH of its Philox block).  Returns true when the walk
 // stops: inside the eps-shell, or at the step cap (then bit 31 of s is set).  CAP = false when no
-// walk of the wave can reach the cap within this Philox block.
+// walk of the wave can reach the cap within this Philox block; then s is not advanced here (the
+// caller adds the block's steps at its end and PH + 1 for a walk that stops inside it).
 template <typename R, int DIM, int KIND, int PH, bool CAP>
 __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], R *x, R &d,
                                           uint32_t &s, uint32_t &n_fp64)
@@ -189,9 +191,10 @@ __device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs,
         const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, I.neg2delta);
         step32<DIM>(I, x, r, U);
         d = dist32<KIND, DIM>(I, x, segs);
-        s += 1;
-        fin = d <= I.eps_lo;
-        if (!fin && d <= I.eps_hi) {
+        if constexpr (CAP) s += 1;
+        const bool gt_lo = d > I.eps_lo;
+        fin = !gt_lo;
+        if (gt_lo && d <= I.eps_hi) {
             // ambiguous band: decide in FP64 at the stored position
             double xd[DIM];
 #pragma unroll
@@ -284,7 +287,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                 uint32_t base = 0;
                 if (lane == leader) base = atomicAdd(&sh.next, nneed);
                 base = __builtin_amdgcn_readlane(base, leader);
-                const uint32_t mine = base + __popcll(need & lanemask_lt());
+                const uint32_t mine = base + prefix_count(need);
                 if (!live && mine < cnt) {
                     live = true;
                     koff = k0 + mine;
@@ -315,11 +318,11 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                         qn = 0;
                     }
                     if (fin) {
-                        const uint32_t slot = qn + __popcll(fmask & lanemask_lt());
+                        const uint32_t slot = qn + prefix_count(fmask);
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
                         q.koff[slot] = koff;
-                        q.steps[slot] = s;
+                        q.steps[slot] = (sizeof(R) == 8 || CAP) ? s : s + PH + 1;
                         live = false;
                     }
                     qn += nf;
@@ -336,8 +339,12 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             // FP32: the step cap is tested only in blocks where some walk can reach it (the second copy
             // of the block costs the FP64 variants more in registers than it saves)
             if constexpr (sizeof(R) == 4) {
-                if (__any(live && s + SPB >= I.max_steps)) block(std::true_type{});
-                else block(std::false_type{});
+                if (__any(live && s + SPB >= I.max_steps)) {
+                    block(std::true_type{});
+                } else {
+                    block(std::false_type{});
+                    s += SPB;  // steps of the block (a stopped walk's count was written when it stopped)
+                }
             } else {
                 block(std::true_type{});
             }

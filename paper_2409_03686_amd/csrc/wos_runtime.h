@@ -20,6 +20,8 @@ struct RingSlot {
     bool used = false;
 };
 
+struct LiveServer;
+
 struct wos_ctx {
     int device = 0;
     size_t hbm_budget = 0;
@@ -32,6 +34,7 @@ struct wos_ctx {
     std::mutex mu;                  // tuning table
     std::recursive_mutex launch_mu; // staging ring and launches
     std::map<int, wos_tuning> tuning;
+    LiveServer *live = nullptr;     // live serving thread (wos_serve_start), or none
 };
 
 namespace wos {
@@ -46,6 +49,7 @@ struct GroupLaunch {
 };
 
 wos_status set_error(wos_status st, const char *fmt, ...);
+void live_server_stop(wos_ctx *ctx);  // stops and frees the context's live server, if any
 wos_status ctx_malloc(wos_ctx *ctx, void **p, size_t bytes);
 void ctx_free(wos_ctx *ctx, void *p, size_t bytes);
 wos_status validate_geometry(const wos_geometry *g, int *n_elem);

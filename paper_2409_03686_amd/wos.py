@@ -106,6 +106,10 @@ _SIGS = {
     "wos_plan_launch": (C.c_int, [_VP, _VP]),
     "wos_plan_destroy": (C.c_int, [_VP]),
     "wos_serve": (C.c_int, [_VP, C.POINTER(WosRequest), C.c_int32, C.POINTER(WosResult), C.POINTER(WosServeOpts)]),
+    "wos_serve_start": (C.c_int, [_VP, C.POINTER(WosServeOpts)]),
+    "wos_serve_submit": (C.c_int, [_VP, C.POINTER(WosRequest), C.POINTER(C.c_uint64)]),
+    "wos_serve_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(WosResult), C.c_int32]),
+    "wos_serve_stop": (C.c_int, [_VP]),
 }
 
 _lib = None
@@ -312,6 +316,30 @@ def wos_serve(ctx, requests: Sequence[WosRequest], results: Sequence[WosResult],
     opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s))
     _check(lib().wos_serve(ctx, req, len(requests), res, C.byref(opts)))
     return list(res)
+
+
+def wos_serve_start(ctx, hbm_budget_bytes=0, max_inflight=4, timeout_s=0.0):
+    opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s))
+    _check(lib().wos_serve_start(ctx, C.byref(opts)))
+
+
+def wos_serve_submit(ctx, request: WosRequest) -> int:
+    t = C.c_uint64()
+    _check(lib().wos_serve_submit(ctx, C.byref(request), C.byref(t)))
+    return t.value
+
+
+def wos_serve_poll(ctx, ticket: int, result: WosResult, wait_ms: int = -1) -> bool:
+    """True when the request finished (result filled, ticket released), False if still running."""
+    st = lib().wos_serve_poll(ctx, int(ticket), C.byref(result), int(wait_ms))
+    if st == WOS_EBUSY:
+        return False
+    _check(st)
+    return True
+
+
+def wos_serve_stop(ctx):
+    _check(lib().wos_serve_stop(ctx))
 
 
 # ------------------------------------------------------------------------------- torch helpers

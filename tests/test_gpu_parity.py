@@ -555,6 +555,36 @@ def test_serving_results_same_alone_and_in_mix(wos, ctx):
         assert np.array_equal(alone, mix[k]), inst.name
 
 
+def test_live_serving_matches_blocking_driver(wos, ctx):
+    """The live form (submit / poll from the caller's thread, a serving thread owned by the context)
+    returns the same result for each request as the blocking driver, and unknown tickets and
+    polling before completion are reported."""
+    rng = np.random.default_rng(57)
+    insts = [wi.random_instance(rng, i, walk_scale=0.05) for i in range(5)]
+    for inst in insts:
+        inst.x_obs, inst.uD = inst.x_obs[:150], inst.uD[:150]
+    reqs, res, keep = _requests(wos, insts, np.zeros(5))
+    ref = wos.wos_serve(ctx, reqs, res, max_inflight=2)
+    ref_u1 = [np.ctypeslib.as_array(o.u1_host, shape=(int(i.geom.gamma1_mask.sum()),)).copy() for o, i in zip(ref, insts)]
+    wos.wos_serve_start(ctx, max_inflight=3)
+    try:
+        tickets = [wos.wos_serve_submit(ctx, r) for r in reqs]
+        assert len(set(tickets)) == len(tickets)
+        with pytest.raises(wos.WosError):
+            wos.wos_serve_poll(ctx, max(tickets) + 1000, wos.WosResult(), 0)
+        for t, inst, u1r, o_ref in zip(tickets, insts, ref_u1, ref):
+            u1 = np.zeros(u1r.shape)
+            out = wos.WosResult()
+            out.u1_host = u1.ctypes.data_as(C.POINTER(C.c_double))
+            assert wos.wos_serve_poll(ctx, t, out, -1)
+            assert out.status == 0 and out.walks == o_ref.walks and out.t_done >= out.t_admit >= out.t_arrive
+            assert np.array_equal(u1, u1r), inst.name
+            with pytest.raises(wos.WosError):  # the ticket is released
+                wos.wos_serve_poll(ctx, t, out, 0)
+    finally:
+        wos.wos_serve_stop(ctx)
+
+
 def test_serving_admission_by_memory(wos, ctx):
     rng = np.random.default_rng(56)
     insts = [wi.random_instance(rng, i, walk_scale=0.02) for i in range(5)]
