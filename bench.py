@@ -85,6 +85,9 @@ def parse():
                    help="time every walk launch shape first (its launches then appear in kernel traces)")
     p.add_argument("--serve", action="store_true", help="also run the serving latency measurement")
     p.add_argument("--serve-seconds", type=float, default=3.0)
+    p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1),
+                   help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
+    p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
     p.add_argument("--kernel-only", action="store_true",
                    help="for counter collection: one 1 GiB device copy (calibration), then the FP32 walk "
@@ -119,7 +122,7 @@ def cpu_baseline(inst, target_s):
             "steps_per_s": st["steps"] / t_walk}
 
 
-def serve_latency(ctx, wos, wi, seconds, rate=200.0):
+def serve_latency(ctx, wos, wi, seconds, rate=200.0, svd_mode=1):
     """Poisson arrivals of requests from the heterogeneous-instance generator (1-5 % noise, random
     harmonic data of degree <= 6): build H + FP64 SVD + TSVD reconstruction each."""
     import ctypes as C
@@ -149,12 +152,12 @@ def serve_latency(ctx, wos, wi, seconds, rate=200.0):
         reqs.append(r)
         res.append(o)
     t0 = time.perf_counter()
-    out = wos.wos_serve(ctx, reqs, res, hbm_budget_bytes=32 << 30, max_inflight=16)
+    out = wos.wos_serve(ctx, reqs, res, hbm_budget_bytes=32 << 30, max_inflight=16, svd_mode=svd_mode)
     wall = time.perf_counter() - t0
     ok = [o for o in out if o.status == 0]
     lat = np.array([o.t_done - o.t_arrive for o in ok])
     walks = sum(o.walks for o in ok)
-    return {"requests": len(out), "completed": len(ok), "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+    return {"requests": len(out), "completed": len(ok), "rate_req_s": rate, "svd_mode": svd_mode, "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": walks / wall, "wall_s": wall}
 
 
@@ -294,7 +297,7 @@ def main():
     }
     if a.serve:
         log("serving run")
-        out["serving"] = serve_latency(ctx, wos, wi, a.serve_seconds)
+        out["serving"] = serve_latency(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)
     if not a.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)

@@ -280,6 +280,14 @@ typedef struct {
     size_t hbm_budget_bytes;       /* admission bound on the device memory of in-flight requests */
     int32_t max_inflight;          /* concurrent requests on the device (streams) */
     double timeout_s;              /* per request, from arrival; 0 = none */
+    int32_t svd_mode;              /* 0: full SVD of each request (the cooperative Jacobi kernels
+                                    * of wos_svd, which run one at a time on the device);
+                                    * 1: truncated SVD from plain kernels, so requests overlap:
+                                    * the leading min(k, kt) triplets, kt = 64 when min(m, n) <= 64
+                                    * else 128 (a random range sketch of kt columns first when
+                                    * min(m, n) > kt); components below 1e-5 s_1 are not used by
+                                    * the reconstruction, and s_host receives min(k, kt) values
+                                    * followed by zeros. */
 } wos_serve_opts;
 
 /* Blocking driver: replays the requests at their arrival times (open loop), admits each when a

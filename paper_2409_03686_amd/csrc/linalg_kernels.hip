@@ -9,6 +9,8 @@
 //                or Tikhonov), u_1 = sigma^{-1/2} V (phi c), predicted data H_1 u_1 + H_0 u^0.
 // Matrix work is small next to the walks (a 1024 x 192 B at the annulus workload), so every kernel
 // is written for latency: few launches, wave-level shuffles, no host round trips.
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -81,7 +83,7 @@ __global__ void assemble_kernel(SvdDevView v, const uint32_t *__restrict__ count
         }
         v.A[e] = val;
     }
-    const size_t wtot = static_cast<size_t>(v.colsp) * v.colsp;
+    const size_t wtot = v.tk ? 0 : static_cast<size_t>(v.colsp) * v.colsp;  // no W on the truncated path
     for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < wtot;
          e += static_cast<size_t>(gridDim.x) * blockDim.x)
         v.W[e] = (e % v.colsp) == (e / v.colsp) ? 1.0 : 0.0;
@@ -733,6 +735,189 @@ __global__ void gram_accept_kernel(SvdDevView v)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Truncated path (serving): the leading kt singular triplets with single-workgroup and plain
+// kernels only, so that requests on different streams overlap on the device.
+//   cols <= kt: the Gram path of A itself with the Jacobi of one workgroup (lds_jacobi_kernel).
+//   cols >  kt: a range sketch Y = A Om (Om a +-1 matrix from Philox) and an orthonormal basis
+//               Q = Y E diag(1/lambda) from the eigenvectors E, eigenvalues lambda^2 of Y^T Y (Gram
+//               path); two subspace iterations Y = A A^T Q, each re-orthonormalised the same way
+//               (without them the leading singular values come out only to ~1e-3 when the
+//               spectrum has a Monte Carlo noise floor; with them to ~1e-14); then C = Q^T A, the
+//               Gram path of C^T, U = Q E_C, V = C^T E_C / s.
+// Components with s <= rank_cut s_1 (1e-5) are left out of the reconstruction: below that the
+// Gram path's squaring of the condition number makes them inaccurate.
+// ---------------------------------------------------------------------------------------------
+
+// One-sided Jacobi on X (NPD x NPD, column-major) in one workgroup: X in LDS, the NPD / 2 pairs
+// of each round of the circle ordering split over the 16 waves (lanes over rows, DPP totals),
+// norms tracked through the rotations and recomputed at the start of each sweep.  Writes the
+// rotated columns back and their norms to zs.
+template <int NPD>
+__global__ __launch_bounds__(1024) void lds_jacobi_kernel(double *__restrict__ X, double *__restrict__ zs,
+                                                          int32_t *info)
+{
+    extern __shared__ double xs[];  // NPD * NPD
+    __shared__ double nrm[NPD];
+    __shared__ uint32_t nrot_sh;
+    constexpr int RPL = NPD / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int e = tid; e < NPD * NPD; e += 1024) xs[e] = X[e];
+    const double tol = static_cast<double>(NPD) * 0x1.0p-52;
+    const double tol2 = tol * tol;
+    __syncthreads();
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
+        for (int c = w; c < NPD; c += 16) {
+            double acc[1] = {0.0};
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) acc[0] = __builtin_fma(xs[c * NPD + lane + 64 * i], xs[c * NPD + lane + 64 * i], acc[0]);
+            wave_totals<1>(acc);
+            if (lane == 0) nrm[c] = acc[0];
+        }
+        if (tid == 0) nrot_sh = 0u;
+        __syncthreads();
+        uint32_t nrot = 0;
+        for (int t = 0; t < NPD - 1; ++t) {
+            for (int pi = w; pi < NPD / 2; pi += 16) {
+                int p, q;
+                pair_of(t, pi, NPD, p, q);
+                double xp[RPL], xq[RPL], g[1] = {0.0};
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    xp[i] = xs[p * NPD + lane + 64 * i];
+                    xq[i] = xs[q * NPD + lane + 64 * i];
+                    g[0] = __builtin_fma(xp[i], xq[i], g[0]);
+                }
+                wave_totals<1>(g);
+                const double a = nrm[p], b = nrm[q], gg = g[0];
+                if (gg != 0.0 && gg * gg > tol2 * a * b) {
+                    double c, sn, tt;
+                    rot_params(a, b, gg, c, sn, tt);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) {
+                        xs[p * NPD + lane + 64 * i] = c * xp[i] - sn * xq[i];
+                        xs[q * NPD + lane + 64 * i] = sn * xp[i] + c * xq[i];
+                    }
+                    if (lane == 0) {
+                        nrm[p] = a - tt * gg;
+                        nrm[q] = b + tt * gg;
+                    }
+                    ++nrot;
+                }
+            }
+            __syncthreads();
+        }
+        if (lane == 0 && nrot) atomicAdd(&nrot_sh, nrot);
+        __syncthreads();
+        const bool done = nrot_sh == 0u;
+        __syncthreads();
+        if (done) {
+            ++sweep;
+            break;
+        }
+    }
+    for (int e = tid; e < NPD * NPD; e += 1024) X[e] = xs[e];
+    for (int c = w; c < NPD; c += 16) {
+        double acc[1] = {0.0};
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc[0] = __builtin_fma(xs[c * NPD + lane + 64 * i], xs[c * NPD + lane + 64 * i], acc[0]);
+        wave_totals<1>(acc);
+        if (lane == 0) zs[c] = __builtin_sqrt(acc[0]);
+    }
+    if (tid == 0 && info) {
+        info[0] = sweep;
+        info[1] = sweep >= kMaxSweeps ? 2 : 0;
+    }
+}
+
+// C(i, j) = scale_j sum_k opA(i, k) opB(k, j), opA(i, k) = A[i sai + k sak],
+// opB(k, j) = B[k sbk + col(j) sbj] with col(j) = bcol ? bcol[j] : j, and scale_j from z[col(j)]:
+// mode 0: 1, mode 1: 1 / z^2, mode 2: 1 / z (0 where z <= 1e-7 max z).  One 16 x 16 tile per
+// wave (v_mfma_f64_16x16x4f64), C column-major with leading dimension ldc.
+struct GemmArgs {
+    const double *A;
+    long sai, sak;
+    const double *B;
+    long sbk, sbj;
+    const int32_t *bcol;
+    double *C;
+    long ldc;
+    int m, n, kd;
+    const double *z;
+    int zn, mode;
+};
+
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
+{
+    const int tm = (g.m + 15) / 16, tn = (g.n + 15) / 16;
+    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (wave >= tm * tn) return;  // whole waves
+    const int i0 = (wave % tm) * 16, j0 = (wave / tm) * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int i = i0 + li, j = j0 + li;
+    const int cj = j < g.n ? (g.bcol ? g.bcol[j] : j) : 0;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < g.kd; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = (i < g.m && k < g.kd) ? g.A[i * g.sai + k * g.sak] : 0.0;
+        const double b = (j < g.n && k < g.kd) ? g.B[k * g.sbk + cj * g.sbj] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (j >= g.n) return;
+    double scale = 1.0;
+    if (g.mode) {
+        double zmax = 0.0;
+        for (int e = 0; e < g.zn; ++e) zmax = g.z[e] > zmax ? g.z[e] : zmax;
+        const double zc = g.z[cj];
+        scale = zc > 1e-7 * zmax ? (g.mode == 1 ? 1.0 / (zc * zc) : 1.0 / zc) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = i0 + 4 * e + lk;
+        if (r < g.m) g.C[r + j * g.ldc] = acc[e] * scale;
+    }
+}
+
+// Om (rows x cols, column-major) = +-1 from the top bit of Philox4x32-10 words, keyed by the
+// request's seed; counter (row / 4, column, 0x534b4554, 0).
+__global__ void sketch_kernel(double *Om, int rows, int cols, uint32_t k0, uint32_t k1)
+{
+    const size_t total = static_cast<size_t>(rows) * cols;
+    for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int r = static_cast<int>(e % rows), c = static_cast<int>(e / rows);
+        uint32_t c0 = static_cast<uint32_t>(r >> 2), c1 = static_cast<uint32_t>(c), c2 = 0x534b4554u, c3 = 0u;
+        philox4x32_10(c0, c1, c2, c3, k0, k1);
+        const uint32_t wsel = (r & 3) == 0 ? c0 : (r & 3) == 1 ? c1 : (r & 3) == 2 ? c2 : c3;
+        Om[e] = (wsel >> 31) ? 1.0 : -1.0;
+    }
+}
+
+// s[rank] = z[c], perm[rank] = c for the k largest of z[0..n) (descending, ties by index).
+__global__ void rank_kernel(const double *__restrict__ z, int n, int k, double *__restrict__ s_out,
+                            int32_t *__restrict__ perm)
+{
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const double zc = z[c];
+        int rank = 0;
+        for (int o = 0; o < n; ++o) rank += (z[o] > zc || (z[o] == zc && o < c)) ? 1 : 0;
+        if (rank < k) {
+            s_out[rank] = zc;
+            perm[rank] = c;
+        }
+    }
+}
+
+constexpr int kPowerIters = 2;
+
+static hipError_t gemm(const GemmArgs &g, hipStream_t stream)
+{
+    const int tiles = ((g.m + 15) / 16) * ((g.n + 15) / 16);
+    gemm_kernel<<<(tiles + 3) / 4, 256, 0, stream>>>(g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // Reconstruction
 // ---------------------------------------------------------------------------------------------
 __global__ void recon_q_kernel(SvdDevView v, const uint32_t *__restrict__ counts, double inv_n,
@@ -777,7 +962,8 @@ __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out,
     __shared__ int sh_rank;
     const int k = v.k;
     const double s0 = k > 0 ? v.s[0] : 0.0;
-    const double rank_tol = static_cast<double>(v.m > v.n ? v.m : v.n) * 0x1.0p-52 * s0;
+    double rank_tol = static_cast<double>(v.m > v.n ? v.m : v.n) * 0x1.0p-52 * s0;
+    if (v.rank_cut * s0 > rank_tol) rank_tol = v.rank_cut * s0;  // truncated path
     if (threadIdx.x == 0) {
         int kpos = 0;
         for (int l = 0; l < k; ++l) kpos += v.s[l] > rank_tol ? 1 : 0;
@@ -959,6 +1145,79 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     colnorm_kernel<<<gc, 256, 0, stream>>>(v.A, v.rows, v.rows, v.cols, v.work, skip);
     scatter_kernel<<<gc, 256, 0, stream>>>(v, skip);
     return hipGetLastError();
+}
+
+hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, uint64_t seed, hipStream_t stream)
+{
+    static std::once_flag lds_once;
+    std::call_once(lds_once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&lds_jacobi_kernel<64>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 64 * 8);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&lds_jacobi_kernel<128>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
+    });
+    if (v.tk != 64 && v.tk != 128) return hipErrorInvalidValue;
+    const size_t total = static_cast<size_t>(v.rows) * v.colsp;
+    int g = static_cast<int>((total + 255) / 256);
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    assemble_kernel<<<g, 256, 0, stream>>>(v, counts, inv_n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int K = v.tk;
+    const size_t lds = static_cast<size_t>(K) * K * 8;
+    auto chol = [&](double *G, double *L) {
+        SvdDevView w = v;
+        w.G = G;
+        w.L = L;
+        if (K == 64) gram_chol_kernel<1><<<1, 1024, 0, stream>>>(w);
+        else gram_chol_kernel<2><<<1, 1024, 0, stream>>>(w);
+    };
+    auto jac = [&](double *X, double *z) {
+        if (K == 64) lds_jacobi_kernel<64><<<1, 1024, lds, stream>>>(X, z, v.info);
+        else lds_jacobi_kernel<128><<<1, 1024, lds, stream>>>(X, z, v.info);
+    };
+    if (v.cols <= K) {  // the Gram path of A with the one-workgroup Jacobi
+        const int nt = K / 16;
+        gram_kernel<<<(nt * nt + 3) / 4, 256, 0, stream>>>(v);
+        chol(v.G, v.L);
+        jac(v.L, v.zs);
+        gram_vside_kernel<<<K, 64, 0, stream>>>(v);
+        const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
+        gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
+        return hipGetLastError();
+    }
+    const long R = v.rows, Cc = v.cols, Kl = K;
+    const int sg = static_cast<int>(std::min<size_t>(4096, (static_cast<size_t>(Cc) * K + 255) / 256));
+    sketch_kernel<<<sg, 256, 0, stream>>>(v.Om, v.cols, K, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    // Y = A Om
+    if ((e = gemm({v.A, 1, R, v.Om, 1, Cc, nullptr, v.Y, R, v.rows, K, v.cols, nullptr, 0, 0}, stream)) != hipSuccess) return e;
+    // Orthonormal basis of range(Y): Y^T Y = Lt Lt^T, Jacobi -> eigenvectors Lt / zt and eigenvalues
+    // zt^2, Q = Y Lt diag(1 / zt^2) (columns with zt <= 1e-7 max zt dropped)
+    auto orth = [&]() -> hipError_t {
+        hipError_t e2 = gemm({v.Y, R, 1, v.Y, 1, R, nullptr, v.Gt, Kl, K, K, v.rows, nullptr, 0, 0}, stream);
+        if (e2 != hipSuccess) return e2;
+        chol(v.Gt, v.Lt);
+        jac(v.Lt, v.zt);
+        return gemm({v.Y, 1, R, v.Lt, 1, Kl, nullptr, v.Q, R, v.rows, K, K, v.zt, K, 1}, stream);
+    };
+    if ((e = orth()) != hipSuccess) return e;
+    // two subspace iterations Y = A (A^T Q), each followed by orth (Om holds A^T Q)
+    for (int it = 0; it < kPowerIters; ++it) {
+        if ((e = gemm({v.A, R, 1, v.Q, 1, R, nullptr, v.Om, Cc, v.cols, K, v.rows, nullptr, 0, 0}, stream)) != hipSuccess) return e;
+        if ((e = gemm({v.A, 1, R, v.Om, 1, Cc, nullptr, v.Y, R, v.rows, K, v.cols, nullptr, 0, 0}, stream)) != hipSuccess) return e;
+        if ((e = orth()) != hipSuccess) return e;
+    }
+    // C = Q^T A, then the Gram path of C^T: G = C C^T, factor, Jacobi
+    if ((e = gemm({v.Q, R, 1, v.A, 1, R, nullptr, v.Cm, Kl, K, v.cols, v.rows, nullptr, 0, 0}, stream)) != hipSuccess) return e;
+    if ((e = gemm({v.Cm, 1, Kl, v.Cm, Kl, 1, nullptr, v.G, Kl, K, K, v.cols, nullptr, 0, 0}, stream)) != hipSuccess) return e;
+    chol(v.G, v.L);
+    jac(v.L, v.zs);
+    rank_kernel<<<1, 256, 0, stream>>>(v.zs, K, v.k, v.s, v.perm);
+    double *rowside = v.trans ? v.V : v.U;  // rows x k
+    double *colside = v.trans ? v.U : v.V;  // cols x k
+    // U_A = Q E / s (E = L[:, perm] / zs[perm]), V_A = C^T E / s = C^T L[:, perm] / zs^2
+    if ((e = gemm({v.Q, 1, R, v.L, 1, Kl, v.perm, rowside, R, v.rows, v.k, K, v.zs, K, 2}, stream)) != hipSuccess) return e;
+    return gemm({v.Cm, Kl, 1, v.L, 1, Kl, v.perm, colside, Cc, v.cols, v.k, K, v.zs, K, 1}, stream);
 }
 
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,

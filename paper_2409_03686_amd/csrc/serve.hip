@@ -76,14 +76,14 @@ struct Arena {  // first-fit sub-allocator over one device allocation
 };
 
 struct ReqLayout {
-    int M = 0, n1 = 0, n0 = 0, k = 0, dim = 2;
+    int M = 0, n1 = 0, n0 = 0, k = 0, kfull = 0, dim = 2;
     size_t off_x, off_counts, off_stats, off_uD, off_u0, off_u1, off_pred, off_scal, off_svd, total;
     SvdHost svd;
 };
 
 size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
-wos_status layout_request(const wos_request &r, ReqLayout &L)
+wos_status layout_request(const wos_request &r, ReqLayout &L, int svd_mode)
 {
     int M = 0;
     wos_status st = validate_geometry(&r.geom, &M);
@@ -95,7 +95,7 @@ wos_status layout_request(const wos_request &r, ReqLayout &L)
     std::vector<double> sigma(M);
     st = wos_element_measures(&r.geom, sigma.data());
     if (st != WOS_OK) return st;
-    st = svd_layout(r.n_obs, M, r.gamma1_mask_host, sigma.data(), nullptr, L.svd);
+    st = svd_layout(r.n_obs, M, r.gamma1_mask_host, sigma.data(), nullptr, L.svd, svd_mode == 1 ? kTruncRank : 0);
     if (st != WOS_OK) return st;
     st = check_reg(&r.reg);
     if (st != WOS_OK) return st;
@@ -104,6 +104,7 @@ wos_status layout_request(const wos_request &r, ReqLayout &L)
     L.n1 = L.svd.v.n;
     L.n0 = L.svd.v.n0;
     L.k = L.svd.v.k;
+    L.kfull = std::min(L.svd.v.m, L.svd.v.n);
     if (L.n0 > 0 && !r.u0_host) return set_error(WOS_EINVAL, "request needs u0 (Gamma_0 is not empty)");
     size_t o = 0;
     L.off_x = o; o += up256(8ull * r.n_obs * L.dim);
@@ -159,6 +160,7 @@ class Engine {
         max_inflight_ = opts && opts->max_inflight > 0 ? std::min(opts->max_inflight, 64) : 4;
         budget_ = opts && opts->hbm_budget_bytes ? opts->hbm_budget_bytes : (size_t(4) << 30);
         timeout_ = opts ? opts->timeout_s : 0.0;
+        svd_mode_ = opts ? opts->svd_mode : 0;
     }
     ~Engine() { shutdown(); }
 
@@ -181,7 +183,8 @@ class Engine {
     // Validates and lays out a request; on failure the status is recorded in the job's result.
     wos_status prepare(Job &j)
     {
-        wos_status st = layout_request(j.req, j.L);
+        wos_status st = (svd_mode_ == 0 || svd_mode_ == 1) ? layout_request(j.req, j.L, svd_mode_)
+                                                           : set_error(WOS_EINVAL, "svd_mode must be 0 or 1");
         if (st == WOS_OK && j.L.total > budget_)
             st = set_error(WOS_ENOMEM, "request needs %zu bytes, budget %zu", j.L.total, budget_);
         if (st == WOS_OK && !j.res->u1_host) st = set_error(WOS_EINVAL, "request has no u1 output buffer");
@@ -234,7 +237,10 @@ class Engine {
                 const uint8_t *pin = static_cast<const uint8_t *>(s.pinned);
                 std::memcpy(R.u1_host, pin + s.out_u1, 8ull * j.L.n1);
                 if (R.pred_host) std::memcpy(R.pred_host, pin + s.out_pred, 8ull * j.req.n_obs);
-                if (R.s_host) std::memcpy(R.s_host, pin + s.out_s, 8ull * j.L.k);
+                if (R.s_host) {
+                    std::memcpy(R.s_host, pin + s.out_s, 8ull * j.L.k);
+                    std::fill(R.s_host + j.L.k, R.s_host + j.L.kfull, 0.0);
+                }
                 std::memcpy(&R.rank_used, pin + s.out_scal, 4);
                 std::memcpy(&R.alpha_used, pin + s.out_scal + 8, 8);
                 uint64_t stw[WOS_STATS_WORDS];
@@ -319,8 +325,14 @@ class Engine {
             if (st2 != WOS_OK) return st2;
         }
         const uint64_t nw = r.walk.walk_end - r.walk.walk_begin;
-        const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx_->n_cu);
-        e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, s.stream);
+        if (e == hipSuccess) {
+            if (L.svd.v.tk) {
+                e = tsvd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), r.walk.seed ^ (uint64_t(r.walk.instance) << 32) ^ 0x9e3779b97f4a7c15ull, s.stream);
+            } else {
+                const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx_->n_cu);
+                e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, s.stream);
+            }
+        }
         double *u1 = reinterpret_cast<double *>(base + L.off_u1);
         double *pred = reinterpret_cast<double *>(base + L.off_pred);
         int32_t *rank = reinterpret_cast<int32_t *>(base + L.off_scal);
@@ -350,6 +362,7 @@ class Engine {
     int max_inflight_ = 4, inflight_ = 0;
     size_t budget_ = 0;
     double timeout_ = 0.0;
+    int svd_mode_ = 0;
     void *arena_mem_ = nullptr;
     Arena arena_;
     std::vector<Slot> slots_;
@@ -611,7 +624,7 @@ extern "C" wos_status wos_serve_poll(wos_ctx *ctx, uint64_t ticket, wos_result *
     const wos_result &R = j->own;
     if (out->u1_host) std::memcpy(out->u1_host, j->u1.data(), 8ull * j->L.n1);
     if (out->pred_host) std::memcpy(out->pred_host, j->pred.data(), 8ull * j->req.n_obs);
-    if (out->s_host) std::memcpy(out->s_host, j->sv.data(), 8ull * j->L.k);
+    if (out->s_host) std::memcpy(out->s_host, j->sv.data(), 8ull * j->sv.size());
     out->rank_used = R.rank_used;
     out->alpha_used = R.alpha_used;
     out->status = R.status;

@@ -59,7 +59,7 @@ hipError_t wos::fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t stream)
     } while (0)
 
 wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_mask_host, const double *sigma_host,
-                           const double *nu_host, SvdHost &hs)
+                           const double *nu_host, SvdHost &hs, int trunc_k)
 {
     if (n_obs < 1 || n_elem < 1) return set_error(WOS_EINVAL, "n_obs and n_elem must be >= 1");
     if (!gamma1_mask_host || !sigma_host) return set_error(WOS_EINVAL, "gamma1 mask and sigma are required");
@@ -98,16 +98,28 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
     v.n0 = static_cast<int>(hs.g0.size());
     v.tol = static_cast<double>(v.rows) * 0x1.0p-52;
     v.np = gram_order(v.cols);
+    if (trunc_k > 0) {
+        // truncated path: kt = 64 or 128 columns, Gram order kt; k = at most kt triplets
+        v.tk = v.cols <= 64 ? 64 : kTruncRank;
+        v.np = v.tk;
+        v.k = std::min(v.k, v.tk);
+        v.rank_cut = 1e-5;
+    }
     const size_t npn = static_cast<size_t>(v.np);
+    const size_t tkn = static_cast<size_t>(v.tk);
+    const size_t big = v.tk && v.cols > v.tk ? tkn : 0;  // sketch buffers only when projecting
     hs.bytes = 0;
     // device arrays, in carve order
     const size_t sz[] = {
-        carve_size(size_t(v.rows) * v.colsp, 8), carve_size(size_t(v.colsp) * v.colsp, 8), carve_size(v.k, 8),
+        carve_size(size_t(v.rows) * v.colsp, 8), carve_size(v.tk ? 0 : size_t(v.colsp) * v.colsp, 8), carve_size(v.k, 8),
         carve_size(size_t(v.m) * v.k, 8), carve_size(size_t(v.n) * v.k, 8), carve_size(v.m, 8),
         carve_size(v.n, 8), carve_size(hs.g1.size(), 4), carve_size(std::max<size_t>(hs.g0.size(), 1), 4),
         carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
         carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
-        carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(1, 8)};
+        carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(1, 8),
+        carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * big, 8), carve_size(size_t(v.rows) * big, 8),
+        carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(big, 8),
+        carve_size(std::max<size_t>(tkn, 1), 4)};
     for (size_t s : sz) hs.bytes += s;
     return WOS_OK;
 }
@@ -117,7 +129,7 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     SvdDevView &v = hs.v;
     uint8_t *cur = static_cast<uint8_t *>(mem);
     v.A = carve<double>(cur, size_t(v.rows) * v.colsp);
-    v.W = carve<double>(cur, size_t(v.colsp) * v.colsp);
+    v.W = carve<double>(cur, v.tk ? 0 : size_t(v.colsp) * v.colsp);  // Hestenes path only
     v.s = carve<double>(cur, v.k);
     v.U = carve<double>(cur, size_t(v.m) * v.k);
     v.V = carve<double>(cur, size_t(v.n) * v.k);
@@ -138,6 +150,16 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     v.L = carve<double>(cur, npn * npn);
     v.zs = carve<double>(cur, npn);
     v.crit = carve<unsigned long long>(cur, 1);
+    const size_t tkn = static_cast<size_t>(v.tk);
+    const size_t big = v.tk && v.cols > v.tk ? tkn : 0;
+    v.Om = carve<double>(cur, size_t(v.cols) * big);
+    v.Y = carve<double>(cur, size_t(v.rows) * big);
+    v.Q = carve<double>(cur, size_t(v.rows) * big);
+    v.Cm = carve<double>(cur, big * v.cols);
+    v.Gt = carve<double>(cur, big * big);
+    v.Lt = carve<double>(cur, big * big);
+    v.zt = carve<double>(cur, big);
+    v.perm = carve<int32_t>(cur, std::max<size_t>(tkn, 1));
 }
 
 // Bytes of pinned staging svd_upload needs.

@@ -50,6 +50,14 @@ struct SvdDevView {
     double *L;              // np x np factor X with X X^T = G, then its Jacobi-rotated columns
     double *zs;             // np column norms of the rotated factor
     unsigned long long *crit;  // acceptance statistic (bit pattern of a non-negative double)
+    // Truncated path (serving; tk = 0: not used): the kt leading singular triplets from a range
+    // sketch of kt columns (cols > kt) or from the Gram path of A itself (cols <= kt), with
+    // single-workgroup kernels only.
+    int tk;                 // kt, a multiple of 64 (at most 128)
+    double rank_cut;        // components with s <= rank_cut s_1 are left out of reconstructions
+    double *Om, *Y, *Q;     // cols x kt sketch, rows x kt range, rows x kt orthonormal basis
+    double *Cm, *Gt, *Lt, *zt;  // kt x cols projection, kt x kt Gram and factor, kt norms
+    int32_t *perm;          // kt: factor column of each rank
 };
 
 struct RegDev {
@@ -68,6 +76,10 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
                       hipStream_t stream);
 int svd_coop_grid(int rows, int colsp, int n_cu);
 int gram_order(int cols);  // np of the Gram path for this column count, 0 if it does not apply
+// truncated SVD of the assembled work matrix (serving): non-cooperative kernels only
+hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, uint64_t seed,
+                       hipStream_t stream);
+constexpr int kTruncRank = 128;
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
                         const double *u0, const RegDev &reg, double *u1, double *pred, int32_t *rank_out,
                         double *alpha_out, hipStream_t stream);

@@ -68,8 +68,9 @@ struct SvdHost {
     std::vector<double> nu, isig;
     std::vector<int32_t> g1, g0, emap;
 };
+// trunc_k > 0: layout for the truncated path (tsvd_launch) keeping at most trunc_k triplets
 wos_status svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_mask_host, const double *sigma_host,
-                      const double *nu_host, SvdHost &hs);
+                      const double *nu_host, SvdHost &hs, int trunc_k = 0);
 void svd_bind(SvdHost &hs, void *mem);
 size_t svd_staging_bytes(const SvdHost &hs);
 hipError_t svd_upload(const SvdHost &hs, void *staging, hipStream_t stream);

@@ -76,7 +76,8 @@ class WosResult(C.Structure):
 
 
 class WosServeOpts(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32), ("timeout_s", C.c_double)]
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32), ("timeout_s", C.c_double),
+                ("svd_mode", C.c_int32)]
 
 
 # exported entry points: name -> (restype, argtypes)
@@ -310,16 +311,16 @@ def wos_plan_destroy(plan):
 
 
 def wos_serve(ctx, requests: Sequence[WosRequest], results: Sequence[WosResult], hbm_budget_bytes=0,
-              max_inflight=4, timeout_s=0.0):
+              max_inflight=4, timeout_s=0.0, svd_mode=0):
     req = (WosRequest * len(requests))(*requests)
     res = (WosResult * len(results))(*results)
-    opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s))
+    opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s), int(svd_mode))
     _check(lib().wos_serve(ctx, req, len(requests), res, C.byref(opts)))
     return list(res)
 
 
-def wos_serve_start(ctx, hbm_budget_bytes=0, max_inflight=4, timeout_s=0.0):
-    opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s))
+def wos_serve_start(ctx, hbm_budget_bytes=0, max_inflight=4, timeout_s=0.0, svd_mode=0):
+    opts = WosServeOpts(int(hbm_budget_bytes), int(max_inflight), float(timeout_s), int(svd_mode))
     _check(lib().wos_serve_start(ctx, C.byref(opts)))
 
 

@@ -609,3 +609,66 @@ def test_autotune_returns_valid_shape_and_keeps_results(wos, ctx):
     after, _, _ = _gpu(wos, ctx, inst)
     assert np.array_equal(before, after)
     wos.wos_set_tuning(ctx, 2, -1, inst.precision, 256, 32)
+
+
+def _trunc_cases():
+    """Three column regimes of the truncated serving SVD: min(m, n) <= 64 and <= 128 (the Gram path
+    of the matrix itself) and > 128 (range sketch + subspace iterations), the last both as the
+    transposed (n_obs < |Gamma_1|) and the plain orientation."""
+    rng = np.random.default_rng(58)
+    want = [("d64", 48, None), ("d128", 100, None), ("sketch_T", 300, lambda n1: n1 >= 500),
+            ("sketch_N", 900, lambda n1: 160 <= n1 <= 700)]
+    out, i = [], 0
+    for name, n_obs, ok in want:
+        while True:
+            inst = wi.random_instance(rng, i, kind_name="disk" if i % 2 else "annulus")
+            i += 1
+            n1 = int(inst.geom.gamma1_mask.sum())
+            if inst.x_obs.shape[0] >= n_obs and (ok is None or ok(n1)) and n1 >= 8:
+                break
+        inst.x_obs, inst.uD = inst.x_obs[:n_obs], inst.uD[:n_obs]
+        inst.n_walks = 4000
+        inst.name = name
+        out.append(inst)
+    return out
+
+
+def test_serving_truncated_svd_matches_full_svd(wos, ctx):
+    """svd_mode 1 (truncated SVD from plain kernels) against svd_mode 0 (the full Jacobi SVD) on
+    the same requests: the same walks, leading singular values to 1e-8 relative and the rank-8
+    TSVD reconstruction to 1e-4 relative (the sketch's subspace error with 4000 walks per point is
+    ~1e-5 there); trailing s_host entries beyond the kept triplets are zero."""
+    insts = _trunc_cases()
+    out = {}
+    for mode in (0, 1):
+        reqs, res, keep = _requests(wos, insts, np.zeros(len(insts)))
+        svals = []
+        for r, o, inst in zip(reqs, res, insts):
+            r.reg = wos.reg_params(wos.WOS_TSVD_RANK, rank=8)
+            sv = np.full(min(inst.x_obs.shape[0], int(inst.geom.gamma1_mask.sum())), -1.0)
+            o.s_host = sv.ctypes.data_as(C.POINTER(C.c_double))
+            svals.append(sv)
+        print("svd_mode", mode, [(i.name, i.x_obs.shape[0], int(i.geom.gamma1_mask.sum())) for i in insts], flush=True)
+        got = wos.wos_serve(ctx, reqs, res, max_inflight=4, svd_mode=mode)
+        out[mode] = [(o.status, o.walks, o.rank_used,
+                      np.ctypeslib.as_array(o.u1_host, shape=(int(i.geom.gamma1_mask.sum()),)).copy(), sv.copy())
+                     for o, i, sv in zip(got, insts, svals)]
+    for inst, full, tr in zip(insts, out[0], out[1]):
+        assert full[0] == 0 and tr[0] == 0, inst.name
+        assert full[1] == tr[1]
+        assert full[2] == tr[2] == 8, (inst.name, full[2], tr[2])
+        k = len(full[4])
+        kt = min(k, 64 if k <= 64 else 128)
+        np.testing.assert_allclose(tr[4][:8], full[4][:8], rtol=1e-8, err_msg=inst.name)
+        assert np.all(tr[4][kt:] == 0.0), inst.name
+        assert np.all(np.diff(tr[4][:kt]) <= 0.0), inst.name
+        d = np.linalg.norm(tr[3] - full[3]) / np.linalg.norm(full[3])
+        print(inst.name, "k", k, "u1 rel diff %.2e" % d, flush=True)
+        assert d < 1e-4, (inst.name, d)
+
+
+def test_serving_truncated_svd_rejects_bad_mode(wos, ctx):
+    insts = _trunc_cases()[:1]
+    reqs, res, keep = _requests(wos, insts, np.zeros(1))
+    out = wos.wos_serve(ctx, reqs, res, max_inflight=1, svd_mode=3)
+    assert out[0].status == wos.WOS_EINVAL
