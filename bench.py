@@ -4,7 +4,10 @@ Workload (the configuration the metric is quoted on): 2D annulus r in [0.3, 1], 
 [.5, 2]], 128 + 128 boundary arcs, 1024 observation points, N = 1e5 walks per point, eps = 1e-4,
 FP32 walk geometry with FP64 exit test / binning, then FP64 SVD of the 1024 x 192 Gamma_1 block and
 the TSVD reconstruction (discrepancy principle) of u_1.  One step = zero counts + walk kernel +
-assembly + SVD + reconstruction, replayed as one captured HIP graph; inputs are resident in HBM.
+assembly + SVD + reconstruction; inputs are resident in HBM.  Steps are pipelined over two CU
+partitions (two streams with CU masks): the walk kernel of step i + 1 runs on most CUs while the
+SVD and reconstruction of step i run on the rest; ms_per_step is the interval between step
+completions, and the latency of one step alone (a captured HIP graph) is reported beside it.
 
 Prints one JSON line (rank 0).  Extra fields: the walk kernel alone (HIP events on its stream), the
 FP64 walk path, the roofline of the walk kernel, the CPU oracle baseline and serving latency.
@@ -77,9 +80,11 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--walks", type=int, default=100_000)
+    p.add_argument("--spectral-cus", type=int, default=32,
+                   help="CUs of the spectral stream (SVD + reconstruction); the walk kernel gets the rest")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--autotune", action="store_true",
                    help="time every walk launch shape first (its launches then appear in kernel traces)")
@@ -210,27 +215,89 @@ def main():
     if a.autotune:
         tuned = tuple(wos.wos_autotune(ctx, job, max(1, inst.n_walks // 5)))
         log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}")
-    plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred, rank)
-    stream = torch.cuda.current_stream()
+    # --- timed region: the path pipelined over two CU partitions.  Step i runs its walk kernel on
+    # the walk stream and its spectral step (assembly, SVD, reconstruction) on the spectral stream,
+    # where it overlaps the walk kernel of step i + 1; buffers alternate between two sets, and a
+    # set is reused only after the spectral step that read it has finished.
+    walk_s, spec_s = wos.wos_streams_create(ctx, a.spectral_cus)
+    sw, ss = torch.cuda.ExternalStream(walk_s), torch.cuda.ExternalStream(spec_s)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    sets = []
+    for b in range(2):
+        c_b = counts if b == 0 else torch.zeros_like(counts)
+        st_b = stats if b == 0 else torch.zeros_like(stats)
+        h_b = h if b == 0 else wos.wos_svd_create(ctx, n_obs, M, g.gamma1_mask, sigma)
+        sets.append({"counts": c_b, "stats": st_b, "h": h_b, "u1": u1 if b == 0 else torch.zeros_like(u1),
+                     "pred": pred if b == 0 else torch.zeros_like(pred),
+                     "rank": rank if b == 0 else torch.zeros_like(rank)})
+    wp = wos.walk_params_of(inst)
+    spec_done = [None, None]
+    walk_ev = []
 
-    log("plan captured; warmup")
-    for _ in range(a.warmup):
-        wos.wos_plan_launch(plan, stream)
+    def step(i, timed):
+        S = sets[i % 2]
+        if spec_done[i % 2] is not None:
+            sw.wait_event(spec_done[i % 2])
+        with torch.cuda.stream(sw):
+            S["counts"].zero_()
+            S["stats"].zero_()
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sw)
+        wos.wos_build_measure(ctx, g, wp, x, n_obs, S["counts"], S["stats"], None, walk_s)
+        walked = torch.cuda.Event()
+        walked.record(sw)
+        if timed:
+            e1.record(sw)
+            walk_ev.append((e0, e1))
+        ss.wait_event(walked)
+        wos.wos_svd(ctx, S["h"], S["counts"], inst.n_walks, spec_s)
+        wos.wos_reconstruct(ctx, S["h"], S["counts"], inst.n_walks, uD, u0, reg, S["u1"], S["pred"], S["rank"],
+                            None, spec_s)
+        done = torch.cuda.Event()
+        done.record(ss)
+        spec_done[i % 2] = done
+
+    log(f"pipelined path on {n_cu - a.spectral_cus} + {a.spectral_cus} CUs; warmup")
+    for i in range(a.warmup):
+        step(i, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        wos.wos_plan_launch(plan, stream)
+    for i in range(a.steps):
+        step(a.warmup + i, True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    st = wos.stats_dict(stats)
+    walk_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in walk_ev]))
     walks_step = n_obs * inst.n_walks
-    steps_step = st["steps"]
-    assert st["walks"] == walks_step, st
+    steps_step, lane_slots, fp64_evals = 0, 0, 0
+    for S in sets:
+        st = wos.stats_dict(S["stats"])
+        assert st["walks"] == walks_step, st
+        steps_step = st["steps"]
+        lane_slots = st["lane_slots"]
+        fp64_evals = st["fp64_evals"]
+    last = sets[(a.warmup + a.steps - 1) % 2]
     ms_step = elapsed / a.steps * 1e3
-    u1_h = u1.cpu().numpy()
+    u1_h = last["u1"].cpu().numpy()
     err = float(np.abs(u1_h - inst.u_exact_g1).max() / np.abs(inst.u_exact_g1).max())
+    rank_used = int(last["rank"].item())
+    log(f"timed {a.steps} pipelined steps: {ms_step:.2f} ms/step; walk kernel {walk_ms:.3f} ms")
 
-    # walk kernel alone: HIP events on the launch stream
+    # --- one step at a time (latency): the whole path of one instance as one captured HIP graph
+    plan = wos.wos_plan_create(ctx, job, h, uD, u0, reg, u1, pred, rank)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        wos.wos_plan_launch(plan, stream)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(5):
+        t1 = time.perf_counter()
+        wos.wos_plan_launch(plan, stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    latency_ms = float(np.median(lat))
+
+    # the walk kernel alone on the whole device: HIP events on the launch stream
     def time_walks(precision, reps):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         w = wos.walk_params_of(inst, precision=precision)
@@ -259,18 +326,20 @@ def main():
     sweeps, svd_err, method = wos.wos_svd_info(h, stream)
     svd_info = {"ms": float(np.mean(svd_ms)), "sweeps": sweeps, "error_flag": svd_err,
                 "method": "gram" if method == wos.WOS_SVD_GRAM else "hestenes"}
-    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step; svd {svd_info}; timing the walk kernel alone")
-    walk_ms, st32 = time_walks(wi.FP32_GEOM_FP64_EXIT, max(3, a.steps // 2))
+    full_ms, st32 = time_walks(wi.FP32_GEOM_FP64_EXIT, 3)
     walk64_ms, st64 = time_walks(wi.FP64, 3)
-    ops = st32["steps"] * OPS_PER_STEP_2D_FP32 + st32["walks"] * OPS_PER_WALK
+    ops = steps_step * OPS_PER_STEP_2D_FP32 + walks_step * OPS_PER_WALK
     achieved = ops / (walk_ms * 1e-3)
     traffic, traffic_detail = measured_traffic(tuned)
+    walk_cus = n_cu - a.spectral_cus
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "traffic_detail": traffic_detail,
             "algorithmic_bytes": n_obs * ALGO_BYTES_PER_POINT,
-            "kernel": "walk_kernel<float,2,annulus>", "avg_ms": walk_ms,
+            "kernel": "walk_kernel<float,2,annulus>", "avg_ms": walk_ms, "cus": walk_cus,
+            "frac_of_partition": achieved / (VALU_PEAK_OPS * walk_cus / n_cu),
+            "whole_device": {"avg_ms": full_ms, "frac": ops / (full_ms * 1e-3) / VALU_PEAK_OPS},
             "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
-            "simd_efficiency": st32["steps"] / max(st32["lane_slots"], 1),
+            "simd_efficiency": steps_step / max(lane_slots, 1),
             "launch_shape": {"block": tuned[0], "walks_per_lane": tuned[1]}}
 
     out = {
@@ -286,13 +355,15 @@ def main():
                                "the 1024x192 Gamma_1 block; TSVD (discrepancy) reconstruction of u_1",
                    "n_obs": n_obs, "n_walks": inst.n_walks, "n_elem": M, "eps": inst.eps},
         "sphere_steps_per_s": steps_step * a.steps / elapsed,
-        "walk_kernel": {"fp32_ms": walk_ms, "fp32_walks_per_s": walks_step / (walk_ms * 1e-3),
-                        "fp32_steps_per_s": st32["steps"] / (walk_ms * 1e-3),
+        "pipeline": {"walk_cus": walk_cus, "spectral_cus": a.spectral_cus, "buffer_sets": 2,
+                     "step_latency_ms": latency_ms},
+        "walk_kernel": {"fp32_ms": full_ms, "fp32_walks_per_s": walks_step / (full_ms * 1e-3),
+                        "fp32_steps_per_s": st32["steps"] / (full_ms * 1e-3),
                         "fp64_ms": walk64_ms, "fp64_walks_per_s": walks_step / (walk64_ms * 1e-3),
                         "fp64_steps_per_s": st64["steps"] / (walk64_ms * 1e-3),
                         "fp32_fp64_evals": st32["fp64_evals"], "escapes": st32["escapes"] + st64["escapes"]},
         "svd": svd_info,
-        "reconstruction": {"rank": int(rank.item()), "max_rel_err_u1": err},
+        "reconstruction": {"rank": rank_used, "max_rel_err_u1": err},
         "roofline": roof,
     }
     if a.serve:
@@ -302,7 +373,10 @@ def main():
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     wos.wos_plan_destroy(plan)
-    wos.wos_svd_destroy(ctx, h)
+    torch.cuda.synchronize()
+    wos.wos_streams_destroy(ctx, walk_s, spec_s)
+    for S in sets:
+        wos.wos_svd_destroy(ctx, S["h"])
     wos.wos_destroy(ctx)
     print(json.dumps(out))
 

@@ -58,6 +58,18 @@ wos_status wos_destroy(wos_ctx *ctx);
 /* Message of the last non-OK status returned on this thread ("" if none). */
 const char *wos_last_error(void);
 
+/* Two streams of the context's device on disjoint sets of CUs (HIP CU masks): *spectral_stream
+ * may use the last spectral_cus CUs, *walk_stream all the others.  With the walk kernel of one
+ * instance on the walk stream and the spectral step (assembly, SVD, reconstruction) of the
+ * previous instance on the spectral stream, the two overlap: the spectral step is latency-bound
+ * on a few workgroups, and its cooperative Jacobi launch does not share CUs with the persistent
+ * walk kernel.  Walk grids and cooperative SVD grids are sized for the CUs of the stream they are
+ * launched on, so every entry point that takes a stream works on either; results are the same as
+ * on an unrestricted stream.  1 <= spectral_cus < number of CUs.  The caller owns the streams and
+ * releases them with wos_streams_destroy (after its work on them has finished). */
+wos_status wos_streams_create(wos_ctx *ctx, int32_t spectral_cus, void **walk_stream, void **spectral_stream);
+wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_stream);
+
 /* ------------------------------------------------------------------------------------------- */
 /* Geometry                                                                                      */
 /* ------------------------------------------------------------------------------------------- */

@@ -568,6 +568,7 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    gl.per_cu = per_cu;
     uint64_t grid = static_cast<uint64_t>(per_cu) * ctx->n_cu;
     grid = std::min<uint64_t>(grid, std::max<uint64_t>(items, 1));
     gl.grid = static_cast<int>(grid);
@@ -580,6 +581,54 @@ static void patch_segs(std::vector<uint8_t> &buf, int n_inst, uintptr_t dev_base
     DevInst *I = reinterpret_cast<DevInst *>(buf.data());
     for (int q = 0; q < n_inst; ++q)
         I[q].segs = reinterpret_cast<const PolySeg *>(dev_base + reinterpret_cast<uintptr_t>(I[q].segs));
+}
+
+int wos::stream_cus(const wos_ctx *ctx, hipStream_t s)
+{
+    if (!s) return ctx->n_cu;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return ctx->n_cu;
+    constexpr int kWords = 64;  // up to 2048 CUs
+    uint32_t mask[kWords] = {};
+    const int words = std::min(kWords, (ctx->n_cu + 31) / 32);
+    if (hipExtStreamGetCUMask(s, static_cast<uint32_t>(words), mask) != hipSuccess) return ctx->n_cu;
+    int c = 0;
+    for (int w = 0; w < words; ++w) c += __builtin_popcount(w == words - 1 && ctx->n_cu % 32 ? mask[w] & ((1u << (ctx->n_cu % 32)) - 1u) : mask[w]);
+    return c >= 1 ? c : ctx->n_cu;
+}
+
+extern "C" wos_status wos_streams_create(wos_ctx *ctx, int32_t spectral_cus, void **walk_stream, void **spectral_stream)
+{
+    if (!ctx || !walk_stream || !spectral_stream) return set_error(WOS_EINVAL, "NULL argument");
+    if (spectral_cus < 1 || spectral_cus >= ctx->n_cu)
+        return set_error(WOS_EINVAL, "spectral_cus must be in [1, %d]", ctx->n_cu - 1);
+    *walk_stream = *spectral_stream = nullptr;
+    const int words = (ctx->n_cu + 31) / 32;
+    std::vector<uint32_t> mw(words, 0u), ms(words, 0u);
+    for (int c = 0; c < ctx->n_cu; ++c) {
+        std::vector<uint32_t> &m = c >= ctx->n_cu - spectral_cus ? ms : mw;
+        m[c / 32] |= 1u << (c % 32);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t a = nullptr, b = nullptr;
+    hipError_t e = hipExtStreamCreateWithCUMask(&a, static_cast<uint32_t>(words), mw.data());
+    if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&b, static_cast<uint32_t>(words), ms.data());
+    if (e != hipSuccess) {
+        if (a) (void)hipStreamDestroy(a);
+        return set_error(WOS_EDEVICE, "hipExtStreamCreateWithCUMask failed: %s", hipGetErrorString(e));
+    }
+    *walk_stream = a;
+    *spectral_stream = b;
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_stream)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx NULL");
+    (void)hipSetDevice(ctx->device);
+    if (walk_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(walk_stream));
+    if (spectral_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(spectral_stream));
+    return WOS_OK;
 }
 
 wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const GroupLaunch &gl, hipStream_t stream)
@@ -611,8 +660,11 @@ wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const 
     std::memcpy(slot.host, buf.data(), buf.size());
     uint32_t *cursor = reinterpret_cast<uint32_t *>(dev + ((buf.size() + 15) & ~size_t(15)));
     HIP_TRY(ctx, hipMemcpyAsync(dev, slot.host, buf.size(), hipMemcpyHostToDevice, stream));
+    // a persistent grid for the CUs this stream may use (fewer on a CU-masked stream)
+    const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(gl.per_cu) * stream_cus(ctx, stream),
+                                             std::max<uint64_t>(gl.items, 1));
     HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, reinterpret_cast<const DevInst *>(dev), gl.n_inst, gl.items,
-                              cursor, gl.hist_words, gl.seg_bytes, gl.block, gl.grid, stream));
+                              cursor, gl.hist_words, gl.seg_bytes, gl.block, static_cast<int>(grid), stream));
     HIP_TRY(ctx, hipEventRecord(slot.done, stream));
     slot.used = true;
     return WOS_OK;

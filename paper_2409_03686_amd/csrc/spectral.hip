@@ -239,7 +239,9 @@ extern "C" wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts
     if (n_walks == 0) return set_error(WOS_EINVAL, "n_walks must be >= 1");
     if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, svd_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), h->coop_grid,
+    // cooperative grids sized for the CUs the stream may use (all, or its CU mask)
+    const int coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, stream_cus(ctx, static_cast<hipStream_t>(stream)));
+    HIP_TRY(ctx, svd_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), coop_grid,
                             static_cast<hipStream_t>(stream)));
     return WOS_OK;
 }

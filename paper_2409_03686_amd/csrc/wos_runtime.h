@@ -43,12 +43,14 @@ struct GroupLaunch {
     int n_inst = 0;
     uint64_t items = 0;
     int block = 256, grid = 1;
+    int per_cu = 1;  // resident blocks per CU (grid = per_cu x CUs of the launch stream, at most items)
     int hist_words = 4, seg_bytes = 0;
     int precision = 0, dim = 2;
     int kind_sel = -1;  // shared domain kind of the instances, -1 if mixed
 };
 
 wos_status set_error(wos_status st, const char *fmt, ...);
+int stream_cus(const wos_ctx *ctx, hipStream_t s);  // CUs the stream may use (its CU mask), else all
 void live_server_stop(wos_ctx *ctx);  // stops and frees the context's live server, if any
 wos_status ctx_malloc(wos_ctx *ctx, void **p, size_t bytes);
 void ctx_free(wos_ctx *ctx, void *p, size_t bytes);

@@ -84,6 +84,8 @@ class WosServeOpts(C.Structure):
 _VP = C.c_void_p
 _SIGS = {
     "wos_create": (C.c_int, [C.POINTER(_VP), C.c_int, C.c_size_t]),
+    "wos_streams_create": (C.c_int, [_VP, C.c_int32, C.POINTER(_VP), C.POINTER(_VP)]),
+    "wos_streams_destroy": (C.c_int, [_VP, _VP, _VP]),
     "wos_destroy": (C.c_int, [_VP]),
     "wos_last_error": (C.c_char_p, []),
     "wos_element_count": (C.c_int, [C.POINTER(WosGeometry), C.POINTER(C.c_int32)]),
@@ -199,6 +201,17 @@ def wos_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
 
 def wos_destroy(ctx: int):
     _check(lib().wos_destroy(ctx))
+
+
+def wos_streams_create(ctx, spectral_cus: int):
+    """(walk_stream, spectral_stream) raw hipStream_t handles on disjoint CU sets."""
+    a, b = C.c_void_p(), C.c_void_p()
+    _check(lib().wos_streams_create(ctx, int(spectral_cus), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def wos_streams_destroy(ctx, walk_stream, spectral_stream):
+    _check(lib().wos_streams_destroy(ctx, walk_stream, spectral_stream))
 
 
 def wos_last_error() -> str:

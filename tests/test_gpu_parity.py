@@ -672,3 +672,45 @@ def test_serving_truncated_svd_rejects_bad_mode(wos, ctx):
     reqs, res, keep = _requests(wos, insts, np.zeros(1))
     out = wos.wos_serve(ctx, reqs, res, max_inflight=1, svd_mode=3)
     assert out[0].status == wos.WOS_EINVAL
+
+
+def test_partitioned_streams_give_the_same_results(wos, ctx):
+    """Walks on the walk stream of a CU partition and SVDs (a Gram-path size and a Hestenes-path
+    size, whose cooperative grid is sized for the partition's CUs) on the spectral stream give the
+    same counts and factors as on an unrestricted stream; both streams run at once; bad partition
+    sizes are rejected."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for bad in (0, n_cu):
+        with pytest.raises(wos.WosError):
+            wos.wos_streams_create(ctx, bad)
+    walk_s, spec_s = wos.wos_streams_create(ctx, 8)
+    try:
+        inst = wi.cfg2_annulus(n_walks=3000, n_obs=256, precision=wi.FP32_GEOM_FP64_EXIT)
+        ref, _, _ = _gpu(wos, ctx, inst)
+        x = wos.device_inputs(inst)
+        cnt = torch.zeros((256, inst.geom.n_elem), dtype=torch.int32, device="cuda")
+        rng = np.random.default_rng(59)
+        cases = []
+        for m, M, n1 in ((300, 200, 160), (600, 700, 300)):  # Gram path (160 cols), Hestenes path (300)
+            p = rng.dirichlet(np.ones(M), size=m)
+            ct = np.stack([rng.multinomial(2000, pi) for pi in p]).astype(np.int32)
+            mask = np.zeros(M, np.uint8)
+            mask[rng.choice(M, n1, replace=False)] = 1
+            sigma = np.full(M, 1.0 / M)
+            h_ref, ct_d, U0, s0, V0, _, _ = _svd_case(wos, ctx, ct, 2000, mask, sigma)
+            h = wos.wos_svd_create(ctx, m, M, mask, sigma)
+            cases.append((h, h_ref, ct_d, s0, U0, V0))
+        print("partitioned streams: walks + SVDs concurrently", flush=True)
+        wos.wos_build_measure(ctx, inst.geom, wos.walk_params_of(inst), x, 256, cnt, None, None, walk_s)
+        for h, _, ct_d, _, _, _ in cases:
+            wos.wos_svd(ctx, h, ct_d, 2000, spec_s)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(cnt), ref)
+        for h, h_ref, _, s0, U0, V0 in cases:
+            U, s, V = wos.svd_factors_numpy(h)
+            assert np.array_equal(s, s0) and np.array_equal(U, U0) and np.array_equal(V, V0)
+            wos.wos_svd_destroy(ctx, h)
+            wos.wos_svd_destroy(ctx, h_ref)
+    finally:
+        torch.cuda.synchronize()
+        wos.wos_streams_destroy(ctx, walk_s, spec_s)
