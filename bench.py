@@ -88,7 +88,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--autotune", action="store_true",
                    help="time every walk launch shape first (its launches then appear in kernel traces)")
-    p.add_argument("--serve", action="store_true", help="also run the serving latency measurement")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
@@ -127,15 +127,11 @@ def cpu_baseline(inst, target_s):
             "steps_per_s": st["steps"] / t_walk}
 
 
-def serve_latency(ctx, wos, wi, seconds, rate=200.0, svd_mode=1):
-    """Poisson arrivals of requests from the heterogeneous-instance generator (1-5 % noise, random
-    harmonic data of degree <= 6): build H + FP64 SVD + TSVD reconstruction each."""
+def _requests(wos, insts, arrivals):
+    """wos_request / wos_result arrays for the instances (host buffers kept alive in `keep`)."""
     import ctypes as C
-    arr = wi.cfg5_arrivals(rate=rate, duration_s=seconds, seed=5)
-    rng = np.random.default_rng(5)
-    insts = [wi.random_instance(rng, i) for i in range(len(arr))]
     reqs, res, keep = [], [], []
-    for inst, t in zip(insts, arr):
+    for inst, t in zip(insts, arrivals):
         r = wos.WosRequest()
         gs = wos.geometry(inst.geom)
         r.geom = gs
@@ -156,14 +152,44 @@ def serve_latency(ctx, wos, wi, seconds, rate=200.0, svd_mode=1):
         keep += [gs, x, m, uD, u0, u1]
         reqs.append(r)
         res.append(o)
+    return reqs, res, keep
+
+
+def _serve(ctx, wos, insts, arrivals, svd_mode):
+    reqs, res, keep = _requests(wos, insts, arrivals)
     t0 = time.perf_counter()
     out = wos.wos_serve(ctx, reqs, res, hbm_budget_bytes=32 << 30, max_inflight=16, svd_mode=svd_mode)
     wall = time.perf_counter() - t0
     ok = [o for o in out if o.status == 0]
-    lat = np.array([o.t_done - o.t_arrive for o in ok])
-    walks = sum(o.walks for o in ok)
-    return {"requests": len(out), "completed": len(ok), "rate_req_s": rate, "svd_mode": svd_mode, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": walks / wall, "wall_s": wall}
+    lat = np.array([o.t_done - o.t_arrive for o in ok]) if ok else np.zeros(1)
+    return {"requests": len(out), "completed": len(ok), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": sum(o.walks for o in ok) / wall,
+            "steps_per_s": sum(o.steps for o in ok) / wall, "wall_s": wall}
+
+
+def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1):
+    """Request serving on the heterogeneous-instance generator (kinds, conductivities, sizes and walk
+    budgets drawn per request; 1-5 % noise; random harmonic data of degree <= 6): each request is
+    build H + FP64 SVD + TSVD reconstruction, host buffers in and out.  Capacity = requests per
+    second with every request queued at t = 0; then open-loop Poisson arrivals at `rate` for
+    `seconds`, and, when that load exceeds the capacity, at 0.8 x capacity as well."""
+    arr = wi.cfg5_arrivals(rate=rate, duration_s=seconds, seed=5)
+    rng = np.random.default_rng(5)
+    insts = [wi.random_instance(rng, i) for i in range(len(arr))]
+    cap = _serve(ctx, wos, insts, np.zeros(len(insts)), svd_mode)
+    capacity = cap["completed"] / cap["wall_s"]
+    offered = _serve(ctx, wos, insts, arr, svd_mode)
+    mean_walks = float(np.mean([i.x_obs.shape[0] * i.n_walks for i in insts]))
+    out = {"svd_mode": svd_mode, "capacity_req_s": capacity, "capacity_walks_per_s": cap["walks_per_s"],
+           "capacity_steps_per_s": cap["steps_per_s"], "mean_walks_per_request": mean_walks,
+           "offered_rate_req_s": rate, "utilisation": rate / capacity, "at_offered_rate": offered}
+    if rate >= capacity:
+        r8 = 0.8 * capacity
+        arr8 = wi.cfg5_arrivals(rate=r8, duration_s=seconds, seed=5)
+        while len(insts) < len(arr8):
+            insts.append(wi.random_instance(rng, len(insts)))
+        out["at_0.8_capacity"] = dict(_serve(ctx, wos, insts[:len(arr8)], arr8, svd_mode), rate_req_s=r8)
+    return out
 
 
 def main():
@@ -366,9 +392,9 @@ def main():
         "reconstruction": {"rank": rank_used, "max_rel_err_u1": err},
         "roofline": roof,
     }
-    if a.serve:
-        log("serving run")
-        out["serving"] = serve_latency(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)
+    if not a.no_serve:
+        log("serving runs")
+        out["serving"] = serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)
     if not a.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
