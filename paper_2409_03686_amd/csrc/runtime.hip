@@ -390,6 +390,10 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         I.p[k] = g->params[k];
         I.pf[k] = static_cast<float>(g->params[k]);
     }
+    if (g->kind == WOS_ANNULUS) {
+        I.pf[4] = static_cast<float>(0.5 * (g->params[2] + g->params[3]));
+        I.pf[5] = static_cast<float>(0.5 * (g->params[3] - g->params[2]));
+    }
     if (g->kind == WOS_ELLIPSE) {
         I.pf[4] = static_cast<float>(1.0 / g->params[2]);
         I.pf[5] = static_cast<float>(1.0 / g->params[3]);
@@ -414,6 +418,16 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
     const double delta = std::ldexp(domain_scale(g), dexp);
     I.delta = static_cast<float>(delta);
     I.neg2delta = -2.0f * I.delta;
+    if (g->dim == 2) {
+        for (int a = 0; a < 2; ++a) {
+            const double A = std::hypot(I.S[a * 3 + 0], I.S[a * 3 + 1]);
+            const double phi = std::atan2(I.S[a * 3 + 1], I.S[a * 3 + 0]) / (2.0 * M_PI);  // revolutions
+            I.fold_off[a] = static_cast<float>(0x1.0p-25 - phi);
+            // FP32 rounding moves these by 2^-24 relative at most, well inside the 2^-16 shrink
+            I.fold_rs[a] = static_cast<float>(A * (1.0 - 0x1.0p-16));
+            I.fold_rn[a] = static_cast<float>(A * static_cast<double>(I.neg2delta));
+        }
+    }
     // thresholds rounded outward so that the certain-exit test stays certain after rounding
     float lo = static_cast<float>(w->eps - delta), hi = static_cast<float>(w->eps + delta);
     if (static_cast<double>(lo) > w->eps - delta) lo = std::nextafter(lo, -INFINITY);

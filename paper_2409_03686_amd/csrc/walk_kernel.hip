@@ -149,7 +149,7 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
     if (lane < n) {
         double x[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) x[a] = static_cast<double>(q.pos[a * kWave + lane]);
+        for (int a = 0; a < DIM; ++a) x[a] = static_cast<double>(q.pos[a * kWave + lane]) + origin<R, KIND>(I, a);
         const int j = element64<KIND, DIM>(I, x, segs);
         atomicAdd(&hist[j], 1u);
         const uint32_t sw = q.steps[lane];
@@ -167,49 +167,66 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
     }
 }
 
-// One sphere step of a live walk (phase PH of its Philox block).  Returns true when the walk
-// stops: inside the eps-shell, or at the step cap (then bit 31 of s is set).  CAP = false when no
-// walk of the wave can reach the cap within this Philox block; then s is not advanced here (the
-// caller adds the block's steps at its end and PH + 1 for a walk that stops inside it).
+// Loop-invariant operands of the folded 2D FP32 step, held in VGPRs (a fused multiply-add has room
+// for one scalar operand only, so scalar ones would cost a move per use).
+struct Fold32 {
+    float off0, off1, rs0, rs1, rn0, rn1;
+};
+
+// One sphere step of a live walk (phase PH of its Philox block).  A walk that stops gets d = -1
+// when the decision was not the plain comparison d <= eps (FP64 band test, step cap), so that the
+// caller's test d <= eps (FP64) / d <= eps_lo (FP32) alone tells which walks stopped.  At the cap,
+// bit 31 of s is set.  CAP = false when no walk of the wave can reach the cap within this Philox
+// block; then s is not advanced here (the caller adds the block's steps at its end and PH + 1 for
+// a walk that stops inside it).
 template <typename R, int DIM, int KIND, int PH, bool CAP>
-__device__ __forceinline__ bool walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], R *x, R &d,
-                                          uint32_t &s, uint32_t &n_fp64)
+__device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], const Fold32 &F,
+                                          R *x, R &d, uint32_t &s, uint32_t &n_fp64)
 {
-    R U[DIM];
-    Dir<R, DIM>::template get<PH>(w, U);
-    bool fin;
     if constexpr (sizeof(R) == 8) {
+        R U[DIM];
+        Dir<R, DIM>::template get<PH>(w, U);
         const double r = radius64<KIND, DIM>(I, x, d);
         step64<DIM>(I, x, r, U);
         d = dist64<KIND, DIM>(I, x, segs);
         s += 1;
-        fin = !(d > I.eps);
+        if (d > I.eps && s >= I.max_steps) {
+            d = -1.0;
+            s |= kCapBit;
+        }
     } else {
         // conservative radius: below the true distance by more than the FP32 distance error
         // (2 delta) and the direction's norm error (relative 2^-16)
         const float rr = radius32<KIND, DIM>(I, x, d);
-        const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, I.neg2delta);
-        step32<DIM>(I, x, r, U);
+        if constexpr (DIM == 2) {
+            const float t = static_cast<float>(w[PH] >> 8);
+            const float c0 = __builtin_amdgcn_cosf(__builtin_fmaf(t, 0x1.0p-24f, F.off0));
+            const float c1 = __builtin_amdgcn_cosf(__builtin_fmaf(t, 0x1.0p-24f, F.off1));
+            x[0] = __builtin_fmaf(__builtin_fmaf(rr, F.rs0, F.rn0), c0, x[0]);
+            x[1] = __builtin_fmaf(__builtin_fmaf(rr, F.rs1, F.rn1), c1, x[1]);
+        } else {
+            R U[DIM];
+            Dir<R, DIM>::template get<PH>(w, U);
+            const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, I.neg2delta);
+            step32<DIM>(I, x, r, U);
+        }
         d = dist32<KIND, DIM>(I, x, segs);
         if constexpr (CAP) s += 1;
-        const bool gt_lo = d > I.eps_lo;
-        fin = !gt_lo;
-        if (gt_lo && d <= I.eps_hi) {
+        if (d > I.eps_lo && d <= I.eps_hi) {
             // ambiguous band: decide in FP64 at the stored position
             double xd[DIM];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) xd[a] = static_cast<double>(x[a]);
-            fin = !(dist64<KIND, DIM>(I, xd, segs) > I.eps);
+            for (int a = 0; a < DIM; ++a) xd[a] = static_cast<double>(x[a]) + origin<R, KIND>(I, a);
+            if (!(dist64<KIND, DIM>(I, xd, segs) > I.eps)) d = -1.0f;
             ++n_fp64;
         }
-    }
-    if constexpr (CAP) {
-        if (!fin && s >= I.max_steps) {
-            fin = true;
-            s |= kCapBit;
+        if constexpr (CAP) {
+            if (d > I.eps_lo && s >= I.max_steps) {
+                d = -1.0f;
+                s |= kCapBit;
+            }
         }
     }
-    return fin;
 }
 
 template <typename R, int DIM, int KIND>
@@ -263,14 +280,19 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         }
         R x0[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) x0[a] = static_cast<R>(x0d[a]);
+        for (int a = 0; a < DIM; ++a) x0[a] = static_cast<R>(x0d[a] - origin<R, KIND>(I, a));
+        Fold32 F{};
+        if constexpr (sizeof(R) == 4 && DIM == 2) {
+            F = Fold32{I.fold_off[0], I.fold_off[1], I.fold_rs[0], I.fold_rs[1], I.fold_rn[0], I.fold_rn[1]};
+            asm volatile("" : "+v"(F.off0), "+v"(F.off1), "+v"(F.rs0), "+v"(F.rs1), "+v"(F.rn0), "+v"(F.rn1));
+        }
         R d0;
         if constexpr (sizeof(R) == 8) d0 = d0d; else d0 = dist32<KIND, DIM>(I, x0, segs);
 
         bool live = false;
         uint32_t koff = 0, s = 0;
         R x[DIM];
-        R d = d0;
+        R d = static_cast<R>(__builtin_inf());  // +inf while the lane has no walk
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
         uint32_t qn = 0;  // wave-uniform queue length
@@ -308,8 +330,9 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
-                bool fin = false;
-                if (live) fin = walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, x, d, s, n_fp64);
+                if (live) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
+                // lanes without a walk hold d = +inf (or the start distance), so this alone is the stop mask
+                const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
                 const uint64_t fmask = __ballot(fin);
                 if (fmask != 0ull) {
                     const uint32_t nf = __popcll(fmask);
@@ -324,6 +347,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                         q.koff[slot] = koff;
                         q.steps[slot] = (sizeof(R) == 8 || CAP) ? s : s + PH + 1;
                         live = false;
+                        d = static_cast<R>(__builtin_inf());
                     }
                     qn += nf;
                 }

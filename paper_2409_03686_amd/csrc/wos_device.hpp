@@ -39,6 +39,12 @@ struct alignas(16) DevInst {
     float eps_hi;     // FP32 distance >  eps_hi: certainly outside it
     float delta;      // bound on |dist_fp32 - dist| for this domain (absolute)
     float neg2delta;  // -2 delta (radius shrink)
+    // 2D FP32 step with S folded into the direction: for U = (cos 2 pi u, sin 2 pi u),
+    // (S U)_a = A_a cos 2 pi (u - phi_a), A_a the length of row a of S and phi_a its polar angle in
+    // revolutions, so one cosine per coordinate replaces the cosine, the sine and the 2 x 2 product.
+    float fold_off[2];  // 2^-25 - phi_a: the angle of coordinate a is (w >> 8) 2^-24 + fold_off[a]
+    float fold_rs[2];   // A_a (1 - 2^-16)
+    float fold_rn[2];   // A_a (-2 delta): step of coordinate a = (r fold_rs + fold_rn) cos(angle)
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call
@@ -184,19 +190,31 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
     }
 }
 
+// FP32 walk positions of the kinds with a centre (disk, annulus, ellipse, ball) are stored relative
+// to that centre, which saves the subtractions in every distance; the FP64 exit test and the
+// binning add it back.  FP64 positions are absolute.
+template <int KIND> constexpr bool centred32()
+{
+    return KIND == kDisk || KIND == kAnnulus || KIND == kEllipse || KIND == kBall;
+}
+template <typename R, int KIND> __device__ __forceinline__ double origin(const DevInst &I, int a)
+{
+    if constexpr (sizeof(R) == 4 && centred32<KIND>()) return I.p[a];
+    else return 0.0;
+}
+
 template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevInst &I, const float *x,
                                                                      const PolySeg *segs)
 {
     if constexpr (KIND == kDisk) {
-        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1];
-        return I.pf[2] - __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
+        return I.pf[2] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1]);
     } else if constexpr (KIND == kAnnulus) {
-        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1];
-        const float rho = __builtin_amdgcn_sqrtf(dx * dx + dy * dy);
-        return __builtin_fminf(I.pf[3] - rho, rho - I.pf[2]);
+        // min(R_out - rho, rho - R_in) = w - |rho - m|, m = (R_in + R_out) / 2 = pf[4], w = (R_out - R_in) / 2 = pf[5]
+        const float rho = __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1]);
+        return I.pf[5] - __builtin_fabsf(rho - I.pf[4]);
     } else if constexpr (KIND == kEllipse) {
         // pf[4] = 1/a, pf[5] = 1/b, pf[6] = min(a, b)
-        const float u = (x[0] - I.pf[0]) * I.pf[4], v = (x[1] - I.pf[1]) * I.pf[5];
+        const float u = x[0] * I.pf[4], v = x[1] * I.pf[5];
         return I.pf[6] * (1.0f - __builtin_amdgcn_sqrtf(u * u + v * v));
     } else if constexpr (KIND == kPolygon) {
         float best = __builtin_inff();
@@ -207,8 +225,7 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
         }
         return __builtin_amdgcn_sqrtf(best);
     } else if constexpr (KIND == kBall) {
-        const float dx = x[0] - I.pf[0], dy = x[1] - I.pf[1], dz = x[2] - I.pf[2];
-        return I.pf[3] - __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+        return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     } else {
         float best = __builtin_inff();
 #pragma unroll
