@@ -327,27 +327,36 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                 w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
             }
             wave_iters += SPB;
+            // A walk that stops leaves the live set in its phase (d = +inf marks a lane without a
+            // walk, so the single compare below is the stop mask of every phase) and joins the stop
+            // queue at the end of the block, all stops of the block in one append.
+            bool stopped = false;
+            uint32_t fph = 0;  // phase of the stop within the block
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
                 if (live) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
-                // lanes without a walk hold d = +inf (or the start distance), so this alone is the stop mask
                 const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
-                const uint64_t fmask = __ballot(fin);
+                live = live && !fin;
+                stopped = stopped || fin;
+                fph = fin ? static_cast<uint32_t>(PH) : fph;
+                d = fin ? static_cast<R>(__builtin_inf()) : d;
+            };
+            auto append = [&](auto cap_tag) {
+                constexpr bool CAP = decltype(cap_tag)::value;
+                const uint64_t fmask = __ballot(stopped);
                 if (fmask != 0ull) {
                     const uint32_t nf = __popcll(fmask);
                     if (qn + nf > static_cast<uint32_t>(kWave)) {
                         flush_queue<R, DIM, KIND>(I, q, qn, point, hist, segs, ls);
                         qn = 0;
                     }
-                    if (fin) {
+                    if (stopped) {
                         const uint32_t slot = qn + prefix_count(fmask);
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
                         q.koff[slot] = koff;
-                        q.steps[slot] = (sizeof(R) == 8 || CAP) ? s : s + PH + 1;
-                        live = false;
-                        d = static_cast<R>(__builtin_inf());
+                        q.steps[slot] = (sizeof(R) == 8 || CAP) ? s : s + fph + 1;
                     }
                     qn += nf;
                 }
@@ -359,6 +368,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                     phase(std::integral_constant<int, 2>{}, cap_tag);
                     phase(std::integral_constant<int, 3>{}, cap_tag);
                 }
+                append(cap_tag);
             };
             // FP32: the step cap is tested only in blocks where some walk can reach it (the second copy
             // of the block costs the FP64 variants more in registers than it saves)
@@ -367,7 +377,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                     block(std::true_type{});
                 } else {
                     block(std::false_type{});
-                    s += SPB;  // steps of the block (a stopped walk's count was written when it stopped)
+                    s += SPB;  // steps of the block (the stops of the block were appended with s + PH + 1)
                 }
             } else {
                 block(std::true_type{});
