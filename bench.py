@@ -83,7 +83,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--walks", type=int, default=100_000)
-    p.add_argument("--spectral-cus", type=int, default=32,
+    p.add_argument("--spectral-cus", type=int, default=8,
                    help="CUs of the spectral stream (SVD + reconstruction); the walk kernel gets the rest")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--autotune", action="store_true",

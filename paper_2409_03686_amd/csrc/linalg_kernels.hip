@@ -830,6 +830,262 @@ __global__ __launch_bounds__(1024) void lds_jacobi_kernel(double *__restrict__ X
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// One-workgroup Jacobi of the Gram path's factor (np = 64 R <= 192 columns).
+//
+// X stays in registers: 32 blocks of BW = 2 R columns, wave w (of 16) holding block w ("top") and
+// block 31 - w ("bottom"), lane l rows l + 64 i.  A sweep rotates the pairs inside each block, then
+// lets the blocks meet in round-robin order (circle method: block 0 fixed, the other 31 move one
+// position per round, so every two blocks meet once and the arrangement is back at the start after
+// 31 rounds); a meeting sweeps the BW x BW cross pairs of the wave's two blocks in BW rounds of BW
+// disjoint pairs.  Blocks move between waves through LDS (16 one-block slots).  In a round the BW
+// dot products are reduced together (split_totals leaves pair j's total in lane j), lane j computes
+// pair j's rotation from the tracked squared norms (LDS), and the rotations are applied with
+// broadcast parameters.  Norms are recomputed from the columns at the start of every sweep.  No
+// grid-wide synchronisation: the kernel runs beside other work on a few CUs.
+// ---------------------------------------------------------------------------------------------
+
+// x from lane (lane ^ M), M = 1, 2, 4, 8, 16, 32.
+template <int M> __device__ __forceinline__ double xor_lane(double x)
+{
+    if constexpr (M == 1) return dpp64<0xB1>(x);        // quad_perm (1, 0, 3, 2)
+    else if constexpr (M == 2) return dpp64<0x4E>(x);   // quad_perm (2, 3, 0, 1)
+    else if constexpr (M == 8) return dpp64<0x128>(x);  // row_ror 8 within rows of 16
+    else if constexpr (M == 32) {
+        const int lo = __shfl_xor(__double2loint(x), 32), hi = __shfl_xor(__double2hiint(x), 32);
+        return __hiloint2double(hi, lo);
+    } else {  // 4, 16: swizzle in bit-mask mode within groups of 32 lanes, lane' = lane ^ M
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x1F | (M << 10));
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x1F | (M << 10));
+        return __hiloint2double(hi, lo);
+    }
+}
+
+// Wave sums of P values (P = 2, 4, 8); lane l receives the sum of value l % P.  Stage k halves the
+// list: with b = bit k of the lane, a lane keeps the values whose index has bit k equal to b and
+// adds its partner's (lane ^ 2^k) copies of them; the one value left is summed over the other
+// lane bits.
+template <int P> __device__ __forceinline__ double split_totals(double (&v)[P], int lane)
+{
+    static_for<0, (P == 2 ? 1 : (P == 4 ? 2 : 3))>([&](auto st) {
+        constexpr int k = decltype(st)::value, M = 1 << k, N = P >> k;
+        const bool b = (lane & M) != 0;
+        static_for<0, N / 2>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const double keep = b ? v[2 * i + 1] : v[2 * i];
+            const double send = b ? v[2 * i] : v[2 * i + 1];
+            v[i] = keep + xor_lane<M>(send);
+        });
+    });
+    double t = v[0];
+    if constexpr (P <= 2) t += xor_lane<2>(t);
+    if constexpr (P <= 4) t += xor_lane<4>(t);
+    t += xor_lane<8>(t);
+    t += xor_lane<16>(t);
+    t += xor_lane<32>(t);
+    return t;
+}
+
+// Pair J of round RI: CROSS = 0, the circle ordering inside the top block (J < BW / 2) or the
+// bottom block; CROSS = 1, top column J with bottom column (J + RI) mod BW.
+template <int BW, int CROSS, int RI, int J> struct WjPair {
+    static constexpr int k = J < BW / 2 ? J : J - BW / 2;
+    static constexpr int off = J < BW / 2 ? 0 : BW;
+    static constexpr int p = CROSS ? J : PairC<BW, RI, k>::p + off;
+    static constexpr int q = CROSS ? BW + (J + RI) % BW : PairC<BW, RI, k>::q + off;
+};
+
+template <int R, int CROSS, int RI>
+__device__ __forceinline__ void wj_round(double (&x)[R][4 * R], double *nrm_w, int lane, uint32_t &nrot, double tol2)
+{
+    constexpr int BW = 2 * R, P = BW <= 2 ? 2 : (BW <= 4 ? 4 : 8);
+    double g[P];
+    static_for<0, P>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        if constexpr (j < BW) {
+            constexpr int p = WjPair<BW, CROSS, RI, j>::p, q = WjPair<BW, CROSS, RI, j>::q;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc = __builtin_fma(x[i][p], x[i][q], acc);
+            g[j] = acc;
+        } else {
+            g[j] = 0.0;
+        }
+    });
+    const double gj = split_totals<P>(g, lane);
+    double c = 1.0, sn = 0.0;
+    bool act = false;
+    // an opaque copy of the lane index: the per-round norm addresses are then formed in the round
+    // instead of being hoisted out of the sweep loop for all rounds at once (registers)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    if (ln < BW) {
+        int p, q;
+        if constexpr (CROSS) {
+            p = ln;
+            q = BW + (ln + RI) % BW;
+        } else {
+            const int k = ln < BW / 2 ? ln : ln - BW / 2, off = ln < BW / 2 ? 0 : BW;
+            pair_of(RI, k, BW, p, q);
+            p += off;
+            q += off;
+        }
+        const double a = nrm_w[p], b = nrm_w[q];
+        act = gj != 0.0 && gj * gj > tol2 * a * b;
+        if (act) {
+            double t;
+            rot_params(a, b, gj, c, sn, t);
+            nrm_w[p] = a - t * gj;
+            nrm_w[q] = b + t * gj;
+        }
+    }
+    const uint64_t rm = __ballot(act);
+    nrot += static_cast<uint32_t>(__popcll(rm));
+    static_for<0, BW>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        constexpr int p = WjPair<BW, CROSS, RI, j>::p, q = WjPair<BW, CROSS, RI, j>::q;
+        if (rm & (1ull << j)) {  // uniform
+            const double cj = readlane64(c, j), sj = readlane64(sn, j);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const double xp = x[i][p], xq = x[i][q];
+                x[i][p] = cj * xp - sj * xq;
+                x[i][q] = sj * xp + cj * xq;
+            }
+        }
+    });
+}
+
+// One move of the circle method: tops shift up one wave (wave 0 keeps its top, wave 0's bottom
+// becomes wave 1's top), bottoms shift down one wave (wave 15's top becomes its bottom).  The
+// squared norms travel with their columns.
+template <int R>
+__device__ __forceinline__ void wj_exchange(double (&x)[R][4 * R], double *stage, double (*nrm)[4 * R],
+                                            double (*nst)[2 * R], int lane, int w)
+{
+    constexpr int BW = 2 * R, NPD = 64 * R;
+    auto put = [&](int slot, auto off_tag) {
+        constexpr int off = decltype(off_tag)::value;
+        double *d = stage + static_cast<size_t>(slot) * BW * NPD;
+        static_for<0, BW>([&](auto cc) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) d[decltype(cc)::value * NPD + lane + 64 * i] = x[i][off + decltype(cc)::value];
+        });
+        if (lane < BW) nst[slot][lane] = nrm[w][off + lane];
+    };
+    auto get = [&](int slot, auto off_tag) {
+        constexpr int off = decltype(off_tag)::value;
+        const double *d = stage + static_cast<size_t>(slot) * BW * NPD;
+        static_for<0, BW>([&](auto cc) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i][off + decltype(cc)::value] = d[decltype(cc)::value * NPD + lane + 64 * i];
+        });
+        if (lane < BW) nrm[w][off + lane] = nst[slot][lane];
+    };
+    using Top = std::integral_constant<int, 0>;
+    using Bot = std::integral_constant<int, BW>;
+    __syncthreads();  // the previous move's reads are done
+    if (w >= 1) put(w, Top{});
+    else put(0, Bot{});
+    __syncthreads();
+    if (w >= 2) get(w - 1, Top{});
+    else if (w == 1) get(0, Top{});
+    __syncthreads();
+    if (w >= 1) put(w - 1, Bot{});  // slots 0..14; slot 15 still holds wave 15's old top
+    __syncthreads();
+    get(w <= 14 ? w : 15, Bot{});
+}
+
+template <int R>
+__global__ __launch_bounds__(1024) void gram_jacobi1_kernel(double *__restrict__ X, double *__restrict__ zs,
+                                                            int32_t *info)
+{
+    constexpr int NPD = 64 * R, BW = 2 * R, NC = 4 * R;
+    extern __shared__ double stage[];  // 16 slots of BW x NPD
+    __shared__ double nrm[16][NC];
+    __shared__ double nst[16][BW];
+    __shared__ uint32_t nrot_sh;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tb = w, bb = 31 - w;
+    double x[R][NC];
+    static_for<0, BW>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            x[i][c] = X[static_cast<size_t>(tb * BW + c) * NPD + lane + 64 * i];
+            x[i][BW + c] = X[static_cast<size_t>(bb * BW + c) * NPD + lane + 64 * i];
+        }
+    });
+    const double tol = static_cast<double>(NPD) * 0x1.0p-52;
+    const double tol2 = tol * tol;
+    double *nrm_w = nrm[w];
+    // squared column norms, one wave reduction at a time (keeps the register footprint small)
+    auto norms = [&](double (&n2)[NC]) {
+        static_for<0, NC>([&](auto cc) {
+            double acc[1] = {0.0};
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc[0] = __builtin_fma(x[i][decltype(cc)::value], x[i][decltype(cc)::value], acc[0]);
+            wave_totals<1>(acc);
+            n2[decltype(cc)::value] = acc[0];
+        });
+    };
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
+        {
+            double n2[NC];
+            norms(n2);
+            if (lane == 0) static_for<0, NC>([&](auto cc) { nrm_w[decltype(cc)::value] = n2[decltype(cc)::value]; });
+        }
+        if (threadIdx.x == 0) nrot_sh = 0u;
+        __syncthreads();
+        uint32_t nrot = 0;
+        static_for<0, BW - 1>([&](auto ri) { wj_round<R, 0, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2); });
+        for (int r = 0; r < 31; ++r) {
+            static_for<0, BW>([&](auto ri) { wj_round<R, 1, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2); });
+            wj_exchange<R>(x, stage, nrm, nst, lane, w);
+        }
+        if (lane == 0 && nrot) atomicAdd(&nrot_sh, nrot);
+        __syncthreads();
+        const bool done = nrot_sh == 0u;
+        __syncthreads();
+        if (done) {
+            ++sweep;
+            break;
+        }
+    }
+    // after whole sweeps every block is back in its home wave
+    double n2[NC];
+    norms(n2);
+    static_for<0, BW>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            X[static_cast<size_t>(tb * BW + c) * NPD + lane + 64 * i] = x[i][c];
+            X[static_cast<size_t>(bb * BW + c) * NPD + lane + 64 * i] = x[i][BW + c];
+        }
+        if (lane == 0) {
+            zs[tb * BW + c] = __builtin_sqrt(n2[c]);
+            zs[bb * BW + c] = __builtin_sqrt(n2[BW + c]);
+        }
+    });
+    if (threadIdx.x == 0 && info) {
+        info[0] = sweep;
+        info[1] = sweep >= kMaxSweeps ? 2 : 0;
+    }
+}
+
+template <int R> static hipError_t launch_gram_jacobi1(double *X, double *zs, int32_t *info, hipStream_t stream)
+{
+    constexpr size_t lds = static_cast<size_t>(16) * (2 * R) * (64 * R) * sizeof(double);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_jacobi1_kernel<R>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    });
+    gram_jacobi1_kernel<R><<<1, 1024, lds, stream>>>(X, zs, info);
+    return hipGetLastError();
+}
+
 // C(i, j) = scale_j sum_k opA(i, k) opB(k, j), opA(i, k) = A[i sai + k sak],
 // opB(k, j) = B[k sbk + col(j) sbj] with col(j) = bcol ? bcol[j] : j, and scale_j from z[col(j)]:
 // mode 0: 1, mode 1: 1 / z^2, mode 2: 1 / z (0 where z <= 1e-7 max z).  One 16 x 16 tile per
@@ -1113,16 +1369,11 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
         else if (v.np == 128) gram_chol_kernel<2><<<1, 1024, 0, stream>>>(v);
         else gram_chol_kernel<3><<<1, 1024, 0, stream>>>(v);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const JacobiShape gs = gram_jacobi_shape(v.np);
-        if (!gs.fn) return hipErrorInvalidValue;
-        JacobiArgs J{v.L, nullptr, v.np, v.np, v.np, static_cast<double>(v.np) * 0x1.0p-52,
-                     v.rot + kMaxSweeps, v.ctrl + kCtrlGramBarrier, v.ctrl + kCtrlGramError, v.info + 2, nullptr};
-        void *args[] = {&J};
-        // the factor's Jacobi: np / 8 block pairs (at most 24), gpb per co-resident workgroup
-        const int gpairs = v.np / (2 * gs.bw);
-        e = hipLaunchCooperativeKernel(gs.fn, dim3((gpairs + gs.gpb - 1) / gs.gpb), dim3(gs.threads), args, 0, stream);
+        // the factor's Jacobi in one workgroup (zs = the rotated columns' norms)
+        if (v.np == 64) e = launch_gram_jacobi1<1>(v.L, v.zs, v.info + 2, stream);
+        else if (v.np == 128) e = launch_gram_jacobi1<2>(v.L, v.zs, v.info + 2, stream);
+        else e = launch_gram_jacobi1<3>(v.L, v.zs, v.info + 2, stream);
         if (e != hipSuccess) return e;
-        colnorm_kernel<<<v.np, 64, 0, stream>>>(v.L, v.np, v.np, v.np, v.zs, nullptr);
         gram_vside_kernel<<<v.np, 64, 0, stream>>>(v);
         const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
         gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
