@@ -93,6 +93,7 @@ def parse():
     p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
     p.add_argument("--serve-rate", type=float, default=200.0)
+    p.add_argument("--serve-only", action="store_true", help="only the serving measurement (for profiling)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
     p.add_argument("--kernel-only", action="store_true",
                    help="for counter collection: one 1 GiB device copy (calibration), then the FP32 walk "
@@ -204,6 +205,11 @@ def main():
 
     torch.cuda.set_device(0)
     inst = wi.cfg2_annulus(n_walks=a.walks, precision=wi.FP32_GEOM_FP64_EXIT)
+    if a.serve_only:
+        ctx = wos.wos_create(0)
+        print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)}))
+        wos.wos_destroy(ctx)
+        return
     if a.kernel_only:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)

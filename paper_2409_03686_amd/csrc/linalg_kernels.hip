@@ -737,7 +737,7 @@ __global__ void gram_accept_kernel(SvdDevView v)
 // ---------------------------------------------------------------------------------------------
 // Truncated path (serving): the leading kt singular triplets with single-workgroup and plain
 // kernels only, so that requests on different streams overlap on the device.
-//   cols <= kt: the Gram path of A itself with the Jacobi of one workgroup (lds_jacobi_kernel).
+//   cols <= kt: the Gram path of A itself with the Jacobi of one workgroup (gram_jacobi1_kernel).
 //   cols >  kt: a range sketch Y = A Om (Om a +-1 matrix from Philox) and an orthonormal basis
 //               Q = Y E diag(1/lambda) from the eigenvectors E, eigenvalues lambda^2 of Y^T Y (Gram
 //               path); two subspace iterations Y = A A^T Q, each re-orthonormalised the same way
@@ -747,88 +747,6 @@ __global__ void gram_accept_kernel(SvdDevView v)
 // Components with s <= rank_cut s_1 (1e-5) are left out of the reconstruction: below that the
 // Gram path's squaring of the condition number makes them inaccurate.
 // ---------------------------------------------------------------------------------------------
-
-// One-sided Jacobi on X (NPD x NPD, column-major) in one workgroup: X in LDS, the NPD / 2 pairs
-// of each round of the circle ordering split over the 16 waves (lanes over rows, DPP totals),
-// norms tracked through the rotations and recomputed at the start of each sweep.  Writes the
-// rotated columns back and their norms to zs.
-template <int NPD>
-__global__ __launch_bounds__(1024) void lds_jacobi_kernel(double *__restrict__ X, double *__restrict__ zs,
-                                                          int32_t *info)
-{
-    extern __shared__ double xs[];  // NPD * NPD
-    __shared__ double nrm[NPD];
-    __shared__ uint32_t nrot_sh;
-    constexpr int RPL = NPD / 64;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int e = tid; e < NPD * NPD; e += 1024) xs[e] = X[e];
-    const double tol = static_cast<double>(NPD) * 0x1.0p-52;
-    const double tol2 = tol * tol;
-    __syncthreads();
-    int sweep = 0;
-    for (; sweep < kMaxSweeps; ++sweep) {
-        for (int c = w; c < NPD; c += 16) {
-            double acc[1] = {0.0};
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) acc[0] = __builtin_fma(xs[c * NPD + lane + 64 * i], xs[c * NPD + lane + 64 * i], acc[0]);
-            wave_totals<1>(acc);
-            if (lane == 0) nrm[c] = acc[0];
-        }
-        if (tid == 0) nrot_sh = 0u;
-        __syncthreads();
-        uint32_t nrot = 0;
-        for (int t = 0; t < NPD - 1; ++t) {
-            for (int pi = w; pi < NPD / 2; pi += 16) {
-                int p, q;
-                pair_of(t, pi, NPD, p, q);
-                double xp[RPL], xq[RPL], g[1] = {0.0};
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    xp[i] = xs[p * NPD + lane + 64 * i];
-                    xq[i] = xs[q * NPD + lane + 64 * i];
-                    g[0] = __builtin_fma(xp[i], xq[i], g[0]);
-                }
-                wave_totals<1>(g);
-                const double a = nrm[p], b = nrm[q], gg = g[0];
-                if (gg != 0.0 && gg * gg > tol2 * a * b) {
-                    double c, sn, tt;
-                    rot_params(a, b, gg, c, sn, tt);
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) {
-                        xs[p * NPD + lane + 64 * i] = c * xp[i] - sn * xq[i];
-                        xs[q * NPD + lane + 64 * i] = sn * xp[i] + c * xq[i];
-                    }
-                    if (lane == 0) {
-                        nrm[p] = a - tt * gg;
-                        nrm[q] = b + tt * gg;
-                    }
-                    ++nrot;
-                }
-            }
-            __syncthreads();
-        }
-        if (lane == 0 && nrot) atomicAdd(&nrot_sh, nrot);
-        __syncthreads();
-        const bool done = nrot_sh == 0u;
-        __syncthreads();
-        if (done) {
-            ++sweep;
-            break;
-        }
-    }
-    for (int e = tid; e < NPD * NPD; e += 1024) X[e] = xs[e];
-    for (int c = w; c < NPD; c += 16) {
-        double acc[1] = {0.0};
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) acc[0] = __builtin_fma(xs[c * NPD + lane + 64 * i], xs[c * NPD + lane + 64 * i], acc[0]);
-        wave_totals<1>(acc);
-        if (lane == 0) zs[c] = __builtin_sqrt(acc[0]);
-    }
-    if (tid == 0 && info) {
-        info[0] = sweep;
-        info[1] = sweep >= kMaxSweeps ? 2 : 0;
-    }
-}
 
 // ---------------------------------------------------------------------------------------------
 // One-workgroup Jacobi of the Gram path's factor (np = 64 R <= 192 columns).
@@ -1400,13 +1318,6 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
 
 hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, uint64_t seed, hipStream_t stream)
 {
-    static std::once_flag lds_once;
-    std::call_once(lds_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&lds_jacobi_kernel<64>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 64 * 8);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&lds_jacobi_kernel<128>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
-    });
     if (v.tk != 64 && v.tk != 128) return hipErrorInvalidValue;
     const size_t total = static_cast<size_t>(v.rows) * v.colsp;
     int g = static_cast<int>((total + 255) / 256);
@@ -1415,7 +1326,6 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int K = v.tk;
-    const size_t lds = static_cast<size_t>(K) * K * 8;
     auto chol = [&](double *G, double *L) {
         SvdDevView w = v;
         w.G = G;
@@ -1424,8 +1334,8 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
         else gram_chol_kernel<2><<<1, 1024, 0, stream>>>(w);
     };
     auto jac = [&](double *X, double *z) {
-        if (K == 64) lds_jacobi_kernel<64><<<1, 1024, lds, stream>>>(X, z, v.info);
-        else lds_jacobi_kernel<128><<<1, 1024, lds, stream>>>(X, z, v.info);
+        if (K == 64) (void)launch_gram_jacobi1<1>(X, z, v.info, stream);
+        else (void)launch_gram_jacobi1<2>(X, z, v.info, stream);
     };
     if (v.cols <= K) {  // the Gram path of A with the one-workgroup Jacobi
         const int nt = K / 16;
