@@ -171,9 +171,23 @@ class Engine {
         if (st != WOS_OK) return st;
         arena_.init(budget_);
         slots_.resize(max_inflight_);
-        for (auto &s : slots_) {
-            if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        // Each of the first kMaskedSlots slots gets a stream with a CU mask of its own (every CU but
+        // one, a different one per slot): HIP gives such a stream a hardware queue of its own, so a
+        // request's chain of small dependent kernels (the single-workgroup factor and Jacobi kernels
+        // above all) does not wait behind another request's kernels in a shared queue (plain streams
+        // share the process's few hardware queues).  Further slots use plain streams.
+        constexpr size_t kMaskedSlots = 16;
+        const int words = (ctx_->n_cu + 31) / 32;
+        std::vector<uint32_t> mask(words);
+        for (size_t i = 0; i < slots_.size(); ++i) {
+            Slot &s = slots_[i];
+            std::fill(mask.begin(), mask.end(), 0u);
+            for (int c = 0; c < ctx_->n_cu; ++c)
+                if (c != static_cast<int>(i % ctx_->n_cu)) mask[c / 32] |= 1u << (c % 32);
+            const hipError_t se = i < kMaskedSlots && ctx_->n_cu > 1
+                                      ? hipExtStreamCreateWithCUMask(&s.stream, static_cast<uint32_t>(words), mask.data())
+                                      : hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+            if (se != hipSuccess || hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
                 return set_error(WOS_EDEVICE, "serving slot set-up failed");
             if (!grow_pinned(s, std::max<size_t>(stage_hint, 4096))) return set_error(WOS_EDEVICE, "pinned staging allocation failed");
         }
