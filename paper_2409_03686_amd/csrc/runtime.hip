@@ -391,8 +391,12 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         I.pf[k] = static_cast<float>(g->params[k]);
     }
     if (g->kind == WOS_ANNULUS) {
-        I.pf[4] = static_cast<float>(0.5 * (g->params[2] + g->params[3]));
-        I.pf[5] = static_cast<float>(0.5 * (g->params[3] - g->params[2]));
+        const double m = 0.5 * (g->params[2] + g->params[3]), w = 0.5 * (g->params[3] - g->params[2]);
+        I.pf[4] = static_cast<float>(m);
+        I.pf[5] = static_cast<float>(w);
+        // FP32 circle decision of the binning: inner below (m - w/4)^2, outer above (m + w/4)^2
+        I.pf[6] = static_cast<float>((m - 0.25 * w) * (m - 0.25 * w));
+        I.pf[7] = static_cast<float>((m + 0.25 * w) * (m + 0.25 * w));
     }
     if (g->kind == WOS_ELLIPSE) {
         I.pf[4] = static_cast<float>(1.0 / g->params[2]);

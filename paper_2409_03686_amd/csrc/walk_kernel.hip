@@ -147,10 +147,18 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
 {
     const uint32_t lane = __lane_id();
     if (lane < n) {
+        R xs[DIM];
         double x[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) x[a] = static_cast<double>(q.pos[a * kWave + lane]) + origin<R, KIND>(I, a);
-        const int j = element64<KIND, DIM>(I, x, segs);
+        for (int a = 0; a < DIM; ++a) {
+            xs[a] = q.pos[a * kWave + lane];
+            x[a] = static_cast<double>(xs[a]) + origin<R, KIND>(I, a);
+        }
+        // FP32 positions on circles: the cell in FP32 where that is certain, else in FP64
+        int j = -1;
+        if constexpr (sizeof(R) == 4 && DIM == 2 && (KIND == kDisk || KIND == kAnnulus))
+            j = element32_certified<KIND>(I, xs[0], xs[1]);
+        if (j < 0) j = element64<KIND, DIM>(I, x, segs);
         atomicAdd(&hist[j], 1u);
         const uint32_t sw = q.steps[lane];
         const uint32_t st = sw & ~kCapBit;
@@ -158,7 +166,10 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
         ls.steps += st;
         ls.max_s = max(ls.max_s, st);
         ls.cap += sw >> 31;
-        if (dist64<KIND, DIM>(I, x, segs) < 0.0) ls.esc += 1;
+        // escape (stop outside D): certain "no" when the FP32 distance exceeds its error bound
+        bool maybe_out = true;
+        if constexpr (sizeof(R) == 4 && KIND != kPolygon) maybe_out = !(dist32<KIND, DIM>(I, xs, segs) > I.delta);
+        if (maybe_out && dist64<KIND, DIM>(I, x, segs) < 0.0) ls.esc += 1;
         if (I.trace) {
             const size_t t = (static_cast<size_t>(point) * I.n_walks + q.koff[lane]) * 2;
             I.trace[t] = j;

@@ -290,6 +290,53 @@ __device__ __forceinline__ int arc_of(double theta, int n)
     return clamp_index(theta * static_cast<double>(n) / kTwoPi, n);
 }
 
+// Cell index of an FP32 stop position (relative to the centre) on the circles of a disk or an
+// annulus, computed in FP32 and returned only where it certainly equals element64's result, else
+// -1.  The angle in revolutions, atan2(y, x) / 2 pi, comes from an odd polynomial in
+// a = min(|x|, |y|) / max(|x|, |y|) (least-squares fit of atan(a) / 2 pi on [0, 1], evaluated error
+// below 2^-24 rev) and three reflections; with the division and the reflections its error stays
+// below 2^-21 rev, and t = rev n below n (2^-21 + 2^-24) from the exact value.  The arc floor(t) is
+// accepted when t lies farther than n 2^-20 from an integer.  The annulus circle is decided by
+// rho^2 against (m -+ w/4)^2 (pf[6], pf[7]; m, w the middle radius and half width); stops lie
+// within eps of a circle, w from the middle.
+template <int KIND> __device__ __forceinline__ int element32_certified(const DevInst &I, float x, float y)
+{
+    const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+    const float a = __builtin_fminf(ax, ay) * __builtin_amdgcn_rcpf(__builtin_fmaxf(ax, ay));
+    const float z = a * a;
+    float p = 0.0010841292096301913f;
+    p = __builtin_fmaf(p, z, -0.005348275415599346f);
+    p = __builtin_fmaf(p, z, 0.012672500684857368f);
+    p = __builtin_fmaf(p, z, -0.021061519160866737f);
+    p = __builtin_fmaf(p, z, 0.03152512013912201f);
+    p = __builtin_fmaf(p, z, -0.053026240319013596f);
+    p = __builtin_fmaf(p, z, 0.15915432572364807f);
+    float r = p * a;                 // atan(a) / 2 pi, in [0, 1/8]
+    if (ay > ax) r = 0.25f - r;      // angle of (max, min) reflected about the diagonal
+    if (x < 0.0f) r = 0.5f - r;
+    if (y < 0.0f) r = -r;            // (-1/2, 1/2]
+    if (r < 0.0f) r += 1.0f;         // [0, 1]
+    int n = I.layout[0], off = 0;
+    if constexpr (KIND == kAnnulus) {
+        const float rho2 = __builtin_fmaf(x, x, y * y);
+        if (rho2 >= I.pf[7]) {
+            n = I.layout[0];
+        } else if (rho2 <= I.pf[6]) {
+            n = I.layout[1];
+            off = I.layout[0];
+        } else {
+            return -1;
+        }
+    }
+    const float nf = static_cast<float>(n);
+    const float t = r * nf;
+    const float fl = __builtin_floorf(t);
+    const float fr = t - fl;
+    const float m = nf * 0x1.0p-20f;
+    if (!(fr > m && fr < 1.0f - m)) return -1;
+    return off + static_cast<int>(fl);
+}
+
 template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevInst &I, const double *x,
                                                                       const PolySeg *segs)
 {
