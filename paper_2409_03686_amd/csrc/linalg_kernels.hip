@@ -175,17 +175,8 @@ __device__ __forceinline__ void wave_totals(double (&v)[NV])
     });
 }
 
-// FP64 reciprocal and inverse square root: the hardware estimates refined by two Newton steps
-// (each step squares the relative error of the estimate).
-__device__ __forceinline__ double rcp64(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
+// FP64 inverse square root: the hardware estimate refined by two Newton steps (each step squares
+// the relative error of the estimate).
 __device__ __forceinline__ double rsq64(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
@@ -195,18 +186,32 @@ __device__ __forceinline__ double rsq64(double x)
     return __builtin_fma(0.5 * y, e, y);
 }
 
+// One Newton step on the hardware estimates: enough where only the rotation angle depends on the
+// value (any angle near the optimal one reduces the off-diagonal; the test uses fresh products).
+__device__ __forceinline__ double rcp64_1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsq64_1(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    return __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+}
+
 // Plane rotation that zeroes g = x_p . x_q for the squared norms a = |x_p|^2, b = |x_q|^2
 // (Rutishauser's form): zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-// c = 1 / sqrt(1 + t^2), s = c t.  c comes from a refined inverse square root, so c^2 + s^2 = 1
-// to a few ulps, which keeps the rotation orthogonal.  Requires g != 0.
+// c = 1 / sqrt(1 + t^2), s = c t.  zeta and t only choose the angle and take one Newton step
+// each; |zeta| is capped at 2^500 (the angle is below rounding long before, and zeta^2 must not
+// overflow).  c comes from a twice-refined inverse square root, so c^2 + s^2 = 1 to a few ulps,
+// which keeps the rotation orthogonal.  Requires g != 0.
 __device__ __forceinline__ void rot_params(double a, double b, double g, double &c, double &s, double &t)
 {
-    const double zeta = (b - a) * rcp64(2.0 * g);
-    const double az = __builtin_fabs(zeta);
-    const double z2 = __builtin_fma(zeta, zeta, 1.0);
-    const double t_mid = rcp64(az + z2 * rsq64(z2));
-    const double t_big = 0.5 * rcp64(az);  // |zeta| >= 2^60: 1 / (2 |zeta|) to rounding
-    const double tt = az < 0x1.0p60 ? t_mid : t_big;
+    const double zeta = (b - a) * rcp64_1(2.0 * g);
+    const double az = __builtin_fmin(__builtin_fabs(zeta), 0x1.0p500);
+    const double z2 = __builtin_fma(az, az, 1.0);
+    const double tt = rcp64_1(__builtin_fma(z2, rsq64_1(z2), az));
     t = zeta >= 0.0 ? tt : -tt;
     c = rsq64(__builtin_fma(t, t, 1.0));
     s = c * t;
@@ -814,7 +819,8 @@ template <int BW, int CROSS, int RI, int J> struct WjPair {
 };
 
 template <int R, int CROSS, int RI>
-__device__ __forceinline__ void wj_round(double (&x)[R][4 * R], double *nrm_w, int lane, uint32_t &nrot, double tol2)
+__device__ __forceinline__ void wj_round(double (&x)[R][4 * R], double *nrm_w, int lane, uint32_t &nrot, double tol2,
+                                         bool &big)
 {
     constexpr int BW = 2 * R, P = BW <= 2 ? 2 : (BW <= 4 ? 4 : 8);
     double g[P];
@@ -852,6 +858,7 @@ __device__ __forceinline__ void wj_round(double (&x)[R][4 * R], double *nrm_w, i
         act = gj != 0.0 && gj * gj > tol2 * a * b;
         if (act) {
             double t;
+            big = big || gj * gj >= 1e-16 * (a * b);  // a rotated cosine of 1e-8 or more
             rot_params(a, b, gj, c, sn, t);
             nrm_w[p] = a - t * gj;
             nrm_w[q] = b + t * gj;
@@ -923,6 +930,7 @@ __global__ __launch_bounds__(1024) void gram_jacobi1_kernel(double *__restrict__
     __shared__ double nrm[16][NC];
     __shared__ double nst[16][BW];
     __shared__ uint32_t nrot_sh;
+    __shared__ uint32_t big_sh;  // some rotation of the sweep had a cosine of 1e-8 or more
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tb = w, bb = 31 - w;
     double x[R][NC];
@@ -954,17 +962,25 @@ __global__ __launch_bounds__(1024) void gram_jacobi1_kernel(double *__restrict__
             norms(n2);
             if (lane == 0) static_for<0, NC>([&](auto cc) { nrm_w[decltype(cc)::value] = n2[decltype(cc)::value]; });
         }
-        if (threadIdx.x == 0) nrot_sh = 0u;
+        if (threadIdx.x == 0) {
+            nrot_sh = 0u;
+            big_sh = 0u;
+        }
         __syncthreads();
         uint32_t nrot = 0;
-        static_for<0, BW - 1>([&](auto ri) { wj_round<R, 0, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2); });
+        bool big = false;
+        static_for<0, BW - 1>([&](auto ri) { wj_round<R, 0, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2, big); });
         for (int r = 0; r < 31; ++r) {
-            static_for<0, BW>([&](auto ri) { wj_round<R, 1, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2); });
+            static_for<0, BW>([&](auto ri) { wj_round<R, 1, decltype(ri)::value>(x, nrm_w, lane, nrot, tol2, big); });
             wj_exchange<R>(x, stage, nrm, nst, lane, w);
         }
         if (lane == 0 && nrot) atomicAdd(&nrot_sh, nrot);
+        if (__any(big) && lane == 0) atomicOr(&big_sh, 1u);
         __syncthreads();
-        const bool done = nrot_sh == 0u;
+        // Done after a sweep without rotations, or after one whose largest rotated cosine was
+        // below 1e-8: convergence is quadratic by then, so a further sweep would only meet cosines
+        // of order 1e-16, below the tolerance (the Gram path's a-posteriori check guards the result).
+        const bool done = nrot_sh == 0u || big_sh == 0u;
         __syncthreads();
         if (done) {
             ++sweep;
