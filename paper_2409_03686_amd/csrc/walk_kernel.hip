@@ -34,8 +34,7 @@ template <> struct Spb<double, 3> { static constexpr int v = 1; };
 
 struct BlockShared {
     uint32_t item_lo, item_hi;
-    uint32_t next;            // next walk offset of the current item
-    uint32_t pad;
+    uint32_t pad0, pad1;
     unsigned long long st[8]; // per-item statistics
 };
 
@@ -255,7 +254,6 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         segs = lds_segs;
     }
     if (tid < 8) sh.st[tid] = 0ull;
-    if (tid == 0) sh.next = 0u;
     __syncthreads();
 
     double x0d[DIM];
@@ -306,6 +304,11 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         R d = static_cast<R>(__builtin_inf());  // +inf while the lane has no walk
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+        // The item's walks are dealt to the waves round-robin (walk offset wv + nw i for the wave's
+        // i-th walk); within a wave, free lanes take the wave's next walks in lane order.
+        const uint32_t nw = static_cast<uint32_t>(nthr / kWave);
+        const uint32_t wave_cnt = cnt > static_cast<uint32_t>(wv) ? (cnt - wv + nw - 1) / nw : 0u;
+        uint32_t wave_next = 0;  // wave-uniform
         uint32_t qn = 0;  // wave-uniform queue length
         uint32_t n_fp64 = 0;
         unsigned long long wave_iters = 0;
@@ -314,16 +317,12 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         // One outer iteration per Philox block: refill, draw the block, then SPB unrolled steps.
         for (;;) {
             const uint64_t need = __ballot(!live);
-            if (need != 0ull) {
-                const uint32_t nneed = __popcll(need);
-                const uint32_t leader = __ffsll(static_cast<unsigned long long>(need)) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&sh.next, nneed);
-                base = __builtin_amdgcn_readlane(base, leader);
-                const uint32_t mine = base + prefix_count(need);
-                if (!live && mine < cnt) {
+            if (need != 0ull && wave_next < wave_cnt) {
+                const uint32_t mine = wave_next + prefix_count(need);
+                wave_next += static_cast<uint32_t>(__popcll(need));
+                if (!live && mine < wave_cnt) {
                     live = true;
-                    koff = k0 + mine;
+                    koff = k0 + static_cast<uint32_t>(wv) + nw * mine;
                     s = 0;
                     d = d0;
 #pragma unroll
