@@ -435,16 +435,6 @@ static JacobiShape jacobi_shape(int rows, int colsp)
 }
 #undef WOS_BJ
 
-// The Gram path's Jacobi runs on the np x np factor, one wave per block pair, four block pairs per
-// workgroup, without W.
-static JacobiShape gram_jacobi_shape(int np)
-{
-    if (np == 64) return {reinterpret_cast<const void *>(&jacobi_kernel<1, 0, 64, 4, 4>), 256, 4, 4};
-    if (np == 128) return {reinterpret_cast<const void *>(&jacobi_kernel<2, 0, 64, 4, 4>), 256, 4, 4};
-    if (np == 192) return {reinterpret_cast<const void *>(&jacobi_kernel<3, 0, 64, 4, 4>), 256, 4, 4};
-    return {nullptr, 0, 4, 1};
-}
-
 // Column norms out[c] = |X[:, c]| for c < ncols (one block per column).
 __global__ void colnorm_kernel(const double *__restrict__ X, int rows, int ld, int ncols, double *__restrict__ out,
                                const uint32_t *skip)

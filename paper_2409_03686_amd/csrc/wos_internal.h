@@ -19,9 +19,7 @@ constexpr int kGramMaxCols = 192;
 enum SvdCtrl : int {
     kCtrlBarrier = 0,    // grid barrier counter, Hestenes path
     kCtrlError = 1,      // barrier time-out, Hestenes path
-    kCtrlGramBarrier = 2,
-    kCtrlGramError = 3,
-    kCtrlGramOk = 4,     // 1: the Gram path's result was accepted, the Hestenes path is skipped
+    kCtrlGramOk = 2,     // 1: the Gram path's result was accepted, the Hestenes path is skipped
     kCtrlWords = 8
 };
 // info words: [0] sweeps, [1] error flags of the result returned; [2], [3] the same for the
