@@ -298,10 +298,12 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         R d0;
         if constexpr (sizeof(R) == 8) d0 = d0d; else d0 = dist32<KIND, DIM>(I, x0, segs);
 
-        bool live = false;
+        // A lane holds a walk while d is finite: d = +inf marks a free lane (a lane flag kept in
+        // memory form would cost a compare and a select per phase).
+        constexpr R kFree = static_cast<R>(__builtin_inf());
         uint32_t koff = 0, s = 0;
         R x[DIM];
-        R d = static_cast<R>(__builtin_inf());  // +inf while the lane has no walk
+        R d = kFree;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
         // The item's walks are dealt to the waves round-robin (walk offset wv + nw i for the wave's
@@ -316,12 +318,11 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
 
         // One outer iteration per Philox block: refill, draw the block, then SPB unrolled steps.
         for (;;) {
-            const uint64_t need = __ballot(!live);
+            const uint64_t need = __ballot(d == kFree);
             if (need != 0ull && wave_next < wave_cnt) {
                 const uint32_t mine = wave_next + prefix_count(need);
                 wave_next += static_cast<uint32_t>(__popcll(need));
-                if (!live && mine < wave_cnt) {
-                    live = true;
+                if (d == kFree && mine < wave_cnt) {
                     koff = k0 + static_cast<uint32_t>(wv) + nw * mine;
                     s = 0;
                     d = d0;
@@ -329,7 +330,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                     for (int a = 0; a < DIM; ++a) x[a] = x0[a];
                 }
             }
-            if (!__any(live)) break;
+            if (!__any(d != kFree)) break;
             uint32_t w[4];
             {
                 uint32_t c0 = s / SPB, c1 = I.walk_begin + koff, c2 = point, c3 = I.inst;
@@ -337,23 +338,22 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                 w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
             }
             wave_iters += SPB;
-            // A walk that stops leaves the live set in its phase (d = +inf marks a lane without a
-            // walk, so the single compare below is the stop mask of every phase) and joins the stop
-            // queue at the end of the block, all stops of the block in one append.
-            bool stopped = false;
-            uint32_t fph = 0;  // phase of the stop within the block
+            // A walk that stops frees its lane in its phase (d = +inf, so the single compare below is
+            // the stop mask of every phase) and joins the stop queue at the end of the block, all
+            // stops of the block in one append.
+            constexpr uint32_t kNoStop = 0xFFu;
+            uint32_t fph = kNoStop;  // phase of the stop within the block
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
-                if (live) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
+                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
                 const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
-                live = live && !fin;
-                stopped = stopped || fin;
                 fph = fin ? static_cast<uint32_t>(PH) : fph;
-                d = fin ? static_cast<R>(__builtin_inf()) : d;
+                d = fin ? kFree : d;
             };
             auto append = [&](auto cap_tag) {
                 constexpr bool CAP = decltype(cap_tag)::value;
+                const bool stopped = fph != kNoStop;
                 const uint64_t fmask = __ballot(stopped);
                 if (fmask != 0ull) {
                     const uint32_t nf = __popcll(fmask);
@@ -383,7 +383,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             // FP32: the step cap is tested only in blocks where some walk can reach it (the second copy
             // of the block costs the FP64 variants more in registers than it saves)
             if constexpr (sizeof(R) == 4) {
-                if (__any(live && s + SPB >= I.max_steps)) {
+                if (__any(d != kFree && s + SPB >= I.max_steps)) {
                     block(std::true_type{});
                 } else {
                     block(std::false_type{});
