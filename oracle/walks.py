@@ -57,10 +57,11 @@ def make_geom(g):
     for k, v in enumerate(g.layout):
         s.layout[k] = int(v)
     if g.verts is not None:
+        import wos_inputs as wi
         v = np.ascontiguousarray(np.asarray(g.verts, np.float64).ravel())
         s._verts = v
         s.verts = _ptr(v, C.c_double)
-        s.n_verts = len(v) // 2
+        s.n_verts = len(v) // 3 if g.kind == wi.PERFORATED else len(v) // 2
     return s
 
 
@@ -104,6 +105,11 @@ def element_measures(g) -> np.ndarray:
     if g.kind == wi.BALL:
         nz, nphi = g.layout
         return np.full(M, 4 * np.pi * g.params[3] ** 2 / (nz * nphi))
+    if g.kind == wi.PERFORATED:
+        mo, mh, k = g.layout[:3]
+        holes = np.asarray(g.verts, float).reshape(k, 3)
+        return np.concatenate([np.full(mo, 2 * np.pi * g.params[2] / mo)] +
+                              [np.full(mh, 2 * np.pi * r / mh) for r in holes[:, 2]])
     if g.kind == wi.BOX:
         d, n = g.dim, g.layout[0]
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])

@@ -39,6 +39,7 @@
 #define OG_POLYGON 3
 #define OG_BALL 4
 #define OG_BOX 5
+#define OG_PERFORATED 6
 
 #define OG_TWO_PI 6.283185307179586
 
@@ -47,8 +48,9 @@ typedef struct {
     int32_t kind;
     double p[8];          /* shape parameters, see the geometry table in the docs */
     int32_t layout[4];    /* element layout */
-    const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise */
-    int32_t n_verts;
+    const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise; for the perforated
+                             disk the holes as (cx, cy, r) triples */
+    int32_t n_verts;      /* polygon vertices, or holes of the perforated disk */
 } og_geom;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -181,6 +183,19 @@ double oracle_dist(const og_geom *g, const double *x)
         }
         return best;
     }
+    case OG_PERFORATED: {
+        /* outer circle |x - c0| = R0 and hole circles |x - c_l| = r_l (the paper's Example with a
+         * disc perforated by smaller discs): the nearest of the circles */
+        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
+        double best = g->p[2] - sqrt(dx * dx + dy * dy);
+        for (int l = 0; l < g->n_verts; ++l) {
+            const double *h = g->verts + 3 * l;
+            double hx = x[0] - h[0], hy = x[1] - h[1];
+            double d = sqrt(hx * hx + hy * hy) - h[2];
+            if (d < best) best = d;
+        }
+        return best;
+    }
     }
     return -INFINITY;
 }
@@ -265,6 +280,21 @@ int oracle_element(const og_geom *g, const double *x)
         }
         int per_face = (d == 2) ? n : n * n;
         return fb * per_face + idx;
+    }
+    case OG_PERFORATED: {
+        /* the nearest circle (ties: the outer one, then the lowest hole), then the arc of the angle
+         * about its centre; outer arcs come first, then layout[1] arcs per hole in hole order */
+        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
+        double best = g->p[2] - sqrt(dx * dx + dy * dy), ax = dx, ay = dy;
+        int comp = -1;
+        for (int l = 0; l < g->n_verts; ++l) {
+            const double *h = g->verts + 3 * l;
+            double hx = x[0] - h[0], hy = x[1] - h[1];
+            double d = sqrt(hx * hx + hy * hy) - h[2];
+            if (d < best) { best = d; comp = l; ax = hx; ay = hy; }
+        }
+        if (comp < 0) return arc_index(atan2(ay, ax), g->layout[0]);
+        return g->layout[0] + comp * g->layout[1] + arc_index(atan2(ay, ax), g->layout[1]);
     }
     }
     return -1;

@@ -82,6 +82,14 @@ def _boundary_samples(g, n):
         pi_ = np.stack([np.cos(t), np.sin(t)], 1) * g.params[2]
         return (np.concatenate([po, pi_]),
                 np.concatenate([(t * mo / (2 * np.pi)).astype(int), mo + (t * mi / (2 * np.pi)).astype(int)]))
+    if g.kind == wi.PERFORATED:
+        mo, mh, k = g.layout[:3]
+        t = (np.arange(n) + 0.5) * 2 * np.pi / n
+        circles = [(g.params[0], g.params[1], g.params[2], mo, 0)]
+        circles += [(hx, hy, r, mh, mo + l * mh) for l, (hx, hy, r) in enumerate(np.asarray(g.verts).reshape(k, 3))]
+        pts = [np.stack([cx + r * np.cos(t), cy + r * np.sin(t)], 1) for cx, cy, r, _, _ in circles]
+        el = [off + (t * m / (2 * np.pi)).astype(int) for _, _, _, m, off in circles]
+        return np.concatenate(pts), np.concatenate(el)
     if g.kind == wi.POLYGON:
         v = np.asarray(g.verts)
         seg = np.roll(v, -1, 0) - v
@@ -122,10 +130,13 @@ def _boundary_samples(g, n):
     raise ValueError(g.kind)
 
 
-@pytest.mark.parametrize("case", ["disk", "annulus", "lshape", "square", "cube", "ball"])
+@pytest.mark.parametrize("case", ["disk", "annulus", "lshape", "square", "cube", "ball", "perforated"])
 def test_distance_and_element_vs_brute_force(case):
     rng = np.random.default_rng(1)
-    if case == "disk":
+    if case == "perforated":
+        holes = np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])
+        g = wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (41, 17, 3), verts=holes)
+    elif case == "disk":
         g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (37,))
     elif case == "annulus":
         g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.3, 1.0), (29, 13))
@@ -138,7 +149,9 @@ def test_distance_and_element_vs_brute_force(case):
     else:
         g = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (6, 11))
     bp, be = _boundary_samples(g, 400_000 if g.dim == 2 else 360_000)
-    pts = wi.sample_points(g, 300, rng)
+    if case == "perforated":  # the same angular density on every circle: coarser on the smaller ones
+        bp, be = _boundary_samples(g, 1_600_000)
+    pts = wi.sample_points(g, 100 if case == "perforated" else 300, rng)
     d, e = walks.geom_eval(g, pts)
     spacing = 2e-5 if g.dim == 2 else 6e-3
     for k in range(len(pts)):
@@ -405,3 +418,45 @@ def test_empty_inputs():
     assert c.shape == (0, 8) and st["walks"] == 0
     c, st, _ = walks.build_measure(g, np.eye(2), np.zeros((3, 2)), 1e-4, walk_begin=5, walk_end=5)
     assert c.sum() == 0 and st["walks"] == 0
+
+
+# ---------------------------------------------------------------- perforated disc (multiply connected)
+
+def test_perforated_with_one_concentric_hole_is_the_annulus_walk_for_walk():
+    """One hole at the centre of the outer disc is an annulus: the same distances, the same nearest
+    circle (ties to the outer one), the same arcs in the same order, hence identical counts."""
+    gp = wi.Geometry(2, wi.PERFORATED, (0.1, -0.2, 1.0), (23, 11, 1), verts=np.array([[0.1, -0.2, 0.35]]))
+    ga = wi.Geometry(2, wi.ANNULUS, (0.1, -0.2, 0.35, 1.0), (23, 11))
+    x = wi.sample_points(ga, 9, np.random.default_rng(31))
+    K = np.array([[1.0, 0.3], [0.3, 0.5]])
+    cp, sp, tp = walks.build_measure(gp, K, x, 1e-4, seed=77, walk_end=600, trace=True)
+    ca, sa, ta = walks.build_measure(ga, K, x, 1e-4, seed=77, walk_end=600, trace=True)
+    assert np.array_equal(tp, ta) and np.array_equal(cp, ca) and sp == sa
+    assert np.allclose(walks.element_measures(gp), walks.element_measures(ga), rtol=1e-15, atol=0)
+
+
+def test_perforated_disc_matches_the_papers_average_measure():
+    """The paper's Example with a disc perforated by five smaller discs (K = I): the harmonic measure
+    of the holes averaged over the points of the circle at distance 0.05 from the outer one is about
+    0.1126 (the paper's value; its Monte Carlo error is not stated, so the bound is loose).  100
+    points x 20 000 walks: standard error 2e-4; eps = 1e-4 instead of the paper's 1e-10."""
+    inst = wi.perforated_disk_example(n_walks=20_000)
+    c, st, _ = walks.build_instance(inst)
+    assert st["escapes"] == 0 and st["cap_hits"] == 0
+    g1 = inst.geom.gamma1_mask.astype(bool)
+    avg = c[:, g1].sum(1).mean() / inst.n_walks
+    assert abs(avg - 0.1126) < 0.002, avg
+    # symmetric under rotation by 2 pi / 5: the five holes take equal shares
+    share = c[:, g1].reshape(100, 5, -1).sum((0, 2)) / c[:, g1].sum()
+    assert np.all(np.abs(share - 0.2) < 0.01), share
+
+
+def test_perforated_disc_reproduces_paper_solution():
+    """2D-sol3 (harmonic) from the stop points: E u(X_N) = u(x) within the Monte Carlo error and the
+    O(eps) bias."""
+    inst = wi.perforated_disk_example()
+    g = inst.geom
+    x = wi.sample_points(g, 6, np.random.default_rng(12), margin=0.02)
+    _, _, S = walks.instance_setup(np.eye(2), 2)
+    sol3 = lambda p: p[:, 0] ** 2 - p[:, 1] ** 2
+    assert np.all(_exit_mean_z(g, S, x, sol3, 30_000, grad_bound=2.0) < 4.5)

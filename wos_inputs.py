@@ -14,6 +14,9 @@ Geometry kinds (codes shared by the C ABI and the oracle):
   POLYGON  verts  (n, 2), one counter-clockwise loop  layout (M,)         equal pieces of perimeter
   BALL     params (cx, cy, cz, R)                  layout (n_z, n_phi)    equal-area (z, phi) cells
   BOX      params (lo_0..lo_{d-1}, hi_0..hi_{d-1}) layout (n,)            n^(d-1) patches per face
+  PERFORATED params (cx, cy, R) of the outer disc, verts (k, 3) rows (cx, cy, r) of the holes
+           layout (M_out, M_hole, k)   outer arcs first, then M_hole arcs per hole in hole order, all
+           counter-clockwise from angle 0 about their own centre
 
 The paper's problem statement (Section 1.1, the discrete inverse problem with interior data) fixes
 what an instance holds: the domain D, its boundary split into an accessible part Gamma_0 and an
@@ -27,9 +30,9 @@ from typing import Optional
 
 import numpy as np
 
-DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX = 0, 1, 2, 3, 4, 5
+DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX, PERFORATED = 0, 1, 2, 3, 4, 5, 6
 KIND_NAMES = {DISK: "disk", ANNULUS: "annulus", ELLIPSE: "ellipse", POLYGON: "polygon",
-              BALL: "ball", BOX: "box"}
+              BALL: "ball", BOX: "box", PERFORATED: "perforated"}
 
 FP64 = 0
 FP32_GEOM_FP64_EXIT = 1
@@ -81,6 +84,8 @@ def element_count(dim: int, kind: int, layout) -> int:
         return layout[0] * layout[1]
     if kind == BOX:
         return 2 * dim * layout[0] ** (dim - 1)
+    if kind == PERFORATED:
+        return layout[0] + layout[1] * layout[2]
     raise ValueError(f"unknown geometry kind {kind}")
 
 
@@ -106,6 +111,14 @@ def element_ref_points(g: Geometry) -> np.ndarray:
         cx, cy, a, b = g.params
         t = (np.arange(M) + 0.5) * 2 * np.pi / M
         return np.stack([cx + a * np.cos(t), cy + b * np.sin(t)], 1)
+    if g.kind == PERFORATED:
+        cx, cy, R = g.params[:3]
+        mo, mh, k = g.layout[:3]
+        pts = []
+        for (hx, hy, r), m in [((cx, cy, R), mo)] + [(tuple(h), mh) for h in np.asarray(g.verts, float).reshape(k, 3)]:
+            t = (np.arange(m) + 0.5) * 2 * np.pi / m
+            pts.append(np.stack([hx + r * np.cos(t), hy + r * np.sin(t)], 1))
+        return np.concatenate(pts, 0)
     if g.kind == POLYGON:
         v = np.asarray(g.verts, float)
         seg = np.roll(v, -1, 0) - v
@@ -214,6 +227,29 @@ def cfg1_disk(n_walks: int = 10_000) -> Instance:
                     name="disk64_K=I_64pts")
 
 
+def perforated_disk_example(n_walks: int = 10_000, n_obs: int = 100, eps: float = 1e-4,
+                            precision: int = FP64, m_out: int = 500, m_hole: int = 100) -> Instance:
+    """The paper's Example of a disc perforated by five smaller discs (Section 5.2, Example 4):
+    D_0 the unit disc, holes of radius 0.2 centred at 0.5 (cos t_l, sin t_l), t_l = 2 (l - 1) pi / 5;
+    Gamma_0 the outer circle (m_out arcs), Gamma_1 the five hole circles (m_hole arcs each); K = I;
+    the interior points equally spaced on the circle at distance 0.05 from Gamma_0 (radius 0.95).
+    Data: 2D-sol3, u = x_1^2 - x_2^2, without noise.  (The paper uses N = 10^6 and eps = 10^-10.)"""
+    t = 2 * np.pi * np.arange(5) / 5
+    holes = np.stack([0.5 * np.cos(t), 0.5 * np.sin(t), np.full(5, 0.2)], 1)
+    g = Geometry(2, PERFORATED, (0.0, 0.0, 1.0), (m_out, m_hole, 5), verts=holes)
+    g.gamma1_mask = (np.arange(g.n_elem) >= m_out).astype(np.uint8)
+    s = 2 * np.pi * np.arange(n_obs) / n_obs
+    x = 0.95 * np.stack([np.cos(s), np.sin(s)], 1)
+    inst = Instance(g, np.eye(2), x, n_walks, eps=eps, seed=4, precision=precision,
+                    name="perforated_disc_5holes")
+    u = lambda p: p[:, 0] ** 2 - p[:, 1] ** 2
+    ref = element_ref_points(g)
+    inst.uD = u(x)
+    inst.u0 = u(ref[g.gamma1_mask == 0])
+    inst.u_exact_g1 = u(ref[g.gamma1_mask == 1])
+    return inst
+
+
 def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP32_GEOM_FP64_EXIT,
                  eta: float = 0.01) -> Instance:
     """2D annulus r in [0.3, 1], K = [[1, .5], [.5, 2]], 128 + 128 arcs, 1024 points uniform by area.
@@ -299,12 +335,18 @@ def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
         d = g.dim
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])
         return np.all((p > lo) & (p < hi), 1)
+    if g.kind == PERFORATED:
+        cx, cy, R = g.params[:3]
+        ok = (p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 < R * R
+        for hx, hy, r in np.asarray(g.verts, float).reshape(-1, 3):
+            ok &= (p[:, 0] - hx) ** 2 + (p[:, 1] - hy) ** 2 > r * r
+        return ok
     raise ValueError(g.kind)
 
 
 def _bbox(g: Geometry):
-    if g.kind == DISK:
-        cx, cy, R = g.params
+    if g.kind in (DISK, PERFORATED):
+        cx, cy, R = g.params[:3]
         return np.array([cx - R, cy - R]), np.array([cx + R, cy + R])
     if g.kind == ANNULUS:
         cx, cy, _, R = g.params
