@@ -89,10 +89,17 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *   WOS_BOX      dim 2 or 3, params (lo_0..lo_{d-1}, hi_0..hi_{d-1}), layout (n): faces in the
  *                order (x=lo, x=hi, y=lo, y=hi[, z=lo, z=hi]), n^(d-1) patches each, patch
  *                indices along the remaining axes in increasing axis order; j = f n^(d-1) + idx.
+ *   WOS_PERFORATED dim 2, params (cx, cy, R) of the outer disc, verts = k holes as (cx, cy, r)
+ *                triples (host, n_verts = k), layout (M_out, M_hole, k): the multiply connected disc
+ *                of the paper's Example 4.  Cells: M_out arcs of the outer circle, then M_hole arcs
+ *                of each hole in hole order, all counter-clockwise from angle 0 about their own
+ *                centre; a point goes to the nearest circle (ties: the outer one, then the lowest
+ *                hole).  Holes must lie inside the outer disc and must not overlap.
  * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
  * weights of the paper's appendix, Ex. A.3); ties go to the lowest face/segment index. */
 typedef enum {
-    WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5
+    WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5,
+    WOS_PERFORATED = 6
 } wos_geom_kind;
 
 typedef struct {
@@ -100,11 +107,12 @@ typedef struct {
     int32_t kind;         /* wos_geom_kind */
     double params[8];
     int32_t layout[4];
-    const double *verts;  /* host; polygon only (copied during the call) */
-    int32_t n_verts;      /* 3..WOS_MAX_POLY_VERTS */
+    const double *verts;  /* host; polygon vertices or perforated-disc holes (copied during the call) */
+    int32_t n_verts;      /* polygon: 3..WOS_MAX_POLY_VERTS vertices; perforated disc: holes */
 } wos_geometry;
 
 #define WOS_MAX_POLY_VERTS 64
+#define WOS_MAX_HOLES 32
 #define WOS_MAX_ELEMENTS 16384  /* one LDS histogram row must fit in 64 KiB */
 
 /* Number of boundary cells M of a geometry. */

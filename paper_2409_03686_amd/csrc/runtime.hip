@@ -128,6 +128,7 @@ static int elements_of(const wos_geometry *g)
     case WOS_ANNULUS: return g->layout[0] + g->layout[1];
     case WOS_BALL: return g->layout[0] * g->layout[1];
     case WOS_BOX: return g->dim == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
+    case WOS_PERFORATED: return g->layout[0] + g->layout[1] * g->layout[2];
     }
     return -1;
 }
@@ -173,6 +174,26 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
         for (int a = 0; a < g->dim; ++a)
             if (!(p[g->dim + a] > p[a])) return set_error(WOS_EINVAL, "box needs lo < hi on every axis");
         break;
+    case WOS_PERFORATED: {
+        if (g->dim != 2 || !(p[2] > 0)) return set_error(WOS_EINVAL, "perforated disc needs dim 2 and R > 0");
+        const int k = g->layout[2];
+        if (g->layout[1] < 1 || k < 1 || k > WOS_MAX_HOLES)
+            return set_error(WOS_EINVAL, "perforated disc needs layout (M_out >= 1, M_hole >= 1, 1..%d holes)", WOS_MAX_HOLES);
+        if (!g->verts || g->n_verts != k) return set_error(WOS_EINVAL, "perforated disc needs verts = %d (cx, cy, r) triples", k);
+        for (int l = 0; l < k; ++l) {
+            const double *h = g->verts + 3 * l;
+            if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !(h[2] > 0) || !std::isfinite(h[2]))
+                return set_error(WOS_EINVAL, "hole %d needs a finite centre and r > 0", l);
+            if (!(std::hypot(h[0] - p[0], h[1] - p[1]) + h[2] < p[2]))
+                return set_error(WOS_EINVAL, "hole %d is not inside the outer disc", l);
+            for (int m = 0; m < l; ++m) {
+                const double *o = g->verts + 3 * m;
+                if (!(std::hypot(h[0] - o[0], h[1] - o[1]) > h[2] + o[2]))
+                    return set_error(WOS_EINVAL, "holes %d and %d overlap", m, l);
+            }
+        }
+        break;
+    }
     default:
         return set_error(WOS_EINVAL, "unknown geometry kind %d", g->kind);
     }
@@ -259,6 +280,13 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
     case WOS_BALL:
         for (int j = 0; j < M; ++j) sigma[j] = 4.0 * M_PI * p[3] * p[3] / M;
         break;
+    case WOS_PERFORATED: {
+        const int mo = g->layout[0], mh = g->layout[1];
+        for (int j = 0; j < mo; ++j) sigma[j] = 2.0 * M_PI * p[2] / mo;
+        for (int l = 0; l < g->layout[2]; ++l)
+            for (int j = 0; j < mh; ++j) sigma[mo + l * mh + j] = 2.0 * M_PI * g->verts[3 * l + 2] / mh;
+        break;
+    }
     case WOS_BOX: {
         const int d = g->dim, n = g->layout[0];
         const int per_face = d == 2 ? n : n * n;
@@ -362,7 +390,7 @@ static double domain_scale(const wos_geometry *g)
     const double *p = g->params;
     double s = 0.0;
     switch (g->kind) {
-    case WOS_DISK: s = std::fabs(p[0]) + std::fabs(p[1]) + p[2]; break;
+    case WOS_DISK: case WOS_PERFORATED: s = std::fabs(p[0]) + std::fabs(p[1]) + p[2]; break;
     case WOS_ANNULUS: s = std::fabs(p[0]) + std::fabs(p[1]) + p[3]; break;
     case WOS_ELLIPSE: s = std::fabs(p[0]) + std::fabs(p[1]) + std::max(p[2], p[3]); break;
     case WOS_POLYGON:
@@ -470,6 +498,22 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             segs.push_back(s);
         }
         I.perim = cum;
+    }
+    if (g->kind == WOS_PERFORATED) {
+        // holes as (centre, radius) records; FP32 centres relative to the outer centre, like the
+        // FP32 walk positions of the centred kinds
+        I.n_verts = g->layout[2];
+        for (int l = 0; l < I.n_verts; ++l) {
+            const double *h = g->verts + 3 * l;
+            PolySeg s{};
+            s.ax = h[0];
+            s.ay = h[1];
+            s.ex = h[2];
+            s.fax = static_cast<float>(h[0] - g->params[0]);
+            s.fay = static_cast<float>(h[1] - g->params[1]);
+            s.fex = static_cast<float>(h[2]);
+            segs.push_back(s);
+        }
     }
     return WOS_OK;
 }

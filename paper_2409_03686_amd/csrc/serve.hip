@@ -145,7 +145,7 @@ struct Job {
     wos_request req{};
     wos_result *res = nullptr;
     ReqLayout L;
-    std::vector<double> x, uD, u0, u1, pred, sv;
+    std::vector<double> x, uD, u0, u1, pred, sv, verts;
     std::vector<uint8_t> mask;
     wos_result own{};
     bool done = false;
@@ -600,6 +600,11 @@ extern "C" wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uin
     j->req.uD_host = j->uD.data();
     j->req.u0_host = n0 ? j->u0.data() : nullptr;
     j->req.gamma1_mask_host = j->mask.data();
+    if (req->geom.verts && req->geom.n_verts > 0) {  // polygon vertices / perforated-disc holes
+        const size_t nv = static_cast<size_t>(req->geom.n_verts) * (req->geom.kind == WOS_PERFORATED ? 3 : 2);
+        j->verts.assign(req->geom.verts, req->geom.verts + nv);
+        j->req.geom.verts = j->verts.data();
+    }
     const int n1 = M - n0, k = std::min(req->n_obs, n1);
     j->u1.assign(std::max(n1, 1), 0.0);
     j->pred.assign(req->n_obs, 0.0);

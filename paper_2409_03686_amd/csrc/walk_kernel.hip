@@ -249,7 +249,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     const int M = I.n_elem;
     for (int j = tid; j < M; j += nthr) hist[j] = 0u;
     const PolySeg *segs = I.segs;
-    if constexpr (KIND == kPolygon) {
+    if constexpr (KIND == kPolygon || KIND == kPerforated) {  // edges / holes read every step
         for (int e = tid; e < I.n_verts; e += nthr) lds_segs[e] = I.segs[e];
         segs = lds_segs;
     }
@@ -471,6 +471,7 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
             case kAnnulus: run_item<R, 2, kAnnulus>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             case kEllipse: run_item<R, 2, kEllipse>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             case kPolygon: run_item<R, 2, kPolygon>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kPerforated: run_item<R, 2, kPerforated>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             default: run_item<R, 2, kBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             }
         } else {
@@ -505,6 +506,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel)
         case kAnnulus: return kptr<R, 2, kAnnulus>();
         case kEllipse: return kptr<R, 2, kEllipse>();
         case kPolygon: return kptr<R, 2, kPolygon>();
+        case kPerforated: return kptr<R, 2, kPerforated>();
         case kBox: return kptr<R, 2, kBox>();
         default: return kptr<R, 2, -1>();
         }

@@ -11,12 +11,14 @@
 
 namespace wos {
 
-enum Kind : int32_t { kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5 };
+enum Kind : int32_t { kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5, kPerforated = 6 };
 
 constexpr int kMaxPolyVerts = 64;
 constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
 
-// One polygon edge a -> b in FP64 (exit tests and cell indices) and FP32 (bulk distance).
+// One polygon edge a -> b in FP64 (exit tests and cell indices) and FP32 (bulk distance); for the
+// perforated disc one hole: centre (ax, ay), radius ex, and in FP32 the centre relative to the
+// outer centre (fax, fay) and the radius fex.
 struct PolySeg {
     double ax, ay, ex, ey, ll, cum, len, pad;
     float fax, fay, fex, fey, finv_ll, fpad0, fpad1, fpad2;
@@ -179,6 +181,16 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);
         return I.p[3] - __builtin_sqrt(s);
+    } else if constexpr (KIND == kPerforated) {
+        // the nearest of the outer circle and the hole circles
+        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
+        double best = I.p[2] - __builtin_sqrt(dx * dx + dy * dy);
+        for (int l = 0; l < I.n_verts; ++l) {
+            const double hx = x[0] - segs[l].ax, hy = x[1] - segs[l].ay;
+            const double d = __builtin_sqrt(hx * hx + hy * hy) - segs[l].ex;
+            best = d < best ? d : best;
+        }
+        return best;
     } else {  // kBox
         double best = __builtin_inf();
         for (int a = 0; a < DIM; ++a) {
@@ -195,7 +207,7 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
 // binning add it back.  FP64 positions are absolute.
 template <int KIND> constexpr bool centred32()
 {
-    return KIND == kDisk || KIND == kAnnulus || KIND == kEllipse || KIND == kBall;
+    return KIND == kDisk || KIND == kAnnulus || KIND == kEllipse || KIND == kBall || KIND == kPerforated;
 }
 template <typename R, int KIND> __device__ __forceinline__ double origin(const DevInst &I, int a)
 {
@@ -226,6 +238,13 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
         return __builtin_amdgcn_sqrtf(best);
     } else if constexpr (KIND == kBall) {
         return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    } else if constexpr (KIND == kPerforated) {
+        float best = I.pf[2] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1]);
+        for (int l = 0; l < I.n_verts; ++l) {
+            const float hx = x[0] - segs[l].fax, hy = x[1] - segs[l].fay;
+            best = __builtin_fminf(best, __builtin_amdgcn_sqrtf(hx * hx + hy * hy) - segs[l].fex);
+        }
+        return best;
     } else {
         float best = __builtin_inff();
 #pragma unroll
@@ -363,6 +382,23 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
         }
         const double s_at = segs[eb].cum + tb * segs[eb].len;
         return clamp_index(s_at * static_cast<double>(I.layout[0]) / I.perim, I.layout[0]);
+    } else if constexpr (KIND == kPerforated) {
+        // the nearest circle (ties: the outer one, then the lowest hole), then the arc about its centre
+        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
+        double best = I.p[2] - __builtin_sqrt(dx * dx + dy * dy), ax = dx, ay = dy;
+        int comp = -1;
+        for (int l = 0; l < I.n_verts; ++l) {
+            const double hx = x[0] - segs[l].ax, hy = x[1] - segs[l].ay;
+            const double d = __builtin_sqrt(hx * hx + hy * hy) - segs[l].ex;
+            if (d < best) {
+                best = d;
+                comp = l;
+                ax = hx;
+                ay = hy;
+            }
+        }
+        if (comp < 0) return arc_of(atan2(ay, ax), I.layout[0]);
+        return I.layout[0] + comp * I.layout[1] + arc_of(atan2(ay, ax), I.layout[1]);
     } else if constexpr (KIND == kBall) {
         double v[3], s = 0.0;
         for (int a = 0; a < 3; ++a) { v[a] = x[a] - I.p[a]; s += v[a] * v[a]; }

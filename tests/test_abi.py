@@ -46,6 +46,7 @@ def _geoms():
         wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (8, 16)),
         wi.Geometry(2, wi.BOX, (0.0, 0.0, 2.0, 1.0), (10,)),
         wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (24,)),
+        wi.perforated_disk_example().geom,
     ]
 
 
@@ -78,6 +79,12 @@ def test_invalid_geometries_are_rejected_on_the_host(wos):
         (wi.Geometry(2, 9, (0.0, 0.0, 1.0), (8,)), wos.WOS_EINVAL),                            # unknown kind
         (wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16385,)), wos.WOS_ENOTSUP),                 # too many cells
         (wi.Geometry(2, wi.DISK, (0.0, 0.0, float("nan")), (8,)), wos.WOS_EINVAL),
+        (wi.Geometry(2, wi.PERFORATED, (0.0, 0.0, 1.0), (8, 4, 1), verts=np.array([[0.7, 0.0, 0.4]])),
+         wos.WOS_EINVAL),                                                                      # hole sticks out
+        (wi.Geometry(2, wi.PERFORATED, (0.0, 0.0, 1.0), (8, 4, 2), verts=np.array([[0.2, 0.0, 0.3], [-0.2, 0.0, 0.3]])),
+         wos.WOS_EINVAL),                                                                      # holes overlap
+        (wi.Geometry(2, wi.PERFORATED, (0.0, 0.0, 1.0), (8, 4, 2), verts=np.array([[0.2, 0.0, 0.1]])),
+         wos.WOS_EINVAL),                                                                      # 1 hole given, 2 declared
     ]
     for g, code in bad:
         with pytest.raises(wos.WosError) as e:
