@@ -256,6 +256,46 @@ wos_status wos_reconstruct(wos_ctx *ctx, const wos_svd_t *h, const uint32_t *cou
                            int32_t *rank_used_dev, double *alpha_used_dev, void *stream);
 
 /* ------------------------------------------------------------------------------------------- */
+/* Products of the estimated measure (Section 5.2, items (i)-(iv))                               */
+/* ------------------------------------------------------------------------------------------- */
+/* The truncation sweep of Section 5.2, items (iii) and (iv): for every r = 1..r_max the r-TSVD
+ * solution (eq. u1r with the same numerical-rank rule as wos_reconstruct), the data it predicts at
+ * the points and the residual norm:
+ *   u1_dev[(r-1) n + j]   = (diag(sigma_1)^{-1/2} V_r S_r^{-1} U_r^T q)_j      (n x r_max, column-major),
+ *   pred_dev[(r-1) m + i] = ((counts/N)[:, Gamma_1] u1^(r) + (counts/N)[:, Gamma_0] u0)_i, formed as
+ *                           (counts/N)[:, Gamma_0] u0 + (U_r U_r^T q)_i / nu_i  (m x r_max; optional),
+ *   resid_dev[r]          = |q - B w_r| for r = 0..r_max (r_max + 1 values; optional),
+ * with q = diag(nu) (uD - (counts/N)[:, Gamma_0] u0).  Column r - 1 of u1 equals wos_reconstruct with
+ * WOS_TSVD_RANK and rank r bit for bit.  1 <= r_max <= k (the triplets the handle holds); pred needs
+ * every nu_i != 0.  Uses the handle's work matrix as scratch (the factors stay valid).  Arguments
+ * as for wos_reconstruct; asynchronous on `stream`. */
+wos_status wos_reconstruct_sweep(wos_ctx *ctx, const wos_svd_t *h, const uint32_t *counts_dev,
+                                 uint64_t n_walks, const double *uD_dev, const double *u0_dev,
+                                 int32_t r_max, double *u1_dev, double *pred_dev, double *resid_dev,
+                                 void *stream);
+
+/* Eigenvalues of Lambda^nu (eq. Lambda_tilde_nu), lambda_f = s_f^2, and the eigenfunction estimators
+ * of eq. eigenfunctions_MC on the Gamma_1 cells, for f = 0..n_fun-1:
+ *   ef_dev[f n + l] = lambda_f^{-1/2} sum_i nu_i [u_f]_i rho_i(l) = V[l, f] / sqrt(sigma_l),
+ * u_f the f-th left singular vector of B (an orthonormal eigenvector of Lambda^nu); the right-hand
+ * form is the one evaluated.  Each estimator is orthonormal in L^2(Gamma_1) (sum_l sigma_l ef_f ef_g
+ * = delta_fg); its sign is that of the handle's singular pair.  Meaningful for s_f above the
+ * numerical rank.  0 <= n_fun <= k; lambda_dev: double[n_fun] (optional), ef_dev: double[n x n_fun]
+ * (optional), device.  Asynchronous on `stream`. */
+wos_status wos_eigenfunctions(wos_ctx *ctx, const wos_svd_t *h, int32_t n_fun, double *lambda_dev,
+                              double *ef_dev, void *stream);
+
+/* Density estimator of the elliptic measure on every boundary cell (eq. rho omega1 MC with the
+ * cells as weight functions, Section 5.2 item (i)) and its average over the points:
+ *   rho_dev[i n_elem + j] = (counts[i n_elem + j] / n_walks) / sigma_j   (n_obs x n_elem, row-major),
+ *   mean_dev[j]           = (1 / n_obs) sum_i rho[i, j].
+ * sigma_dev: double[n_elem] cell measures (device); either output may be NULL, not both.  Needs no
+ * SVD.  Asynchronous on `stream`. */
+wos_status wos_density(wos_ctx *ctx, const uint32_t *counts_dev, int32_t n_obs, int32_t n_elem,
+                       uint64_t n_walks, const double *sigma_dev, double *rho_dev, double *mean_dev,
+                       void *stream);
+
+/* ------------------------------------------------------------------------------------------- */
 /* Captured pipeline: the whole path of one instance as one HIP graph                            */
 /* ------------------------------------------------------------------------------------------- */
 typedef struct wos_plan wos_plan;

@@ -15,6 +15,11 @@ Definitions followed (paper, Sections 3, 3.1, 4.3 and Algorithm "Main" of Sectio
   u_hat^D  = H[:, Gamma_1] u_1 + H[:, Gamma_0] u^0          (residual check, Section 5.2 item (iv))
 Truncation by the discrepancy principle: smallest r with |B w_r - nu b| <= tau * delta; Tikhonov
 alpha solves |B w_alpha - nu b| = tau * delta.
+Products (Section 5.2, items (i)-(iv)):
+  rho_i(l) = H_il / sigma_l                                  (eq. rho omega1 MC, cell indicators as weights)
+  Lambda^nu = diag(nu) H_1 diag(sigma_1)^{-1} H_1^T diag(nu)  (eq. Lambda_tilde_nu), eigenpairs by eigh
+  u_j      = lambda_j^{-1/2} sum_i nu_i [u_j]_i rho_i         (eq. eigenfunctions_MC) on the Gamma_1 cells
+  sweep    : u_1^(r), u_hat^{D,r} and |nu b - B w_r| for r = 1..r_max (items (iii), (iv))
 """
 from __future__ import annotations
 
@@ -113,3 +118,55 @@ def predicted_data(H, g1, u1, u0=None):
     if u0 is not None and (~g1).any():
         out = out + H[:, ~g1] @ u0
     return out
+
+
+def density(counts, n_walks, sigma):
+    """rho[i, l] = (counts[i, l] / N) / sigma_l on every boundary cell (eq. rho omega1 MC with the
+    cell indicators as the weight functions)."""
+    H = np.asarray(counts).astype(np.float64) / float(n_walks)
+    return H / np.asarray(sigma, float)[None, :]
+
+
+def mean_density(counts, n_walks, sigma):
+    """The density averaged over the points x^D_i."""
+    return density(counts, n_walks, sigma).mean(axis=0)
+
+
+def eigenfunctions(H, g1, sigma, nu=None, n_fun=None):
+    """Eigenvalues of Lambda^nu (descending, eq. Lambda_tilde_nu) and the eigenfunction estimators of
+    eq. eigenfunctions_MC on the Gamma_1 cells (n1 x n_fun), formed as written there: the eigenvectors
+    of Lambda^nu from LAPACK dsyevd, then lambda^{-1/2} sum_i nu_i [u_j]_i rho_i."""
+    g1 = np.asarray(g1).astype(bool)
+    H1 = np.asarray(H, float)[:, g1]
+    M_D = H1.shape[0]
+    nu = np.full(M_D, 1.0 / np.sqrt(M_D)) if nu is None else np.asarray(nu, float)
+    sig1 = np.asarray(sigma, float)[g1]
+    Lam = (nu[:, None] * H1 / sig1[None, :]) @ (H1.T * nu[None, :])
+    lam, E = sla.eigh(Lam, driver="evd")
+    order = np.argsort(lam)[::-1]
+    lam, E = lam[order], E[:, order]
+    if n_fun is None:  # the eigenbasis of the orthogonal complement of the kernel
+        n_fun = int(np.sum(lam > max(H1.shape) * np.finfo(float).eps * lam[0]))
+    rho = H1 / sig1[None, :]                               # rho_i on the Gamma_1 cells
+    ef = rho.T @ (nu[:, None] * E[:, :n_fun]) / np.sqrt(lam[:n_fun])[None, :]
+    return lam[:n_fun], ef
+
+
+def tsvd_sweep(U, s, Vt, sigma1, q, B, r_max, H=None, g1=None, u0=None, rank_tol=None):
+    """Items (iii) and (iv) of Section 5.2 for every truncation r = 1..r_max: columns r - 1 of
+    u1_all (the r-TSVD solution of reconstruct) and of pred_all (H_1 u1 + H_0 u0), and the residual
+    norms |q - B w_r| for r = 0..r_max, w_r = diag(sigma_1)^{1/2} u1^(r) evaluated with B itself."""
+    n1 = Vt.shape[1]
+    u1_all = np.zeros((n1, r_max))
+    pred_all = None if H is None else np.zeros((H.shape[0], r_max))
+    resid = np.empty(r_max + 1)
+    resid[0] = np.linalg.norm(q)
+    sq = np.sqrt(np.asarray(sigma1, float))
+    for r in range(1, r_max + 1):
+        u1, _, _ = reconstruct(U, s, Vt, sigma1, q, kind=TSVD_RANK, rank=r, rank_tol=rank_tol)
+        u1_all[:, r - 1] = u1
+        resid[r] = np.linalg.norm(q - B @ (sq * u1))
+        if H is not None:
+            pred_all[:, r - 1] = predicted_data(H, g1, u1, u0)
+    return u1_all, pred_all, resid
+

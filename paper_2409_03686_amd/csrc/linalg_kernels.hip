@@ -1134,6 +1134,15 @@ __global__ void recon_c_kernel(SvdDevView v)
     }
 }
 
+// Components with s_l at or below this level are left out of every solution: the numerical rank
+// (max(m, n) u s_1), or the cut of the truncated path when that is larger.
+__device__ __forceinline__ double rank_level(const SvdDevView &v)
+{
+    const double s0 = v.k > 0 ? v.s[0] : 0.0;
+    const double t = static_cast<double>(v.m > v.n ? v.m : v.n) * 0x1.0p-52 * s0;
+    return v.rank_cut * s0 > t ? v.rank_cut * s0 : t;
+}
+
 // Single block: filter factors phi and the regularisation actually used.
 __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out, double *alpha_out)
 {
@@ -1142,8 +1151,7 @@ __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out,
     __shared__ int sh_rank;
     const int k = v.k;
     const double s0 = k > 0 ? v.s[0] : 0.0;
-    double rank_tol = static_cast<double>(v.m > v.n ? v.m : v.n) * 0x1.0p-52 * s0;
-    if (v.rank_cut * s0 > rank_tol) rank_tol = v.rank_cut * s0;  // truncated path
+    const double rank_tol = rank_level(v);
     if (threadIdx.x == 0) {
         int kpos = 0;
         for (int l = 0; l < k; ++l) kpos += v.s[l] > rank_tol ? 1 : 0;
@@ -1247,6 +1255,135 @@ __global__ void recon_pred_kernel(SvdDevView v, const uint32_t *__restrict__ cou
         acc = block_sum(acc, scratch);
         if (threadIdx.x == 0) pred[i] = acc;
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Products of the estimated measure (Section 5.2, items (i)-(iv))
+// ---------------------------------------------------------------------------------------------
+// Density estimator on the boundary cells (eq. rho omega1 MC with the cell indicators as weight
+// functions): rho[i, j] = (counts[i, j] / N) / sigma_j, divided in that order.
+__global__ void density_kernel(const uint32_t *__restrict__ counts, int m, int n_elem, double n_walks,
+                               const double *__restrict__ sigma, double *__restrict__ rho)
+{
+    for (int i = blockIdx.y; i < m; i += gridDim.y) {
+        const size_t base = static_cast<size_t>(i) * n_elem;
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_elem; j += gridDim.x * blockDim.x)
+            rho[base + j] = static_cast<double>(counts[base + j]) / n_walks / sigma[j];
+    }
+}
+
+// Average of the density over the points: one block per 64 cells, its 16 waves take every 16th
+// row, then a fixed-order sum of the 16 partials.
+__global__ __launch_bounds__(1024) void density_mean_kernel(const uint32_t *__restrict__ counts, int m, int n_elem,
+                                                            double n_walks, const double *__restrict__ sigma,
+                                                            double *__restrict__ mean)
+{
+    __shared__ double part[16][kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int j = blockIdx.x * kWave + lane;
+    double acc = 0.0;
+    if (j < n_elem) {
+        const double sj = sigma[j];
+        for (int i = w; i < m; i += 16)
+            acc += static_cast<double>(counts[static_cast<size_t>(i) * n_elem + j]) / n_walks / sj;
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && j < n_elem) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += part[q][lane];
+        mean[j] = t / static_cast<double>(m);
+    }
+}
+
+// Eigenvalues lambda_f = s_f^2 of Lambda^nu = B B^T and the eigenfunction estimators on the Gamma_1
+// cells.  The estimator of eq. eigenfunctions_MC, lambda_f^{-1/2} sum_i nu_i [u_f]_i rho_i, equals
+// lambda_f^{-1/2} diag(sigma_1)^{-1/2} B^T u_f = diag(sigma_1)^{-1/2} v_f, which is what is formed here
+// (no division by s_f).
+__global__ void eigfun_kernel(SvdDevView v, int n_fun, double *__restrict__ lam, double *__restrict__ ef)
+{
+    for (int f = blockIdx.y; f < n_fun; f += gridDim.y) {
+        if (lam && blockIdx.x == 0 && threadIdx.x == 0) lam[f] = v.s[f] * v.s[f];
+        if (!ef) continue;
+        const double *vf = v.V + static_cast<size_t>(f) * v.n;
+        for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < v.n; l += gridDim.x * blockDim.x)
+            ef[static_cast<size_t>(f) * v.n + l] = vf[l] * v.isig1[l];
+    }
+}
+
+// u1 of every truncation r = 1..r_max (column r - 1).  Same filter factors and accumulation order
+// as recon_select_kernel / recon_u1_kernel, so column r - 1 equals the rank-r reconstruction bit for
+// bit.
+__global__ void sweep_u1_kernel(SvdDevView v, int r_max, double *__restrict__ u1)
+{
+    const double lev = rank_level(v);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < v.n; j += gridDim.x * blockDim.x) {
+        const double is = v.isig1[j];
+        double acc = 0.0;
+        for (int l = 0; l < r_max; ++l) {
+            const double sl = v.s[l];
+            if (sl > lev) acc = __builtin_fma(v.V[static_cast<size_t>(l) * v.n + j], (1.0 / sl) * v.cvec[l], acc);
+            u1[static_cast<size_t>(l) * v.n + j] = acc * is;
+        }
+    }
+}
+
+// Rows of the sweep, 256 per block.  Per row: g0 = (counts/N)[:, Gamma_0] u0 (one wave per row),
+// then for r = 0..r_max the projection p_r = U_r c_r, the data predicted at the point,
+// g0 + p_r / nu (because (counts/N)[:, Gamma_1] u1^(r) = diag(nu)^{-1} B w_r = diag(nu)^{-1} U_r c_r),
+// and the block's share of |q - p_r|^2, written to part[r * gridDim.x + block].
+__global__ __launch_bounds__(256) void sweep_rows_kernel(SvdDevView v, const uint32_t *__restrict__ counts,
+                                                         double inv_n, const double *__restrict__ u0, int r_max,
+                                                         double *__restrict__ pred, double *__restrict__ part)
+{
+    __shared__ double g0s[256];
+    __shared__ double red[4][kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int row0 = blockIdx.x * 256;
+    for (int t = w; t < 256; t += 4) {
+        const int i = row0 + t;
+        double acc = 0.0;
+        if (i < v.m && u0) {
+            const uint32_t *row = counts + static_cast<size_t>(i) * v.n_elem;
+            for (int l = lane; l < v.n0; l += kWave)
+                acc = __builtin_fma(static_cast<double>(row[v.g0idx[l]]) * inv_n, u0[l], acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) g0s[t] = acc;
+    }
+    __syncthreads();
+    const int i = row0 + static_cast<int>(threadIdx.x);
+    const bool live = i < v.m;
+    const double lev = rank_level(v);
+    const double qi = live ? v.q[i] : 0.0, nui = live ? v.nu[i] : 1.0, g0 = g0s[threadIdx.x];
+    double p = 0.0;
+    for (int r = 0; r <= r_max; ++r) {
+        if (r > 0) {
+            const int l = r - 1;
+            if (live && v.s[l] > lev) p = __builtin_fma(v.U[static_cast<size_t>(l) * v.m + i], v.cvec[l], p);
+            if (live && pred) pred[static_cast<size_t>(l) * v.m + i] = g0 + p / nui;
+        }
+        const double e = live ? qi - p : 0.0;
+        const double e2 = wave_sum(e * e);
+        if (lane == 0) red[w][r & (kWave - 1)] = e2;
+        if ((r & (kWave - 1)) == kWave - 1 || r == r_max) {  // uniform over the block
+            __syncthreads();
+            const int t = static_cast<int>(threadIdx.x);
+            if (t <= (r & (kWave - 1)))
+                part[static_cast<size_t>((r & ~(kWave - 1)) + t) * gridDim.x + blockIdx.x] =
+                    ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void sweep_resid_kernel(const double *__restrict__ part, int nb, int r_max, double *__restrict__ resid)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r <= r_max; r += gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int b = 0; b < nb; ++b) t += part[static_cast<size_t>(r) * nb + b];
+        resid[r] = __builtin_sqrt(t);
     }
 }
 
@@ -1399,6 +1536,49 @@ hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_
     const int gn = (v.n + 255) / 256 < 1 ? 1 : (v.n + 255) / 256;
     recon_u1_kernel<<<gn, 256, 0, stream>>>(v, u1);
     if (pred) recon_pred_kernel<<<gm, 256, 0, stream>>>(v, counts, inv_n, u1, u0, pred);
+    return hipGetLastError();
+}
+
+hipError_t density_launch(const uint32_t *counts, int m, int n_elem, uint64_t n_walks, const double *sigma,
+                          double *rho, double *mean, hipStream_t stream)
+{
+    const double n = static_cast<double>(n_walks);
+    if (rho) {
+        const dim3 grid((n_elem + 255) / 256 > 64 ? 64 : (n_elem + 255) / 256, m > 32768 ? 32768 : m);
+        density_kernel<<<grid, 256, 0, stream>>>(counts, m, n_elem, n, sigma, rho);
+    }
+    if (mean) density_mean_kernel<<<(n_elem + kWave - 1) / kWave, 1024, 0, stream>>>(counts, m, n_elem, n, sigma, mean);
+    return hipGetLastError();
+}
+
+hipError_t eigfun_launch(const SvdDevView &v, int n_fun, double *lam, double *ef, hipStream_t stream)
+{
+    if (n_fun <= 0) return hipSuccess;
+    const dim3 grid((v.n + 255) / 256 > 64 ? 64 : (v.n + 255) / 256, n_fun > 32768 ? 32768 : n_fun);
+    eigfun_kernel<<<grid, 256, 0, stream>>>(v, n_fun, lam, ef);
+    return hipGetLastError();
+}
+
+size_t sweep_part_words(const SvdDevView &v, int r_max)
+{
+    return static_cast<size_t>((v.m + 255) / 256) * static_cast<size_t>(r_max + 1);
+}
+
+hipError_t sweep_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
+                        const double *u0, int r_max, double *u1, double *pred, double *resid, hipStream_t stream)
+{
+    const int gm = v.m < 1 ? 1 : (v.m > 2048 ? 2048 : v.m);
+    const int gk = v.k < 1 ? 1 : (v.k > 2048 ? 2048 : v.k);
+    recon_q_kernel<<<gm, 256, 0, stream>>>(v, counts, inv_n, uD, u0);
+    recon_c_kernel<<<gk, 256, 0, stream>>>(v);
+    const int gn = (v.n + 255) / 256 < 1 ? 1 : (v.n + 255) / 256;
+    sweep_u1_kernel<<<gn, 256, 0, stream>>>(v, r_max, u1);
+    if (pred || resid) {
+        // the block partials of the residual norms go to the work matrix, free once the factors exist
+        const int nb = (v.m + 255) / 256;
+        sweep_rows_kernel<<<nb, 256, 0, stream>>>(v, counts, inv_n, u0, r_max, pred, v.A);
+        if (resid) sweep_resid_kernel<<<(r_max + 256) / 256, 256, 0, stream>>>(v.A, nb, r_max, resid);
+    }
     return hipGetLastError();
 }
 

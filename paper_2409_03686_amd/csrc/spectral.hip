@@ -18,6 +18,7 @@ struct wos_svd_t {
     void *mem = nullptr;
     size_t bytes = 0;
     int coop_grid = 1;
+    bool nu_nonzero = true;  // every nu_i != 0: the sweep's predicted data divide by nu
 };
 
 namespace {
@@ -220,6 +221,7 @@ extern "C" wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem
     }
     h->v = hs.v;
     h->coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, ctx->n_cu);
+    for (double x : hs.nu) h->nu_nonzero = h->nu_nonzero && x != 0.0;
     *out = h;
     return WOS_OK;
 }
@@ -300,6 +302,55 @@ extern "C" wos_status wos_reconstruct(wos_ctx *ctx, const wos_svd_t *h, const ui
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, recon_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), uD_dev, h->v.n0 ? u0_dev : nullptr,
                               r, u1_dev, pred_dev, rank_used_dev, alpha_used_dev, static_cast<hipStream_t>(stream)));
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_reconstruct_sweep(wos_ctx *ctx, const wos_svd_t *h, const uint32_t *counts_dev,
+                                            uint64_t n_walks, const double *uD_dev, const double *u0_dev,
+                                            int32_t r_max, double *u1_dev, double *pred_dev, double *resid_dev,
+                                            void *stream)
+{
+    if (!ctx || !h || !counts_dev || !uD_dev || !u1_dev) return set_error(WOS_EINVAL, "NULL argument");
+    if (n_walks == 0) return set_error(WOS_EINVAL, "n_walks must be >= 1");
+    if (h->v.n0 > 0 && !u0_dev) return set_error(WOS_EINVAL, "u0_dev is required when Gamma_0 is not empty");
+    if (r_max < 1 || r_max > h->v.k)
+        return set_error(WOS_EINVAL, "r_max = %d outside [1, %d] (the singular triplets held)", r_max, h->v.k);
+    if (pred_dev && !h->nu_nonzero) return set_error(WOS_EINVAL, "predicted data need every nu_i != 0");
+    if (sweep_part_words(h->v, r_max) > static_cast<size_t>(h->v.rows) * h->v.colsp)
+        return set_error(WOS_EINVAL, "residual partials exceed the work matrix");  // cannot happen for r_max <= k
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, sweep_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), uD_dev,
+                              h->v.n0 ? u0_dev : nullptr, r_max, u1_dev, pred_dev, resid_dev,
+                              static_cast<hipStream_t>(stream)));
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_eigenfunctions(wos_ctx *ctx, const wos_svd_t *h, int32_t n_fun, double *lambda_dev,
+                                         double *ef_dev, void *stream)
+{
+    if (!ctx || !h) return set_error(WOS_EINVAL, "ctx or handle NULL");
+    if (n_fun < 0 || n_fun > h->v.k)
+        return set_error(WOS_EINVAL, "n_fun = %d outside [0, %d] (the singular triplets held)", n_fun, h->v.k);
+    if (n_fun > 0 && !lambda_dev && !ef_dev) return set_error(WOS_EINVAL, "no output given");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, eigfun_launch(h->v, n_fun, lambda_dev, ef_dev, static_cast<hipStream_t>(stream)));
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_density(wos_ctx *ctx, const uint32_t *counts_dev, int32_t n_obs, int32_t n_elem,
+                                  uint64_t n_walks, const double *sigma_dev, double *rho_dev, double *mean_dev,
+                                  void *stream)
+{
+    if (!ctx || !counts_dev || !sigma_dev) return set_error(WOS_EINVAL, "NULL argument");
+    if (!rho_dev && !mean_dev) return set_error(WOS_EINVAL, "no output given");
+    if (n_obs < 1 || n_elem < 1) return set_error(WOS_EINVAL, "n_obs and n_elem must be >= 1");
+    if (n_walks == 0) return set_error(WOS_EINVAL, "n_walks must be >= 1");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, density_launch(counts_dev, n_obs, n_elem, n_walks, sigma_dev, rho_dev, mean_dev,
+                                static_cast<hipStream_t>(stream)));
     return WOS_OK;
 }
 

@@ -81,6 +81,12 @@ constexpr int kTruncRank = 128;
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
                         const double *u0, const RegDev &reg, double *u1, double *pred, int32_t *rank_out,
                         double *alpha_out, hipStream_t stream);
+hipError_t density_launch(const uint32_t *counts, int m, int n_elem, uint64_t n_walks, const double *sigma,
+                          double *rho, double *mean, hipStream_t stream);
+hipError_t eigfun_launch(const SvdDevView &v, int n_fun, double *lam, double *ef, hipStream_t stream);
+size_t sweep_part_words(const SvdDevView &v, int r_max);  // doubles of residual partials (in v.A)
+hipError_t sweep_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,
+                        const double *u0, int r_max, double *u1, double *pred, double *resid, hipStream_t stream);
 hipError_t fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t stream);
 
 }  // namespace wos

@@ -106,6 +106,9 @@ _SIGS = {
     "wos_svd_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _VP]),
     "wos_reconstruct": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP, _VP,
                                   _VP, _VP]),
+    "wos_reconstruct_sweep": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "wos_eigenfunctions": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP]),
+    "wos_density": (C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_uint64, _VP, _VP, _VP, _VP]),
     "wos_plan_create": (C.c_int, [_VP, C.POINTER(WosMeasureJob), _VP, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP,
                                   _VP, _VP, C.POINTER(_VP)]),
     "wos_plan_launch": (C.c_int, [_VP, _VP]),
@@ -306,6 +309,22 @@ def wos_reconstruct(ctx, h, counts_dev, n_walks, uD_dev, u0_dev, reg: WosRegPara
     _check(lib().wos_reconstruct(ctx, h, _ptr(counts_dev), int(n_walks), _ptr(uD_dev), _ptr(u0_dev), C.byref(reg),
                                  _ptr(u1_dev), _ptr(pred_dev), _ptr(rank_used_dev), _ptr(alpha_used_dev),
                                  _stream(stream)))
+
+
+def wos_reconstruct_sweep(ctx, h, counts_dev, n_walks, uD_dev, u0_dev, r_max, u1_dev, pred_dev=None,
+                          resid_dev=None, stream=None):
+    _check(lib().wos_reconstruct_sweep(ctx, h, _ptr(counts_dev), int(n_walks), _ptr(uD_dev), _ptr(u0_dev),
+                                       int(r_max), _ptr(u1_dev), _ptr(pred_dev), _ptr(resid_dev),
+                                       _stream(stream)))
+
+
+def wos_eigenfunctions(ctx, h, n_fun, lambda_dev=None, ef_dev=None, stream=None):
+    _check(lib().wos_eigenfunctions(ctx, h, int(n_fun), _ptr(lambda_dev), _ptr(ef_dev), _stream(stream)))
+
+
+def wos_density(ctx, counts_dev, n_obs, n_elem, n_walks, sigma_dev, rho_dev=None, mean_dev=None, stream=None):
+    _check(lib().wos_density(ctx, _ptr(counts_dev), int(n_obs), int(n_elem), int(n_walks), _ptr(sigma_dev),
+                             _ptr(rho_dev), _ptr(mean_dev), _stream(stream)))
 
 
 def wos_plan_create(ctx, job: WosMeasureJob, svd=None, uD_dev=None, u0_dev=None, reg: Optional[WosRegParams] = None,

@@ -108,3 +108,7 @@ def test_null_arguments_are_rejected(wos):
     L = wos.lib()
     assert L.wos_element_count(None, None) == wos.WOS_EINVAL
     assert L.wos_plan_destroy(None) in (wos.WOS_OK, wos.WOS_EINVAL)
+    # the products reject missing arguments before touching a device
+    assert L.wos_density(None, None, 1, 1, 1, None, None, None, None) == wos.WOS_EINVAL
+    assert L.wos_eigenfunctions(None, None, 0, None, None, None) == wos.WOS_EINVAL
+    assert L.wos_reconstruct_sweep(None, None, None, 1, None, None, 1, None, None, None, None) == wos.WOS_EINVAL

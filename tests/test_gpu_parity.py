@@ -480,6 +480,90 @@ def test_reconstruction_matches_oracle(wos, ctx):
     wos.wos_svd_destroy(ctx, h)
 
 
+def test_products_match_oracle(wos, ctx):
+    """Section 5.2 items (i)-(iv) on the anisotropic annulus: the density estimator and its average,
+    the eigenvalues and eigenfunction estimators of Lambda^nu, and the truncation sweep (u1, predicted
+    data and residual norm for every r), each against the oracle's literal formula."""
+    inst = wi.cfg2_annulus(n_walks=20_000)
+    c, _, _ = _gpu(wos, ctx, inst)
+    g = inst.geom
+    sigma = ow.element_measures(g)
+    g1 = g.gamma1_mask.astype(bool)
+    m, M = c.shape
+    n1 = int(g1.sum())
+    h, ct, U, s, V, _, _ = _svd_case(wos, ctx, c, inst.n_walks, g.gamma1_mask, sigma)
+    out = ol.assemble(c, inst.n_walks, g.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+    Ur, sr, Vtr = ol.svd(out["B"])
+    k = len(sr)
+
+    # (i) density and its average over the points
+    sig_d = torch.as_tensor(sigma, dtype=torch.float64, device="cuda")
+    rho = torch.zeros((m, M), dtype=torch.float64, device="cuda")
+    mean = torch.zeros(M, dtype=torch.float64, device="cuda")
+    wos.wos_density(ctx, ct, m, M, inst.n_walks, sig_d, rho, mean)
+    torch.cuda.synchronize()
+    rho_r = ol.density(c, inst.n_walks, sigma)
+    print(f"density: bit-exact {np.array_equal(rho.cpu().numpy(), rho_r)}")
+    assert np.abs(rho.cpu().numpy() - rho_r).max() <= 2.0 ** -51 * np.abs(rho_r).max()
+    mr = ol.mean_density(c, inst.n_walks, sigma)
+    assert np.abs(mean.cpu().numpy() - mr).max() <= 1e-14 * np.abs(mr).max()
+
+    # (ii) eigenvalues and eigenfunction estimators
+    nf = 16
+    lam = torch.zeros(nf, dtype=torch.float64, device="cuda")
+    ef = torch.zeros((nf, n1), dtype=torch.float64, device="cuda")  # column f at ef[f]
+    wos.wos_eigenfunctions(ctx, h, nf, lam, ef)
+    torch.cuda.synchronize()
+    lam_r, ef_r = ol.eigenfunctions(out["H"], g1, sigma, n_fun=nf)
+    lam, ef = lam.cpu().numpy(), ef.cpu().numpy().T
+    assert np.abs(lam - lam_r).max() <= 3e-10 * lam_r[0]
+    gram = ef.T @ (sigma[g1][:, None] * ef)
+    assert np.abs(gram - np.eye(nf)).max() <= 1e-10
+    gap = np.concatenate([[np.inf], -np.diff(sr), [np.inf]]) / sr[0]
+    worst = 0.0
+    for f in range(nf):
+        if min(gap[f], gap[f + 1]) < 1e-3:
+            continue  # eigenfunction of a (nearly) repeated eigenvalue: not unique
+        sgn = np.sign(ef[:, f] @ ef_r[:, f])
+        err = np.abs(sgn * ef[:, f] - ef_r[:, f]).max() / np.abs(ef_r[:, f]).max()
+        worst = max(worst, err)
+        assert err <= 2.0 ** -36 * np.linalg.norm(out["B"]) / (sr[0] * min(gap[f], gap[f + 1]))
+    print(f"eigenfunctions: max rel err {worst:.2e} over the separated ones")
+
+    # (iii)-(iv) truncation sweep
+    r_max = min(k, 40)
+    uD_d = torch.as_tensor(inst.uD, dtype=torch.float64, device="cuda")
+    u0_d = torch.as_tensor(inst.u0, dtype=torch.float64, device="cuda")
+    u1s = torch.zeros((r_max, n1), dtype=torch.float64, device="cuda")
+    preds = torch.zeros((r_max, m), dtype=torch.float64, device="cuda")
+    res = torch.zeros(r_max + 1, dtype=torch.float64, device="cuda")
+    wos.wos_reconstruct_sweep(ctx, h, ct, inst.n_walks, uD_d, u0_d, r_max, u1s, preds, res)
+    torch.cuda.synchronize()
+    u1s, preds, res = u1s.cpu().numpy().T, preds.cpu().numpy().T, res.cpu().numpy()
+    for r in (1, 6, r_max):
+        u1, _, r_used, _ = _recon(wos, ctx, h, ct, inst.n_walks, inst.uD, inst.u0,
+                                  wos.reg_params(wos.WOS_TSVD_RANK, rank=r), n1, m)
+        assert r_used == r and np.array_equal(u1, u1s[:, r - 1])
+    u1_r, pred_r, res_r = ol.tsvd_sweep(Ur, sr, Vtr, sigma[g1], out["q"], out["B"], r_max, out["H"], g1, inst.u0)
+    qn = np.linalg.norm(out["q"])
+    assert abs(res[0] - qn) <= 1e-14 * qn
+    fro = np.linalg.norm(out["B"])
+    worst = [0.0, 0.0, 0.0]
+    for r in range(1, r_max + 1):
+        gr = gap[r]  # gap between s_r and s_{r+1} (0-based gap[r] = s_{r-1} - s_r)
+        if r < k and gr < 1e-9:
+            continue  # cut inside a numerically degenerate pair: subspace not unique
+        tol = max(1e-10, 2.0 ** -36 * fro / sr[0] * sr[0] / sr[r - 1])
+        e1 = np.abs(u1s[:, r - 1] - u1_r[:, r - 1]).max() / np.abs(u1_r[:, r - 1]).max()
+        e2 = np.abs(preds[:, r - 1] - pred_r[:, r - 1]).max() / np.abs(pred_r[:, r - 1]).max()
+        e3 = abs(res[r] - res_r[r]) / qn
+        worst = [max(worst[0], e1 / tol), max(worst[1], e2 / tol), max(worst[2], e3)]
+        assert e1 <= tol and e2 <= tol
+        assert e3 <= 1e-10 + 2.0 ** -36 * fro / (sr[0] * (gr if r < k else 1.0))
+    print(f"sweep r=1..{r_max}: u1 err/tol {worst[0]:.2e}, pred err/tol {worst[1]:.2e}, resid rel {worst[2]:.2e}")
+    wos.wos_svd_destroy(ctx, h)
+
+
 def test_exact_data_is_recovered(wos, ctx):
     """Counts = round(H 2^26) of the exact disk measure and data generated by them: the full-rank
     TSVD must return the boundary values that generated the data."""
