@@ -80,7 +80,7 @@ def log(msg):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--walks", type=int, default=100_000)
     p.add_argument("--spectral-cus", type=int, default=8,

@@ -129,7 +129,10 @@ typedef enum { WOS_RADIUS_WOE_BOUND = 0, WOS_RADIUS_MAPPED_EXACT = 1 } wos_radiu
 typedef struct {
     double K[9];          /* conductivity, row-major, leading dim x dim block; symmetric positive
                              definite; only K / lambda_max(K) enters the walk (Section 4.2) */
-    double eps;           /* stopping shell width, > 0 */
+    double eps;           /* stopping shell width, > 0; or 0 with WOS_FP64 and max_steps >= 1: the
+                             fixed-iteration walk (Remark on Algorithm MC-REM, item (i)), in which
+                             every walk makes exactly max_steps steps, stops earlier only on
+                             reaching dD (dist <= 0) and is binned at its last point */
     uint64_t walk_begin;  /* walks k in [walk_begin, walk_end) are run for every point; */
     uint64_t walk_end;    /* walk_end <= 2^32, walk_end - walk_begin < 2^32.  Splitting a range and summing is bit-exact. */
     uint64_t seed;        /* Philox key (low word, high word) */

@@ -14,7 +14,9 @@
  *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
  *   radius: r = dist(x, dD) ("WoE bound") or, for boxes, the largest r with x + r S B(0,1) inside D
  *   ("mapped exact").  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
- *   epsilon x"), tested before each step.  The stop point is projected onto dD and the element
+ *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
+ *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
+ *   reaching dD, dist <= 0) and its last point is binned.  The stop point is projected onto dD and the element
  *   that contains the projection receives one count (intrinsic Voronoi weights, Appendix
  *   Ex. A.3; for equally spaced arcs this equals the extrinsic Voronoi cells of Ex. A.2).  So
  *   counts[i, j] / N is the Monte Carlo estimate A_{omega, eps, N} of eq. "WoE_matrix_MC".
@@ -396,7 +398,8 @@ int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, doub
                          uint64_t *stats_out, int32_t *trace, const uint32_t *point_ids,
                          int n_threads)
 {
-    if (!g || !S || !counts || n_obs < 0 || walk_end < walk_begin || eps <= 0.0) return -1;
+    if (!g || !S || !counts || n_obs < 0 || walk_end < walk_begin || !(eps >= 0.0)) return -1;
+    if (eps == 0.0 && max_steps == 0) return -1; /* the fixed-iteration loop needs its count */
     if (radius_mode == 1 && g->kind != OG_BOX) return -1;
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
@@ -449,7 +452,8 @@ int oracle_walk_exits(const og_geom *g, const double *S, double eps, int radius_
                       uint32_t seed_lo, uint32_t seed_hi, uint32_t inst, uint32_t max_steps,
                       const double *x0, uint32_t i, uint64_t kb, uint64_t ke, double *pos_out)
 {
-    if (!g || !S || !x0 || !pos_out || ke < kb || eps <= 0.0) return -1;
+    if (!g || !S || !x0 || !pos_out || ke < kb || !(eps >= 0.0)) return -1;
+    if (eps == 0.0 && max_steps == 0) return -1;
     if (radius_mode == 1 && g->kind != OG_BOX) return -1;
     int dim = g->dim;
     for (uint64_t k = kb; k < ke; ++k) {

@@ -370,7 +370,9 @@ wos_status wos::conductivity_root(const double *K, int d, double S[9], double *l
 wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
 {
     if (!w) return set_error(WOS_EINVAL, "walk params are NULL");
-    if (!(w->eps > 0) || !std::isfinite(w->eps)) return set_error(WOS_EINVAL, "eps must be finite and > 0");
+    if (!(w->eps >= 0) || !std::isfinite(w->eps)) return set_error(WOS_EINVAL, "eps must be finite and >= 0");
+    if (w->eps == 0 && (w->precision != WOS_FP64 || w->max_steps == 0))
+        return set_error(WOS_EINVAL, "eps = 0 (the fixed-iteration walk) needs WOS_FP64 and max_steps >= 1");
     if (w->walk_end < w->walk_begin) return set_error(WOS_EINVAL, "walk_end < walk_begin");
     if (w->walk_end > (1ull << 32)) return set_error(WOS_EINVAL, "walk ids must be below 2^32");
     if (w->walk_end - w->walk_begin >= (1ull << 32)) return set_error(WOS_EINVAL, "at most 2^32 - 1 walks per call");

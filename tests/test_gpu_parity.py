@@ -290,12 +290,33 @@ def test_degenerate_inputs(wos, ctx):
     assert np.all(c.sum(1) == 5000) and _agreement(tr, trr) >= 0.999
 
 
+@pytest.mark.parametrize("n", [16, 64])
+def test_fixed_iteration_walk_for_walk(wos, ctx, n):
+    """eps = 0, FP64: the fixed-iteration loop.  Each walk makes n steps (fewer only when it reaches
+    dD in FP64) and is binned at its last point; exit cells walk for walk against the oracle.  At
+    n = 64 most walks reach dD to FP64 resolution before n, at a step that the last bit of sin/cos
+    decides, so only the cells are compared there."""
+    inst = wi.cfg1_disk(n_walks=5000)
+    inst.eps, inst.max_steps = 0.0, n
+    c, st, tr = _gpu(wos, ctx, inst, trace=True, precision=wi.FP64)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    assert np.all(c.sum(1) == inst.n_walks) and st["walks"] == sr["walks"]
+    cells = float(np.mean(tr[..., 0] == trr[..., 0]))
+    print(f"fixed-iteration walk n={n}: cell agreement {cells:.6f}, cap hits {st['cap_hits']} (oracle {sr['cap_hits']})")
+    assert cells >= 0.999 and st["max_steps"] == n
+    if n == 16:
+        assert _agreement(tr, trr) >= 0.999
+        assert abs(st["cap_hits"] - sr["cap_hits"]) <= 0.001 * st["walks"]
+
+
 def test_invalid_arguments_raise(wos, ctx):
     g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16,))
     x = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
     cnt = torch.zeros((4, 16), dtype=torch.int32, device="cuda")
     bad = [
-        (g, wos.walk_params(np.eye(2), -1.0, 0, 10)),                      # eps <= 0
+        (g, wos.walk_params(np.eye(2), -1.0, 0, 10)),                      # eps < 0
+        (g, wos.walk_params(np.eye(2), 0.0, 0, 10)),                       # eps = 0 without a step count
+        (g, wos.walk_params(np.eye(2), 0.0, 0, 10, precision=1, max_steps=8)),  # eps = 0 in FP32
         (g, wos.walk_params(np.array([[1, 2], [2, 1.0]]), 1e-4, 0, 10)),  # not SPD
         (g, wos.walk_params(np.array([[1, 0.5], [0.0, 1.0]]), 1e-4, 0, 10)),  # not symmetric
         (g, wos.walk_params(np.eye(2), 1e-4, 10, 5)),                       # empty range reversed

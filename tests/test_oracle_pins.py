@@ -460,3 +460,25 @@ def test_perforated_disc_reproduces_paper_solution():
     _, _, S = walks.instance_setup(np.eye(2), 2)
     sol3 = lambda p: p[:, 0] ** 2 - p[:, 1] ** 2
     assert np.all(_exit_mean_z(g, S, x, sol3, 30_000, grad_bound=2.0) < 4.5)
+
+
+def test_fixed_iteration_walk():
+    """eps = 0: the fixed-iteration loop (Remark on Algorithm MC-REM, item (i)).  Every walk makes
+    exactly n steps unless it reaches dD (dist <= 0 in FP64) first, and its last point is binned.  The
+    distance to the boundary shrinks geometrically, so at n = 8 the disk estimate already matches the
+    Poisson-kernel closed form at N = 10^4 while n = 3 is visibly biased (walks still well inside D)."""
+    inst = wi.cfg1_disk()
+    P = cf.disk_H(inst.x_obs, 1.0, 64)
+    c3, st3, _ = walks.build_measure(inst.geom, inst.K, inst.x_obs, 0.0, max_steps=3, walk_end=10_000, threads=8)
+    assert st3["cap_hits"] == st3["walks"] == 640_000 and st3["steps"] == 3 * 640_000
+    assert not statutil.vs_probabilities(c3, 10_000, P)["ok"]
+    c8, st8, _ = walks.build_measure(inst.geom, inst.K, inst.x_obs, 0.0, max_steps=8, walk_end=10_000, threads=8)
+    assert np.all(c8.sum(1) == 10_000) and st8["max_steps"] == 8 and st8["cap_hits"] >= 0.99 * st8["walks"]
+    assert statutil.vs_probabilities(c8, 10_000, P)["ok"] and statutil.row_chi2(c8, 10_000, P)["ok"]
+    # a walk that stops before n is on dD to FP64 resolution: its stop point rounds onto the circle
+    _, _, S = walks.instance_setup(np.eye(2), 2)
+    pos = walks.walk_exits(inst.geom, S, inst.x_obs[0], 0.0, 2000, max_steps=200)
+    assert np.all(np.abs(np.hypot(pos[:, 0], pos[:, 1]) - 1.0) <= 4e-16)
+    # eps = 0 needs its step count
+    with pytest.raises(Exception):
+        walks.build_measure(inst.geom, inst.K, inst.x_obs, 0.0, max_steps=0, walk_end=10, threads=1)
