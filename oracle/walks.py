@@ -61,7 +61,7 @@ def make_geom(g):
         v = np.ascontiguousarray(np.asarray(g.verts, np.float64).ravel())
         s._verts = v
         s.verts = _ptr(v, C.c_double)
-        s.n_verts = len(v) // 3 if g.kind == wi.PERFORATED else len(v) // 2
+        s.n_verts = len(v) // (g.dim + 1) if g.kind in (wi.PERFORATED, wi.PERFBOX) else len(v) // 2
     return s
 
 
@@ -105,11 +105,21 @@ def element_measures(g) -> np.ndarray:
     if g.kind == wi.BALL:
         nz, nphi = g.layout
         return np.full(M, 4 * np.pi * g.params[3] ** 2 / (nz * nphi))
-    if g.kind == wi.PERFORATED:
-        mo, mh, k = g.layout[:3]
-        holes = np.asarray(g.verts, float).reshape(k, 3)
-        return np.concatenate([np.full(mo, 2 * np.pi * g.params[2] / mo)] +
-                              [np.full(mh, 2 * np.pi * r / mh) for r in holes[:, 2]])
+    if g.kind in (wi.PERFORATED, wi.PERFBOX):
+        # the outer boundary's cells, then each hole's: arcs 2 pi r / m, or sphere cells 4 pi r^2 / (nz nphi)
+        d = g.dim
+        holes = np.asarray(g.verts, float).reshape(-1, d + 1)
+        if g.kind == wi.PERFORATED:
+            R = g.params[d]
+            outer = (np.full(g.layout[0], 2 * np.pi * R / g.layout[0]) if d == 2 else
+                     np.full(g.layout[0] * g.layout[1], 4 * np.pi * R * R / (g.layout[0] * g.layout[1])))
+            hc = (g.layout[1],) if d == 2 else (g.layout[2], g.layout[3])
+        else:
+            outer = element_measures(wi.Geometry(d, wi.BOX, g.params, (g.layout[0],)))
+            hc = tuple(g.layout[1:d])
+        m = int(np.prod(hc))
+        return np.concatenate([outer] + [np.full(m, (2 * np.pi * r if d == 2 else 4 * np.pi * r * r) / m)
+                                         for r in holes[:, d]])
     if g.kind == wi.BOX:
         d, n = g.dim, g.layout[0]
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])

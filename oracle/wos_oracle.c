@@ -42,6 +42,7 @@
 #define OG_BALL 4
 #define OG_BOX 5
 #define OG_PERFORATED 6
+#define OG_PERFBOX 7
 
 #define OG_TWO_PI 6.283185307179586
 
@@ -51,8 +52,8 @@ typedef struct {
     double p[8];          /* shape parameters, see the geometry table in the docs */
     int32_t layout[4];    /* element layout */
     const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise; for the perforated
-                             disk the holes as (cx, cy, r) triples */
-    int32_t n_verts;      /* polygon vertices, or holes of the perforated disk */
+                             domains the holes as (centre, r), dim + 1 numbers each */
+    int32_t n_verts;      /* polygon vertices, or holes of a perforated domain */
 } og_geom;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -145,6 +146,38 @@ static double ellipse_lb(const og_geom *g, const double *x)
     return m * (1.0 - f);
 }
 
+/* Perforated domains: distance to the outer boundary (ball / disc, or box) and to hole l (the
+ * vector from its centre in v when v is not NULL). */
+static double outer_dist(const og_geom *g, const double *x)
+{
+    int d = g->dim;
+    if (g->kind == OG_PERFORATED) {
+        double s = 0.0;
+        for (int a = 0; a < d; ++a) s += (x[a] - g->p[a]) * (x[a] - g->p[a]);
+        return g->p[d] - sqrt(s);
+    }
+    double best = INFINITY;
+    for (int a = 0; a < d; ++a) {
+        double lo = x[a] - g->p[a], hi = g->p[d + a] - x[a];
+        if (lo < best) best = lo;
+        if (hi < best) best = hi;
+    }
+    return best;
+}
+
+static double hole_dist(const og_geom *g, int l, const double *x, double *v)
+{
+    int d = g->dim;
+    const double *h = g->verts + (d + 1) * l;
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double t = x[a] - h[a];
+        if (v) v[a] = t;
+        s += t * t;
+    }
+    return sqrt(s) - h[d];
+}
+
 double oracle_dist(const og_geom *g, const double *x)
 {
     switch (g->kind) {
@@ -185,15 +218,13 @@ double oracle_dist(const og_geom *g, const double *x)
         }
         return best;
     }
-    case OG_PERFORATED: {
-        /* outer circle |x - c0| = R0 and hole circles |x - c_l| = r_l (the paper's Example with a
-         * disc perforated by smaller discs): the nearest of the circles */
-        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
-        double best = g->p[2] - sqrt(dx * dx + dy * dy);
+    case OG_PERFORATED:
+    case OG_PERFBOX: {
+        /* a disc / ball (the paper's Examples 2-4, 6, 7) or a box (Examples 1, 5) with disjoint
+         * spherical holes |x - c_l| < r_l removed: the nearest of the outer boundary and the holes */
+        double best = outer_dist(g, x);
         for (int l = 0; l < g->n_verts; ++l) {
-            const double *h = g->verts + 3 * l;
-            double hx = x[0] - h[0], hy = x[1] - h[1];
-            double d = sqrt(hx * hx + hy * hy) - h[2];
+            double d = hole_dist(g, l, x, NULL);
             if (d < best) best = d;
         }
         return best;
@@ -214,6 +245,38 @@ static int arc_index(double theta, int M)
 {
     if (theta < 0.0) theta += OG_TWO_PI;
     return clampi((long)floor(theta * (double)M / OG_TWO_PI), M);
+}
+
+/* Equal-area cell of a direction v (any length > 0) on a sphere: band iz of the height z / |v|
+ * from the top (nz bands), sector of the azimuth (nphi sectors from angle 0). */
+static int sphere_cell(const double *v, int nz, int nphi)
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double zc = v[2] / n;
+    int iz = clampi((long)floor((1.0 - zc) * 0.5 * (double)nz), nz);
+    return iz * nphi + arc_index(atan2(v[1], v[0]), nphi);
+}
+
+/* Box: the nearest face (ties: the lowest face index), then the patch of the other coordinates. */
+static int box_cell(const og_geom *g, const double *x)
+{
+    int d = g->dim, n = g->layout[0];
+    double best = INFINITY;
+    int fb = 0;
+    for (int f = 0; f < 2 * d; ++f) {
+        int a = f / 2;
+        double df = (f % 2 == 0) ? x[a] - g->p[a] : g->p[d + a] - x[a];
+        if (df < best) { best = df; fb = f; }
+    }
+    int a = fb / 2, idx = 0;
+    for (int b = 0; b < d; ++b) {
+        if (b == a) continue;
+        double lo = g->p[b], hi = g->p[d + b];
+        int ib = clampi((long)floor((x[b] - lo) / (hi - lo) * (double)n), n);
+        idx = idx * n + ib;
+    }
+    int per_face = (d == 2) ? n : n * n;
+    return fb * per_face + idx;
 }
 
 /* Element index of the projection pi(x) of x onto dD (intrinsic Voronoi cells; ties go to the
@@ -255,48 +318,40 @@ int oracle_element(const og_geom *g, const double *x)
         return clampi((long)floor(s_at * (double)M / perim), M);
     }
     case OG_BALL: {
-        double v[3], s = 0.0;
-        for (int a = 0; a < 3; ++a) { v[a] = x[a] - g->p[a]; s += v[a] * v[a]; }
-        double n = sqrt(s);
-        int nz = g->layout[0], nphi = g->layout[1];
-        double zc = v[2] / n;
-        int iz = clampi((long)floor((1.0 - zc) * 0.5 * (double)nz), nz);
-        int ip = arc_index(atan2(v[1], v[0]), nphi);
-        return iz * nphi + ip;
+        double v[3];
+        for (int a = 0; a < 3; ++a) v[a] = x[a] - g->p[a];
+        return sphere_cell(v, g->layout[0], g->layout[1]);
     }
-    case OG_BOX: {
-        int d = g->dim, n = g->layout[0];
-        double best = INFINITY;
-        int fb = 0;
-        for (int f = 0; f < 2 * d; ++f) {
-            int a = f / 2;
-            double df = (f % 2 == 0) ? x[a] - g->p[a] : g->p[d + a] - x[a];
-            if (df < best) { best = df; fb = f; }
-        }
-        int a = fb / 2, idx = 0;
-        for (int b = 0; b < d; ++b) {
-            if (b == a) continue;
-            double lo = g->p[b], hi = g->p[d + b];
-            int ib = clampi((long)floor((x[b] - lo) / (hi - lo) * (double)n), n);
-            idx = idx * n + ib;
-        }
-        int per_face = (d == 2) ? n : n * n;
-        return fb * per_face + idx;
-    }
-    case OG_PERFORATED: {
-        /* the nearest circle (ties: the outer one, then the lowest hole), then the arc of the angle
-         * about its centre; outer arcs come first, then layout[1] arcs per hole in hole order */
-        double dx = x[0] - g->p[0], dy = x[1] - g->p[1];
-        double best = g->p[2] - sqrt(dx * dx + dy * dy), ax = dx, ay = dy;
-        int comp = -1;
+    case OG_BOX:
+        return box_cell(g, x);
+    case OG_PERFORATED:
+    case OG_PERFBOX: {
+        /* the nearest piece of the boundary (ties: the outer boundary, then the lowest hole), then
+         * the cell of the direction from the piece's centre (arcs from angle 0 in 2D, equal-area
+         * (z band, azimuth) cells in 3D).  Outer cells come first, then each hole's in hole order. */
+        int d = g->dim, comp = -1, c = 0, n_outer, hole_cells;
+        double best = outer_dist(g, x), v[3] = { 0.0, 0.0, 0.0 }, vb[3] = { 0.0, 0.0, 0.0 };
         for (int l = 0; l < g->n_verts; ++l) {
-            const double *h = g->verts + 3 * l;
-            double hx = x[0] - h[0], hy = x[1] - h[1];
-            double d = sqrt(hx * hx + hy * hy) - h[2];
-            if (d < best) { best = d; comp = l; ax = hx; ay = hy; }
+            double dl = hole_dist(g, l, x, v);
+            if (dl < best) { best = dl; comp = l; vb[0] = v[0]; vb[1] = v[1]; vb[2] = v[2]; }
         }
-        if (comp < 0) return arc_index(atan2(ay, ax), g->layout[0]);
-        return g->layout[0] + comp * g->layout[1] + arc_index(atan2(ay, ax), g->layout[1]);
+        if (g->kind == OG_PERFORATED) {
+            n_outer = d == 2 ? g->layout[0] : g->layout[0] * g->layout[1];
+            hole_cells = d == 2 ? g->layout[1] : g->layout[2] * g->layout[3];
+            if (comp < 0) {
+                double w[3] = { 0.0, 0.0, 0.0 };
+                for (int a = 0; a < d; ++a) w[a] = x[a] - g->p[a];
+                return d == 2 ? arc_index(atan2(w[1], w[0]), g->layout[0])
+                              : sphere_cell(w, g->layout[0], g->layout[1]);
+            }
+            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1]) : sphere_cell(vb, g->layout[2], g->layout[3]);
+        } else {
+            n_outer = d == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
+            hole_cells = d == 2 ? g->layout[1] : g->layout[1] * g->layout[2];
+            if (comp < 0) return box_cell(g, x);
+            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1]) : sphere_cell(vb, g->layout[1], g->layout[2]);
+        }
+        return n_outer + comp * hole_cells + c;
     }
     }
     return -1;

@@ -9,6 +9,7 @@ import os
 import numpy as np
 import pytest
 from scipy import integrate, stats
+from scipy.spatial import cKDTree
 
 import wos_inputs as wi
 from oracle import closed_forms as cf
@@ -82,6 +83,28 @@ def _boundary_samples(g, n):
         pi_ = np.stack([np.cos(t), np.sin(t)], 1) * g.params[2]
         return (np.concatenate([po, pi_]),
                 np.concatenate([(t * mo / (2 * np.pi)).astype(int), mo + (t * mi / (2 * np.pi)).astype(int)]))
+    if g.kind in (wi.PERFORATED, wi.PERFBOX) and (g.dim == 3 or g.kind == wi.PERFBOX):
+        # outer boundary, then each hole (circles: arcs from angle 0; spheres: (z band, azimuth) cells)
+        d = g.dim
+        holes = np.asarray(g.verts, float).reshape(-1, d + 1)
+        if g.kind == wi.PERFORATED:
+            pts, el = _sphere_samples(g.params[:3], g.params[3], g.layout[0], g.layout[1], n)
+            hc = (g.layout[2], g.layout[3])
+        else:
+            pts, el = _boundary_samples(wi.Geometry(d, wi.BOX, g.params, (g.layout[0],)), n)
+            hc = tuple(g.layout[1:d])
+        off, P, E = len(set(el.tolist())), [pts], [el]
+        for h in holes:
+            if d == 2:
+                t = (np.arange(n) + 0.5) * 2 * np.pi / n
+                P.append(np.stack([h[0] + h[2] * np.cos(t), h[1] + h[2] * np.sin(t)], 1))
+                E.append(off + (t * hc[0] / (2 * np.pi)).astype(int))
+            else:
+                q, c = _sphere_samples(h[:3], h[3], hc[0], hc[1], n)
+                P.append(q)
+                E.append(off + c)
+            off += int(np.prod(hc))
+        return np.concatenate(P), np.concatenate(E)
     if g.kind == wi.PERFORATED:
         mo, mh, k = g.layout[:3]
         t = (np.arange(n) + 0.5) * 2 * np.pi / n
@@ -101,6 +124,7 @@ def _boundary_samples(g, n):
         return p, (s * M / cum[-1]).astype(int)
     if g.kind == wi.BOX:
         d, nn = g.dim, g.layout[0]
+        lo, hi = np.array(g.params[:d], float), np.array(g.params[d:2 * d], float)
         m = int(round(n ** (1.0 / (d - 1))))
         pts, el = [], []
         for f in range(2 * d):
@@ -108,32 +132,46 @@ def _boundary_samples(g, n):
             others = [b for b in range(d) if b != a]
             grid = np.stack(np.meshgrid(*[(np.arange(m) + 0.5) / m] * (d - 1), indexing="ij"), -1).reshape(-1, d - 1)
             p = np.zeros((grid.shape[0], d))
-            p[:, a] = float(side)
+            p[:, a] = hi[a] if side else lo[a]
             idx = np.zeros(grid.shape[0], int)
             for c, b in enumerate(others):
-                p[:, b] = grid[:, c]
+                p[:, b] = lo[b] + grid[:, c] * (hi[b] - lo[b])
                 idx = idx * nn + (grid[:, c] * nn).astype(int)
             pts.append(p)
             el.append(f * nn ** (d - 1) + idx)
         return np.concatenate(pts), np.concatenate(el)
     if g.kind == wi.BALL:
-        nz, nphi = g.layout
-        m = int(np.sqrt(n))
-        z = 1 - 2 * (np.arange(m) + 0.5) / m
-        ph = (np.arange(2 * m) + 0.5) * np.pi / m
-        Z, P = np.meshgrid(z, ph, indexing="ij")
-        r = np.sqrt(1 - Z ** 2)
-        p = np.stack([r * np.cos(P), r * np.sin(P), Z], -1).reshape(-1, 3)
-        iz = ((1 - Z) / 2 * nz).astype(int).ravel()
-        ip = (P * nphi / (2 * np.pi)).astype(int).ravel()
-        return p, iz * nphi + ip
+        return _sphere_samples(g.params[:3], g.params[3], g.layout[0], g.layout[1], n)
     raise ValueError(g.kind)
 
 
-@pytest.mark.parametrize("case", ["disk", "annulus", "lshape", "square", "cube", "ball", "perforated"])
+def _sphere_samples(c, R, nz, nphi, n):
+    """About n points of a (z, azimuth) grid on the sphere |x - c| = R and their equal-area cells."""
+    m = int(np.sqrt(n))
+    z = 1 - 2 * (np.arange(m) + 0.5) / m
+    ph = (np.arange(2 * m) + 0.5) * np.pi / m
+    Z, P = np.meshgrid(z, ph, indexing="ij")
+    r = np.sqrt(1 - Z ** 2)
+    p = np.stack([r * np.cos(P), r * np.sin(P), Z], -1).reshape(-1, 3) * R + np.asarray(c, float)
+    iz = ((1 - Z) / 2 * nz).astype(int).ravel()
+    ip = (P * nphi / (2 * np.pi)).astype(int).ravel()
+    return p, iz * nphi + ip
+
+
+@pytest.mark.parametrize("case", ["disk", "annulus", "lshape", "square", "cube", "ball", "perforated",
+                                  "perforated_ball", "square_with_holes", "cube_with_hole"])
 def test_distance_and_element_vs_brute_force(case):
     rng = np.random.default_rng(1)
-    if case == "perforated":
+    if case == "perforated_ball":
+        holes = np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]])
+        g = wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (6, 11, 4, 7), verts=holes)
+    elif case == "square_with_holes":
+        holes = np.array([[0.5, 0.0, 0.2], [-0.4, 0.45, 0.3]])
+        g = wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.2), (13, 11), verts=holes)
+    elif case == "cube_with_hole":
+        g = wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (5, 4, 6),
+                        verts=np.array([[0.55, 0.45, 0.5, 0.3]]))
+    elif case == "perforated":
         holes = np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])
         g = wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (41, 17, 3), verts=holes)
     elif case == "disk":
@@ -149,18 +187,19 @@ def test_distance_and_element_vs_brute_force(case):
     else:
         g = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (6, 11))
     bp, be = _boundary_samples(g, 400_000 if g.dim == 2 else 360_000)
-    if case == "perforated":  # the same angular density on every circle: coarser on the smaller ones
+    if case in ("perforated", "square_with_holes"):  # the same angular density on every circle
         bp, be = _boundary_samples(g, 1_600_000)
-    pts = wi.sample_points(g, 100 if case == "perforated" else 300, rng)
+    pts = wi.sample_points(g, 100 if case in ("perforated", "square_with_holes") else 300, rng)
     d, e = walks.geom_eval(g, pts)
     spacing = 2e-5 if g.dim == 2 else 6e-3
+    tree = cKDTree(bp)  # exact nearest-neighbour search over the boundary samples
+    dmin, jmin = tree.query(pts)
     for k in range(len(pts)):
-        dd = np.sqrt(((bp - pts[k]) ** 2).sum(1))
-        j = int(np.argmin(dd))
-        assert abs(d[k] - dd[j]) <= spacing, (k, d[k], dd[j])
+        j = int(jmin[k])
+        assert abs(d[k] - dmin[k]) <= spacing, (k, d[k], dmin[k])
         # the element of the nearest boundary sample, unless the point is close to a cell edge
         # or equidistant between two parts of the boundary
-        near = be[dd <= dd[j] + 2 * spacing]
+        near = be[tree.query_ball_point(pts[k], dmin[k] + 2 * spacing)]
         assert e[k] in set(near.tolist()) or len(set(near.tolist())) > 1, (k, e[k], be[j])
         assert e[k] == be[j] or len(set(near.tolist())) > 1
 
@@ -482,3 +521,50 @@ def test_fixed_iteration_walk():
     # eps = 0 needs its step count
     with pytest.raises(Exception):
         walks.build_measure(inst.geom, inst.K, inst.x_obs, 0.0, max_steps=0, walk_end=10, threads=1)
+
+
+def test_concentric_spherical_shell_inner_mass():
+    """Examples 6 and 7 of Section 5.3 are balls with a ball removed.  For the concentric shell
+    R_1 < |x| < R_0 the harmonic measure of the inner sphere seen from radius rho is the Newtonian
+    ratio (1/rho - 1/R_0) / (1/R_1 - 1/R_0) (the radial harmonic function with boundary values 1, 0),
+    whatever the direction."""
+    g = wi.spherical_shell_example(6).geom
+    rng = np.random.default_rng(5)
+    dirs = rng.standard_normal((6, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    rho = np.array([0.55, 0.6, 0.7, 0.8, 0.9, 0.95])
+    x = dirs * rho[:, None]
+    N = 20_000
+    counts, st, _ = walks.build_measure(g, np.eye(3), x, 1e-6, seed=9, walk_end=N, threads=8)
+    inner = counts[:, g.gamma1_mask == 1].sum(1) / N
+    p = (1 / rho - 1.0) / (1 / 0.5 - 1.0)
+    assert np.all(np.abs(inner - p) < 4.5 * np.sqrt(p * (1 - p) / N) + 1e-5), (inner, p)
+    assert st["escapes"] == 0 and st["cap_hits"] == 0
+
+
+def test_perforated_domains_reproduce_paper_solutions():
+    """Harmonic functions from the stop points, E u(X_N) = u(x) within the Monte Carlo error and the
+    O(eps) bias: 3D-sol1 and 3D-sol2 = 1/|x| (harmonic in D: the origin lies inside the removed ball)
+    on the eccentric shell of Example 7; 2D-sol2 and 2D-sol3 on the square with a hole of Examples 1
+    and 5."""
+    _, _, S3 = walks.instance_setup(np.eye(3), 3)
+    g = wi.spherical_shell_example(7).geom
+    x = wi.sample_points(g, 5, np.random.default_rng(13), margin=0.02)
+    sol1 = lambda p: p[:, 0] * p[:, 1] + p[:, 1] ** 2 - p[:, 2] ** 2
+    sol2 = lambda p: 1.0 / np.sqrt((p ** 2).sum(1))
+    assert np.all(_exit_mean_z(g, S3, x, sol1, 20_000, grad_bound=3.0) < 4.5)
+    assert np.all(_exit_mean_z(g, S3, x, sol2, 20_000, grad_bound=25.0) < 4.5)
+    _, _, S2 = walks.instance_setup(np.eye(2), 2)
+    g = wi.square_hole_example(1).geom
+    x = wi.sample_points(g, 5, np.random.default_rng(14), margin=0.02)
+    sol2d = lambda p: -p[:, 0] ** 3 / 3 - p[:, 0] ** 2 * p[:, 1] + p[:, 0] * p[:, 1] ** 2 + p[:, 1] ** 3 / 3
+    sol3d = lambda p: p[:, 0] ** 2 - p[:, 1] ** 2
+    assert np.all(_exit_mean_z(g, S2, x, sol2d, 20_000, grad_bound=5.0) < 4.5)
+    assert np.all(_exit_mean_z(g, S2, x, sol3d, 20_000, grad_bound=3.0) < 4.5)
+    # log |x - c| (c the hole's centre) is harmonic in D but not in the square: reproduced by the
+    # walks of D, visibly not by a planted slip that leaves the hole out of the distance
+    logc = lambda p: 0.5 * np.log((p[:, 0] - 0.5) ** 2 + p[:, 1] ** 2)
+    xh = np.array([[0.5, 0.25], [0.75, 0.05], [0.28, -0.05]])
+    assert np.all(_exit_mean_z(g, S2, xh, logc, 20_000, grad_bound=5.0) < 4.5)
+    g_nohole = wi.Geometry(2, wi.BOX, g.params, (g.layout[0],))
+    assert _exit_mean_z(g_nohole, S2, xh, logc, 20_000, grad_bound=5.0).max() > 8

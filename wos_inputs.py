@@ -14,9 +14,14 @@ Geometry kinds (codes shared by the C ABI and the oracle):
   POLYGON  verts  (n, 2), one counter-clockwise loop  layout (M,)         equal pieces of perimeter
   BALL     params (cx, cy, cz, R)                  layout (n_z, n_phi)    equal-area (z, phi) cells
   BOX      params (lo_0..lo_{d-1}, hi_0..hi_{d-1}) layout (n,)            n^(d-1) patches per face
-  PERFORATED params (cx, cy, R) of the outer disc, verts (k, 3) rows (cx, cy, r) of the holes
-           layout (M_out, M_hole, k)   outer arcs first, then M_hole arcs per hole in hole order, all
-           counter-clockwise from angle 0 about their own centre
+  PERFORATED a disc / ball with k disjoint round holes.  params (centre, R) of the outer disc or
+           ball, verts (k, dim + 1) rows (centre, r) of the holes.  2D layout (M_out, M_hole, k):
+           outer arcs first, then M_hole arcs per hole in hole order, all counter-clockwise from
+           angle 0 about their own centre.  3D layout (nz_out, nphi_out, nz_hole, nphi_hole), k the
+           number of verts rows: equal-area (z, phi) cells of the outer sphere, then of each hole
+  PERFBOX  a box with k disjoint round holes.  params (lo, hi) as BOX, verts as PERFORATED.
+           2D layout (n, M_hole), 3D layout (n, nz_hole, nphi_hole): the box's face patches
+           first, then each hole's cells as above
 
 The paper's problem statement (Section 1.1, the discrete inverse problem with interior data) fixes
 what an instance holds: the domain D, its boundary split into an accessible part Gamma_0 and an
@@ -30,9 +35,9 @@ from typing import Optional
 
 import numpy as np
 
-DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX, PERFORATED = 0, 1, 2, 3, 4, 5, 6
+DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX, PERFORATED, PERFBOX = 0, 1, 2, 3, 4, 5, 6, 7
 KIND_NAMES = {DISK: "disk", ANNULUS: "annulus", ELLIPSE: "ellipse", POLYGON: "polygon",
-              BALL: "ball", BOX: "box", PERFORATED: "perforated"}
+              BALL: "ball", BOX: "box", PERFORATED: "perforated", PERFBOX: "perforated box"}
 
 FP64 = 0
 FP32_GEOM_FP64_EXIT = 1
@@ -50,8 +55,12 @@ class Geometry:
     gamma1_mask: Optional[np.ndarray] = None  # uint8, length n_elem, 1 = Gamma_1
 
     @property
+    def n_holes(self) -> int:
+        return 0 if self.verts is None else int(np.asarray(self.verts).size // (self.dim + 1))
+
+    @property
     def n_elem(self) -> int:
-        return element_count(self.dim, self.kind, self.layout)
+        return element_count(self.dim, self.kind, self.layout, self.n_holes)
 
 
 @dataclasses.dataclass
@@ -74,7 +83,7 @@ class Instance:
     noise_delta: float = 0.0          # expected norm of nu * noise(b), for the discrepancy principle
 
 
-def element_count(dim: int, kind: int, layout) -> int:
+def element_count(dim: int, kind: int, layout, n_holes: int = 0) -> int:
     layout = tuple(int(v) for v in layout)
     if kind in (DISK, ELLIPSE, POLYGON):
         return layout[0]
@@ -85,8 +94,36 @@ def element_count(dim: int, kind: int, layout) -> int:
     if kind == BOX:
         return 2 * dim * layout[0] ** (dim - 1)
     if kind == PERFORATED:
-        return layout[0] + layout[1] * layout[2]
+        if dim == 2:
+            return layout[0] + layout[1] * layout[2]
+        return layout[0] * layout[1] + n_holes * layout[2] * layout[3]
+    if kind == PERFBOX:
+        if dim == 2:
+            return 4 * layout[0] + n_holes * layout[1]
+        return 6 * layout[0] ** 2 + n_holes * layout[1] * layout[2]
     raise ValueError(f"unknown geometry kind {kind}")
+
+
+def _sphere_cell_centres(c, R, nz, nphi):
+    iz, ip = np.meshgrid(np.arange(nz), np.arange(nphi), indexing="ij")
+    z = 1 - 2 * (iz.ravel() + 0.5) / nz
+    ph = (ip.ravel() + 0.5) * 2 * np.pi / nphi
+    rr = np.sqrt(1 - z * z)
+    return np.stack([c[0] + R * rr * np.cos(ph), c[1] + R * rr * np.sin(ph), c[2] + R * z], 1)
+
+
+def _circle_arc_centres(c, R, m):
+    t = (np.arange(m) + 0.5) * 2 * np.pi / m
+    return np.stack([c[0] + R * np.cos(t), c[1] + R * np.sin(t)], 1)
+
+
+def _hole_ref_points(g: "Geometry", cells) -> list:
+    d = g.dim
+    out = []
+    for h in np.asarray(g.verts, float).reshape(-1, d + 1):
+        out.append(_circle_arc_centres(h[:2], h[2], cells[0]) if d == 2
+                   else _sphere_cell_centres(h[:3], h[3], cells[0], cells[1]))
+    return out
 
 
 # --------------------------------------------------------------------------------------------
@@ -112,13 +149,14 @@ def element_ref_points(g: Geometry) -> np.ndarray:
         t = (np.arange(M) + 0.5) * 2 * np.pi / M
         return np.stack([cx + a * np.cos(t), cy + b * np.sin(t)], 1)
     if g.kind == PERFORATED:
-        cx, cy, R = g.params[:3]
-        mo, mh, k = g.layout[:3]
-        pts = []
-        for (hx, hy, r), m in [((cx, cy, R), mo)] + [(tuple(h), mh) for h in np.asarray(g.verts, float).reshape(k, 3)]:
-            t = (np.arange(m) + 0.5) * 2 * np.pi / m
-            pts.append(np.stack([hx + r * np.cos(t), hy + r * np.sin(t)], 1))
-        return np.concatenate(pts, 0)
+        if g.dim == 2:
+            outer = _circle_arc_centres(g.params[:2], g.params[2], g.layout[0])
+            return np.concatenate([outer] + _hole_ref_points(g, (g.layout[1],)), 0)
+        outer = _sphere_cell_centres(g.params[:3], g.params[3], g.layout[0], g.layout[1])
+        return np.concatenate([outer] + _hole_ref_points(g, (g.layout[2], g.layout[3])), 0)
+    if g.kind == PERFBOX:
+        box = element_ref_points(Geometry(g.dim, BOX, g.params, (g.layout[0],)))
+        return np.concatenate([box] + _hole_ref_points(g, tuple(g.layout[1:])), 0)
     if g.kind == POLYGON:
         v = np.asarray(g.verts, float)
         seg = np.roll(v, -1, 0) - v
@@ -250,6 +288,80 @@ def perforated_disk_example(n_walks: int = 10_000, n_obs: int = 100, eps: float 
     return inst
 
 
+def _with_data(inst: Instance, u) -> Instance:
+    ref = element_ref_points(inst.geom)
+    m = inst.geom.gamma1_mask
+    inst.uD = u(inst.x_obs)
+    inst.u0 = u(ref[m == 0])
+    inst.u_exact_g1 = u(ref[m == 1])
+    return inst
+
+
+def bauer_spiral(n: int) -> np.ndarray:
+    """n nearly uniform unit vectors on Bauer's spiral (Bauer 2000): z_i = 1 - (2i - 1)/n,
+    azimuth sqrt(n pi) asin(z_i), i = 1..n."""
+    i = np.arange(1, n + 1)
+    z = 1.0 - (2.0 * i - 1.0) / n
+    ph = np.sqrt(n * np.pi) * np.arcsin(z)
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z], 1)
+
+
+def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: float = 1e-7,
+                        precision: int = FP64, m_face: int = 100, m_hole: int = 50,
+                        n_obs: int = 40) -> Instance:
+    """The paper's Examples 1 and 5 (Section 5.2): D = (-1, 1)^2 minus the disc of radius 0.2 about
+    (0.5, 0), K = I, M_0 + M_1 = 4 m_face + m_hole cells (the paper: 400 + 50).
+    Example 1: Gamma_0 the square, Gamma_1 the hole circle; the points equally spaced by perimeter
+    on Gamma_D = {dist(x, Gamma_0) = 0.05}, the square of half side 0.95, counter-clockwise from
+    (0.95, -0.95 + h/2), h the spacing; eps = 1e-7 in the paper.
+    Example 5: Gamma_0 empty, Gamma_1 the whole boundary; the points equally spaced on the circle
+    of radius 0.3 about (-0.5, 0.5); eps = 1e-10 in the paper.
+    Data: 2D-sol2, u = -x1^3/3 - x1^2 x2 + x1 x2^2 + x2^3/3 (harmonic), without noise."""
+    g = Geometry(2, PERFBOX, (-1.0, -1.0, 1.0, 1.0), (m_face, m_hole), verts=np.array([[0.5, 0.0, 0.2]]))
+    M0 = 4 * m_face
+    if example == 1:
+        g.gamma1_mask = (np.arange(g.n_elem) >= M0).astype(np.uint8)
+        a, L = 0.95, 8 * 0.95
+        s = (np.arange(n_obs) + 0.5) * L / n_obs
+        side, t = np.floor_divide(s, 2 * a).astype(int), np.mod(s, 2 * a) - a
+        x = np.empty((n_obs, 2))
+        for k, (cx, cy) in enumerate([(a, None), (None, a), (-a, None), (None, -a)]):
+            on = side == k
+            if cx is not None:
+                x[on] = np.stack([np.full(on.sum(), cx), t[on] if k == 0 else -t[on]], 1)
+            else:
+                x[on] = np.stack([-t[on] if k == 1 else t[on], np.full(on.sum(), cy)], 1)
+    elif example == 5:
+        g.gamma1_mask = np.ones(g.n_elem, np.uint8)
+        t = 2 * np.pi * np.arange(n_obs) / n_obs
+        x = np.stack([-0.5 + 0.3 * np.cos(t), 0.5 + 0.3 * np.sin(t)], 1)
+    else:
+        raise ValueError(example)
+    inst = Instance(g, np.eye(2), x, n_walks, eps=eps, seed=1, precision=precision,
+                    name=f"square_with_hole_example{example}")
+    return _with_data(inst, lambda p: (-p[:, 0] ** 3 / 3 - p[:, 0] ** 2 * p[:, 1] + p[:, 0] * p[:, 1] ** 2
+                                       + p[:, 1] ** 3 / 3))
+
+
+def spherical_shell_example(example: int = 6, n_walks: int = 10_000, eps: float = 1e-10,
+                            precision: int = FP64, outer=(25, 40), inner=(10, 10),
+                            n_obs: int = 100) -> Instance:
+    """The paper's Examples 6 and 7 (Section 5.3): the unit ball minus the ball of radius 0.5 about
+    the origin (Example 6) or about (0.3, 0, 0) (Example 7), K = I; Gamma_0 the outer sphere
+    (M_0 = 25 x 40 = 1000 equal-area cells), Gamma_1 the inner sphere (M_1 = 10 x 10 = 100); the
+    points on Bauer's spiral on Gamma_D = {dist(x, Gamma_0) = 0.05}, the sphere of radius 0.95.
+    Data: 3D-sol1, u = x1 x2 + x2^2 - x3^2 (harmonic), without noise."""
+    c = {6: (0.0, 0.0, 0.0), 7: (0.3, 0.0, 0.0)}[example]
+    g = Geometry(3, PERFORATED, (0.0, 0.0, 0.0, 1.0), tuple(outer) + tuple(inner),
+                 verts=np.array([[c[0], c[1], c[2], 0.5]]))
+    g.gamma1_mask = (np.arange(g.n_elem) >= outer[0] * outer[1]).astype(np.uint8)
+    x = 0.95 * bauer_spiral(n_obs)
+    inst = Instance(g, np.eye(3), x, n_walks, eps=eps, seed=2, precision=precision,
+                    name=f"spherical_shell_example{example}")
+    return _with_data(inst, lambda p: p[:, 0] * p[:, 1] + p[:, 1] ** 2 - p[:, 2] ** 2)
+
+
 def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP32_GEOM_FP64_EXIT,
                  eta: float = 0.01) -> Instance:
     """2D annulus r in [0.3, 1], K = [[1, .5], [.5, 2]], 128 + 128 arcs, 1024 points uniform by area.
@@ -335,17 +447,25 @@ def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
         d = g.dim
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])
         return np.all((p > lo) & (p < hi), 1)
-    if g.kind == PERFORATED:
-        cx, cy, R = g.params[:3]
-        ok = (p[:, 0] - cx) ** 2 + (p[:, 1] - cy) ** 2 < R * R
-        for hx, hy, r in np.asarray(g.verts, float).reshape(-1, 3):
-            ok &= (p[:, 0] - hx) ** 2 + (p[:, 1] - hy) ** 2 > r * r
+    if g.kind in (PERFORATED, PERFBOX):
+        d = g.dim
+        if g.kind == PERFORATED:
+            ok = ((p - np.array(g.params[:d])) ** 2).sum(1) < g.params[d] ** 2
+        else:
+            ok = np.all((p > np.array(g.params[:d])) & (p < np.array(g.params[d:2 * d])), 1)
+        for h in np.asarray(g.verts, float).reshape(-1, d + 1):
+            ok &= ((p - h[:d]) ** 2).sum(1) > h[d] ** 2
         return ok
     raise ValueError(g.kind)
 
 
 def _bbox(g: Geometry):
-    if g.kind in (DISK, PERFORATED):
+    if g.kind == PERFORATED:
+        c, R = np.array(g.params[:g.dim]), g.params[g.dim]
+        return c - R, c + R
+    if g.kind == PERFBOX:
+        return np.array(g.params[:g.dim]), np.array(g.params[g.dim:2 * g.dim])
+    if g.kind == DISK:
         cx, cy, R = g.params[:3]
         return np.array([cx - R, cy - R]), np.array([cx + R, cy + R])
     if g.kind == ANNULUS:
