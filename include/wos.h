@@ -89,17 +89,23 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *   WOS_BOX      dim 2 or 3, params (lo_0..lo_{d-1}, hi_0..hi_{d-1}), layout (n): faces in the
  *                order (x=lo, x=hi, y=lo, y=hi[, z=lo, z=hi]), n^(d-1) patches each, patch
  *                indices along the remaining axes in increasing axis order; j = f n^(d-1) + idx.
- *   WOS_PERFORATED dim 2, params (cx, cy, R) of the outer disc, verts = k holes as (cx, cy, r)
- *                triples (host, n_verts = k), layout (M_out, M_hole, k): the multiply connected disc
- *                of the paper's Example 4.  Cells: M_out arcs of the outer circle, then M_hole arcs
- *                of each hole in hole order, all counter-clockwise from angle 0 about their own
- *                centre; a point goes to the nearest circle (ties: the outer one, then the lowest
- *                hole).  Holes must lie inside the outer disc and must not overlap.
+ *   WOS_PERFORATED a disc or ball with k disjoint round holes (the paper's Examples 2-4, 6, 7).
+ *                params (centre, R) of the outer disc / ball; verts = k holes as (centre, r)
+ *                records of dim + 1 numbers (host, n_verts = k).  dim 2: layout (M_out, M_hole, k):
+ *                M_out arcs of the outer circle, then M_hole arcs of each hole in hole order, all
+ *                counter-clockwise from angle 0 about their own centre.  dim 3: layout (n_z, n_phi,
+ *                n_z hole, n_phi hole): the outer sphere's equal-area cells as for WOS_BALL, then
+ *                each hole sphere's, about its own centre.  A point goes to the nearest piece
+ *                (ties: the outer one, then the lowest hole).  Holes must lie strictly inside the
+ *                outer boundary and must not overlap.
+ *   WOS_PERFBOX  a box with k disjoint round holes (the paper's Examples 1 and 5).  params and
+ *                face patches as WOS_BOX, holes as for WOS_PERFORATED; layout (n, M_hole) in 2D,
+ *                (n, n_z hole, n_phi hole) in 3D: the box's patches first, then each hole's cells.
  * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
  * weights of the paper's appendix, Ex. A.3); ties go to the lowest face/segment index. */
 typedef enum {
     WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5,
-    WOS_PERFORATED = 6
+    WOS_PERFORATED = 6, WOS_PERFBOX = 7
 } wos_geom_kind;
 
 typedef struct {
@@ -107,8 +113,8 @@ typedef struct {
     int32_t kind;         /* wos_geom_kind */
     double params[8];
     int32_t layout[4];
-    const double *verts;  /* host; polygon vertices or perforated-disc holes (copied during the call) */
-    int32_t n_verts;      /* polygon: 3..WOS_MAX_POLY_VERTS vertices; perforated disc: holes */
+    const double *verts;  /* host; polygon vertices or the holes of a perforated domain (copied during the call) */
+    int32_t n_verts;      /* polygon: 3..WOS_MAX_POLY_VERTS vertices; perforated domains: holes */
 } wos_geometry;
 
 #define WOS_MAX_POLY_VERTS 64

@@ -128,9 +128,48 @@ static int elements_of(const wos_geometry *g)
     case WOS_ANNULUS: return g->layout[0] + g->layout[1];
     case WOS_BALL: return g->layout[0] * g->layout[1];
     case WOS_BOX: return g->dim == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
-    case WOS_PERFORATED: return g->layout[0] + g->layout[1] * g->layout[2];
+    case WOS_PERFORATED:
+        if (g->dim == 2) return g->layout[0] + g->layout[1] * g->layout[2];
+        return g->layout[0] * g->layout[1] + g->n_verts * g->layout[2] * g->layout[3];
+    case WOS_PERFBOX:
+        if (g->dim == 2) return 4 * g->layout[0] + g->n_verts * g->layout[1];
+        return 6 * g->layout[0] * g->layout[0] + g->n_verts * g->layout[1] * g->layout[2];
     }
     return -1;
+}
+
+// Holes of a perforated domain: k disjoint balls (centre, r), dim + 1 numbers each, strictly inside
+// the outer disc / ball (outer = true) or box.
+static wos_status validate_holes(const wos_geometry *g, int k)
+{
+    const int d = g->dim, st = d + 1;
+    const double *p = g->params;
+    if (k < 1 || k > WOS_MAX_HOLES) return set_error(WOS_EINVAL, "a perforated domain needs 1..%d holes", WOS_MAX_HOLES);
+    if (!g->verts || g->n_verts != k)
+        return set_error(WOS_EINVAL, "a perforated domain needs verts = %d (centre, r) records of %d numbers", k, st);
+    auto dist = [d](const double *a, const double *b) {
+        double s = 0.0;
+        for (int c = 0; c < d; ++c) s += (a[c] - b[c]) * (a[c] - b[c]);
+        return std::sqrt(s);
+    };
+    for (int l = 0; l < k; ++l) {
+        const double *h = g->verts + st * l;
+        for (int c = 0; c <= d; ++c)
+            if (!std::isfinite(h[c])) return set_error(WOS_EINVAL, "hole %d is not finite", l);
+        if (!(h[d] > 0)) return set_error(WOS_EINVAL, "hole %d needs r > 0", l);
+        bool inside = true;
+        if (g->kind == WOS_PERFORATED) {
+            inside = dist(h, p) + h[d] < p[d];
+        } else {
+            for (int c = 0; c < d; ++c) inside = inside && h[c] - h[d] > p[c] && h[c] + h[d] < p[d + c];
+        }
+        if (!inside) return set_error(WOS_EINVAL, "hole %d is not strictly inside the outer boundary", l);
+        for (int m = 0; m < l; ++m) {
+            const double *o = g->verts + st * m;
+            if (!(dist(h, o) > h[d] + o[d])) return set_error(WOS_EINVAL, "holes %d and %d overlap", m, l);
+        }
+    }
+    return WOS_OK;
 }
 
 wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
@@ -175,23 +214,24 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
             if (!(p[g->dim + a] > p[a])) return set_error(WOS_EINVAL, "box needs lo < hi on every axis");
         break;
     case WOS_PERFORATED: {
-        if (g->dim != 2 || !(p[2] > 0)) return set_error(WOS_EINVAL, "perforated disc needs dim 2 and R > 0");
-        const int k = g->layout[2];
-        if (g->layout[1] < 1 || k < 1 || k > WOS_MAX_HOLES)
-            return set_error(WOS_EINVAL, "perforated disc needs layout (M_out >= 1, M_hole >= 1, 1..%d holes)", WOS_MAX_HOLES);
-        if (!g->verts || g->n_verts != k) return set_error(WOS_EINVAL, "perforated disc needs verts = %d (cx, cy, r) triples", k);
-        for (int l = 0; l < k; ++l) {
-            const double *h = g->verts + 3 * l;
-            if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !(h[2] > 0) || !std::isfinite(h[2]))
-                return set_error(WOS_EINVAL, "hole %d needs a finite centre and r > 0", l);
-            if (!(std::hypot(h[0] - p[0], h[1] - p[1]) + h[2] < p[2]))
-                return set_error(WOS_EINVAL, "hole %d is not inside the outer disc", l);
-            for (int m = 0; m < l; ++m) {
-                const double *o = g->verts + 3 * m;
-                if (!(std::hypot(h[0] - o[0], h[1] - o[1]) > h[2] + o[2]))
-                    return set_error(WOS_EINVAL, "holes %d and %d overlap", m, l);
-            }
-        }
+        if ((g->dim != 2 && g->dim != 3) || !(p[g->dim] > 0))
+            return set_error(WOS_EINVAL, "perforated disc / ball needs dim 2 or 3 and R > 0");
+        if (g->dim == 2 && (g->layout[1] < 1 || g->layout[2] < 1))
+            return set_error(WOS_EINVAL, "perforated disc needs layout (M_out >= 1, M_hole >= 1, holes >= 1)");
+        if (g->dim == 3 && (g->layout[1] < 1 || g->layout[2] < 1 || g->layout[3] < 1))
+            return set_error(WOS_EINVAL, "perforated ball needs layout (n_z, n_phi, n_z hole, n_phi hole), all >= 1");
+        const wos_status st = validate_holes(g, g->dim == 2 ? g->layout[2] : g->n_verts);
+        if (st != WOS_OK) return st;
+        break;
+    }
+    case WOS_PERFBOX: {
+        if (g->dim != 2 && g->dim != 3) return set_error(WOS_EINVAL, "perforated box needs dim 2 or 3");
+        for (int a = 0; a < g->dim; ++a)
+            if (!(p[g->dim + a] > p[a])) return set_error(WOS_EINVAL, "perforated box needs lo < hi on every axis");
+        if (g->layout[1] < 1 || (g->dim == 3 && g->layout[2] < 1))
+            return set_error(WOS_EINVAL, "perforated box needs layout (n, M_hole) or (n, n_z hole, n_phi hole), all >= 1");
+        const wos_status st = validate_holes(g, g->n_verts);
+        if (st != WOS_OK) return st;
         break;
     }
     default:
@@ -280,11 +320,32 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
     case WOS_BALL:
         for (int j = 0; j < M; ++j) sigma[j] = 4.0 * M_PI * p[3] * p[3] / M;
         break;
-    case WOS_PERFORATED: {
-        const int mo = g->layout[0], mh = g->layout[1];
-        for (int j = 0; j < mo; ++j) sigma[j] = 2.0 * M_PI * p[2] / mo;
-        for (int l = 0; l < g->layout[2]; ++l)
-            for (int j = 0; j < mh; ++j) sigma[mo + l * mh + j] = 2.0 * M_PI * g->verts[3 * l + 2] / mh;
+    case WOS_PERFORATED: case WOS_PERFBOX: {
+        // outer cells (arcs / equal-area sphere cells of the disc or ball, or box patches), then the
+        // cells of each hole: 2 pi r / m arcs or 4 pi r^2 / (n_z n_phi) sphere cells
+        const int d = g->dim;
+        int n_out = 0, hc = 0;
+        if (g->kind == WOS_PERFORATED) {
+            n_out = d == 2 ? g->layout[0] : g->layout[0] * g->layout[1];
+            const double R = p[d], a = d == 2 ? 2.0 * M_PI * R : 4.0 * M_PI * R * R;
+            for (int j = 0; j < n_out; ++j) sigma[j] = a / n_out;
+            hc = d == 2 ? g->layout[1] : g->layout[2] * g->layout[3];
+        } else {
+            const int n = g->layout[0], per_face = d == 2 ? n : n * n;
+            for (int f = 0; f < 2 * d; ++f) {
+                double area = 1.0;
+                for (int b = 0; b < d; ++b)
+                    if (b != f / 2) area *= (p[d + b] - p[b]) / n;
+                for (int j = 0; j < per_face; ++j) sigma[f * per_face + j] = area;
+            }
+            n_out = 2 * d * per_face;
+            hc = d == 2 ? g->layout[1] : g->layout[1] * g->layout[2];
+        }
+        const int k = (M - n_out) / hc;
+        for (int l = 0; l < k; ++l) {
+            const double r = g->verts[(d + 1) * l + d], a = d == 2 ? 2.0 * M_PI * r : 4.0 * M_PI * r * r;
+            for (int j = 0; j < hc; ++j) sigma[n_out + l * hc + j] = a / hc;
+        }
         break;
     }
     case WOS_BOX: {
@@ -392,14 +453,18 @@ static double domain_scale(const wos_geometry *g)
     const double *p = g->params;
     double s = 0.0;
     switch (g->kind) {
-    case WOS_DISK: case WOS_PERFORATED: s = std::fabs(p[0]) + std::fabs(p[1]) + p[2]; break;
+    case WOS_DISK: s = std::fabs(p[0]) + std::fabs(p[1]) + p[2]; break;
+    case WOS_PERFORATED:
+        for (int a = 0; a < g->dim; ++a) s += std::fabs(p[a]);
+        s += p[g->dim];
+        break;
     case WOS_ANNULUS: s = std::fabs(p[0]) + std::fabs(p[1]) + p[3]; break;
     case WOS_ELLIPSE: s = std::fabs(p[0]) + std::fabs(p[1]) + std::max(p[2], p[3]); break;
     case WOS_POLYGON:
         for (int e = 0; e < 2 * g->n_verts; ++e) s = std::max(s, std::fabs(g->verts[e]));
         break;
     case WOS_BALL: s = std::fabs(p[0]) + std::fabs(p[1]) + std::fabs(p[2]) + p[3]; break;
-    case WOS_BOX:
+    case WOS_BOX: case WOS_PERFBOX:
         for (int a = 0; a < 2 * g->dim; ++a) s = std::max(s, std::fabs(p[a]));
         break;
     }
@@ -501,19 +566,24 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         }
         I.perim = cum;
     }
-    if (g->kind == WOS_PERFORATED) {
-        // holes as (centre, radius) records; FP32 centres relative to the outer centre, like the
-        // FP32 walk positions of the centred kinds
-        I.n_verts = g->layout[2];
+    if (g->kind == WOS_PERFORATED || g->kind == WOS_PERFBOX) {
+        // holes as (centre (ax, ay, ey), radius ex) records; FP32 centres relative to the outer
+        // centre for the disc / ball (like the FP32 walk positions of the centred kinds), absolute
+        // for the box
+        const int d = g->dim;
+        I.n_verts = g->n_verts;
+        const bool centred = g->kind == WOS_PERFORATED;
         for (int l = 0; l < I.n_verts; ++l) {
-            const double *h = g->verts + 3 * l;
+            const double *h = g->verts + (d + 1) * l;
             PolySeg s{};
             s.ax = h[0];
             s.ay = h[1];
-            s.ex = h[2];
-            s.fax = static_cast<float>(h[0] - g->params[0]);
-            s.fay = static_cast<float>(h[1] - g->params[1]);
-            s.fex = static_cast<float>(h[2]);
+            s.ey = d == 3 ? h[2] : 0.0;
+            s.ex = h[d];
+            s.fax = static_cast<float>(h[0] - (centred ? g->params[0] : 0.0));
+            s.fay = static_cast<float>(h[1] - (centred ? g->params[1] : 0.0));
+            s.fey = d == 3 ? static_cast<float>(h[2] - (centred ? g->params[2] : 0.0)) : 0.0f;
+            s.fex = static_cast<float>(h[d]);
             segs.push_back(s);
         }
     }
@@ -545,7 +615,7 @@ extern "C" wos_status wos_set_tuning(wos_ctx *ctx, int32_t dim, int32_t kind, in
 {
     if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
     if (!valid_tuning(t)) return set_error(WOS_EINVAL, "block must be 64..1024 (power of two), walks_per_lane >= 1");
-    if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > 5)
+    if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > WOS_PERFBOX)
         return set_error(WOS_EINVAL, "bad (dim, kind, precision)");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tuning[tune_key(dim, kind, precision)] = *t;

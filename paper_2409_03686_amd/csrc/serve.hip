@@ -600,8 +600,9 @@ extern "C" wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uin
     j->req.uD_host = j->uD.data();
     j->req.u0_host = n0 ? j->u0.data() : nullptr;
     j->req.gamma1_mask_host = j->mask.data();
-    if (req->geom.verts && req->geom.n_verts > 0) {  // polygon vertices / perforated-disc holes
-        const size_t nv = static_cast<size_t>(req->geom.n_verts) * (req->geom.kind == WOS_PERFORATED ? 3 : 2);
+    if (req->geom.verts && req->geom.n_verts > 0) {  // polygon vertices / holes of a perforated domain
+        const bool holes = req->geom.kind == WOS_PERFORATED || req->geom.kind == WOS_PERFBOX;
+        const size_t nv = static_cast<size_t>(req->geom.n_verts) * (holes ? req->geom.dim + 1 : 2);
         j->verts.assign(req->geom.verts, req->geom.verts + nv);
         j->req.geom.verts = j->verts.data();
     }

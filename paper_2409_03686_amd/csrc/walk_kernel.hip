@@ -249,7 +249,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     const int M = I.n_elem;
     for (int j = tid; j < M; j += nthr) hist[j] = 0u;
     const PolySeg *segs = I.segs;
-    if constexpr (KIND == kPolygon || KIND == kPerforated) {  // edges / holes read every step
+    if constexpr (KIND == kPolygon || KIND == kPerforated || KIND == kPerfBox) {  // edges / holes read every step
         for (int e = tid; e < I.n_verts; e += nthr) lds_segs[e] = I.segs[e];
         segs = lds_segs;
     }
@@ -472,11 +472,14 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
             case kEllipse: run_item<R, 2, kEllipse>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             case kPolygon: run_item<R, 2, kPolygon>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             case kPerforated: run_item<R, 2, kPerforated>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kPerfBox: run_item<R, 2, kPerfBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             default: run_item<R, 2, kBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             }
         } else {
             switch (I.kind) {
             case kBall: run_item<R, 3, kBall>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kPerforated: run_item<R, 3, kPerforated>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
+            case kPerfBox: run_item<R, 3, kPerfBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             default: run_item<R, 3, kBox>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
             }
         }
@@ -507,12 +510,15 @@ template <typename R> static const void *kernel_of(int dim, int ksel)
         case kEllipse: return kptr<R, 2, kEllipse>();
         case kPolygon: return kptr<R, 2, kPolygon>();
         case kPerforated: return kptr<R, 2, kPerforated>();
+        case kPerfBox: return kptr<R, 2, kPerfBox>();
         case kBox: return kptr<R, 2, kBox>();
         default: return kptr<R, 2, -1>();
         }
     }
     switch (ksel) {
     case kBall: return kptr<R, 3, kBall>();
+    case kPerforated: return kptr<R, 3, kPerforated>();
+    case kPerfBox: return kptr<R, 3, kPerfBox>();
     case kBox: return kptr<R, 3, kBox>();
     default: return kptr<R, 3, -1>();
     }

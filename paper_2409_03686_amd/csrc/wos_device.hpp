@@ -11,14 +11,17 @@
 
 namespace wos {
 
-enum Kind : int32_t { kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5, kPerforated = 6 };
+enum Kind : int32_t {
+    kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5, kPerforated = 6, kPerfBox = 7
+};
 
 constexpr int kMaxPolyVerts = 64;
 constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
 
 // One polygon edge a -> b in FP64 (exit tests and cell indices) and FP32 (bulk distance); for the
-// perforated disc one hole: centre (ax, ay), radius ex, and in FP32 the centre relative to the
-// outer centre (fax, fay) and the radius fex.
+// perforated domains one hole: centre (ax, ay[, ey]), radius ex, and in FP32 the centre (fax, fay
+// [, fey]) -- relative to the outer centre for the disc / ball, absolute for the box -- and the
+// radius fex.
 struct PolySeg {
     double ax, ay, ex, ey, ll, cum, len, pad;
     float fax, fay, fex, fey, finv_ll, fpad0, fpad1, fpad2;
@@ -150,6 +153,39 @@ template <> __device__ __forceinline__ float seg_dist_sq<float>(float ax, float 
     return dx * dx + dy * dy;
 }
 
+// Perforated domains (FP64, absolute coordinates): distance to the outer boundary (disc / ball, or
+// box), and to hole h with the vector from its centre in v.
+template <int KIND, int DIM> __device__ __forceinline__ double outer_dist64(const DevInst &I, const double *x)
+{
+#pragma clang fp contract(off)
+    if constexpr (KIND == kPerforated) {
+        double s = 0.0;
+        for (int a = 0; a < DIM; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);
+        return I.p[DIM] - __builtin_sqrt(s);
+    } else {
+        double best = __builtin_inf();
+        for (int a = 0; a < DIM; ++a) {
+            const double lo = x[a] - I.p[a], hi = I.p[DIM + a] - x[a];
+            best = lo < best ? lo : best;
+            best = hi < best ? hi : best;
+        }
+        return best;
+    }
+}
+
+template <int DIM> __device__ __forceinline__ double hole_dist64(const PolySeg &h, const double *x, double *v)
+{
+#pragma clang fp contract(off)
+    v[0] = x[0] - h.ax;
+    v[1] = x[1] - h.ay;
+    double s = v[0] * v[0] + v[1] * v[1];
+    if constexpr (DIM == 3) {
+        v[2] = x[2] - h.ey;
+        s += v[2] * v[2];
+    }
+    return __builtin_sqrt(s) - h.ex;
+}
+
 template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevInst &I, const double *x,
                                                                       const PolySeg *segs)
 {
@@ -181,13 +217,11 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);
         return I.p[3] - __builtin_sqrt(s);
-    } else if constexpr (KIND == kPerforated) {
-        // the nearest of the outer circle and the hole circles
-        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
-        double best = I.p[2] - __builtin_sqrt(dx * dx + dy * dy);
+    } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
+        // the nearest of the outer boundary and the holes
+        double best = outer_dist64<KIND, DIM>(I, x), v[DIM];
         for (int l = 0; l < I.n_verts; ++l) {
-            const double hx = x[0] - segs[l].ax, hy = x[1] - segs[l].ay;
-            const double d = __builtin_sqrt(hx * hx + hy * hy) - segs[l].ex;
+            const double d = hole_dist64<DIM>(segs[l], x, v);
             best = d < best ? d : best;
         }
         return best;
@@ -238,11 +272,26 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
         return __builtin_amdgcn_sqrtf(best);
     } else if constexpr (KIND == kBall) {
         return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    } else if constexpr (KIND == kPerforated) {
-        float best = I.pf[2] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1]);
+    } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
+        float best;
+        if constexpr (KIND == kPerforated) {  // centred positions
+            float s = x[0] * x[0] + x[1] * x[1];
+            if constexpr (DIM == 3) s = __builtin_fmaf(x[2], x[2], s);
+            best = I.pf[DIM] - __builtin_amdgcn_sqrtf(s);
+        } else {
+            best = __builtin_inff();
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+                best = __builtin_fminf(best, __builtin_fminf(x[a] - I.pf[a], I.pf[DIM + a] - x[a]));
+        }
         for (int l = 0; l < I.n_verts; ++l) {
             const float hx = x[0] - segs[l].fax, hy = x[1] - segs[l].fay;
-            best = __builtin_fminf(best, __builtin_amdgcn_sqrtf(hx * hx + hy * hy) - segs[l].fex);
+            float s = hx * hx + hy * hy;
+            if constexpr (DIM == 3) {
+                const float hz = x[2] - segs[l].fey;
+                s = __builtin_fmaf(hz, hz, s);
+            }
+            best = __builtin_fminf(best, __builtin_amdgcn_sqrtf(s) - segs[l].fex);
         }
         return best;
     } else {
@@ -356,6 +405,40 @@ template <int KIND> __device__ __forceinline__ int element32_certified(const Dev
     return off + static_cast<int>(fl);
 }
 
+// Equal-area cell of a direction v (any length > 0): band of the height v_z / |v| from the top
+// (nz bands), then the azimuth sector (nphi sectors from angle 0).
+__device__ __forceinline__ int sphere_cell(const double *v, int nz, int nphi)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) s += v[a] * v[a];
+    const double zc = v[2] / __builtin_sqrt(s);
+    const int iz = clamp_index((1.0 - zc) * 0.5 * static_cast<double>(nz), nz);
+    return iz * nphi + arc_of(atan2(v[1], v[0]), nphi);
+}
+
+// Box: the nearest face (ties: the lowest face index), then the patch of the other coordinates.
+template <int DIM> __device__ __forceinline__ int box_cell(const DevInst &I, const double *x)
+{
+#pragma clang fp contract(off)
+    const int n = I.layout[0];
+    double best = __builtin_inf();
+    int fb = 0;
+    for (int f = 0; f < 2 * DIM; ++f) {
+        const int a = f >> 1;
+        const double df = (f & 1) == 0 ? x[a] - I.p[a] : I.p[DIM + a] - x[a];
+        if (df < best) { best = df; fb = f; }
+    }
+    const int a = fb >> 1;
+    int idx = 0;
+    for (int b = 0; b < DIM; ++b) {
+        if (b == a) continue;
+        const double lo = I.p[b], hi = I.p[DIM + b];
+        idx = idx * n + clamp_index((x[b] - lo) / (hi - lo) * static_cast<double>(n), n);
+    }
+    return fb * (DIM == 2 ? n : n * n) + idx;
+}
+
 template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevInst &I, const double *x,
                                                                       const PolySeg *segs)
 {
@@ -382,47 +465,44 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
         }
         const double s_at = segs[eb].cum + tb * segs[eb].len;
         return clamp_index(s_at * static_cast<double>(I.layout[0]) / I.perim, I.layout[0]);
-    } else if constexpr (KIND == kPerforated) {
-        // the nearest circle (ties: the outer one, then the lowest hole), then the arc about its centre
-        const double dx = x[0] - I.p[0], dy = x[1] - I.p[1];
-        double best = I.p[2] - __builtin_sqrt(dx * dx + dy * dy), ax = dx, ay = dy;
+    } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
+        // the nearest piece of the boundary (ties: the outer one, then the lowest hole), then the
+        // cell of the direction from the piece's centre; outer cells first, then each hole's
+        double best = outer_dist64<KIND, DIM>(I, x), v[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0};
         int comp = -1;
         for (int l = 0; l < I.n_verts; ++l) {
-            const double hx = x[0] - segs[l].ax, hy = x[1] - segs[l].ay;
-            const double d = __builtin_sqrt(hx * hx + hy * hy) - segs[l].ex;
+            const double d = hole_dist64<DIM>(segs[l], x, v);
             if (d < best) {
                 best = d;
                 comp = l;
-                ax = hx;
-                ay = hy;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) vb[a] = v[a];
             }
         }
-        if (comp < 0) return arc_of(atan2(ay, ax), I.layout[0]);
-        return I.layout[0] + comp * I.layout[1] + arc_of(atan2(ay, ax), I.layout[1]);
+        int n_out, hc, c;
+        if constexpr (KIND == kPerforated) {
+            n_out = DIM == 2 ? I.layout[0] : I.layout[0] * I.layout[1];
+            hc = DIM == 2 ? I.layout[1] : I.layout[2] * I.layout[3];
+            if (comp < 0) {
+                double w[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) w[a] = x[a] - I.p[a];
+                return DIM == 2 ? arc_of(atan2(w[1], w[0]), I.layout[0]) : sphere_cell(w, I.layout[0], I.layout[1]);
+            }
+            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1]) : sphere_cell(vb, I.layout[2], I.layout[3]);
+        } else {
+            n_out = DIM == 2 ? 4 * I.layout[0] : 6 * I.layout[0] * I.layout[0];
+            hc = DIM == 2 ? I.layout[1] : I.layout[1] * I.layout[2];
+            if (comp < 0) return box_cell<DIM>(I, x);
+            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1]) : sphere_cell(vb, I.layout[1], I.layout[2]);
+        }
+        return n_out + comp * hc + c;
     } else if constexpr (KIND == kBall) {
-        double v[3], s = 0.0;
-        for (int a = 0; a < 3; ++a) { v[a] = x[a] - I.p[a]; s += v[a] * v[a]; }
-        const double zc = v[2] / __builtin_sqrt(s);
-        const int nz = I.layout[0], nphi = I.layout[1];
-        const int iz = clamp_index((1.0 - zc) * 0.5 * static_cast<double>(nz), nz);
-        return iz * nphi + arc_of(atan2(v[1], v[0]), nphi);
+        double v[3];
+        for (int a = 0; a < 3; ++a) v[a] = x[a] - I.p[a];
+        return sphere_cell(v, I.layout[0], I.layout[1]);
     } else {  // kBox
-        const int n = I.layout[0];
-        double best = __builtin_inf();
-        int fb = 0;
-        for (int f = 0; f < 2 * DIM; ++f) {
-            const int a = f >> 1;
-            const double df = (f & 1) == 0 ? x[a] - I.p[a] : I.p[DIM + a] - x[a];
-            if (df < best) { best = df; fb = f; }
-        }
-        const int a = fb >> 1;
-        int idx = 0;
-        for (int b = 0; b < DIM; ++b) {
-            if (b == a) continue;
-            const double lo = I.p[b], hi = I.p[DIM + b];
-            idx = idx * n + clamp_index((x[b] - lo) / (hi - lo) * static_cast<double>(n), n);
-        }
-        return fb * (DIM == 2 ? n : n * n) + idx;
+        return box_cell<DIM>(I, x);
     }
 }
 

@@ -47,6 +47,10 @@ def _geoms():
         wi.Geometry(2, wi.BOX, (0.0, 0.0, 2.0, 1.0), (10,)),
         wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (24,)),
         wi.perforated_disk_example().geom,
+        wi.square_hole_example(1).geom,
+        wi.spherical_shell_example(7).geom,
+        wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 2.0, 1.0), (6, 4, 5),
+                    verts=np.array([[0.3, 0.5, 0.5, 0.2], [0.6, 1.4, 0.5, 0.25]])),
     ]
 
 
@@ -85,6 +89,16 @@ def test_invalid_geometries_are_rejected_on_the_host(wos):
          wos.WOS_EINVAL),                                                                      # holes overlap
         (wi.Geometry(2, wi.PERFORATED, (0.0, 0.0, 1.0), (8, 4, 2), verts=np.array([[0.2, 0.0, 0.1]])),
          wos.WOS_EINVAL),                                                                      # 1 hole given, 2 declared
+        (wi.Geometry(3, wi.PERFORATED, (0.0, 0.0, 0.0, 1.0), (4, 8, 2, 4), verts=np.array([[0.0, 0.0, 0.6, 0.5]])),
+         wos.WOS_EINVAL),                                                                      # hole sticks out
+        (wi.Geometry(3, wi.PERFORATED, (0.0, 0.0, 0.0, 1.0), (4, 8, 0, 4), verts=np.array([[0.0, 0.0, 0.0, 0.5]])),
+         wos.WOS_EINVAL),                                                                      # no hole cells
+        (wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.0), (4, 8), verts=np.array([[0.9, 0.0, 0.2]])),
+         wos.WOS_EINVAL),                                                                      # hole crosses a face
+        (wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.0), (4, 8), verts=np.array([[0.0, 0.0, -0.2]])),
+         wos.WOS_EINVAL),                                                                      # r < 0
+        (wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (4, 8), verts=np.array([[0.5, 0.5, 0.5, 0.2]])),
+         wos.WOS_EINVAL),                                                                      # 3D hole cells missing
     ]
     for g, code in bad:
         with pytest.raises(wos.WosError) as e:

@@ -86,6 +86,13 @@ def _kind_cases():
         "perforated_aniso": (wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (40, 12, 3),
                                          verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])),
                              K2, 0),
+        "perforated_ball_aniso": (wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (6, 11, 4, 7),
+                                              verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]])),
+                                  K3, 0),
+        "square_with_holes_aniso": (wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.2), (13, 11),
+                                                verts=np.array([[0.5, 0.0, 0.2], [-0.4, 0.45, 0.3]])), K2, 0),
+        "cube_with_hole_aniso": (wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (5, 4, 6),
+                                             verts=np.array([[0.55, 0.45, 0.5, 0.3]])), K3, 0),
     }
     return cases
 
@@ -195,6 +202,40 @@ def test_perforated_disc_example(wos, ctx):
     rep = statutil.two_sample(c, inst.n_walks, c64, inst.n_walks)
     print("FP32 vs FP64 perforated disc", rep)
     assert rep["ok"]
+
+
+@pytest.mark.parametrize("example", [1, 5, 6, 7])
+def test_paper_perforated_examples(wos, ctx, example):
+    """The paper's Examples 1 and 5 (the square with a hole) and 6 and 7 (the concentric and the
+    eccentric spherical shell) at their eps: FP64 walk for walk against the oracle on a few walks per
+    point, then FP32 geometry (at the smallest eps it allows) against FP64 entry by entry; for the
+    concentric shell, the inner sphere's harmonic measure against the Newtonian closed form
+    (1/rho - 1/R_0) / (1/R_1 - 1/R_0) at rho = 0.95."""
+    make = (lambda **kw: wi.square_hole_example(example, **kw)) if example in (1, 5) else \
+        (lambda **kw: wi.spherical_shell_example(example, **kw))
+    small = make(n_walks=300 if example in (6, 7) else 1000)
+    c, st, tr = _gpu(wos, ctx, small, trace=True, precision=wi.FP64)
+    cr, sr, trr = ow.build_instance(small, trace=True)
+    agree = _agreement(tr, trr)
+    print(f"example {example} (eps {small.eps:g}) FP64 walk agreement {agree:.7f}, "
+          f"{st['steps'] / st['walks']:.1f} steps per walk")
+    assert agree >= 0.999 and st["walks"] == sr["walks"] and np.all(c.sum(1) == small.n_walks)
+    n = 20_000
+    big = {}
+    for prec in (wi.FP64, wi.FP32_GEOM_FP64_EXIT):
+        inst = make(n_walks=n, eps=1e-5, precision=prec)
+        big[prec], st, _ = _gpu(wos, ctx, inst)
+        assert np.all(big[prec].sum(1) == n) and st["cap_hits"] == 0 and st["escapes"] <= 10
+    rep = statutil.two_sample(big[wi.FP32_GEOM_FP64_EXIT], n, big[wi.FP64], n)
+    print(f"example {example}: FP32 vs FP64", rep)
+    assert rep["ok"]
+    if example == 6:
+        g1 = small.geom.gamma1_mask.astype(bool)
+        p = (1 / 0.95 - 1.0) / (1 / 0.5 - 1.0)
+        for prec, cc in big.items():
+            mass = cc[:, g1].sum() / (n * cc.shape[0])
+            print(f"concentric shell, precision {prec}: inner-sphere measure {mass:.6f} (closed form {p:.6f})")
+            assert abs(mass - p) < 4.5 * np.sqrt(p * (1 - p) / (n * cc.shape[0])) + 2e-5
 
 
 def test_fp32_cube_vs_fp64(wos, ctx):

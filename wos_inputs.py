@@ -307,7 +307,7 @@ def bauer_spiral(n: int) -> np.ndarray:
     return np.stack([r * np.cos(ph), r * np.sin(ph), z], 1)
 
 
-def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: float = 1e-7,
+def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: Optional[float] = None,
                         precision: int = FP64, m_face: int = 100, m_hole: int = 50,
                         n_obs: int = 40) -> Instance:
     """The paper's Examples 1 and 5 (Section 5.2): D = (-1, 1)^2 minus the disc of radius 0.2 about
@@ -338,6 +338,8 @@ def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: float = 1e
         x = np.stack([-0.5 + 0.3 * np.cos(t), 0.5 + 0.3 * np.sin(t)], 1)
     else:
         raise ValueError(example)
+    if eps is None:
+        eps = 1e-7 if example == 1 else 1e-10
     inst = Instance(g, np.eye(2), x, n_walks, eps=eps, seed=1, precision=precision,
                     name=f"square_with_hole_example{example}")
     return _with_data(inst, lambda p: (-p[:, 0] ** 3 / 3 - p[:, 0] ** 2 * p[:, 1] + p[:, 0] * p[:, 1] ** 2
