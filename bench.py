@@ -65,12 +65,15 @@ def measured_traffic(shape):
     try:
         if rec.get("kernel_sources_sha256") != kernel_sources_hash():
             return None, "kernel changed since the counters were taken"
-        if rec.get("launch_shape") != f"{shape[0]},{shape[1]}":
+        if rec.get("launch_shape") != f"{shape[0]},{shape[1]},{ITEM_MODES[shape[2]]}":
             return None, "counters were taken at another launch shape"
         f, w = float(rec["fetch_bytes_per_launch"]), float(rec["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None, "counter summary unreadable"
     return f + w, {"fetch_bytes": f, "write_bytes": w}
+
+
+ITEM_MODES = ("auto", "block", "wave")
 
 
 def log(msg):
@@ -95,6 +98,8 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement (for profiling)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
+    p.add_argument("--items", choices=("auto", "block", "wave"), default="auto",
+                   help="who owns a walk work item: the library's choice, a block, or a wave")
     p.add_argument("--kernel-only", action="store_true",
                    help="for counter collection: one 1 GiB device copy (calibration), then the FP32 walk "
                         "kernel of the workload --steps times")
@@ -210,12 +215,14 @@ def main():
         print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)}))
         wos.wos_destroy(ctx)
         return
+    items = {"auto": wos.WOS_ITEMS_AUTO, "block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE}[a.items]
     if a.kernel_only:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         ctx = wos.wos_create(0)
+        wos.wos_set_tuning(ctx, 2, -1, inst.precision, 256, 16, items)
         x = wos.device_inputs(inst)
         for _ in range(a.steps):
             wos.run_measure(ctx, inst, x_dev=x)
@@ -243,10 +250,12 @@ def main():
     job = wos.measure_job(g, wos.walk_params_of(inst), x, n_obs, counts, stats)
     # launch shape (threads per block, walks per lane): the library default, or the autotuner's
     # choice on a walk sub-range
-    tuned = (256, 16)
+    tuned = (256, 16, items)
+    for prec in (wi.FP32_GEOM_FP64_EXIT, wi.FP64):
+        wos.wos_set_tuning(ctx, 2, -1, prec, *tuned)
     if a.autotune:
         tuned = tuple(wos.wos_autotune(ctx, job, max(1, inst.n_walks // 5)))
-        log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}")
+        log(f"autotuned walk launch shape: block {tuned[0]}, walks per lane {tuned[1]}, items {tuned[2]}")
     # --- timed region: the path pipelined over two CU partitions.  Step i runs its walk kernel on
     # the walk stream and its spectral step (assembly, SVD, reconstruction) on the spectral stream,
     # where it overlaps the walk kernel of step i + 1; buffers alternate between two sets, and a
@@ -372,7 +381,7 @@ def main():
             "whole_device": {"avg_ms": full_ms, "frac": ops / (full_ms * 1e-3) / VALU_PEAK_OPS},
             "ops_per_step": OPS_PER_STEP_2D_FP32, "ops_per_walk": OPS_PER_WALK,
             "simd_efficiency": steps_step / max(lane_slots, 1),
-            "launch_shape": {"block": tuned[0], "walks_per_lane": tuned[1]}}
+            "launch_shape": {"block": tuned[0], "walks_per_lane": tuned[1], "items": ITEM_MODES[tuned[2]]}}
 
     out = {
         "metric": "walks/s (whole path: walks + SVD + TSVD reconstruction)",

@@ -190,10 +190,17 @@ typedef struct {
 wos_status wos_build_measure_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs,
                                    void *stream);
 
-/* Launch shape of the walk kernel: threads per block and walks per lane per work item. */
+/* Launch shape of the walk kernel: threads per block, walks per lane per work item, and who owns a
+ * work item.  WOS_ITEMS_BLOCK: the waves of a block share an item and drain together at its end.
+ * WOS_ITEMS_WAVE: every wave owns its items and starts the walks of its next item while the last
+ * walks of the previous one still run (two histogram rows per wave in LDS): fewer idle lanes, more
+ * instructions per step.  WOS_ITEMS_AUTO is the block mode (the faster one on every workload
+ * measured); the autotuner times both.  The counts never depend on these choices. */
+typedef enum { WOS_ITEMS_AUTO = 0, WOS_ITEMS_BLOCK = 1, WOS_ITEMS_WAVE = 2 } wos_item_mode;
 typedef struct {
     int32_t block;          /* 64, 128, 256, 512 or 1024 */
     int32_t walks_per_lane; /* >= 1 */
+    int32_t items;          /* wos_item_mode */
 } wos_tuning;
 
 /* Sets the launch shape used for (dim, kind, precision) from now on (kind < 0: all kinds). */

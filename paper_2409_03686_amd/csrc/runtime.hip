@@ -602,19 +602,23 @@ wos_tuning wos::get_tuning(wos_ctx *ctx, int dim, int kind, int precision)
     if (it != ctx->tuning.end()) return it->second;
     it = ctx->tuning.find(tune_key(dim, -1, precision));
     if (it != ctx->tuning.end()) return it->second;
-    return wos_tuning{256, 16};
+    return wos_tuning{256, 16, WOS_ITEMS_AUTO};
 }
 
 static bool valid_tuning(const wos_tuning *t)
 {
     return t && (t->block == 64 || t->block == 128 || t->block == 256 || t->block == 512 || t->block == 1024) &&
-           t->walks_per_lane >= 1 && t->walks_per_lane <= 4096;
+           t->walks_per_lane >= 1 && t->walks_per_lane <= 4096 && t->items >= WOS_ITEMS_AUTO &&
+           t->items <= WOS_ITEMS_WAVE;
 }
+
+
 
 extern "C" wos_status wos_set_tuning(wos_ctx *ctx, int32_t dim, int32_t kind, int32_t precision, const wos_tuning *t)
 {
     if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
-    if (!valid_tuning(t)) return set_error(WOS_EINVAL, "block must be 64..1024 (power of two), walks_per_lane >= 1");
+    if (!valid_tuning(t))
+        return set_error(WOS_EINVAL, "block must be 64..1024 (power of two), walks_per_lane 1..4096, items a wos_item_mode");
     if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > WOS_PERFBOX)
         return set_error(WOS_EINVAL, "bad (dim, kind, precision)");
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -651,7 +655,16 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
         max_elem = std::max(max_elem, M);
         seg_max = std::max(seg_max, static_cast<int>(segs[q].size()));
     }
-    const uint32_t chunk = static_cast<uint32_t>(tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
+    gl.hist_words = (max_elem + 3) & ~3;
+    gl.seg_bytes = static_cast<int>(sizeof(PolySeg)) * seg_max;
+    gl.precision = jobs[idx[0]].walk.precision;
+    gl.dim = jobs[idx[0]].geom.dim;
+    gl.block = tn.block;
+    // the automatic choice is the block mode: the wave mode keeps 95 % of the lane slots busy
+    // against 90 %, but its loop issues about 14 % more instructions per step (annulus, FP32)
+    gl.wave = tn.items == WOS_ITEMS_WAVE;
+    // a work item holds walks_per_lane walks per lane of its owner (a wave or a block)
+    const uint32_t chunk = static_cast<uint32_t>(gl.wave ? 64 : tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
     uint64_t items = 0;
     size_t seg_off = sizeof(DevInst) * n;
     for (int q = 0; q < n; ++q) {
@@ -675,7 +688,8 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
         I.segs = reinterpret_cast<const PolySeg *>(static_cast<uintptr_t>(seg_off));
         seg_off += sizeof(PolySeg) * segs[q].size();
     }
-    if (items >= (1ull << 32)) return set_error(WOS_ENOTSUP, "more than 2^32 work items in one launch");
+    // every block or wave takes one item past the end before it stops: keep the 32-bit cursor clear of wrapping
+    if (items >= (1ull << 32) - (1ull << 20)) return set_error(WOS_ENOTSUP, "more than 2^32 - 2^20 work items in one launch");
     buf.assign(seg_off, 0);
     std::memcpy(buf.data(), insts.data(), sizeof(DevInst) * n);
     size_t off = sizeof(DevInst) * n;
@@ -686,20 +700,15 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.n_inst = n;
     gl.items = items;
     gl.block = tn.block;
-    gl.hist_words = (max_elem + 3) & ~3;
-    gl.seg_bytes = static_cast<int>(sizeof(PolySeg)) * seg_max;
-    gl.precision = jobs[idx[0]].walk.precision;
-    gl.dim = jobs[idx[0]].geom.dim;
     gl.kind_sel = jobs[idx[0]].geom.kind;
     for (int q = 1; q < n; ++q)
         if (jobs[idx[q]].geom.kind != gl.kind_sel) gl.kind_sel = -1;
-    const size_t lds = static_cast<size_t>(gl.hist_words) * 4 + gl.seg_bytes + walk_queue_bytes(gl.precision, gl.dim, gl.block);
+    const size_t lds = walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, gl.wave);
     if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;
-    if (hipFuncSetAttribute(walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(lds)) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel), gl.block, lds) !=
-            hipSuccess ||
+    const void *fn = walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel, gl.wave);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, gl.block, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     gl.per_cu = per_cu;
@@ -797,8 +806,8 @@ wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const 
     // a persistent grid for the CUs this stream may use (fewer on a CU-masked stream)
     const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(gl.per_cu) * stream_cus(ctx, stream),
                                              std::max<uint64_t>(gl.items, 1));
-    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, reinterpret_cast<const DevInst *>(dev), gl.n_inst, gl.items,
-                              cursor, gl.hist_words, gl.seg_bytes, gl.block, static_cast<int>(grid), stream));
+    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.wave, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
+                              gl.items, cursor, gl.hist_words, gl.seg_bytes, gl.block, static_cast<int>(grid), stream));
     HIP_TRY(ctx, hipEventRecord(slot.done, stream));
     slot.used = true;
     return WOS_OK;
@@ -905,11 +914,13 @@ extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uin
     HIP_TRY(ctx, hipEventCreate(&e1));
     const int blocks[] = {128, 256, 512, 1024};
     const int wpls[] = {4, 8, 16, 32, 64};
+    const int modes[] = {WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE};
     float best_ms = 1e30f;
-    wos_tuning bt{256, 16};
+    wos_tuning bt{256, 16, WOS_ITEMS_AUTO};
+    for (int md : modes)
     for (int b : blocks)
         for (int w : wpls) {
-            wos_tuning t{b, w};
+            wos_tuning t{b, w, md};
             float ms_min = 1e30f;
             for (int rep = 0; rep < 2; ++rep) {
                 HIP_TRY(ctx, hipEventRecord(e0, s));

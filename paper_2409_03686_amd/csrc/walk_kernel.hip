@@ -129,6 +129,7 @@ template <typename R, int DIM> struct StopQueue {
     R *pos;          // [DIM][kWave]
     uint32_t *koff;  // [kWave]
     uint32_t *steps; // [kWave]
+    uint32_t *slot;  // [kWave], wave-item mode only: the item slot (0 or 1) of the entry
 };
 
 constexpr uint32_t kCapBit = 0x80000000u;
@@ -139,13 +140,23 @@ struct LaneStats {
     unsigned long long steps = 0;
 };
 
-template <typename R, int DIM, int KIND>
+// W (wave-item mode): an entry belongs to item slot q.slot[lane], whose point is point1 for slot 1,
+// and its cell goes to that slot's histogram row (hist + slot hist_words).
+template <typename R, int DIM, int KIND, bool W = false>
 __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R, DIM> &q, uint32_t n,
-                                            uint32_t point, uint32_t *hist, const PolySeg *segs,
-                                            LaneStats &ls)
+                                            uint32_t point0, uint32_t *hist0, const PolySeg *segs,
+                                            LaneStats &ls, uint32_t point1 = 0, int hist_words = 0)
 {
     const uint32_t lane = __lane_id();
     if (lane < n) {
+        uint32_t point = point0;
+        uint32_t *hist = hist0;
+        if constexpr (W) {
+            if (q.slot[lane]) {
+                point = point1;
+                hist = hist0 + hist_words;
+            }
+        }
         R xs[DIM];
         double x[DIM];
 #pragma unroll
@@ -420,14 +431,365 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     __syncthreads();
 }
 
-// KSEL: the domain kind of every instance of the launch (its own register allocation), or -1 for
-// launches that mix kinds (dispatch per item).
-template <typename R, int DIM, int KSEL>
+// Item (instance, point, first walk, walk count) of global work item `item` of instance I.
+__device__ __forceinline__ void decode_item(const DevInst &I, uint64_t item, uint32_t &point, uint32_t &k0,
+                                            uint32_t &cnt)
+{
+    const uint64_t local = item - I.item_begin;
+    const uint64_t n_big_items = static_cast<uint64_t>(I.n_obs) * I.n_big;
+    if (local < n_big_items) {
+        point = static_cast<uint32_t>(local / I.n_big);
+        k0 = static_cast<uint32_t>(local % I.n_big) * I.big_chunk;
+        cnt = I.big_chunk;
+    } else {
+        const uint64_t l2 = local - n_big_items;
+        point = static_cast<uint32_t>(l2 / I.n_chunks);
+        k0 = I.n_big * I.big_chunk + static_cast<uint32_t>(l2 % I.n_chunks) * I.chunk;
+        cnt = min(I.chunk, I.n_walks - k0);
+    }
+}
+
+// Wave-item mode: each wave owns its items and runs them as one stream.  When the wave has dealt
+// every walk of its current item it fetches the next item of the same instance into its other
+// slot and keeps refilling free lanes from it, so the walks of consecutive items overlap and the
+// lanes do not drain at item boundaries.  Each slot has its own histogram row in the wave's part
+// of LDS (rows[0], rows[hist_words]); a row is added to HBM as soon as every walk of its item has
+// been binned, which frees the slot for the item after next.  No step of this needs another wave.
+// The bookkeeping needed only when an item ends lives in the wave's LDS control block (registers
+// are the kernel's limit); what a refill needs stays in scalar registers.  Returns the first item
+// it fetched but could not take (another instance, or past the end).
+// A wave-uniform value computed on the vector unit, made a scalar-register value explicitly.
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+struct WaveCtl {
+    uint64_t next_item;  // fetched, not yet taken (valid when have_next)
+    uint32_t rem[2];     // walks of the slot's item not yet binned
+    uint32_t have_next, pad;
+};
+constexpr size_t kWaveCtlBytes = 32;
+
+template <typename R, int DIM, int KIND>
+__device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, uint32_t *cursor, uint64_t total_items,
+                              uint32_t *rows, int hist_words, PolySeg *lds_segs, uint8_t *qb, LaneStats &ls,
+                              uint32_t &n_fp64, unsigned long long &wave_iters)
+{
+    constexpr int SPB = Spb<R, DIM>::v;
+    const uint32_t lane = __lane_id();
+    const int M = I.n_elem;
+    const PolySeg *segs = I.segs;
+    if constexpr (KIND == kPolygon || KIND == kPerforated || KIND == kPerfBox) {  // edges / holes read every step
+        for (int e = lane; e < I.n_verts; e += kWave) lds_segs[e] = I.segs[e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        segs = lds_segs;
+    }
+    StopQueue<R, DIM> q;
+    q.pos = reinterpret_cast<R *>(qb);
+    q.koff = reinterpret_cast<uint32_t *>(qb + kWave * DIM * sizeof(R));
+    q.steps = q.koff + kWave;
+    q.slot = q.steps + kWave;
+    WaveCtl *wc = reinterpret_cast<WaveCtl *>(q.slot + kWave);
+    Fold32 F{};
+    if constexpr (sizeof(R) == 4 && DIM == 2) {
+        F = Fold32{I.fold_off[0], I.fold_off[1], I.fold_rs[0], I.fold_rs[1], I.fold_rn[0], I.fold_rn[1]};
+        asm volatile("" : "+v"(F.off0), "+v"(F.off1), "+v"(F.rs0), "+v"(F.rs1), "+v"(F.rn0), "+v"(F.rn1));
+    }
+    constexpr R kFree = static_cast<R>(__builtin_inf());
+
+    // wave-uniform state: the points of both slots (random-number counters, binning), the item
+    // being dealt (slot, first walk, count, walks dealt, start point and its distance), the stop
+    // queue's fill, and whether the chain has ended
+    uint32_t pt0 = 0, pt1 = 0, cur = 0, k0c = 0, cntc = 0, dealt = 0, qn = 0, qn1 = 0;
+    R x0c[DIM], d0c = kFree;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x0c[a] = static_cast<R>(0);
+    bool ended = false;
+    if (lane == 0) {
+        wc->next_item = item;
+        wc->have_next = 1u;
+        wc->rem[0] = 0u;
+        wc->rem[1] = 0u;
+    }
+    auto rd = [](uint32_t v) { return __builtin_amdgcn_readfirstlane(v); };
+
+    auto flush_row = [&](uint32_t sl) {
+        uint32_t *row = rows + (sl ? hist_words : 0);
+        uint32_t *out = I.counts + static_cast<size_t>(sl ? pt1 : pt0) * M;
+        for (int j = lane; j < M; j += kWave) {
+            const uint32_t v = row[j];
+            if (v) {
+                atomicAdd(&out[j], v);
+                row[j] = 0u;
+            }
+        }
+    };
+    auto flushq = [&]() {
+        flush_queue<R, DIM, KIND, true>(I, q, qn, pt0, rows, segs, ls, pt1, hist_words);
+        const uint32_t n0 = qn - qn1;
+        const uint32_t r0 = rd(wc->rem[0]) - n0, r1 = rd(wc->rem[1]) - qn1;
+        if (lane == 0) {
+            wc->rem[0] = r0;
+            wc->rem[1] = r1;
+        }
+        if (n0 && r0 == 0u) flush_row(0);
+        if (qn1 && r1 == 0u) flush_row(1);
+        qn = 0;
+        qn1 = 0;
+    };
+    // Takes items into slot `sl` until one has walks to run (true) or the chain ends (false).  Items
+    // whose start point lies in the eps-shell (or outside D) are binned at once with zero steps.
+    auto take = [&](uint32_t sl) -> bool {
+        for (;;) {
+            uint64_t it = rd(static_cast<uint32_t>(wc->next_item));
+            if (!rd(wc->have_next)) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(cursor, 1u);
+                it = rd(t);
+            }
+            if (it >= total_items || it < I.item_begin || it >= I.item_begin + I.n_items) {
+                if (lane == 0) {
+                    wc->next_item = it;
+                    wc->have_next = 1u;
+                }
+                return false;
+            }
+            uint32_t point, k0, cnt;
+            decode_item(I, it, point, k0, cnt);
+            if (lane == 0) wc->have_next = 0u;
+            double x0d[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) x0d[a] = I.x_obs[static_cast<size_t>(point) * DIM + a];
+            const double d0d = dist64<KIND, DIM>(I, x0d, segs);
+            if (!(d0d > I.eps)) {
+                const int j0 = element64<KIND, DIM>(I, x0d, segs);
+                if (lane == 0) {
+                    atomicAdd(&I.counts[static_cast<size_t>(point) * M + j0], cnt);
+                    ls.walks += cnt;
+                    if (d0d < 0.0) ls.esc += cnt;
+                }
+                if (I.trace) {
+                    for (uint32_t w = lane; w < cnt; w += kWave) {
+                        const size_t t = (static_cast<size_t>(point) * I.n_walks + k0 + w) * 2;
+                        I.trace[t] = j0;
+                        I.trace[t + 1] = 0;
+                    }
+                }
+                continue;
+            }
+            if (sl) pt1 = point; else pt0 = point;
+            if (lane == 0) wc->rem[sl] = cnt;
+            cur = sl;
+            k0c = k0;
+            cntc = cnt;
+            dealt = 0u;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) x0c[a] = uniform(static_cast<R>(x0d[a] - origin<R, KIND>(I, a)));
+            if constexpr (sizeof(R) == 8) d0c = uniform(d0d); else d0c = uniform(dist32<KIND, DIM>(I, x0c, segs));
+            return true;
+        }
+    };
+
+    uint32_t koff = 0, s = 0, sl = 0;
+    R x[DIM];
+    R d = kFree;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x[a] = static_cast<R>(0);
+    if (!take(0)) ended = true;
+    // deals the current item's next walks to the lanes in `need` (free lanes) in lane order
+    auto deal = [&](uint64_t need) {
+        const uint32_t mine = dealt + prefix_count(need);
+        const uint32_t np = static_cast<uint32_t>(__popcll(need));
+        dealt = cntc - dealt > np ? dealt + np : cntc;
+        if (d == kFree && mine < cntc) {
+            koff = k0c + mine;
+            sl = cur;
+            s = 0;
+            d = d0c;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) x[a] = x0c[a];
+        }
+    };
+
+    for (;;) {
+        const uint64_t need = __ballot(d == kFree);
+        if (need != 0ull && dealt >= cntc && !ended) {
+            // the current item is fully dealt: move on to the other slot once its item is binned
+            const uint32_t other = cur ^ 1u;
+            if (rd(wc->rem[other]) != 0u && qn != 0u) flushq();
+            if (rd(wc->rem[other]) == 0u && !take(other)) ended = true;
+        }
+        // one refill site: lanes left free when an item runs out take the next item's walks one
+        // Philox block later
+        if (need != 0ull && dealt < cntc) deal(need);
+        if (!__any(d != kFree)) break;
+        uint32_t w[4];
+        {
+            uint32_t c0 = s / SPB, c1 = I.walk_begin + koff, c2 = sl ? pt1 : pt0, c3 = I.inst;
+            // the round keys are formed in the loop on the scalar unit rather than held in 20 SGPRs
+            uint32_t k0 = I.key0, k1 = I.key1;
+            asm volatile("" : "+s"(k0), "+s"(k1));
+            philox4x32_10(c0, c1, c2, c3, k0, k1);
+            w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+        }
+        wave_iters += SPB;
+        constexpr uint32_t kNoStop = 0xFFu;
+        uint32_t fph = kNoStop;
+        auto phase = [&](auto ph_tag, auto cap_tag) {
+            constexpr int PH = decltype(ph_tag)::value;
+            constexpr bool CAP = decltype(cap_tag)::value;
+            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
+            const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
+            fph = fin ? static_cast<uint32_t>(PH) : fph;
+            d = fin ? kFree : d;
+        };
+        auto append = [&](auto cap_tag) {
+            constexpr bool CAP = decltype(cap_tag)::value;
+            const bool stopped = fph != kNoStop;
+            const uint64_t fmask = __ballot(stopped);
+            if (fmask != 0ull) {
+                const uint32_t nf = __popcll(fmask);
+                if (qn + nf > static_cast<uint32_t>(kWave)) flushq();
+                if (stopped) {
+                    const uint32_t slot = qn + prefix_count(fmask);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) q.pos[a * kWave + slot] = x[a];
+                    q.koff[slot] = koff;
+                    q.steps[slot] = (sizeof(R) == 8 || CAP) ? s : s + fph + 1;
+                    q.slot[slot] = sl;
+                }
+                qn += nf;
+                qn1 += static_cast<uint32_t>(__popcll(fmask & __ballot(sl != 0u)));
+            }
+        };
+        auto block = [&](auto cap_tag) {
+            phase(std::integral_constant<int, 0>{}, cap_tag);
+            if constexpr (SPB > 1) phase(std::integral_constant<int, 1>{}, cap_tag);
+            if constexpr (SPB > 2) {
+                phase(std::integral_constant<int, 2>{}, cap_tag);
+                phase(std::integral_constant<int, 3>{}, cap_tag);
+            }
+            append(cap_tag);
+        };
+        if constexpr (sizeof(R) == 4) {
+            if (__any(d != kFree && s + SPB >= I.max_steps)) {
+                block(std::true_type{});
+            } else {
+                block(std::false_type{});
+                s += SPB;
+            }
+        } else {
+            block(std::true_type{});
+        }
+    }
+    if (qn) flushq();
+    // every walk is binned by now; add whatever a row still holds (nothing, when the counts above
+    // are exact) so that no count can be lost
+    flush_row(0);
+    flush_row(1);
+    return rd(wc->have_next) ? static_cast<uint64_t>(rd(static_cast<uint32_t>(wc->next_item))) : total_items;
+}
+
+// Adds a wave's statistics for instance I (sums over its lanes, one atomic per counter).
+__device__ __forceinline__ void wave_stats_flush(const DevInst &I, LaneStats &ls, uint32_t &n_fp64,
+                                                 unsigned long long &wave_iters)
+{
+    unsigned long long v[7] = {ls.walks, ls.steps, ls.max_s, ls.cap, ls.esc, n_fp64, 0ull};
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const unsigned long long t = __shfl_xor(v[c], o);
+            v[c] = c == 2 ? (t > v[c] ? t : v[c]) : v[c] + t;
+        }
+    }
+    v[6] = wave_iters * kWave;
+    if (I.stats && __lane_id() == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            if (c == 2) {
+                if (v[c]) atomicMax(&I.stats[2], v[c]);
+            } else if (v[c]) {
+                atomicAdd(&I.stats[c], v[c]);
+            }
+        }
+    }
+    ls = LaneStats{};
+    n_fp64 = 0;
+    wave_iters = 0;
+}
+
+__device__ __forceinline__ int instance_of(const DevInst *insts, int n_inst, uint64_t item)
+{
+    int lo = 0, hi = n_inst - 1;  // descriptors sorted by item_begin
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// WAVE: wave-item mode (run_chain); LDS holds, per wave, two histogram rows, the staged segments
+// and the stop queue.  Otherwise block-item mode (run_item).
+template <typename R, int DIM, int KSEL, bool WAVE>
 __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
                                                     uint64_t total_items, uint32_t *cursor,
                                                     int hist_words, int seg_bytes)
 {
     extern __shared__ __align__(16) uint8_t smem[];
+    if constexpr (WAVE) {
+        const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+        const uint32_t lane = __lane_id();
+        const size_t row_bytes = static_cast<size_t>(2 * hist_words) * 4;
+        uint32_t *rows = reinterpret_cast<uint32_t *>(smem + static_cast<size_t>(wv) * row_bytes);
+        PolySeg *segs_w = reinterpret_cast<PolySeg *>(smem + nw * row_bytes + static_cast<size_t>(wv) * seg_bytes);
+        uint8_t *qb = smem + nw * (row_bytes + seg_bytes) +
+                      static_cast<size_t>(wv) * (kWave * (DIM * sizeof(R) + 12) + kWaveCtlBytes);
+        for (int j = lane; j < 2 * hist_words; j += kWave) rows[j] = 0u;
+        LaneStats ls;
+        uint32_t n_fp64 = 0;
+        unsigned long long wave_iters = 0;
+        uint32_t it0 = 0;
+        if (lane == 0) it0 = atomicAdd(cursor, 1u);
+        uint64_t item = __builtin_amdgcn_readfirstlane(it0);
+        while (item < total_items) {
+            const DevInst &I = insts[instance_of(insts, n_inst, item)];
+            const int kind = KSEL >= 0 ? KSEL : I.kind;
+            const uint64_t first = item;
+            if constexpr (KSEL >= 0) {
+                item = run_chain<R, DIM, KSEL>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters);
+            } else if constexpr (DIM == 2) {
+                switch (kind) {
+                case kDisk: item = run_chain<R, 2, kDisk>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kAnnulus: item = run_chain<R, 2, kAnnulus>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kEllipse: item = run_chain<R, 2, kEllipse>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kPolygon: item = run_chain<R, 2, kPolygon>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kPerforated: item = run_chain<R, 2, kPerforated>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kPerfBox: item = run_chain<R, 2, kPerfBox>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                default: item = run_chain<R, 2, kBox>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                }
+            } else {
+                switch (kind) {
+                case kBall: item = run_chain<R, 3, kBall>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kPerforated: item = run_chain<R, 3, kPerforated>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                case kPerfBox: item = run_chain<R, 3, kPerfBox>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                default: item = run_chain<R, 3, kBox>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
+                }
+            }
+            wave_stats_flush(I, ls, n_fp64, wave_iters);
+        }
+        return;
+    }
     __shared__ BlockShared sh;
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
     PolySeg *lds_segs = reinterpret_cast<PolySeg *>(smem + static_cast<size_t>(hist_words) * 4);
@@ -490,54 +852,57 @@ __global__ void reset_cursor_kernel(uint32_t *cursor) { *cursor = 0u; }
 
 }  // namespace
 
-size_t walk_queue_bytes(int precision, int dim, int block)
+size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, bool wave)
 {
     const size_t rs = precision == 0 ? 8 : 4;
-    return static_cast<size_t>(block / kWave) * kWave * (dim * rs + 8);
+    const size_t nw = static_cast<size_t>(block / kWave);
+    if (wave) return nw * (static_cast<size_t>(2 * hist_words) * 4 + seg_bytes + kWave * (dim * rs + 12) + kWaveCtlBytes);
+    return static_cast<size_t>(hist_words) * 4 + seg_bytes + nw * kWave * (dim * rs + 8);
 }
 
-template <typename R, int DIM, int KSEL> static const void *kptr()
+template <typename R, int DIM, int KSEL> static const void *kptr(bool wave)
 {
-    return reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL>);
+    return wave ? reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, true>)
+                : reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, false>);
 }
 
-template <typename R> static const void *kernel_of(int dim, int ksel)
+template <typename R> static const void *kernel_of(int dim, int ksel, bool wave)
 {
     if (dim == 2) {
         switch (ksel) {
-        case kDisk: return kptr<R, 2, kDisk>();
-        case kAnnulus: return kptr<R, 2, kAnnulus>();
-        case kEllipse: return kptr<R, 2, kEllipse>();
-        case kPolygon: return kptr<R, 2, kPolygon>();
-        case kPerforated: return kptr<R, 2, kPerforated>();
-        case kPerfBox: return kptr<R, 2, kPerfBox>();
-        case kBox: return kptr<R, 2, kBox>();
-        default: return kptr<R, 2, -1>();
+        case kDisk: return kptr<R, 2, kDisk>(wave);
+        case kAnnulus: return kptr<R, 2, kAnnulus>(wave);
+        case kEllipse: return kptr<R, 2, kEllipse>(wave);
+        case kPolygon: return kptr<R, 2, kPolygon>(wave);
+        case kPerforated: return kptr<R, 2, kPerforated>(wave);
+        case kPerfBox: return kptr<R, 2, kPerfBox>(wave);
+        case kBox: return kptr<R, 2, kBox>(wave);
+        default: return kptr<R, 2, -1>(wave);
         }
     }
     switch (ksel) {
-    case kBall: return kptr<R, 3, kBall>();
-    case kPerforated: return kptr<R, 3, kPerforated>();
-    case kPerfBox: return kptr<R, 3, kPerfBox>();
-    case kBox: return kptr<R, 3, kBox>();
-    default: return kptr<R, 3, -1>();
+    case kBall: return kptr<R, 3, kBall>(wave);
+    case kPerforated: return kptr<R, 3, kPerforated>(wave);
+    case kPerfBox: return kptr<R, 3, kPerfBox>(wave);
+    case kBox: return kptr<R, 3, kBox>(wave);
+    default: return kptr<R, 3, -1>(wave);
     }
 }
 
-const void *walk_kernel_ptr(int precision, int dim, int kind_sel)
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel, bool wave)
 {
-    return precision == 0 ? kernel_of<double>(dim, kind_sel) : kernel_of<float>(dim, kind_sel);
+    return precision == 0 ? kernel_of<double>(dim, kind_sel, wave) : kernel_of<float>(dim, kind_sel, wave);
 }
 
-hipError_t launch_walks(int precision, int dim, int kind_sel, const DevInst *insts, int n_inst, uint64_t total_items,
-                        uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
+hipError_t launch_walks(int precision, int dim, int kind_sel, bool wave, const DevInst *insts, int n_inst,
+                        uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream)
 {
     reset_cursor_kernel<<<1, 1, 0, stream>>>(cursor);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = static_cast<size_t>(hist_words) * 4 + seg_bytes + walk_queue_bytes(precision, dim, block);
-    const void *fn = walk_kernel_ptr(precision, dim, kind_sel);
+    const size_t lds = walk_lds_bytes(precision, dim, block, hist_words, seg_bytes, wave);
+    const void *fn = walk_kernel_ptr(precision, dim, kind_sel, wave);
     void *args[] = {&insts, &n_inst, &total_items, &cursor, &hist_words, &seg_bytes};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }

@@ -63,11 +63,13 @@ struct RegDev {
     double alpha, delta, tau;
 };
 
-size_t walk_queue_bytes(int precision, int dim, int block);
+// Dynamic LDS of a walk launch.  wave: wave-item mode (two histogram rows, the segments and a stop
+// queue per wave) instead of block-item mode (one row, one copy of the segments, a queue per wave).
+size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, bool wave);
 // kind_sel: the domain kind shared by all instances of the launch, or -1 when they differ
-const void *walk_kernel_ptr(int precision, int dim, int kind_sel);
-hipError_t launch_walks(int precision, int dim, int kind_sel, const DevInst *insts, int n_inst, uint64_t total_items,
-                        uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel, bool wave);
+hipError_t launch_walks(int precision, int dim, int kind_sel, bool wave, const DevInst *insts, int n_inst,
+                        uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream);
 
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,

@@ -55,7 +55,10 @@ class WosMeasureJob(C.Structure):
 
 
 class WosTuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("walks_per_lane", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("walks_per_lane", C.c_int32), ("items", C.c_int32)]
+
+
+WOS_ITEMS_AUTO, WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE = 0, 1, 2
 
 
 class WosRegParams(C.Structure):
@@ -260,15 +263,16 @@ def wos_build_measure_batch(ctx, jobs: Sequence[WosMeasureJob], stream=None):
     _check(lib().wos_build_measure_batch(ctx, arr, len(jobs), _stream(stream)))
 
 
-def wos_set_tuning(ctx, dim, kind, precision, block, walks_per_lane):
-    t = WosTuning(int(block), int(walks_per_lane))
+def wos_set_tuning(ctx, dim, kind, precision, block, walks_per_lane, items=WOS_ITEMS_AUTO):
+    t = WosTuning(int(block), int(walks_per_lane), int(items))
     _check(lib().wos_set_tuning(ctx, int(dim), int(kind), int(precision), C.byref(t)))
 
 
 def wos_autotune(ctx, job: WosMeasureJob, sample_walks: int, stream=None):
+    """(block, walks_per_lane, item mode) of the fastest candidate."""
     t = WosTuning()
     _check(lib().wos_autotune(ctx, C.byref(job), int(sample_walks), C.byref(t), _stream(stream)))
-    return t.block, t.walks_per_lane
+    return t.block, t.walks_per_lane, t.items
 
 
 def wos_svd_create(ctx, n_obs, n_elem, gamma1_mask, sigma, nu=None) -> int:

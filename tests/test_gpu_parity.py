@@ -253,15 +253,22 @@ def test_fp32_cube_vs_fp64(wos, ctx):
 
 @pytest.mark.parametrize("prec", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
 def test_counts_do_not_depend_on_launch_shape(wos, ctx, prec):
+    """Counts and statistics are the same for every launch shape and for both item modes (a block
+    or a wave owning a work item), including items whose walks overlap the next item's."""
     inst = wi.cfg2_annulus(n_walks=3001, n_obs=96, precision=prec)
     outs = []
-    for block, wpl in [(256, 32), (64, 1), (1024, 3), (128, 17)]:
-        wos.wos_set_tuning(ctx, 2, -1, prec, block, wpl)
-        c, _, _ = _gpu(wos, ctx, inst)
-        outs.append(c)
-    wos.wos_set_tuning(ctx, 2, -1, prec, 256, 32)
+    for block, wpl, items in [(256, 32, wos.WOS_ITEMS_BLOCK), (64, 1, wos.WOS_ITEMS_BLOCK),
+                              (1024, 3, wos.WOS_ITEMS_BLOCK), (128, 17, wos.WOS_ITEMS_BLOCK),
+                              (256, 16, wos.WOS_ITEMS_WAVE), (64, 1, wos.WOS_ITEMS_WAVE),
+                              (1024, 3, wos.WOS_ITEMS_WAVE), (128, 17, wos.WOS_ITEMS_WAVE)]:
+        wos.wos_set_tuning(ctx, 2, -1, prec, block, wpl, items)
+        c, st, _ = _gpu(wos, ctx, inst)
+        st.pop("lane_slots", None)  # the only statistic that depends on the schedule
+        outs.append((c, st))
+    wos.wos_set_tuning(ctx, 2, -1, prec, 256, 16, wos.WOS_ITEMS_AUTO)
     for o in outs[1:]:
-        assert np.array_equal(outs[0], o)
+        assert np.array_equal(outs[0][0], o[0])
+        assert outs[0][1] == o[1]
 
 
 @pytest.mark.parametrize("prec", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
@@ -780,8 +787,8 @@ def test_autotune_returns_valid_shape_and_keeps_results(wos, ctx):
     x = wos.device_inputs(inst)
     cnt = torch.zeros((128, 256), dtype=torch.int32, device="cuda")
     job = wos.measure_job(inst.geom, wos.walk_params_of(inst), x, 128, cnt)
-    block, wpl = wos.wos_autotune(ctx, job, 2000)
-    assert block in (128, 256, 512, 1024) and wpl >= 1
+    block, wpl, items = wos.wos_autotune(ctx, job, 2000)
+    assert block in (128, 256, 512, 1024) and wpl >= 1 and items in (wos.WOS_ITEMS_BLOCK, wos.WOS_ITEMS_WAVE)
     assert int(cnt.sum()) == 0  # timing runs do not touch the caller's counts
     after, _, _ = _gpu(wos, ctx, inst)
     assert np.array_equal(before, after)
