@@ -282,7 +282,14 @@ def test_walk_range_splits_sum_exactly(wos, ctx, prec):
     assert np.array_equal(full, _np(counts))
 
 
-def test_batch_equals_separate_and_oracle(wos, ctx):
+@pytest.mark.parametrize("items", ["block", "wave"])
+def test_batch_equals_separate_and_oracle(wos, ctx, items):
+    """A batch of instances of mixed kinds in one launch per dimension equals separate launches,
+    with block-owned items and with wave-owned items (where a wave's chain of items ends at an
+    instance boundary and the next instance starts with its own descriptor)."""
+    mode = {"block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE}[items]
+    for dim in (2, 3):
+        wos.wos_set_tuning(ctx, dim, -1, wi.FP64, 256, 16, mode)
     insts = wi.cfg4_batch(n_instances=10, walk_scale=0.02, precision=wi.FP64)
     for k, inst in enumerate(insts):  # keep the CPU side small
         inst.x_obs = inst.x_obs[:24]
@@ -302,6 +309,8 @@ def test_batch_equals_separate_and_oracle(wos, ctx):
         assert np.array_equal(got, sep[k]), inst.name
         cr, _, _ = ow.build_instance(inst)
         assert np.abs(got.astype(np.int64) - cr).sum() <= 2e-3 * got.sum() + 2, inst.name
+    for dim in (2, 3):
+        wos.wos_set_tuning(ctx, dim, -1, wi.FP64, 256, 16, wos.WOS_ITEMS_AUTO)
 
 
 # -------------------------------------------------------------------------- edge cases
