@@ -73,7 +73,7 @@ def measured_traffic(shape):
     return f + w, {"fetch_bytes": f, "write_bytes": w}
 
 
-ITEM_MODES = ("auto", "block", "wave")
+ITEM_MODES = ("auto", "block", "wave", "point")
 
 
 def log(msg):
@@ -98,8 +98,9 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement (for profiling)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
-    p.add_argument("--items", choices=("auto", "block", "wave"), default="auto",
-                   help="who owns a walk work item: the library's choice, a block, or a wave")
+    p.add_argument("--items", choices=("auto", "block", "wave", "point"), default="auto",
+                   help="who owns the walk work: the library's choice, a block per item, a wave per item, "
+                        "or a block per point")
     p.add_argument("--kernel-only", action="store_true",
                    help="for counter collection: one 1 GiB device copy (calibration), then the FP32 walk "
                         "kernel of the workload --steps times")
@@ -215,7 +216,8 @@ def main():
         print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)}))
         wos.wos_destroy(ctx)
         return
-    items = {"auto": wos.WOS_ITEMS_AUTO, "block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE}[a.items]
+    items = {"auto": wos.WOS_ITEMS_AUTO, "block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE,
+             "point": wos.WOS_ITEMS_POINT}[a.items]
     if a.kernel_only:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)

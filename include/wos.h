@@ -190,13 +190,15 @@ typedef struct {
 wos_status wos_build_measure_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs,
                                    void *stream);
 
-/* Launch shape of the walk kernel: threads per block, walks per lane per work item, and who owns a
- * work item.  WOS_ITEMS_BLOCK: the waves of a block share an item and drain together at its end.
- * WOS_ITEMS_WAVE: every wave owns its items and starts the walks of its next item while the last
- * walks of the previous one still run (two histogram rows per wave in LDS): fewer idle lanes, more
- * instructions per step.  WOS_ITEMS_AUTO is the block mode (the faster one on every workload
- * measured); the autotuner times both.  The counts never depend on these choices. */
-typedef enum { WOS_ITEMS_AUTO = 0, WOS_ITEMS_BLOCK = 1, WOS_ITEMS_WAVE = 2 } wos_item_mode;
+/* Launch shape of the walk kernel: threads per block, walks per lane per work item, and who owns the
+ * work.  WOS_ITEMS_BLOCK: the waves of a block share an item (point, walk range) and drain together
+ * at its end.  WOS_ITEMS_WAVE: every wave owns its items and starts the walks of its next item while
+ * the last walks of the previous one still run (two histogram rows per wave in LDS): fewer idle
+ * lanes, more instructions per step.  WOS_ITEMS_POINT: a block owns a point and its waves reserve
+ * the point's walks walks_per_lane per lane at a time until none are left; blocks without a point
+ * join points that still have walks, so lanes drain only when a point runs out.  WOS_ITEMS_AUTO is
+ * the block mode; the autotuner times all three.  The counts never depend on these choices. */
+typedef enum { WOS_ITEMS_AUTO = 0, WOS_ITEMS_BLOCK = 1, WOS_ITEMS_WAVE = 2, WOS_ITEMS_POINT = 3 } wos_item_mode;
 typedef struct {
     int32_t block;          /* 64, 128, 256, 512 or 1024 */
     int32_t walks_per_lane; /* >= 1 */

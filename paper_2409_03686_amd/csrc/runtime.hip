@@ -609,7 +609,7 @@ static bool valid_tuning(const wos_tuning *t)
 {
     return t && (t->block == 64 || t->block == 128 || t->block == 256 || t->block == 512 || t->block == 1024) &&
            t->walks_per_lane >= 1 && t->walks_per_lane <= 4096 && t->items >= WOS_ITEMS_AUTO &&
-           t->items <= WOS_ITEMS_WAVE;
+           t->items <= WOS_ITEMS_POINT;
 }
 
 
@@ -660,11 +660,14 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.precision = jobs[idx[0]].walk.precision;
     gl.dim = jobs[idx[0]].geom.dim;
     gl.block = tn.block;
-    // the automatic choice is the block mode: the wave mode keeps 95 % of the lane slots busy
-    // against 90 %, but its loop issues about 14 % more instructions per step (annulus, FP32)
-    gl.wave = tn.items == WOS_ITEMS_WAVE;
-    // a work item holds walks_per_lane walks per lane of its owner (a wave or a block)
-    const uint32_t chunk = static_cast<uint32_t>(gl.wave ? 64 : tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
+    gl.mode = tn.items == WOS_ITEMS_WAVE ? 1 : tn.items == WOS_ITEMS_POINT ? 2 : 0;
+    // point mode keeps each point's 32-bit walk cursor clear of wrapping (failed reservations add to
+    // it too): at most 2^30 walks per point
+    for (int q = 0; q < n && gl.mode == 2; ++q)
+        if (jobs[idx[q]].walk.walk_end - jobs[idx[q]].walk.walk_begin > (1ull << 30)) gl.mode = 0;
+    // a work item holds walks_per_lane walks per lane of its owner (a wave or a block); in point
+    // mode a wave reserves walks_per_lane walks per lane at a time
+    const uint32_t chunk = static_cast<uint32_t>(gl.mode != 0 ? 64 : tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
     uint64_t items = 0;
     size_t seg_off = sizeof(DevInst) * n;
     for (int q = 0; q < n; ++q) {
@@ -678,7 +681,8 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
         I.n_chunks = (rest + chunk - 1) / chunk;
         I.n_obs = J.n_obs;
         I.item_begin = items;
-        I.n_items = static_cast<uint64_t>(J.n_obs) * (I.n_big + I.n_chunks);
+        // point mode: the "items" are the points
+        I.n_items = gl.mode == 2 ? static_cast<uint64_t>(J.n_obs) : static_cast<uint64_t>(J.n_obs) * (I.n_big + I.n_chunks);
         items += I.n_items;
         I.x_obs = J.x_obs_dev;
         I.counts = J.counts_dev;
@@ -703,17 +707,17 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.kind_sel = jobs[idx[0]].geom.kind;
     for (int q = 1; q < n; ++q)
         if (jobs[idx[q]].geom.kind != gl.kind_sel) gl.kind_sel = -1;
-    const size_t lds = walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, gl.wave);
+    const size_t lds = walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, gl.mode);
     if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;
-    const void *fn = walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel, gl.wave);
+    const void *fn = walk_kernel_ptr(gl.precision, gl.dim, gl.kind_sel, gl.mode);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, gl.block, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     gl.per_cu = per_cu;
     uint64_t grid = static_cast<uint64_t>(per_cu) * ctx->n_cu;
-    grid = std::min<uint64_t>(grid, std::max<uint64_t>(items, 1));
+    if (gl.mode != 2) grid = std::min<uint64_t>(grid, std::max<uint64_t>(items, 1));  // points can be shared
     gl.grid = static_cast<int>(grid);
     return WOS_OK;
 }
@@ -780,7 +784,7 @@ wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const 
     RingSlot &slot = ctx->ring[ctx->ring_next];
     ctx->ring_next = (ctx->ring_next + 1) % ctx->ring.size();
     if (slot.used) HIP_TRY(ctx, hipEventSynchronize(slot.done));
-    const size_t need = buf.size() + 64;
+    const size_t need = ((buf.size() + 15) & ~size_t(15)) + 4 * walk_cursor_words(gl.mode, gl.items) + 64;
     if (slot.cap < need) {
         if (slot.host) (void)hipHostFree(slot.host);
         ctx_free(ctx, slot.dev, slot.cap);
@@ -804,9 +808,9 @@ wos_status wos::stage_and_launch(wos_ctx *ctx, std::vector<uint8_t> &buf, const 
     uint32_t *cursor = reinterpret_cast<uint32_t *>(dev + ((buf.size() + 15) & ~size_t(15)));
     HIP_TRY(ctx, hipMemcpyAsync(dev, slot.host, buf.size(), hipMemcpyHostToDevice, stream));
     // a persistent grid for the CUs this stream may use (fewer on a CU-masked stream)
-    const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(gl.per_cu) * stream_cus(ctx, stream),
-                                             std::max<uint64_t>(gl.items, 1));
-    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.wave, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
+    uint64_t grid = static_cast<uint64_t>(gl.per_cu) * stream_cus(ctx, stream);
+    if (gl.mode != 2) grid = std::min<uint64_t>(grid, std::max<uint64_t>(gl.items, 1));
+    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.mode, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
                               gl.items, cursor, gl.hist_words, gl.seg_bytes, gl.block, static_cast<int>(grid), stream));
     HIP_TRY(ctx, hipEventRecord(slot.done, stream));
     slot.used = true;
@@ -914,7 +918,7 @@ extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uin
     HIP_TRY(ctx, hipEventCreate(&e1));
     const int blocks[] = {128, 256, 512, 1024};
     const int wpls[] = {4, 8, 16, 32, 64};
-    const int modes[] = {WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE};
+    const int modes[] = {WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE, WOS_ITEMS_POINT};
     float best_ms = 1e30f;
     wos_tuning bt{256, 16, WOS_ITEMS_AUTO};
     for (int md : modes)

@@ -392,7 +392,7 @@ extern "C" wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     wos_plan *p = new wos_plan();
     p->ctx = ctx;
-    p->desc_bytes = buf.size() + 64;
+    p->desc_bytes = ((buf.size() + 15) & ~size_t(15)) + 4 * walk_cursor_words(gl.mode, gl.items) + 64;
     st = ctx_malloc(ctx, &p->desc, p->desc_bytes);
     if (st != WOS_OK) {
         delete p;
@@ -420,7 +420,7 @@ extern "C" wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, 
     if (e == hipSuccess) e = fill_u32(job->counts_dev, static_cast<size_t>(job->n_obs) * M, 0u, cs);
     if (e == hipSuccess && job->stats_dev) e = fill_u32(reinterpret_cast<uint32_t *>(job->stats_dev), 2 * WOS_STATS_WORDS, 0u, cs);
     if (e == hipSuccess)
-        e = launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.wave, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
+        e = launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.mode, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
                          gl.items, cursor, gl.hist_words, gl.seg_bytes, gl.block, gl.grid, cs);
     if (e == hipSuccess && svd) {
         e = svd_launch(svd->v, job->counts_dev, 1.0 / static_cast<double>(n_walks), svd->coop_grid, cs);

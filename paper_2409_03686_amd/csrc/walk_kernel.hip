@@ -15,6 +15,7 @@
 // Stop points are appended to a per-wave LDS queue and binned 64 at a time (full-wave FP64
 // projection), then counted in an LDS histogram row of the item's point; at the end of the item
 // the non-zero bins are flushed to the count matrix in HBM with atomics.
+#include <algorithm>
 #include <type_traits>
 
 #include "wos_device.hpp"
@@ -250,9 +251,12 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
     }
 }
 
-template <typename R, int DIM, int KIND>
+// PTS (point mode): the block runs point `point` with no fixed walk range; its waves reserve the
+// point's walks I.chunk at a time from the point's walk cursor *pcur until it passes N, so the
+// lanes drain only when the point's walks run out (several blocks may share a point).
+template <typename R, int DIM, int KIND, bool PTS = false>
 __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t cnt, uint32_t *hist,
-                         PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh)
+                         PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh, uint32_t *pcur = nullptr)
 {
     constexpr int SPB = Spb<R, DIM>::v;
     const int tid = threadIdx.x;
@@ -275,6 +279,13 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     if (!(d0d > I.eps)) {
         // The start point lies in the eps-shell (or outside D): every walk stops with zero steps
         // in the cell of the start point's projection.
+        if constexpr (PTS) {  // claim every walk of the point not yet claimed (idempotent: no wrap)
+            if (tid == 0) sh.item_hi = atomicMax(pcur, I.n_walks);
+            __syncthreads();
+            const uint32_t r = sh.item_hi;
+            k0 = r < I.n_walks ? r : I.n_walks;
+            cnt = I.n_walks - k0;
+        }
         const int j0 = element64<KIND, DIM>(I, x0d, segs);
         if (tid == 0) {
             hist[j0] += cnt;
@@ -322,6 +333,9 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         const uint32_t nw = static_cast<uint32_t>(nthr / kWave);
         const uint32_t wave_cnt = cnt > static_cast<uint32_t>(wv) ? (cnt - wv + nw - 1) / nw : 0u;
         uint32_t wave_next = 0;  // wave-uniform
+        // point mode: the wave's current reservation [res_next, res_end) of the point's walks
+        uint32_t res_next = 0, res_end = 0;
+        bool exhausted = false;
         uint32_t qn = 0;  // wave-uniform queue length
         uint32_t n_fp64 = 0;
         unsigned long long wave_iters = 0;
@@ -330,7 +344,31 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         // One outer iteration per Philox block: refill, draw the block, then SPB unrolled steps.
         for (;;) {
             const uint64_t need = __ballot(d == kFree);
-            if (need != 0ull && wave_next < wave_cnt) {
+            if constexpr (PTS) {
+                if (need != 0ull && res_next >= res_end && !exhausted) {
+                    uint32_t r = 0;
+                    if (lane == 0) r = atomicAdd(pcur, I.chunk);
+                    r = __builtin_amdgcn_readfirstlane(r);
+                    if (r >= I.n_walks) {
+                        exhausted = true;
+                    } else {
+                        res_next = r;
+                        res_end = I.n_walks - r > I.chunk ? r + I.chunk : I.n_walks;
+                    }
+                }
+                if (need != 0ull && res_next < res_end) {
+                    const uint32_t mine = res_next + prefix_count(need);
+                    const uint32_t np = static_cast<uint32_t>(__popcll(need));
+                    res_next = res_end - res_next > np ? res_next + np : res_end;
+                    if (d == kFree && mine < res_end) {
+                        koff = mine;
+                        s = 0;
+                        d = d0;
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) x[a] = x0[a];
+                    }
+                }
+            } else if (need != 0ull && wave_next < wave_cnt) {
                 const uint32_t mine = wave_next + prefix_count(need);
                 wave_next += static_cast<uint32_t>(__popcll(need));
                 if (d == kFree && mine < wave_cnt) {
@@ -739,15 +777,53 @@ __device__ __forceinline__ int instance_of(const DevInst *insts, int n_inst, uin
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// WAVE: wave-item mode (run_chain); LDS holds, per wave, two histogram rows, the staged segments
-// and the stop queue.  Otherwise block-item mode (run_item).
-template <typename R, int DIM, int KSEL, bool WAVE>
+// Instance of global point / item index q for one lane (descriptors sorted by item_begin).
+__device__ __forceinline__ int instance_of_lane(const DevInst *insts, int n_inst, uint64_t q)
+{
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].item_begin <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Point mode, once every point has been handed out: the block looks for a point whose walks are
+// not all reserved yet, scanning all points from a block-dependent start, blockDim points per
+// round.  Returns total_points when there is none.
+__device__ uint32_t steal_point(const DevInst *insts, int n_inst, uint32_t total_points, const uint32_t *pcur,
+                                BlockShared &sh)
+{
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t start = static_cast<uint32_t>((blockIdx.x * 2654435761ull) % total_points);
+    if (threadIdx.x == 0) sh.pad0 = kNone;
+    __syncthreads();
+    for (uint32_t base = 0; base < total_points; base += blockDim.x) {
+        const uint32_t k = base + threadIdx.x;
+        if (k < total_points) {
+            const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(start) + k) % total_points);
+            const uint32_t n = insts[instance_of_lane(insts, n_inst, q)].n_walks;
+            if (__hip_atomic_load(&pcur[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) atomicMin(&sh.pad0, k);
+        }
+        __syncthreads();
+        const bool found = sh.pad0 != kNone;
+        __syncthreads();
+        if (found) break;
+    }
+    const uint32_t k = sh.pad0;
+    return k == kNone ? total_points : static_cast<uint32_t>((static_cast<uint64_t>(start) + k) % total_points);
+}
+
+// MODE 0: block-item mode (run_item over items).  1: wave-item mode (run_chain); LDS holds, per
+// wave, two histogram rows, the staged segments and the stop queue.  2: point mode (run_item over
+// points with walk reservations; cursor[2 + p] is point p's walk cursor).
+template <typename R, int DIM, int KSEL, int MODE>
 __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
                                                     uint64_t total_items, uint32_t *cursor,
                                                     int hist_words, int seg_bytes)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    if constexpr (WAVE) {
+    if constexpr (MODE == 1) {
         const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
         const uint32_t lane = __lane_id();
         const size_t row_bytes = static_cast<size_t>(2 * hist_words) * 4;
@@ -795,6 +871,43 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
     PolySeg *lds_segs = reinterpret_cast<PolySeg *>(smem + static_cast<size_t>(hist_words) * 4);
     uint8_t *qbase = smem + static_cast<size_t>(hist_words) * 4 + seg_bytes;
 
+    if constexpr (MODE == 2) {
+        const uint32_t total_points = static_cast<uint32_t>(total_items);
+        uint32_t *pcur = cursor + 2;
+        for (;;) {
+            if (threadIdx.x == 0) sh.item_lo = atomicAdd(cursor, 1u);
+            __syncthreads();
+            uint32_t p = __builtin_amdgcn_readfirstlane(sh.item_lo);
+            __syncthreads();
+            if (p >= total_points) {
+                p = __builtin_amdgcn_readfirstlane(steal_point(insts, n_inst, total_points, pcur, sh));
+                if (p >= total_points) return;
+            }
+            const int idx = instance_of(insts, n_inst, p);
+            const DevInst &I = insts[idx];
+            const uint32_t point = p - static_cast<uint32_t>(I.item_begin);
+            if constexpr (KSEL >= 0) {
+                run_item<R, DIM, KSEL, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p);
+            } else if constexpr (DIM == 2) {
+                switch (I.kind) {
+                case kDisk: run_item<R, 2, kDisk, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kAnnulus: run_item<R, 2, kAnnulus, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kEllipse: run_item<R, 2, kEllipse, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kPolygon: run_item<R, 2, kPolygon, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kPerforated: run_item<R, 2, kPerforated, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kPerfBox: run_item<R, 2, kPerfBox, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                default: run_item<R, 2, kBox, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                }
+            } else {
+                switch (I.kind) {
+                case kBall: run_item<R, 3, kBall, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kPerforated: run_item<R, 3, kPerforated, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                case kPerfBox: run_item<R, 3, kPerfBox, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                default: run_item<R, 3, kBox, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
+                }
+            }
+        }
+    }
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t it = atomicAdd(cursor, 1u);
@@ -848,25 +961,31 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
     }
 }
 
-__global__ void reset_cursor_kernel(uint32_t *cursor) { *cursor = 0u; }
+__global__ void reset_cursor_kernel(uint32_t *cursor, size_t n)
+{
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        cursor[i] = 0u;
+}
 
 }  // namespace
 
-size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, bool wave)
+size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, int mode)
 {
     const size_t rs = precision == 0 ? 8 : 4;
     const size_t nw = static_cast<size_t>(block / kWave);
-    if (wave) return nw * (static_cast<size_t>(2 * hist_words) * 4 + seg_bytes + kWave * (dim * rs + 12) + kWaveCtlBytes);
+    if (mode == 1) return nw * (static_cast<size_t>(2 * hist_words) * 4 + seg_bytes + kWave * (dim * rs + 12) + kWaveCtlBytes);
     return static_cast<size_t>(hist_words) * 4 + seg_bytes + nw * kWave * (dim * rs + 8);
 }
 
-template <typename R, int DIM, int KSEL> static const void *kptr(bool wave)
+template <typename R, int DIM, int KSEL> static const void *kptr(int mode)
 {
-    return wave ? reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, true>)
-                : reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, false>);
+    return mode == 1   ? reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, 1>)
+           : mode == 2 ? reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, 2>)
+                       : reinterpret_cast<const void *>(&walk_kernel<R, DIM, KSEL, 0>);
 }
 
-template <typename R> static const void *kernel_of(int dim, int ksel, bool wave)
+template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
 {
     if (dim == 2) {
         switch (ksel) {
@@ -889,20 +1008,26 @@ template <typename R> static const void *kernel_of(int dim, int ksel, bool wave)
     }
 }
 
-const void *walk_kernel_ptr(int precision, int dim, int kind_sel, bool wave)
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel, int mode)
 {
-    return precision == 0 ? kernel_of<double>(dim, kind_sel, wave) : kernel_of<float>(dim, kind_sel, wave);
+    return precision == 0 ? kernel_of<double>(dim, kind_sel, mode) : kernel_of<float>(dim, kind_sel, mode);
 }
 
-hipError_t launch_walks(int precision, int dim, int kind_sel, bool wave, const DevInst *insts, int n_inst,
+size_t walk_cursor_words(int mode, uint64_t total_items)
+{
+    return mode == 2 ? 2 + static_cast<size_t>(total_items) : 2;
+}
+
+hipError_t launch_walks(int precision, int dim, int kind_sel, int mode, const DevInst *insts, int n_inst,
                         uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream)
 {
-    reset_cursor_kernel<<<1, 1, 0, stream>>>(cursor);
+    const size_t nc = walk_cursor_words(mode, total_items);
+    reset_cursor_kernel<<<static_cast<int>(std::min<size_t>((nc + 255) / 256, 1024)), 256, 0, stream>>>(cursor, nc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = walk_lds_bytes(precision, dim, block, hist_words, seg_bytes, wave);
-    const void *fn = walk_kernel_ptr(precision, dim, kind_sel, wave);
+    const size_t lds = walk_lds_bytes(precision, dim, block, hist_words, seg_bytes, mode);
+    const void *fn = walk_kernel_ptr(precision, dim, kind_sel, mode);
     void *args[] = {&insts, &n_inst, &total_items, &cursor, &hist_words, &seg_bytes};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }

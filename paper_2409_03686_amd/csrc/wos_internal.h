@@ -63,12 +63,17 @@ struct RegDev {
     double alpha, delta, tau;
 };
 
-// Dynamic LDS of a walk launch.  wave: wave-item mode (two histogram rows, the segments and a stop
-// queue per wave) instead of block-item mode (one row, one copy of the segments, a queue per wave).
-size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, bool wave);
+// Walk launch modes: who owns the work.  0: a block owns an item (point, walk range); 1: a wave owns
+// an item and overlaps it with its next one (two histogram rows, the segments and a stop queue per
+// wave in LDS); 2: a block owns a point and reserves its walks chunk by chunk from the point's walk
+// cursor, blocks that run out of points join points with walks left.
+size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg_bytes, int mode);
+// 32-bit words of the launch's cursors (zeroed by launch_walks): the item / point cursor, a spare
+// word, and in point mode one walk cursor per point.
+size_t walk_cursor_words(int mode, uint64_t total_items);
 // kind_sel: the domain kind shared by all instances of the launch, or -1 when they differ
-const void *walk_kernel_ptr(int precision, int dim, int kind_sel, bool wave);
-hipError_t launch_walks(int precision, int dim, int kind_sel, bool wave, const DevInst *insts, int n_inst,
+const void *walk_kernel_ptr(int precision, int dim, int kind_sel, int mode);
+hipError_t launch_walks(int precision, int dim, int kind_sel, int mode, const DevInst *insts, int n_inst,
                         uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream);
 

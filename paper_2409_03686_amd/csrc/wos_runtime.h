@@ -47,7 +47,7 @@ struct GroupLaunch {
     int hist_words = 4, seg_bytes = 0;
     int precision = 0, dim = 2;
     int kind_sel = -1;  // shared domain kind of the instances, -1 if mixed
-    bool wave = false;  // wave-item mode
+    int mode = 0;       // 0 block items, 1 wave items, 2 points (walk_lds_bytes)
 };
 
 wos_status set_error(wos_status st, const char *fmt, ...);

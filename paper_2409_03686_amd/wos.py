@@ -58,7 +58,7 @@ class WosTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("walks_per_lane", C.c_int32), ("items", C.c_int32)]
 
 
-WOS_ITEMS_AUTO, WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE = 0, 1, 2
+WOS_ITEMS_AUTO, WOS_ITEMS_BLOCK, WOS_ITEMS_WAVE, WOS_ITEMS_POINT = 0, 1, 2, 3
 
 
 class WosRegParams(C.Structure):

@@ -260,7 +260,9 @@ def test_counts_do_not_depend_on_launch_shape(wos, ctx, prec):
     for block, wpl, items in [(256, 32, wos.WOS_ITEMS_BLOCK), (64, 1, wos.WOS_ITEMS_BLOCK),
                               (1024, 3, wos.WOS_ITEMS_BLOCK), (128, 17, wos.WOS_ITEMS_BLOCK),
                               (256, 16, wos.WOS_ITEMS_WAVE), (64, 1, wos.WOS_ITEMS_WAVE),
-                              (1024, 3, wos.WOS_ITEMS_WAVE), (128, 17, wos.WOS_ITEMS_WAVE)]:
+                              (1024, 3, wos.WOS_ITEMS_WAVE), (128, 17, wos.WOS_ITEMS_WAVE),
+                              (256, 16, wos.WOS_ITEMS_POINT), (64, 1, wos.WOS_ITEMS_POINT),
+                              (1024, 3, wos.WOS_ITEMS_POINT), (128, 17, wos.WOS_ITEMS_POINT)]:
         wos.wos_set_tuning(ctx, 2, -1, prec, block, wpl, items)
         c, st, _ = _gpu(wos, ctx, inst)
         st.pop("lane_slots", None)  # the only statistic that depends on the schedule
@@ -282,12 +284,13 @@ def test_walk_range_splits_sum_exactly(wos, ctx, prec):
     assert np.array_equal(full, _np(counts))
 
 
-@pytest.mark.parametrize("items", ["block", "wave"])
+@pytest.mark.parametrize("items", ["block", "wave", "point"])
 def test_batch_equals_separate_and_oracle(wos, ctx, items):
     """A batch of instances of mixed kinds in one launch per dimension equals separate launches,
-    with block-owned items and with wave-owned items (where a wave's chain of items ends at an
-    instance boundary and the next instance starts with its own descriptor)."""
-    mode = {"block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE}[items]
+    with block-owned items, with wave-owned items (where a wave's chain of items ends at an
+    instance boundary and the next instance starts with its own descriptor) and with block-owned
+    points (shared by several blocks once every point has been handed out)."""
+    mode = {"block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE, "point": wos.WOS_ITEMS_POINT}[items]
     for dim in (2, 3):
         wos.wos_set_tuning(ctx, dim, -1, wi.FP64, 256, 16, mode)
     insts = wi.cfg4_batch(n_instances=10, walk_scale=0.02, precision=wi.FP64)
@@ -315,7 +318,19 @@ def test_batch_equals_separate_and_oracle(wos, ctx, items):
 
 # -------------------------------------------------------------------------- edge cases
 
-def test_degenerate_inputs(wos, ctx):
+@pytest.mark.parametrize("items", ["auto", "wave", "point"])
+def test_degenerate_inputs(wos, ctx, items):
+    mode = {"auto": wos.WOS_ITEMS_AUTO, "wave": wos.WOS_ITEMS_WAVE, "point": wos.WOS_ITEMS_POINT}[items]
+    for prec in (wi.FP64, wi.FP32_GEOM_FP64_EXIT):
+        wos.wos_set_tuning(ctx, 2, -1, prec, 256, 16, mode)
+    try:
+        _degenerate_cases(wos, ctx)
+    finally:
+        for prec in (wi.FP64, wi.FP32_GEOM_FP64_EXIT):
+            wos.wos_set_tuning(ctx, 2, -1, prec, 256, 16, wos.WOS_ITEMS_AUTO)
+
+
+def _degenerate_cases(wos, ctx):
     g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16,))
     x = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
     cnt = torch.zeros((0, 16), dtype=torch.int32, device="cuda")
@@ -797,7 +812,8 @@ def test_autotune_returns_valid_shape_and_keeps_results(wos, ctx):
     cnt = torch.zeros((128, 256), dtype=torch.int32, device="cuda")
     job = wos.measure_job(inst.geom, wos.walk_params_of(inst), x, 128, cnt)
     block, wpl, items = wos.wos_autotune(ctx, job, 2000)
-    assert block in (128, 256, 512, 1024) and wpl >= 1 and items in (wos.WOS_ITEMS_BLOCK, wos.WOS_ITEMS_WAVE)
+    assert block in (128, 256, 512, 1024) and wpl >= 1 and items in (wos.WOS_ITEMS_BLOCK, wos.WOS_ITEMS_WAVE,
+                                                                      wos.WOS_ITEMS_POINT)
     assert int(cnt.sum()) == 0  # timing runs do not touch the caller's counts
     after, _, _ = _gpu(wos, ctx, inst)
     assert np.array_equal(before, after)
