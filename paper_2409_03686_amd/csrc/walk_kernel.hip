@@ -873,6 +873,7 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
 
     if constexpr (MODE == 2) {
         const uint32_t total_points = static_cast<uint32_t>(total_items);
+        if (total_points == 0u) return;
         uint32_t *pcur = cursor + 2;
         for (;;) {
             if (threadIdx.x == 0) sh.item_lo = atomicAdd(cursor, 1u);
