@@ -665,6 +665,9 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     // it too): at most 2^30 walks per point
     for (int q = 0; q < n && gl.mode == 2; ++q)
         if (jobs[idx[q]].walk.walk_end - jobs[idx[q]].walk.walk_begin > (1ull << 30)) gl.mode = 0;
+    // wave mode holds two histogram rows per wave: with many cells it does not fit in LDS
+    if (gl.mode == 1 && walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, 1) > 64 * 1024)
+        gl.mode = 0;
     // a work item holds walks_per_lane walks per lane of its owner (a wave or a block); in point
     // mode a wave reserves walks_per_lane walks per lane at a time
     const uint32_t chunk = static_cast<uint32_t>(gl.mode != 0 ? 64 : tn.block) * static_cast<uint32_t>(tn.walks_per_lane);
