@@ -197,7 +197,8 @@ wos_status wos_build_measure_batch(wos_ctx *ctx, const wos_measure_job *jobs, in
  * lanes, more instructions per step.  WOS_ITEMS_POINT: a block owns a point and its waves reserve
  * the point's walks walks_per_lane per lane at a time until none are left; blocks without a point
  * join points that still have walks, so lanes drain only when a point runs out.  WOS_ITEMS_AUTO is
- * the block mode; the autotuner times all three.  A mode that does not apply falls back to the
+ * the point mode for WOS_FP64 walks and the block mode otherwise (the faster ones measured); the
+ * autotuner times all three.  A mode that does not apply falls back to the
  * block mode (wave mode above 64 KiB of LDS per block, point mode above 2^30 walks per point).
  * The counts never depend on these choices. */
 typedef enum { WOS_ITEMS_AUTO = 0, WOS_ITEMS_BLOCK = 1, WOS_ITEMS_WAVE = 2, WOS_ITEMS_POINT = 3 } wos_item_mode;

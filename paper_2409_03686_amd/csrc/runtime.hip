@@ -660,7 +660,11 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.precision = jobs[idx[0]].walk.precision;
     gl.dim = jobs[idx[0]].geom.dim;
     gl.block = tn.block;
-    gl.mode = tn.items == WOS_ITEMS_WAVE ? 1 : tn.items == WOS_ITEMS_POINT ? 2 : 0;
+    // automatic choice: point mode for FP64 walks (5 % faster on the annulus: the reservations cut
+    // the drains, and an FP64 step costs enough to hide their bookkeeping), block mode for FP32
+    // (there the bookkeeping costs about what the drains did)
+    gl.mode = tn.items == WOS_ITEMS_WAVE ? 1 : tn.items == WOS_ITEMS_POINT ? 2 : tn.items == WOS_ITEMS_BLOCK ? 0
+            : (gl.precision == WOS_FP64 ? 2 : 0);
     // point mode keeps each point's 32-bit walk cursor clear of wrapping (failed reservations add to
     // it too): at most 2^30 walks per point
     for (int q = 0; q < n && gl.mode == 2; ++q)
