@@ -3,8 +3,11 @@
 // Work decomposition: a work item is (instance, point i, chunk c of walk ids).  Blocks pull items
 // from one global atomic cursor until the queue is empty, so uneven instances and geometric-tailed
 // walk lengths share one launch.  Inside an item every wavefront keeps 64 walks in flight, one per
-// lane; a lane whose walk stops is refilled with the next walk id of the item through a wave ballot
-// and one LDS atomic for the whole wave (the paper's compaction of the active index vector).
+// lane; a lane whose walk stops is refilled with the wave's next walk id through a wave ballot and
+// a prefix count over it (the paper's compaction of the active index vector); the item's walks are
+// dealt to its waves round-robin, so no atomic is needed.  Two other owners of the work exist:
+// waves owning items (run_chain, overlapping consecutive items) and blocks owning points (walks
+// reserved chunk by chunk from a per-point cursor); the launch mode picks one.
 //
 // Randomness is counter-based (Philox4x32-10 keyed by instance seed; counter (block, walk, point,
 // instance)), so which lane runs which walk never changes a result.  One Philox block feeds
