@@ -78,10 +78,8 @@ template <> struct Dir<double, 2> {
     template <int PH> static __device__ __forceinline__ void get(const uint32_t w[4], double *U)
     {
 #pragma clang fp contract(off)
-        const double u = u53(w[2 * PH], w[2 * PH + 1]);
-        const double th = kTwoPi * u;
         double s, c;
-        sincos(th, &s, &c);
+        sincos2pi(u53(w[2 * PH], w[2 * PH + 1]), &s, &c);
         U[0] = c;
         U[1] = s;
     }
@@ -91,10 +89,9 @@ template <> struct Dir<double, 3> {
     {
 #pragma clang fp contract(off)
         const double z = 1.0 - 2.0 * u53(w[0], w[1]);
-        const double ph = kTwoPi * u53(w[2], w[3]);
         const double rho = __builtin_sqrt((1.0 - z) * (1.0 + z));
         double s, c;
-        sincos(ph, &s, &c);
+        sincos2pi(u53(w[2], w[3]), &s, &c);
         U[0] = rho * c;
         U[1] = rho * s;
         U[2] = z;

@@ -100,6 +100,45 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo)
     return static_cast<double>(m) * 0x1.0p-53 + 0x1.0p-54;
 }
 
+// sin(2 pi u) and cos(2 pi u) for u in [0, 1], the direction of an FP64 step.  u splits exactly into
+// a quarter turn q = rint(4u) and r = u - q/4 in [-1/8, 1/8]; x = 2 pi r lies in [-pi/4, pi/4],
+// where the Taylor series of sin x through x^17 and of cos x through x^18 leave a truncation below
+// 10^-19 (the next terms are x^19/19! and x^20/20!); the quarter turn then rotates (sin x, cos x).
+// About 30 arithmetic instructions against some 75 for the general sincos, whose argument reduction
+// serves any argument.  Within a few ulps of the correctly rounded values (host-side test).
+__host__ __device__ inline void sincos2pi(double u, double *sp, double *cp)
+{
+#pragma clang fp contract(off)
+    const double q = __builtin_rint(4.0 * u);
+    const double r = __builtin_fma(q, -0.25, u);  // exact: u and q / 4 are multiples of 2^-54 here
+    const double x = r * 6.283185307179586;       // 2 pi rounded to double
+    const double x2 = x * x;
+    double ps = 1.0 / 355687428096000.0;           // 1/17!
+    ps = __builtin_fma(ps, x2, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 120.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 6.0);
+    const double sn = __builtin_fma(x * x2, ps, x);
+    double pc = 1.0 / 6402373705728000.0;          // 1/18!
+    pc = __builtin_fma(pc, x2, -1.0 / 20922789888000.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, x2, -1.0 / 479001600.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 3628800.0);
+    pc = __builtin_fma(pc, x2, -1.0 / 40320.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 720.0);
+    pc = __builtin_fma(pc, x2, -1.0 / 24.0);
+    pc = __builtin_fma(pc, x2, 0.5);
+    const double cs = __builtin_fma(-x2, pc, 1.0);
+    // angle = q pi/2 + x
+    const int k = static_cast<int>(q) & 3;
+    const double s1 = (k & 1) ? cs : sn, c1 = (k & 1) ? sn : cs;
+    *sp = (k & 2) ? -s1 : s1;
+    *cp = ((k + 1) & 2) ? -c1 : c1;
+}
+
 // Uniform in (0,1]: the top 24 bits of w at the centre of their 2^-24 cell.
 __device__ __forceinline__ float u24(uint32_t w)
 {
