@@ -680,8 +680,12 @@ def test_exact_data_is_recovered(wos, ctx):
 
 # -------------------------------------------------------------------------- plans and serving
 
-def test_plan_graph_replays_match_eager(wos, ctx):
-    inst = wi.cfg2_annulus(n_walks=4000, n_obs=256)
+@pytest.mark.parametrize("prec", [wi.FP32_GEOM_FP64_EXIT, wi.FP64])
+def test_plan_graph_replays_match_eager(wos, ctx, prec):
+    """The captured plan (counts reset, walks, SVD, reconstruction) replays to the eager result
+    every time; in FP64 the walks run in point mode, whose per-point walk cursors the captured reset
+    kernel must clear before each replay."""
+    inst = wi.cfg2_annulus(n_walks=4000, n_obs=256, precision=prec)
     g = inst.geom
     M = g.n_elem
     x = wos.device_inputs(inst)
