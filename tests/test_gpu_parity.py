@@ -657,6 +657,53 @@ def test_products_match_oracle(wos, ctx):
     wos.wos_svd_destroy(ctx, h)
 
 
+def test_products_edge_cases(wos, ctx):
+    """The products at their limits on a tiny problem: the sweep up to the full rank (its last column
+    equals the full-rank reconstruction, its last residual the part of q outside range(B)), all
+    eigenpairs, a single point's density; and the arguments they reject."""
+    g = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (8,))
+    g.gamma1_mask = (np.arange(8) >= 3).astype(np.uint8)
+    inst = wi.Instance(g, np.eye(2), np.array([[0.3, 0.1], [-0.2, 0.4], [0.1, -0.5]]), 3000, precision=wi.FP64)
+    c, _, _ = _gpu(wos, ctx, inst)
+    sigma = ow.element_measures(g)
+    h, ct, U, s, V, _, _ = _svd_case(wos, ctx, c, inst.n_walks, g.gamma1_mask, sigma)
+    k = len(s)  # min(3 points, 5 cells) = 3
+    uD = np.array([0.2, -0.1, 0.4])
+    u0 = np.array([0.3, 0.0, -0.2])
+    uD_d = torch.as_tensor(uD, device="cuda")
+    u0_d = torch.as_tensor(u0, device="cuda")
+    u1s = torch.zeros((k, 5), dtype=torch.float64, device="cuda")
+    res = torch.zeros(k + 1, dtype=torch.float64, device="cuda")
+    wos.wos_reconstruct_sweep(ctx, h, ct, inst.n_walks, uD_d, u0_d, k, u1s, None, res)
+    u1, _, r_used, _ = _recon(wos, ctx, h, ct, inst.n_walks, uD, u0, wos.reg_params(wos.WOS_TSVD_RANK, rank=k), 5, 3)
+    torch.cuda.synchronize()
+    assert r_used == k and np.array_equal(u1s.cpu().numpy()[-1], u1)
+    out = ol.assemble(c, inst.n_walks, g.gamma1_mask, sigma, uD=uD, u0=u0)
+    Ur, _, _ = ol.svd(out["B"])
+    qperp = out["q"] - Ur @ (Ur.T @ out["q"])  # zero: 3 points, rank 3
+    assert abs(res.cpu().numpy()[-1] - np.linalg.norm(qperp)) <= 1e-12 * np.linalg.norm(out["q"])
+    lam = torch.zeros(k, dtype=torch.float64, device="cuda")
+    ef = torch.zeros((k, 5), dtype=torch.float64, device="cuda")
+    wos.wos_eigenfunctions(ctx, h, k, lam, ef)
+    wos.wos_eigenfunctions(ctx, h, 0, None, None)  # nothing to do
+    sig_d = torch.as_tensor(sigma, device="cuda")
+    mean = torch.zeros(8, dtype=torch.float64, device="cuda")
+    wos.wos_density(ctx, ct[:1], 1, 8, inst.n_walks, sig_d, None, mean)
+    torch.cuda.synchronize()
+    assert np.allclose(lam.cpu().numpy(), s ** 2, rtol=1e-14)
+    assert np.abs(mean.cpu().numpy() - ol.density(c[:1], inst.n_walks, sigma)[0]).max() <= 1e-15 * mean.max().item()
+    for bad in (lambda: wos.wos_reconstruct_sweep(ctx, h, ct, inst.n_walks, uD_d, u0_d, 0, u1s),
+                lambda: wos.wos_reconstruct_sweep(ctx, h, ct, inst.n_walks, uD_d, u0_d, k + 1, u1s),
+                lambda: wos.wos_reconstruct_sweep(ctx, h, ct, inst.n_walks, uD_d, None, k, u1s),
+                lambda: wos.wos_eigenfunctions(ctx, h, k + 1, lam, ef),
+                lambda: wos.wos_eigenfunctions(ctx, h, 2, None, None),
+                lambda: wos.wos_density(ctx, ct, 3, 8, inst.n_walks, sig_d, None, None),
+                lambda: wos.wos_density(ctx, ct, 3, 8, 0, sig_d, None, mean)):
+        with pytest.raises(wos.WosError):
+            bad()
+    wos.wos_svd_destroy(ctx, h)
+
+
 def test_exact_data_is_recovered(wos, ctx):
     """Counts = round(H 2^26) of the exact disk measure and data generated by them: the full-rank
     TSVD must return the boundary values that generated the data."""
