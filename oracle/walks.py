@@ -203,6 +203,17 @@ def geom_eval(geom, pts):
     return d, e
 
 
+def step_radii(geom, S, pts, radius_mode):
+    """Step radius of the given mode at each point (NaN where the mode does not apply)."""
+    g = make_geom(geom)
+    S = np.ascontiguousarray(np.asarray(S, np.float64))
+    p = np.ascontiguousarray(np.asarray(pts, np.float64).reshape(-1, geom.dim))
+    r = np.zeros(p.shape[0])
+    lib().oracle_step_radii(C.byref(g), _ptr(S, C.c_double), C.c_int(radius_mode), _ptr(p, C.c_double),
+                            C.c_int32(p.shape[0]), _ptr(r, C.c_double))
+    return r
+
+
 def walk_exits(geom, S, x0, eps, n, i=0, seed=0, instance_id=0, radius_mode=0, max_steps=10000):
     """Stop positions of n walks from x0 with the given step matrix S (3x3, row-major)."""
     L = lib()

@@ -12,8 +12,9 @@
  *     X_0 = x_i;  X_{n+1} = X_n + r(X_n) * S * U_n,  U_n uniform on the unit sphere,
  *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
  *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
- *   radius: r = dist(x, dD) ("WoE bound") or, for boxes, the largest r with x + r S B(0,1) inside D
- *   ("mapped exact").  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
+ *   radius: r = dist(x, dD) ("WoE bound"), or, for boxes, the largest r with x + r S B(0,1) inside D
+ *   ("mapped exact"), or, for discs, annuli and balls, a larger radius certified by a support bound
+ *   ("mapped bound", see step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
  *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
  *   reaching dD, dist <= 0) and its last point is binned.  The stop point is projected onto dD and the element
@@ -357,13 +358,62 @@ int oracle_element(const og_geom *g, const double *x)
     return -1;
 }
 
-/* Step radius.  mode 0: r = dist (the ellipsoid x + r S B(0,1) lies in the Euclidean ball of
- * radius r because |S| <= 1).  mode 1 (boxes): r = min over faces of (face distance)/|S e_a|,
- * the largest r whose ellipsoid stays inside the box. */
+/* Radius of the largest ellipsoid x + r S B(0,1) certified inside the ball B(c, R), from
+ * |v + r S u|^2 = |v|^2 + 2 r (S v).u + r^2 |S u|^2 <= |v|^2 + 2 r |S v| + r^2 for |u| <= 1
+ * (S symmetric, |S| <= 1, v = x - c): the positive root of r^2 + 2 a r - (R^2 - |v|^2) = 0,
+ * r = sqrt(a^2 + R^2 - |v|^2) - a with a = |S v|.  q = |v|^2 and a2 = a^2 are passed in. */
+static double inside_ball_radius(double q, double a2, double R)
+{
+    return sqrt(a2 + (R * R - q)) - sqrt(a2);
+}
+
+/* Radius certified outside the ball B(c, R_in) (a hole), from |v + r S u|^2 >= |v|^2 - 2 r |S v|:
+ * r = (|v|^2 - R_in^2) / (2 |S v|). */
+static double outside_ball_radius(double q, double a2, double R_in)
+{
+    return (q - R_in * R_in) / (2.0 * sqrt(a2));
+}
+
+/* |v|^2 and |S v|^2 for v = x - c. */
+static void centred_norms(int dim, const double *S, const double *x, const double *c, double *q, double *a2)
+{
+    double v[3] = { 0.0, 0.0, 0.0 };
+    double qq = 0.0, aa = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        v[a] = x[a] - c[a];
+        qq += v[a] * v[a];
+    }
+    for (int r = 0; r < dim; ++r) {
+        double w = 0.0;
+        for (int a = 0; a < dim; ++a) w += S[r * 3 + a] * v[a];
+        aa += w * w;
+    }
+    *q = qq;
+    *a2 = aa;
+}
+
+/* Step radius.  Any ellipsoid x + r S B(0,1) inside D is a valid step of the chain (the chain is the
+ * trace of the diffusion on inscribed ellipsoids, Section 4.2); the exit law does not depend on the
+ * choice.  mode 0: r = dist (the ellipsoid lies in the Euclidean ball of radius r because
+ * |S| <= 1).  mode 1 (boxes): r = min over faces of (face distance)/|S e_a|, the largest r whose
+ * ellipsoid stays inside the box.  mode 2 (disc, annulus, ball): the bounds above for the outer
+ * circle or sphere and, for the annulus, the inner circle, where dist itself is also a valid bound
+ * for the inner circle: r = min(r_out, max(r_in, d)). */
 static double step_radius(const og_geom *g, int mode, const double *S, const double *x, double d)
 {
     if (mode == 0) return d;
     int dim = g->dim;
+    if (mode == 2) {
+        double q, a2;
+        centred_norms(dim, S, x, g->p, &q, &a2);
+        if (g->kind == OG_DISK) return inside_ball_radius(q, a2, g->p[2]);
+        if (g->kind == OG_BALL) return inside_ball_radius(q, a2, g->p[3]);
+        /* annulus: p = (centre, R_in, R_out) */
+        double r_out = inside_ball_radius(q, a2, g->p[3]);
+        double r_in = outside_ball_radius(q, a2, g->p[2]);
+        if (r_in < d) r_in = d;
+        return r_out < r_in ? r_out : r_in;
+    }
     double best = INFINITY;
     for (int a = 0; a < dim; ++a) {
         double cn = 0.0;
@@ -374,6 +424,24 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
         if (hi < best) best = hi;
     }
     return best;
+}
+
+static int radius_mode_valid(const og_geom *g, int mode)
+{
+    if (mode == 0) return 1;
+    if (mode == 1) return g->kind == OG_BOX;
+    if (mode == 2) return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL;
+    return 0;
+}
+
+/* Radius probe for tests: the step radius of mode `mode` at each of n points (NaN where the mode
+ * does not apply to the domain). */
+void oracle_step_radii(const og_geom *g, const double *S, int mode, const double *x, int32_t n, double *r_out)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        const double *p = x + (size_t)i * g->dim;
+        r_out[i] = radius_mode_valid(g, mode) ? step_radius(g, mode, S, p, oracle_dist(g, p)) : NAN;
+    }
 }
 
 typedef struct {
@@ -455,7 +523,7 @@ int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, doub
 {
     if (!g || !S || !counts || n_obs < 0 || walk_end < walk_begin || !(eps >= 0.0)) return -1;
     if (eps == 0.0 && max_steps == 0) return -1; /* the fixed-iteration loop needs its count */
-    if (radius_mode == 1 && g->kind != OG_BOX) return -1;
+    if (!radius_mode_valid(g, radius_mode)) return -1;
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
     og_job *jobs = (og_job *)calloc((size_t)n_threads, sizeof(og_job));
@@ -509,7 +577,7 @@ int oracle_walk_exits(const og_geom *g, const double *S, double eps, int radius_
 {
     if (!g || !S || !x0 || !pos_out || ke < kb || !(eps >= 0.0)) return -1;
     if (eps == 0.0 && max_steps == 0) return -1;
-    if (radius_mode == 1 && g->kind != OG_BOX) return -1;
+    if (!radius_mode_valid(g, radius_mode)) return -1;
     int dim = g->dim;
     for (uint64_t k = kb; k < ke; ++k) {
         double x[3] = { 0.0, 0.0, 0.0 }, U[3], y[3];

@@ -413,6 +413,117 @@ def test_mapped_exact_radius_same_law_fewer_steps():
     assert rep["ok"], rep
 
 
+def _random_spd(dim, cond, rng):
+    import scipy.stats as st_
+    Q = st_.special_ortho_group.rvs(dim, random_state=int(rng.integers(1 << 30)))
+    return Q @ np.diag(np.geomspace(1.0, cond, dim)) @ Q.T
+
+
+def _sphere_dirs(dim, n):
+    if dim == 2:
+        t = 2 * np.pi * (np.arange(n) + 0.5) / n
+        return np.stack([np.cos(t), np.sin(t)], 1)
+    z = 1 - (2 * np.arange(n) + 1) / n
+    phi = np.pi * (3 - np.sqrt(5)) * np.arange(n)
+    rr = np.sqrt(1 - z * z)
+    return np.stack([rr * np.cos(phi), rr * np.sin(phi), z], 1)
+
+
+@pytest.mark.parametrize("case", ["disk", "annulus", "ball"])
+def test_mapped_bound_radius_keeps_the_ellipsoid_inside(case):
+    """Mapped bound (radius mode 2): brute force over the ellipsoid's boundary x + r S u, |u| = 1,
+    shows it inside the outer circle / sphere and, for the annulus, outside the inner circle (whose
+    centre stays outside the ellipsoid); r >= dist everywhere, r = dist when S = I, and for an
+    anisotropic S the radius is larger than dist on average (a bound with |x - c| in place of
+    |S (x - c)|, or a halved denominator of the inner bound, fails one of these)."""
+    rng = np.random.default_rng({"disk": 1, "annulus": 2, "ball": 3}[case])
+    if case == "disk":
+        g = wi.Geometry(2, wi.DISK, (0.2, -0.1, 1.3), (8,))
+    elif case == "annulus":
+        g = wi.Geometry(2, wi.ANNULUS, (0.1, 0.2, 0.3, 1.0), (8, 8))
+    else:
+        g = wi.Geometry(3, wi.BALL, (0.1, -0.2, 0.3, 0.9), (4, 4))
+    dim = g.dim
+    c = np.asarray(g.params[:dim])
+    R = g.params[dim] if case != "annulus" else g.params[3]
+    x = wi.sample_points(g, 400, rng)
+    # and points in the boundary layers, where the bound matters most
+    dirs = _sphere_dirs(dim, 200)
+    x = np.concatenate([x, c + dirs * (R - rng.uniform(1e-5, 1e-2, (200, 1)))])
+    if case == "annulus":
+        x = np.concatenate([x, c + dirs * (0.3 + rng.uniform(1e-5, 1e-2, (200, 1)))])
+    U = _sphere_dirs(dim, 4096 if dim == 2 else 20000)
+    gain = []
+    for cond in (1.0, 4.0, 20.0):
+        K = _random_spd(dim, cond, rng)
+        _, _, S = walks.instance_setup(K, dim)
+        Sd = S[:dim, :dim]
+        r = walks.step_radii(g, S, x, 2)
+        d, _ = walks.geom_eval(g, x)
+        assert np.all(r >= d * (1 - 1e-12)), (cond, (r - d).min())
+        if cond == 1.0:
+            np.testing.assert_allclose(r, d, rtol=1e-10, atol=1e-14)
+        else:
+            gain.append(np.mean(r / d))
+        Sinv = np.linalg.inv(Sd)
+        for i in range(len(x)):
+            pts = x[i] + r[i] * (U @ Sd.T) - c
+            rho = np.sqrt((pts ** 2).sum(1))
+            assert rho.max() <= R * (1 + 1e-12), (cond, i, rho.max() - R)
+            if case == "annulus":
+                assert rho.min() >= 0.3 * (1 - 1e-12), (cond, i, rho.min())
+                assert np.linalg.norm(Sinv @ (c - x[i])) > r[i]
+    assert min(gain) > 1.15, gain
+
+
+def test_mapped_bound_radius_same_law_fewer_steps():
+    """The mapped-bound chain has the exit law of the WoE-bound chain (the two estimates agree within
+    their sampling error) and takes far fewer steps on the anisotropic annulus."""
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.3, 1.0), (16, 16))
+    K = np.array([[1.0, 0.5], [0.5, 2.0]])
+    x = wi.sample_points(g, 6, np.random.default_rng(21))
+    N = 20_000
+    c0, s0, _ = walks.build_measure(g, K, x, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c2, s2, _ = walks.build_measure(g, K, x, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=2)
+    assert s2["steps"] < 0.6 * s0["steps"], (s0["steps"], s2["steps"])
+    assert s2["escapes"] == 0
+    rep = statutil.two_sample(c0, N, c2, N)
+    assert rep["ok"], rep
+
+
+def test_mapped_bound_reproduces_harmonic_functions():
+    """E u(X_N) = u(x) under the mapped-bound chain: the paper's K-harmonic 2D-sol4 on an annulus and
+    3D-sol1 composed with K^{-1/2} in an anisotropic ball."""
+    K = np.array([[1.0, 0.3], [0.3, 0.4]])
+    u = _sol4(K)
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.5, 1.0), (8, 8))
+    x = wi.sample_points(g, 8, np.random.default_rng(7))
+    _, _, S = walks.instance_setup(K, 2)
+    z = _exit_mean_z(g, S, x, u, 40_000, grad_bound=3.0, radius_mode=2)
+    assert np.all(z < 4.5), z
+    import scipy.stats as st_
+    Q = st_.special_ortho_group.rvs(3, random_state=3)
+    K3 = Q @ np.diag([1.0, 2.0, 6.0]) @ Q.T
+    Kis = wi.spd_inv_sqrt(K3)
+    def u3(p):
+        y = p @ Kis.T
+        return y[:, 0] * y[:, 1] + y[:, 1] ** 2 - y[:, 2] ** 2
+    gb = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (4, 4))
+    xb = wi.sample_points(gb, 6, np.random.default_rng(10))
+    _, _, S3 = walks.instance_setup(K3, 3)
+    assert np.all(_exit_mean_z(gb, S3, xb, u3, 30_000, grad_bound=6.0, radius_mode=2) < 4.5)
+
+
+def test_radius_modes_rejected_where_they_do_not_apply():
+    g = wi.Geometry(2, wi.POLYGON, (), (16,), verts=wi.L_SHAPE)
+    assert np.isnan(walks.step_radii(g, np.eye(3), [[0.5, 0.5]], 2)).all()
+    with pytest.raises(ValueError):
+        walks.walk_exits(g, np.eye(3), [0.5, 0.5], 1e-4, 4, radius_mode=2)
+    gb = wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 1.0), (4,))
+    with pytest.raises(ValueError):
+        walks.walk_exits(gb, np.eye(3), [0.5, 0.5], 1e-4, 4, radius_mode=3)
+
+
 # ---------------------------------------------------------------- exact invariants
 
 def test_row_sums_threads_and_resume_exact():

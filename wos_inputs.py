@@ -43,6 +43,7 @@ FP64 = 0
 FP32_GEOM_FP64_EXIT = 1
 RADIUS_WOE_BOUND = 0
 RADIUS_MAPPED_EXACT = 1
+RADIUS_MAPPED_BOUND = 2   # discs, annuli, balls: support bound of the inscribed ellipsoid
 
 
 @dataclasses.dataclass
@@ -365,7 +366,7 @@ def spherical_shell_example(example: int = 6, n_walks: int = 10_000, eps: float 
 
 
 def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP32_GEOM_FP64_EXIT,
-                 eta: float = 0.01) -> Instance:
+                 eta: float = 0.01, radius_mode: int = RADIUS_WOE_BOUND) -> Instance:
     """2D annulus r in [0.3, 1], K = [[1, .5], [.5, 2]], 128 + 128 arcs, 1024 points uniform by area.
 
     Gamma_0 = outer arcs with angle in [0, pi); Gamma_1 = the rest.  Data u = Re(z^3) in mapped
@@ -379,7 +380,7 @@ def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP3
     th = rng.uniform(0, 2 * np.pi, n_obs)
     x = np.stack([r * np.cos(th), r * np.sin(th)], 1)
     K = np.array([[1.0, 0.5], [0.5, 2.0]])
-    inst = Instance(g, K, x, n_walks, eps=1e-4, seed=0, precision=precision,
+    inst = Instance(g, K, x, n_walks, eps=1e-4, seed=0, precision=precision, radius_mode=radius_mode,
                     name="annulus256_Kaniso_1024pts")
     ref = element_ref_points(g)
     u_ref = harmonic_re_z3(ref, K)
