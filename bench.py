@@ -341,9 +341,9 @@ def main():
     latency_ms = float(np.median(lat))
 
     # the walk kernel alone on the whole device: HIP events on the launch stream
-    def time_walks(precision, reps):
+    def time_walks(precision, reps, radius_mode=None):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        w = wos.walk_params_of(inst, precision=precision)
+        w = wos.walk_params_of(inst, precision=precision, radius_mode=radius_mode)
         ms = []
         for r in range(reps + 1):
             counts.zero_()
@@ -371,6 +371,17 @@ def main():
                 "method": "gram" if method == wos.WOS_SVD_GRAM else "hestenes"}
     full_ms, st32 = time_walks(wi.FP32_GEOM_FP64_EXIT, 3)
     walk64_ms, st64 = time_walks(wi.FP64, 3)
+    # the same workload with the mapped-bound radius (a larger inscribed ellipsoid per step, same exit
+    # law): walk kernel alone, and the reconstruction from its counts
+    mb_ms, stmb = time_walks(wi.FP32_GEOM_FP64_EXIT, 3, radius_mode=wos.WOS_RADIUS_MAPPED_BOUND)
+    wos.wos_svd(ctx, h, counts, inst.n_walks, stream)
+    wos.wos_reconstruct(ctx, h, counts, inst.n_walks, uD, u0, reg, u1, pred, rank, None, stream)
+    err_mb = float(np.abs(u1.cpu().numpy() - inst.u_exact_g1).max() / np.abs(inst.u_exact_g1).max())
+    mapped_bound = {"fp32_ms": mb_ms, "fp32_walks_per_s": walks_step / (mb_ms * 1e-3),
+                    "mean_steps_per_walk": stmb["steps"] / walks_step,
+                    "woe_bound_mean_steps_per_walk": st32["steps"] / walks_step,
+                    "escapes": stmb["escapes"], "max_rel_err_u1": err_mb, "rank": int(rank.item())}
+    log(f"mapped-bound radius: walk kernel {mb_ms:.3f} ms, {mapped_bound['mean_steps_per_walk']:.2f} steps/walk")
     ops = steps_step * OPS_PER_STEP_2D_FP32 + walks_step * OPS_PER_WALK
     achieved = ops / (walk_ms * 1e-3)
     traffic, traffic_detail = measured_traffic(tuned)
@@ -407,6 +418,7 @@ def main():
                         "fp32_fp64_evals": st32["fp64_evals"], "escapes": st32["escapes"] + st64["escapes"]},
         "svd": svd_info,
         "reconstruction": {"rank": rank_used, "max_rel_err_u1": err},
+        "mapped_bound_radius": mapped_bound,
         "roofline": roof,
     }
     if not a.no_serve:

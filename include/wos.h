@@ -130,7 +130,16 @@ wos_status wos_element_measures(const wos_geometry *geom, double *sigma_host);
 /* Measure building (Algorithm MC-REM)                                                           */
 /* ------------------------------------------------------------------------------------------- */
 typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
-typedef enum { WOS_RADIUS_WOE_BOUND = 0, WOS_RADIUS_MAPPED_EXACT = 1 } wos_radius_mode;
+/* Step radius r of X + r S U (S = (K / lambda_max)^{1/2}).  The chain of Section 4.2 is the trace
+ * of the diffusion on ellipsoids inscribed in D, so any r whose ellipsoid X + r S B(0,1) lies in D
+ * gives the same exit law; larger radii give shorter walks.
+ *   WOE_BOUND     r = dist(X, dD), the radius of eq. "wos chain" (every domain).
+ *   MAPPED_EXACT  boxes only: the largest inscribed radius, min over faces of gap_a / |S e_a|.
+ *   MAPPED_BOUND  discs, annuli, balls: with v = X - c and a = |S v|, r = sqrt(a^2 + R^2 - |v|^2) - a
+ *                 for the outer circle or sphere of radius R; for the inner circle of an annulus
+ *                 max((|v|^2 - R_in^2) / (2 a), dist); r is the smaller.  Equal to dist when S = I.
+ * Other combinations return WOS_ENOTSUP. */
+typedef enum { WOS_RADIUS_WOE_BOUND = 0, WOS_RADIUS_MAPPED_EXACT = 1, WOS_RADIUS_MAPPED_BOUND = 2 } wos_radius_mode;
 
 typedef struct {
     double K[9];          /* conductivity, row-major, leading dim x dim block; symmetric positive
@@ -144,7 +153,7 @@ typedef struct {
     uint64_t seed;        /* Philox key (low word, high word) */
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */
-    int32_t radius_mode;  /* wos_radius_mode; MAPPED_EXACT only for WOS_BOX */
+    int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes; MAPPED_BOUND: discs, annuli, balls) */
     uint32_t max_steps;   /* step cap S_max (0 -> 10000, must be < 2^31); capped walks are binned where they are */
 } wos_walk_params;
 

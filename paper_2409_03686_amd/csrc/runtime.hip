@@ -440,10 +440,14 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->max_steps >= (1u << 31)) return set_error(WOS_EINVAL, "max_steps must be below 2^31");
     if (w->precision != WOS_FP64 && w->precision != WOS_FP32_GEOM_FP64_EXIT)
         return set_error(WOS_EINVAL, "unknown precision %d", w->precision);
-    if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT)
+    if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT &&
+        w->radius_mode != WOS_RADIUS_MAPPED_BOUND)
         return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX)
         return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes only");
+    if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
+        g->kind != WOS_BALL)
+        return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs, annuli and balls only");
     return WOS_OK;
 }
 
@@ -525,6 +529,22 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             // FP32 rounding moves these by 2^-24 relative at most, well inside the 2^-16 shrink
             I.fold_rs[a] = static_cast<float>(A * (1.0 - 0x1.0p-16));
             I.fold_rn[a] = static_cast<float>(A * static_cast<double>(I.neg2delta));
+        }
+    }
+    if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
+        // FP32 mapped bound (centred positions, |v| <= R_out): R_out^2, R_in^2 and absolute error
+        // bounds of the two radii, subtracted on the device so that they never exceed the exact ones.
+        // With u = 2^-24 and s = sigma_min(S) = (lambda_min / lambda_max)^{1/2}: |S v| and |v|^2
+        // carry about 6 u |v| and 3 u R_out^2; sqrt(a^2 + R^2 - |v|^2) >= s R_out turns the latter into
+        // 1.5 u R_out / s; the inner bound divides by 2 a >= 2 s R_in.  Twice the estimates are used.
+        const double u = 0x1.0p-24, sg = std::sqrt(lmin / lmax);
+        const double Ro = g->kind == WOS_ANNULUS ? g->params[3] : g->params[g->dim];
+        I.mbf[0] = static_cast<float>(Ro * Ro);
+        I.mbf[1] = static_cast<float>(u * Ro * (16.0 / sg + 16.0));
+        if (g->kind == WOS_ANNULUS) {
+            const double Ri = g->params[2];
+            I.mbf[2] = static_cast<float>(Ri * Ri);
+            I.mbf[3] = static_cast<float>(u * (4.0 * Ro * Ro / (sg * Ri) + Ro * (22.0 / sg + 20.0)));
         }
     }
     // thresholds rounded outward so that the certain-exit test stays certain after rounding
@@ -711,9 +731,14 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     gl.n_inst = n;
     gl.items = items;
     gl.block = tn.block;
-    gl.kind_sel = jobs[idx[0]].geom.kind;
+    // one kind (and radius variant) for the whole launch: compiled in; else read per instance
+    auto kernel_kind = [&](int q) {
+        const wos_measure_job &j = jobs[idx[q]];
+        return j.geom.kind + (j.walk.radius_mode == WOS_RADIUS_MAPPED_BOUND ? kRadiusVariant : 0);
+    };
+    gl.kind_sel = kernel_kind(0);
     for (int q = 1; q < n; ++q)
-        if (jobs[idx[q]].geom.kind != gl.kind_sel) gl.kind_sel = -1;
+        if (kernel_kind(q) != gl.kind_sel) gl.kind_sel = -1;
     const size_t lds = walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, gl.mode);
     if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;

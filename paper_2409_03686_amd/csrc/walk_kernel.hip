@@ -201,14 +201,14 @@ struct Fold32 {
 // bit 31 of s is set.  CAP = false when no walk of the wave can reach the cap within this Philox
 // block; then s is not advanced here (the caller adds the block's steps at its end and PH + 1 for
 // a walk that stops inside it).
-template <typename R, int DIM, int KIND, int PH, bool CAP>
+template <typename R, int DIM, int KIND, int PH, bool CAP, int RV>
 __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], const Fold32 &F,
                                           R *x, R &d, uint32_t &s, uint32_t &n_fp64)
 {
     if constexpr (sizeof(R) == 8) {
         R U[DIM];
         Dir<R, DIM>::template get<PH>(w, U);
-        const double r = radius64<KIND, DIM>(I, x, d);
+        const double r = radius64<KIND, DIM, RV>(I, x, d);
         step64<DIM>(I, x, r, U);
         d = dist64<KIND, DIM>(I, x, segs);
         s += 1;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
     } else {
         // conservative radius: below the true distance by more than the FP32 distance error
         // (2 delta) and the direction's norm error (relative 2^-16)
-        const float rr = radius32<KIND, DIM>(I, x, d);
+        const float rr = radius32<KIND, DIM, RV>(I, x, d);
         if constexpr (DIM == 2) {
             const float t = static_cast<float>(w[PH] >> 8);
             const float c0 = __builtin_amdgcn_cosf(__builtin_fmaf(t, 0x1.0p-24f, F.off0));
@@ -254,7 +254,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
 // PTS (point mode): the block runs point `point` with no fixed walk range; its waves reserve the
 // point's walks I.chunk at a time from the point's walk cursor *pcur until it passes N, so the
 // lanes drain only when the point's walks run out (several blocks may share a point).
-template <typename R, int DIM, int KIND, bool PTS = false>
+template <typename R, int DIM, int KIND, bool PTS = false, int RV = -1>
 __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint32_t k0, uint32_t cnt, uint32_t *hist,
                          PolySeg *lds_segs, uint8_t *qbase, BlockShared &sh, uint32_t *pcur = nullptr)
 {
@@ -395,7 +395,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
-                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
+                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64);
                 const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
                 fph = fin ? static_cast<uint32_t>(PH) : fph;
                 d = fin ? kFree : d;
@@ -516,7 +516,7 @@ struct WaveCtl {
 };
 constexpr size_t kWaveCtlBytes = 32;
 
-template <typename R, int DIM, int KIND>
+template <typename R, int DIM, int KIND, int RV = -1>
 __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, uint32_t *cursor, uint64_t total_items,
                               uint32_t *rows, int hist_words, PolySeg *lds_segs, uint8_t *qb, LaneStats &ls,
                               uint32_t &n_fp64, unsigned long long &wave_iters)
@@ -686,7 +686,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
         auto phase = [&](auto ph_tag, auto cap_tag) {
             constexpr int PH = decltype(ph_tag)::value;
             constexpr bool CAP = decltype(cap_tag)::value;
-            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP>(I, segs, w, F, x, d, s, n_fp64);
+            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64);
             const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
             fph = fin ? static_cast<uint32_t>(PH) : fph;
             d = fin ? kFree : d;
@@ -817,11 +817,15 @@ __device__ uint32_t steal_point(const DevInst *insts, int n_inst, uint32_t total
 // MODE 0: block-item mode (run_item over items).  1: wave-item mode (run_chain); LDS holds, per
 // wave, two histogram rows, the staged segments and the stop queue.  2: point mode (run_item over
 // points with walk reservations; cursor[2 + p] is point p's walk cursor).
+// KSEL: -1 for launches that mix kinds (kind and radius mode read per instance), else the kind plus
+// kRadiusVariant when the launch uses the mapped-bound radius, both then fixed at compile time.
 template <typename R, int DIM, int KSEL, int MODE>
 __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
                                                     uint64_t total_items, uint32_t *cursor,
                                                     int hist_words, int seg_bytes)
 {
+    constexpr int KK = KSEL >= 0 ? KSEL % kRadiusVariant : -1;
+    constexpr int RV = KSEL >= 0 ? KSEL / kRadiusVariant : -1;
     extern __shared__ __align__(16) uint8_t smem[];
     if constexpr (MODE == 1) {
         const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
@@ -840,10 +844,10 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
         uint64_t item = __builtin_amdgcn_readfirstlane(it0);
         while (item < total_items) {
             const DevInst &I = insts[instance_of(insts, n_inst, item)];
-            const int kind = KSEL >= 0 ? KSEL : I.kind;
+            const int kind = KSEL >= 0 ? KK : I.kind;
             const uint64_t first = item;
             if constexpr (KSEL >= 0) {
-                item = run_chain<R, DIM, KSEL>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters);
+                item = run_chain<R, DIM, KK, RV>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters);
             } else if constexpr (DIM == 2) {
                 switch (kind) {
                 case kDisk: item = run_chain<R, 2, kDisk>(I, first, cursor, total_items, rows, hist_words, segs_w, qb, ls, n_fp64, wave_iters); break;
@@ -888,7 +892,7 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
             const DevInst &I = insts[idx];
             const uint32_t point = p - static_cast<uint32_t>(I.item_begin);
             if constexpr (KSEL >= 0) {
-                run_item<R, DIM, KSEL, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p);
+                run_item<R, DIM, KK, true, RV>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p);
             } else if constexpr (DIM == 2) {
                 switch (I.kind) {
                 case kDisk: run_item<R, 2, kDisk, true>(I, point, 0, 0, hist, lds_segs, qbase, sh, pcur + p); break;
@@ -940,7 +944,7 @@ __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ 
             cnt = min(I.chunk, I.n_walks - k0);
         }
         if constexpr (KSEL >= 0) {
-            run_item<R, DIM, KSEL>(I, point, k0, cnt, hist, lds_segs, qbase, sh);
+            run_item<R, DIM, KK, false, RV>(I, point, k0, cnt, hist, lds_segs, qbase, sh);
         } else if constexpr (DIM == 2) {
             switch (I.kind) {
             case kDisk: run_item<R, 2, kDisk>(I, point, k0, cnt, hist, lds_segs, qbase, sh); break;
@@ -992,6 +996,8 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
         switch (ksel) {
         case kDisk: return kptr<R, 2, kDisk>(wave);
         case kAnnulus: return kptr<R, 2, kAnnulus>(wave);
+        case kRadiusVariant + kDisk: return kptr<R, 2, kRadiusVariant + kDisk>(wave);
+        case kRadiusVariant + kAnnulus: return kptr<R, 2, kRadiusVariant + kAnnulus>(wave);
         case kEllipse: return kptr<R, 2, kEllipse>(wave);
         case kPolygon: return kptr<R, 2, kPolygon>(wave);
         case kPerforated: return kptr<R, 2, kPerforated>(wave);
@@ -1002,6 +1008,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
     }
     switch (ksel) {
     case kBall: return kptr<R, 3, kBall>(wave);
+    case kRadiusVariant + kBall: return kptr<R, 3, kRadiusVariant + kBall>(wave);
     case kPerforated: return kptr<R, 3, kPerforated>(wave);
     case kPerfBox: return kptr<R, 3, kPerfBox>(wave);
     case kBox: return kptr<R, 3, kBox>(wave);

@@ -50,6 +50,7 @@ struct alignas(16) DevInst {
     float fold_off[2];  // 2^-25 - phi_a: the angle of coordinate a is (w >> 8) 2^-24 + fold_off[a]
     float fold_rs[2];   // A_a (1 - 2^-16)
     float fold_rn[2];   // A_a (-2 delta): step of coordinate a = (r fold_rs + fold_rn) cos(angle)
+    float mbf[4];       // mapped-bound radius (FP32): R_out^2, its error bound, R_in^2, its error bound
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call
@@ -344,10 +345,46 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 
 // Step radius.  WoE bound: r = dist (the ellipsoid x + r S B(0,1) lies in B(x, r) since |S| <= 1).
 // Mapped exact (boxes): the largest r with x + r S B(0,1) inside the box, min_a gap_a / |S e_a|.
-template <int KIND, int DIM> __device__ __forceinline__ double radius64(const DevInst &I, const double *x,
-                                                                        double d)
+// Mapped bound (discs, annuli, balls): with v = x - c and a = |S v|, |v + r S u|^2 lies between
+// |v|^2 - 2 r a and |v|^2 + 2 r a + r^2 for |u| <= 1, so r_out = sqrt(a^2 + R^2 - |v|^2) - a keeps the
+// ellipsoid inside the circle / sphere of radius R and r_in = (|v|^2 - R_in^2) / (2 a) keeps it off
+// the inner circle of an annulus, where dist is valid as well: r = min(r_out, max(r_in, dist)).
+// RV: the radius variant of a launch, fixed at compile time (0: dist, or the box's radius by its mode;
+// 1: mapped bound) or -1: read the instance's radius mode.  A launch-wide kind selector adds
+// kRadiusVariant to the kind for the mapped bound.
+constexpr bool mapped_bound_kind(int kind) { return kind == kDisk || kind == kAnnulus || kind == kBall; }
+constexpr int kRadiusVariant = 16;
+
+template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(const DevInst &I, const double *x,
+                                                                                double d)
 {
 #pragma clang fp contract(off)
+    if constexpr (mapped_bound_kind(KIND) && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {
+            double v[DIM], q = 0.0, a2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                v[a] = x[a] - I.p[a];
+                q += v[a] * v[a];
+            }
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                double w = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) w += I.S[r * 3 + a] * v[a];
+                a2 += w * w;
+            }
+            const double R = KIND == kAnnulus ? I.p[3] : I.p[DIM];
+            const double r_out = __builtin_sqrt(a2 + (R * R - q)) - __builtin_sqrt(a2);
+            if constexpr (KIND != kAnnulus) {
+                return r_out;
+            } else {
+                double r_in = (q - I.p[2] * I.p[2]) / (2.0 * __builtin_sqrt(a2));
+                if (r_in < d) r_in = d;
+                return r_out < r_in ? r_out : r_in;
+            }
+        }
+    }
     if constexpr (KIND == kBox) {
         if (I.radius_mode == 1) {
             double best = __builtin_inf();
@@ -362,9 +399,39 @@ template <int KIND, int DIM> __device__ __forceinline__ double radius64(const De
     return d;
 }
 
-template <int KIND, int DIM> __device__ __forceinline__ float radius32(const DevInst &I, const float *x,
-                                                                       float d)
+// FP32 form of the mapped bound on centred positions; the error bounds in mbf are subtracted.
+template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(const DevInst &I, const float *x,
+                                                                               float d)
 {
+    if constexpr (mapped_bound_kind(KIND) && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {
+            float q, a2;
+            if constexpr (DIM == 2) {
+                q = __builtin_fmaf(x[0], x[0], x[1] * x[1]);
+                const float w0 = __builtin_fmaf(I.Sf[0], x[0], I.Sf[1] * x[1]);
+                const float w1 = __builtin_fmaf(I.Sf[3], x[0], I.Sf[4] * x[1]);
+                a2 = __builtin_fmaf(w0, w0, w1 * w1);
+            } else {
+                q = __builtin_fmaf(x[2], x[2], __builtin_fmaf(x[1], x[1], x[0] * x[0]));
+                a2 = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float w = __builtin_fmaf(I.Sf[r * 3 + 2], x[2],
+                                                   __builtin_fmaf(I.Sf[r * 3 + 1], x[1], I.Sf[r * 3] * x[0]));
+                    a2 = __builtin_fmaf(w, w, a2);
+                }
+            }
+            const float s = __builtin_amdgcn_sqrtf(a2 + (I.mbf[0] - q));
+            if constexpr (KIND == kAnnulus) {
+                const float rq = __builtin_amdgcn_rsqf(a2);  // a2 >= (sigma_min R_in)^2 > 0
+                const float r_out = s - __builtin_fmaf(a2, rq, I.mbf[1]);
+                const float r_in = __builtin_fmaf(q - I.mbf[2], 0.5f * rq, -I.mbf[3]);
+                return __builtin_fminf(r_out, __builtin_fmaxf(r_in, d));
+            } else {
+                return s - (__builtin_amdgcn_sqrtf(a2) + I.mbf[1]);
+            }
+        }
+    }
     if constexpr (KIND == kBox) {
         if (I.radius_mode == 1) {
             float best = __builtin_inff();

@@ -71,7 +71,8 @@ size_t walk_lds_bytes(int precision, int dim, int block, int hist_words, int seg
 // 32-bit words of the launch's cursors (zeroed by launch_walks): the item / point cursor, a spare
 // word, and in point mode one walk cursor per point.
 size_t walk_cursor_words(int mode, uint64_t total_items);
-// kind_sel: the domain kind shared by all instances of the launch, or -1 when they differ
+// kind_sel: the domain kind shared by all instances of the launch (plus kRadiusVariant when they all
+// use the mapped-bound radius), or -1 when they differ
 const void *walk_kernel_ptr(int precision, int dim, int kind_sel, int mode);
 hipError_t launch_walks(int precision, int dim, int kind_sel, int mode, const DevInst *insts, int n_inst,
                         uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,

@@ -46,7 +46,7 @@ struct GroupLaunch {
     int per_cu = 1;  // resident blocks per CU (grid = per_cu x CUs of the launch stream, at most items)
     int hist_words = 4, seg_bytes = 0;
     int precision = 0, dim = 2;
-    int kind_sel = -1;  // shared domain kind of the instances, -1 if mixed
+    int kind_sel = -1;  // shared domain kind (+ kRadiusVariant for the mapped bound), -1 if mixed
     int mode = 0;       // 0 block items, 1 wave items, 2 points (walk_lds_bytes)
 };
 

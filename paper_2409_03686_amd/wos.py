@@ -20,7 +20,7 @@ WOS_OK, WOS_EINVAL, WOS_ENOMEM, WOS_EDEVICE, WOS_EBUSY, WOS_ETIMEOUT, WOS_ENOTSU
 STATUS_NAMES = ["WOS_OK", "WOS_EINVAL", "WOS_ENOMEM", "WOS_EDEVICE", "WOS_EBUSY", "WOS_ETIMEOUT",
                 "WOS_ENOTSUP", "WOS_ECANCELLED"]
 WOS_FP64, WOS_FP32_GEOM_FP64_EXIT = 0, 1
-WOS_RADIUS_WOE_BOUND, WOS_RADIUS_MAPPED_EXACT = 0, 1
+WOS_RADIUS_WOE_BOUND, WOS_RADIUS_MAPPED_EXACT, WOS_RADIUS_MAPPED_BOUND = 0, 1, 2
 WOS_TSVD_RANK, WOS_TSVD_DISCREPANCY, WOS_TIKHONOV = 0, 1, 2
 WOS_STATS_WORDS = 8
 STAT_NAMES = ["walks", "steps", "max_steps", "cap_hits", "escapes", "fp64_evals", "lane_slots", "reserved"]
@@ -383,12 +383,13 @@ def wos_serve_stop(ctx):
 
 # ------------------------------------------------------------------------------- torch helpers
 
-def walk_params_of(inst, walk_begin=0, walk_end=None, precision=None) -> WosWalkParams:
+def walk_params_of(inst, walk_begin=0, walk_end=None, precision=None, radius_mode=None) -> WosWalkParams:
     """wos_walk_params of a wos_inputs.Instance."""
     return walk_params(inst.K, inst.eps, walk_begin, inst.n_walks if walk_end is None else walk_end,
                        seed=inst.seed, instance=inst.instance_id,
                        precision=inst.precision if precision is None else precision,
-                       radius_mode=inst.radius_mode, max_steps=inst.max_steps)
+                       radius_mode=inst.radius_mode if radius_mode is None else radius_mode,
+                       max_steps=inst.max_steps)
 
 
 def device_inputs(inst, device="cuda"):

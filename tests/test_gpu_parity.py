@@ -83,6 +83,9 @@ def _kind_cases():
         "cube_woe": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 0),
         "cube_exact": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 1),
         "ball_aniso": (wi.Geometry(3, wi.BALL, (0.0, 0.1, 0.0, 1.0), (6, 10)), K3, 0),
+        "disk_mapped_bound": (wi.Geometry(2, wi.DISK, (0.2, -0.1, 1.3), (37,)), K2, 2),
+        "annulus_mapped_bound": (wi.Geometry(2, wi.ANNULUS, (0.1, -0.05, 0.3, 1.0), (40, 24)), K2, 2),
+        "ball_mapped_bound": (wi.Geometry(3, wi.BALL, (0.0, 0.1, 0.0, 1.0), (6, 10)), K3, 2),
         "perforated_aniso": (wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (40, 12, 3),
                                          verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])),
                              K2, 0),
@@ -174,6 +177,38 @@ def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
     rep2 = statutil.two_sample(c32[rows], inst.n_walks, cr, inst.n_walks)
     print("FP32 vs independent oracle rows", rep2)
     assert rep2["ok"]
+
+
+@pytest.mark.parametrize("case", ["annulus", "ball"])
+def test_fp32_mapped_bound_vs_oracle(wos, ctx, case):
+    """Mapped-bound radius with FP32 geometry: no escapes (the radius stays certified after its FP32
+    error bound is taken off), counts against the FP64 path and the oracle, and the shorter walks
+    against the WoE-bound chain on the same workload."""
+    if case == "annulus":
+        inst = wi.cfg2_annulus(n_walks=40_000, n_obs=96, precision=wi.FP32_GEOM_FP64_EXIT,
+                               radius_mode=wi.RADIUS_MAPPED_BOUND)
+    else:
+        g, K, _ = _kind_cases()["ball_mapped_bound"]
+        inst = wi.Instance(g, K, wi.sample_points(g, 48, np.random.default_rng(4)), 40_000, eps=1e-4, seed=9,
+                           precision=wi.FP32_GEOM_FP64_EXIT, radius_mode=wi.RADIUS_MAPPED_BOUND)
+    c32, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0 and st["cap_hits"] == 0
+    c64, st64, _ = _gpu(wos, ctx, inst, precision=wi.FP64)
+    rep = statutil.two_sample(c32, inst.n_walks, c64, inst.n_walks)
+    print(f"{case} mapped bound FP32 vs FP64", rep)
+    assert rep["ok"]
+    assert abs(st["steps"] - st64["steps"]) <= 0.02 * st64["steps"]
+    rows = [0, 17, 40]
+    cr, sr, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed + 1,
+                                 radius_mode=2, walk_end=inst.n_walks, point_ids=rows)
+    rep2 = statutil.two_sample(c32[rows], inst.n_walks, cr, inst.n_walks)
+    print(f"{case} mapped bound FP32 vs independent oracle rows", rep2)
+    assert rep2["ok"]
+    inst.radius_mode = wi.RADIUS_WOE_BOUND
+    c0, st0, _ = _gpu(wos, ctx, inst)
+    rep3 = statutil.two_sample(c32, inst.n_walks, c0, inst.n_walks)
+    print(f"{case} mapped bound vs WoE bound: steps {st['steps']} vs {st0['steps']}", rep3)
+    assert rep3["ok"] and st["steps"] < 0.8 * st0["steps"]
 
 
 def test_perforated_disc_example(wos, ctx):
@@ -297,6 +332,9 @@ def test_batch_equals_separate_and_oracle(wos, ctx, items):
     for k, inst in enumerate(insts):  # keep the CPU side small
         inst.x_obs = inst.x_obs[:24]
         inst.n_walks = min(inst.n_walks, 400)
+        if k % 2 and inst.geom.kind in (wi.DISK, wi.ANNULUS, wi.BALL):
+            inst.radius_mode = wi.RADIUS_MAPPED_BOUND  # per-instance radius modes in the mixed launch
+    assert any(inst.radius_mode == wi.RADIUS_MAPPED_BOUND for inst in insts)
     sep = [_gpu(wos, ctx, inst)[0] for inst in insts]
     jobs, keep = [], []
     for inst in insts:
@@ -393,6 +431,9 @@ def test_invalid_arguments_raise(wos, ctx):
         (g, wos.walk_params(np.array([[1, 0.5], [0.0, 1.0]]), 1e-4, 0, 10)),  # not symmetric
         (g, wos.walk_params(np.eye(2), 1e-4, 10, 5)),                       # empty range reversed
         (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=1)),        # mapped-exact on a disk
+        (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=3)),        # unknown radius mode
+        (wi.Geometry(2, wi.ELLIPSE, (0, 0, 1.0, 0.5), (8,)),
+         wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=2)),             # mapped-bound on an ellipse
         (wi.Geometry(2, wi.ANNULUS, (0, 0, 1.0, 0.5), (4, 4)), wos.walk_params(np.eye(2), 1e-4, 0, 10)),
         (g, wos.walk_params(np.eye(2), 1e-4, 0, (1 << 32) + 1)),
     ]
