@@ -12,8 +12,8 @@
  *     X_0 = x_i;  X_{n+1} = X_n + r(X_n) * S * U_n,  U_n uniform on the unit sphere,
  *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
  *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
- *   radius: r = dist(x, dD) ("WoE bound"), or, for boxes, the largest r with x + r S B(0,1) inside D
- *   ("mapped exact"), or, for discs, annuli and balls, a larger radius certified by a support bound
+ *   radius: r = dist(x, dD) ("WoE bound"), or, for boxes and polygons, the largest r with
+ *   x + r S B(0,1) inside D ("mapped exact"), or, for discs, annuli and balls, a larger radius certified by a support bound
  *   ("mapped bound", see step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
  *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
@@ -395,14 +395,34 @@ static void centred_norms(int dim, const double *S, const double *x, const doubl
 /* Step radius.  Any ellipsoid x + r S B(0,1) inside D is a valid step of the chain (the chain is the
  * trace of the diffusion on inscribed ellipsoids, Section 4.2); the exit law does not depend on the
  * choice.  mode 0: r = dist (the ellipsoid lies in the Euclidean ball of radius r because
- * |S| <= 1).  mode 1 (boxes): r = min over faces of (face distance)/|S e_a|, the largest r whose
- * ellipsoid stays inside the box.  mode 2 (disc, annulus, ball): the bounds above for the outer
+ * |S| <= 1).  mode 1 (boxes, polygons): the largest r whose ellipsoid stays inside D -- for a box
+ * min over faces of (face distance)/|S e_a|, for a polygon the distance of S^{-1} x to the mapped
+ * edges.  mode 2 (disc, annulus, ball): the bounds above for the outer
  * circle or sphere and, for the annulus, the inner circle, where dist itself is also a valid bound
  * for the inner circle: r = min(r_out, max(r_in, d)). */
 static double step_radius(const og_geom *g, int mode, const double *S, const double *x, double d)
 {
     if (mode == 0) return d;
     int dim = g->dim;
+    if (mode == 1 && g->kind == OG_POLYGON) {
+        /* The ellipsoid is { z : |S^{-1}(z - x)| <= r }: it misses edge [a, b] exactly while r is
+         * below the distance from S^{-1} x to the mapped edge [S^{-1} a, S^{-1} b], and, being
+         * connected and centred in D, lies in D while it misses every edge.  The largest inscribed
+         * radius is the smallest of these distances.  S^{-1} by the 2 x 2 inverse formula. */
+        double det = S[0] * S[4] - S[1] * S[3];
+        double Si[4] = { S[4] / det, -S[1] / det, -S[3] / det, S[0] / det };
+        double y[2] = { Si[0] * x[0] + Si[1] * x[1], Si[2] * x[0] + Si[3] * x[1] };
+        double best = INFINITY, t;
+        for (int e = 0; e < g->n_verts; ++e) {
+            const double *a = g->verts + 2 * e;
+            const double *b = g->verts + 2 * ((e + 1) % g->n_verts);
+            double ma[2] = { Si[0] * a[0] + Si[1] * a[1], Si[2] * a[0] + Si[3] * a[1] };
+            double mb[2] = { Si[0] * b[0] + Si[1] * b[1], Si[2] * b[0] + Si[3] * b[1] };
+            double dd = seg_dist(ma, mb, y, &t);
+            if (dd < best) best = dd;
+        }
+        return best;
+    }
     if (mode == 2) {
         double q, a2;
         centred_norms(dim, S, x, g->p, &q, &a2);
@@ -429,7 +449,7 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
 static int radius_mode_valid(const og_geom *g, int mode)
 {
     if (mode == 0) return 1;
-    if (mode == 1) return g->kind == OG_BOX;
+    if (mode == 1) return g->kind == OG_BOX || g->kind == OG_POLYGON;
     if (mode == 2) return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL;
     return 0;
 }

@@ -514,14 +514,81 @@ def test_mapped_bound_reproduces_harmonic_functions():
     assert np.all(_exit_mean_z(gb, S3, xb, u3, 30_000, grad_bound=6.0, radius_mode=2) < 4.5)
 
 
+def _inside_polygon(P, V):
+    """Crossing-number point-in-polygon test (points P, vertices V counter-clockwise)."""
+    inside = np.zeros(len(P), bool)
+    for a, b in zip(V, np.roll(V, -1, 0)):
+        crosses = (a[1] > P[:, 1]) != (b[1] > P[:, 1])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xc = a[0] + (P[:, 1] - a[1]) * (b[0] - a[0]) / (b[1] - a[1])
+        inside ^= crosses & (P[:, 0] < xc)
+    return inside
+
+
+def test_polygon_mapped_exact_radius_is_the_largest_inscribed():
+    """Mapped-exact radius on the L-shape: the ellipsoid x + r S B(0,1) shrunk by 1e-9 lies inside
+    the polygon (brute force over its boundary), and a dense sampling of the polygon's edges finds a
+    point at mapped distance |S^{-1}(z - x)| within 1e-4 of r, so no larger ellipsoid fits; r >= dist,
+    r = dist for S = I."""
+    rng = np.random.default_rng(31)
+    V = np.asarray(wi.L_SHAPE, float)
+    g = wi.Geometry(2, wi.POLYGON, (), (24,), verts=V)
+    x = wi.sample_points(g, 150, rng)
+    # edge samples for the maximality check
+    Z = np.concatenate([a + np.linspace(0, 1, 20001)[:, None] * (b - a) for a, b in zip(V, np.roll(V, -1, 0))])
+    U = _sphere_dirs(2, 4096)
+    for cond in (1.0, 4.0, 20.0):
+        K = _random_spd(2, cond, rng)
+        _, _, S = walks.instance_setup(K, 2)
+        Sd = S[:2, :2]
+        r = walks.step_radii(g, S, x, 1)
+        d, _ = walks.geom_eval(g, x)
+        assert np.all(r >= d * (1 - 1e-12))
+        if cond == 1.0:
+            np.testing.assert_allclose(r, d, rtol=1e-12, atol=1e-15)
+        Si = np.linalg.inv(Sd)
+        for i in range(len(x)):
+            pts = x[i] + (r[i] * (1 - 1e-9)) * (U @ Sd.T)
+            assert _inside_polygon(pts, V).all(), (cond, i)
+            dz = np.sqrt((((Z - x[i]) @ Si.T) ** 2).sum(1))
+            k = int(np.argmin(dz))  # refine between the neighbouring samples
+            lo, hi = Z[max(k - 1, 0)], Z[min(k + 1, len(Z) - 1)]
+            Zf = lo + np.linspace(0, 1, 20001)[:, None] * (hi - lo)
+            md = min(dz[k], np.sqrt((((Zf - x[i]) @ Si.T) ** 2).sum(1)).min())
+            assert md <= r[i] * (1 + 1e-4) + 1e-12, (cond, i, md, r[i])
+
+
+def test_polygon_mapped_exact_same_law_fewer_steps():
+    """On the L-shape with an anisotropic K the mapped-exact chain has the WoE chain's exit law
+    and reproduces the paper's K-harmonic 2D-sol4, with fewer steps."""
+    K = np.array([[1.0, 0.3], [0.3, 0.4]])
+    g = wi.Geometry(2, wi.POLYGON, (), (24,), verts=wi.L_SHAPE)
+    x = wi.sample_points(g, 6, np.random.default_rng(22))
+    N = 20_000
+    c0, s0, _ = walks.build_measure(g, K, x, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c1, s1, _ = walks.build_measure(g, K, x, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=1)
+    assert s1["steps"] < 0.8 * s0["steps"], (s0["steps"], s1["steps"])
+    assert s1["escapes"] == 0
+    rep = statutil.two_sample(c0, N, c1, N)
+    assert rep["ok"], rep
+    _, _, S = walks.instance_setup(K, 2)
+    z = _exit_mean_z(g, S, x, _sol4(K), 30_000, grad_bound=4.0, radius_mode=1)
+    assert np.all(z < 4.5), z
+
+
 def test_radius_modes_rejected_where_they_do_not_apply():
     g = wi.Geometry(2, wi.POLYGON, (), (16,), verts=wi.L_SHAPE)
     assert np.isnan(walks.step_radii(g, np.eye(3), [[0.5, 0.5]], 2)).all()
+    assert np.isnan(walks.step_radii(wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.5), (8,)), np.eye(3),
+                                     [[0.1, 0.1]], 1)).all()
     with pytest.raises(ValueError):
         walks.walk_exits(g, np.eye(3), [0.5, 0.5], 1e-4, 4, radius_mode=2)
     gb = wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 1.0), (4,))
     with pytest.raises(ValueError):
         walks.walk_exits(gb, np.eye(3), [0.5, 0.5], 1e-4, 4, radius_mode=3)
+    ge = wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.5), (8,))
+    with pytest.raises(ValueError):
+        walks.walk_exits(ge, np.eye(3), [0.1, 0.1], 1e-4, 4, radius_mode=1)
 
 
 # ---------------------------------------------------------------- exact invariants
