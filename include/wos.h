@@ -134,7 +134,9 @@ typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
  * of the diffusion on ellipsoids inscribed in D, so any r whose ellipsoid X + r S B(0,1) lies in D
  * gives the same exit law; larger radii give shorter walks.
  *   WOE_BOUND     r = dist(X, dD), the radius of eq. "wos chain" (every domain).
- *   MAPPED_EXACT  boxes only: the largest inscribed radius, min over faces of gap_a / |S e_a|.
+ *   MAPPED_EXACT  boxes and polygons: the largest inscribed radius; for a box min over faces of
+ *                 gap_a / |S e_a|, for a polygon the distance from S^{-1} X to the mapped edges
+ *                 S^{-1}[a, b] (the ellipsoid is the set of z with |S^{-1}(z - X)| <= r).
  *   MAPPED_BOUND  discs, annuli, balls: with v = X - c and a = |S v|, r = sqrt(a^2 + R^2 - |v|^2) - a
  *                 for the outer circle or sphere of radius R; for the inner circle of an annulus
  *                 max((|v|^2 - R_in^2) / (2 a), dist); r is the smaller.  Equal to dist when S = I.
@@ -153,7 +155,7 @@ typedef struct {
     uint64_t seed;        /* Philox key (low word, high word) */
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */
-    int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes; MAPPED_BOUND: discs, annuli, balls) */
+    int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes, polygons; MAPPED_BOUND: discs, annuli, balls) */
     uint32_t max_steps;   /* step cap S_max (0 -> 10000, must be < 2^31); capped walks are binned where they are */
 } wos_walk_params;
 

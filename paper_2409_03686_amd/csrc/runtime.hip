@@ -443,8 +443,8 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT &&
         w->radius_mode != WOS_RADIUS_MAPPED_BOUND)
         return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
-    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX)
-        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes only");
+    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON)
+        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes and polygons only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
         g->kind != WOS_BALL)
         return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs, annuli and balls only");
@@ -506,6 +506,14 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
     wos_status st = conductivity_root(w->K, g->dim, I.S, &lmax, &lmin);
     if (st != WOS_OK) return st;
     for (int k = 0; k < 9; ++k) I.Sf[k] = static_cast<float>(I.S[k]);
+    if (g->dim == 2) {  // S^{-1} by the 2 x 2 inverse formula
+        const double det = I.S[0] * I.S[4] - I.S[1] * I.S[3];
+        I.Si[0] = I.S[4] / det;
+        I.Si[1] = -I.S[1] / det;
+        I.Si[2] = -I.S[3] / det;
+        I.Si[3] = I.S[0] / det;
+        for (int k = 0; k < 4; ++k) I.Sif[k] = static_cast<float>(I.Si[k]);
+    }
     for (int a = 0; a < 3; ++a) {
         double cn = 0.0;
         for (int r = 0; r < g->dim; ++r) cn += I.S[r * 3 + a] * I.S[r * 3 + a];
@@ -585,6 +593,30 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             segs.push_back(s);
         }
         I.perim = cum;
+        if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT) {
+            // the mapped edges S^{-1}[a, b] after the edges, for the mapped-exact radius
+            for (int e = 0; e < g->n_verts; ++e) {
+                const double *a = g->verts + 2 * e, *b = g->verts + 2 * ((e + 1) % g->n_verts);
+                const double ma[2] = {I.Si[0] * a[0] + I.Si[1] * a[1], I.Si[2] * a[0] + I.Si[3] * a[1]};
+                const double mb[2] = {I.Si[0] * b[0] + I.Si[1] * b[1], I.Si[2] * b[0] + I.Si[3] * b[1]};
+                PolySeg s{};
+                s.ax = ma[0];
+                s.ay = ma[1];
+                s.ex = mb[0] - ma[0];
+                s.ey = mb[1] - ma[1];
+                s.ll = s.ex * s.ex + s.ey * s.ey;
+                s.fax = static_cast<float>(s.ax);
+                s.fay = static_cast<float>(s.ay);
+                s.fex = static_cast<float>(s.ex);
+                s.fey = static_cast<float>(s.ey);
+                s.finv_ll = static_cast<float>(1.0 / s.ll);
+                segs.push_back(s);
+            }
+            // FP32 error bound of the mapped distance: the polygon distance's 32 units of 2^-24 at
+            // the mapped scale (at most the domain scale / sigma_min(S)), doubled for the mapping of
+            // x and the rounding of the mapped edges
+            I.mbf[1] = static_cast<float>(std::ldexp(domain_scale(g), -18) / std::sqrt(lmin / lmax));
+        }
     }
     if (g->kind == WOS_PERFORATED || g->kind == WOS_PERFBOX) {
         // holes as (centre (ax, ay, ey), radius ex) records; FP32 centres relative to the outer
@@ -607,6 +639,7 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             segs.push_back(s);
         }
     }
+    I.n_segs = static_cast<int32_t>(segs.size());
     return WOS_OK;
 }
 
@@ -734,7 +767,9 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
     // one kind (and radius variant) for the whole launch: compiled in; else read per instance
     auto kernel_kind = [&](int q) {
         const wos_measure_job &j = jobs[idx[q]];
-        return j.geom.kind + (j.walk.radius_mode == WOS_RADIUS_MAPPED_BOUND ? kRadiusVariant : 0);
+        const bool mapped = j.walk.radius_mode == WOS_RADIUS_MAPPED_BOUND ||
+                            (j.geom.kind == WOS_POLYGON && j.walk.radius_mode == WOS_RADIUS_MAPPED_EXACT);
+        return j.geom.kind + (mapped ? kRadiusVariant : 0);
     };
     gl.kind_sel = kernel_kind(0);
     for (int q = 1; q < n; ++q)

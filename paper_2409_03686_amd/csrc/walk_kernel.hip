@@ -208,7 +208,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
     if constexpr (sizeof(R) == 8) {
         R U[DIM];
         Dir<R, DIM>::template get<PH>(w, U);
-        const double r = radius64<KIND, DIM, RV>(I, x, d);
+        const double r = radius64<KIND, DIM, RV>(I, x, d, segs);
         step64<DIM>(I, x, r, U);
         d = dist64<KIND, DIM>(I, x, segs);
         s += 1;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
     } else {
         // conservative radius: below the true distance by more than the FP32 distance error
         // (2 delta) and the direction's norm error (relative 2^-16)
-        const float rr = radius32<KIND, DIM, RV>(I, x, d);
+        const float rr = radius32<KIND, DIM, RV>(I, x, d, segs);
         if constexpr (DIM == 2) {
             const float t = static_cast<float>(w[PH] >> 8);
             const float c0 = __builtin_amdgcn_cosf(__builtin_fmaf(t, 0x1.0p-24f, F.off0));
@@ -265,7 +265,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     for (int j = tid; j < M; j += nthr) hist[j] = 0u;
     const PolySeg *segs = I.segs;
     if constexpr (KIND == kPolygon || KIND == kPerforated || KIND == kPerfBox) {  // edges / holes read every step
-        for (int e = tid; e < I.n_verts; e += nthr) lds_segs[e] = I.segs[e];
+        for (int e = tid; e < I.n_segs; e += nthr) lds_segs[e] = I.segs[e];
         segs = lds_segs;
     }
     if (tid < 8) sh.st[tid] = 0ull;
@@ -526,7 +526,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
     const int M = I.n_elem;
     const PolySeg *segs = I.segs;
     if constexpr (KIND == kPolygon || KIND == kPerforated || KIND == kPerfBox) {  // edges / holes read every step
-        for (int e = lane; e < I.n_verts; e += kWave) lds_segs[e] = I.segs[e];
+        for (int e = lane; e < I.n_segs; e += kWave) lds_segs[e] = I.segs[e];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -818,7 +818,8 @@ __device__ uint32_t steal_point(const DevInst *insts, int n_inst, uint32_t total
 // wave, two histogram rows, the staged segments and the stop queue.  2: point mode (run_item over
 // points with walk reservations; cursor[2 + p] is point p's walk cursor).
 // KSEL: -1 for launches that mix kinds (kind and radius mode read per instance), else the kind plus
-// kRadiusVariant when the launch uses the mapped-bound radius, both then fixed at compile time.
+// kRadiusVariant when the launch uses the mapped-bound radius (the mapped-exact one for polygons),
+// both then fixed at compile time.
 template <typename R, int DIM, int KSEL, int MODE>
 __global__ __launch_bounds__(1024) void walk_kernel(const DevInst *__restrict__ insts, int n_inst,
                                                     uint64_t total_items, uint32_t *cursor,
@@ -1000,6 +1001,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
         case kRadiusVariant + kAnnulus: return kptr<R, 2, kRadiusVariant + kAnnulus>(wave);
         case kEllipse: return kptr<R, 2, kEllipse>(wave);
         case kPolygon: return kptr<R, 2, kPolygon>(wave);
+        case kRadiusVariant + kPolygon: return kptr<R, 2, kRadiusVariant + kPolygon>(wave);
         case kPerforated: return kptr<R, 2, kPerforated>(wave);
         case kPerfBox: return kptr<R, 2, kPerfBox>(wave);
         case kBox: return kptr<R, 2, kBox>(wave);

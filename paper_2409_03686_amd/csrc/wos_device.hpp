@@ -32,13 +32,16 @@ struct alignas(16) DevInst {
     int32_t dim, kind, radius_mode, n_elem;
     int32_t layout[4];
     int32_t n_verts, precision;
+    int32_t n_segs, pad0;  // PolySeg records to stage in LDS: n_verts, or 2 n_verts with the mapped edges
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
+    double Si[4];     // 2D: S^{-1}, row-major 2x2 (mapped-exact radius of polygons)
     double cn[3];     // |S e_a|: the half-extent of the unit ellipsoid S B(0,1) along axis a
     double eps;
     double perim;     // polygon perimeter
     float pf[8];
     float Sf[9];
+    float Sif[4];
     float icnf[3];    // 1 / |S e_a|
     float eps_lo;     // FP32 distance <= eps_lo: certainly inside the eps-shell
     float eps_hi;     // FP32 distance >  eps_hi: certainly outside it
@@ -50,7 +53,8 @@ struct alignas(16) DevInst {
     float fold_off[2];  // 2^-25 - phi_a: the angle of coordinate a is (w >> 8) 2^-24 + fold_off[a]
     float fold_rs[2];   // A_a (1 - 2^-16)
     float fold_rn[2];   // A_a (-2 delta): step of coordinate a = (r fold_rs + fold_rn) cos(angle)
-    float mbf[4];       // mapped-bound radius (FP32): R_out^2, its error bound, R_in^2, its error bound
+    float mbf[4];       // mapped-bound radius (FP32): R_out^2, its error bound, R_in^2, its error bound;
+                        // polygons: mbf[1] = error bound of the FP32 mapped distance
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call
@@ -350,15 +354,30 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 // ellipsoid inside the circle / sphere of radius R and r_in = (|v|^2 - R_in^2) / (2 a) keeps it off
 // the inner circle of an annulus, where dist is valid as well: r = min(r_out, max(r_in, dist)).
 // RV: the radius variant of a launch, fixed at compile time (0: dist, or the box's radius by its mode;
-// 1: mapped bound) or -1: read the instance's radius mode.  A launch-wide kind selector adds
+// 1: mapped bound, or mapped exact for polygons) or -1: read the instance's radius mode.  A launch-wide kind selector adds
 // kRadiusVariant to the kind for the mapped bound.
 constexpr bool mapped_bound_kind(int kind) { return kind == kDisk || kind == kAnnulus || kind == kBall; }
 constexpr int kRadiusVariant = 16;
 
+// Polygons (mapped exact): the ellipsoid is { z : |S^{-1}(z - x)| <= r }, so the largest inscribed r is
+// the distance from S^{-1} x to the mapped edges, staged after the edges (segs[n_verts + e]).
 template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(const DevInst &I, const double *x,
-                                                                                double d)
+                                                                                double d, const PolySeg *segs)
 {
 #pragma clang fp contract(off)
+    if constexpr (KIND == kPolygon && RV != 0) {
+        if (RV == 1 || I.radius_mode == 1) {
+            const double y0 = I.Si[0] * x[0] + I.Si[1] * x[1], y1 = I.Si[2] * x[0] + I.Si[3] * x[1];
+            double best = __builtin_inf();
+            for (int e = 0; e < I.n_verts; ++e) {
+                const PolySeg &m = segs[I.n_verts + e];
+                double t;
+                const double dd = __builtin_sqrt(seg_dist_sq<double>(m.ax, m.ay, m.ex, m.ey, m.ll, y0, y1, &t));
+                best = dd < best ? dd : best;
+            }
+            return best;
+        }
+    }
     if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
             double v[DIM], q = 0.0, a2 = 0.0;
@@ -401,8 +420,21 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
 
 // FP32 form of the mapped bound on centred positions; the error bounds in mbf are subtracted.
 template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(const DevInst &I, const float *x,
-                                                                               float d)
+                                                                               float d, const PolySeg *segs)
 {
+    if constexpr (KIND == kPolygon && RV != 0) {
+        if (RV == 1 || I.radius_mode == 1) {
+            const float y0 = __builtin_fmaf(I.Sif[0], x[0], I.Sif[1] * x[1]);
+            const float y1 = __builtin_fmaf(I.Sif[2], x[0], I.Sif[3] * x[1]);
+            float best = __builtin_inff();
+            for (int e = 0; e < I.n_verts; ++e) {
+                const PolySeg &m = segs[I.n_verts + e];
+                float t;
+                best = __builtin_fminf(best, seg_dist_sq<float>(m.fax, m.fay, m.fex, m.fey, m.finv_ll, y0, y1, &t));
+            }
+            return __builtin_amdgcn_sqrtf(best) - I.mbf[1];
+        }
+    }
     if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
             float q, a2;

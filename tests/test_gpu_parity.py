@@ -79,6 +79,7 @@ def _kind_cases():
         "annulus_aniso": (wi.Geometry(2, wi.ANNULUS, (0.1, -0.05, 0.3, 1.0), (40, 24)), K2, 0),
         "ellipse_aniso": (wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.4), (50,)), K2, 0),
         "lshape_aniso": (wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE), K2, 0),
+        "lshape_mapped_exact": (wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE), K2, 1),
         "square_exact": (wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 2.0), (9,)), K2, 1),
         "cube_woe": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 0),
         "cube_exact": (wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (7,)), K3, 1),
@@ -179,35 +180,36 @@ def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
     assert rep2["ok"]
 
 
-@pytest.mark.parametrize("case", ["annulus", "ball"])
-def test_fp32_mapped_bound_vs_oracle(wos, ctx, case):
-    """Mapped-bound radius with FP32 geometry: no escapes (the radius stays certified after its FP32
-    error bound is taken off), counts against the FP64 path and the oracle, and the shorter walks
-    against the WoE-bound chain on the same workload."""
+@pytest.mark.parametrize("case", ["annulus", "ball", "lshape"])
+def test_fp32_mapped_radius_vs_oracle(wos, ctx, case):
+    """Mapped radii with FP32 geometry (the bound on the annulus and the ball, the exact radius on
+    the L-shape): no escapes (the radius stays certified after its FP32 error bound is taken off),
+    counts against the FP64 path and the oracle, and the shorter walks against the WoE-bound chain
+    on the same workload."""
     if case == "annulus":
         inst = wi.cfg2_annulus(n_walks=40_000, n_obs=96, precision=wi.FP32_GEOM_FP64_EXIT,
                                radius_mode=wi.RADIUS_MAPPED_BOUND)
     else:
-        g, K, _ = _kind_cases()["ball_mapped_bound"]
+        g, K, mode = _kind_cases()["ball_mapped_bound" if case == "ball" else "lshape_mapped_exact"]
         inst = wi.Instance(g, K, wi.sample_points(g, 48, np.random.default_rng(4)), 40_000, eps=1e-4, seed=9,
-                           precision=wi.FP32_GEOM_FP64_EXIT, radius_mode=wi.RADIUS_MAPPED_BOUND)
+                           precision=wi.FP32_GEOM_FP64_EXIT, radius_mode=mode)
     c32, st, _ = _gpu(wos, ctx, inst)
     assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0 and st["cap_hits"] == 0
     c64, st64, _ = _gpu(wos, ctx, inst, precision=wi.FP64)
     rep = statutil.two_sample(c32, inst.n_walks, c64, inst.n_walks)
-    print(f"{case} mapped bound FP32 vs FP64", rep)
+    print(f"{case} mapped radius FP32 vs FP64", rep)
     assert rep["ok"]
     assert abs(st["steps"] - st64["steps"]) <= 0.02 * st64["steps"]
     rows = [0, 17, 40]
     cr, sr, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed + 1,
-                                 radius_mode=2, walk_end=inst.n_walks, point_ids=rows)
+                                 radius_mode=inst.radius_mode, walk_end=inst.n_walks, point_ids=rows)
     rep2 = statutil.two_sample(c32[rows], inst.n_walks, cr, inst.n_walks)
-    print(f"{case} mapped bound FP32 vs independent oracle rows", rep2)
+    print(f"{case} mapped radius FP32 vs independent oracle rows", rep2)
     assert rep2["ok"]
     inst.radius_mode = wi.RADIUS_WOE_BOUND
     c0, st0, _ = _gpu(wos, ctx, inst)
     rep3 = statutil.two_sample(c32, inst.n_walks, c0, inst.n_walks)
-    print(f"{case} mapped bound vs WoE bound: steps {st['steps']} vs {st0['steps']}", rep3)
+    print(f"{case} mapped radius vs WoE bound: steps {st['steps']} vs {st0['steps']}", rep3)
     assert rep3["ok"] and st["steps"] < 0.8 * st0["steps"]
 
 
