@@ -96,6 +96,9 @@ def parse():
     p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
     p.add_argument("--serve-rate", type=float, default=200.0)
+    p.add_argument("--serve-radius", default="mapped", choices=("mapped", "dist"),
+                   help="step radius of the serving requests: each kind's mapped radius, or r = dist (the "
+                        "cube's exact radius only)")
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement (for profiling)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
     p.add_argument("--items", choices=("auto", "block", "wave", "point"), default="auto",
@@ -169,32 +172,41 @@ def _serve(ctx, wos, insts, arrivals, svd_mode):
     wall = time.perf_counter() - t0
     ok = [o for o in out if o.status == 0]
     lat = np.array([o.t_done - o.t_arrive for o in ok]) if ok else np.zeros(1)
-    return {"requests": len(out), "completed": len(ok), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+    # reconstruction error of each completed request: max |u1 - u| / max |u| on Gamma_1
+    errs = []
+    for k, (inst, o) in enumerate(zip(insts, out)):
+        if o.status == 0 and inst.u_exact_g1 is not None:
+            u1 = keep[6 * k + 5]
+            errs.append(float(np.abs(u1 - inst.u_exact_g1).max() / max(np.abs(inst.u_exact_g1).max(), 1e-300)))
+    return {"requests": len(out), "completed": len(ok), "median_rel_err_u1": float(np.median(errs)) if errs else None,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": sum(o.walks for o in ok) / wall,
             "steps_per_s": sum(o.steps for o in ok) / wall, "wall_s": wall}
 
 
-def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1):
+def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1, radius="mapped"):
     """Request serving on the heterogeneous-instance generator (kinds, conductivities, sizes and walk
     budgets drawn per request; 1-5 % noise; random harmonic data of degree <= 6): each request is
     build H + FP64 SVD + TSVD reconstruction, host buffers in and out.  Capacity = requests per
     second with every request queued at t = 0; then open-loop Poisson arrivals at `rate` for
-    `seconds`, and, when that load exceeds the capacity, at 0.8 x capacity as well."""
+    `seconds`, and, when that load exceeds the capacity, at 0.8 x capacity as well.  Step radius: each
+    kind's mapped radius (the same exit law as r = dist, shorter walks), or r = dist."""
     arr = wi.cfg5_arrivals(rate=rate, duration_s=seconds, seed=5)
     rng = np.random.default_rng(5)
-    insts = [wi.random_instance(rng, i) for i in range(len(arr))]
+    mapped = radius == "mapped"
+    insts = [wi.random_instance(rng, i, mapped_radii=mapped) for i in range(len(arr))]
     cap = _serve(ctx, wos, insts, np.zeros(len(insts)), svd_mode)
     capacity = cap["completed"] / cap["wall_s"]
     offered = _serve(ctx, wos, insts, arr, svd_mode)
     mean_walks = float(np.mean([i.x_obs.shape[0] * i.n_walks for i in insts]))
-    out = {"svd_mode": svd_mode, "capacity_req_s": capacity, "capacity_walks_per_s": cap["walks_per_s"],
+    out = {"svd_mode": svd_mode, "radius": radius, "capacity_req_s": capacity, "capacity_walks_per_s": cap["walks_per_s"],
            "capacity_steps_per_s": cap["steps_per_s"], "mean_walks_per_request": mean_walks,
            "offered_rate_req_s": rate, "utilisation": rate / capacity, "at_offered_rate": offered}
     if rate >= capacity:
         r8 = 0.8 * capacity
         arr8 = wi.cfg5_arrivals(rate=r8, duration_s=seconds, seed=5)
         while len(insts) < len(arr8):
-            insts.append(wi.random_instance(rng, len(insts)))
+            insts.append(wi.random_instance(rng, len(insts), mapped_radii=mapped))
         out["at_0.8_capacity"] = dict(_serve(ctx, wos, insts[:len(arr8)], arr8, svd_mode), rate_req_s=r8)
     return out
 
@@ -213,7 +225,8 @@ def main():
     inst = wi.cfg2_annulus(n_walks=a.walks, precision=wi.FP32_GEOM_FP64_EXIT)
     if a.serve_only:
         ctx = wos.wos_create(0)
-        print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)}))
+        print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd,
+                                                                 a.serve_radius)}))
         wos.wos_destroy(ctx)
         return
     items = {"auto": wos.WOS_ITEMS_AUTO, "block": wos.WOS_ITEMS_BLOCK, "wave": wos.WOS_ITEMS_WAVE,
@@ -423,7 +436,7 @@ def main():
     }
     if not a.no_serve:
         log("serving runs")
-        out["serving"] = serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd)
+        out["serving"] = serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd, a.serve_radius)
     if not a.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)

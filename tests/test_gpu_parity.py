@@ -334,9 +334,9 @@ def test_batch_equals_separate_and_oracle(wos, ctx, items):
     for k, inst in enumerate(insts):  # keep the CPU side small
         inst.x_obs = inst.x_obs[:24]
         inst.n_walks = min(inst.n_walks, 400)
-        if k % 2 and inst.geom.kind in (wi.DISK, wi.ANNULUS, wi.BALL):
-            inst.radius_mode = wi.RADIUS_MAPPED_BOUND  # per-instance radius modes in the mixed launch
-    assert any(inst.radius_mode == wi.RADIUS_MAPPED_BOUND for inst in insts)
+        if k % 2:
+            inst.radius_mode = wi.RADIUS_WOE_BOUND  # per-instance radius modes in the mixed launch
+    assert {inst.radius_mode for inst in insts} == {0, 1, 2}
     sep = [_gpu(wos, ctx, inst)[0] for inst in insts]
     jobs, keep = [], []
     for inst in insts:

@@ -516,13 +516,23 @@ def _layout_for(kind: int, dim: int, M_target: int):
     raise ValueError(kind)
 
 
+def _radius_for(kind: int, mapped_radii: bool) -> int:
+    if kind == BOX or (mapped_radii and kind == POLYGON):
+        return RADIUS_MAPPED_EXACT
+    if mapped_radii and kind in (DISK, ANNULUS, BALL):
+        return RADIUS_MAPPED_BOUND
+    return RADIUS_WOE_BOUND
+
+
 def random_instance(rng: np.random.Generator, instance_id: int, kind_name: Optional[str] = None,
                     walk_scale: float = 1.0, precision: int = FP32_GEOM_FP64_EXIT,
-                    data_degree: int = 6, eta: Optional[float] = None) -> Instance:
+                    data_degree: int = 6, eta: Optional[float] = None, mapped_radii: bool = True) -> Instance:
     """One instance of the heterogeneous batch: disk, ellipse (1 x 0.4), L-shape, annulus (0.3, 1),
     unit ball or unit cube; random SPD K with condition number in [1, 20] (lambda_max = 1);
     points per instance in [32, 2048]; elements in [64, 2048]; walks log-uniform in [1e3, 1e5];
-    Gamma_0 = elements whose reference point's last coordinate is >= the domain centre's."""
+    Gamma_0 = elements whose reference point's last coordinate is >= the domain centre's.
+    Step radius: the kind's mapped radius (exact for the cube and the L-shape, the bound for the
+    disk, annulus and ball; r = dist for the ellipse), or with mapped_radii=False the cube's only."""
     kinds = ["disk", "ellipse", "lshape", "annulus", "ball", "cube"]
     kn = kind_name or kinds[int(rng.integers(len(kinds)))]
     if kn == "disk":
@@ -561,7 +571,7 @@ def random_instance(rng: np.random.Generator, instance_id: int, kind_name: Optio
     N = max(N, 1)
     inst = Instance(g, K, x, N, eps=1e-4, seed=instance_id + 1000, instance_id=instance_id,
                     precision=precision,
-                    radius_mode=RADIUS_MAPPED_EXACT if g.kind == BOX else RADIUS_WOE_BOUND,
+                    radius_mode=_radius_for(g.kind, mapped_radii),
                     name=f"{kn}{g.n_elem}")
     u = random_harmonic_poly(d, K, data_degree, rng)
     uref = u(ref)
@@ -574,9 +584,9 @@ def random_instance(rng: np.random.Generator, instance_id: int, kind_name: Optio
 
 
 def cfg4_batch(n_instances: int = 64, seed: int = 4, walk_scale: float = 1.0,
-               precision: int = FP32_GEOM_FP64_EXIT) -> list:
+               precision: int = FP32_GEOM_FP64_EXIT, mapped_radii: bool = True) -> list:
     rng = np.random.default_rng(seed)
-    return [random_instance(rng, i, walk_scale=walk_scale, precision=precision)
+    return [random_instance(rng, i, walk_scale=walk_scale, precision=precision, mapped_radii=mapped_radii)
             for i in range(n_instances)]
 
 
