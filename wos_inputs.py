@@ -299,13 +299,12 @@ def _with_data(inst: Instance, u) -> Instance:
 
 
 def bauer_spiral(n: int) -> np.ndarray:
-    """n nearly uniform unit vectors on Bauer's spiral (Bauer 2000): z_i = 1 - (2i - 1)/n,
-    azimuth sqrt(n pi) asin(z_i), i = 1..n."""
-    i = np.arange(1, n + 1)
-    z = 1.0 - (2.0 * i - 1.0) / n
-    ph = np.sqrt(n * np.pi) * np.arcsin(z)
-    r = np.sqrt(1.0 - z * z)
-    return np.stack([r * np.cos(ph), r * np.sin(ph), z], 1)
+    """n nearly uniform unit vectors on Bauer's spiral as Section 5.3 states it: polar angle
+    phi_k = arccos(1 - (2k - 1)/n), azimuth theta_k = sqrt(n pi) phi_k, k = 1..n."""
+    k = np.arange(1, n + 1)
+    phi = np.arccos(1.0 - (2.0 * k - 1.0) / n)
+    th = np.sqrt(n * np.pi) * phi
+    return np.stack([np.sin(phi) * np.cos(th), np.sin(phi) * np.sin(th), np.cos(phi)], 1)
 
 
 def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: Optional[float] = None,
