@@ -17,7 +17,7 @@ _LIB = None
 class OgGeom(C.Structure):
     _fields_ = [("dim", C.c_int32), ("kind", C.c_int32), ("p", C.c_double * 8),
                 ("layout", C.c_int32 * 4), ("verts", C.POINTER(C.c_double)),
-                ("n_verts", C.c_int32)]
+                ("n_verts", C.c_int32), ("nodes", C.c_void_p * 2)]
 
 
 def lib():
@@ -79,6 +79,18 @@ def instance_setup(K, dim):
     return lam, K / lam, S3
 
 
+def sphere_cell_measures(nz, nphi, R) -> np.ndarray:
+    """Areas of the cells of a sphere of radius R: nz x nphi equal-area (z band, azimuth) cells, or,
+    for the layout (n, 0), the Voronoi cells of n Bauer nodes (scipy's spherical Voronoi diagram;
+    on the sphere the extrinsic Voronoi cells of nodes on it are the spherical ones)."""
+    if nphi:
+        return np.full(nz * nphi, 4 * np.pi * R * R / (nz * nphi))
+    from scipy.spatial import SphericalVoronoi
+    import wos_inputs as wi
+    sv = SphericalVoronoi(wi.bauer_spiral(nz), radius=1.0)
+    return sv.calculate_areas() * R * R
+
+
 def element_measures(g) -> np.ndarray:
     """sigma(omega_j): surface measure of each boundary element (eq. boundary_weights)."""
     import wos_inputs as wi
@@ -103,8 +115,7 @@ def element_measures(g) -> np.ndarray:
         L = np.sqrt(((np.roll(v, -1, 0) - v) ** 2).sum(1)).sum()
         return np.full(M, L / M)
     if g.kind == wi.BALL:
-        nz, nphi = g.layout
-        return np.full(M, 4 * np.pi * g.params[3] ** 2 / (nz * nphi))
+        return sphere_cell_measures(g.layout[0], g.layout[1], g.params[3])
     if g.kind in (wi.PERFORATED, wi.PERFBOX):
         # the outer boundary's cells, then each hole's: arcs 2 pi r / m, or sphere cells 4 pi r^2 / (nz nphi)
         d = g.dim
@@ -112,14 +123,14 @@ def element_measures(g) -> np.ndarray:
         if g.kind == wi.PERFORATED:
             R = g.params[d]
             outer = (np.full(g.layout[0], 2 * np.pi * R / g.layout[0]) if d == 2 else
-                     np.full(g.layout[0] * g.layout[1], 4 * np.pi * R * R / (g.layout[0] * g.layout[1])))
+                     sphere_cell_measures(g.layout[0], g.layout[1], R))
             hc = (g.layout[1],) if d == 2 else (g.layout[2], g.layout[3])
         else:
             outer = element_measures(wi.Geometry(d, wi.BOX, g.params, (g.layout[0],)))
             hc = tuple(g.layout[1:d])
-        m = int(np.prod(hc))
-        return np.concatenate([outer] + [np.full(m, (2 * np.pi * r if d == 2 else 4 * np.pi * r * r) / m)
-                                         for r in holes[:, d]])
+        if d == 2:
+            return np.concatenate([outer] + [np.full(hc[0], 2 * np.pi * r / hc[0]) for r in holes[:, d]])
+        return np.concatenate([outer] + [sphere_cell_measures(hc[0], hc[1], r) for r in holes[:, d]])
     if g.kind == wi.BOX:
         d, n = g.dim, g.layout[0]
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])

@@ -55,6 +55,8 @@ typedef struct {
     const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise; for the perforated
                              domains the holes as (centre, r), dim + 1 numbers each */
     int32_t n_verts;      /* polygon vertices, or holes of a perforated domain */
+    const double *nodes[2]; /* Bauer-spiral unit vectors (3 per node) of the outer sphere / of the holes
+                               when their layout is (n, 0); set by the entry points, not the caller */
 } og_geom;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -250,12 +252,74 @@ static int arc_index(double theta, int M)
 
 /* Equal-area cell of a direction v (any length > 0) on a sphere: band iz of the height z / |v|
  * from the top (nz bands), sector of the azimuth (nphi sectors from angle 0). */
+static int sphere_cells(int nz, int nphi) { return nphi == 0 ? nz : nz * nphi; }
+
 static int sphere_cell(const double *v, int nz, int nphi)
 {
     double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     double zc = v[2] / n;
     int iz = clampi((long)floor((1.0 - zc) * 0.5 * (double)nz), nz);
     return iz * nphi + arc_index(atan2(v[1], v[0]), nphi);
+}
+
+/* The n nodes of Bauer's spiral on the unit sphere as Section 5.3 gives them: polar angle
+ * phi_k = arccos(1 - (2k - 1)/n), azimuth theta_k = sqrt(n pi) phi_k, k = 1..n (node k - 1 here). */
+static double *bauer_nodes(int n)
+{
+    double *u = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int k = 1; k <= n; ++k) {
+        double ph = acos(1.0 - (2.0 * k - 1.0) / n);
+        double th = sqrt(n * 3.14159265358979323846) * ph;
+        u[3 * (k - 1) + 0] = sin(ph) * cos(th);
+        u[3 * (k - 1) + 1] = sin(ph) * sin(th);
+        u[3 * (k - 1) + 2] = cos(ph);
+    }
+    return u;
+}
+
+/* Extrinsic Voronoi cell (Appendix Ex. A.2): the node R u_k nearest the point, v its position relative
+ * to the sphere's centre; the lowest index wins ties (the disjoint cells V_i take the earlier index). */
+static int bauer_cell(const double *v, double R, int n, const double *u)
+{
+    double best = INFINITY;
+    int bk = 0;
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double t = v[a] - R * u[3 * k + a];
+            s += t * t;
+        }
+        if (s < best) { best = s; bk = k; }
+    }
+    return bk;
+}
+
+/* Cell of a sphere: layout (nz, nphi) gives nz x nphi equal-area (z band, azimuth) cells, (n, 0) the
+ * extrinsic Voronoi cells of n Bauer nodes. */
+static int sphere_cell_of(const double *v, int nz, int nphi, double R, const double *nodes)
+{
+    if (nphi == 0) return nodes ? bauer_cell(v, R, nz, nodes) : -1;
+    return sphere_cell(v, nz, nphi);
+}
+
+/* Copies g and attaches the node tables its Bauer layouts need (free with detach_nodes). */
+static og_geom attach_nodes(const og_geom *g)
+{
+    og_geom G = *g;
+    G.nodes[0] = G.nodes[1] = NULL;
+    if (g->dim == 3) {
+        if (g->kind == OG_BALL && g->layout[1] == 0) G.nodes[0] = bauer_nodes(g->layout[0]);
+        if (g->kind == OG_PERFORATED && g->layout[1] == 0) G.nodes[0] = bauer_nodes(g->layout[0]);
+        if (g->kind == OG_PERFORATED && g->layout[3] == 0) G.nodes[1] = bauer_nodes(g->layout[2]);
+        if (g->kind == OG_PERFBOX && g->layout[2] == 0) G.nodes[1] = bauer_nodes(g->layout[1]);
+    }
+    return G;
+}
+
+static void detach_nodes(og_geom *G)
+{
+    free((void *)G->nodes[0]);
+    free((void *)G->nodes[1]);
 }
 
 /* Box: the nearest face (ties: the lowest face index), then the patch of the other coordinates. */
@@ -321,7 +385,7 @@ int oracle_element(const og_geom *g, const double *x)
     case OG_BALL: {
         double v[3];
         for (int a = 0; a < 3; ++a) v[a] = x[a] - g->p[a];
-        return sphere_cell(v, g->layout[0], g->layout[1]);
+        return sphere_cell_of(v, g->layout[0], g->layout[1], g->p[3], g->nodes[0]);
     }
     case OG_BOX:
         return box_cell(g, x);
@@ -336,21 +400,24 @@ int oracle_element(const og_geom *g, const double *x)
             double dl = hole_dist(g, l, x, v);
             if (dl < best) { best = dl; comp = l; vb[0] = v[0]; vb[1] = v[1]; vb[2] = v[2]; }
         }
+        double Rh = comp >= 0 ? g->verts[(size_t)(d + 1) * comp + d] : 0.0;
         if (g->kind == OG_PERFORATED) {
-            n_outer = d == 2 ? g->layout[0] : g->layout[0] * g->layout[1];
-            hole_cells = d == 2 ? g->layout[1] : g->layout[2] * g->layout[3];
+            n_outer = d == 2 ? g->layout[0] : sphere_cells(g->layout[0], g->layout[1]);
+            hole_cells = d == 2 ? g->layout[1] : sphere_cells(g->layout[2], g->layout[3]);
             if (comp < 0) {
                 double w[3] = { 0.0, 0.0, 0.0 };
                 for (int a = 0; a < d; ++a) w[a] = x[a] - g->p[a];
                 return d == 2 ? arc_index(atan2(w[1], w[0]), g->layout[0])
-                              : sphere_cell(w, g->layout[0], g->layout[1]);
+                              : sphere_cell_of(w, g->layout[0], g->layout[1], g->p[d], g->nodes[0]);
             }
-            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1]) : sphere_cell(vb, g->layout[2], g->layout[3]);
+            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1])
+                       : sphere_cell_of(vb, g->layout[2], g->layout[3], Rh, g->nodes[1]);
         } else {
             n_outer = d == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
-            hole_cells = d == 2 ? g->layout[1] : g->layout[1] * g->layout[2];
+            hole_cells = d == 2 ? g->layout[1] : sphere_cells(g->layout[1], g->layout[2]);
             if (comp < 0) return box_cell(g, x);
-            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1]) : sphere_cell(vb, g->layout[1], g->layout[2]);
+            c = d == 2 ? arc_index(atan2(vb[1], vb[0]), g->layout[1])
+                       : sphere_cell_of(vb, g->layout[1], g->layout[2], Rh, g->nodes[1]);
         }
         return n_outer + comp * hole_cells + c;
     }
@@ -546,11 +613,12 @@ int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, doub
     if (!radius_mode_valid(g, radius_mode)) return -1;
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
+    og_geom G = attach_nodes(g);
     og_job *jobs = (og_job *)calloc((size_t)n_threads, sizeof(og_job));
     pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
     for (int t = 0; t < n_threads; ++t) {
         og_job *J = &jobs[t];
-        J->g = g; J->S = S; J->eps = eps; J->radius_mode = radius_mode;
+        J->g = &G; J->S = S; J->eps = eps; J->radius_mode = radius_mode;
         J->key0 = seed_lo; J->key1 = seed_hi; J->inst = inst; J->max_steps = max_steps;
         J->x_obs = x_obs; J->n_obs = n_obs; J->wb = walk_begin; J->we = walk_end;
         J->counts = counts; J->trace = trace; J->point_ids = point_ids; J->n_elem = n_elem;
@@ -569,17 +637,20 @@ int oracle_build_measure(const og_geom *g, int32_t n_elem, const double *S, doub
     if (stats_out) memcpy(stats_out, st, sizeof(st));
     free(jobs);
     free(th);
+    detach_nodes(&G);
     return 0;
 }
 
 /* Geometry probe for tests: distance and element of each of n points. */
 void oracle_geom_eval(const og_geom *g, const double *x, int32_t n, double *d_out, int32_t *e_out)
 {
+    og_geom G = attach_nodes(g);
     for (int32_t i = 0; i < n; ++i) {
-        const double *p = x + (size_t)i * g->dim;
-        if (d_out) d_out[i] = oracle_dist(g, p);
-        if (e_out) e_out[i] = oracle_element(g, p);
+        const double *p = x + (size_t)i * G.dim;
+        if (d_out) d_out[i] = oracle_dist(&G, p);
+        if (e_out) e_out[i] = oracle_element(&G, p);
     }
+    detach_nodes(&G);
 }
 
 /* Direction probe for tests: U for steps s in [0, n) of walk (k, i, inst). */

@@ -576,6 +576,39 @@ def test_polygon_mapped_exact_same_law_fewer_steps():
     assert np.all(z < 4.5), z
 
 
+def test_bauer_voronoi_cells():
+    """Sphere layout (n, 0): the extrinsic Voronoi cells (Appendix Ex. A.2) of n nodes of Bauer's
+    spiral.  The nodes follow Section 5.3's formula (unit length, z equally spaced); on the paper's
+    concentric shell (Example 6: 1000 outer, 100 inner nodes) the oracle's cell of points in both
+    eps-shells is the nearest node over all 1100 nodes (brute force, lowest index on ties); the cell
+    measures sum to 4 pi R^2 and match the frequencies of 2e6 uniform points (z-scores below 5.5)."""
+    n = 1000
+    u = wi.bauer_spiral(n)
+    np.testing.assert_allclose((u ** 2).sum(1), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(u[:, 2], 1 - (2 * np.arange(1, n + 1) - 1) / n, atol=1e-14)
+    g = wi.Geometry(3, wi.PERFORATED, (0.0, 0.0, 0.0, 1.0), (1000, 0, 100, 0),
+                    verts=np.array([[0.0, 0.0, 0.0, 0.5]]))
+    assert g.n_elem == 1100
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(6000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    t = rng.uniform(0, 1e-3, (6000, 1))
+    pts = np.concatenate([v[:3000] * (1 - t[:3000]), v[3000:] * (0.5 + t[3000:])])
+    _, e = walks.geom_eval(g, pts)
+    nodes = np.concatenate([u, 0.5 * wi.bauer_spiral(100)])
+    np.testing.assert_array_equal(e, np.argmin(((pts[:, None, :] - nodes[None]) ** 2).sum(2), 1))
+    sig = walks.element_measures(g)
+    assert abs(sig[:1000].sum() - 4 * np.pi) < 1e-10 and abs(sig[1000:].sum() - np.pi) < 1e-10
+    gb = wi.Geometry(3, wi.BALL, (0.1, 0.0, -0.2, 1.0), (1000, 0))
+    w = rng.normal(size=(2_000_000, 3))
+    w /= np.linalg.norm(w, axis=1)[:, None]
+    _, eb = walks.geom_eval(gb, np.asarray(gb.params[:3]) + w * (1 - 1e-6))
+    cnt = np.bincount(eb, minlength=1000)
+    p = walks.element_measures(gb) / (4 * np.pi)
+    z = (cnt - 2e6 * p) / np.sqrt(2e6 * p * (1 - p))
+    assert np.abs(z).max() < 5.5, np.abs(z).max()
+
+
 def test_radius_modes_rejected_where_they_do_not_apply():
     g = wi.Geometry(2, wi.POLYGON, (), (16,), verts=wi.L_SHAPE)
     assert np.isnan(walks.step_radii(g, np.eye(3), [[0.5, 0.5]], 2)).all()

@@ -84,6 +84,12 @@ class Instance:
     noise_delta: float = 0.0          # expected norm of nu * noise(b), for the discrepancy principle
 
 
+def _sphere_cells(nz: int, nphi: int) -> int:
+    """Cells of a sphere: nz x nphi (z band, azimuth) cells, or, for the layout (n, 0), the Voronoi
+    cells of n nodes of Bauer's spiral."""
+    return nz if nphi == 0 else nz * nphi
+
+
 def element_count(dim: int, kind: int, layout, n_holes: int = 0) -> int:
     layout = tuple(int(v) for v in layout)
     if kind in (DISK, ELLIPSE, POLYGON):
@@ -91,21 +97,23 @@ def element_count(dim: int, kind: int, layout, n_holes: int = 0) -> int:
     if kind == ANNULUS:
         return layout[0] + layout[1]
     if kind == BALL:
-        return layout[0] * layout[1]
+        return _sphere_cells(layout[0], layout[1])
     if kind == BOX:
         return 2 * dim * layout[0] ** (dim - 1)
     if kind == PERFORATED:
         if dim == 2:
             return layout[0] + layout[1] * layout[2]
-        return layout[0] * layout[1] + n_holes * layout[2] * layout[3]
+        return _sphere_cells(layout[0], layout[1]) + n_holes * _sphere_cells(layout[2], layout[3])
     if kind == PERFBOX:
         if dim == 2:
             return 4 * layout[0] + n_holes * layout[1]
-        return 6 * layout[0] ** 2 + n_holes * layout[1] * layout[2]
+        return 6 * layout[0] ** 2 + n_holes * _sphere_cells(layout[1], layout[2])
     raise ValueError(f"unknown geometry kind {kind}")
 
 
 def _sphere_cell_centres(c, R, nz, nphi):
+    if nphi == 0:  # Voronoi cells: their nodes
+        return np.asarray(c, float) + R * bauer_spiral(nz)
     iz, ip = np.meshgrid(np.arange(nz), np.arange(nphi), indexing="ij")
     z = 1 - 2 * (iz.ravel() + 0.5) / nz
     ph = (ip.ravel() + 0.5) * 2 * np.pi / nphi
@@ -168,6 +176,8 @@ def element_ref_points(g: Geometry) -> np.ndarray:
         e = np.searchsorted(cum, s, side="right") - 1
         t = (s - cum[e]) / ln[e]
         return v[e] + t[:, None] * seg[e]
+    if g.kind == BALL and g.layout[1] == 0:
+        return _sphere_cell_centres(g.params[:3], g.params[3], g.layout[0], 0)
     if g.kind == BALL:
         cx, cy, cz, R = g.params
         nz, nphi = g.layout
