@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/wos.h"
@@ -121,21 +122,129 @@ extern "C" wos_status wos_destroy(wos_ctx *ctx)
 // ---------------------------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------------------------
-static int elements_of(const wos_geometry *g)
+// Cells of a sphere: layout (n_z, n_phi) gives n_z x n_phi equal-area (z band, azimuth) cells, (n, 0)
+// the extrinsic Voronoi cells (Appendix Ex. A.2) of n nodes of Bauer's spiral (Section 5.3).
+static long long sphere_cells(int nz, int nphi) { return nphi == 0 ? nz : static_cast<long long>(nz) * nphi; }
+static bool sphere_layout_ok(int nz, int nphi) { return nphi == 0 ? nz >= 16 : (nz >= 1 && nphi >= 1); }
+
+static long long elements_of(const wos_geometry *g)
 {
     switch (g->kind) {
     case WOS_DISK: case WOS_ELLIPSE: case WOS_POLYGON: return g->layout[0];
     case WOS_ANNULUS: return g->layout[0] + g->layout[1];
-    case WOS_BALL: return g->layout[0] * g->layout[1];
+    case WOS_BALL: return sphere_cells(g->layout[0], g->layout[1]);
     case WOS_BOX: return g->dim == 2 ? 4 * g->layout[0] : 6 * g->layout[0] * g->layout[0];
     case WOS_PERFORATED:
         if (g->dim == 2) return g->layout[0] + g->layout[1] * g->layout[2];
-        return g->layout[0] * g->layout[1] + g->n_verts * g->layout[2] * g->layout[3];
+        return sphere_cells(g->layout[0], g->layout[1]) + g->n_verts * sphere_cells(g->layout[2], g->layout[3]);
     case WOS_PERFBOX:
         if (g->dim == 2) return 4 * g->layout[0] + g->n_verts * g->layout[1];
-        return 6 * g->layout[0] * g->layout[0] + g->n_verts * g->layout[1] * g->layout[2];
+        return 6 * g->layout[0] * g->layout[0] + g->n_verts * sphere_cells(g->layout[1], g->layout[2]);
     }
     return -1;
+}
+
+// Unit vectors of the n nodes of Bauer's spiral as Section 5.3 gives them: polar angle
+// phi_k = arccos(1 - (2k - 1)/n), azimuth theta_k = sqrt(n pi) phi_k, k = 1..n (node k - 1 here).
+static void bauer_nodes(int n, std::vector<double> &u)
+{
+    u.resize(3 * static_cast<size_t>(n));
+    for (int k = 1; k <= n; ++k) {
+        const double ph = std::acos(1.0 - (2.0 * k - 1.0) / n);
+        const double th = std::sqrt(n * 3.14159265358979323846) * ph;
+        u[3 * (k - 1) + 0] = std::sin(ph) * std::cos(th);
+        u[3 * (k - 1) + 1] = std::sin(ph) * std::sin(th);
+        u[3 * (k - 1) + 2] = std::cos(ph);
+    }
+}
+
+// Areas of the Voronoi cells of the Bauer nodes on the unit sphere.  The cell of node c is the set of
+// points p with p.(c - u_j) >= 0 for all j; in the gnomonic chart p ~ c + a e1 + b e2 around c (great
+// circles become lines) each condition is the half-plane (1 - c.u_j) - a e1.u_j - b e2.u_j >= 0, so the
+// cell is a convex polygon clipped from a large square.  Only nodes with |z_j - z_c| within twice the
+// cell's chordal radius can clip it (a farther node is farther from every point of the cell than c is);
+// the window is widened until it covers that.  The area is the sum of the solid angles of the fan
+// triangles (c, p_m, p_m+1), each 2 atan2(|a.(b x c)|, 1 + a.b + b.c + c.a) (Van Oosterom-Strackee).
+static void bauer_cell_areas(int n, double *area)
+{
+    std::vector<double> u;
+    bauer_nodes(n, u);
+    auto dot = [](const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto cross = [](const double *a, const double *b, double *c) {
+        c[0] = a[1] * b[2] - a[2] * b[1];
+        c[1] = a[2] * b[0] - a[0] * b[2];
+        c[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    for (int i = 0; i < n; ++i) {
+        const double *c = &u[3 * static_cast<size_t>(i)];
+        const double h[3] = {std::fabs(c[2]) < 0.9 ? 0.0 : 1.0, 0.0, std::fabs(c[2]) < 0.9 ? 1.0 : 0.0};
+        double e1[3], e2[3];
+        cross(h, c, e1);
+        const double l1 = std::sqrt(dot(e1, e1));
+        for (double &v : e1) v /= l1;
+        cross(c, e1, e2);
+        double win = 8.0 / std::sqrt(static_cast<double>(n));
+        std::vector<std::array<double, 2>> P;
+        for (;;) {
+            const double L = 8.0;
+            P = {{-L, -L}, {L, -L}, {L, L}, {-L, L}};
+            for (int j = 0; j < n && !P.empty(); ++j) {
+                const double *w = &u[3 * static_cast<size_t>(j)];
+                if (j == i || std::fabs(w[2] - c[2]) > win) continue;
+                const double k0 = 1.0 - dot(c, w), ka = -dot(e1, w), kb = -dot(e2, w);
+                std::vector<std::array<double, 2>> Q;
+                for (size_t m = 0; m < P.size(); ++m) {
+                    const auto &A = P[m], &B = P[(m + 1) % P.size()];
+                    const double fa = k0 + ka * A[0] + kb * A[1], fb = k0 + ka * B[0] + kb * B[1];
+                    if (fa >= 0) Q.push_back(A);
+                    if ((fa >= 0) != (fb >= 0)) {
+                        const double t = fa / (fa - fb);
+                        Q.push_back({A[0] + t * (B[0] - A[0]), A[1] + t * (B[1] - A[1])});
+                    }
+                }
+                P.swap(Q);
+            }
+            double rmax = 0.0;  // chordal radius of the cell around c
+            for (const auto &q : P) {
+                double pv[3];
+                for (int a = 0; a < 3; ++a) pv[a] = c[a] + q[0] * e1[a] + q[1] * e2[a];
+                const double ln = std::sqrt(dot(pv, pv));
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) d2 += (pv[a] / ln - c[a]) * (pv[a] / ln - c[a]);
+                rmax = std::max(rmax, std::sqrt(d2));
+            }
+            if (2.0 * rmax <= win || win > 2.0) break;
+            win = 2.0 * rmax + 1e-9;
+        }
+        double acc = 0.0;
+        for (size_t m = 0; m < P.size(); ++m) {
+            double p0[3], p1[3], x[3];
+            const auto &A = P[m], &B = P[(m + 1) % P.size()];
+            for (int a = 0; a < 3; ++a) {
+                p0[a] = c[a] + A[0] * e1[a] + A[1] * e2[a];
+                p1[a] = c[a] + B[0] * e1[a] + B[1] * e2[a];
+            }
+            const double n0 = std::sqrt(dot(p0, p0)), n1 = std::sqrt(dot(p1, p1));
+            for (int a = 0; a < 3; ++a) {
+                p0[a] /= n0;
+                p1[a] /= n1;
+            }
+            cross(p0, p1, x);
+            acc += 2.0 * std::atan2(std::fabs(dot(c, x)), 1.0 + dot(c, p0) + dot(p0, p1) + dot(p1, c));
+        }
+        area[i] = acc;
+    }
+}
+
+// Measures of the cells of a sphere of radius R (see sphere_cells).
+static void sphere_measures(int nz, int nphi, double R, double *sigma)
+{
+    if (nphi == 0) {
+        bauer_cell_areas(nz, sigma);
+        for (int j = 0; j < nz; ++j) sigma[j] *= R * R;
+    } else {
+        for (int j = 0; j < nz * nphi; ++j) sigma[j] = 4.0 * M_PI * R * R / (nz * nphi);
+    }
 }
 
 // Holes of a perforated domain: k disjoint balls (centre, r), dim + 1 numbers each, strictly inside
@@ -206,7 +315,8 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
     }
     case WOS_BALL:
         if (g->dim != 3 || !(p[3] > 0)) return set_error(WOS_EINVAL, "ball needs dim 3 and R > 0");
-        if (g->layout[1] < 1) return set_error(WOS_EINVAL, "ball needs layout (n_z >= 1, n_phi >= 1)");
+        if (!sphere_layout_ok(g->layout[0], g->layout[1]))
+            return set_error(WOS_EINVAL, "ball needs layout (n_z >= 1, n_phi >= 1) or (n >= 16, 0)");
         break;
     case WOS_BOX:
         if (g->dim != 2 && g->dim != 3) return set_error(WOS_EINVAL, "box needs dim 2 or 3");
@@ -218,8 +328,9 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
             return set_error(WOS_EINVAL, "perforated disc / ball needs dim 2 or 3 and R > 0");
         if (g->dim == 2 && (g->layout[1] < 1 || g->layout[2] < 1))
             return set_error(WOS_EINVAL, "perforated disc needs layout (M_out >= 1, M_hole >= 1, holes >= 1)");
-        if (g->dim == 3 && (g->layout[1] < 1 || g->layout[2] < 1 || g->layout[3] < 1))
-            return set_error(WOS_EINVAL, "perforated ball needs layout (n_z, n_phi, n_z hole, n_phi hole), all >= 1");
+        if (g->dim == 3 && (!sphere_layout_ok(g->layout[0], g->layout[1]) || !sphere_layout_ok(g->layout[2], g->layout[3])))
+            return set_error(WOS_EINVAL, "perforated ball needs sphere layouts (n_z >= 1, n_phi >= 1) or (n >= 16, 0) "
+                                         "for the ball and the holes");
         const wos_status st = validate_holes(g, g->dim == 2 ? g->layout[2] : g->n_verts);
         if (st != WOS_OK) return st;
         break;
@@ -228,8 +339,9 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
         if (g->dim != 2 && g->dim != 3) return set_error(WOS_EINVAL, "perforated box needs dim 2 or 3");
         for (int a = 0; a < g->dim; ++a)
             if (!(p[g->dim + a] > p[a])) return set_error(WOS_EINVAL, "perforated box needs lo < hi on every axis");
-        if (g->layout[1] < 1 || (g->dim == 3 && g->layout[2] < 1))
-            return set_error(WOS_EINVAL, "perforated box needs layout (n, M_hole) or (n, n_z hole, n_phi hole), all >= 1");
+        if ((g->dim == 2 && g->layout[1] < 1) || (g->dim == 3 && !sphere_layout_ok(g->layout[1], g->layout[2])))
+            return set_error(WOS_EINVAL, "perforated box needs layout (n, M_hole) or (n, n_z hole, n_phi hole) with "
+                                         "the sphere layout (n_z >= 1, n_phi >= 1) or (n >= 16, 0)");
         const wos_status st = validate_holes(g, g->n_verts);
         if (st != WOS_OK) return st;
         break;
@@ -318,7 +430,7 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
         break;
     }
     case WOS_BALL:
-        for (int j = 0; j < M; ++j) sigma[j] = 4.0 * M_PI * p[3] * p[3] / M;
+        sphere_measures(g->layout[0], g->layout[1], p[3], sigma);
         break;
     case WOS_PERFORATED: case WOS_PERFBOX: {
         // outer cells (arcs / equal-area sphere cells of the disc or ball, or box patches), then the
@@ -326,10 +438,12 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
         const int d = g->dim;
         int n_out = 0, hc = 0;
         if (g->kind == WOS_PERFORATED) {
-            n_out = d == 2 ? g->layout[0] : g->layout[0] * g->layout[1];
-            const double R = p[d], a = d == 2 ? 2.0 * M_PI * R : 4.0 * M_PI * R * R;
-            for (int j = 0; j < n_out; ++j) sigma[j] = a / n_out;
-            hc = d == 2 ? g->layout[1] : g->layout[2] * g->layout[3];
+            n_out = d == 2 ? g->layout[0] : static_cast<int>(sphere_cells(g->layout[0], g->layout[1]));
+            if (d == 2)
+                for (int j = 0; j < n_out; ++j) sigma[j] = 2.0 * M_PI * p[d] / n_out;
+            else
+                sphere_measures(g->layout[0], g->layout[1], p[d], sigma);
+            hc = d == 2 ? g->layout[1] : static_cast<int>(sphere_cells(g->layout[2], g->layout[3]));
         } else {
             const int n = g->layout[0], per_face = d == 2 ? n : n * n;
             for (int f = 0; f < 2 * d; ++f) {
@@ -339,12 +453,18 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
                 for (int j = 0; j < per_face; ++j) sigma[f * per_face + j] = area;
             }
             n_out = 2 * d * per_face;
-            hc = d == 2 ? g->layout[1] : g->layout[1] * g->layout[2];
+            hc = d == 2 ? g->layout[1] : static_cast<int>(sphere_cells(g->layout[1], g->layout[2]));
         }
         const int k = (M - n_out) / hc;
         for (int l = 0; l < k; ++l) {
-            const double r = g->verts[(d + 1) * l + d], a = d == 2 ? 2.0 * M_PI * r : 4.0 * M_PI * r * r;
-            for (int j = 0; j < hc; ++j) sigma[n_out + l * hc + j] = a / hc;
+            const double r = g->verts[(d + 1) * l + d];
+            if (d == 2) {
+                for (int j = 0; j < hc; ++j) sigma[n_out + l * hc + j] = 2.0 * M_PI * r / hc;
+            } else {
+                const int nz = g->kind == WOS_PERFORATED ? g->layout[2] : g->layout[1];
+                const int nphi = g->kind == WOS_PERFORATED ? g->layout[3] : g->layout[2];
+                sphere_measures(nz, nphi, r, sigma + n_out + l * hc);
+            }
         }
         break;
     }
@@ -640,6 +760,24 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         }
     }
     I.n_segs = static_cast<int32_t>(segs.size());
+    // Bauer node tables of the spheres with layout (n, 0), after the staged records (not staged)
+    auto add_nodes = [&](int n, int slot) {
+        std::vector<double> u;
+        bauer_nodes(n, u);
+        I.node_off[slot] = static_cast<int32_t>(segs.size());
+        for (int k = 0; k < n; ++k) {
+            PolySeg s{};
+            s.ax = u[3 * k];
+            s.ay = u[3 * k + 1];
+            s.ey = u[3 * k + 2];
+            segs.push_back(s);
+        }
+    };
+    if (g->dim == 3) {
+        if ((g->kind == WOS_BALL || g->kind == WOS_PERFORATED) && g->layout[1] == 0) add_nodes(g->layout[0], 0);
+        if (g->kind == WOS_PERFORATED && g->layout[3] == 0) add_nodes(g->layout[2], 1);
+        if (g->kind == WOS_PERFBOX && g->layout[2] == 0) add_nodes(g->layout[1], 1);
+    }
     return WOS_OK;
 }
 
@@ -706,7 +844,7 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
         st = fill_inst(&J.geom, &J.walk, M, insts[q], segs[q]);
         if (st != WOS_OK) return st;
         max_elem = std::max(max_elem, M);
-        seg_max = std::max(seg_max, static_cast<int>(segs[q].size()));
+        seg_max = std::max(seg_max, static_cast<int>(insts[q].n_segs));  // the records staged in LDS
     }
     gl.hist_words = (max_elem + 3) & ~3;
     gl.seg_bytes = static_cast<int>(sizeof(PolySeg)) * seg_max;

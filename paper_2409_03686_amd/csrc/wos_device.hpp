@@ -33,6 +33,8 @@ struct alignas(16) DevInst {
     int32_t layout[4];
     int32_t n_verts, precision;
     int32_t n_segs, pad0;  // PolySeg records to stage in LDS: n_verts, or 2 n_verts with the mapped edges
+    int32_t node_off[2];   // record index in segs of the Bauer node table (unit vectors in ax, ay, ey) of
+                           // the outer sphere / of the holes, for sphere layouts (n, 0); read from HBM
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
     double Si[4];     // 2D: S^{-1}, row-major 2x2 (mapped-exact radius of polygons)
@@ -555,6 +557,65 @@ __device__ __forceinline__ int sphere_cell(const double *v, int nz, int nphi)
     return iz * nphi + arc_of(atan2(v[1], v[0]), nphi);
 }
 
+// Extrinsic Voronoi cell (Appendix Ex. A.2) among the n Bauer nodes R u_k of a sphere, v the point
+// relative to the centre: the node nearest v, the lowest index on ties.  Node k has u_k.z = 1 - (2k + 1)/n,
+// and |v - R u_k|^2 = (|v| - R)^2 + R |v| |u - u_k|^2 >= (|v| - R)^2 + R |v| (z - u_k.z)^2 (u = v/|v|,
+// z = u.z): after a first window of about one turn of the spiral around the node of v's z band, a node
+// can only beat the best score s when (z - u_k.z)^2 <= (s - (|v| - R)^2) / (R |v|), an index range that
+// the search then completes.  Scores are the plain squared distances, so the cell equals a full scan's.
+__device__ __forceinline__ int bauer_cell(const double *v, double R, int n, const PolySeg *u)
+{
+#pragma clang fp contract(off)
+    const double rv = __builtin_sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double z = v[2] / rv;
+    auto score = [&](int k) {
+        const double t0 = v[0] - R * u[k].ax, t1 = v[1] - R * u[k].ay, t2 = v[2] - R * u[k].ey;
+        return t0 * t0 + t1 * t1 + t2 * t2;
+    };
+    const int k0 = clamp_index((1.0 - z) * 0.5 * static_cast<double>(n), n);
+    const int w = static_cast<int>(__builtin_sqrt(static_cast<double>(n) * 3.141592653589793)) + 2;
+    const int lo = k0 - w < 0 ? 0 : k0 - w, hi = k0 + w > n - 1 ? n - 1 : k0 + w;
+    double best = __builtin_inf();
+    int bk = lo;
+    for (int k = lo; k <= hi; ++k) {
+        const double sc = score(k);
+        if (sc < best) {
+            best = sc;
+            bk = k;
+        }
+    }
+    // the z range that can still hold a better node (1e-12: far above the scores' rounding)
+    const double t = (best - (rv - R) * (rv - R)) / (R * rv) + 1e-12;
+    const double dz = __builtin_sqrt(t > 0.0 ? t : 0.0);
+    const double nn = static_cast<double>(n);
+    double flo = __builtin_floor(((1.0 - (z + dz)) * nn - 1.0) * 0.5);
+    double fhi = __builtin_ceil(((1.0 - (z - dz)) * nn - 1.0) * 0.5);
+    const int klo = !(flo > 0.0) ? 0 : (flo > nn - 1.0 ? n - 1 : static_cast<int>(flo));  // NaN: 0
+    const int khi = !(fhi > 0.0) ? 0 : (fhi > nn - 1.0 ? n - 1 : static_cast<int>(fhi));
+    for (int k = klo; k < lo; ++k) {
+        const double sc = score(k);
+        if (sc < best || (sc == best && k < bk)) {
+            best = sc;
+            bk = k;
+        }
+    }
+    for (int k = hi + 1; k <= khi; ++k) {
+        const double sc = score(k);
+        if (sc < best) {
+            best = sc;
+            bk = k;
+        }
+    }
+    return bk;
+}
+
+// Cell of a sphere of radius R: layout (n_z, n_phi) gives the equal-area (z band, azimuth) cells,
+// (n, 0) the Voronoi cells of n Bauer nodes (table `nodes`, in HBM).
+__device__ __forceinline__ int sphere_cell_of(const double *v, int nz, int nphi, double R, const PolySeg *nodes)
+{
+    return nphi == 0 ? bauer_cell(v, R, nz, nodes) : sphere_cell(v, nz, nphi);
+}
+
 // Box: the nearest face (ties: the lowest face index), then the patch of the other coordinates.
 template <int DIM> __device__ __forceinline__ int box_cell(const DevInst &I, const double *x)
 {
@@ -618,27 +679,31 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
             }
         }
         int n_out, hc, c;
+        const double Rh = comp >= 0 ? segs[comp].ex : 0.0;
         if constexpr (KIND == kPerforated) {
-            n_out = DIM == 2 ? I.layout[0] : I.layout[0] * I.layout[1];
-            hc = DIM == 2 ? I.layout[1] : I.layout[2] * I.layout[3];
+            n_out = DIM == 2 ? I.layout[0] : (I.layout[1] == 0 ? I.layout[0] : I.layout[0] * I.layout[1]);
+            hc = DIM == 2 ? I.layout[1] : (I.layout[3] == 0 ? I.layout[2] : I.layout[2] * I.layout[3]);
             if (comp < 0) {
                 double w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) w[a] = x[a] - I.p[a];
-                return DIM == 2 ? arc_of(atan2(w[1], w[0]), I.layout[0]) : sphere_cell(w, I.layout[0], I.layout[1]);
+                return DIM == 2 ? arc_of(atan2(w[1], w[0]), I.layout[0])
+                                : sphere_cell_of(w, I.layout[0], I.layout[1], I.p[DIM], I.segs + I.node_off[0]);
             }
-            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1]) : sphere_cell(vb, I.layout[2], I.layout[3]);
+            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1])
+                         : sphere_cell_of(vb, I.layout[2], I.layout[3], Rh, I.segs + I.node_off[1]);
         } else {
             n_out = DIM == 2 ? 4 * I.layout[0] : 6 * I.layout[0] * I.layout[0];
-            hc = DIM == 2 ? I.layout[1] : I.layout[1] * I.layout[2];
+            hc = DIM == 2 ? I.layout[1] : (I.layout[2] == 0 ? I.layout[1] : I.layout[1] * I.layout[2]);
             if (comp < 0) return box_cell<DIM>(I, x);
-            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1]) : sphere_cell(vb, I.layout[1], I.layout[2]);
+            c = DIM == 2 ? arc_of(atan2(vb[1], vb[0]), I.layout[1])
+                         : sphere_cell_of(vb, I.layout[1], I.layout[2], Rh, I.segs + I.node_off[1]);
         }
         return n_out + comp * hc + c;
     } else if constexpr (KIND == kBall) {
         double v[3];
         for (int a = 0; a < 3; ++a) v[a] = x[a] - I.p[a];
-        return sphere_cell(v, I.layout[0], I.layout[1]);
+        return sphere_cell_of(v, I.layout[0], I.layout[1], I.p[3], I.segs + I.node_off[0]);
     } else {  // kBox
         return box_cell<DIM>(I, x);
     }

@@ -87,6 +87,9 @@ def _kind_cases():
         "disk_mapped_bound": (wi.Geometry(2, wi.DISK, (0.2, -0.1, 1.3), (37,)), K2, 2),
         "annulus_mapped_bound": (wi.Geometry(2, wi.ANNULUS, (0.1, -0.05, 0.3, 1.0), (40, 24)), K2, 2),
         "ball_mapped_bound": (wi.Geometry(3, wi.BALL, (0.0, 0.1, 0.0, 1.0), (6, 10)), K3, 2),
+        "ball_bauer_voronoi": (wi.Geometry(3, wi.BALL, (0.0, 0.1, 0.0, 1.0), (500, 0)), K3, 0),
+        "cube_with_bauer_hole": (wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (5, 64, 0),
+                                             verts=np.array([[0.55, 0.45, 0.5, 0.3]])), K3, 0),
         "perforated_aniso": (wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (40, 12, 3),
                                          verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])),
                              K2, 0),

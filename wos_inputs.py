@@ -357,17 +357,18 @@ def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: Optional[f
 
 
 def spherical_shell_example(example: int = 6, n_walks: int = 10_000, eps: float = 1e-10,
-                            precision: int = FP64, outer=(25, 40), inner=(10, 10),
+                            precision: int = FP64, outer=(1000, 0), inner=(100, 0),
                             n_obs: int = 100) -> Instance:
     """The paper's Examples 6 and 7 (Section 5.3): the unit ball minus the ball of radius 0.5 about
     the origin (Example 6) or about (0.3, 0, 0) (Example 7), K = I; Gamma_0 the outer sphere
-    (M_0 = 25 x 40 = 1000 equal-area cells), Gamma_1 the inner sphere (M_1 = 10 x 10 = 100); the
+    (M_0 = 1000 extrinsic Voronoi cells of Bauer nodes), Gamma_1 the inner sphere (M_1 = 100); the
     points on Bauer's spiral on Gamma_D = {dist(x, Gamma_0) = 0.05}, the sphere of radius 0.95.
+    Sphere layouts (n_z, n_phi) give equal-area cells instead.
     Data: 3D-sol1, u = x1 x2 + x2^2 - x3^2 (harmonic), without noise."""
     c = {6: (0.0, 0.0, 0.0), 7: (0.3, 0.0, 0.0)}[example]
     g = Geometry(3, PERFORATED, (0.0, 0.0, 0.0, 1.0), tuple(outer) + tuple(inner),
                  verts=np.array([[c[0], c[1], c[2], 0.5]]))
-    g.gamma1_mask = (np.arange(g.n_elem) >= outer[0] * outer[1]).astype(np.uint8)
+    g.gamma1_mask = (np.arange(g.n_elem) >= _sphere_cells(*outer)).astype(np.uint8)
     x = 0.95 * bauer_spiral(n_obs)
     inst = Instance(g, np.eye(3), x, n_walks, eps=eps, seed=2, precision=precision,
                     name=f"spherical_shell_example{example}")
