@@ -86,6 +86,11 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *                (M): M equal pieces of the perimeter, counted from vertex 0.
  *   WOS_BALL     dim 3, params (cx, cy, cz, R),       layout (n_z, n_phi)   equal-area cells:
  *                band iz over z from the top, sector iphi over the azimuth; j = iz n_phi + iphi.
+ *                Every sphere layout may instead be (n, 0), n >= 16: the extrinsic Voronoi cells
+ *                (appendix, Ex. A.2) of the n nodes of Bauer's spiral of Section 5.3, polar angle
+ *                arccos(1 - (2k - 1)/n) and azimuth sqrt(n pi) times it, k = 1..n (cell k - 1):
+ *                the point goes to the nearest node of its sphere, ties to the lower index; cell
+ *                measures are the spherical Voronoi areas.
  *   WOS_BOX      dim 2 or 3, params (lo_0..lo_{d-1}, hi_0..hi_{d-1}), layout (n): faces in the
  *                order (x=lo, x=hi, y=lo, y=hi[, z=lo, z=hi]), n^(d-1) patches each, patch
  *                indices along the remaining axes in increasing axis order; j = f n^(d-1) + idx.
@@ -102,7 +107,8 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *                face patches as WOS_BOX, holes as for WOS_PERFORATED; layout (n, M_hole) in 2D,
  *                (n, n_z hole, n_phi hole) in 3D: the box's patches first, then each hole's cells.
  * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
- * weights of the paper's appendix, Ex. A.3); ties go to the lowest face/segment index. */
+ * weights of the paper's appendix, Ex. A.3; for Bauer layouts the extrinsic ones of Ex. A.2, taken
+ * on the stop point's nearest sphere); ties go to the lowest face/segment index. */
 typedef enum {
     WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5,
     WOS_PERFORATED = 6, WOS_PERFBOX = 7
