@@ -13,8 +13,8 @@
  *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
  *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
  *   radius: r = dist(x, dD) ("WoE bound"), or, for boxes and polygons, the largest r with
- *   x + r S B(0,1) inside D ("mapped exact"), or, for discs, annuli and balls, a larger radius certified by a support bound
- *   ("mapped bound", see step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
+ *   x + r S B(0,1) inside D ("mapped exact"), or, for discs, annuli, balls and ellipses, a larger radius
+ *   certified by a support bound ("mapped bound", see step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
  *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
  *   reaching dD, dist <= 0) and its last point is binned.  The stop point is projected onto dD and the element
@@ -459,6 +459,27 @@ static void centred_norms(int dim, const double *S, const double *x, const doubl
     *a2 = aa;
 }
 
+/* Ellipse (semi-axes a, b about c) in its own coordinates w = A^{-1}(x - c), A = diag(a, b): the step
+ * ellipsoid is w + r T u, T = A^{-1} S, and |w + r T u|^2 <= |w|^2 + 2 r |T^T w| + r^2 |T|^2 for
+ * |u| <= 1, so it stays in the unit disc for r <= the positive root of |T|^2 r^2 + 2 t r - g = 0,
+ * t = |T^T w| = |S A^{-1} w|, g = 1 - |w|^2, which is g / (sqrt(t^2 + |T|^2 g) + t).  |T|^2 is the
+ * largest eigenvalue of T^T T = S A^{-2} S. */
+static double ellipse_mapped_bound(const og_geom *g, const double *S, const double *x)
+{
+    double a = g->p[2], b = g->p[3];
+    double w0 = (x[0] - g->p[0]) / a, w1 = (x[1] - g->p[1]) / b;
+    double gg = 1.0 - (w0 * w0 + w1 * w1);
+    double v0 = w0 / a, v1 = w1 / b;
+    double t0 = S[0] * v0 + S[1] * v1, t1 = S[3] * v0 + S[4] * v1;
+    double t = sqrt(t0 * t0 + t1 * t1);
+    double m00 = (S[0] / a) * (S[0] / a) + (S[3] / b) * (S[3] / b);
+    double m11 = (S[1] / a) * (S[1] / a) + (S[4] / b) * (S[4] / b);
+    double m01 = (S[0] / a) * (S[1] / a) + (S[3] / b) * (S[4] / b);
+    double h = 0.5 * (m00 - m11);
+    double sig2 = 0.5 * (m00 + m11) + sqrt(h * h + m01 * m01);
+    return gg / (sqrt(t * t + sig2 * gg) + t);
+}
+
 /* Step radius.  Any ellipsoid x + r S B(0,1) inside D is a valid step of the chain (the chain is the
  * trace of the diffusion on inscribed ellipsoids, Section 4.2); the exit law does not depend on the
  * choice.  mode 0: r = dist (the ellipsoid lies in the Euclidean ball of radius r because
@@ -466,7 +487,7 @@ static void centred_norms(int dim, const double *S, const double *x, const doubl
  * min over faces of (face distance)/|S e_a|, for a polygon the distance of S^{-1} x to the mapped
  * edges.  mode 2 (disc, annulus, ball): the bounds above for the outer
  * circle or sphere and, for the annulus, the inner circle, where dist itself is also a valid bound
- * for the inner circle: r = min(r_out, max(r_in, d)). */
+ * for the inner circle: r = min(r_out, max(r_in, d)); for the ellipse max(ellipse_mapped_bound, d). */
 static double step_radius(const og_geom *g, int mode, const double *S, const double *x, double d)
 {
     if (mode == 0) return d;
@@ -493,6 +514,10 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
     if (mode == 2) {
         double q, a2;
         centred_norms(dim, S, x, g->p, &q, &a2);
+        if (g->kind == OG_ELLIPSE) {
+            double r = ellipse_mapped_bound(g, S, x);
+            return r > d ? r : d;  /* d (the Lipschitz bound) is valid too */
+        }
         if (g->kind == OG_DISK) return inside_ball_radius(q, a2, g->p[2]);
         if (g->kind == OG_BALL) return inside_ball_radius(q, a2, g->p[3]);
         /* annulus: p = (centre, R_in, R_out) */
@@ -517,7 +542,7 @@ static int radius_mode_valid(const og_geom *g, int mode)
 {
     if (mode == 0) return 1;
     if (mode == 1) return g->kind == OG_BOX || g->kind == OG_POLYGON;
-    if (mode == 2) return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL;
+    if (mode == 2) return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL || g->kind == OG_ELLIPSE;
     return 0;
 }
 

@@ -476,6 +476,42 @@ def test_mapped_bound_radius_keeps_the_ellipsoid_inside(case):
     assert min(gain) > 1.15, gain
 
 
+def test_ellipse_mapped_bound_keeps_the_ellipsoid_inside_and_the_law():
+    """Mapped bound on the ellipse (1 x 0.4): brute force over 4096 points of each step ellipsoid's
+    boundary shows it inside the ellipse for three conductivities, r >= the Lipschitz distance bound,
+    and the chain keeps the WoE chain's exit law and reproduces 2D-sol4 with far fewer steps."""
+    rng = np.random.default_rng(41)
+    g = wi.Geometry(2, wi.ELLIPSE, (0.1, -0.2, 1.0, 0.4), (24,))
+    c, A = np.array([0.1, -0.2]), np.array([1.0, 0.4])
+    x = wi.sample_points(g, 400, rng)
+    t = rng.uniform(0, 2 * np.pi, 200)
+    s = 1 - rng.uniform(1e-5, 1e-2, 200)
+    x = np.concatenate([x, c + np.stack([A[0] * s * np.cos(t), A[1] * s * np.sin(t)], 1)])
+    U = _sphere_dirs(2, 4096)
+    gains = []
+    for cond in (1.0, 4.0, 20.0):
+        K = _random_spd(2, cond, rng)
+        _, _, S = walks.instance_setup(K, 2)
+        r = walks.step_radii(g, S, x, 2)
+        d, _ = walks.geom_eval(g, x)
+        assert np.all(r >= d)
+        gains.append(np.mean(r / d))
+        for i in range(len(x)):
+            pts = (x[i] + r[i] * (U @ S[:2, :2].T) - c) / A
+            assert np.sqrt((pts ** 2).sum(1)).max() <= 1 + 1e-12, (cond, i)
+    assert min(gains) > 1.3, gains
+    K = np.array([[1.0, 0.3], [0.3, 0.4]])
+    x = wi.sample_points(g, 6, np.random.default_rng(23))
+    N = 20_000
+    c0, s0, _ = walks.build_measure(g, K, x, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c2, s2, _ = walks.build_measure(g, K, x, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=2)
+    assert s2["steps"] < 0.5 * s0["steps"] and s2["escapes"] == 0, (s0["steps"], s2["steps"])
+    rep = statutil.two_sample(c0, N, c2, N)
+    assert rep["ok"], rep
+    _, _, S = walks.instance_setup(K, 2)
+    assert np.all(_exit_mean_z(g, S, x, _sol4(K), 30_000, grad_bound=4.0, radius_mode=2) < 4.5)
+
+
 def test_mapped_bound_radius_same_law_fewer_steps():
     """The mapped-bound chain has the exit law of the WoE-bound chain (the two estimates agree within
     their sampling error) and takes far fewer steps on the anisotropic annulus."""
