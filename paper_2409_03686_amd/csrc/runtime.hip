@@ -566,8 +566,8 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON)
         return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes and polygons only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
-        g->kind != WOS_BALL)
-        return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs, annuli and balls only");
+        g->kind != WOS_BALL && g->kind != WOS_ELLIPSE)
+        return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs, annuli, balls and ellipses only");
     return WOS_OK;
 }
 
@@ -659,7 +659,21 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             I.fold_rn[a] = static_cast<float>(A * static_cast<double>(I.neg2delta));
         }
     }
-    if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
+    if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind == WOS_ELLIPSE) {
+        // |T|^2, T = A^{-1} S: the largest eigenvalue of T^T T = S A^{-2} S (2 x 2)
+        const double a = g->params[2], b = g->params[3];
+        const double m00 = (I.S[0] / a) * (I.S[0] / a) + (I.S[3] / b) * (I.S[3] / b);
+        const double m11 = (I.S[1] / a) * (I.S[1] / a) + (I.S[4] / b) * (I.S[4] / b);
+        const double m01 = (I.S[0] / a) * (I.S[1] / a) + (I.S[3] / b) * (I.S[4] / b);
+        const double h = 0.5 * (m00 - m11);
+        I.msig2 = 0.5 * (m00 + m11) + std::sqrt(h * h + m01 * m01);
+        // FP32 error bound of the radius: |w|^2 and g carry about 6 units of 2^-24, t, s, the
+        // reciprocal and the product some 16 relative units of a radius at most 1/m, where
+        // m = min(sigma_min(S) / max(a, b), |T|) bounds s + t from below; three times that
+        const double m = std::min(std::sqrt(lmin / lmax) / std::max(a, b), std::sqrt(I.msig2));
+        I.mbf[0] = static_cast<float>(I.msig2);
+        I.mbf[1] = static_cast<float>(0x1.0p-24 * 64.0 / m);
+    } else if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
         // FP32 mapped bound (centred positions, |v| <= R_out): R_out^2, R_in^2 and absolute error
         // bounds of the two radii, subtracted on the device so that they never exceed the exact ones.
         // With u = 2^-24 and s = sigma_min(S) = (lambda_min / lambda_max)^{1/2}: |S v| and |v|^2

@@ -1000,6 +1000,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
         case kRadiusVariant + kDisk: return kptr<R, 2, kRadiusVariant + kDisk>(wave);
         case kRadiusVariant + kAnnulus: return kptr<R, 2, kRadiusVariant + kAnnulus>(wave);
         case kEllipse: return kptr<R, 2, kEllipse>(wave);
+        case kRadiusVariant + kEllipse: return kptr<R, 2, kRadiusVariant + kEllipse>(wave);
         case kPolygon: return kptr<R, 2, kPolygon>(wave);
         case kRadiusVariant + kPolygon: return kptr<R, 2, kRadiusVariant + kPolygon>(wave);
         case kPerforated: return kptr<R, 2, kPerforated>(wave);

@@ -37,6 +37,7 @@ struct alignas(16) DevInst {
                            // the outer sphere / of the holes, for sphere layouts (n, 0); read from HBM
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
+    double msig2;     // ellipse, mapped bound: |A^{-1} S|^2 (A = diag(a, b))
     double Si[4];     // 2D: S^{-1}, row-major 2x2 (mapped-exact radius of polygons)
     double cn[3];     // |S e_a|: the half-extent of the unit ellipsoid S B(0,1) along axis a
     double eps;
@@ -56,7 +57,8 @@ struct alignas(16) DevInst {
     float fold_rs[2];   // A_a (1 - 2^-16)
     float fold_rn[2];   // A_a (-2 delta): step of coordinate a = (r fold_rs + fold_rn) cos(angle)
     float mbf[4];       // mapped-bound radius (FP32): R_out^2, its error bound, R_in^2, its error bound;
-                        // polygons: mbf[1] = error bound of the FP32 mapped distance
+                        // ellipse: |A^{-1} S|^2, error bound; polygons: mbf[1] = error bound of the
+                        // FP32 mapped distance
     uint32_t key0, key1, inst, max_steps;
     uint64_t walk_begin;  // first walk id of the range
     uint32_t n_walks;     // walks per point in this call
@@ -351,6 +353,9 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 
 // Step radius.  WoE bound: r = dist (the ellipsoid x + r S B(0,1) lies in B(x, r) since |S| <= 1).
 // Mapped exact (boxes): the largest r with x + r S B(0,1) inside the box, min_a gap_a / |S e_a|.
+// Ellipse (semi-axes a, b): in w = A^{-1}(x - c) the step ellipsoid is w + r T u, T = A^{-1} S, inside the
+// unit disc for r <= g / (sqrt(t^2 + |T|^2 g) + t), t = |S A^{-1} w|, g = 1 - |w|^2 (the support bound
+// |w + r T u|^2 <= |w|^2 + 2 r t + r^2 |T|^2); the Lipschitz distance bound stays valid: r = max(., d).
 // Mapped bound (discs, annuli, balls): with v = x - c and a = |S v|, |v + r S u|^2 lies between
 // |v|^2 - 2 r a and |v|^2 + 2 r a + r^2 for |u| <= 1, so r_out = sqrt(a^2 + R^2 - |v|^2) - a keeps the
 // ellipsoid inside the circle / sphere of radius R and r_in = (|v|^2 - R_in^2) / (2 a) keeps it off
@@ -358,7 +363,10 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 // RV: the radius variant of a launch, fixed at compile time (0: dist, or the box's radius by its mode;
 // 1: mapped bound, or mapped exact for polygons) or -1: read the instance's radius mode.  A launch-wide kind selector adds
 // kRadiusVariant to the kind for the mapped bound.
-constexpr bool mapped_bound_kind(int kind) { return kind == kDisk || kind == kAnnulus || kind == kBall; }
+constexpr bool mapped_bound_kind(int kind)
+{
+    return kind == kDisk || kind == kAnnulus || kind == kBall || kind == kEllipse;
+}
 constexpr int kRadiusVariant = 16;
 
 // Polygons (mapped exact): the ellipsoid is { z : |S^{-1}(z - x)| <= r }, so the largest inscribed r is
@@ -380,7 +388,18 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
             return best;
         }
     }
-    if constexpr (mapped_bound_kind(KIND) && RV != 0) {
+    if constexpr (KIND == kEllipse && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {
+            const double a = I.p[2], b = I.p[3];
+            const double w0 = (x[0] - I.p[0]) / a, w1 = (x[1] - I.p[1]) / b;
+            const double g = 1.0 - (w0 * w0 + w1 * w1);
+            const double v0 = w0 / a, v1 = w1 / b;
+            const double t0 = I.S[0] * v0 + I.S[1] * v1, t1 = I.S[3] * v0 + I.S[4] * v1;
+            const double t = __builtin_sqrt(t0 * t0 + t1 * t1);
+            const double r = g / (__builtin_sqrt(t * t + I.msig2 * g) + t);
+            return r > d ? r : d;
+        }
+    } else if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
             double v[DIM], q = 0.0, a2 = 0.0;
 #pragma unroll
@@ -437,7 +456,20 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
             return __builtin_amdgcn_sqrtf(best) - I.mbf[1];
         }
     }
-    if constexpr (mapped_bound_kind(KIND) && RV != 0) {
+    if constexpr (KIND == kEllipse && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {  // centred position; pf[4] = 1/a, pf[5] = 1/b
+            const float w0 = x[0] * I.pf[4], w1 = x[1] * I.pf[5];
+            const float g = 1.0f - __builtin_fmaf(w0, w0, w1 * w1);
+            const float v0 = w0 * I.pf[4], v1 = w1 * I.pf[5];
+            const float t0 = __builtin_fmaf(I.Sf[0], v0, I.Sf[1] * v1);
+            const float t1 = __builtin_fmaf(I.Sf[3], v0, I.Sf[4] * v1);
+            const float t2 = __builtin_fmaf(t0, t0, t1 * t1);
+            const float t = __builtin_amdgcn_sqrtf(t2);
+            const float sq = __builtin_amdgcn_sqrtf(__builtin_fmaf(I.mbf[0], g, t2));
+            const float r = __builtin_fmaf(g, __builtin_amdgcn_rcpf(sq + t), -I.mbf[1]);
+            return __builtin_fmaxf(r, d);
+        }
+    } else if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
             float q, a2;
             if constexpr (DIM == 2) {

@@ -78,6 +78,7 @@ def _kind_cases():
     cases = {
         "annulus_aniso": (wi.Geometry(2, wi.ANNULUS, (0.1, -0.05, 0.3, 1.0), (40, 24)), K2, 0),
         "ellipse_aniso": (wi.Geometry(2, wi.ELLIPSE, (0.0, 0.0, 1.0, 0.4), (50,)), K2, 0),
+        "ellipse_mapped_bound": (wi.Geometry(2, wi.ELLIPSE, (0.1, -0.2, 1.0, 0.4), (50,)), K2, 2),
         "lshape_aniso": (wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE), K2, 0),
         "lshape_mapped_exact": (wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE), K2, 1),
         "square_exact": (wi.Geometry(2, wi.BOX, (0.0, 0.0, 1.0, 2.0), (9,)), K2, 1),
@@ -183,7 +184,7 @@ def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
     assert rep2["ok"]
 
 
-@pytest.mark.parametrize("case", ["annulus", "ball", "lshape"])
+@pytest.mark.parametrize("case", ["annulus", "ball", "lshape", "ellipse"])
 def test_fp32_mapped_radius_vs_oracle(wos, ctx, case):
     """Mapped radii with FP32 geometry (the bound on the annulus and the ball, the exact radius on
     the L-shape): no escapes (the radius stays certified after its FP32 error bound is taken off),
@@ -193,7 +194,8 @@ def test_fp32_mapped_radius_vs_oracle(wos, ctx, case):
         inst = wi.cfg2_annulus(n_walks=40_000, n_obs=96, precision=wi.FP32_GEOM_FP64_EXIT,
                                radius_mode=wi.RADIUS_MAPPED_BOUND)
     else:
-        g, K, mode = _kind_cases()["ball_mapped_bound" if case == "ball" else "lshape_mapped_exact"]
+        g, K, mode = _kind_cases()[{"ball": "ball_mapped_bound", "lshape": "lshape_mapped_exact",
+                                    "ellipse": "ellipse_mapped_bound"}[case]]
         inst = wi.Instance(g, K, wi.sample_points(g, 48, np.random.default_rng(4)), 40_000, eps=1e-4, seed=9,
                            precision=wi.FP32_GEOM_FP64_EXIT, radius_mode=mode)
     c32, st, _ = _gpu(wos, ctx, inst)

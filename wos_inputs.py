@@ -43,7 +43,7 @@ FP64 = 0
 FP32_GEOM_FP64_EXIT = 1
 RADIUS_WOE_BOUND = 0
 RADIUS_MAPPED_EXACT = 1
-RADIUS_MAPPED_BOUND = 2   # discs, annuli, balls: support bound of the inscribed ellipsoid
+RADIUS_MAPPED_BOUND = 2   # discs, annuli, balls, ellipses: support bound of the inscribed ellipsoid
 
 
 @dataclasses.dataclass
@@ -529,7 +529,7 @@ def _layout_for(kind: int, dim: int, M_target: int):
 def _radius_for(kind: int, mapped_radii: bool) -> int:
     if kind == BOX or (mapped_radii and kind == POLYGON):
         return RADIUS_MAPPED_EXACT
-    if mapped_radii and kind in (DISK, ANNULUS, BALL):
+    if mapped_radii and kind in (DISK, ANNULUS, BALL, ELLIPSE):
         return RADIUS_MAPPED_BOUND
     return RADIUS_WOE_BOUND
 
@@ -542,7 +542,7 @@ def random_instance(rng: np.random.Generator, instance_id: int, kind_name: Optio
     points per instance in [32, 2048]; elements in [64, 2048]; walks log-uniform in [1e3, 1e5];
     Gamma_0 = elements whose reference point's last coordinate is >= the domain centre's.
     Step radius: the kind's mapped radius (exact for the cube and the L-shape, the bound for the
-    disk, annulus and ball; r = dist for the ellipse), or with mapped_radii=False the cube's only."""
+    disk, annulus, ball and ellipse), or with mapped_radii=False the cube's only."""
     kinds = ["disk", "ellipse", "lshape", "annulus", "ball", "cube"]
     kn = kind_name or kinds[int(rng.integers(len(kinds)))]
     if kn == "disk":
