@@ -512,6 +512,44 @@ def test_ellipse_mapped_bound_keeps_the_ellipsoid_inside_and_the_law():
     assert np.all(_exit_mean_z(g, S, x, _sol4(K), 30_000, grad_bound=4.0, radius_mode=2) < 4.5)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_perforated_mapped_bound_keeps_the_ellipsoid_inside_and_the_law(dim):
+    """Mapped bound on a disc / ball with holes: each step ellipsoid (brute force over its boundary)
+    stays in the outer circle or sphere and off every hole (whose centre it does not contain), r >=
+    dist; the chain keeps the WoE chain's exit law with fewer steps."""
+    rng = np.random.default_rng(50 + dim)
+    if dim == 2:
+        g = wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (24, 8, 3),
+                        verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]]))
+    else:
+        g = wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (4, 6, 3, 4),
+                        verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]]))
+    c, R = np.asarray(g.params[:dim]), g.params[dim]
+    holes = np.asarray(g.verts, float).reshape(-1, dim + 1)
+    x = wi.sample_points(g, 300, rng)
+    U = _sphere_dirs(dim, 2048 if dim == 2 else 6000)
+    K = _random_spd(dim, 10.0, rng)
+    _, _, S = walks.instance_setup(K, dim)
+    Sd = S[:dim, :dim]
+    r = walks.step_radii(g, S, x, 2)
+    d, _ = walks.geom_eval(g, x)
+    assert np.all(r >= d * (1 - 1e-12)) and np.mean(r / d) > 1.1
+    Si = np.linalg.inv(Sd)
+    for i in range(len(x)):
+        pts = x[i] + r[i] * (U @ Sd.T)
+        assert np.sqrt(((pts - c) ** 2).sum(1)).max() <= R * (1 + 1e-12)
+        for h in holes:
+            assert np.sqrt(((pts - h[:dim]) ** 2).sum(1)).min() >= h[dim] * (1 - 1e-12)
+            assert np.linalg.norm(Si @ (h[:dim] - x[i])) > r[i]
+    xs = wi.sample_points(g, 4, np.random.default_rng(60 + dim))
+    N = 10_000
+    c0, s0, _ = walks.build_measure(g, K, xs, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c2, s2, _ = walks.build_measure(g, K, xs, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=2)
+    assert s2["steps"] < 0.9 * s0["steps"] and s2["escapes"] == 0, (s0["steps"], s2["steps"])
+    rep = statutil.two_sample(c0, N, c2, N)
+    assert rep["ok"], rep
+
+
 def test_mapped_bound_radius_same_law_fewer_steps():
     """The mapped-bound chain has the exit law of the WoE-bound chain (the two estimates agree within
     their sampling error) and takes far fewer steps on the anisotropic annulus."""
