@@ -566,8 +566,9 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON)
         return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes and polygons only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
-        g->kind != WOS_BALL && g->kind != WOS_ELLIPSE)
-        return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs, annuli, balls and ellipses only");
+        g->kind != WOS_BALL && g->kind != WOS_ELLIPSE && g->kind != WOS_PERFORATED)
+        return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs and balls (with or without holes), "
+                                      "annuli and ellipses only");
     return WOS_OK;
 }
 
@@ -680,7 +681,7 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         // carry about 6 u |v| and 3 u R_out^2; sqrt(a^2 + R^2 - |v|^2) >= s R_out turns the latter into
         // 1.5 u R_out / s; the inner bound divides by 2 a >= 2 s R_in.  Twice the estimates are used.
         const double u = 0x1.0p-24, sg = std::sqrt(lmin / lmax);
-        const double Ro = g->kind == WOS_ANNULUS ? g->params[3] : g->params[g->dim];
+        const double Ro = g->kind == WOS_ANNULUS ? g->params[3] : g->params[g->dim];  // disc, ball, perforated
         I.mbf[0] = static_cast<float>(Ro * Ro);
         I.mbf[1] = static_cast<float>(u * Ro * (16.0 / sg + 16.0));
         if (g->kind == WOS_ANNULUS) {
@@ -770,6 +771,13 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             s.fay = static_cast<float>(h[1] - (centred ? g->params[1] : 0.0));
             s.fey = d == 3 ? static_cast<float>(h[2] - (centred ? g->params[2] : 0.0)) : 0.0f;
             s.fex = static_cast<float>(h[d]);
+            if (centred && w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
+                // the hole's mapped bound in FP32: R_l^2 and its error bound, the annulus's inner-circle
+                // bound with |v| <= 2 R_out (v from the hole's centre)
+                const double u = 0x1.0p-24, sg = std::sqrt(lmin / lmax), Ro = 2.0 * g->params[d], Rl = h[d];
+                s.fpad0 = static_cast<float>(Rl * Rl);
+                s.fpad1 = static_cast<float>(u * (4.0 * Ro * Ro / (sg * Rl) + Ro * (22.0 / sg + 20.0)));
+            }
             segs.push_back(s);
         }
     }

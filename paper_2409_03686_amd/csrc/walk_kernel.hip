@@ -1004,6 +1004,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
         case kPolygon: return kptr<R, 2, kPolygon>(wave);
         case kRadiusVariant + kPolygon: return kptr<R, 2, kRadiusVariant + kPolygon>(wave);
         case kPerforated: return kptr<R, 2, kPerforated>(wave);
+        case kRadiusVariant + kPerforated: return kptr<R, 2, kRadiusVariant + kPerforated>(wave);
         case kPerfBox: return kptr<R, 2, kPerfBox>(wave);
         case kBox: return kptr<R, 2, kBox>(wave);
         default: return kptr<R, 2, -1>(wave);
@@ -1013,6 +1014,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
     case kBall: return kptr<R, 3, kBall>(wave);
     case kRadiusVariant + kBall: return kptr<R, 3, kRadiusVariant + kBall>(wave);
     case kPerforated: return kptr<R, 3, kPerforated>(wave);
+    case kRadiusVariant + kPerforated: return kptr<R, 3, kRadiusVariant + kPerforated>(wave);
     case kPerfBox: return kptr<R, 3, kPerfBox>(wave);
     case kBox: return kptr<R, 3, kBox>(wave);
     default: return kptr<R, 3, -1>(wave);

@@ -365,7 +365,7 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 // kRadiusVariant to the kind for the mapped bound.
 constexpr bool mapped_bound_kind(int kind)
 {
-    return kind == kDisk || kind == kAnnulus || kind == kBall || kind == kEllipse;
+    return kind == kDisk || kind == kAnnulus || kind == kBall || kind == kEllipse || kind == kPerforated;
 }
 constexpr int kRadiusVariant = 16;
 
@@ -398,6 +398,46 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
             const double t = __builtin_sqrt(t0 * t0 + t1 * t1);
             const double r = g / (__builtin_sqrt(t * t + I.msig2 * g) + t);
             return r > d ? r : d;
+        }
+    } else if constexpr (KIND == kPerforated && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {  // the outer circle / sphere, then each hole as an inner one
+            double r_out, r_in = __builtin_inf();
+            {
+                double q = 0.0, a2 = 0.0, v[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    v[a] = x[a] - I.p[a];
+                    q += v[a] * v[a];
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) w += I.S[r * 3 + a] * v[a];
+                    a2 += w * w;
+                }
+                r_out = __builtin_sqrt(a2 + (I.p[DIM] * I.p[DIM] - q)) - __builtin_sqrt(a2);
+            }
+            for (int l = 0; l < I.n_verts; ++l) {
+                const double c[3] = {segs[l].ax, segs[l].ay, segs[l].ey};
+                double q = 0.0, a2 = 0.0, v[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    v[a] = x[a] - c[a];
+                    q += v[a] * v[a];
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) w += I.S[r * 3 + a] * v[a];
+                    a2 += w * w;
+                }
+                const double rl = (q - segs[l].ex * segs[l].ex) / (2.0 * __builtin_sqrt(a2));
+                r_in = rl < r_in ? rl : r_in;
+            }
+            if (r_in < d) r_in = d;
+            return r_out < r_in ? r_out : r_in;
         }
     } else if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
@@ -439,6 +479,25 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
     return d;
 }
 
+// |v|^2 and |S v|^2 in FP32.
+template <int DIM> __device__ __forceinline__ void centred_norms32(const DevInst &I, const float *v, float &q, float &a2)
+{
+    if constexpr (DIM == 2) {
+        q = __builtin_fmaf(v[0], v[0], v[1] * v[1]);
+        const float w0 = __builtin_fmaf(I.Sf[0], v[0], I.Sf[1] * v[1]);
+        const float w1 = __builtin_fmaf(I.Sf[3], v[0], I.Sf[4] * v[1]);
+        a2 = __builtin_fmaf(w0, w0, w1 * w1);
+    } else {
+        q = __builtin_fmaf(v[2], v[2], __builtin_fmaf(v[1], v[1], v[0] * v[0]));
+        a2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float w = __builtin_fmaf(I.Sf[r * 3 + 2], v[2], __builtin_fmaf(I.Sf[r * 3 + 1], v[1], I.Sf[r * 3] * v[0]));
+            a2 = __builtin_fmaf(w, w, a2);
+        }
+    }
+}
+
 // FP32 form of the mapped bound on centred positions; the error bounds in mbf are subtracted.
 template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(const DevInst &I, const float *x,
                                                                                float d, const PolySeg *segs)
@@ -469,24 +528,29 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
             const float r = __builtin_fmaf(g, __builtin_amdgcn_rcpf(sq + t), -I.mbf[1]);
             return __builtin_fmaxf(r, d);
         }
+    } else if constexpr (KIND == kPerforated && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {  // centred positions; hole records: centre, R_l, R_l^2 (fpad0),
+                                              // the FP32 error bound of the hole's radius (fpad1)
+            float r_in = __builtin_inff();
+            for (int l = 0; l < I.n_verts; ++l) {
+                float v[DIM];
+                v[0] = x[0] - segs[l].fax;
+                v[1] = x[1] - segs[l].fay;
+                if constexpr (DIM == 3) v[2] = x[2] - segs[l].fey;
+                float ql, a2l;
+                centred_norms32<DIM>(I, v, ql, a2l);
+                r_in = __builtin_fminf(r_in, __builtin_fmaf(ql - segs[l].fpad0, 0.5f * __builtin_amdgcn_rsqf(a2l),
+                                                            -segs[l].fpad1));
+            }
+            float q, a2;
+            centred_norms32<DIM>(I, x, q, a2);
+            const float r_out = __builtin_amdgcn_sqrtf(a2 + (I.mbf[0] - q)) - (__builtin_amdgcn_sqrtf(a2) + I.mbf[1]);
+            return __builtin_fminf(r_out, __builtin_fmaxf(r_in, d));
+        }
     } else if constexpr (mapped_bound_kind(KIND) && RV != 0) {
         if (RV == 1 || I.radius_mode == 2) {
             float q, a2;
-            if constexpr (DIM == 2) {
-                q = __builtin_fmaf(x[0], x[0], x[1] * x[1]);
-                const float w0 = __builtin_fmaf(I.Sf[0], x[0], I.Sf[1] * x[1]);
-                const float w1 = __builtin_fmaf(I.Sf[3], x[0], I.Sf[4] * x[1]);
-                a2 = __builtin_fmaf(w0, w0, w1 * w1);
-            } else {
-                q = __builtin_fmaf(x[2], x[2], __builtin_fmaf(x[1], x[1], x[0] * x[0]));
-                a2 = 0.0f;
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const float w = __builtin_fmaf(I.Sf[r * 3 + 2], x[2],
-                                                   __builtin_fmaf(I.Sf[r * 3 + 1], x[1], I.Sf[r * 3] * x[0]));
-                    a2 = __builtin_fmaf(w, w, a2);
-                }
-            }
+            centred_norms32<DIM>(I, x, q, a2);
             const float s = __builtin_amdgcn_sqrtf(a2 + (I.mbf[0] - q));
             if constexpr (KIND == kAnnulus) {
                 const float rq = __builtin_amdgcn_rsqf(a2);  // a2 >= (sigma_min R_in)^2 > 0
