@@ -13,8 +13,9 @@
  *   where S = Khat^{1/2}, Khat = K / lambda_max(K) (the paper assumes lambda_max = 1 without loss of
  *   generality; the walk-on-ellipsoids chain, Section 4.2 eq. "wos chain"), and r(x) is the step
  *   radius: r = dist(x, dD) ("WoE bound"), or, for boxes and polygons, the largest r with
- *   x + r S B(0,1) inside D ("mapped exact"), or, for discs and balls (with holes), annuli and
- *   ellipses, a larger radius certified by a support bound ("mapped bound", see step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
+ *   x + r S B(0,1) inside D ("mapped exact"), or, for discs, balls and boxes with holes, discs,
+ *   annuli, balls and ellipses, a larger radius certified by a support bound ("mapped bound", see
+ *   step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
  *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
  *   reaching dD, dist <= 0) and its last point is binned.  The stop point is projected onto dD and the element
@@ -487,8 +488,9 @@ static double ellipse_mapped_bound(const og_geom *g, const double *S, const doub
  * min over faces of (face distance)/|S e_a|, for a polygon the distance of S^{-1} x to the mapped
  * edges.  mode 2 (disc, annulus, ball): the bounds above for the outer
  * circle or sphere and, for the annulus, the inner circle, where dist itself is also a valid bound
- * for the inner circle: r = min(r_out, max(r_in, d)), and for a disc or ball with holes the smallest
- * hole bound as r_in; for the ellipse max(ellipse_mapped_bound, d). */
+ * for the inner circle: r = min(r_out, max(r_in, d)), and for a disc, ball or box with holes the
+ * smallest hole bound as r_in (the box's r_out its exact radius); for the ellipse
+ * max(ellipse_mapped_bound, d). */
 static double step_radius(const og_geom *g, int mode, const double *S, const double *x, double d)
 {
     if (mode == 0) return d;
@@ -519,9 +521,23 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
             double r = ellipse_mapped_bound(g, S, x);
             return r > d ? r : d;  /* d (the Lipschitz bound) is valid too */
         }
-        if (g->kind == OG_PERFORATED) {
-            /* the outer circle / sphere, then every hole as the annulus's inner circle */
-            double r_out = inside_ball_radius(q, a2, g->p[dim]), r_in = INFINITY;
+        if (g->kind == OG_PERFORATED || g->kind == OG_PERFBOX) {
+            /* the outer circle / sphere (or the box's exact radius, as mode 1), then every hole as the
+             * annulus's inner circle */
+            double r_out, r_in = INFINITY;
+            if (g->kind == OG_PERFORATED) {
+                r_out = inside_ball_radius(q, a2, g->p[dim]);
+            } else {
+                r_out = INFINITY;
+                for (int a = 0; a < dim; ++a) {
+                    double cn = 0.0;
+                    for (int r = 0; r < dim; ++r) cn += S[r * 3 + a] * S[r * 3 + a];
+                    cn = sqrt(cn);
+                    double lo = (x[a] - g->p[a]) / cn, hi = (g->p[dim + a] - x[a]) / cn;
+                    if (lo < r_out) r_out = lo;
+                    if (hi < r_out) r_out = hi;
+                }
+            }
             for (int l = 0; l < g->n_verts; ++l) {
                 const double *h = g->verts + (size_t)(dim + 1) * l;
                 double ql, a2l;
@@ -558,7 +574,7 @@ static int radius_mode_valid(const og_geom *g, int mode)
     if (mode == 1) return g->kind == OG_BOX || g->kind == OG_POLYGON;
     if (mode == 2)
         return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL || g->kind == OG_ELLIPSE ||
-               g->kind == OG_PERFORATED;
+               g->kind == OG_PERFORATED || g->kind == OG_PERFBOX;
     return 0;
 }
 

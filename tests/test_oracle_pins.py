@@ -512,19 +512,25 @@ def test_ellipse_mapped_bound_keeps_the_ellipsoid_inside_and_the_law():
     assert np.all(_exit_mean_z(g, S, x, _sol4(K), 30_000, grad_bound=4.0, radius_mode=2) < 4.5)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim", [2, 3, "box"])
 def test_perforated_mapped_bound_keeps_the_ellipsoid_inside_and_the_law(dim):
-    """Mapped bound on a disc / ball with holes: each step ellipsoid (brute force over its boundary)
-    stays in the outer circle or sphere and off every hole (whose centre it does not contain), r >=
-    dist; the chain keeps the WoE chain's exit law with fewer steps."""
-    rng = np.random.default_rng(50 + dim)
-    if dim == 2:
+    """Mapped bound on a disc / ball / square with holes: each step ellipsoid (brute force over its
+    boundary) stays in the outer circle, sphere or square and off every hole (whose centre it does not
+    contain), r >= dist; the chain keeps the WoE chain's exit law with fewer steps."""
+    box = dim == "box"
+    dim = 2 if box else dim
+    rng = np.random.default_rng(50 + dim + 7 * box)
+    if box:
+        g = wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.2), (13, 11),
+                        verts=np.array([[0.5, 0.0, 0.2], [-0.4, 0.45, 0.3]]))
+    elif dim == 2:
         g = wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (24, 8, 3),
                         verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]]))
     else:
         g = wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (4, 6, 3, 4),
                         verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]]))
     c, R = np.asarray(g.params[:dim]), g.params[dim]
+    lo, hi = np.asarray(g.params[:dim]), np.asarray(g.params[dim:2 * dim])
     holes = np.asarray(g.verts, float).reshape(-1, dim + 1)
     x = wi.sample_points(g, 300, rng)
     U = _sphere_dirs(dim, 2048 if dim == 2 else 6000)
@@ -537,11 +543,14 @@ def test_perforated_mapped_bound_keeps_the_ellipsoid_inside_and_the_law(dim):
     Si = np.linalg.inv(Sd)
     for i in range(len(x)):
         pts = x[i] + r[i] * (U @ Sd.T)
-        assert np.sqrt(((pts - c) ** 2).sum(1)).max() <= R * (1 + 1e-12)
+        if box:
+            assert np.all(pts >= lo - 1e-12) and np.all(pts <= hi + 1e-12)
+        else:
+            assert np.sqrt(((pts - c) ** 2).sum(1)).max() <= R * (1 + 1e-12)
         for h in holes:
             assert np.sqrt(((pts - h[:dim]) ** 2).sum(1)).min() >= h[dim] * (1 - 1e-12)
             assert np.linalg.norm(Si @ (h[:dim] - x[i])) > r[i]
-    xs = wi.sample_points(g, 4, np.random.default_rng(60 + dim))
+    xs = wi.sample_points(g, 4, np.random.default_rng(60 + dim + 7 * box))
     N = 10_000
     c0, s0, _ = walks.build_measure(g, K, xs, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
     c2, s2, _ = walks.build_measure(g, K, xs, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=2)
