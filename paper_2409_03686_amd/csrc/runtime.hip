@@ -566,9 +566,9 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON)
         return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes and polygons only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
-        g->kind != WOS_BALL && g->kind != WOS_ELLIPSE && g->kind != WOS_PERFORATED)
+        g->kind != WOS_BALL && g->kind != WOS_ELLIPSE && g->kind != WOS_PERFORATED && g->kind != WOS_PERFBOX)
         return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs and balls (with or without holes), "
-                                      "annuli and ellipses only");
+                                      "boxes with holes, annuli and ellipses only");
     return WOS_OK;
 }
 
@@ -771,10 +771,17 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             s.fay = static_cast<float>(h[1] - (centred ? g->params[1] : 0.0));
             s.fey = d == 3 ? static_cast<float>(h[2] - (centred ? g->params[2] : 0.0)) : 0.0f;
             s.fex = static_cast<float>(h[d]);
-            if (centred && w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
+            if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND) {
                 // the hole's mapped bound in FP32: R_l^2 and its error bound, the annulus's inner-circle
-                // bound with |v| <= 2 R_out (v from the hole's centre)
-                const double u = 0x1.0p-24, sg = std::sqrt(lmin / lmax), Ro = 2.0 * g->params[d], Rl = h[d];
+                // bound with |v| <= Ro (v from the hole's centre): twice the outer radius, or for the
+                // box (absolute positions) twice the larger of its diagonal and the coordinate scale
+                double Ro = 2.0 * g->params[d];
+                if (!centred) {
+                    double diag = 0.0;
+                    for (int a = 0; a < d; ++a) diag += (g->params[d + a] - g->params[a]) * (g->params[d + a] - g->params[a]);
+                    Ro = 2.0 * std::max(std::sqrt(diag), domain_scale(g));
+                }
+                const double u = 0x1.0p-24, sg = std::sqrt(lmin / lmax), Rl = h[d];
                 s.fpad0 = static_cast<float>(Rl * Rl);
                 s.fpad1 = static_cast<float>(u * (4.0 * Ro * Ro / (sg * Rl) + Ro * (22.0 / sg + 20.0)));
             }

@@ -1006,6 +1006,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
         case kPerforated: return kptr<R, 2, kPerforated>(wave);
         case kRadiusVariant + kPerforated: return kptr<R, 2, kRadiusVariant + kPerforated>(wave);
         case kPerfBox: return kptr<R, 2, kPerfBox>(wave);
+        case kRadiusVariant + kPerfBox: return kptr<R, 2, kRadiusVariant + kPerfBox>(wave);
         case kBox: return kptr<R, 2, kBox>(wave);
         default: return kptr<R, 2, -1>(wave);
         }
@@ -1016,6 +1017,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
     case kPerforated: return kptr<R, 3, kPerforated>(wave);
     case kRadiusVariant + kPerforated: return kptr<R, 3, kRadiusVariant + kPerforated>(wave);
     case kPerfBox: return kptr<R, 3, kPerfBox>(wave);
+    case kRadiusVariant + kPerfBox: return kptr<R, 3, kRadiusVariant + kPerfBox>(wave);
     case kBox: return kptr<R, 3, kBox>(wave);
     default: return kptr<R, 3, -1>(wave);
     }

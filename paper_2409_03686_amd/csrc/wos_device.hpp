@@ -365,7 +365,8 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
 // kRadiusVariant to the kind for the mapped bound.
 constexpr bool mapped_bound_kind(int kind)
 {
-    return kind == kDisk || kind == kAnnulus || kind == kBall || kind == kEllipse || kind == kPerforated;
+    return kind == kDisk || kind == kAnnulus || kind == kBall || kind == kEllipse || kind == kPerforated ||
+           kind == kPerfBox;
 }
 constexpr int kRadiusVariant = 16;
 
@@ -399,10 +400,18 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
             const double r = g / (__builtin_sqrt(t * t + I.msig2 * g) + t);
             return r > d ? r : d;
         }
-    } else if constexpr (KIND == kPerforated && RV != 0) {
-        if (RV == 1 || I.radius_mode == 2) {  // the outer circle / sphere, then each hole as an inner one
+    } else if constexpr ((KIND == kPerforated || KIND == kPerfBox) && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {  // the outer circle / sphere (the box's exact radius), then
+                                              // each hole as an inner circle
             double r_out, r_in = __builtin_inf();
-            {
+            if constexpr (KIND == kPerfBox) {
+                r_out = __builtin_inf();
+                for (int a = 0; a < DIM; ++a) {
+                    const double lo = (x[a] - I.p[a]) / I.cn[a], hi = (I.p[DIM + a] - x[a]) / I.cn[a];
+                    r_out = lo < r_out ? lo : r_out;
+                    r_out = hi < r_out ? hi : r_out;
+                }
+            } else {
                 double q = 0.0, a2 = 0.0, v[DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
@@ -528,9 +537,10 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
             const float r = __builtin_fmaf(g, __builtin_amdgcn_rcpf(sq + t), -I.mbf[1]);
             return __builtin_fmaxf(r, d);
         }
-    } else if constexpr (KIND == kPerforated && RV != 0) {
-        if (RV == 1 || I.radius_mode == 2) {  // centred positions; hole records: centre, R_l, R_l^2 (fpad0),
-                                              // the FP32 error bound of the hole's radius (fpad1)
+    } else if constexpr ((KIND == kPerforated || KIND == kPerfBox) && RV != 0) {
+        if (RV == 1 || I.radius_mode == 2) {  // hole records: centre (relative to the disc / ball's centre,
+                                              // absolute for the box), R_l, R_l^2 (fpad0), the FP32 error
+                                              // bound of the hole's radius (fpad1)
             float r_in = __builtin_inff();
             for (int l = 0; l < I.n_verts; ++l) {
                 float v[DIM];
@@ -542,9 +552,18 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
                 r_in = __builtin_fminf(r_in, __builtin_fmaf(ql - segs[l].fpad0, 0.5f * __builtin_amdgcn_rsqf(a2l),
                                                             -segs[l].fpad1));
             }
-            float q, a2;
-            centred_norms32<DIM>(I, x, q, a2);
-            const float r_out = __builtin_amdgcn_sqrtf(a2 + (I.mbf[0] - q)) - (__builtin_amdgcn_sqrtf(a2) + I.mbf[1]);
+            float r_out;
+            if constexpr (KIND == kPerfBox) {  // the box's exact radius, as for WOS_BOX
+                r_out = __builtin_inff();
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+                    r_out = __builtin_fminf(r_out, __builtin_fminf((x[a] - I.pf[a]) * I.icnf[a],
+                                                                   (I.pf[DIM + a] - x[a]) * I.icnf[a]));
+            } else {
+                float q, a2;
+                centred_norms32<DIM>(I, x, q, a2);
+                r_out = __builtin_amdgcn_sqrtf(a2 + (I.mbf[0] - q)) - (__builtin_amdgcn_sqrtf(a2) + I.mbf[1]);
+            }
             return __builtin_fminf(r_out, __builtin_fmaxf(r_in, d));
         }
     } else if constexpr (mapped_bound_kind(KIND) && RV != 0) {

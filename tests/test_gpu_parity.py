@@ -97,6 +97,10 @@ def _kind_cases():
         "perforated_ball_aniso": (wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (6, 11, 4, 7),
                                               verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]])),
                                   K3, 0),
+        "square_with_holes_mapped": (wi.Geometry(2, wi.PERFBOX, (-1.0, -1.0, 1.0, 1.2), (13, 11),
+                                                 verts=np.array([[0.5, 0.0, 0.2], [-0.4, 0.45, 0.3]])), K2, 2),
+        "cube_with_hole_mapped": (wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (5, 4, 6),
+                                              verts=np.array([[0.55, 0.45, 0.5, 0.3]])), K3, 2),
         "perforated_mapped_bound": (wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (40, 12, 3),
                                                 verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15],
                                                                 [-0.35, 0.45, 0.2]])), K2, 2),
@@ -190,7 +194,7 @@ def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
     assert rep2["ok"]
 
 
-@pytest.mark.parametrize("case", ["annulus", "ball", "lshape", "ellipse", "perforated"])
+@pytest.mark.parametrize("case", ["annulus", "ball", "lshape", "ellipse", "perforated", "perfbox"])
 def test_fp32_mapped_radius_vs_oracle(wos, ctx, case):
     """Mapped radii with FP32 geometry (the bound on the annulus and the ball, the exact radius on
     the L-shape): no escapes (the radius stays certified after its FP32 error bound is taken off),
@@ -201,7 +205,8 @@ def test_fp32_mapped_radius_vs_oracle(wos, ctx, case):
                                radius_mode=wi.RADIUS_MAPPED_BOUND)
     else:
         g, K, mode = _kind_cases()[{"ball": "ball_mapped_bound", "lshape": "lshape_mapped_exact",
-                                    "ellipse": "ellipse_mapped_bound", "perforated": "perforated_mapped_bound"}[case]]
+                                    "ellipse": "ellipse_mapped_bound", "perforated": "perforated_mapped_bound",
+                                    "perfbox": "cube_with_hole_mapped"}[case]]
         inst = wi.Instance(g, K, wi.sample_points(g, 48, np.random.default_rng(4)), 40_000, eps=1e-4, seed=9,
                            precision=wi.FP32_GEOM_FP64_EXIT, radius_mode=mode)
     c32, st, _ = _gpu(wos, ctx, inst)
