@@ -143,11 +143,12 @@ typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
  *   MAPPED_EXACT  boxes and polygons: the largest inscribed radius; for a box min over faces of
  *                 gap_a / |S e_a|, for a polygon the distance from S^{-1} X to the mapped edges
  *                 S^{-1}[a, b] (the ellipsoid is the set of z with |S^{-1}(z - X)| <= r).
- *   MAPPED_BOUND  discs, annuli, balls, ellipses, and discs and balls with holes (WOS_PERFORATED):
- *                 with v = X - c and a = |S v|, r = sqrt(a^2 + R^2 - |v|^2) - a for the outer circle
- *                 or sphere of radius R; for the inner circle of an annulus, or each hole (v and a
- *                 from its centre), (|v|^2 - R_in^2) / (2 a); r = min(outer, max(smallest inner,
- *                 dist)) (equal to dist when S = I).  Ellipse (semi-axes a, b, A = diag(a, b)):
+ *   MAPPED_BOUND  discs, annuli, balls, ellipses, and discs, balls and boxes with holes
+ *                 (WOS_PERFORATED, WOS_PERFBOX): with v = X - c and a = |S v|,
+ *                 r = sqrt(a^2 + R^2 - |v|^2) - a for the outer circle or sphere of radius R (for a
+ *                 box its exact radius as above); for the inner circle of an annulus, or each hole
+ *                 (v and a from its centre), (|v|^2 - R_in^2) / (2 a); r = min(outer, max(smallest
+ *                 inner, dist)) (equal to dist when S = I).  Ellipse (semi-axes a, b, A = diag(a, b)):
  *                 with w = A^{-1}(X - c), t = |S A^{-1} w|, g = 1 - |w|^2 and s2 = |A^{-1} S|^2,
  *                 r = max(g / (sqrt(t^2 + s2 g) + t), dist bound).
  * Other combinations return WOS_ENOTSUP. */
@@ -166,7 +167,7 @@ typedef struct {
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */
     int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes, polygons; MAPPED_BOUND: discs, annuli, balls,
-                             ellipses, perforated discs and balls) */
+                             ellipses, perforated discs, balls and boxes) */
     uint32_t max_steps;   /* step cap S_max (0 -> 10000, must be < 2^31); capped walks are binned where they are */
 } wos_walk_params;
 
