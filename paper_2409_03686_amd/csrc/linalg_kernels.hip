@@ -735,10 +735,11 @@ __global__ void gram_accept_kernel(SvdDevView v)
 //   cols <= kt: the Gram path of A itself with the Jacobi of one workgroup (gram_jacobi1_kernel).
 //   cols >  kt: a range sketch Y = A Om (Om a +-1 matrix from Philox) and an orthonormal basis
 //               Q = Y E diag(1/lambda) from the eigenvectors E, eigenvalues lambda^2 of Y^T Y (Gram
-//               path); two subspace iterations Y = A A^T Q, each re-orthonormalised the same way
-//               (without them the leading singular values come out only to ~1e-3 when the
-//               spectrum has a Monte Carlo noise floor; with them to ~1e-14); then C = Q^T A, the
-//               Gram path of C^T, U = Q E_C, V = C^T E_C / s.
+//               path); one subspace iteration Y = A A^T Q, re-orthonormalised the same way
+//               (without it the leading singular values come out only to ~1e-3 when the spectrum
+//               has a Monte Carlo noise floor; with one the TSVD solutions stay within ~4e-5 of the
+//               full SVD's, with two within ~1e-7 at one more one-workgroup Jacobi run per
+//               request); then C = Q^T A, the Gram path of C^T, U = Q E_C, V = C^T E_C / s.
 // Components with s <= rank_cut s_1 (1e-5) are left out of the reconstruction: below that the
 // Gram path's squaring of the condition number makes them inaccurate.
 // ---------------------------------------------------------------------------------------------
@@ -1088,7 +1089,7 @@ __global__ void rank_kernel(const double *__restrict__ z, int n, int k, double *
     }
 }
 
-constexpr int kPowerIters = 2;
+constexpr int kPowerIters = 1;
 
 static hipError_t gemm(const GemmArgs &g, hipStream_t stream)
 {
@@ -1505,7 +1506,7 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
         return gemm({v.Y, 1, R, v.Lt, 1, Kl, nullptr, v.Q, R, v.rows, K, K, v.zt, K, 1}, stream);
     };
     if ((e = orth()) != hipSuccess) return e;
-    // two subspace iterations Y = A (A^T Q), each followed by orth (Om holds A^T Q)
+    // kPowerIters subspace iterations Y = A (A^T Q), each followed by orth (Om holds A^T Q)
     for (int it = 0; it < kPowerIters; ++it) {
         if ((e = gemm({v.A, R, 1, v.Q, 1, R, nullptr, v.Om, Cc, v.cols, K, v.rows, nullptr, 0, 0}, stream)) != hipSuccess) return e;
         if ((e = gemm({v.A, 1, R, v.Om, 1, Cc, nullptr, v.Y, R, v.rows, K, v.cols, nullptr, 0, 0}, stream)) != hipSuccess) return e;
