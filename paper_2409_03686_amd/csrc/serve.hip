@@ -343,8 +343,9 @@ class Engine {
             if (L.svd.v.tk) {
                 e = tsvd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), r.walk.seed ^ (uint64_t(r.walk.instance) << 32) ^ 0x9e3779b97f4a7c15ull, s.stream);
             } else {
-                const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, ctx_->n_cu);
-                e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, s.stream);
+                const int cus = stream_cus(ctx_, s.stream);
+                const int grid = svd_coop_grid(L.svd.v.rows, L.svd.v.colsp, cus);
+                e = svd_launch(L.svd.v, counts, 1.0 / static_cast<double>(nw), grid, cus, s.stream);
             }
         }
         double *u1 = reinterpret_cast<double *>(base + L.off_u1);

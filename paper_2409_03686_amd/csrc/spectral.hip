@@ -109,6 +109,7 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
     const size_t npn = static_cast<size_t>(v.np);
     const size_t tkn = static_cast<size_t>(v.tk);
     const size_t big = v.tk && v.cols > v.tk ? tkn : 0;  // sketch buffers only when projecting
+    const bool grid = !v.tk && v.np > kGramMaxCols;      // device-wide Gram path
     hs.bytes = 0;
     // device arrays, in carve order
     const size_t sz[] = {
@@ -117,7 +118,8 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
         carve_size(v.n, 8), carve_size(hs.g1.size(), 4), carve_size(std::max<size_t>(hs.g0.size(), 1), 4),
         carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
         carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
-        carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(1, 8),
+        carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(grid ? npn : 0, 8),
+        carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn : 0, 4), carve_size(1, 8),
         carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * big, 8), carve_size(size_t(v.rows) * big, 8),
         carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(big, 8),
         carve_size(std::max<size_t>(tkn, 1), 4)};
@@ -150,6 +152,10 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     v.G = carve<double>(cur, npn * npn);
     v.L = carve<double>(cur, npn * npn);
     v.zs = carve<double>(cur, npn);
+    const bool grid = !v.tk && v.np > kGramMaxCols;
+    v.gnrm = grid ? carve<double>(cur, npn) : nullptr;
+    v.gctl = grid ? carve<uint32_t>(cur, kGridCtlWords) : nullptr;
+    v.gpiv = grid ? carve<int32_t>(cur, 3 * npn) : nullptr;
     v.crit = carve<unsigned long long>(cur, 1);
     const size_t tkn = static_cast<size_t>(v.tk);
     const size_t big = v.tk && v.cols > v.tk ? tkn : 0;
@@ -244,7 +250,7 @@ extern "C" wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts
     // cooperative grids sized for the CUs the stream may use (all, or its CU mask)
     const int coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, stream_cus(ctx, static_cast<hipStream_t>(stream)));
     HIP_TRY(ctx, svd_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), coop_grid,
-                            static_cast<hipStream_t>(stream)));
+                            stream_cus(ctx, static_cast<hipStream_t>(stream)), static_cast<hipStream_t>(stream)));
     return WOS_OK;
 }
 
@@ -272,6 +278,27 @@ extern "C" wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t 
     if (sweeps) *sweeps = info[0];
     if (error_flag) *error_flag = info[1];
     if (method) *method = info[4] ? WOS_SVD_GRAM : WOS_SVD_HESTENES;
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_svd_gram_check(const wos_svd_t *h, int32_t *gram_sweeps, int32_t *gram_error_flag,
+                                         double *check, void *stream)
+{
+    if (!h) return set_error(WOS_EINVAL, "handle NULL");
+    int32_t info[kInfoWords] = {};
+    unsigned long long crit = 0ull;
+    hipError_t e = hipMemcpyAsync(info, h->v.info, sizeof info, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&crit, h->v.crit, sizeof crit, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(WOS_EDEVICE, "reading SVD diagnostics failed: %s", hipGetErrorString(e));
+    if (gram_sweeps) *gram_sweeps = info[2];
+    if (gram_error_flag) *gram_error_flag = info[3];
+    if (check) {
+        double c;
+        std::memcpy(&c, &crit, sizeof c);
+        *check = c;
+    }
     return WOS_OK;
 }
 
@@ -423,7 +450,7 @@ extern "C" wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, 
         e = launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.mode, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
                          gl.items, cursor, gl.hist_words, gl.seg_bytes, gl.block, gl.grid, cs);
     if (e == hipSuccess && svd) {
-        e = svd_launch(svd->v, job->counts_dev, 1.0 / static_cast<double>(n_walks), svd->coop_grid, cs);
+        e = svd_launch(svd->v, job->counts_dev, 1.0 / static_cast<double>(n_walks), svd->coop_grid, ctx->n_cu, cs);
         if (e == hipSuccess) {
             RegDev r{reg->kind, reg->rank, reg->alpha, reg->noise_delta, reg->tau};
             e = recon_launch(svd->v, job->counts_dev, 1.0 / static_cast<double>(n_walks), uD_dev,

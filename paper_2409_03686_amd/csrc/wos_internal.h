@@ -11,9 +11,17 @@ namespace wos {
 constexpr int kMaxSweeps = 60;
 
 // View of an SVD workspace passed by value to the linear-algebra kernels.
-// Largest column count (after transposing wide blocks) that the Gram path handles: its
+// Largest column count (after transposing wide blocks) of the one-workgroup Gram path: its
 // factorisation keeps the whole Gram matrix in the registers of one 1024-thread workgroup.
 constexpr int kGramMaxCols = 192;
+// Largest column count of the device-wide Gram path (blocked Cholesky factor, Jacobi with the
+// factor's rows in the registers of 256-thread workgroups, at most 8 rows per thread).
+constexpr int kGramGridMaxCols = 2048;
+// Round flags of the device-wide Jacobi (one per workgroup: kGramGridMaxCols / 16 workgroups).
+constexpr int kGridFlags = 128;
+// Control words of the device-wide Jacobi: flags, rotations and large rotations per sweep, a grid
+// barrier counter and an error word.
+constexpr int kGridCtlWords = kGridFlags + 2 * kMaxSweeps + 2;
 
 // Control words of an SVD (device, zeroed by the assemble kernel).
 enum SvdCtrl : int {
@@ -47,6 +55,9 @@ struct SvdDevView {
     double *G;              // np x np Gram matrix A^T A
     double *L;              // np x np factor X with X X^T = G, then its Jacobi-rotated columns
     double *zs;             // np column norms of the rotated factor
+    double *gnrm;           // np squared norms in flight (device-wide Jacobi; null otherwise)
+    uint32_t *gctl;         // kGridCtlWords control words (device-wide Jacobi; null otherwise)
+    int32_t *gpiv;          // 3 np row states of the pivoted blocked Cholesky (null otherwise)
     unsigned long long *crit;  // acceptance statistic (bit pattern of a non-negative double)
     // Truncated path (serving; tk = 0: not used): the kt leading singular triplets from a range
     // sketch of kt columns (cols > kt) or from the Gram path of A itself (cols <= kt), with
@@ -78,7 +89,8 @@ hipError_t launch_walks(int precision, int dim, int kind_sel, int mode, const De
                         uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream);
 
-hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid,
+// n_cu: CUs the stream may use (cooperative grids are sized for them)
+hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid, int n_cu,
                       hipStream_t stream);
 int svd_coop_grid(int rows, int colsp, int n_cu);
 int gram_order(int cols);  // np of the Gram path for this column count, 0 if it does not apply
