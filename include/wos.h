@@ -258,12 +258,15 @@ wos_status wos_svd_destroy(wos_ctx *ctx, wos_svd_t *h);
  * s^2 are the eigenvalues of Lambda^nu = B B^T (the spectrum the paper studies).
  * Method: with A = B (or B^T when m < n) and c = min(m, n) <= 2048, first the Gram path:
  * G = A^T A, a factor X with X X^T = G (c <= 192: pivoted elimination in one workgroup; wider: a
- * blocked Cholesky factorisation), one-sided Jacobi on X (right vectors and s; c > 192: spread over
- * the device, which needs c / 32 rounded up to 2 resident workgroups of 256 threads on the
- * stream's CUs, else the Gram path is skipped), left vectors A v / s.  Its result is kept only if
- * the left vectors pass the check max_ij |u_i.u_j - delta_ij| s_i s_j <= max(2^-40, 16 c' 2^-52) s_1^2
- * (c' = c rounded up to 64) and the smallest non-zero singular value is at least 2^-30 s_1; otherwise (and for c > 2048) one-sided
- * Jacobi (Hestenes) on A itself computes the result. */
+ * blocked Cholesky factorisation with diagonal pivoting), one-sided Jacobi on X (right vectors and
+ * s; c > 192: spread over the device, which needs c / 16 (rounded up to a multiple of 4) resident
+ * workgroups of 256 threads on the stream's CUs, else the Gram path is skipped, and followed by a
+ * first-order correction of the right vectors), left vectors u_j = A v_j / s_j.  Its result is kept
+ * only if the left vectors pass the check max_ij |u_i.u_j - delta_ij| s_i s_j <= max(2^-40,
+ * 16 c' 2^-52) s_1^2 (c' = c rounded up to 64), every s_j is positive and the residual certificate
+ * |A^T u_j - s_j v_j| + s_j | |u_j|^2 - 1 | <= 2^-35 s_1 holds for every j (it bounds the distance
+ * from s_j to a singular value of A); otherwise (and for c > 2048) one-sided Jacobi (Hestenes) on
+ * A itself computes the result. */
 wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts_dev, uint64_t n_walks,
                    void *stream);
 /* Device pointers and sizes of the factors (valid until the handle is destroyed). */
@@ -276,11 +279,12 @@ typedef enum { WOS_SVD_HESTENES = 0, WOS_SVD_GRAM = 1 } wos_svd_method;
 wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag, int32_t *method,
                         void *stream);
 /* Diagnostics of the Gram path of the last completed wos_svd: its Jacobi sweeps and error flags
- * (as in wos_svd_info; both 0 when the path did not run) and its acceptance statistic
- * max_ij |u_i.u_j - delta_ij| s_i s_j / s_1^2 (accepted at or below max(2^-40, 16 c' 2^-52)).  Any out-pointer may be
- * NULL.  Synchronises `stream`. */
+ * (as in wos_svd_info; both 0 when the path did not run), its orthogonality statistic
+ * max_ij |u_i.u_j - delta_ij| s_i s_j / s_1^2 and its residual certificate
+ * max_j |A^T u_j - s_j v_j| + s_j | |u_j|^2 - 1 | (absolute).  Any out-pointer may be NULL.
+ * Synchronises `stream`. */
 wos_status wos_svd_gram_check(const wos_svd_t *h, int32_t *gram_sweeps, int32_t *gram_error_flag,
-                              double *check, void *stream);
+                              double *check, double *residual, void *stream);
 
 /* ------------------------------------------------------------------------------------------- */
 /* Reconstruction (Algorithm Main)                                                               */

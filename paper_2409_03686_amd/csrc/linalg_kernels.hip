@@ -95,7 +95,7 @@ __global__ void assemble_kernel(SvdDevView v, const uint32_t *__restrict__ count
         for (int t = threadIdx.x; t < 2 * kMaxSweeps; t += blockDim.x) v.rot[t] = 0u;
         if (threadIdx.x < kCtrlWords) v.ctrl[threadIdx.x] = 0u;
         if (threadIdx.x < kInfoWords) v.info[threadIdx.x] = 0;
-        if (threadIdx.x == 0) *v.crit = 0ull;
+        if (threadIdx.x < 2) v.crit[threadIdx.x] = 0ull;
         if (v.gctl)
             for (int t = threadIdx.x; t < kGridCtlWords; t += blockDim.x) v.gctl[t] = 0u;
     }
@@ -492,16 +492,16 @@ __global__ void scatter_kernel(SvdDevView v, const uint32_t *skip)
 //   columns, so G = Z Z^T and the right singular vectors of A are Z's columns over their norms s;
 //   the left ones are A v / s (MFMA).  Up to kGramMaxCols columns the factor comes from an
 //   outer-product elimination with diagonal pivoting and the Jacobi runs in one workgroup; wider
-//   blocks take the device-wide kernels further down.  The result is accepted when the computed
+//   blocks take the device-wide kernels further down.  The result is accepted when (i) the computed
 //   left vectors pass max_ij |u_i.u_j - delta_ij| s_i s_j <= max(2^-40, 16 np 2^-52) s_1^2 (so
 //   V^T A^T A V = diag(s^2) holds to that level entrywise: a consistency check of the factor and the
-//   iteration, whose stopping rule leaves cosines up to np 2^-52 between the columns) and the
-//   smallest non-zero singular value is at least 2^-30 s_1; otherwise the Hestenes path on A runs.
-//   The singular values then agree with LAPACK's to a few 1e-13 s_1 (tests against gesvd on
-//   Monte Carlo blocks with s_min / s_1 down to 1e-6, and on random blocks with prescribed
-//   spectra down to 1e-9): rounding in G is proportional to the column norms it combines, which
-//   is what a backward error on the columns of A would give, so the small singular values lose
-//   relative accuracy but not accuracy relative to s_1.
+//   iteration, whose stopping rule leaves cosines up to np 2^-52 between the columns) and (ii) the
+//   residual certificate (gram_resid_kernel) bounds the error of every singular value by 2^-35 s_1;
+//   otherwise the Hestenes path on A runs.  Rounding in G is proportional to the column norms it
+//   combines, so singular values whose vectors are localised (small columns, as on Monte Carlo
+//   blocks with s_min / s_1 = 1e-6) stay accurate to a few 1e-13 s_1, while values below ~sqrt(u) s_1
+//   that arise from cancellation cannot be resolved from G at all: the certificate tells the two
+//   apart.
 // ---------------------------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -689,8 +689,9 @@ __global__ __launch_bounds__(256) void gram_yside_kernel(SvdDevView v)
 }
 
 // Acceptance statistic max_ij |y_i . y_j - delta_ij| s_i s_j / s_1^2 over the k x k Gram matrix of
-// Y (MFMA over the rows), folded into crit with an atomic max on the bit pattern.
-__global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v)
+// Y (MFMA over the rows), folded into crit with an atomic max on the bit pattern; the Gram matrix
+// itself goes to store (k x k, column-major) when that is not null.
+__global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v, double *store)
 {
     const double *ys = v.trans ? v.V : v.U;
     const int tk = (v.k + 15) / 16;
@@ -712,6 +713,13 @@ __global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v)
     const double inv2 = s0 > 0.0 ? 1.0 / (s0 * s0) : 0.0;
     double dev = 0.0;
     const int j = j0 + li;
+    if (store && j < v.k) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + 4 * e + lk;
+            if (i < v.k) store[static_cast<size_t>(j) * v.k + i] = acc[e];
+        }
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int i = i0 + 4 * e + lk;
@@ -728,23 +736,90 @@ __global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v)
     if (lane == 0) atomicMax(v.crit, static_cast<unsigned long long>(__double_as_longlong(dev)));
 }
 
+// Certificate of the singular values: with u_j = A v_j / s_j (so A v_j = s_j u_j exactly), the
+// residual of the other side, e_j = |A^T u_j - s_j v_j| + s_j | |u_j|^2 - 1 |, bounds the distance
+// from s_j to a singular value of A (the symmetric matrix [[0, A], [A^T, 0]] has the residual
+// (0, A^T u - s v) / sqrt 2 at (u, v) / sqrt 2, after u is normalised).  C = A^T Ys (cols x k) is in
+// Cm; one block per column j folds e_j into crit[1] (bit pattern, atomic max).
+__global__ __launch_bounds__(256) void gram_resid_kernel(SvdDevView v, const double *__restrict__ Cm)
+{
+    __shared__ double scratch[16];
+    const double *vs = v.trans ? v.U : v.V;
+    const double *ys = v.trans ? v.V : v.U;
+    for (int j = blockIdx.x; j < v.k; j += gridDim.x) {
+        const double sj = v.s[j];
+        double r2 = 0.0, u2 = 0.0;
+        for (int i = threadIdx.x; i < v.cols; i += 256) {
+            const double d = Cm[static_cast<size_t>(j) * v.cols + i] - sj * vs[static_cast<size_t>(j) * v.cols + i];
+            r2 = __builtin_fma(d, d, r2);
+        }
+        for (int i = threadIdx.x; i < v.rows; i += 256) {
+            const double y = ys[static_cast<size_t>(j) * v.rows + i];
+            u2 = __builtin_fma(y, y, u2);
+        }
+        r2 = block_sum(r2, scratch);
+        u2 = block_sum(u2, scratch);
+        const double ej = __builtin_sqrt(r2) + sj * __builtin_fabs(u2 - 1.0);
+        if (threadIdx.x == 0)
+            atomicMax(v.crit + 1, static_cast<unsigned long long>(__double_as_longlong(ej != ej ? __builtin_inf() : ej)));
+        __syncthreads();
+    }
+}
+
+// Accepts the Gram path's result when the iteration ended without error, the left vectors pass the
+// orthogonality check, every singular value is positive (a zero one would leave its eigenvector
+// column empty: V = Z / s; the Hestenes path gives it a basis vector of the null space) and the
+// residual certificate bounds every singular value's error by 2^-35 s_1.
 __global__ void gram_accept_kernel(SvdDevView v)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double s0 = v.s[0];
-    int last = v.k - 1;  // exact zeros come from exactly zero columns (their factor columns stay zero)
-    while (last > 0 && v.s[last] == 0.0) --last;
-    const double sk = v.s[last];
-    const double crit = __longlong_as_double(static_cast<long long>(*v.crit));
-    // the Jacobi leaves |z_p.z_q| <= np 2^-52 |z_p| |z_q|, so the statistic's floor grows with np
+    const double s0 = v.s[0], sk = v.s[v.k - 1];
+    const double crit = __longlong_as_double(static_cast<long long>(v.crit[0]));
+    const double resid = __longlong_as_double(static_cast<long long>(v.crit[1]));
+    // the Jacobi leaves |z_p.z_q| <= np 2^-52 |z_p| |z_q|, so the check's floor grows with np
     const double limit = __builtin_fmax(0x1.0p-40, 16.0 * v.np * 0x1.0p-52);
-    const bool ok = v.info[3] == 0 && s0 > 0.0 && sk >= 0x1.0p-30 * s0 && crit <= limit;
+    const bool ok = v.info[3] == 0 && s0 > 0.0 && sk > 0.0 && crit <= limit && resid <= 0x1.0p-35 * s0;
     v.ctrl[kCtrlGramOk] = ok ? 1u : 0u;
     if (ok) {
         v.info[0] = v.info[2];
         v.info[1] = 0;
         v.info[4] = 1;
     }
+}
+
+// First-order correction of the eigenvector side Vs (device-wide path).  The rotated factor's
+// columns are orthogonal only up to cosines of np 2^-52 relative to their own norms, so
+// F = Vs^T A^T A Vs - diag(s^2) = diag(s) (Ys^T Ys - I) diag(s) keeps entries of that size times
+// s_i^2 + s_j^2, which for a large and a small singular value is large next to the small one's
+// square (regularised solutions, which act like (A^T A + alpha^2)^{-1}, amplify it by
+// (s_1 / alpha)^2).  Perturbation theory of the symmetric eigenproblem gives the correction
+// Vs <- Vs (I + K), K_ij = F_ij / (s_j^2 - s_i^2), taken only where |F_ij| <= |s_j^2 - s_i^2| / 10 (a
+// pair that close stays as it is; filters hardly tell its members apart).  C = Ys^T Ys is in Cm; the
+// kernel writes I + K (k x k, column-major) to Km and clears the acceptance statistic for the
+// check that follows the correction.
+__global__ void gram_fix_kernel(SvdDevView v, const double *__restrict__ Cm, double *__restrict__ Km)
+{
+    const size_t kk = static_cast<size_t>(v.k) * v.k;
+    for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < kk;
+         e += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int i = static_cast<int>(e % v.k), j = static_cast<int>(e / v.k);
+        double val = i == j ? 1.0 : 0.0;
+        if (i != j) {
+            const double si = v.s[i], sj = v.s[j];
+            const double f = si * Cm[e] * sj;
+            const double d2 = (sj - si) * (sj + si);
+            if (d2 != 0.0 && __builtin_fabs(f) <= 0.1 * __builtin_fabs(d2)) val = f / d2;
+        }
+        Km[e] = val;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) v.crit[0] = 0ull;
+}
+
+__global__ void copy_f64_kernel(double *__restrict__ dst, const double *__restrict__ src, size_t n)
+{
+    for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * blockDim.x)
+        dst[e] = src[e];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1290,7 +1365,9 @@ static hipError_t chol_pivoted(const SvdDevView &v, hipStream_t stream)
 // After nblk - 1 moves every block is home again.  Each sweep ends with device-wide counts of its
 // rotations and of rotations with a cosine >= 1e-8; the iteration stops after a sweep without the
 // latter (convergence is quadratic by then).  Every wait is bounded: an expired wait sets the error
-// word and the workgroups leave, the result is then rejected.
+// word and the workgroups leave, the result is then rejected.  When the stream's CUs cannot hold P
+// workgroups, G < P workgroups take P / G positions each per round through memory, with a device-wide
+// barrier between rounds (same arithmetic per meeting, so the same result bit for bit).
 // ---------------------------------------------------------------------------------------------
 struct GridJacobiArgs {
     double *X;       // np x np factor, column-major, rotated in place
@@ -1299,6 +1376,7 @@ struct GridJacobiArgs {
     uint32_t *ctl;   // kGridFlags round flags, then the counters of GridCtl (zeroed before the launch)
     int32_t *info;   // [0] sweeps, [1] error flags (1 wait expired, 2 not converged)
     int np;
+    int P;           // block pairs (np / (2 BW)); the grid has P workgroups or fewer
 };
 
 __device__ __forceinline__ bool spin_until(const uint32_t *word, uint32_t target, uint32_t *err)
@@ -1316,8 +1394,8 @@ __device__ __forceinline__ bool spin_until(const uint32_t *word, uint32_t target
 }
 
 // One sub-round: BW disjoint pairs (WjPair<BW, CROSS, RI, j>) of the workgroup's 2 BW columns.
-template <int R, int BW, int CROSS, int RI>
-__device__ __forceinline__ void gj_round(double (&x)[R][2 * BW], double *nrm_w, double (*part)[4][8], int &ph,
+template <int R, int BW, int NW, int CROSS, int RI>
+__device__ __forceinline__ void gj_round(double (&x)[R][2 * BW], double *nrm_w, double (*part)[NW][8], int &ph,
                                          int lane, int wv, uint32_t &nrot, bool &big, double tol2)
 {
     constexpr int P8 = BW <= 2 ? 2 : (BW <= 4 ? 4 : 8);
@@ -1338,7 +1416,9 @@ __device__ __forceinline__ void gj_round(double (&x)[R][2 * BW], double *nrm_w, 
     if (lane < BW) part[ph][wv][lane] = gw;
     __syncthreads();
     const int ls = lane & 7;
-    const double gj = ((part[ph][0][ls] + part[ph][1][ls]) + part[ph][2][ls]) + part[ph][3][ls];
+    double gj = part[ph][0][ls];
+#pragma unroll
+    for (int w2 = 1; w2 < NW; ++w2) gj += part[ph][w2][ls];
     ph ^= 1;
     double c = 1.0, sn = 0.0;
     bool act = false;
@@ -1382,14 +1462,15 @@ __device__ __forceinline__ void gj_round(double (&x)[R][2 * BW], double *nrm_w, 
     });
 }
 
-template <int R, int BW>
-__global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
+template <int R, int BW, int NT>
+__global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
 {
-    __shared__ double part[2][4][8];
-    __shared__ double nrm_s[4][2 * BW];
+    constexpr int NW = NT / 64;
+    __shared__ double part[2][NW][8];
+    __shared__ double nrm_s[NW][2 * BW];
     __shared__ uint32_t stop_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w = blockIdx.x, P = gridDim.x, nblk = 2 * P, m1 = nblk - 1, np = J.np;
+    const int w = blockIdx.x, G = gridDim.x, P = J.P, nblk = 2 * P, m1 = nblk - 1, np = J.np;
     uint32_t *flag = J.ctl;
     uint32_t *rot = J.ctl + kGridFlags;
     uint32_t *bigc = rot + kMaxSweeps;
@@ -1405,7 +1486,7 @@ __global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
         for (int c = 0; c < BW; ++c)
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const int r = tid + 256 * i;
+                const int r = tid + NT * i;
                 x[i][off + c] = r < np ? src[static_cast<size_t>(c) * np + r] : 0.0;
             }
         if (lane < BW) nrm_w[off + lane] = J.nrm[blk * BW + lane];
@@ -1416,7 +1497,7 @@ __global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
         for (int c = 0; c < BW; ++c)
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const int r = tid + 256 * i;
+                const int r = tid + NT * i;
                 if (r < np) dst[static_cast<size_t>(c) * np + r] = x[i][off + c];
             }
         if (with_norms && wv == 0 && lane < BW) J.nrm[blk * BW + lane] = nrm_w[off + lane];
@@ -1431,28 +1512,104 @@ __global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
             wave_totals<1>(acc);
             if (lane == 0) part[0][wv][c & 7] = acc[0];
             __syncthreads();
-            if (lane == 0) nrm_w[c] = ((part[0][0][c & 7] + part[0][1][c & 7]) + part[0][2][c & 7]) + part[0][3][c & 7];
+            if (lane == 0) {
+                double t = part[0][0][c & 7];
+#pragma unroll
+                for (int w2 = 1; w2 < NW; ++w2) t += part[0][w2][c & 7];
+                nrm_w[c] = t;
+            }
             __syncthreads();
         });
     };
-    load(w, 0);
-    load(nblk - 1 - w, BW);
     const double tol = static_cast<double>(np) * 0x1.0p-52;
     const double tol2 = tol * tol;
     uint32_t gen = 0, rho = 0;
     int ph = 0, sweep = 0;
     bool failed = false;
+    auto intra = [&](uint32_t &nrot, bool &big) {
+        static_for<0, BW - 1>([&](auto ri) {
+            gj_round<R, BW, NW, 0, decltype(ri)::value>(x, nrm_w, part, ph, lane, wv, nrot, big, tol2);
+        });
+    };
+    auto meet = [&](uint32_t &nrot, bool &big) {
+        static_for<0, BW>([&](auto ri) {
+            gj_round<R, BW, NW, 1, decltype(ri)::value>(x, nrm_w, part, ph, lane, wv, nrot, big, tol2);
+        });
+    };
+    // sweep totals: a device-wide barrier, then every workgroup reads the same counts
+    auto sweep_done = [&](uint32_t nrot, bool big) {
+        if (tid == 0) {
+            if (nrot) atomicAdd(&rot[sweep], nrot);
+            if (big) atomicAdd(&bigc[sweep], 1u);
+        }
+        grid_barrier(bar, err, static_cast<uint32_t>(G), gen);
+        const uint32_t nr = __hip_atomic_load(&rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t nb = __hip_atomic_load(&bigc[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        failed = __hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        return nr == 0u || nb == 0u;
+    };
+    if (G < P) {
+        // Fewer workgroups than block pairs (the stream's CUs cannot hold P): workgroup w takes the
+        // positions w, w + G, ... of every round, loading both blocks from their home columns and
+        // storing them back, with a device-wide barrier between rounds.  Each meeting runs the
+        // same code on the same data as in the resident mode below, so the result is the same bit
+        // for bit whatever the number of workgroups.
+        for (; sweep < kMaxSweeps && !failed; ++sweep) {
+            uint32_t nrot = 0;
+            bool big = false;
+            for (int t = 0; t < m1 && !failed; ++t) {
+                for (int pos = w; pos < P; pos += G) {
+                    load(top_of(t, pos), 0);
+                    load(bot_of(t, pos), BW);
+                    __syncthreads();
+                    if (t == 0) {  // home blocks: fresh norms, the pairs inside each block
+                        norms();
+                        intra(nrot, big);
+                    }
+                    meet(nrot, big);
+                    store(top_of(t, pos), 0, true);
+                    store(bot_of(t, pos), BW, true);
+                    __syncthreads();
+                }
+                if (t + 1 < m1) {
+                    grid_barrier(bar, err, static_cast<uint32_t>(G), gen);
+                    failed = __hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+                }
+            }
+            if (failed) break;
+            if (sweep_done(nrot, big)) {
+                ++sweep;
+                break;
+            }
+        }
+        for (int pos = w; pos < P; pos += G) {
+            load(pos, 0);
+            load(nblk - 1 - pos, BW);
+            __syncthreads();
+            norms();
+            if (wv == 0 && lane < 2 * BW) {
+                const int col = lane < BW ? pos * BW + lane : (nblk - 1 - pos) * BW + lane - BW;
+                J.zs[col] = __builtin_sqrt(nrm_w[lane]);
+            }
+            __syncthreads();
+        }
+        if (w == 0 && tid == 0) {
+            J.info[0] = sweep;
+            J.info[1] = (failed || __hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u ? 1 : 0) |
+                        (sweep >= kMaxSweeps ? 2 : 0);
+        }
+        return;
+    }
+    load(w, 0);
+    load(nblk - 1 - w, BW);
+    __syncthreads();
     for (; sweep < kMaxSweeps && !failed; ++sweep) {
         norms();
         uint32_t nrot = 0;
         bool big = false;
-        static_for<0, BW - 1>([&](auto ri) {
-            gj_round<R, BW, 0, decltype(ri)::value>(x, nrm_w, part, ph, lane, wv, nrot, big, tol2);
-        });
+        intra(nrot, big);
         for (int t = 0; t < m1 && !failed; ++t) {
-            static_for<0, BW>([&](auto ri) {
-                gj_round<R, BW, 1, decltype(ri)::value>(x, nrm_w, part, ph, lane, wv, nrot, big, tol2);
-            });
+            meet(nrot, big);
             if (P == 1) continue;  // two blocks: nothing moves
             // outgoing: the top to w - 1 (w >= 1), the bottom to w + 1 (w <= P - 2)
             if (w >= 1) store(top_of(t, w), 0, true);
@@ -1488,15 +1645,7 @@ __global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
             __syncthreads();
         }
         if (failed) break;
-        if (tid == 0) {
-            if (nrot) atomicAdd(&rot[sweep], nrot);
-            if (big) atomicAdd(&bigc[sweep], 1u);
-        }
-        grid_barrier(bar, err, static_cast<uint32_t>(P), gen);
-        const uint32_t nr = __hip_atomic_load(&rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t nb = __hip_atomic_load(&bigc[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        failed = __hip_atomic_load(err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-        if (nr == 0u || nb == 0u) {
+        if (sweep_done(nrot, big)) {
             ++sweep;
             break;
         }
@@ -1518,22 +1667,27 @@ __global__ __launch_bounds__(256) void gram_jacobi_grid_kernel(GridJacobiArgs J)
 
 constexpr int kGridBW = 8;
 
-template <int R> static const void *grid_jacobi_fn()
+// The device-wide Jacobi: 256 threads per workgroup (one wave per SIMD) and R = np / 256 rounded up
+// rows per thread.  (512 or 1024 threads with fewer rows each measured slower: more waves meet at
+// every sub-round's barrier, and the larger variants spill.)
+constexpr int kGridThreads = 256;
+
+template <int R> static const void *grid_fn()
 {
-    return reinterpret_cast<const void *>(&gram_jacobi_grid_kernel<R, kGridBW>);
+    return reinterpret_cast<const void *>(&gram_jacobi_grid_kernel<R, kGridBW, kGridThreads>);
 }
 
-static const void *grid_jacobi_ptr(int np)
+static const void *grid_jacobi_fn(int np)
 {
-    switch ((np + 255) / 256) {
-    case 1: return grid_jacobi_fn<1>();
-    case 2: return grid_jacobi_fn<2>();
-    case 3: return grid_jacobi_fn<3>();
-    case 4: return grid_jacobi_fn<4>();
-    case 5: return grid_jacobi_fn<5>();
-    case 6: return grid_jacobi_fn<6>();
-    case 7: return grid_jacobi_fn<7>();
-    case 8: return grid_jacobi_fn<8>();
+    switch ((np + kGridThreads - 1) / kGridThreads) {
+    case 1: return grid_fn<1>();
+    case 2: return grid_fn<2>();
+    case 3: return grid_fn<3>();
+    case 4: return grid_fn<4>();
+    case 5: return grid_fn<5>();
+    case 6: return grid_fn<6>();
+    case 7: return grid_fn<7>();
+    case 8: return grid_fn<8>();
     }
     return nullptr;
 }
@@ -1955,12 +2109,14 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     const bool grid = v.np > kGramMaxCols;
     // the device-wide Jacobi needs all of its P = np / 16 workgroups resident on the stream's CUs
     bool gram = v.np > 0;
+    int grid_wgs = 0;  // workgroups of the device-wide Jacobi: all P block pairs resident, or fewer
     if (grid) {
         int per_cu = 0;
-        const void *fn = grid_jacobi_ptr(v.np);
-        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess ||
-            per_cu * n_cu < v.np / (2 * kGridBW))
+        const void *fn = grid_jacobi_fn(v.np);
+        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kGridThreads, 0) != hipSuccess ||
+            per_cu < 1)
             gram = false;
+        grid_wgs = std::min(v.np / (2 * kGridBW), per_cu * std::max(n_cu, 1));
     }
     if (gram) {
         const int nt = v.np / 16;
@@ -1968,10 +2124,9 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
         if (grid) {
             if ((e = chol_pivoted(v, stream)) != hipSuccess) return e;
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            GridJacobiArgs J{v.L, v.zs, v.gnrm, v.gctl, v.info + 2, v.np};
+            GridJacobiArgs J{v.L, v.zs, v.gnrm, v.gctl, v.info + 2, v.np, v.np / (2 * kGridBW)};
             void *args[] = {&J};
-            e = hipLaunchCooperativeKernel(grid_jacobi_ptr(v.np), dim3(v.np / (2 * kGridBW)), dim3(256), args, 0,
-                                           stream);
+            e = hipLaunchCooperativeKernel(grid_jacobi_fn(v.np), dim3(grid_wgs), dim3(kGridThreads), args, 0, stream);
             if (e != hipSuccess) return e;
         } else {
             if (v.np == 64) gram_chol_kernel<1><<<1, 1024, 0, stream>>>(v);
@@ -1988,7 +2143,26 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
         const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
         gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
         const int tk = (v.k + 15) / 16;
-        gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v);
+        if (grid) {  // first-order correction of the eigenvector side, then the other side again
+            double *vs = v.trans ? v.U : v.V;
+            gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v, v.G);
+            const size_t kk = static_cast<size_t>(v.k) * v.k, nk = static_cast<size_t>(v.cols) * v.k;
+            gram_fix_kernel<<<static_cast<int>(std::min<size_t>(4096, (kk + 255) / 256)), 256, 0, stream>>>(v, v.G, v.L);
+            const long cl = v.cols, kl = v.k;
+            if ((e = gemm({vs, 1, cl, v.L, 1, kl, nullptr, v.G, cl, v.cols, v.k, v.k, nullptr, 0, 0}, stream)) != hipSuccess)
+                return e;
+            copy_f64_kernel<<<static_cast<int>(std::min<size_t>(4096, (nk + 255) / 256)), 256, 0, stream>>>(vs, v.G, nk);
+            gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
+        }
+        gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v, nullptr);
+        {  // residual certificate: C = A^T Ys (cols x k) in G
+            const double *ys = v.trans ? v.V : v.U;
+            const long rl = v.rows, cl2 = v.cols;
+            if ((e = gemm({v.A, rl, 1, ys, 1, rl, nullptr, v.G, cl2, v.cols, v.k, v.rows, nullptr, 0, 0}, stream)) !=
+                hipSuccess)
+                return e;
+            gram_resid_kernel<<<std::min(v.k, 2048), 256, 0, stream>>>(v, v.G);
+        }
         gram_accept_kernel<<<1, 64, 0, stream>>>(v);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         skip = v.ctrl + kCtrlGramOk;

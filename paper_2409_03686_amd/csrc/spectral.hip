@@ -119,7 +119,7 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
         carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
         carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
         carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(grid ? npn : 0, 8),
-        carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn : 0, 4), carve_size(1, 8),
+        carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn : 0, 4), carve_size(2, 8),
         carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * big, 8), carve_size(size_t(v.rows) * big, 8),
         carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(big, 8),
         carve_size(std::max<size_t>(tkn, 1), 4)};
@@ -156,7 +156,7 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     v.gnrm = grid ? carve<double>(cur, npn) : nullptr;
     v.gctl = grid ? carve<uint32_t>(cur, kGridCtlWords) : nullptr;
     v.gpiv = grid ? carve<int32_t>(cur, 3 * npn) : nullptr;
-    v.crit = carve<unsigned long long>(cur, 1);
+    v.crit = carve<unsigned long long>(cur, 2);
     const size_t tkn = static_cast<size_t>(v.tk);
     const size_t big = v.tk && v.cols > v.tk ? tkn : 0;
     v.Om = carve<double>(cur, size_t(v.cols) * big);
@@ -282,23 +282,22 @@ extern "C" wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t 
 }
 
 extern "C" wos_status wos_svd_gram_check(const wos_svd_t *h, int32_t *gram_sweeps, int32_t *gram_error_flag,
-                                         double *check, void *stream)
+                                         double *check, double *residual, void *stream)
 {
     if (!h) return set_error(WOS_EINVAL, "handle NULL");
     int32_t info[kInfoWords] = {};
-    unsigned long long crit = 0ull;
+    unsigned long long crit[2] = {0ull, 0ull};
     hipError_t e = hipMemcpyAsync(info, h->v.info, sizeof info, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&crit, h->v.crit, sizeof crit, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
+        e = hipMemcpyAsync(crit, h->v.crit, sizeof crit, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return set_error(WOS_EDEVICE, "reading SVD diagnostics failed: %s", hipGetErrorString(e));
     if (gram_sweeps) *gram_sweeps = info[2];
     if (gram_error_flag) *gram_error_flag = info[3];
-    if (check) {
-        double c;
-        std::memcpy(&c, &crit, sizeof c);
-        *check = c;
-    }
+    double c[2];
+    std::memcpy(c, crit, sizeof c);
+    if (check) *check = c[0];
+    if (residual) *residual = c[1];
     return WOS_OK;
 }
 

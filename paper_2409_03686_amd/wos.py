@@ -107,7 +107,8 @@ _SIGS = {
     "wos_svd_factors": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "wos_svd_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _VP]),
-    "wos_svd_gram_check": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double), _VP]),
+    "wos_svd_gram_check": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), _VP]),
     "wos_reconstruct": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP, _VP,
                                   _VP, _VP]),
     "wos_reconstruct_sweep": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -310,10 +311,11 @@ def wos_svd_info(h, stream=None):
 
 
 def wos_svd_gram_check(h, stream=None):
-    """(Gram-path Jacobi sweeps, its error flags, its acceptance statistic) of the last wos_svd."""
-    sw, er, ck = C.c_int32(), C.c_int32(), C.c_double()
-    _check(lib().wos_svd_gram_check(h, C.byref(sw), C.byref(er), C.byref(ck), _stream(stream)))
-    return sw.value, er.value, ck.value
+    """(Gram-path Jacobi sweeps, its error flags, orthogonality statistic, residual certificate) of the
+    last wos_svd."""
+    sw, er, ck, rs = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+    _check(lib().wos_svd_gram_check(h, C.byref(sw), C.byref(er), C.byref(ck), C.byref(rs), _stream(stream)))
+    return sw.value, er.value, ck.value, rs.value
 
 
 def wos_reconstruct(ctx, h, counts_dev, n_walks, uD_dev, u0_dev, reg: WosRegParams, u1_dev, pred_dev=None,

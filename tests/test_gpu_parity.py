@@ -292,14 +292,59 @@ def test_paper_perforated_examples(wos, ctx, example):
 
 
 def test_fp32_cube_vs_fp64(wos, ctx):
+    """FP32 geometry against the FP64 path on the cube, patch by patch (every one of the 3456 cells of
+    1024 points)."""
     inst = wi.cfg3_cube(n_walks=20_000, precision=wi.FP32_GEOM_FP64_EXIT, stride=4)
     c32, st, _ = _gpu(wos, ctx, inst)
     assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0
     c64, _, _ = _gpu(wos, ctx, inst, precision=wi.FP64)
-    merge = lambda c: c.reshape(c.shape[0], 6, 6, 4, 6, 4).sum((3, 5)).reshape(c.shape[0], -1)
-    rep = statutil.two_sample(merge(c32), inst.n_walks, merge(c64), inst.n_walks)
-    print("FP32 vs FP64 cube (4x4 merged patches)", rep)
+    rep = statutil.two_sample(c32, inst.n_walks, c64, inst.n_walks)
+    print("FP32 vs FP64 cube, per patch", rep)
     assert rep["ok"]
+
+
+def test_cube_full_size_rows_svd_and_reconstruction(wos, ctx):
+    """The cube at full size (4096 points x 1e5 walks, FP32 geometry, exact mapped radius): every 16th
+    row against an independent oracle run patch by patch; then the FP64 SVD of the 4096 x 1728
+    Gamma_1 block against LAPACK (R-13: |s - s_ref| <= 1e-10 s_1, per-value 1e-10 relative above
+    5e-3 s_1, orthogonality, reconstruction of B), taken by the device-wide Gram path, and the
+    reconstructions against the oracle's on the same counts."""
+    inst = wi.cfg3_cube(precision=wi.FP32_GEOM_FP64_EXIT)
+    c, st, _ = _gpu(wos, ctx, inst)
+    assert np.all(c.sum(1) == inst.n_walks) and st["escapes"] == 0 and st["cap_hits"] == 0
+    rows = np.arange(0, c.shape[0], 16)
+    cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed + 1,
+                                radius_mode=inst.radius_mode, walk_end=inst.n_walks, point_ids=rows)
+    rep = statutil.two_sample(c[rows], inst.n_walks, cr, inst.n_walks)
+    print(f"cube FP32, {len(rows)} rows x 3456 patches vs independent oracle rows", rep)
+    assert rep["ok"]
+    g = inst.geom
+    sigma = ow.element_measures(g)
+    g1 = g.gamma1_mask.astype(bool)
+    h, ct, U, s, V, sweeps, err = _svd_case(wos, ctx, c, inst.n_walks, g.gamma1_mask, sigma)
+    assert err == 0
+    assert wos.wos_svd_info(h)[2] == wos.WOS_SVD_GRAM
+    gs, ge, check, resid = wos.wos_svd_gram_check(h)
+    print(f"cube SVD: Gram path {gs} sweeps, error flags {ge}, check {check:.2e}, residual {resid / s[0]:.2e} s_1")
+    assert ge == 0 and resid <= 2.0 ** -35 * s[0]
+    out = ol.assemble(c, inst.n_walks, g.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+    _check_svd(out["B"], U, s, V, f"cube 4096x1728 ({sweeps} sweeps)")
+    Ur, sr, Vtr = ol.svd(out["B"])
+    n1, m = int(g1.sum()), c.shape[0]
+    for reg, kind in [(wos.reg_params(wos.WOS_TSVD_RANK, rank=20), ol.TSVD_RANK),
+                      (wos.reg_params(wos.WOS_TIKHONOV, alpha=1e-3 * sr[0]), ol.TIKHONOV)]:
+        u1, pred, r_used, a_used = _recon(wos, ctx, h, ct, inst.n_walks, inst.uD, inst.u0, reg, n1, m)
+        u1r, rr, ar = ol.reconstruct(Ur, sr, Vtr, sigma[g1], out["q"], kind=kind, rank=reg.rank,
+                                     alpha=reg.alpha, delta=reg.noise_delta, tau=reg.tau)
+        if kind == ol.TSVD_RANK:
+            assert r_used == rr
+            assert -np.diff(sr)[rr - 1] > 1e-9 * sr[0]  # the truncated subspace is well defined
+        kappa = sr[0] / (sr[rr - 1] if kind != ol.TIKHONOV else ar)
+        tol = max(1e-10, 2.0 ** -36 * np.linalg.norm(out["B"]) / sr[0] * kappa)
+        rel = np.abs(u1 - u1r).max() / np.abs(u1r).max()
+        print(f"cube reconstruction kind {kind}: rank {r_used} rel err vs oracle {rel:.2e} (tolerance {tol:.1e})")
+        assert rel <= tol
+    wos.wos_svd_destroy(ctx, h)
 
 
 # -------------------------------------------------------------------------- determinism
@@ -538,16 +583,21 @@ def test_svd_wide_tall_odd(wos, ctx, shape):
     wos.wos_svd_destroy(ctx, h)
 
 
-@pytest.mark.parametrize("case", ["tall_gram", "wide_gram", "rank_deficient", "ill_conditioned", "too_wide_for_gram"])
+@pytest.mark.parametrize("case", ["tall_gram", "wide_gram", "rank_deficient", "ill_conditioned", "grid_gram",
+                                  "grid_gram_wide", "too_wide_for_gram"])
 def test_svd_method_selection(wos, ctx, case):
-    """The Gram path (Cholesky-type factor of A^T A, Jacobi on it) is kept only when its left vectors
-    pass the orthogonality check and s_min >= 1e-3 s_1; otherwise, or with more than 192 columns,
-    the Hestenes path on A runs.  Both must match LAPACK."""
+    """The Gram path (Cholesky-type factor of A^T A, Jacobi on it; one workgroup up to 192 columns,
+    the device-wide kernels up to 2048) is kept only when its left vectors pass the orthogonality
+    check, every singular value is positive and the residual certificate bounds their errors by
+    2^-35 s_1; otherwise, or with more than 2048 columns, the Hestenes path on A runs.  Both must
+    match LAPACK."""
     rng = np.random.default_rng(7)
     m, M, expect = {"tall_gram": (300, 150, wos.WOS_SVD_GRAM), "wide_gram": (90, 160, wos.WOS_SVD_GRAM),
                     "rank_deficient": (200, 120, wos.WOS_SVD_HESTENES),
                     "ill_conditioned": (256, 96, wos.WOS_SVD_HESTENES),
-                    "too_wide_for_gram": (400, 250, wos.WOS_SVD_HESTENES)}[case]
+                    "grid_gram": (400, 250, wos.WOS_SVD_GRAM),
+                    "grid_gram_wide": (300, 1100, wos.WOS_SVD_GRAM),
+                    "too_wide_for_gram": (2100, 2060, wos.WOS_SVD_HESTENES)}[case]
     counts = rng.integers(20, 60, size=(m, M)).astype(np.uint32)
     sigma = rng.uniform(0.5, 2.0, M)
     if case == "rank_deficient":
@@ -993,8 +1043,39 @@ def test_serving_truncated_svd_rejects_bad_mode(wos, ctx):
     assert out[0].status == wos.WOS_EINVAL
 
 
+@pytest.mark.parametrize("shape,spectral_cus", [((600, 700, 300), 8), ((1400, 1500, 1100), 8)])
+def test_grid_jacobi_same_bits_on_few_cus(wos, ctx, shape, spectral_cus):
+    """The device-wide Jacobi on the whole device (all workgroups resident) and on an 8-CU partition
+    (300 columns: still resident; 1100 columns: 72 block pairs on 8 workgroups, several pairs per
+    workgroup and round through memory) gives the same singular values and vectors bit for bit.
+    (A CU mask must reach every XCD, so 8 is the smallest partition.)"""
+    m, M, n1 = shape
+    rng = np.random.default_rng(m)
+    p = rng.dirichlet(np.ones(M), size=m)
+    ct = np.stack([rng.multinomial(4000, pi) for pi in p]).astype(np.int32)
+    mask = np.zeros(M, np.uint8)
+    mask[rng.choice(M, n1, replace=False)] = 1
+    sigma = np.full(M, 1.0 / M)
+    h0, ct_d, U0, s0, V0, sweeps, err = _svd_case(wos, ctx, ct, 4000, mask, sigma)
+    assert err == 0 and wos.wos_svd_info(h0)[2] == wos.WOS_SVD_GRAM
+    walk_s, spec_s = wos.wos_streams_create(ctx, spectral_cus)
+    try:
+        h = wos.wos_svd_create(ctx, m, M, mask, sigma)
+        wos.wos_svd(ctx, h, ct_d, 4000, spec_s)
+        torch.cuda.synchronize()
+        assert wos.wos_svd_info(h)[2] == wos.WOS_SVD_GRAM
+        U, s, V = wos.svd_factors_numpy(h)
+        print(f"grid Jacobi {m}x{n1} on {spectral_cus} CUs: {wos.wos_svd_info(h)[0]} sweeps (whole device {sweeps})")
+        assert np.array_equal(s, s0) and np.array_equal(U, U0) and np.array_equal(V, V0)
+        wos.wos_svd_destroy(ctx, h)
+        wos.wos_svd_destroy(ctx, h0)
+    finally:
+        torch.cuda.synchronize()
+        wos.wos_streams_destroy(ctx, walk_s, spec_s)
+
+
 def test_partitioned_streams_give_the_same_results(wos, ctx):
-    """Walks on the walk stream of a CU partition and SVDs (a Gram-path size and a Hestenes-path
+    """Walks on the walk stream of a CU partition and SVDs (a one-workgroup and a device-wide Gram-path
     size, whose cooperative grid is sized for the partition's CUs) on the spectral stream give the
     same counts and factors as on an unrestricted stream; both streams run at once; bad partition
     sizes are rejected."""
@@ -1010,7 +1091,7 @@ def test_partitioned_streams_give_the_same_results(wos, ctx):
         cnt = torch.zeros((256, inst.geom.n_elem), dtype=torch.int32, device="cuda")
         rng = np.random.default_rng(59)
         cases = []
-        for m, M, n1 in ((300, 200, 160), (600, 700, 300)):  # Gram path (160 cols), Hestenes path (300)
+        for m, M, n1 in ((300, 200, 160), (600, 700, 300)):  # one-workgroup and device-wide Gram path
             p = rng.dirichlet(np.ones(M), size=m)
             ct = np.stack([rng.multinomial(2000, pi) for pi in p]).astype(np.int32)
             mask = np.zeros(M, np.uint8)
