@@ -285,6 +285,11 @@ wos_status wos_svd_info(const wos_svd_t *h, int32_t *sweeps, int32_t *error_flag
  * Synchronises `stream`. */
 wos_status wos_svd_gram_check(const wos_svd_t *h, int32_t *gram_sweeps, int32_t *gram_error_flag,
                               double *check, double *residual, void *stream);
+/* Device time of the last wos_svd called outside stream capture (HIP events on its stream): the
+ * Gram path's Jacobi kernel (0 if it did not run) and the whole call, in milliseconds, and the
+ * plane rotations the device-wide Jacobi applied (0 for the one-workgroup Jacobi).  Waits for that
+ * call to finish.  WOS_EINVAL if no such call has run on the handle. */
+wos_status wos_svd_timing(const wos_svd_t *h, float *jacobi_ms, float *total_ms, uint64_t *rotations);
 
 /* ------------------------------------------------------------------------------------------- */
 /* Reconstruction (Algorithm Main)                                                               */

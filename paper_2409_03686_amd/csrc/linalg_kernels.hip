@@ -2097,8 +2097,12 @@ int svd_coop_grid(int rows, int colsp, int n_cu)
 // assemble -> [Gram path: G, factor, Jacobi on the factor, norms, V side, U side, check, accept]
 // -> Hestenes path on A (skipped when the Gram result was accepted) -> norms -> scatter.
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid, int n_cu,
-                      hipStream_t stream)
+                      hipStream_t stream, SvdEvents *ev)
 {
+    if (ev) {
+        ev->jac_recorded = false;
+        (void)hipEventRecord(ev->all0, stream);
+    }
     const size_t total = static_cast<size_t>(v.rows) * v.colsp;
     int g = static_cast<int>((total + 255) / 256);
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
@@ -2126,18 +2130,28 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
             if ((e = hipGetLastError()) != hipSuccess) return e;
             GridJacobiArgs J{v.L, v.zs, v.gnrm, v.gctl, v.info + 2, v.np, v.np / (2 * kGridBW)};
             void *args[] = {&J};
+            if (ev) (void)hipEventRecord(ev->jac0, stream);
             e = hipLaunchCooperativeKernel(grid_jacobi_fn(v.np), dim3(grid_wgs), dim3(kGridThreads), args, 0, stream);
             if (e != hipSuccess) return e;
+            if (ev) {
+                (void)hipEventRecord(ev->jac1, stream);
+                ev->jac_recorded = true;
+            }
         } else {
             if (v.np == 64) gram_chol_kernel<1><<<1, 1024, 0, stream>>>(v);
             else if (v.np == 128) gram_chol_kernel<2><<<1, 1024, 0, stream>>>(v);
             else gram_chol_kernel<3><<<1, 1024, 0, stream>>>(v);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             // the factor's Jacobi in one workgroup (zs = the rotated columns' norms)
+            if (ev) (void)hipEventRecord(ev->jac0, stream);
             if (v.np == 64) e = launch_gram_jacobi1<1>(v.L, v.zs, v.info + 2, stream);
             else if (v.np == 128) e = launch_gram_jacobi1<2>(v.L, v.zs, v.info + 2, stream);
             else e = launch_gram_jacobi1<3>(v.L, v.zs, v.info + 2, stream);
             if (e != hipSuccess) return e;
+            if (ev) {
+                (void)hipEventRecord(ev->jac1, stream);
+                ev->jac_recorded = true;
+            }
         }
         gram_vside_kernel<<<v.np, 64, 0, stream>>>(v);
         const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
@@ -2179,6 +2193,7 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     const int gc = v.cols < 1 ? 1 : (v.cols > 2048 ? 2048 : v.cols);
     colnorm_kernel<<<gc, 256, 0, stream>>>(v.A, v.rows, v.rows, v.cols, v.work, skip);
     scatter_kernel<<<gc, 256, 0, stream>>>(v, skip);
+    if (ev) (void)hipEventRecord(ev->all1, stream);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ struct wos_svd_t {
     size_t bytes = 0;
     int coop_grid = 1;
     bool nu_nonzero = true;  // every nu_i != 0: the sweep's predicted data divide by nu
+    SvdEvents ev{};          // recorded by wos_svd (eager calls) for wos_svd_timing
+    bool timed = false;      // a wos_svd has recorded them
 };
 
 namespace {
@@ -227,6 +229,13 @@ extern "C" wos_status wos_svd_create(wos_ctx *ctx, int32_t n_obs, int32_t n_elem
     }
     h->v = hs.v;
     h->coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, ctx->n_cu);
+    for (hipEvent_t *pe : {&h->ev.jac0, &h->ev.jac1, &h->ev.all0, &h->ev.all1}) {
+        if (hipEventCreate(pe) != hipSuccess) {
+            *pe = nullptr;
+            (void)wos_svd_destroy(ctx, h);
+            return set_error(WOS_EDEVICE, "hipEventCreate failed");
+        }
+    }
     for (double x : hs.nu) h->nu_nonzero = h->nu_nonzero && x != 0.0;
     *out = h;
     return WOS_OK;
@@ -236,6 +245,8 @@ extern "C" wos_status wos_svd_destroy(wos_ctx *ctx, wos_svd_t *h)
 {
     if (!ctx || !h) return set_error(WOS_EINVAL, "ctx or handle NULL");
     (void)hipDeviceSynchronize();
+    for (hipEvent_t e : {h->ev.jac0, h->ev.jac1, h->ev.all0, h->ev.all1})
+        if (e) (void)hipEventDestroy(e);
     ctx_free(ctx, h->mem, h->bytes);
     delete h;
     return WOS_OK;
@@ -249,8 +260,14 @@ extern "C" wos_status wos_svd(wos_ctx *ctx, wos_svd_t *h, const uint32_t *counts
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // cooperative grids sized for the CUs the stream may use (all, or its CU mask)
     const int coop_grid = svd_coop_grid(h->v.rows, h->v.colsp, stream_cus(ctx, static_cast<hipStream_t>(stream)));
+    // timing events only outside stream capture (a captured graph gets no event nodes from here)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(ctx, hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cap));
+    const bool timed = cap == hipStreamCaptureStatusNone && h->ev.all1;
     HIP_TRY(ctx, svd_launch(h->v, counts_dev, 1.0 / static_cast<double>(n_walks), coop_grid,
-                            stream_cus(ctx, static_cast<hipStream_t>(stream)), static_cast<hipStream_t>(stream)));
+                            stream_cus(ctx, static_cast<hipStream_t>(stream)), static_cast<hipStream_t>(stream),
+                            timed ? &h->ev : nullptr));
+    h->timed = timed;
     return WOS_OK;
 }
 
@@ -298,6 +315,28 @@ extern "C" wos_status wos_svd_gram_check(const wos_svd_t *h, int32_t *gram_sweep
     std::memcpy(c, crit, sizeof c);
     if (check) *check = c[0];
     if (residual) *residual = c[1];
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_svd_timing(const wos_svd_t *h, float *jacobi_ms, float *total_ms, uint64_t *rotations)
+{
+    if (!h) return set_error(WOS_EINVAL, "handle NULL");
+    if (!h->timed) return set_error(WOS_EINVAL, "no timed wos_svd on this handle yet");
+    if (hipEventSynchronize(h->ev.all1) != hipSuccess) return set_error(WOS_EDEVICE, "event synchronisation failed");
+    float jm = 0.0f, tm = 0.0f;
+    const bool jac = h->ev.jac_recorded && hipEventElapsedTime(&jm, h->ev.jac0, h->ev.jac1) == hipSuccess;
+    if (hipEventElapsedTime(&tm, h->ev.all0, h->ev.all1) != hipSuccess)
+        return set_error(WOS_EDEVICE, "reading SVD events failed");
+    uint64_t nrot = 0;
+    if (h->v.gctl) {
+        uint32_t r[kMaxSweeps];
+        if (hipMemcpy(r, h->v.gctl + kGridFlags, sizeof r, hipMemcpyDeviceToHost) != hipSuccess)
+            return set_error(WOS_EDEVICE, "reading rotation counts failed");
+        for (uint32_t x : r) nrot += x;
+    }
+    if (jacobi_ms) *jacobi_ms = jac ? jm : 0.0f;
+    if (total_ms) *total_ms = tm;
+    if (rotations) *rotations = nrot;
     return WOS_OK;
 }
 

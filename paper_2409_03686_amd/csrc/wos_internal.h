@@ -89,9 +89,14 @@ hipError_t launch_walks(int precision, int dim, int kind_sel, int mode, const De
                         uint64_t total_items, uint32_t *cursor, int hist_words, int seg_bytes, int block, int grid,
                         hipStream_t stream);
 
-// n_cu: CUs the stream may use (cooperative grids are sized for them)
+// Events recorded around the Gram path's Jacobi kernel and around the whole SVD (eager calls only).
+struct SvdEvents {
+    hipEvent_t jac0, jac1, all0, all1;
+    bool jac_recorded;  // set by svd_launch when the Jacobi ran between jac0 and jac1
+};
+// n_cu: CUs the stream may use (cooperative grids are sized for them); ev: null, or events to record
 hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, int coop_grid, int n_cu,
-                      hipStream_t stream);
+                      hipStream_t stream, SvdEvents *ev = nullptr);
 int svd_coop_grid(int rows, int colsp, int n_cu);
 int gram_order(int cols);  // np of the Gram path for this column count, 0 if it does not apply
 // truncated SVD of the assembled work matrix (serving): non-cooperative kernels only

@@ -109,6 +109,7 @@ _SIGS = {
     "wos_svd_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _VP]),
     "wos_svd_gram_check": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), _VP]),
+    "wos_svd_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_uint64)]),
     "wos_reconstruct": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP, _VP,
                                   _VP, _VP]),
     "wos_reconstruct_sweep": (C.c_int, [_VP, _VP, _VP, C.c_uint64, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -316,6 +317,13 @@ def wos_svd_gram_check(h, stream=None):
     sw, er, ck, rs = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
     _check(lib().wos_svd_gram_check(h, C.byref(sw), C.byref(er), C.byref(ck), C.byref(rs), _stream(stream)))
     return sw.value, er.value, ck.value, rs.value
+
+
+def wos_svd_timing(h):
+    """(Jacobi ms, whole SVD ms, plane rotations) of the last wos_svd outside stream capture."""
+    jm, tm, nr = C.c_float(), C.c_float(), C.c_uint64()
+    _check(lib().wos_svd_timing(h, C.byref(jm), C.byref(tm), C.byref(nr)))
+    return jm.value, tm.value, nr.value
 
 
 def wos_reconstruct(ctx, h, counts_dev, n_walks, uD_dev, u0_dev, reg: WosRegParams, u1_dev, pred_dev=None,

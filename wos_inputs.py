@@ -404,9 +404,10 @@ def cfg2_annulus(n_walks: int = 100_000, n_obs: int = 1024, precision: int = FP3
 
 
 def cfg3_cube(n_walks: int = 100_000, precision: int = FP32_GEOM_FP64_EXIT,
-              radius_mode: int = RADIUS_MAPPED_EXACT, stride: int = 1) -> Instance:
+              radius_mode: int = RADIUS_MAPPED_EXACT, stride: int = 1, eta: float = 0.01) -> Instance:
     """[0,1]^3, K = Q diag(1,3,10) Q^T (Q Haar-random, seed 1), 24x24 patches per face,
-    Gamma_0 = faces {x=0, y=0, z=0}; 4096 points on the 16^3 interior grid."""
+    Gamma_0 = faces {x=0, y=0, z=0}; 4096 points on the 16^3 interior grid.  Data: a random
+    K-harmonic polynomial of degree 3 (seed 3) with eta (1 %) Gaussian noise (seed 13)."""
     import scipy.stats as st
     n = 24
     g = Geometry(3, BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (n,))
@@ -423,8 +424,7 @@ def cfg3_cube(n_walks: int = 100_000, precision: int = FP32_GEOM_FP64_EXIT,
     ref = element_ref_points(g)
     rng = np.random.default_rng(3)
     u = random_harmonic_poly(3, K, 3, rng)
-    inst.uD = u(x)
-    inst.u0 = u(ref)[g.gamma1_mask == 0]
+    inst.uD, inst.u0, inst.noise_delta = add_noise(u(x), u(ref)[g.gamma1_mask == 0], eta, np.random.default_rng(13))
     inst.u_exact_g1 = u(ref)[g.gamma1_mask == 1]
     return inst
 
