@@ -196,6 +196,20 @@ wos_status wos_build_measure(wos_ctx *ctx, const wos_geometry *geom, const wos_w
                              const double *x_obs_dev, int32_t n_obs, uint32_t *counts_dev,
                              uint64_t *stats_dev, int32_t *trace_dev, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): wos_build_measure with the same arguments, results and errors, whose
+ * scratch (the instance descriptor with its geometry records, at most 64 KiB, and the work cursors,
+ * at most 2^18 + 2 words: 2^18 points in point mode) lives in a static device array of 1.06 MiB
+ * that each GPU holds until the process ends.  The call allocates no device or pinned memory: the
+ * descriptor reaches the array through the arguments of small kernels (so a captured graph holds
+ * the bytes), the cursors are cleared by a kernel.  Larger descriptors or cursor counts return
+ * WOS_EINVAL before anything is enqueued.  Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents: calls that overlap on one GPU (different streams, threads or contexts)
+ * race and must be serialised by the caller. */
+wos_status wos_build_measure_noalloc(wos_ctx *ctx, const wos_geometry *geom, const wos_walk_params *walk,
+                                     const double *x_obs_dev, int32_t n_obs, uint32_t *counts_dev,
+                                     uint64_t *stats_dev, int32_t *trace_dev, void *stream);
+
 /* One instance of a batched build. */
 typedef struct {
     wos_geometry geom;

@@ -78,6 +78,30 @@ void wos::ctx_free(wos_ctx *ctx, void *p, size_t bytes)
 // ---------------------------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------------------
+// Scratch of the allocation-free walk launch (wos_build_measure_noalloc): the instance descriptor
+// with its staged geometry records, then the launch's work cursors.  One copy per GPU, held until
+// the process ends; every call on a GPU shares it.  Host code uses the address that
+// hipGetSymbolAddress returns for the current device (kept in the context), never the name.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocDescBytes = 64 * 1024;               // descriptor and geometry records
+constexpr size_t kNoAllocCursorWords = (size_t(1) << 18) + 2;  // point-mode cursors: 2^18 points
+constexpr size_t kNoAllocBytes = kNoAllocDescBytes + 4 * kNoAllocCursorWords;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace {
+// One piece of a descriptor, passed by value (so a captured graph holds the bytes themselves).
+struct StageChunk {
+    uint64_t w[256];  // 2 KiB
+    uint32_t off, nwords;
+};
+__global__ void stage_chunk_kernel(uint8_t *dst, StageChunk c)
+{
+    uint64_t *d = reinterpret_cast<uint64_t *>(dst + c.off);
+    for (uint32_t i = threadIdx.x; i < c.nwords; i += blockDim.x) d[i] = c.w[i];
+}
+}  // namespace
+
 extern "C" wos_status wos_create(wos_ctx **out, int device, size_t hbm_budget_bytes)
 {
     if (!out) return set_error(WOS_EINVAL, "out is NULL");
@@ -94,6 +118,10 @@ extern "C" wos_status wos_create(wos_ctx **out, int device, size_t hbm_budget_by
         return set_error(WOS_EDEVICE, "cannot open HIP device %d", device);
     }
     ctx->n_cu = ctx->props.multiProcessorCount;
+    // this device's copy of the allocation-free scratch (the device is current)
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess) ctx->noalloc_scratch = static_cast<uint8_t *>(sp);
+    else (void)hipGetLastError();
     for (auto &slot : ctx->ring) {
         if (hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess) {
             delete ctx;
@@ -1124,6 +1152,60 @@ extern "C" wos_status wos_build_measure(wos_ctx *ctx, const wos_geometry *geom, 
     J.stats_dev = stats_dev;
     J.trace_dev = trace_dev;
     return wos_build_measure_batch(ctx, &J, 1, stream);
+}
+
+extern "C" wos_status wos_build_measure_noalloc(wos_ctx *ctx, const wos_geometry *geom, const wos_walk_params *walk,
+                                                const double *x_obs_dev, int32_t n_obs, uint32_t *counts_dev,
+                                                uint64_t *stats_dev, int32_t *trace_dev, void *stream)
+{
+    if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
+    if (!geom || !walk) return set_error(WOS_EINVAL, "geometry or walk params NULL");
+    if (ctx->poisoned) return set_error(WOS_EDEVICE, "context is unusable after a device error");
+    if (!ctx->noalloc_scratch) return set_error(WOS_EDEVICE, "the allocation-free scratch has no device address");
+    wos_measure_job J;
+    J.geom = *geom;
+    J.walk = *walk;
+    J.x_obs_dev = x_obs_dev;
+    J.n_obs = n_obs;
+    J.counts_dev = counts_dev;
+    J.stats_dev = stats_dev;
+    J.trace_dev = trace_dev;
+    std::lock_guard<std::recursive_mutex> lk(ctx->launch_mu);
+    std::vector<std::vector<int>> groups;
+    wos_status st = group_jobs(&J, 1, groups);
+    if (st != WOS_OK || groups.empty()) return st;  // invalid, or nothing to do
+    std::vector<uint8_t> buf;
+    GroupLaunch gl;
+    st = prepare_group(ctx, &J, groups[0], nullptr, buf, gl);
+    if (st != WOS_OK) return st;
+    const size_t desc = (buf.size() + 15) & ~size_t(15);
+    const size_t words = walk_cursor_words(gl.mode, gl.items);
+    if (desc > kNoAllocDescBytes)
+        return set_error(WOS_EINVAL, "descriptor of %zu bytes exceeds the allocation-free scratch (%zu)", desc,
+                         kNoAllocDescBytes);
+    if (words > kNoAllocCursorWords)
+        return set_error(WOS_EINVAL, "%zu work cursors exceed the allocation-free scratch (%zu)", words,
+                         kNoAllocCursorWords);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    uint8_t *dev = ctx->noalloc_scratch;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    patch_segs(buf, gl.n_inst, reinterpret_cast<uintptr_t>(dev));
+    buf.resize(desc, 0);
+    for (size_t off = 0; off < desc; off += sizeof(StageChunk::w)) {
+        StageChunk c{};
+        const size_t n = std::min(sizeof(c.w), desc - off);
+        std::memcpy(c.w, buf.data() + off, n);
+        c.off = static_cast<uint32_t>(off);
+        c.nwords = static_cast<uint32_t>(n / 8);
+        stage_chunk_kernel<<<1, 256, 0, s>>>(dev, c);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    uint64_t grid = static_cast<uint64_t>(gl.per_cu) * stream_cus(ctx, s);
+    if (gl.mode != 2) grid = std::min<uint64_t>(grid, std::max<uint64_t>(gl.items, 1));
+    HIP_TRY(ctx, launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.mode, reinterpret_cast<const DevInst *>(dev), gl.n_inst,
+                              gl.items, reinterpret_cast<uint32_t *>(dev + kNoAllocDescBytes), gl.hist_words,
+                              gl.seg_bytes, gl.block, static_cast<int>(grid), s));
+    return WOS_OK;
 }
 
 extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uint64_t sample_walks, wos_tuning *best,

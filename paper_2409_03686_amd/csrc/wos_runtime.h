@@ -35,6 +35,7 @@ struct wos_ctx {
     std::recursive_mutex launch_mu; // staging ring and launches
     std::map<int, wos_tuning> tuning;
     LiveServer *live = nullptr;     // live serving thread (wos_serve_start), or none
+    uint8_t *noalloc_scratch = nullptr;  // this device's copy of the allocation-free scratch array
 };
 
 namespace wos {

@@ -97,6 +97,8 @@ _SIGS = {
     "wos_element_measures": (C.c_int, [C.POINTER(WosGeometry), C.POINTER(C.c_double)]),
     "wos_build_measure": (C.c_int, [_VP, C.POINTER(WosGeometry), C.POINTER(WosWalkParams), _VP, C.c_int32,
                                     _VP, _VP, _VP, _VP]),
+    "wos_build_measure_noalloc": (C.c_int, [_VP, C.POINTER(WosGeometry), C.POINTER(WosWalkParams), _VP, C.c_int32,
+                                            _VP, _VP, _VP, _VP]),
     "wos_build_measure_batch": (C.c_int, [_VP, C.POINTER(WosMeasureJob), C.c_int32, _VP]),
     "wos_set_tuning": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.POINTER(WosTuning)]),
     "wos_autotune": (C.c_int, [_VP, C.POINTER(WosMeasureJob), C.c_uint64, C.POINTER(WosTuning), _VP]),
@@ -248,6 +250,12 @@ def wos_build_measure(ctx, geom, walk: WosWalkParams, x_obs_dev, n_obs, counts_d
                       trace_dev=None, stream=None):
     _check(lib().wos_build_measure(ctx, C.byref(geometry(geom)), C.byref(walk), _ptr(x_obs_dev), int(n_obs),
                                    _ptr(counts_dev), _ptr(stats_dev), _ptr(trace_dev), _stream(stream)))
+
+
+def wos_build_measure_noalloc(ctx, geom, walk: WosWalkParams, x_obs_dev, n_obs, counts_dev, stats_dev=None,
+                              trace_dev=None, stream=None):
+    _check(lib().wos_build_measure_noalloc(ctx, C.byref(geometry(geom)), C.byref(walk), _ptr(x_obs_dev), int(n_obs),
+                                           _ptr(counts_dev), _ptr(stats_dev), _ptr(trace_dev), _stream(stream)))
 
 
 def measure_job(geom, walk: WosWalkParams, x_obs_dev, n_obs, counts_dev, stats_dev=None, trace_dev=None):
