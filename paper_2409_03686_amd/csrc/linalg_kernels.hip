@@ -102,7 +102,9 @@ __global__ void assemble_kernel(SvdDevView v, const uint32_t *__restrict__ count
 }
 
 // Device-wide barrier for a cooperative grid: arrival counter with a generation target and a
-// bounded spin (an expired spin sets the error flag instead of hanging).
+// bounded spin (an expired spin sets the error flag instead of hanging).  One release fence before
+// the arrival and one acquire fence after the wait; the polls themselves are relaxed (an acquire
+// load per poll would invalidate the L2 of the polling XCD every time).
 __device__ __forceinline__ void grid_barrier(uint32_t *counter, uint32_t *err, uint32_t nblocks,
                                              uint32_t &gen)
 {
@@ -110,10 +112,10 @@ __device__ __forceinline__ void grid_barrier(uint32_t *counter, uint32_t *err, u
     if (threadIdx.x == 0) {
         gen += 1;
         const uint32_t target = gen * nblocks;
-        __threadfence();
-        atomicAdd(counter, 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(4);
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
             if (++spins > (1u << 26)) {
@@ -121,7 +123,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t *counter, uint32_t *err, u
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -179,6 +181,20 @@ __device__ __forceinline__ void wave_totals(double (&v)[NV])
         const int hi = __builtin_amdgcn_readlane(__double2hiint(v[e]), 63);
         v[e] = __hiloint2double(hi, lo);
     });
+}
+
+// Maximum over the 64 lanes of non-negative doubles (which order as their bit patterns), with the
+// same DPP steps as wave_totals; lanes outside a step's row mask contribute 0.
+__device__ __forceinline__ double wave_max_pos(double v)
+{
+    v = __builtin_fmax(v, dpp64<0xB1>(v));
+    v = __builtin_fmax(v, dpp64<0x4E>(v));
+    v = __builtin_fmax(v, dpp64<0x141>(v));
+    v = __builtin_fmax(v, dpp64<0x140>(v));
+    v = __builtin_fmax(v, dpp64<0x142, 0xA>(v));
+    v = __builtin_fmax(v, dpp64<0x143, 0xC>(v));
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // FP64 inverse square root: the hardware estimate refined by two Newton steps (each step squares
@@ -688,54 +704,6 @@ __global__ __launch_bounds__(256) void gram_yside_kernel(SvdDevView v)
     }
 }
 
-// Acceptance statistic max_ij |y_i . y_j - delta_ij| s_i s_j / s_1^2 over the k x k Gram matrix of
-// Y (MFMA over the rows), folded into crit with an atomic max on the bit pattern; the Gram matrix
-// itself goes to store (k x k, column-major) when that is not null.
-__global__ __launch_bounds__(256) void gram_check_kernel(SvdDevView v, double *store)
-{
-    const double *ys = v.trans ? v.V : v.U;
-    const int tk = (v.k + 15) / 16;
-    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (wave >= tk * tk) return;
-    const int i0 = (wave % tk) * 16, j0 = (wave / tk) * 16;
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const bool va = i0 + li < v.k, vb = j0 + li < v.k;
-    const double *ya = ys + static_cast<size_t>(va ? i0 + li : 0) * v.rows;
-    const double *yb = ys + static_cast<size_t>(vb ? j0 + li : 0) * v.rows;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < v.rows; r0 += 4) {
-        const int r = r0 + lk;
-        const double a = (va && r < v.rows) ? ya[r] : 0.0;
-        const double b = (vb && r < v.rows) ? yb[r] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-    const double s0 = v.s[0];
-    const double inv2 = s0 > 0.0 ? 1.0 / (s0 * s0) : 0.0;
-    double dev = 0.0;
-    const int j = j0 + li;
-    if (store && j < v.k) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = i0 + 4 * e + lk;
-            if (i < v.k) store[static_cast<size_t>(j) * v.k + i] = acc[e];
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int i = i0 + 4 * e + lk;
-        if (i < v.k && j < v.k) {
-            const double d = __builtin_fabs(acc[e] - (i == j ? 1.0 : 0.0)) * v.s[i] * v.s[j] * inv2;
-            dev = (d > dev || d != d) ? d : dev;
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double od = __shfl_xor(dev, o);
-        dev = (od > dev || od != od) ? od : dev;
-    }
-    if (lane == 0) atomicMax(v.crit, static_cast<unsigned long long>(__double_as_longlong(dev)));
-}
-
 // Certificate of the singular values: with u_j = A v_j / s_j (so A v_j = s_j u_j exactly), the
 // residual of the other side, e_j = |A^T u_j - s_j v_j| + s_j | |u_j|^2 - 1 |, bounds the distance
 // from s_j to a singular value of A (the symmetric matrix [[0, A], [A^T, 0]] has the residual
@@ -1122,8 +1090,8 @@ template <int R> static hipError_t launch_gram_jacobi1(double *X, double *zs, in
 // ---------------------------------------------------------------------------------------------
 constexpr int kCholNb = 64;     // pivots per panel
 constexpr int kCholCand = 128;  // candidates per panel
-constexpr int kCholLd = kCholCand + 1;
-constexpr size_t kCholLds = static_cast<size_t>(kCholCand) * kCholLd * sizeof(double);
+// sort keys and rows of the candidate selection (np <= 2048 rounded up to a power of two)
+constexpr size_t kCholLds = static_cast<size_t>(2048) * (sizeof(double) + sizeof(int));
 
 // Row state of the pivoted factorisation (int32 arrays of np in SvdDevView::gpiv):
 //   rs[r]  -1 while row r remains, else the panel that eliminated it
@@ -1139,21 +1107,21 @@ __device__ __forceinline__ bool chol_before(double ka, int ia, double kb, int ib
     return ka > kb || (ka == kb && ia < ib);
 }
 
-// Panel k0: candidate selection (bitonic sort of the remaining rows by their Schur diagonal in
-// LDS), then 64 greedy pivot steps on the candidates' Schur block M (LDS); writes the factor's
-// columns k0 .. k0 + 63 at the candidate rows, the pivots and the row states.  Panel 0 first
+// Panel k0, part 1: candidate selection, a bitonic sort of the remaining rows by their Schur diagonal
+// (larger first, then lower row) in LDS; writes the kCholCand candidates (rows, diagonals,
+// dependence thresholds np 2^-52 G_jj) to cand and marks them in the row states.  Panel 0 first
 // copies the diagonal of G to dg and initialises the row states.
-__global__ __launch_bounds__(1024) void chol_pivot_kernel(const double *__restrict__ S, double *__restrict__ X, int np,
-                                                          int k0, double *__restrict__ dg, CholState cs)
+struct CholCand {
+    int32_t row[kCholCand];
+    double d[kCholCand], th[kCholCand];
+};
+
+__global__ __launch_bounds__(1024) void chol_select_kernel(const double *__restrict__ S, int np, int k0,
+                                                           double *__restrict__ dg, CholState cs,
+                                                           CholCand *__restrict__ cand)
 {
-    extern __shared__ double M[];  // kCholCand x kCholLd; before the gather: the sort keys and rows
-    __shared__ int cidx[kCholCand];
-    __shared__ double lv[kCholCand];
-    __shared__ double thc[kCholCand];
-    __shared__ int taken[kCholCand];
-    __shared__ int pv_s;
-    __shared__ double pinv_s;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    extern __shared__ double lds[];  // n2 sort keys, then n2 rows
+    const int tid = threadIdx.x;
     const int panel = k0 / kCholNb;
     if (k0 == 0) {
         for (int j = tid; j < np; j += 1024) {
@@ -1163,11 +1131,10 @@ __global__ __launch_bounds__(1024) void chol_pivot_kernel(const double *__restri
         }
         __syncthreads();
     }
-    // --- candidates: the kCholCand remaining rows with the largest Schur diagonal
     int n2 = 64;
     while (n2 < np) n2 <<= 1;
-    double *key = M;
-    int *row = reinterpret_cast<int *>(M + n2);
+    double *key = lds;
+    int *row = reinterpret_cast<int *>(lds + n2);
     for (int j = tid; j < n2; j += 1024) {
         key[j] = (j < np && cs.rs[j] < 0) ? S[static_cast<size_t>(j) * np + j] : -__builtin_inf();
         row[j] = j;
@@ -1193,74 +1160,130 @@ __global__ __launch_bounds__(1024) void chol_pivot_kernel(const double *__restri
     const int nrem = np - k0;  // every panel eliminates kCholNb rows
     const int nc = nrem < kCholCand ? nrem : kCholCand;
     if (tid < kCholCand) {
-        const int r = tid < nc ? row[tid] : 0;
-        cidx[tid] = r;
-        taken[tid] = tid < nc ? 0 : 1;
-        thc[tid] = tid < nc ? static_cast<double>(np) * 0x1.0p-52 * dg[r] : 0.0;
+        const int r = tid < nc ? row[tid] : -1;
+        cand->row[tid] = r;
+        cand->d[tid] = tid < nc ? key[tid] : -__builtin_inf();
+        cand->th[tid] = tid < nc ? static_cast<double>(np) * 0x1.0p-52 * dg[r] : 0.0;
         if (tid < nc) cs.cp[r] = panel;
     }
+}
+
+// Panel k0, part 2: the 64 greedy pivot steps, one wave.  The candidates' Schur block M (lower
+// triangle) is gathered into LDS once; lane l keeps the factor rows of candidates l and l + 64 in
+// registers.  Step s takes the candidate with the largest updated diagonal (among those above their
+// dependence threshold; none: the first remaining one, with a zero column), its owner publishes its
+// factor row in LDS, and every candidate a forms l_a = (M[a, p] - L[a, 0:s] L[p, 0:s]^T) / sqrt(d_p)
+// and d_a -= l_a^2 (left-looking, so no block update).  The steps are unrolled at compile time (the
+// factor rows stay in registers).  Writes the factor's columns k0 .. k0 + 63 at the candidate rows,
+// the pivots and the row states.
+__global__ __launch_bounds__(256) void chol_steps_kernel(const double *__restrict__ S, double *__restrict__ X, int np,
+                                                         int k0, CholState cs, const CholCand *__restrict__ cand)
+{
+    constexpr int kTri = kCholCand * (kCholCand + 1) / 2;
+    __shared__ double M[kTri];         // M[a (a + 1) / 2 + b], b <= a
+    __shared__ double Lc[kCholCand][kCholNb + 1];  // factor rows of the candidates, as computed
+    __shared__ int rowc[kCholCand];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int panel = k0 / kCholNb;
+    const int nrem = np - k0;
+    const int nc = nrem < kCholCand ? nrem : kCholCand;
+    if (tid < kCholCand) rowc[tid] = cand->row[tid];
     __syncthreads();
-    // --- the candidates' Schur block
-    for (int e = tid; e < nc * nc; e += 1024) {
-        const int a = e % nc, b = e / nc;
-        M[a * kCholLd + b] = S[static_cast<size_t>(cidx[b]) * np + cidx[a]];
+    // gather by the whole workgroup, 8 independent loads in flight per thread
+    for (int e0 = tid; e0 < kTri; e0 += 256 * 8) {
+        double val[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u;
+            val[u] = 0.0;
+            if (e < kTri) {
+                int a = static_cast<int>((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+                while ((a + 1) * (a + 2) / 2 <= e) ++a;
+                while (a * (a + 1) / 2 > e) --a;
+                const int b = e - a * (a + 1) / 2;
+                if (a < nc) val[u] = S[static_cast<size_t>(rowc[b]) * np + rowc[a]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + 256 * u < kTri) M[e0 + 256 * u] = val[u];
     }
     __syncthreads();
-    for (int s = 0; s < kCholNb; ++s) {
-        if (wv == 0) {
-            double best = -1.0;
-            int bi = kCholCand, first = kCholCand;
+    if (tid >= 64) return;
+    double Lr[2][kCholNb];
+    bool taken[2];
+    double d[2], th[2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int a = lane + 64 * h;
-                if (!taken[a]) {
-                    first = a < first ? a : first;
-                    const double d = M[a * kCholLd + a];
-                    if (d > thc[a] && d > best) {
-                        best = d;
-                        bi = a;
-                    }
-                }
-            }
+    for (int h = 0; h < 2; ++h) {
+        const int a = lane + 64 * h;
+        taken[h] = a >= nc;
+        d[h] = cand->d[a];
+        th[h] = cand->th[a];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o);
-                const int oi = __shfl_xor(bi, o), of = __shfl_xor(first, o);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-                first = of < first ? of : first;
-            }
-            if (lane == 0) {
-                if (bi < kCholCand) {
-                    pv_s = bi;
-                    pinv_s = rsq64(best);
-                } else {  // no qualifying candidate: eliminate one with a zero column
-                    pv_s = first;
-                    pinv_s = 0.0;
-                }
+        for (int t = 0; t < kCholNb; ++t) Lr[h][t] = 0.0;
+    }
+    static_for<0, kCholNb>([&](auto ss) {
+        constexpr int st = decltype(ss)::value;
+        // argmax of the qualifying diagonals: positive doubles order as their bit patterns, so the
+        // low 7 mantissa bits carry 127 - a (equal truncated values: the lower candidate wins)
+        double key = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int a = lane + 64 * h;
+            if (!taken[h] && d[h] > th[h]) {
+                const double k = __longlong_as_double(
+                    static_cast<long long>((static_cast<unsigned long long>(__double_as_longlong(d[h])) & ~0x7Full) |
+                                           static_cast<unsigned long long>(127 - a)));
+                key = key > k ? key : k;
             }
         }
-        __syncthreads();
-        const int p = pv_s;
-        const double inv = pinv_s;
-        if (tid < nc) {
-            const double l = taken[tid] ? 0.0 : M[tid * kCholLd + p] * inv;
-            lv[tid] = l;
-            X[static_cast<size_t>(k0 + s) * np + cidx[tid]] = l;
+        key = wave_max_pos(key);
+        const bool qual = key > 0.0;  // uniform
+        int p;
+        double best = 0.0;
+        if (qual) {
+            p = 127 - static_cast<int>(static_cast<unsigned long long>(__double_as_longlong(key)) & 0x7Full);
+            const double dp = (p >> 6) ? d[1] : d[0];
+            best = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(dp), p & 63),
+                                    __builtin_amdgcn_readlane(__double2loint(dp), p & 63));
+        } else {  // none above its threshold: the first remaining candidate, with a zero column
+            const uint64_t m0 = __ballot(!taken[0]), m1 = __ballot(!taken[1]);
+            p = m0 ? __builtin_ctzll(m0) : 64 + __builtin_ctzll(m1);
         }
-        __syncthreads();
-        if (tid == 0) {
-            taken[p] = 1;
-            cs.piv[k0 + s] = cidx[p];
-            cs.rs[cidx[p]] = panel;
+        const double inv = qual ? rsq64(best) : 0.0;
+        const double *lp = Lc[p];  // the pivot's factor row (uniform address: broadcast reads)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int a = lane + 64 * h;
+            double acc0 = a >= p ? M[a * (a + 1) / 2 + p] : M[p * (p + 1) / 2 + a], acc1 = 0.0;
+#pragma unroll
+            for (int t = 0; t + 1 < st; t += 2) {
+                acc0 = __builtin_fma(-Lr[h][t], lp[t], acc0);
+                acc1 = __builtin_fma(-Lr[h][t + 1], lp[t + 1], acc1);
+            }
+            if constexpr (st & 1) acc0 = __builtin_fma(-Lr[h][st - 1], lp[st - 1], acc0);
+            // sqrt(d_p) at the pivot; rows already taken (or absent) keep zeros
+            const double l = taken[h] ? 0.0 : (a == p ? best * inv : (acc0 + acc1) * inv);
+            if (a == p) taken[h] = true;
+            Lr[h][st] = l;
+            Lc[a][st] = l;
+            d[h] = __builtin_fma(-l, l, d[h]);
         }
-        for (int e = tid; e < nc * nc; e += 1024) {
-            const int a = e / nc, b = e % nc;
-            M[a * kCholLd + b] = __builtin_fma(-lv[a], lv[b], M[a * kCholLd + b]);
+        if (lane == 0) {
+            const int rp = rowc[p];
+            cs.piv[k0 + st] = rp;
+            cs.rs[rp] = panel;
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // column st is read by the next steps
+    });
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int a = lane + 64 * h;
+        if (a < nc) {
+            const int r = rowc[a];
+#pragma unroll
+            for (int t = 0; t < kCholNb; ++t) X[static_cast<size_t>(k0 + t) * np + r] = Lr[h][t];
+        }
     }
 }
 
@@ -1331,16 +1354,13 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double *__restrict__ S, 
 
 static hipError_t chol_pivoted(const SvdDevView &v, hipStream_t stream)
 {
-    static std::once_flag once;
-    std::call_once(once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_pivot_kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kCholLds));
-    });
     const CholState cs{reinterpret_cast<int32_t *>(v.gpiv), reinterpret_cast<int32_t *>(v.gpiv) + v.np,
                        reinterpret_cast<int32_t *>(v.gpiv) + 2 * v.np};
+    CholCand *cand = reinterpret_cast<CholCand *>(v.gpiv + 3 * static_cast<size_t>(v.np));
     const int T = v.np / 16;
     for (int k0 = 0; k0 < v.np; k0 += kCholNb) {
-        chol_pivot_kernel<<<1, 1024, kCholLds, stream>>>(v.G, v.L, v.np, k0, v.zs, cs);
+        chol_select_kernel<<<1, 1024, kCholLds, stream>>>(v.G, v.np, k0, v.zs, cs, cand);
+        chol_steps_kernel<<<1, 256, 0, stream>>>(v.G, v.L, v.np, k0, cs, cand);
         chol_rows_kernel<<<(v.np + 255) / 256, 256, 0, stream>>>(v.G, v.L, v.np, k0, cs);
         if (k0 + kCholNb < v.np) chol_syrk_kernel<<<(T * T + 3) / 4, 256, 0, stream>>>(v.G, v.L, v.np, k0);
     }
@@ -1379,10 +1399,11 @@ struct GridJacobiArgs {
     int P;           // block pairs (np / (2 BW)); the grid has P workgroups or fewer
 };
 
+// Relaxed polls of a round flag (the caller issues one acquire fence after all its waits).
 __device__ __forceinline__ bool spin_until(const uint32_t *word, uint32_t target, uint32_t *err)
 {
     uint32_t spins = 0;
-    while (__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(1);
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
         if (++spins > (1u << 26)) {
@@ -1470,7 +1491,12 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
     __shared__ double nrm_s[NW][2 * BW];
     __shared__ uint32_t stop_sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w = blockIdx.x, G = gridDim.x, P = J.P, nblk = 2 * P, m1 = nblk - 1, np = J.np;
+    const int G = gridDim.x, P = J.P, nblk = 2 * P, m1 = nblk - 1, np = J.np;
+    // Ring position of this workgroup.  Workgroups are dispatched to the 8 XCDs round-robin, so
+    // consecutive positions (the neighbours that exchange blocks every round) are given to
+    // workgroups of the same XCD, and only 8 of the ring's links cross XCDs.
+    const int bx = blockIdx.x, xq = G / 8, xr = G % 8, xx = bx % 8;
+    const int w = G < P ? bx : xx * xq + (xx < xr ? xx : xr) + bx / 8;
     uint32_t *flag = J.ctl;
     uint32_t *rot = J.ctl + kGridFlags;
     uint32_t *bigc = rot + kMaxSweeps;
@@ -1480,6 +1506,9 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
     auto top_of = [&](int t, int ww) { return ww == 0 ? 0 : ((ww - 1 + t) % m1) + 1; };
     auto bot_of = [&](int t, int ww) { return ((nblk - 2 - ww + t) % m1) + 1; };
     double x[R][2 * BW];
+    // Blocks move between workgroups through their home columns of X as agent-scope relaxed atomic
+    // stores and loads: they are written through to the device's coherent level, so the release
+    // fence of a round finds no dirty L2 lines of them to write back.
     auto load = [&](int blk, int off) {
         const double *src = J.X + static_cast<size_t>(blk) * BW * np;
 #pragma unroll
@@ -1487,9 +1516,11 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = tid + NT * i;
-                x[i][off + c] = r < np ? src[static_cast<size_t>(c) * np + r] : 0.0;
+                x[i][off + c] = r < np ? __hip_atomic_load(src + static_cast<size_t>(c) * np + r, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : 0.0;
             }
-        if (lane < BW) nrm_w[off + lane] = J.nrm[blk * BW + lane];
+        if (lane < BW) nrm_w[off + lane] = __hip_atomic_load(J.nrm + blk * BW + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     auto store = [&](int blk, int off, bool with_norms) {
         double *dst = J.X + static_cast<size_t>(blk) * BW * np;
@@ -1498,9 +1529,12 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = tid + NT * i;
-                if (r < np) dst[static_cast<size_t>(c) * np + r] = x[i][off + c];
+                if (r < np)
+                    __hip_atomic_store(dst + static_cast<size_t>(c) * np + r, x[i][off + c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-        if (with_norms && wv == 0 && lane < BW) J.nrm[blk * BW + lane] = nrm_w[off + lane];
+        if (with_norms && wv == 0 && lane < BW)
+            __hip_atomic_store(J.nrm + blk * BW + lane, nrm_w[off + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     // squared norms of the 2 BW columns, fresh from the registers (all waves get the same values)
     auto norms = [&]() {
@@ -1615,9 +1649,9 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
             if (w >= 1) store(top_of(t, w), 0, true);
             if (w <= P - 2) store(bot_of(t, w), BW, true);
             __syncthreads();
-            if (tid == 0) {
-                __threadfence();
-                __hip_atomic_store(&flag[w], rho + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) {  // the barrier above ordered the workgroup's stores before this release
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(&flag[w], rho + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (w == P - 1) {  // the bottom becomes the top
 #pragma unroll
@@ -1631,7 +1665,7 @@ __global__ __launch_bounds__(NT) void gram_jacobi_grid_kernel(GridJacobiArgs J)
                 if (w <= P - 2) ok = spin_until(&flag[w + 1], rho + 1, err);
                 if (ok && w >= 1) ok = spin_until(&flag[w - 1], rho + 1, err);
                 stop_sh = ok ? 0u : 1u;
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
             failed = stop_sh != 0u;
@@ -1694,8 +1728,9 @@ static const void *grid_jacobi_fn(int np)
 
 // C(i, j) = scale_j sum_k opA(i, k) opB(k, j), opA(i, k) = A[i sai + k sak],
 // opB(k, j) = B[k sbk + col(j) sbj] with col(j) = bcol ? bcol[j] : j, and scale_j from z[col(j)]:
-// mode 0: 1, mode 1: 1 / z^2, mode 2: 1 / z (0 where z <= 1e-7 max z).  One 16 x 16 tile per
-// wave (v_mfma_f64_16x16x4f64), C column-major with leading dimension ldc.
+// mode 0: 1, mode 1: 1 / z^2, mode 2: 1 / z (0 where z <= 1e-7 max z), mode 3: 1 / z (0 where
+// z = 0).  C column-major with leading dimension ldc; rows m .. mo - 1 and columns n .. no - 1 of C
+// (mo, no: 0 for m, n) are written as zeros.
 struct GemmArgs {
     const double *A;
     long sai, sak;
@@ -1707,36 +1742,83 @@ struct GemmArgs {
     int m, n, kd;
     const double *z;
     int zn, mode;
+    int mo = 0, no = 0;
 };
 
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
+__device__ __forceinline__ double gemm_scale(const GemmArgs &g, int cj)
 {
-    const int tm = (g.m + 15) / 16, tn = (g.n + 15) / 16;
-    const int wave = static_cast<int>((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (wave >= tm * tn) return;  // whole waves
-    const int i0 = (wave % tm) * 16, j0 = (wave / tm) * 16;
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int i = i0 + li, j = j0 + li;
-    const int cj = j < g.n ? (g.bcol ? g.bcol[j] : j) : 0;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < g.kd; k0 += 4) {
-        const int k = k0 + lk;
-        const double a = (i < g.m && k < g.kd) ? g.A[i * g.sai + k * g.sak] : 0.0;
-        const double b = (j < g.n && k < g.kd) ? g.B[k * g.sbk + cj * g.sbj] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    if (g.mode == 0) return 1.0;
+    const double zc = g.z[cj];
+    if (g.mode == 3) return zc > 0.0 ? 1.0 / zc : 0.0;
+    double zmax = 0.0;
+    for (int e = 0; e < g.zn; ++e) zmax = g.z[e] > zmax ? g.z[e] : zmax;
+    return zc > 1e-7 * zmax ? (g.mode == 1 ? 1.0 / (zc * zc) : 1.0 / zc) : 0.0;
+}
+
+// The GEMM in 64 x 64 tiles of C per 256-thread workgroup: K in chunks of 16 staged through LDS
+// (the A chunk 64 x 16 and the B chunk 16 x 64, both stored k-major), each wave computing a 32 x 32
+// quarter as 2 x 2 v_mfma_f64_16x16x4f64 tiles, so every operand fetched from L2 feeds 32 MFMA
+// products instead of one.  Chunks are loaded along the operand's unit stride (coalesced).
+constexpr int kTM = 64, kTK = 16;
+__global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs g)
+{
+    __shared__ double As[kTK][kTM + 1];  // As[k][i]
+    __shared__ double Bs[kTK][kTM + 1];  // Bs[k][j]
+    __shared__ int cols[kTM];
+    const int mo = g.mo > g.m ? g.mo : g.m, no = g.no > g.n ? g.no : g.n;
+    const int tm = (mo + kTM - 1) / kTM;
+    const int i0 = static_cast<int>(blockIdx.x % tm) * kTM, j0 = static_cast<int>(blockIdx.x / tm) * kTM;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wi = (wv & 1) * 32, wj = (wv >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    if (tid < kTM) {
+        const int j = j0 + tid;
+        cols[tid] = j < g.n ? (g.bcol ? g.bcol[j] : j) : -1;
     }
-    if (j >= g.n) return;
-    double scale = 1.0;
-    if (g.mode) {
-        double zmax = 0.0;
-        for (int e = 0; e < g.zn; ++e) zmax = g.z[e] > zmax ? g.z[e] : zmax;
-        const double zc = g.z[cj];
-        scale = zc > 1e-7 * zmax ? (g.mode == 1 ? 1.0 / (zc * zc) : 1.0 / zc) : 0.0;
+    __syncthreads();
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    const bool a_rows = g.sai == 1;  // A contiguous along i, else along k
+    const bool b_ks = g.sbk == 1;    // B contiguous along k, else along j
+    for (int k0 = 0; k0 < g.kd; k0 += kTK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = a_rows ? (tid & 63) : (tid >> 4) + 16 * q;
+            const int k = a_rows ? (tid >> 6) + 4 * q : (tid & 15);
+            const int gi = i0 + i, gk = k0 + k;
+            As[k][i] = (gi < g.m && gk < g.kd) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
+            const int j = b_ks ? (tid >> 4) + 16 * q : (tid & 63);
+            const int kb = b_ks ? (tid & 15) : (tid >> 6) + 4 * q;
+            const int cj = cols[j], gkb = k0 + kb;
+            Bs[kb][j] = (cj >= 0 && gkb < g.kd) ? g.B[gkb * g.sbk + cj * g.sbj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTK; kk += 4) {
+            const double a0 = As[kk + lk][wi + li], a1 = As[kk + lk][wi + 16 + li];
+            const double b0 = Bs[kk + lk][wj + li], b1 = Bs[kk + lk][wj + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int r = i0 + 4 * e + lk;
-        if (r < g.m) g.C[r + j * g.ldc] = acc[e] * scale;
+    for (int y = 0; y < 2; ++y) {
+        const int jl = wj + 16 * y + li, j = j0 + jl;
+        if (j >= no) continue;
+        const double scale = j < g.n ? gemm_scale(g, cols[jl]) : 0.0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = i0 + wi + 16 * x + 4 * e + lk;
+                if (i < mo) g.C[i + static_cast<long>(j) * g.ldc] = (i < g.m && j < g.n) ? acc[x][y][e] * scale : 0.0;
+            }
     }
 }
 
@@ -1774,9 +1856,32 @@ constexpr int kPowerIters = 1;
 
 static hipError_t gemm(const GemmArgs &g, hipStream_t stream)
 {
-    const int tiles = ((g.m + 15) / 16) * ((g.n + 15) / 16);
-    gemm_kernel<<<(tiles + 3) / 4, 256, 0, stream>>>(g);
+    const int mo = g.mo > g.m ? g.mo : g.m, no = g.no > g.n ? g.no : g.n;
+    const int tiles = ((mo + kTM - 1) / kTM) * ((no + kTM - 1) / kTM);
+    if (tiles > 0) gemm_tile_kernel<<<tiles, 256, 0, stream>>>(g);
     return hipGetLastError();
+}
+
+// Acceptance statistic from C = Ys^T Ys (k x k, column-major): max_ij |C_ij - delta_ij| s_i s_j / s_1^2
+// folded into crit[0] (atomic max on the bit pattern).
+__global__ void gram_crit_kernel(SvdDevView v, const double *__restrict__ Cm)
+{
+    const size_t kk = static_cast<size_t>(v.k) * v.k;
+    const double s0 = v.s[0];
+    const double inv2 = s0 > 0.0 ? 1.0 / (s0 * s0) : 0.0;
+    double dev = 0.0;
+    for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < kk;
+         e += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int i = static_cast<int>(e % v.k), j = static_cast<int>(e / v.k);
+        const double d = __builtin_fabs(Cm[e] - (i == j ? 1.0 : 0.0)) * v.s[i] * v.s[j] * inv2;
+        dev = (d > dev || d != d) ? d : dev;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double od = __shfl_xor(dev, o);
+        dev = (od > dev || od != od) ? od : dev;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(v.crit, static_cast<unsigned long long>(__double_as_longlong(dev)));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2123,8 +2228,13 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
         grid_wgs = std::min(v.np / (2 * kGridBW), per_cu * std::max(n_cu, 1));
     }
     if (gram) {
-        const int nt = v.np / 16;
-        gram_kernel<<<(nt * nt + 3) / 4, 256, 0, stream>>>(v);
+        const long rl = v.rows, cl = v.cols, kl = v.k, npl = v.np;
+        double *vs = v.trans ? v.U : v.V;        // the eigenvector side (cols x k)
+        double *ys = v.trans ? v.V : v.U;        // the other side (rows x k)
+        // G = A^T A (np x np; the columns past colsp are zero)
+        if ((e = gemm({v.A, rl, 1, v.A, 1, rl, nullptr, v.G, npl, v.colsp, v.colsp, v.rows, nullptr, 0, 0, v.np, v.np},
+                      stream)) != hipSuccess)
+            return e;
         if (grid) {
             if ((e = chol_pivoted(v, stream)) != hipSuccess) return e;
             if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -2154,29 +2264,27 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
             }
         }
         gram_vside_kernel<<<v.np, 64, 0, stream>>>(v);
-        const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
-        gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
-        const int tk = (v.k + 15) / 16;
+        // Ys = A Vs diag(1 / s) and C = Ys^T Ys (k x k, in G)
+        const GemmArgs yside{v.A, 1, rl, vs, 1, cl, nullptr, ys, rl, v.rows, v.k, v.cols, v.s, v.k, 3};
+        const GemmArgs cross{ys, rl, 1, ys, 1, rl, nullptr, v.G, kl, v.k, v.k, v.rows, nullptr, 0, 0};
+        if ((e = gemm(yside, stream)) != hipSuccess) return e;
+        const size_t kk = static_cast<size_t>(v.k) * v.k;
+        const int gk = static_cast<int>(std::min<size_t>(4096, (kk + 255) / 256));
         if (grid) {  // first-order correction of the eigenvector side, then the other side again
-            double *vs = v.trans ? v.U : v.V;
-            gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v, v.G);
-            const size_t kk = static_cast<size_t>(v.k) * v.k, nk = static_cast<size_t>(v.cols) * v.k;
-            gram_fix_kernel<<<static_cast<int>(std::min<size_t>(4096, (kk + 255) / 256)), 256, 0, stream>>>(v, v.G, v.L);
-            const long cl = v.cols, kl = v.k;
+            if ((e = gemm(cross, stream)) != hipSuccess) return e;
+            const size_t nk = static_cast<size_t>(v.cols) * v.k;
+            gram_fix_kernel<<<gk, 256, 0, stream>>>(v, v.G, v.L);
             if ((e = gemm({vs, 1, cl, v.L, 1, kl, nullptr, v.G, cl, v.cols, v.k, v.k, nullptr, 0, 0}, stream)) != hipSuccess)
                 return e;
             copy_f64_kernel<<<static_cast<int>(std::min<size_t>(4096, (nk + 255) / 256)), 256, 0, stream>>>(vs, v.G, nk);
-            gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
+            if ((e = gemm(yside, stream)) != hipSuccess) return e;
         }
-        gram_check_kernel<<<(tk * tk + 3) / 4, 256, 0, stream>>>(v, nullptr);
-        {  // residual certificate: C = A^T Ys (cols x k) in G
-            const double *ys = v.trans ? v.V : v.U;
-            const long rl = v.rows, cl2 = v.cols;
-            if ((e = gemm({v.A, rl, 1, ys, 1, rl, nullptr, v.G, cl2, v.cols, v.k, v.rows, nullptr, 0, 0}, stream)) !=
-                hipSuccess)
-                return e;
-            gram_resid_kernel<<<std::min(v.k, 2048), 256, 0, stream>>>(v, v.G);
-        }
+        if ((e = gemm(cross, stream)) != hipSuccess) return e;
+        gram_crit_kernel<<<gk, 256, 0, stream>>>(v, v.G);
+        // residual certificate: C = A^T Ys (cols x k) in G
+        if ((e = gemm({v.A, rl, 1, ys, 1, rl, nullptr, v.G, cl, v.cols, v.k, v.rows, nullptr, 0, 0}, stream)) != hipSuccess)
+            return e;
+        gram_resid_kernel<<<std::min(v.k, 2048), 256, 0, stream>>>(v, v.G);
         gram_accept_kernel<<<1, 64, 0, stream>>>(v);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         skip = v.ctrl + kCtrlGramOk;

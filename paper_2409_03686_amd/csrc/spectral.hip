@@ -121,7 +121,7 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
         carve_size(n_elem, 4), carve_size(v.cols + 2, 8), carve_size(v.m, 8), carve_size(v.k, 8),
         carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
         carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(grid ? npn : 0, 8),
-        carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn : 0, 4), carve_size(2, 8),
+        carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn + 1024 : 0, 4), carve_size(2, 8),
         carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * big, 8), carve_size(size_t(v.rows) * big, 8),
         carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(big, 8),
         carve_size(std::max<size_t>(tkn, 1), 4)};
@@ -157,7 +157,7 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     const bool grid = !v.tk && v.np > kGramMaxCols;
     v.gnrm = grid ? carve<double>(cur, npn) : nullptr;
     v.gctl = grid ? carve<uint32_t>(cur, kGridCtlWords) : nullptr;
-    v.gpiv = grid ? carve<int32_t>(cur, 3 * npn) : nullptr;
+    v.gpiv = grid ? carve<int32_t>(cur, 3 * npn + 1024) : nullptr;  // row states, then the candidates
     v.crit = carve<unsigned long long>(cur, 2);
     const size_t tkn = static_cast<size_t>(v.tk);
     const size_t big = v.tk && v.cols > v.tk ? tkn : 0;

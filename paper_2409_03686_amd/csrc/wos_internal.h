@@ -57,7 +57,7 @@ struct SvdDevView {
     double *zs;             // np column norms of the rotated factor
     double *gnrm;           // np squared norms in flight (device-wide Jacobi; null otherwise)
     uint32_t *gctl;         // kGridCtlWords control words (device-wide Jacobi; null otherwise)
-    int32_t *gpiv;          // 3 np row states of the pivoted blocked Cholesky (null otherwise)
+    int32_t *gpiv;          // 3 np row states of the pivoted blocked Cholesky, then 1024 words of candidates
     unsigned long long *crit;  // [0] orthogonality check, [1] residual certificate (bit patterns)
     // Truncated path (serving; tk = 0: not used): the kt leading singular triplets from a range
     // sketch of kt columns (cols > kt) or from the Gram path of A itself (cols <= kt), with
