@@ -103,8 +103,9 @@ def parse():
                    help="annulus: CUs of the spectral stream (SVD + reconstruction); the walk kernel gets the rest")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     p.add_argument("--serve-seconds", type=float, default=10.0)
-    p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1),
+    p.add_argument("--serve-svd", type=int, default=0, choices=(0, 1),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--serve-radius", default="mapped", choices=("mapped", "dist"),
@@ -225,7 +226,8 @@ def _serve(ctx, wos, insts, arrivals, svd_mode):
         if o.status == 0 and inst.u_exact_g1 is not None:
             u1 = keep[6 * k + 5]
             errs.append(float(np.abs(u1 - inst.u_exact_g1).max() / max(np.abs(inst.u_exact_g1).max(), 1e-300)))
-    return {"requests": len(out), "completed": len(ok), "median_rel_err_u1": float(np.median(errs)) if errs else None,
+    return {"requests": len(out), "completed": len(ok), "svd_fallbacks": sum(o.svd_fallback for o in ok),
+            "median_rel_err_u1": float(np.median(errs)) if errs else None,
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks_per_s": sum(o.walks for o in ok) / wall,
             "steps_per_s": sum(o.steps for o in ok) / wall, "wall_s": wall}, keep
@@ -261,7 +263,7 @@ def _oracle_errors(wos, insts, keep, n_sample=20):
             "per_request": [{"oracle": a, "served": b} for a, b in rows]}
 
 
-def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1, radius="mapped", oracle_sample=True):
+def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=0, radius="mapped", oracle_sample=True):
     """Request serving on the heterogeneous-instance generator (kinds, conductivities, sizes and walk
     budgets drawn per request; 1-5 % noise; random harmonic data of degree <= 6): each request is
     build H + FP64 SVD + TSVD reconstruction, host buffers in and out.  Capacity = requests per
@@ -288,6 +290,63 @@ def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1, radius="mapped", orac
             insts.append(wi.random_instance(rng, len(insts), mapped_radii=mapped))
         out["at_0.8_capacity"] = dict(_serve(ctx, wos, insts[:len(arr8)], arr8, svd_mode)[0], rate_req_s=r8)
     return out
+
+
+# ----------------------------------------------------------------------------------------- batch
+
+def bench_batch(ctx, wos, wi, torch, reps=3):
+    """The 64-instance heterogeneous batch at its full walk budgets: disks, ellipses, L-shapes,
+    annuli, balls and cubes with random conductivities (condition numbers 1-20), 32-2048 points,
+    64-2048 cells and 1e3-1e5 walks per point, FP32 geometry with each kind's mapped radius.  Each
+    (dimension, kind) is autotuned on a sample, then the whole batch (one persistent launch per
+    dimension) is captured as one HIP graph and replayed `reps` times, timed with HIP events."""
+    insts = wi.cfg4_batch()
+    stream = torch.cuda.current_stream()
+    jobs, keep = [], []
+    for inst in insts:
+        M = wos.wos_element_count(inst.geom)
+        x = wos.device_inputs(inst)
+        cnt = torch.zeros((x.shape[0], M), dtype=torch.int32, device="cuda")
+        stt = torch.zeros(wos.WOS_STATS_WORDS, dtype=torch.int64, device="cuda")
+        keep += [x, cnt, stt]
+        jobs.append(wos.measure_job(inst.geom, wos.walk_params_of(inst), x, x.shape[0], cnt, stt))
+    walks = sum(i.x_obs.shape[0] * i.n_walks for i in insts)
+    tuned = {}
+    t0 = time.perf_counter()
+    for inst, job in zip(insts, jobs):
+        key = (inst.geom.dim, wi.KIND_NAMES[inst.geom.kind])
+        if key not in tuned:
+            block, wpl, items = wos.wos_autotune(ctx, job, 2000)
+            tuned[key] = {"block": block, "walks_per_lane": wpl, "items": items}
+    tune_s = time.perf_counter() - t0
+    plan = wos.wos_plan_create_batch(ctx, jobs)
+    wos.wos_plan_launch(plan, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        wos.wos_plan_launch(plan, stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    wos.wos_plan_destroy(plan)
+    sts = [wos.stats_dict(keep[3 * k + 2]) for k in range(len(insts))]
+    assert all(st["walks"] == i.x_obs.shape[0] * i.n_walks for st, i in zip(sts, insts))
+    steps = sum(st["steps"] for st in sts)
+    steps_2d = sum(st["steps"] for st, i in zip(sts, insts) if i.geom.dim == 2)
+    walks_2d = sum(i.x_obs.shape[0] * i.n_walks for i in insts if i.geom.dim == 2)
+    ops = (steps_2d * OPS_PER_STEP_2D_FP32 + (steps - steps_2d) * OPS_PER_STEP_3D_FP32
+           + walks_2d * OPS_PER_WALK_2D + (walks - walks_2d) * OPS_PER_WALK_3D)
+    lane_slots = sum(st["lane_slots"] for st in sts)
+    return {"instances": len(insts), "walks": walks, "sphere_steps": steps, "ms_per_launch": ms,
+            "walks_per_s": walks / (ms * 1e-3), "sphere_steps_per_s": steps / (ms * 1e-3),
+            "launch": "one HIP graph: zero-fill + one persistent walk launch per dimension", "replays": reps,
+            "autotune_s": tune_s, "tuning": {f"{d}D {k}": v for (d, k), v in tuned.items()},
+            "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                         "unit": "Tops/s", "frac": ops / (ms * 1e-3) / VALU_PEAK_OPS,
+                         "ops": "approximate: every 2D step priced at the annulus count, every 3D step at the box "
+                                "count, per walk the arc / face binning counts",
+                         "simd_efficiency": steps / max(lane_slots, 1)}}
 
 
 # ----------------------------------------------------------------------------------------- cube
@@ -579,6 +638,9 @@ def main():
     if res is None:
         return
     ctx, inst, out, h = res
+    if not a.no_batch:
+        log("64-instance batch at full walk budgets")
+        out["batch"] = bench_batch(ctx, wos, wi, torch)
     if not a.no_serve:
         log(f"serving runs ({a.serve_seconds:.0f} s of arrivals)")
         out["serving"] = serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd, a.serve_radius)

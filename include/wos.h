@@ -383,6 +383,14 @@ wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, wos_svd_t *
                            const double *uD_dev, const double *u0_dev, const wos_reg_params *reg,
                            double *u1_dev, double *pred_dev, int32_t *rank_used_dev,
                            double *alpha_used_dev, wos_plan **out);
+/* Records a batch of measure jobs (as wos_build_measure_batch: one persistent walk launch per
+ * (precision, dimension) group, mixed kinds and conductivities inside a group; eq. "H_MC" of §4.2
+ * for each instance) into a HIP graph: zero-fill of every job's counts and statistics, then the
+ * launches.  The jobs' device pointers are captured and must stay valid while the plan lives; each
+ * launch of the plan recomputes the counts from zero.  The launch shapes are those of the tuning in
+ * force at creation (wos_set_tuning / wos_autotune).  Errors: WOS_EINVAL for an empty batch or an
+ * invalid job (nothing is recorded), WOS_ENOMEM, WOS_EDEVICE. */
+wos_status wos_plan_create_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs, wos_plan **out);
 wos_status wos_plan_launch(wos_plan *plan, void *stream);
 wos_status wos_plan_destroy(wos_plan *plan);
 
@@ -410,6 +418,8 @@ typedef struct {
     int32_t status;                /* wos_status of this request */
     double t_arrive, t_admit, t_done;  /* seconds since the start of wos_serve */
     uint64_t walks, steps;
+    int32_t svd_fallback;          /* 1: svd_mode 1 could not serve the request from its trusted
+                                    * triplets, so it was served by the full SVD (walks run again) */
 } wos_result;
 
 typedef struct {
@@ -423,7 +433,11 @@ typedef struct {
                                     * else 128 (a random range sketch of kt columns first when
                                     * min(m, n) > kt); components below 1e-5 s_1 are not used by
                                     * the reconstruction, and s_host receives min(k, kt) values
-                                    * followed by zeros. */
+                                    * followed by zeros.  Only the leading triplets whose residual
+                                    * |A v - s u| is at most 2^-35 s_1 are trusted: a TSVD rank
+                                    * (given, or chosen by the discrepancy rule) that needs more
+                                    * sends the request to the full SVD (svd_fallback = 1).
+                                    * Tikhonov requests use every triplet kept. */
 } wos_serve_opts;
 
 /* Blocking driver: replays the requests at their arrival times (open loop), admits each when a

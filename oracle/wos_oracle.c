@@ -198,14 +198,23 @@ double oracle_dist(const og_geom *g, const double *x)
     case OG_ELLIPSE:
         return ellipse_lb(g, x);
     case OG_POLYGON: {
+        /* |distance| to the nearest edge, negative outside: D is the polygon's interior, whose
+         * points have an odd crossing number (horizontal ray towards +x, an edge counted when its
+         * end points lie strictly on either side of the ray's line, or one on it and one above) */
         double best = INFINITY, t;
+        int inside = 0;
         for (int e = 0; e < g->n_verts; ++e) {
             const double *a = g->verts + 2 * e;
             const double *b = g->verts + 2 * ((e + 1) % g->n_verts);
             double d = seg_dist(a, b, x, &t);
             if (d < best) best = d;
+            if ((a[1] > x[1]) != (b[1] > x[1])) {
+                double ex = b[0] - a[0], ey = b[1] - a[1];
+                double side = (x[1] - a[1]) * ex - (x[0] - a[0]) * ey; /* > 0: x left of the edge (ey > 0) */
+                if (ey > 0.0 ? side > 0.0 : side < 0.0) inside ^= 1;
+            }
         }
-        return best;
+        return inside ? best : -best;
     }
     case OG_BALL: {
         double s = 0.0;

@@ -1942,23 +1942,37 @@ __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out,
     if (threadIdx.x == 0) {
         int kpos = 0;
         for (int l = 0; l < k; ++l) kpos += v.s[l] > rank_tol ? 1 : 0;
+        // truncated path: only the trusted triplets may be used; a rank that needs more is flagged
+        // (the serving engine then solves the request with the full SVD)
+        const int kuse = v.tk ? (kpos < static_cast<int>(v.ctrl[kCtrlTrusted]) ? kpos : static_cast<int>(v.ctrl[kCtrlTrusted]))
+                              : kpos;
+        bool unresolved = false;
         int r = 0;
         double alpha = 0.0;
         if (reg.kind == 0) {
-            r = reg.rank < 0 ? 0 : (reg.rank > kpos ? kpos : reg.rank);
+            const int want = reg.rank < 0 ? 0 : (reg.rank > kpos ? kpos : reg.rank);
+            r = want > kuse ? kuse : want;
+            unresolved = want > kuse;
         } else if (reg.kind == 1) {
             const double target = reg.tau * reg.delta;
             double res2 = v.work[v.cols];
             r = kpos;
-            for (int l = 0; l < kpos; ++l) {
+            bool met = false;
+            for (int l = 0; l < kuse; ++l) {
                 res2 -= v.cvec[l] * v.cvec[l];
                 const double res = __builtin_sqrt(res2 > 0.0 ? res2 : 0.0);
                 if (res <= target) {
                     r = l + 1;
+                    met = true;
                     break;
                 }
             }
+            if (!met && kuse < kpos) {
+                r = kuse;
+                unresolved = true;
+            }
         }
+        if (v.tk) v.ctrl[kCtrlUnresolved] = unresolved ? 1u : 0u;
         sh_rank = r;
         sh_alpha = alpha;
     }
@@ -2305,6 +2319,36 @@ hipError_t svd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n,
     return hipGetLastError();
 }
 
+// Residual of each computed triplet of the truncated path, |A v_l - s_l u_l| (W = A V, rows x k),
+// into zt[l]; one block per triplet.
+__global__ void trip_resid_kernel(SvdDevView v, const double *__restrict__ W)
+{
+    __shared__ double scratch[16];
+    const int l = blockIdx.x;
+    if (l >= v.k) return;
+    const double *u = (v.trans ? v.V : v.U) + static_cast<size_t>(l) * v.rows;
+    const double *w = W + static_cast<size_t>(l) * v.rows;
+    const double sl = v.s[l];
+    double acc = 0.0;
+    for (int r = threadIdx.x; r < v.rows; r += blockDim.x) {
+        const double d = w[r] - sl * u[r];
+        acc = __builtin_fma(d, d, acc);
+    }
+    acc = block_sum(acc, scratch);
+    if (threadIdx.x == 0) v.zt[l] = __builtin_sqrt(acc);
+}
+
+// The trusted prefix: the leading triplets whose residual is at most 2^-35 s_1 (the bound the full
+// SVD's acceptance uses), stopping at the first that misses it.
+__global__ void trust_kernel(SvdDevView v)
+{
+    if (threadIdx.x != 0) return;
+    const double lim = 0x1.0p-35 * (v.k > 0 ? v.s[0] : 0.0);
+    int t = 0;
+    while (t < v.k && v.zt[t] <= lim) ++t;
+    v.ctrl[kCtrlTrusted] = static_cast<uint32_t>(t);
+}
+
 hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, uint64_t seed, hipStream_t stream)
 {
     if (v.tk != 64 && v.tk != 128) return hipErrorInvalidValue;
@@ -2326,6 +2370,18 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
         if (K == 64) (void)launch_gram_jacobi1<1>(X, z, v.info, stream);
         else (void)launch_gram_jacobi1<2>(X, z, v.info, stream);
     };
+    // residual certificate of every computed triplet (W = A V_A in Y, which is free by then) and the
+    // trusted prefix
+    auto certify = [&]() -> hipError_t {
+        const double *colside = v.trans ? v.U : v.V;
+        hipError_t e2 = gemm({v.A, 1, static_cast<long>(v.rows), colside, 1, static_cast<long>(v.cols), nullptr, v.Y,
+                              static_cast<long>(v.rows), v.rows, v.k, v.cols, nullptr, 0, 0},
+                             stream);
+        if (e2 != hipSuccess) return e2;
+        trip_resid_kernel<<<v.k, 256, 0, stream>>>(v, v.Y);
+        trust_kernel<<<1, 64, 0, stream>>>(v);
+        return hipGetLastError();
+    };
     if (v.cols <= K) {  // the Gram path of A with the one-workgroup Jacobi
         const int nt = K / 16;
         gram_kernel<<<(nt * nt + 3) / 4, 256, 0, stream>>>(v);
@@ -2334,7 +2390,7 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
         gram_vside_kernel<<<K, 64, 0, stream>>>(v);
         const int ty = ((v.rows + 15) / 16) * ((v.k + 15) / 16);
         gram_yside_kernel<<<(ty + 3) / 4, 256, 0, stream>>>(v);
-        return hipGetLastError();
+        return certify();
     }
     const long R = v.rows, Cc = v.cols, Kl = K;
     const int sg = static_cast<int>(std::min<size_t>(4096, (static_cast<size_t>(Cc) * K + 255) / 256));
@@ -2367,7 +2423,8 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
     double *colside = v.trans ? v.U : v.V;  // cols x k
     // U_A = Q E / s (E = L[:, perm] / zs[perm]), V_A = C^T E / s = C^T L[:, perm] / zs^2
     if ((e = gemm({v.Q, 1, R, v.L, 1, Kl, v.perm, rowside, R, v.rows, v.k, K, v.zs, K, 2}, stream)) != hipSuccess) return e;
-    return gemm({v.Cm, Kl, 1, v.L, 1, Kl, v.perm, colside, Cc, v.cols, v.k, K, v.zs, K, 1}, stream);
+    if ((e = gemm({v.Cm, Kl, 1, v.L, 1, Kl, v.perm, colside, Cc, v.cols, v.k, K, v.zs, K, 1}, stream)) != hipSuccess) return e;
+    return certify();
 }
 
 hipError_t recon_launch(const SvdDevView &v, const uint32_t *counts, double inv_n, const double *uD,

@@ -148,6 +148,7 @@ struct Job {
     std::vector<double> x, uD, u0, u1, pred, sv, verts;
     std::vector<uint8_t> mask;
     wos_result own{};
+    bool full = false;  // served by the full SVD after the truncated one could not resolve its rank
     bool done = false;
 };
 
@@ -208,12 +209,15 @@ class Engine {
 
     double timeout() const { return timeout_; }
     int inflight() const { return inflight_; }
+    bool has_retry() const { return !retry_.empty(); }
 
     // Admits queued jobs in order while a slot and memory are free.  Returns a fatal status.
     wos_status admit(std::deque<Job *> &queue, double now)
     {
-        while (!queue.empty() && inflight_ < max_inflight_) {
-            Job *j = queue.front();
+        // requests sent back for the full SVD go first
+        while ((!retry_.empty() || !queue.empty()) && inflight_ < max_inflight_) {
+            std::deque<Job *> &from = retry_.empty() ? queue : retry_;
+            Job *j = from.front();
             size_t off = 0;
             if (!arena_.alloc(j->L.total, off)) break;  // wait for memory
             Slot *slot = nullptr;
@@ -225,8 +229,8 @@ class Engine {
             slot->job = j;
             slot->mem_off = off;
             slot->mem_len = j->L.total;
-            queue.pop_front();
-            j->res->t_admit = now;
+            from.pop_front();
+            if (!j->full) j->res->t_admit = now;
             wos_status st = launch(*slot, *j);
             if (st != WOS_OK) return st;
             ++inflight_;
@@ -247,6 +251,14 @@ class Engine {
             if (q != hipSuccess) {
                 R.status = WOS_EDEVICE;
                 *fatal = set_error(WOS_EDEVICE, "request failed on the device: %s", hipGetErrorString(q));
+            } else if (svd_mode_ == 1 && !j.full &&
+                       static_cast<const uint8_t *>(s.pinned)[s.out_scal + 4] != 0 && resubmit_full(j)) {
+                // the truncated SVD's trusted triplets do not meet the regularisation rule: the
+                // request runs again with the full SVD (the same walks, so the same counts)
+                arena_.release(s.mem_off, s.mem_len);
+                s.job = nullptr;
+                --inflight_;
+                continue;
             } else {
                 const uint8_t *pin = static_cast<const uint8_t *>(s.pinned);
                 std::memcpy(R.u1_host, pin + s.out_u1, 8ull * j.L.n1);
@@ -261,6 +273,7 @@ class Engine {
                 std::memcpy(stw, pin + s.out_stats, sizeof stw);
                 R.walks = stw[WOS_STAT_WALKS];
                 R.steps = stw[WOS_STAT_STEPS];
+                R.svd_fallback = j.full ? 1 : 0;
                 R.t_done = now;
                 if (timeout_ > 0 && R.t_done - R.t_arrive > timeout_) R.status = WOS_ETIMEOUT;
             }
@@ -288,6 +301,24 @@ class Engine {
     }
 
   private:
+    // Lays the request out again for the full SVD and queues it for admission; false (with the
+    // request's status set) when it cannot be.
+    bool resubmit_full(Job &j)
+    {
+        ReqLayout L;
+        wos_status st = layout_request(j.req, L, 0);
+        if (st == WOS_OK && L.total > budget_)
+            st = set_error(WOS_ENOMEM, "request needs %zu bytes for the full SVD, budget %zu", L.total, budget_);
+        if (st != WOS_OK) {
+            j.res->status = st;
+            return false;
+        }
+        j.L = L;
+        j.full = true;
+        retry_.push_back(&j);
+        return true;
+    }
+
     bool grow_pinned(Slot &s, size_t need)
     {
         if (s.pinned_cap >= need) return true;
@@ -367,6 +398,9 @@ class Engine {
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_pred, pred, 8ull * r.n_obs, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_s, L.svd.v.s, 8ull * L.k, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_scal, base + L.off_scal, 16, hipMemcpyDeviceToHost, s.stream);
+        // the truncated path's flag (rank beyond its trusted triplets) into the scalars' spare word
+        if (e == hipSuccess && L.svd.v.tk)
+            e = hipMemcpyAsync(pin + s.out_scal + 4, L.svd.v.ctrl + kCtrlUnresolved, 4, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_stats, stats, 8ull * WOS_STATS_WORDS, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) return set_error(WOS_EDEVICE, "enqueue failed: %s", hipGetErrorString(e));
@@ -381,6 +415,7 @@ class Engine {
     void *arena_mem_ = nullptr;
     Arena arena_;
     std::vector<Slot> slots_;
+    std::deque<Job *> retry_;
 };
 
 }  // namespace
@@ -405,6 +440,7 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
         results[i].walks = results[i].steps = 0;
         results[i].rank_used = 0;
         results[i].alpha_used = 0.0;
+        results[i].svd_fallback = 0;
         if (eng.prepare(j) == WOS_OK) max_stage = std::max(max_stage, staging_bytes(reqs[i], j.L));
     }
     wos_status st = eng.init(max_stage);
@@ -442,7 +478,7 @@ extern "C" wos_status wos_serve(wos_ctx *ctx, const wos_request *reqs, int32_t n
         done_count += static_cast<size_t>(fin);
         if (fin == 0) {
             const double next_t = next_arrival < order.size() ? reqs[order[next_arrival]].arrival_s : 1e300;
-            if (eng.inflight() == 0 && queue.empty() && next_t > now())
+            if (eng.inflight() == 0 && queue.empty() && !eng.has_retry() && next_t > now())
                 std::this_thread::sleep_for(std::chrono::duration<double>(std::min(next_t - now(), 0.001)));
             else
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -480,9 +516,9 @@ struct LiveServer {
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                if (queue.empty() && eng->inflight() == 0 && pending.empty())
+                if (queue.empty() && eng->inflight() == 0 && pending.empty() && !eng->has_retry())
                     cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] { return stop || !pending.empty(); });
-                if (stop && pending.empty() && queue.empty() && eng->inflight() == 0) return;
+                if (stop && pending.empty() && queue.empty() && eng->inflight() == 0 && !eng->has_retry()) return;
                 while (!pending.empty()) {
                     queue.push_back(pending.front());
                     pending.pop_front();
@@ -654,6 +690,7 @@ extern "C" wos_status wos_serve_poll(wos_ctx *ctx, uint64_t ticket, wos_result *
     out->t_done = R.t_done;
     out->walks = R.walks;
     out->steps = R.steps;
+    out->svd_fallback = R.svd_fallback;
     L->jobs.erase(it);
     return WOS_OK;
 }

@@ -122,8 +122,8 @@ wos_status wos::svd_layout(int32_t n_obs, int32_t n_elem, const uint8_t *gamma1_
         carve_size(v.k, 8), carve_size(2 * kMaxSweeps, 4), carve_size(kCtrlWords, 4), carve_size(kInfoWords, 4),
         carve_size(npn * npn, 8), carve_size(npn * npn, 8), carve_size(npn, 8), carve_size(grid ? npn : 0, 8),
         carve_size(grid ? kGridCtlWords : 0, 4), carve_size(grid ? 3 * npn + 1024 : 0, 4), carve_size(2, 8),
-        carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * big, 8), carve_size(size_t(v.rows) * big, 8),
-        carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(big, 8),
+        carve_size(size_t(v.cols) * big, 8), carve_size(size_t(v.rows) * tkn, 8), carve_size(size_t(v.rows) * big, 8),
+        carve_size(big * v.cols, 8), carve_size(big * big, 8), carve_size(big * big, 8), carve_size(tkn, 8),
         carve_size(std::max<size_t>(tkn, 1), 4)};
     for (size_t s : sz) hs.bytes += s;
     return WOS_OK;
@@ -162,12 +162,12 @@ void wos::svd_bind(SvdHost &hs, void *mem)
     const size_t tkn = static_cast<size_t>(v.tk);
     const size_t big = v.tk && v.cols > v.tk ? tkn : 0;
     v.Om = carve<double>(cur, size_t(v.cols) * big);
-    v.Y = carve<double>(cur, size_t(v.rows) * big);
+    v.Y = carve<double>(cur, size_t(v.rows) * tkn);  // also A V for the triplet residuals
     v.Q = carve<double>(cur, size_t(v.rows) * big);
     v.Cm = carve<double>(cur, big * v.cols);
     v.Gt = carve<double>(cur, big * big);
     v.Lt = carve<double>(cur, big * big);
-    v.zt = carve<double>(cur, big);
+    v.zt = carve<double>(cur, tkn);  // also the triplet residuals
     v.perm = carve<int32_t>(cur, std::max<size_t>(tkn, 1));
 }
 
@@ -494,6 +494,82 @@ extern "C" wos_status wos_plan_create(wos_ctx *ctx, const wos_measure_job *job, 
             e = recon_launch(svd->v, job->counts_dev, 1.0 / static_cast<double>(n_walks), uD_dev,
                              svd->v.n0 ? u0_dev : nullptr, r, u1_dev, pred_dev, rank_used_dev, alpha_used_dev, cs);
         }
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        return cleanup("graph capture", e);
+    }
+    *out = p;
+    return WOS_OK;
+}
+
+extern "C" wos_status wos_plan_create_batch(wos_ctx *ctx, const wos_measure_job *jobs, int32_t n_jobs, wos_plan **out)
+{
+    if (!ctx || !out || n_jobs < 1 || !jobs) return set_error(WOS_EINVAL, "NULL argument or empty batch");
+    *out = nullptr;
+    std::vector<std::vector<int>> groups;
+    wos_status st = group_jobs(jobs, n_jobs, groups);
+    if (st != WOS_OK) return st;
+    if (groups.empty()) return set_error(WOS_EINVAL, "plan has no walks to run");
+    // every group's descriptor (instances, records, then its work cursors) in one allocation
+    std::vector<std::vector<uint8_t>> bufs(groups.size());
+    std::vector<GroupLaunch> gls(groups.size());
+    std::vector<size_t> offs(groups.size());
+    size_t total = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        st = prepare_group(ctx, jobs, groups[g], nullptr, bufs[g], gls[g]);
+        if (st != WOS_OK) return st;
+        offs[g] = total;
+        total += (((bufs[g].size() + 15) & ~size_t(15)) + 4 * walk_cursor_words(gls[g].mode, gls[g].items) + 64 + 255) &
+                 ~size_t(255);
+    }
+    std::lock_guard<std::recursive_mutex> lk(ctx->launch_mu);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    wos_plan *p = new wos_plan();
+    p->ctx = ctx;
+    p->desc_bytes = total;
+    st = ctx_malloc(ctx, &p->desc, p->desc_bytes);
+    if (st != WOS_OK) {
+        delete p;
+        return st;
+    }
+    auto cleanup = [&](const char *what, hipError_t e) {
+        ctx_free(ctx, p->desc, p->desc_bytes);
+        delete p;
+        return set_error(WOS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    std::vector<uint32_t *> cursors(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        uint8_t *dev = static_cast<uint8_t *>(p->desc) + offs[g];
+        DevInst *I = reinterpret_cast<DevInst *>(bufs[g].data());
+        for (int q = 0; q < gls[g].n_inst; ++q)
+            I[q].segs = reinterpret_cast<const PolySeg *>(reinterpret_cast<uintptr_t>(dev) + reinterpret_cast<uintptr_t>(I[q].segs));
+        hipError_t e = hipMemcpy(dev, bufs[g].data(), bufs[g].size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup("descriptor upload", e);
+        cursors[g] = reinterpret_cast<uint32_t *>(dev + ((bufs[g].size() + 15) & ~size_t(15)));
+    }
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup("stream", e);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g)
+        for (int q : groups[g]) {
+            const wos_measure_job &J = jobs[q];
+            int M = 0;
+            (void)validate_geometry(&J.geom, &M);
+            if (e == hipSuccess) e = fill_u32(J.counts_dev, static_cast<size_t>(J.n_obs) * M, 0u, cs);
+            if (e == hipSuccess && J.stats_dev)
+                e = fill_u32(reinterpret_cast<uint32_t *>(J.stats_dev), 2 * WOS_STATS_WORDS, 0u, cs);
+        }
+    for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
+        const GroupLaunch &gl = gls[g];
+        e = launch_walks(gl.precision, gl.dim, gl.kind_sel, gl.mode,
+                         reinterpret_cast<const DevInst *>(static_cast<uint8_t *>(p->desc) + offs[g]), gl.n_inst, gl.items,
+                         cursors[g], gl.hist_words, gl.seg_bytes, gl.block, gl.grid, cs);
     }
     hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
     if (e == hipSuccess) e = e2;

@@ -252,15 +252,24 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
         const double m = I.p[2] < I.p[3] ? I.p[2] : I.p[3];
         return m * (1.0 - f);
     } else if constexpr (KIND == kPolygon) {
+        // signed: negative outside the polygon, by the parity of the edges that a ray from x
+        // towards +x crosses (the straddle test reads the vertices, so two edges that share a vertex
+        // agree on it)
         double best = __builtin_inf();
+        bool inside = false;
         for (int e = 0; e < I.n_verts; ++e) {
             double t;
             const double q = seg_dist_sq<double>(segs[e].ax, segs[e].ay, segs[e].ex, segs[e].ey,
                                                  segs[e].ll, x[0], x[1], &t);
             const double d = __builtin_sqrt(q);
             best = d < best ? d : best;
+            const double by = segs[e + 1 == I.n_verts ? 0 : e + 1].ay;
+            if ((segs[e].ay > x[1]) != (by > x[1])) {
+                const double side = (x[1] - segs[e].ay) * segs[e].ex - (x[0] - segs[e].ax) * segs[e].ey;
+                inside ^= segs[e].ey > 0.0 ? side > 0.0 : side < 0.0;
+            }
         }
-        return best;
+        return inside ? best : -best;
     } else if constexpr (KIND == kBall) {
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);

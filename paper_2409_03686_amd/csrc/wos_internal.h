@@ -28,6 +28,8 @@ enum SvdCtrl : int {
     kCtrlBarrier = 0,    // grid barrier counter, Hestenes path
     kCtrlError = 1,      // barrier time-out, Hestenes path
     kCtrlGramOk = 2,     // 1: the Gram path's result was accepted, the Hestenes path is skipped
+    kCtrlTrusted = 3,    // truncated path: leading triplets whose residual certificate holds
+    kCtrlUnresolved = 4, // truncated path: the regularisation needs triplets beyond the trusted ones
     kCtrlWords = 8
 };
 // info words: [0] sweeps, [1] error flags of the result returned; [2], [3] the same for the

@@ -77,7 +77,7 @@ class WosResult(C.Structure):
     _fields_ = [("u1_host", C.POINTER(C.c_double)), ("pred_host", C.POINTER(C.c_double)),
                 ("s_host", C.POINTER(C.c_double)), ("rank_used", C.c_int32), ("alpha_used", C.c_double),
                 ("status", C.c_int32), ("t_arrive", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double), ("walks", C.c_uint64), ("steps", C.c_uint64)]
+                ("t_done", C.c_double), ("walks", C.c_uint64), ("steps", C.c_uint64), ("svd_fallback", C.c_int32)]
 
 
 class WosServeOpts(C.Structure):
@@ -119,6 +119,7 @@ _SIGS = {
     "wos_density": (C.c_int, [_VP, _VP, C.c_int32, C.c_int32, C.c_uint64, _VP, _VP, _VP, _VP]),
     "wos_plan_create": (C.c_int, [_VP, C.POINTER(WosMeasureJob), _VP, _VP, _VP, C.POINTER(WosRegParams), _VP, _VP,
                                   _VP, _VP, C.POINTER(_VP)]),
+    "wos_plan_create_batch": (C.c_int, [_VP, C.POINTER(WosMeasureJob), C.c_int32, C.POINTER(C.c_void_p)]),
     "wos_plan_launch": (C.c_int, [_VP, _VP]),
     "wos_plan_destroy": (C.c_int, [_VP]),
     "wos_serve": (C.c_int, [_VP, C.POINTER(WosRequest), C.c_int32, C.POINTER(WosResult), C.POINTER(WosServeOpts)]),
@@ -363,6 +364,13 @@ def wos_plan_create(ctx, job: WosMeasureJob, svd=None, uD_dev=None, u0_dev=None,
     _check(lib().wos_plan_create(ctx, C.byref(job), svd, _ptr(uD_dev), _ptr(u0_dev),
                                  None if reg is None else C.byref(reg), _ptr(u1_dev), _ptr(pred_dev),
                                  _ptr(rank_used_dev), _ptr(alpha_used_dev), C.byref(p)))
+    return p.value
+
+
+def wos_plan_create_batch(ctx, jobs: Sequence[WosMeasureJob]) -> int:
+    arr = (WosMeasureJob * len(jobs))(*jobs)
+    p = C.c_void_p()
+    _check(lib().wos_plan_create_batch(ctx, arr, len(jobs), C.byref(p)))
     return p.value
 
 

@@ -131,6 +131,30 @@ def test_fp64_every_kind_walk_for_walk(wos, ctx, case):
     assert st["escapes"] == sr["escapes"] and st["cap_hits"] == 0
 
 
+@pytest.mark.parametrize("precision", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
+@pytest.mark.parametrize("mode", [wi.RADIUS_WOE_BOUND, wi.RADIUS_MAPPED_EXACT])
+def test_polygon_start_points_outside_are_escapes(wos, ctx, precision, mode):
+    """Signed polygon distance on the device: start points outside the L-shape (its notch, beyond an
+    edge, beyond a corner, just right of the inner edge) stop with zero steps in the oracle's
+    projection cell and count as escapes; the points inside walk, and no walk of theirs escapes."""
+    g = wi.Geometry(2, wi.POLYGON, (), (60,), verts=wi.L_SHAPE)
+    x = np.array([[0.75, 0.75], [1.2, 0.3], [-0.1, -0.2], [0.501, 0.9], [0.25, 0.25], [0.8, 0.2], [0.3, 0.7]])
+    out = np.array([1, 1, 1, 1, 0, 0, 0], bool)
+    n = 3000
+    inst = wi.Instance(g, np.array([[1.0, 0.5], [0.5, 2.0]]), x, n, eps=1e-4, seed=31, instance_id=2,
+                       precision=precision, radius_mode=mode)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    assert np.all(c.sum(1) == n)
+    assert np.all(tr[out, :, 1] == 0)
+    assert np.array_equal(tr[out, :, 0], trr[out, :, 0])
+    assert np.array_equal(c[out], cr[out])
+    assert st["escapes"] == sr["escapes"] == out.sum() * n
+    assert np.all(tr[~out, :, 1] > 0)
+    if precision == wi.FP64:
+        assert _agreement(tr[~out], trr[~out]) >= 0.999
+
+
 def test_fp64_full_size_annulus_sampled_rows(wos, ctx):
     """The 1024 x 1e5 annulus workload in FP64: sampled rows recomputed by the oracle alone."""
     inst = wi.cfg2_annulus(precision=wi.FP64)
@@ -415,6 +439,101 @@ def test_batch_equals_separate_and_oracle(wos, ctx, items):
         assert np.abs(got.astype(np.int64) - cr).sum() <= 2e-3 * got.sum() + 2, inst.name
     for dim in (2, 3):
         wos.wos_set_tuning(ctx, dim, -1, wi.FP64, 256, 16, wos.WOS_ITEMS_AUTO)
+
+
+@pytest.mark.parametrize("precision", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
+@pytest.mark.parametrize("items", ["block", "point"])
+def test_batch_many_instances_several_chunks_per_point(wos, ctx, precision, items):
+    """12 instances of mixed kinds, conductivities and radius modes in one launch per dimension, each
+    point spanning big items and at least 3 small chunks (tuning 64 threads x 2 walks per lane:
+    chunks of 128 walks, big items of 512; 1300-2600 walks per point).  The counts equal separate
+    launches bit for bit, and every instance's rows agree with the oracle: FP64 to 2e-3 of the walks
+    in |count difference| (the same walks), FP32 by the exact two-sample test against an oracle run
+    with another seed."""
+    mode = {"block": wos.WOS_ITEMS_BLOCK, "point": wos.WOS_ITEMS_POINT}[items]
+    for dim in (2, 3):
+        wos.wos_set_tuning(ctx, dim, -1, precision, 64, 2, mode)
+    try:
+        insts = wi.cfg4_batch(n_instances=12, seed=14, walk_scale=0.05, precision=precision)
+        rng = np.random.default_rng(9)
+        for inst in insts:
+            inst.x_obs = inst.x_obs[:40]
+            inst.n_walks = int(rng.integers(1300, 2601))
+            assert (inst.n_walks - 3 * 128) // 512 >= 1  # at least one big item, then >= 3 chunks
+        assert len({inst.geom.kind for inst in insts}) >= 4 and len({inst.geom.dim for inst in insts}) == 2
+        sep = [_gpu(wos, ctx, inst)[0] for inst in insts]
+        jobs, keep = [], []
+        for inst in insts:
+            M = wos.wos_element_count(inst.geom)
+            x = wos.device_inputs(inst)
+            cnt = torch.zeros((x.shape[0], M), dtype=torch.int32, device="cuda")
+            keep += [x, cnt]
+            jobs.append(wos.measure_job(inst.geom, wos.walk_params_of(inst), x, x.shape[0], cnt))
+        wos.wos_build_measure_batch(ctx, jobs)
+        torch.cuda.synchronize()
+        for k, inst in enumerate(insts):
+            got = _np(keep[2 * k + 1])
+            assert np.array_equal(got, sep[k]), inst.name
+            assert np.all(got.sum(1) == inst.n_walks), inst.name
+            if precision == wi.FP64:
+                cr, _, _ = ow.build_instance(inst)
+                assert np.abs(got.astype(np.int64) - cr).sum() <= 2e-3 * got.sum() + 2, inst.name
+            else:
+                cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs, inst.eps, seed=inst.seed + 1,
+                                            instance_id=inst.instance_id, radius_mode=inst.radius_mode,
+                                            walk_end=inst.n_walks)
+                rep = statutil.two_sample(got, inst.n_walks, cr, inst.n_walks)
+                assert rep["ok"], (inst.name, rep)
+    finally:
+        for dim in (2, 3):
+            wos.wos_set_tuning(ctx, dim, -1, precision, 256, 16, wos.WOS_ITEMS_AUTO)
+
+
+def test_batch_plan_replays_equal_eager_batch(wos, ctx):
+    """wos_plan_create_batch: the captured zero-fill and walk launches of a 10-instance batch of both
+    dimensions, replayed three times with eager launches (of the same jobs, into other buffers) and
+    host synchronisations between the replays; every replay equals the eager batch bit for bit, and
+    the statistics count every walk once per replay."""
+    insts = wi.cfg4_batch(n_instances=10, seed=15, walk_scale=0.02)
+    for inst in insts:
+        inst.x_obs = inst.x_obs[:64]
+        inst.n_walks = min(inst.n_walks, 3000)
+    assert len({inst.geom.dim for inst in insts}) == 2
+
+    def jobs_for(tag):
+        jobs, keep = [], []
+        for inst in insts:
+            M = wos.wos_element_count(inst.geom)
+            x = wos.device_inputs(inst)
+            cnt = torch.full((x.shape[0], M), 7, dtype=torch.int32, device="cuda")  # the plan zeroes it
+            stt = torch.full((wos.WOS_STATS_WORDS,), 5, dtype=torch.int64, device="cuda")
+            keep += [x, cnt, stt]
+            jobs.append(wos.measure_job(inst.geom, wos.walk_params_of(inst), x, x.shape[0], cnt, stt))
+        return jobs, keep
+
+    jobs_e, keep_e = jobs_for("eager")
+    for k in range(len(insts)):
+        keep_e[3 * k + 1].zero_()
+        keep_e[3 * k + 2].zero_()
+    wos.wos_build_measure_batch(ctx, jobs_e)
+    torch.cuda.synchronize()
+    ref = [_np(keep_e[3 * k + 1]).copy() for k in range(len(insts))]
+    jobs_p, keep_p = jobs_for("plan")
+    plan = wos.wos_plan_create_batch(ctx, jobs_p)
+    try:
+        for rep in range(3):
+            wos.wos_plan_launch(plan)
+            torch.cuda.synchronize()
+            for k, inst in enumerate(insts):
+                assert np.array_equal(_np(keep_p[3 * k + 1]), ref[k]), (rep, inst.name)
+                st = wos.stats_dict(keep_p[3 * k + 2])
+                assert st["walks"] == inst.x_obs.shape[0] * inst.n_walks, (rep, inst.name)
+            for k in range(len(insts)):  # eager work between the replays
+                keep_e[3 * k + 1].zero_()
+            wos.wos_build_measure_batch(ctx, jobs_e)
+            torch.cuda.synchronize()
+    finally:
+        wos.wos_plan_destroy(plan)
 
 
 # -------------------------------------------------------------------------- edge cases
@@ -1020,12 +1139,17 @@ def test_serving_truncated_svd_matches_full_svd(wos, ctx):
         print("svd_mode", mode, [(i.name, i.x_obs.shape[0], int(i.geom.gamma1_mask.sum())) for i in insts], flush=True)
         got = wos.wos_serve(ctx, reqs, res, max_inflight=4, svd_mode=mode)
         out[mode] = [(o.status, o.walks, o.rank_used,
-                      np.ctypeslib.as_array(o.u1_host, shape=(int(i.geom.gamma1_mask.sum()),)).copy(), sv.copy())
+                      np.ctypeslib.as_array(o.u1_host, shape=(int(i.geom.gamma1_mask.sum()),)).copy(), sv.copy(),
+                      o.svd_fallback)
                      for o, i, sv in zip(got, insts, svals)]
     for inst, full, tr in zip(insts, out[0], out[1]):
         assert full[0] == 0 and tr[0] == 0, inst.name
         assert full[1] == tr[1]
         assert full[2] == tr[2] == 8, (inst.name, full[2], tr[2])
+        if tr[5]:  # rank 8 beyond the certified triplets: served by the full SVD
+            print(inst.name, "served by the full SVD", flush=True)
+            assert np.array_equal(tr[3], full[3]) and np.array_equal(tr[4], full[4]), inst.name
+            continue
         k = len(full[4])
         kt = min(k, 64 if k <= 64 else 128)
         np.testing.assert_allclose(tr[4][:8], full[4][:8], rtol=1e-8, err_msg=inst.name)
@@ -1034,6 +1158,44 @@ def test_serving_truncated_svd_matches_full_svd(wos, ctx):
         d = np.linalg.norm(tr[3] - full[3]) / np.linalg.norm(full[3])
         print(inst.name, "k", k, "u1 rel diff %.2e" % d, flush=True)
         assert d < 1e-4, (inst.name, d)
+
+
+@pytest.mark.parametrize("svd_mode", [0, 1])
+def test_served_reconstruction_matches_oracle_on_the_same_counts(wos, ctx, svd_mode):
+    """Served results against the oracle at the discrepancy rank (TSVD, tau = 1.1, the noise level of
+    each request).  A request's walks do not depend on the launch, so wos_build_measure of the same
+    instance gives the counts it was served from; the oracle assembles them and solves with LAPACK's
+    SVD and its own discrepancy rule.  The served rank must equal the oracle's and u1 agree to 1e-6
+    relative: with the full SVD (svd_mode 0), and with the truncated one (svd_mode 1), which uses
+    only its certified leading triplets (residual <= 2^-35 s_1) and sends a request whose rank needs
+    more to the full SVD (svd_fallback)."""
+    rng = np.random.default_rng(61 + svd_mode)
+    insts = [wi.random_instance(rng, i, walk_scale=0.05) for i in range(8)]
+    for inst in insts:
+        inst.x_obs, inst.uD = inst.x_obs[:400], inst.uD[:400]
+    reqs, res, keep = _requests(wos, insts, np.zeros(len(insts)))
+    out = wos.wos_serve(ctx, reqs, res, max_inflight=4, svd_mode=svd_mode)
+    worst, fallbacks = 0.0, 0
+    for k, (inst, o) in enumerate(zip(insts, out)):
+        g1 = inst.geom.gamma1_mask.astype(bool)
+        assert o.status == 0, inst.name
+        assert o.walks == inst.x_obs.shape[0] * inst.n_walks
+        assert o.svd_fallback in (0, 1) and (svd_mode == 1 or o.svd_fallback == 0)
+        fallbacks += o.svd_fallback
+        served = keep[6 * k + 5]
+        counts, _, _ = _gpu(wos, ctx, inst)
+        sigma = ow.element_measures(inst.geom)
+        a = ol.assemble(counts, inst.n_walks, inst.geom.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+        U, s, Vt = ol.svd(a["B"])
+        u1r, rr, _ = ol.reconstruct(U, s, Vt, sigma[g1], a["q"], kind=ol.TSVD_DISCREPANCY,
+                                    delta=inst.noise_delta, tau=1.1)
+        rel = float(np.linalg.norm(served - u1r) / np.linalg.norm(u1r))
+        worst = max(worst, rel)
+        print(f"{inst.name}: {inst.x_obs.shape[0]} x {int(g1.sum())}, N {inst.n_walks}, rank served "
+              f"{o.rank_used} oracle {rr}, fallback {o.svd_fallback}, u1 rel diff {rel:.2e}", flush=True)
+        assert o.rank_used == rr, inst.name
+        assert rel <= 1e-6, inst.name
+    print(f"svd_mode {svd_mode}: worst u1 rel diff {worst:.2e}, {fallbacks} of {len(insts)} served by the full SVD")
 
 
 def test_serving_truncated_svd_rejects_bad_mode(wos, ctx):

@@ -608,6 +608,47 @@ def _inside_polygon(P, V):
     return inside
 
 
+def _in_l_shape(P):
+    """Closed-form membership in the L-shape (0, 1)^2 minus [0.5, 1) x [0.5, 1)."""
+    x, y = P[:, 0], P[:, 1]
+    return (x > 0) & (x < 1) & (y > 0) & (y < 1) & ~((x >= 0.5) & (y >= 0.5))
+
+
+def test_polygon_distance_is_signed():
+    """The polygon's distance is negative outside D (a start point there stops at once and counts as
+    an escape): its sign against the closed-form membership of the L-shape, its magnitude against the
+    nearest of dense boundary samples, on points around the shape and in its notch."""
+    g = wi.Geometry(2, wi.POLYGON, (), (50,), verts=wi.L_SHAPE)
+    rng = np.random.default_rng(21)
+    P = rng.uniform(-0.4, 1.4, size=(4000, 2))
+    bp, _ = _boundary_samples(g, 400_000)
+    dmin, _ = cKDTree(bp).query(P)
+    keep = dmin > 1e-4  # the sign is only defined away from the boundary
+    P, dmin = P[keep], dmin[keep]
+    d, _ = walks.geom_eval(g, P)
+    inside = _in_l_shape(P)
+    assert inside.sum() > 500 and (~inside).sum() > 500
+    assert np.array_equal(d > 0, inside)
+    assert np.max(np.abs(np.abs(d) - dmin)) <= 2e-5
+
+
+def test_walks_from_outside_the_polygon_stop_at_once_as_escapes():
+    """Start points outside D (the notch, beyond an edge, beyond a corner) stop with zero steps in the
+    cell of their projection and count as escapes; the start points inside walk as usual."""
+    g = wi.Geometry(2, wi.POLYGON, (), (50,), verts=wi.L_SHAPE)
+    x = np.array([[0.75, 0.75], [1.2, 0.3], [-0.1, -0.2], [0.501, 0.9], [0.25, 0.25], [0.8, 0.2]])
+    out = ~_in_l_shape(x)
+    assert out.tolist() == [True, True, True, True, False, False]
+    inst = wi.Instance(g, np.array([[1.0, 0.5], [0.5, 2.0]]), x, 200, eps=1e-4, seed=77, precision=wi.FP64)
+    c, st, tr = walks.build_instance(inst, trace=True)
+    _, e_proj = walks.geom_eval(g, x)
+    assert np.all(tr[out, :, 1] == 0)
+    assert np.all(tr[out, :, 0] == e_proj[out][:, None])
+    assert st["escapes"] == out.sum() * 200
+    assert np.all(tr[~out, :, 1] > 0)
+    assert np.all(c.sum(1) == 200)
+
+
 def test_polygon_mapped_exact_radius_is_the_largest_inscribed():
     """Mapped-exact radius on the L-shape: the ellipsoid x + r S B(0,1) shrunk by 1e-9 lies inside
     the polygon (brute force over its boundary), and a dense sampling of the polygon's edges finds a
