@@ -201,8 +201,8 @@ def test_fp32_disk_vs_poisson_kernel_and_oracle(wos, ctx):
 
 
 def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
-    """The benchmark workload (1024 x 1e5, FP32 geometry) against the FP64 path on every entry
-    and against oracle rows."""
+    """The 1024 x 1e5 annulus workload with FP32 geometry against the FP64 path and against an
+    independent-seed oracle run, both on all 262144 entries (exact two-sample tests)."""
     inst = wi.cfg2_annulus(precision=wi.FP32_GEOM_FP64_EXIT)
     c32, st, _ = _gpu(wos, ctx, inst)
     assert np.all(c32.sum(1) == inst.n_walks) and st["escapes"] == 0 and st["cap_hits"] == 0
@@ -210,11 +210,11 @@ def test_fp32_full_size_annulus_vs_fp64_and_oracle(wos, ctx):
     rep = statutil.two_sample(c32, inst.n_walks, c64, inst.n_walks)
     print("FP32 vs FP64, 262144 entries", rep)
     assert rep["ok"]
-    rows = [3, 700]
-    cr, _, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs[rows], inst.eps, seed=inst.seed + 1,
-                                walk_end=inst.n_walks, point_ids=rows)
-    rep2 = statutil.two_sample(c32[rows], inst.n_walks, cr, inst.n_walks)
-    print("FP32 vs independent oracle rows", rep2)
+    cr, sr, _ = ow.build_measure(inst.geom, inst.K, inst.x_obs, inst.eps, seed=inst.seed + 1,
+                                 walk_end=inst.n_walks)
+    assert np.all(cr.sum(1) == inst.n_walks) and sr["escapes"] == 0
+    rep2 = statutil.two_sample(c32, inst.n_walks, cr, inst.n_walks)
+    print("FP32 vs independent-seed oracle, 262144 entries", rep2)
     assert rep2["ok"]
 
 
@@ -534,6 +534,117 @@ def test_batch_plan_replays_equal_eager_batch(wos, ctx):
             torch.cuda.synchronize()
     finally:
         wos.wos_plan_destroy(plan)
+
+
+# -------------------------------------------------------------------------- spectra and replicates
+
+def _device_spectrum(wos, ctx, inst):
+    """Device counts of an instance, then the device SVD of its B: (counts as numpy, s)."""
+    counts, _, _, _ = wos.run_measure(ctx, inst)
+    sigma = wos.wos_element_measures(inst.geom)
+    h = wos.wos_svd_create(ctx, inst.x_obs.shape[0], inst.geom.n_elem, inst.geom.gamma1_mask, sigma)
+    try:
+        wos.wos_svd(ctx, h, counts, inst.n_walks)
+        torch.cuda.synchronize()
+        _, s, _ = wos.svd_factors_numpy(h)
+    finally:
+        wos.wos_svd_destroy(ctx, h)
+    return _np(counts), s
+
+
+def test_concentric_annulus_device_spectrum_comes_in_pairs(wos, ctx):
+    """Section 5.2: on the concentric annulus (K = I, 24 points evenly spaced on the circle of radius
+    0.7, 24 inner arcs as Gamma_1, 40 outer arcs) the spectrum of Lambda^nu pairs up (rotations and
+    reflections commute with it).  Device counts (1e6 walks per point) and the device SVD: every
+    singular value lies within the Weyl bound |s_i(B + E) - s_i(B)| <= |E|_2 of the closed-form
+    spectrum, |E|_2 taken as twice the norm of the difference of two independent device runs (about
+    2.8 times its expected size), so modes 1 .. 11 pair up and modes 0 and 12 stay single."""
+    m = 24
+    t = 2 * np.pi * np.arange(m) / m
+    x = 0.7 * np.stack([np.cos(t), np.sin(t)], 1)
+    g = wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.5, 1.0), (40, m))
+    g.gamma1_mask = np.concatenate([np.zeros(40, np.uint8), np.ones(m, np.uint8)])
+    P = np.stack([cf.annulus_arc_measures(p, 0.5, 1.0, 40, m) for p in x])
+    sigma = np.concatenate([np.full(40, 2 * np.pi / 40), np.full(m, 2 * np.pi * 0.5 / m)])
+    _, s_ex, _ = ol.svd(ol.assemble(P, 1.0, g.gamma1_mask, sigma)["B"])
+    n = 1_000_000
+    runs = []
+    for seed in (11, 12):
+        inst = wi.Instance(g, np.eye(2), x, n, eps=1e-7, seed=seed, precision=wi.FP64)
+        c, s_dev = _device_spectrum(wos, ctx, inst)
+        assert np.all(c.sum(1) == n)
+        runs.append((c, s_dev))
+    B1, B2 = (ol.assemble(c, n, g.gamma1_mask, sigma)["B"] for c, _ in runs)
+    e = 2.0 * np.linalg.norm(B1 - B2, 2)
+    s_dev = runs[0][1]
+    print(f"annulus spectrum: |E| bound {e:.2e} ({e / s_ex[0]:.1e} s1); max |s_dev - s_exact| "
+          f"{np.abs(s_dev - s_ex).max():.2e}; exact gaps between pairs >= "
+          f"{np.min(s_ex[1:-1].reshape(-1, 2)[:-1, 1] - s_ex[1:-1].reshape(-1, 2)[1:, 0]):.2e}")
+    assert np.all(np.abs(s_dev - s_ex) <= e)
+    # the exact spectrum pairs (the structure the bound transfers to the device spectrum)
+    pairs_ex = s_ex[1:-1].reshape(-1, 2)
+    assert np.all(np.abs(pairs_ex[:, 0] - pairs_ex[:, 1]) <= 1e-10 * s_ex[0])
+    pairs = s_dev[1:-1].reshape(-1, 2)
+    assert np.all(np.abs(pairs[:, 0] - pairs[:, 1]) <= 2 * e)
+    # the leading pairs are resolved from each other and from mode 0
+    for i in range(3):
+        assert pairs[i, 1] - pairs[i + 1, 0] > 2 * e
+    assert s_dev[0] - pairs[0, 0] > 2 * e
+
+
+def test_concentric_shell_device_spectrum_groups(wos, ctx):
+    """Section 5.3, Example 6 (unit ball minus the concentric ball of radius 0.5, K = I, 100 points on
+    Bauer's spiral at radius 0.95, Gamma_1 = the inner sphere's 100 Voronoi cells of Bauer nodes):
+    spherical harmonics of degree l diagonalise the continuum operator, so the spectrum comes in
+    groups of 2l + 1 = 1, 3, 5, 7 values whose levels follow the shell's radial factor
+    a_l = (rho^-(l+1) - rho^l) / (r^-(l+1) - r^l) at rho = 0.95, r = 0.5 (singular values a_l / sqrt(pi)).
+    Device counts (2e5 walks per point, eps = 1e-10) and the device SVD: each group sits within 10 %
+    of s_0 a_l / a_0, and every group lies strictly above the next."""
+    inst = wi.spherical_shell_example(6, n_walks=200_000)
+    c, s_dev = _device_spectrum(wos, ctx, inst)
+    assert np.all(c.sum(1) == inst.n_walks)
+    a = np.array([(0.95 ** -(l + 1) - 0.95 ** l) / (0.5 ** -(l + 1) - 0.5 ** l) for l in range(4)])
+    print(f"shell: s_0 {s_dev[0]:.5f} (continuum {a[0] / np.sqrt(np.pi):.5f}); groups / s_0:",
+          [np.round(s_dev[l * l:(l + 1) ** 2] / s_dev[0], 3).tolist() for l in range(4)])
+    assert abs(s_dev[0] - a[0] / np.sqrt(np.pi)) <= 0.05 * a[0] / np.sqrt(np.pi)
+    for l in range(4):
+        grp = s_dev[l * l:(l + 1) ** 2]  # 2l + 1 values
+        assert np.all(np.abs(grp / s_dev[0] - a[l] / a[0]) <= 0.10), (l, grp / s_dev[0])
+        if l < 3:
+            assert grp.min() > s_dev[(l + 1) ** 2:(l + 2) ** 2].max(), l
+
+
+def test_ten_replicates_have_binomial_variance(wos, ctx):
+    """The replicate protocol of the Section 5.2 / 5.3 figures: 10 i.i.d. replicates of H (seeds
+    1 .. 10) on an annulus workload (64 points x 256 arcs, 1e4 walks, FP32 geometry).  Each entry's
+    sample variance over the replicates has expectation p (1 - p) / N; the pooled ratio of sample to
+    binomial variance (p from the pooled mean) must be 1 within 5 of its standard deviations, the
+    replicate means must agree with the oracle (two-sample test on the pooled counts), and no two
+    replicates may share a row."""
+    base = wi.cfg2_annulus(n_walks=10_000, n_obs=64)
+    n, R = base.n_walks, 10
+    reps = []
+    for seed in range(1, R + 1):
+        inst = wi.Instance(base.geom, base.K, base.x_obs, n, eps=base.eps, seed=seed, precision=base.precision)
+        c, _, _ = _gpu(wos, ctx, inst)
+        assert np.all(c.sum(1) == n)
+        reps.append(c.astype(np.float64) / n)
+    F = np.stack(reps)  # R x points x cells
+    for i in range(R):
+        for j in range(i):
+            assert not np.any(np.all(F[i] == F[j], axis=1)), (i, j)
+    ph = F.mean(0)
+    keep = ph > 0
+    s2 = F.var(0, ddof=1)[keep]
+    sig2 = (ph * (1 - ph) / n)[keep]
+    ratio = s2.sum() / sig2.sum()
+    sd = np.sqrt(np.sum(2 * sig2 ** 2 / (R - 1))) / sig2.sum()
+    print(f"replicates: variance ratio {ratio:.4f} (sd {sd:.4f}) over {int(keep.sum())} entries")
+    assert abs(ratio - 1.0) <= 5 * sd
+    cr, _, _ = ow.build_measure(base.geom, base.K, base.x_obs, base.eps, seed=99, walk_end=n * R // 2)
+    rep = statutil.two_sample(np.rint(ph * n * R).astype(np.int64), n * R, cr, n * R // 2)
+    print("pooled replicates vs oracle", rep)
+    assert rep["ok"]
 
 
 # -------------------------------------------------------------------------- edge cases
