@@ -45,8 +45,10 @@ OPS_PER_STEP_3D_FP32 = 40 + 6 + 10 + 18 + 1 + 12 + 11 + 5
 # Per walk: FP64 projection onto the boundary, cell index and LDS histogram (2D arc 30; 3D box
 # face selection and patch index 40).
 OPS_PER_WALK_2D, OPS_PER_WALK_3D = 30, 40
-# MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 lane-ops/s (the published
+# FP32 vector rate, 157.3 TFLOP/s, counts an FMA as two flops; here an FMA is one op).  Integer
+# 32 x 32 -> 64 multiplies (Philox) and transcendentals issue at a quarter of that rate.
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 # MI355X FP64 vector peak (published): 78.6 TFLOP/s (one FP64 FMA per lane per clock).
 FP64_PEAK_FLOPS = 78.6e12
 
@@ -114,8 +116,8 @@ def parse():
     p.add_argument("--serve-only", action="store_true", help="only the serving measurement (for profiling)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU sample")
     p.add_argument("--kernel-only", action="store_true",
-                   help="for counter collection: one 1 GiB device copy (calibration), then the workload's walk "
-                        "kernel and SVD --steps times")
+                   help="for counter collection: one 1 GiB device copy (calibration), the workload's walk kernel "
+                        "in FP64 and in FP32, then the SVD --steps times")
     return p.parse_args()
 
 
@@ -378,6 +380,9 @@ def bench_cube(a, wos, wi, torch):
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        wos.wos_build_measure(ctx, g, wos.walk_params_of(inst, precision=wi.FP64), x, n_obs, counts, stats, None,
+                              stream)
+        counts.zero_()
         wos.wos_build_measure(ctx, g, wp, x, n_obs, counts, stats, None, stream)
         for _ in range(steps):
             wos.wos_svd(ctx, h, counts, inst.n_walks, stream)
