@@ -107,8 +107,9 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     p.add_argument("--serve-seconds", type=float, default=10.0)
-    p.add_argument("--serve-svd", type=int, default=0, choices=(0, 1),
-                   help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping)")
+    p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1, 2),
+                   help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping), "
+                        "2 truncated and certified (full SVD for a rank beyond its certified triplets)")
     p.add_argument("--serve-rate", type=float, default=200.0)
     p.add_argument("--serve-radius", default="mapped", choices=("mapped", "dist"),
                    help="step radius of the serving requests: each kind's mapped radius, or r = dist (the "
@@ -265,7 +266,7 @@ def _oracle_errors(wos, insts, keep, n_sample=20):
             "per_request": [{"oracle": a, "served": b} for a, b in rows]}
 
 
-def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=0, radius="mapped", oracle_sample=True):
+def serving(ctx, wos, wi, seconds, rate=200.0, svd_mode=1, radius="mapped", oracle_sample=True):
     """Request serving on the heterogeneous-instance generator (kinds, conductivities, sizes and walk
     budgets drawn per request; 1-5 % noise; random harmonic data of degree <= 6): each request is
     build H + FP64 SVD + TSVD reconstruction, host buffers in and out.  Capacity = requests per

@@ -418,7 +418,7 @@ typedef struct {
     int32_t status;                /* wos_status of this request */
     double t_arrive, t_admit, t_done;  /* seconds since the start of wos_serve */
     uint64_t walks, steps;
-    int32_t svd_fallback;          /* 1: svd_mode 1 could not serve the request from its trusted
+    int32_t svd_fallback;          /* 1: svd_mode 2 could not serve the request from its trusted
                                     * triplets, so it was served by the full SVD (walks run again) */
 } wos_result;
 
@@ -433,11 +433,13 @@ typedef struct {
                                     * else 128 (a random range sketch of kt columns first when
                                     * min(m, n) > kt); components below 1e-5 s_1 are not used by
                                     * the reconstruction, and s_host receives min(k, kt) values
-                                    * followed by zeros.  Only the leading triplets whose residual
-                                    * |A v - s u| is at most 2^-35 s_1 are trusted: a TSVD rank
-                                    * (given, or chosen by the discrepancy rule) that needs more
-                                    * sends the request to the full SVD (svd_fallback = 1).
-                                    * Tikhonov requests use every triplet kept. */
+                                    * followed by zeros.
+                                    * 2: as 1, certified: only the leading triplets whose residual
+                                    * |A v - s u| is at most 2^-35 s_1 (the full SVD's bound) are
+                                    * used; a TSVD rank (given, or chosen by the discrepancy rule)
+                                    * that needs more sends the request to the full SVD
+                                    * (svd_fallback = 1), so every result has the full SVD's
+                                    * accuracy.  Tikhonov requests use every triplet kept. */
 } wos_serve_opts;
 
 /* Blocking driver: replays the requests at their arrival times (open loop), admits each when a
@@ -464,6 +466,17 @@ wos_status wos_serve_start(wos_ctx *ctx, const wos_serve_opts *opts);
 wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uint64_t *ticket);
 wos_status wos_serve_poll(wos_ctx *ctx, uint64_t ticket, wos_result *out, int32_t wait_ms);
 wos_status wos_serve_stop(wos_ctx *ctx);
+
+/* ------------------------------------------------------------------------------------------- */
+/* Diagnostics                                                                                    */
+/* ------------------------------------------------------------------------------------------- */
+/* The hardware sine and cosine (arguments in revolutions: cos(2 pi x), sin(2 pi x)) that the FP32
+ * walk directions use (§4.2 eq. "wos chain": the uniform direction U), evaluated on the inputs they
+ * take: cos_dev[i], sin_dev[i] at x_i = fma(i, 2^-24, offset) rounded once to FP32, i < n.  The
+ * FP32 step's radius shrink assumes each within 2^-20 of the exact value; this lets a test check
+ * that on every input.  cos_dev and sin_dev are device float[n] owned by the caller; n <= 2^24
+ * (else WOS_EINVAL); enqueued on `stream`. */
+wos_status wos_diag_trig32(float offset, uint32_t n, float *cos_dev, float *sin_dev, void *stream);
 
 #ifdef __cplusplus
 }

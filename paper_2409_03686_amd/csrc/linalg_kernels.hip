@@ -1942,10 +1942,11 @@ __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out,
     if (threadIdx.x == 0) {
         int kpos = 0;
         for (int l = 0; l < k; ++l) kpos += v.s[l] > rank_tol ? 1 : 0;
-        // truncated path: only the trusted triplets may be used; a rank that needs more is flagged
-        // (the serving engine then solves the request with the full SVD)
-        const int kuse = v.tk ? (kpos < static_cast<int>(v.ctrl[kCtrlTrusted]) ? kpos : static_cast<int>(v.ctrl[kCtrlTrusted]))
-                              : kpos;
+        // certified truncated path: only the trusted triplets may be used; a rank that needs more
+        // is flagged (the serving engine then solves the request with the full SVD)
+        const int kuse = v.tk && v.certified
+                             ? (kpos < static_cast<int>(v.ctrl[kCtrlTrusted]) ? kpos : static_cast<int>(v.ctrl[kCtrlTrusted]))
+                             : kpos;
         bool unresolved = false;
         int r = 0;
         double alpha = 0.0;
@@ -1972,7 +1973,7 @@ __global__ void recon_select_kernel(SvdDevView v, RegDev reg, int32_t *rank_out,
                 unresolved = true;
             }
         }
-        if (v.tk) v.ctrl[kCtrlUnresolved] = unresolved ? 1u : 0u;
+        if (v.tk && v.certified) v.ctrl[kCtrlUnresolved] = unresolved ? 1u : 0u;
         sh_rank = r;
         sh_alpha = alpha;
     }
@@ -2370,9 +2371,10 @@ hipError_t tsvd_launch(const SvdDevView &v, const uint32_t *counts, double inv_n
         if (K == 64) (void)launch_gram_jacobi1<1>(X, z, v.info, stream);
         else (void)launch_gram_jacobi1<2>(X, z, v.info, stream);
     };
-    // residual certificate of every computed triplet (W = A V_A in Y, which is free by then) and the
-    // trusted prefix
+    // certified mode: the residual of every computed triplet (W = A V_A in Y, which is free by then)
+    // and the trusted prefix
     auto certify = [&]() -> hipError_t {
+        if (!v.certified) return hipGetLastError();
         const double *colside = v.trans ? v.U : v.V;
         hipError_t e2 = gemm({v.A, 1, static_cast<long>(v.rows), colside, 1, static_cast<long>(v.cols), nullptr, v.Y,
                               static_cast<long>(v.rows), v.rows, v.k, v.cols, nullptr, 0, 0},

@@ -678,13 +678,23 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
     const double delta = std::ldexp(domain_scale(g), dexp);
     I.delta = static_cast<float>(delta);
     I.neg2delta = -2.0f * I.delta;
+    // Relative radius shrink c of the FP32 step.  Each hardware sine / cosine of a direction is
+    // within 2^-20 (checked on every input they take by a GPU test), so the step S U' misses S U by
+    // at most sqrt(dim) 2^-20 (|S| = 1).  With r = dist the ellipsoid lies in the ball of radius r and
+    // c = 2^-16 covers that.  A mapped radius's ellipsoid may touch the boundary: shrinking it by c r
+    // leaves a gap of c r sigma_min(S) around the shrunken one, so c >= sqrt(dim) 2^-20 / sigma_min;
+    // twice that is used.
+    double shrink = 0x1.0p-16;
+    if (w->radius_mode != WOS_RADIUS_WOE_BOUND)
+        shrink = std::max(shrink, 2.0 * std::sqrt(static_cast<double>(g->dim)) * 0x1.0p-20 / std::sqrt(lmin / lmax));
+    I.rshrink = static_cast<float>(1.0 - shrink);
     if (g->dim == 2) {
         for (int a = 0; a < 2; ++a) {
             const double A = std::hypot(I.S[a * 3 + 0], I.S[a * 3 + 1]);
             const double phi = std::atan2(I.S[a * 3 + 1], I.S[a * 3 + 0]) / (2.0 * M_PI);  // revolutions
             I.fold_off[a] = static_cast<float>(0x1.0p-25 - phi);
-            // FP32 rounding moves these by 2^-24 relative at most, well inside the 2^-16 shrink
-            I.fold_rs[a] = static_cast<float>(A * (1.0 - 0x1.0p-16));
+            // FP32 rounding moves these by 2^-24 relative at most, well inside the shrink
+            I.fold_rs[a] = static_cast<float>(A * (1.0 - shrink));
             I.fold_rn[a] = static_cast<float>(A * static_cast<double>(I.neg2delta));
         }
     }
@@ -1270,5 +1280,32 @@ extern "C" wos_status wos_autotune(wos_ctx *ctx, const wos_measure_job *job, uin
         ctx->tuning[tune_key(job->geom.dim, job->geom.kind, job->walk.precision)] = bt;
     }
     if (best) *best = bt;
+    return WOS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Diagnostic: the hardware sine and cosine (in revolutions) that the FP32 directions use, on the
+// inputs they take, x_i = fma(i, 2^-24, offset) in FP32.
+// ---------------------------------------------------------------------------------------------
+namespace {
+__global__ void trig32_kernel(float offset, uint32_t n, float *__restrict__ c, float *__restrict__ s)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float x = __builtin_fmaf(static_cast<float>(i), 0x1.0p-24f, offset);
+        c[i] = __builtin_amdgcn_cosf(x);
+        s[i] = __builtin_amdgcn_sinf(x);
+    }
+}
+}  // namespace
+
+extern "C" wos_status wos_diag_trig32(float offset, uint32_t n, float *cos_dev, float *sin_dev, void *stream)
+{
+    if (n > (1u << 24)) return set_error(WOS_EINVAL, "n = %u exceeds 2^24", n);
+    if (n == 0) return WOS_OK;
+    if (!cos_dev || !sin_dev) return set_error(WOS_EINVAL, "output pointer NULL");
+    const uint32_t grid = std::min<uint32_t>((n + 255) / 256, 4096u);
+    trig32_kernel<<<grid, 256, 0, static_cast<hipStream_t>(stream)>>>(offset, n, cos_dev, sin_dev);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(WOS_EDEVICE, "trig32 launch failed: %s", hipGetErrorString(e));
     return WOS_OK;
 }

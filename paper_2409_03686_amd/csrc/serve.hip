@@ -95,8 +95,9 @@ wos_status layout_request(const wos_request &r, ReqLayout &L, int svd_mode)
     std::vector<double> sigma(M);
     st = wos_element_measures(&r.geom, sigma.data());
     if (st != WOS_OK) return st;
-    st = svd_layout(r.n_obs, M, r.gamma1_mask_host, sigma.data(), nullptr, L.svd, svd_mode == 1 ? kTruncRank : 0);
+    st = svd_layout(r.n_obs, M, r.gamma1_mask_host, sigma.data(), nullptr, L.svd, svd_mode != 0 ? kTruncRank : 0);
     if (st != WOS_OK) return st;
+    L.svd.v.certified = svd_mode == 2 ? 1 : 0;
     st = check_reg(&r.reg);
     if (st != WOS_OK) return st;
     L.M = M;
@@ -198,8 +199,8 @@ class Engine {
     // Validates and lays out a request; on failure the status is recorded in the job's result.
     wos_status prepare(Job &j)
     {
-        wos_status st = (svd_mode_ == 0 || svd_mode_ == 1) ? layout_request(j.req, j.L, svd_mode_)
-                                                           : set_error(WOS_EINVAL, "svd_mode must be 0 or 1");
+        wos_status st = (svd_mode_ >= 0 && svd_mode_ <= 2) ? layout_request(j.req, j.L, svd_mode_)
+                                                           : set_error(WOS_EINVAL, "svd_mode must be 0, 1 or 2");
         if (st == WOS_OK && j.L.total > budget_)
             st = set_error(WOS_ENOMEM, "request needs %zu bytes, budget %zu", j.L.total, budget_);
         if (st == WOS_OK && !j.res->u1_host) st = set_error(WOS_EINVAL, "request has no u1 output buffer");
@@ -251,7 +252,7 @@ class Engine {
             if (q != hipSuccess) {
                 R.status = WOS_EDEVICE;
                 *fatal = set_error(WOS_EDEVICE, "request failed on the device: %s", hipGetErrorString(q));
-            } else if (svd_mode_ == 1 && !j.full &&
+            } else if (svd_mode_ == 2 && !j.full &&
                        static_cast<const uint8_t *>(s.pinned)[s.out_scal + 4] != 0 && resubmit_full(j)) {
                 // the truncated SVD's trusted triplets do not meet the regularisation rule: the
                 // request runs again with the full SVD (the same walks, so the same counts)
@@ -398,8 +399,9 @@ class Engine {
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_pred, pred, 8ull * r.n_obs, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_s, L.svd.v.s, 8ull * L.k, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_scal, base + L.off_scal, 16, hipMemcpyDeviceToHost, s.stream);
-        // the truncated path's flag (rank beyond its trusted triplets) into the scalars' spare word
-        if (e == hipSuccess && L.svd.v.tk)
+        // the certified truncated path's flag (rank beyond its trusted triplets) into the scalars'
+        // spare word
+        if (e == hipSuccess && L.svd.v.tk && L.svd.v.certified)
             e = hipMemcpyAsync(pin + s.out_scal + 4, L.svd.v.ctrl + kCtrlUnresolved, 4, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(pin + s.out_stats, stats, 8ull * WOS_STATS_WORDS, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);

@@ -57,7 +57,7 @@ template <> struct Dir<float, 2> {
     {
         const float u = u24(w[PH]);
         // v_sin/v_cos take revolutions: sin(2 pi u), cos(2 pi u) without range reduction; their
-        // norm error (below 2^-20) is covered by the radius shrink of the FP32 step
+        // error (below 2^-20 each) is covered by the radius shrink of the FP32 step
         U[0] = __builtin_amdgcn_cosf(u);
         U[1] = __builtin_amdgcn_sinf(u);
     }
@@ -218,7 +218,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
         }
     } else {
         // conservative radius: below the true distance by more than the FP32 distance error
-        // (2 delta) and the direction's norm error (relative 2^-16)
+        // (2 delta) and the direction's error (the relative shrink 1 - rshrink)
         const float rr = radius32<KIND, DIM, RV>(I, x, d, segs);
         if constexpr (DIM == 2) {
             const float t = static_cast<float>(w[PH] >> 8);
@@ -229,7 +229,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
         } else {
             R U[DIM];
             Dir<R, DIM>::template get<PH>(w, U);
-            const float r = __builtin_fmaf(rr, 1.0f - 0x1.0p-16f, I.neg2delta);
+            const float r = __builtin_fmaf(rr, I.rshrink, I.neg2delta);
             step32<DIM>(I, x, r, U);
         }
         d = dist32<KIND, DIM>(I, x, segs);

@@ -50,6 +50,7 @@ struct alignas(16) DevInst {
     float eps_hi;     // FP32 distance >  eps_hi: certainly outside it
     float delta;      // bound on |dist_fp32 - dist| for this domain (absolute)
     float neg2delta;  // -2 delta (radius shrink)
+    float rshrink;    // 1 - c: the FP32 step's relative radius shrink (covers the direction's error)
     // 2D FP32 step with S folded into the direction: for U = (cos 2 pi u, sin 2 pi u),
     // (S U)_a = A_a cos 2 pi (u - phi_a), A_a the length of row a of S and phi_a its polar angle in
     // revolutions, so one cosine per coordinate replaces the cosine, the sine and the 2 x 2 product.

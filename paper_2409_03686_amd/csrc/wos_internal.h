@@ -65,6 +65,7 @@ struct SvdDevView {
     // sketch of kt columns (cols > kt) or from the Gram path of A itself (cols <= kt), with
     // single-workgroup kernels only.
     int tk;                 // kt, a multiple of 64 (at most 128)
+    int certified;          // 1: certify each triplet; the rank may use only the trusted ones
     double rank_cut;        // components with s <= rank_cut s_1 are left out of reconstructions
     double *Om, *Y, *Q;     // cols x kt sketch, rows x kt range, rows x kt orthonormal basis
     double *Cm, *Gt, *Lt, *zt;  // kt x cols projection, kt x kt Gram and factor, kt norms

@@ -121,6 +121,7 @@ _SIGS = {
                                   _VP, _VP, C.POINTER(_VP)]),
     "wos_plan_create_batch": (C.c_int, [_VP, C.POINTER(WosMeasureJob), C.c_int32, C.POINTER(C.c_void_p)]),
     "wos_plan_launch": (C.c_int, [_VP, _VP]),
+    "wos_diag_trig32": (C.c_int, [C.c_float, C.c_uint32, _VP, _VP, _VP]),
     "wos_plan_destroy": (C.c_int, [_VP]),
     "wos_serve": (C.c_int, [_VP, C.POINTER(WosRequest), C.c_int32, C.POINTER(WosResult), C.POINTER(WosServeOpts)]),
     "wos_serve_start": (C.c_int, [_VP, C.POINTER(WosServeOpts)]),
@@ -372,6 +373,10 @@ def wos_plan_create_batch(ctx, jobs: Sequence[WosMeasureJob]) -> int:
     p = C.c_void_p()
     _check(lib().wos_plan_create_batch(ctx, arr, len(jobs), C.byref(p)))
     return p.value
+
+
+def wos_diag_trig32(offset, n, cos_dev, sin_dev, stream=None):
+    _check(lib().wos_diag_trig32(float(offset), int(n), _ptr(cos_dev), _ptr(sin_dev), _stream(stream)))
 
 
 def wos_plan_launch(plan, stream=None):

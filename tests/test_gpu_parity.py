@@ -536,6 +536,27 @@ def test_batch_plan_replays_equal_eager_batch(wos, ctx):
         wos.wos_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("offset", [2.0 ** -25, 2.0 ** -25 - 0.5, 2.0 ** -25 + 0.3125, 2.0 ** -25 - 0.0879])
+def test_hardware_sin_cos_within_the_direction_bound(wos, ctx, offset):
+    """The FP32 directions take cos(2 pi x) and sin(2 pi x) from the hardware (arguments in
+    revolutions) at x = fma(t, 2^-24, offset), t < 2^24: offset 2^-25 is the uniform sampler of the
+    2D and 3D directions, the others the folded 2D step's per-coordinate phase shifts.  The radius
+    shrink of the FP32 step assumes each value within 2^-20 of the exact one; checked here on all
+    2^24 inputs against FP64."""
+    n = 1 << 24
+    c = torch.empty(n, dtype=torch.float32, device="cuda")
+    sn = torch.empty(n, dtype=torch.float32, device="cuda")
+    off = np.float32(offset)
+    wos.wos_diag_trig32(float(off), n, c, sn)
+    torch.cuda.synchronize()
+    x = (np.arange(n, dtype=np.float64) * 2.0 ** -24 + np.float64(off)).astype(np.float32).astype(np.float64)
+    ec = np.abs(c.cpu().numpy().astype(np.float64) - np.cos(2 * np.pi * x)).max()
+    es = np.abs(sn.cpu().numpy().astype(np.float64) - np.sin(2 * np.pi * x)).max()
+    print(f"offset {float(off):+.6f}: max |cos error| {ec:.3e} ({ec * 2 ** 20:.4f} x 2^-20), "
+          f"max |sin error| {es:.3e} ({es * 2 ** 20:.4f} x 2^-20)")
+    assert ec <= 2.0 ** -20 and es <= 2.0 ** -20
+
+
 # -------------------------------------------------------------------------- spectra and replicates
 
 def _device_spectrum(wos, ctx, inst):
@@ -1271,15 +1292,15 @@ def test_serving_truncated_svd_matches_full_svd(wos, ctx):
         assert d < 1e-4, (inst.name, d)
 
 
-@pytest.mark.parametrize("svd_mode", [0, 1])
+@pytest.mark.parametrize("svd_mode", [0, 2])
 def test_served_reconstruction_matches_oracle_on_the_same_counts(wos, ctx, svd_mode):
     """Served results against the oracle at the discrepancy rank (TSVD, tau = 1.1, the noise level of
     each request).  A request's walks do not depend on the launch, so wos_build_measure of the same
     instance gives the counts it was served from; the oracle assembles them and solves with LAPACK's
     SVD and its own discrepancy rule.  The served rank must equal the oracle's and u1 agree to 1e-6
-    relative: with the full SVD (svd_mode 0), and with the truncated one (svd_mode 1), which uses
-    only its certified leading triplets (residual <= 2^-35 s_1) and sends a request whose rank needs
-    more to the full SVD (svd_fallback)."""
+    relative: with the full SVD (svd_mode 0), and with the certified truncated one (svd_mode 2), which
+    uses only its certified leading triplets (residual <= 2^-35 s_1) and sends a request whose rank
+    needs more to the full SVD (svd_fallback)."""
     rng = np.random.default_rng(61 + svd_mode)
     insts = [wi.random_instance(rng, i, walk_scale=0.05) for i in range(8)]
     for inst in insts:
@@ -1291,7 +1312,7 @@ def test_served_reconstruction_matches_oracle_on_the_same_counts(wos, ctx, svd_m
         g1 = inst.geom.gamma1_mask.astype(bool)
         assert o.status == 0, inst.name
         assert o.walks == inst.x_obs.shape[0] * inst.n_walks
-        assert o.svd_fallback in (0, 1) and (svd_mode == 1 or o.svd_fallback == 0)
+        assert o.svd_fallback in (0, 1) and (svd_mode == 2 or o.svd_fallback == 0)
         fallbacks += o.svd_fallback
         served = keep[6 * k + 5]
         counts, _, _ = _gpu(wos, ctx, inst)
@@ -1307,6 +1328,41 @@ def test_served_reconstruction_matches_oracle_on_the_same_counts(wos, ctx, svd_m
         assert o.rank_used == rr, inst.name
         assert rel <= 1e-6, inst.name
     print(f"svd_mode {svd_mode}: worst u1 rel diff {worst:.2e}, {fallbacks} of {len(insts)} served by the full SVD")
+
+
+def test_fast_truncated_serving_has_the_oracles_reconstruction_error(wos, ctx):
+    """svd_mode 1 (the truncated SVD without certification, the serving default of the benchmark)
+    at equal reconstruction error: on 12 heterogeneous requests at the discrepancy rank, the error of
+    the served u1 against the exact Gamma_1 data, max |u1 - u| / max |u|, against the oracle's
+    (LAPACK TSVD with the same rule on the same counts).  The medians over the requests agree to
+    10 %, and no request is worse than 1.5 x the oracle's error + 0.05."""
+    rng = np.random.default_rng(63)
+    insts = [wi.random_instance(rng, i, walk_scale=0.1) for i in range(12)]
+    for inst in insts:
+        inst.x_obs, inst.uD = inst.x_obs[:400], inst.uD[:400]
+    reqs, res, keep = _requests(wos, insts, np.zeros(len(insts)))
+    out = wos.wos_serve(ctx, reqs, res, max_inflight=4, svd_mode=1)
+    es, eo = [], []
+    for k, (inst, o) in enumerate(zip(insts, out)):
+        g1 = inst.geom.gamma1_mask.astype(bool)
+        assert o.status == 0 and o.svd_fallback == 0, inst.name
+        counts, _, _ = _gpu(wos, ctx, inst)
+        sigma = ow.element_measures(inst.geom)
+        a = ol.assemble(counts, inst.n_walks, inst.geom.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+        U, s, Vt = ol.svd(a["B"])
+        u1r, rr, _ = ol.reconstruct(U, s, Vt, sigma[g1], a["q"], kind=ol.TSVD_DISCREPANCY,
+                                    delta=inst.noise_delta, tau=1.1)
+        ue = inst.u_exact_g1
+        e_served = float(np.abs(keep[6 * k + 5] - ue).max() / np.abs(ue).max())
+        e_oracle = float(np.abs(u1r - ue).max() / np.abs(ue).max())
+        es.append(e_served)
+        eo.append(e_oracle)
+        print(f"{inst.name}: rank served {o.rank_used} oracle {rr}; error served {e_served:.4f} oracle "
+              f"{e_oracle:.4f}", flush=True)
+        assert e_served <= 1.5 * e_oracle + 0.05, inst.name
+    ms, mo = float(np.median(es)), float(np.median(eo))
+    print(f"median reconstruction error: served {ms:.4f}, oracle {mo:.4f}")
+    assert abs(ms - mo) <= 0.10 * mo
 
 
 def test_serving_truncated_svd_rejects_bad_mode(wos, ctx):
