@@ -281,6 +281,40 @@ def test_perforated_disc_example(wos, ctx):
     assert rep["ok"]
 
 
+@pytest.mark.parametrize("example", [2, 3])
+def test_paper_annulus_examples(wos, ctx, example):
+    """The paper's Examples 2 and 3 (Section 5.2): concentric annuli R_0 = 1, R_1 = 0.5 / 0.2 with
+    500 + 100 arcs and 100 points on the circle of radius 0.95, K = I.  FP64 at the paper's
+    eps = 1e-10 walk for walk against the oracle; then FP64 (eps = 1e-10) and FP32 geometry
+    (eps = 1e-5) counts at 2e4 walks per point against the closed-form arc measures of the
+    concentric annulus: every one of the 60000 entries by the exact binomial test (Bonferroni), each
+    row by a chi-square test with the cells of expected count below 5 pooled, and each point's
+    inner-circle mass by its binomial z.  (Seen from radius 0.95 most of the 600 cells expect far
+    less than one count, where the |z| > 4 tally of the other tests has Poisson, not Gaussian, tails.)"""
+    small = wi.annulus_example(example, n_walks=1000)
+    c, st, tr = _gpu(wos, ctx, small, trace=True)
+    cr, sr, trr = ow.build_instance(small, trace=True)
+    agree = _agreement(tr, trr)
+    print(f"example {example}: FP64 walk agreement {agree:.7f}, {st['steps'] / st['walks']:.1f} steps per walk")
+    assert agree >= 0.999 and np.all(c.sum(1) == small.n_walks)
+    r_in = small.geom.params[2]
+    P = np.stack([cf.annulus_arc_measures(p, r_in, 1.0, 500, 100) for p in small.x_obs])
+    assert np.allclose(P.sum(1), 1.0, atol=1e-12)
+    n = 20_000
+    for prec, eps in ((wi.FP64, 1e-10), (wi.FP32_GEOM_FP64_EXIT, 1e-5)):
+        inst = wi.annulus_example(example, n_walks=n, eps=eps, precision=prec)
+        cc, st, _ = _gpu(wos, ctx, inst)
+        # at eps = 1e-10 a step can round across the circle (the oracle's FP64 walks do too)
+        assert np.all(cc.sum(1) == n) and st["escapes"] <= 1e-4 * n * 100 and st["cap_hits"] == 0
+        rep = statutil.vs_probabilities(cc, n, P, bias=_bias_2d(P, eps))
+        chi = statutil.row_chi2(cc, n, P)
+        pin, mass = P[:, 500:].sum(1), cc[:, 500:].sum(1) / n
+        zin = np.abs(mass - pin) / np.sqrt(pin * (1 - pin) / n)
+        print(f"example {example}, precision {prec}: entries {rep}; rows {chi}; inner-circle mass "
+              f"{mass.mean():.5f} (closed form {pin.mean():.5f}), max |z| {zin.max():.2f}")
+        assert rep["min_p"] >= rep["bonferroni"] and chi["ok"] and zin.max() <= 4.5
+
+
 @pytest.mark.parametrize("example", [1, 5, 6, 7])
 def test_paper_perforated_examples(wos, ctx, example):
     """The paper's Examples 1 and 5 (the square with a hole) and 6 and 7 (the concentric and the

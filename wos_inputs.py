@@ -317,6 +317,24 @@ def bauer_spiral(n: int) -> np.ndarray:
     return np.stack([np.sin(phi) * np.cos(th), np.sin(phi) * np.sin(th), np.cos(phi)], 1)
 
 
+def annulus_example(example: int = 2, n_walks: int = 10_000, eps: float = 1e-10, precision: int = FP64,
+                    m_out: int = 500, m_in: int = 100, n_obs: int = 100) -> Instance:
+    """The paper's Examples 2 and 3 (Section 5.2): the concentric annulus between the unit circle and
+    the circle of radius 0.5 (Example 2) or 0.2 (Example 3), K = I; Gamma_0 the outer circle (m_out
+    arcs), Gamma_1 the inner one (m_in arcs); the points equally spaced from angle 0 on
+    Gamma_D = {dist(x, Gamma_0) = 0.05}, the circle of radius 0.95.  The paper: M_0 = 500, M_1 = 100,
+    M_D = 100, N = 10^6, eps = 10^-10.  Data: 2D-sol2 (as for Examples 1 and 5), without noise."""
+    r_in = {2: 0.5, 3: 0.2}[example]
+    g = Geometry(2, ANNULUS, (0.0, 0.0, r_in, 1.0), (m_out, m_in))
+    g.gamma1_mask = (np.arange(g.n_elem) >= m_out).astype(np.uint8)
+    s = 2 * np.pi * np.arange(n_obs) / n_obs
+    x = 0.95 * np.stack([np.cos(s), np.sin(s)], 1)
+    inst = Instance(g, np.eye(2), x, n_walks, eps=eps, seed=example, precision=precision,
+                    name=f"annulus_example{example}")
+    return _with_data(inst, lambda p: (-p[:, 0] ** 3 / 3 - p[:, 0] ** 2 * p[:, 1] + p[:, 0] * p[:, 1] ** 2
+                                       + p[:, 1] ** 3 / 3))
+
+
 def square_hole_example(example: int = 1, n_walks: int = 10_000, eps: Optional[float] = None,
                         precision: int = FP64, m_face: int = 100, m_hole: int = 50,
                         n_obs: int = 40) -> Instance:
