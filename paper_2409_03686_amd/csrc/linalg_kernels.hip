@@ -1383,8 +1383,9 @@ static hipError_t chol_pivoted(const SvdDevView &v, hipStream_t stream)
 // nrm.  Dot products: per-thread partials, a wave reduction that leaves pair j's sum in lane j, then
 // the four waves' sums added in a fixed order from LDS, so every wave takes the same decisions.
 // After nblk - 1 moves every block is home again.  Each sweep ends with device-wide counts of its
-// rotations and of rotations with a cosine >= 1e-8; the iteration stops after a sweep without the
-// latter (convergence is quadratic by then).  Every wait is bounded: an expired wait sets the error
+// rotations and of rotations with a cosine >= 1e-7; the iteration stops after a sweep without the
+// latter: convergence is quadratic by then, so what is left is of order 1e-14, which the first-order
+// eigenvector correction that follows this kernel reduces to rounding.  Every wait is bounded: an expired wait sets the error
 // word and the workgroups leave, the result is then rejected.  When the stream's CUs cannot hold P
 // workgroups, G < P workgroups take P / G positions each per round through memory, with a device-wide
 // barrier between rounds (same arithmetic per meeting, so the same result bit for bit).
@@ -1460,7 +1461,7 @@ __device__ __forceinline__ void gj_round(double (&x)[R][2 * BW], double *nrm_w, 
         act = gj != 0.0 && gj * gj > tol2 * a * b;
         if (act) {
             double t;
-            big = big || gj * gj >= 1e-16 * (a * b);
+            big = big || gj * gj >= 1e-14 * (a * b);  // a rotated cosine of 1e-7 or more
             rot_params(a, b, gj, c, sn, t);
             nrm_w[p] = a - t * gj;
             nrm_w[q] = b + t * gj;
