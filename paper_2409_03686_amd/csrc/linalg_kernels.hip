@@ -1759,12 +1759,14 @@ __device__ __forceinline__ double gemm_scale(const GemmArgs &g, int cj)
 // The GEMM in 64 x 64 tiles of C per 256-thread workgroup: K in chunks of 16 staged through LDS
 // (the A chunk 64 x 16 and the B chunk 16 x 64, both stored k-major), each wave computing a 32 x 32
 // quarter as 2 x 2 v_mfma_f64_16x16x4f64 tiles, so every operand fetched from L2 feeds 32 MFMA
-// products instead of one.  Chunks are loaded along the operand's unit stride (coalesced).
+// products instead of one.  Chunks are loaded along the operand's unit stride (coalesced), and the
+// next chunk is fetched into registers while the current one is multiplied from the other of two
+// LDS buffers (one barrier per chunk).
 constexpr int kTM = 64, kTK = 16;
 __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs g)
 {
-    __shared__ double As[kTK][kTM + 1];  // As[k][i]
-    __shared__ double Bs[kTK][kTM + 1];  // Bs[k][j]
+    __shared__ double As[2][kTK][kTM + 1];  // As[buf][k][i]
+    __shared__ double Bs[2][kTK][kTM + 1];  // Bs[buf][k][j]
     __shared__ int cols[kTM];
     const int mo = g.mo > g.m ? g.mo : g.m, no = g.no > g.n ? g.no : g.n;
     const int tm = (mo + kTM - 1) / kTM;
@@ -1784,28 +1786,52 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs g)
         for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
     const bool a_rows = g.sai == 1;  // A contiguous along i, else along k
     const bool b_ks = g.sbk == 1;    // B contiguous along k, else along j
-    for (int k0 = 0; k0 < g.kd; k0 += kTK) {
+    // this thread's four elements of each chunk: (k, i) of A and (k, j) of B
+    int ak[4], ai[4], bk[4], bj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ai[q] = a_rows ? (tid & 63) : (tid >> 4) + 16 * q;
+        ak[q] = a_rows ? (tid >> 6) + 4 * q : (tid & 15);
+        bj[q] = b_ks ? (tid >> 4) + 16 * q : (tid & 63);
+        bk[q] = b_ks ? (tid & 15) : (tid >> 6) + 4 * q;
+    }
+    double ra[4], rb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = a_rows ? (tid & 63) : (tid >> 4) + 16 * q;
-            const int k = a_rows ? (tid >> 6) + 4 * q : (tid & 15);
-            const int gi = i0 + i, gk = k0 + k;
-            As[k][i] = (gi < g.m && gk < g.kd) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
-            const int j = b_ks ? (tid >> 4) + 16 * q : (tid & 63);
-            const int kb = b_ks ? (tid & 15) : (tid >> 6) + 4 * q;
-            const int cj = cols[j], gkb = k0 + kb;
-            Bs[kb][j] = (cj >= 0 && gkb < g.kd) ? g.B[gkb * g.sbk + cj * g.sbj] : 0.0;
+            const int gi = i0 + ai[q], gk = k0 + ak[q];
+            ra[q] = (gi < g.m && gk < g.kd) ? g.A[gi * g.sai + gk * g.sak] : 0.0;
+            const int cj = cols[bj[q]], gkb = k0 + bk[q];
+            rb[q] = (cj >= 0 && gkb < g.kd) ? g.B[gkb * g.sbk + cj * g.sbj] : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[buf][ak[q]][ai[q]] = ra[q];
+            Bs[buf][bk[q]][bj[q]] = rb[q];
+        }
+    };
+    const int nch = (g.kd + kTK - 1) / kTK;
+    if (nch > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) fetch((c + 1) * kTK);  // in flight during the products below
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 4) {
-            const double a0 = As[kk + lk][wi + li], a1 = As[kk + lk][wi + 16 + li];
-            const double b0 = Bs[kk + lk][wj + li], b1 = Bs[kk + lk][wj + 16 + li];
+            const double a0 = As[buf][kk + lk][wi + li], a1 = As[buf][kk + lk][wi + 16 + li];
+            const double b0 = Bs[buf][kk + lk][wj + li], b1 = Bs[buf][kk + lk][wj + 16 + li];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
+        // the other buffer was last read in chunk c - 1, before the previous barrier
+        if (c + 1 < nch) stash(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
