@@ -140,9 +140,14 @@ typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
  * of the diffusion on ellipsoids inscribed in D, so any r whose ellipsoid X + r S B(0,1) lies in D
  * gives the same exit law; larger radii give shorter walks.
  *   WOE_BOUND     r = dist(X, dD), the radius of eq. "wos chain" (every domain).
- *   MAPPED_EXACT  boxes and polygons: the largest inscribed radius; for a box min over faces of
- *                 gap_a / |S e_a|, for a polygon the distance from S^{-1} X to the mapped edges
- *                 S^{-1}[a, b] (the ellipsoid is the set of z with |S^{-1}(z - X)| <= r).
+ *   MAPPED_EXACT  the largest inscribed radius, the distance from S^{-1} X to the mapped boundary
+ *                 S^{-1} dD (the ellipsoid is the set of z with |S^{-1}(z - X)| <= r): for a box min
+ *                 over faces of gap_a / |S e_a|; for a polygon the distance to the mapped edges
+ *                 S^{-1}[a, b]; for discs, annuli, balls and discs / balls with holes (FP64 geometry
+ *                 only) the distance to the mapped circles / spheres, ellipses / ellipsoids with
+ *                 semi-axes R / s_k along the eigenvectors of S (eigenvalues s_k), computed by
+ *                 Newton's method on the closest-point equation (§5.1, Remark on Alg. MC-REM,
+ *                 item (ii): a distance replaced by another valid one).
  *   MAPPED_BOUND  discs, annuli, balls, ellipses, and discs, balls and boxes with holes
  *                 (WOS_PERFORATED, WOS_PERFBOX): with v = X - c and a = |S v|,
  *                 r = sqrt(a^2 + R^2 - |v|^2) - a for the outer circle or sphere of radius R (for a

@@ -490,12 +490,134 @@ static double ellipse_mapped_bound(const og_geom *g, const double *S, const doub
     return gg / (sqrt(t * t + sig2 * gg) + t);
 }
 
+/* Eigen-decomposition of the symmetric d x d matrix S (row-major 3 x 3 storage) by cyclic Jacobi
+ * rotations: S = Q diag(ev) Q^T, column k of Q (Q[i*3+k]) the k-th eigenvector. */
+static void sym_eigen(int d, const double *S, double *Q, double *ev)
+{
+    double A[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            A[i][j] = (i < d && j < d) ? S[i * 3 + j] : 0.0;
+            Q[i * 3 + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = i + 1; j < d; ++j) off += A[i][j] * A[i][j];
+        if (off == 0.0) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (A[p][q] == 0.0) continue;
+                /* the rotation that zeroes A[p][q]: tan of the angle from the quadratic t^2 + 2 theta t - 1 = 0 */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+                if (theta < 0.0) t = -t;
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < d; ++k) {
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - sn * akq;
+                    A[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - sn * aqk;
+                    A[q][k] = sn * apk + c * aqk;
+                }
+                A[p][q] = A[q][p] = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    double qkp = Q[k * 3 + p], qkq = Q[k * 3 + q];
+                    Q[k * 3 + p] = c * qkp - sn * qkq;
+                    Q[k * 3 + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int k = 0; k < 3; ++k) ev[k] = k < d ? A[k][k] : 1.0;
+}
+
+/* Distance from y to the ellipsoid sum_i (z_i / e_i)^2 = 1 in R^d, y inside or outside.  The nearest
+ * point z is where y - z is normal to the ellipsoid: z_i = y_i e_i^2 / (e_i^2 + t) for a Lagrange
+ * parameter t with sum_i (y_i e_i / (e_i^2 + t))^2 = 1.  The left side minus one, G(t), is convex and
+ * decreasing for t > -min e_i^2, so the root is the limit of Newton's iteration started where G >= 0.
+ * If y has no component along the shortest axes and G(-min e_i^2), summed over the other axes, is
+ * <= 0, the nearest point has t = -min e_i^2, and its components along the shortest axes complete the
+ * ellipsoid equation. */
+static double ellipsoid_distance(int d, const double *e, const double *y)
+{
+    double b[3], a[3], bmin = INFINITY;
+    for (int i = 0; i < d; ++i) {
+        b[i] = e[i] * e[i];
+        a[i] = fabs(y[i]) * e[i];
+        if (b[i] < bmin) bmin = b[i];
+    }
+    double amax_short = 0.0, g_edge = -1.0;
+    for (int i = 0; i < d; ++i) {
+        if (b[i] == bmin) {
+            if (a[i] > amax_short) amax_short = a[i];
+        } else {
+            double q = a[i] / (b[i] - bmin);
+            g_edge += q * q;
+        }
+    }
+    double t;
+    if (amax_short > 0.0) {
+        t = amax_short - bmin; /* the largest shortest-axis term alone is >= 1 here */
+    } else if (g_edge > 0.0) {
+        t = -bmin;
+    } else {
+        double d2 = 0.0, used = 0.0;
+        for (int i = 0; i < d; ++i) {
+            if (b[i] == bmin) continue;
+            double z = y[i] * b[i] / (b[i] - bmin);
+            d2 += (y[i] - z) * (y[i] - z);
+            used += z * z / b[i];
+        }
+        double rest = 1.0 - used;
+        if (rest < 0.0) rest = 0.0;
+        return sqrt(d2 + bmin * rest);
+    }
+    for (int it = 0; it < 64; ++it) {
+        double g = -1.0, h = 0.0; /* G(t) and -G'(t) / 2 */
+        for (int i = 0; i < d; ++i) {
+            double q = a[i] / (b[i] + t);
+            g += q * q;
+            h += q * q / (b[i] + t);
+        }
+        if (!(g > 0.0)) break;
+        double tn = t + g / (2.0 * h);
+        if (!(tn > t)) break;
+        t = tn;
+    }
+    double d2 = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double z = y[i] * b[i] / (b[i] + t);
+        d2 += (y[i] - z) * (y[i] - z);
+    }
+    return sqrt(d2);
+}
+
+/* The distance from S^{-1} x to the image S^{-1}(c + R S^{d-1}) of the circle / sphere of centre c
+ * and radius R: in the eigenbasis of S (eigenvalues s_k) an ellipsoid with semi-axes R / s_k about
+ * S^{-1} c, and the point (Q^T (x - c))_k / s_k. */
+static double mapped_sphere_distance(int d, const double *Q, const double *ev, const double *x,
+                                     const double *c, double R)
+{
+    double w[3], e[3];
+    for (int k = 0; k < d; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < d; ++i) acc += Q[i * 3 + k] * (x[i] - c[i]);
+        w[k] = acc / ev[k];
+        e[k] = R / ev[k];
+    }
+    return ellipsoid_distance(d, e, w);
+}
+
 /* Step radius.  Any ellipsoid x + r S B(0,1) inside D is a valid step of the chain (the chain is the
  * trace of the diffusion on inscribed ellipsoids, Section 4.2); the exit law does not depend on the
  * choice.  mode 0: r = dist (the ellipsoid lies in the Euclidean ball of radius r because
- * |S| <= 1).  mode 1 (boxes, polygons): the largest r whose ellipsoid stays inside D -- for a box
- * min over faces of (face distance)/|S e_a|, for a polygon the distance of S^{-1} x to the mapped
- * edges.  mode 2 (disc, annulus, ball): the bounds above for the outer
+ * |S| <= 1).  mode 1 (boxes, polygons, discs, annuli, balls, discs and balls with holes): the
+ * largest r whose ellipsoid stays inside D, the distance of S^{-1} x to the mapped boundary -- for a
+ * box min over faces of (face distance)/|S e_a|, for a polygon the distance to the mapped edges, for
+ * circles and spheres the distance to the mapped ellipses / ellipsoids (the smallest over them).  mode 2 (disc, annulus, ball): the bounds above for the outer
  * circle or sphere and, for the annulus, the inner circle, where dist itself is also a valid bound
  * for the inner circle: r = min(r_out, max(r_in, d)), and for a disc, ball or box with holes the
  * smallest hole bound as r_in (the box's r_out its exact radius); for the ellipse
@@ -504,6 +626,24 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
 {
     if (mode == 0) return d;
     int dim = g->dim;
+    if (mode == 1 && (g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL || g->kind == OG_PERFORATED)) {
+        double Q[9], ev[3];
+        sym_eigen(dim, S, Q, ev);
+        const double *c = g->p;
+        if (g->kind == OG_ANNULUS) {
+            double ro = mapped_sphere_distance(2, Q, ev, x, c, g->p[3]);
+            double ri = mapped_sphere_distance(2, Q, ev, x, c, g->p[2]);
+            return ro < ri ? ro : ri;
+        }
+        double r = mapped_sphere_distance(dim, Q, ev, x, c, g->p[dim]);
+        if (g->kind == OG_PERFORATED)
+            for (int l = 0; l < g->n_verts; ++l) {
+                const double *h = g->verts + (size_t)(dim + 1) * l;
+                double rl = mapped_sphere_distance(dim, Q, ev, x, h, h[dim]);
+                if (rl < r) r = rl;
+            }
+        return r;
+    }
     if (mode == 1 && g->kind == OG_POLYGON) {
         /* The ellipsoid is { z : |S^{-1}(z - x)| <= r }: it misses edge [a, b] exactly while r is
          * below the distance from S^{-1} x to the mapped edge [S^{-1} a, S^{-1} b], and, being
@@ -580,7 +720,9 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
 static int radius_mode_valid(const og_geom *g, int mode)
 {
     if (mode == 0) return 1;
-    if (mode == 1) return g->kind == OG_BOX || g->kind == OG_POLYGON;
+    if (mode == 1)
+        return g->kind == OG_BOX || g->kind == OG_POLYGON || g->kind == OG_DISK || g->kind == OG_ANNULUS ||
+               g->kind == OG_BALL || g->kind == OG_PERFORATED;
     if (mode == 2)
         return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL || g->kind == OG_ELLIPSE ||
                g->kind == OG_PERFORATED || g->kind == OG_PERFBOX;

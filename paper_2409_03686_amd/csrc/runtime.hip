@@ -514,7 +514,8 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
 // ---------------------------------------------------------------------------------------------
 // Instance set-up: lambda_max(K) and S = (K / lambda_max)^{1/2} (cyclic Jacobi eigensolver).
 // ---------------------------------------------------------------------------------------------
-wos_status wos::conductivity_root(const double *K, int d, double S[9], double *lam_max, double *lam_min)
+wos_status wos::conductivity_root(const double *K, int d, double S[9], double *lam_max, double *lam_min,
+                                  double *evec, double *eval)
 {
     double A[3][3] = {}, V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     double scale = 0.0;
@@ -573,6 +574,11 @@ wos_status wos::conductivity_root(const double *K, int d, double S[9], double *l
         }
     if (lam_max) *lam_max = lmax;
     if (lam_min) *lam_min = lmin;
+    if (evec)
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) evec[i * 3 + k] = i < d && k < d ? V[i][k] : (i == k ? 1.0 : 0.0);
+    if (eval)
+        for (int k = 0; k < 3; ++k) eval[k] = k < d ? std::sqrt(A[k][k] / lmax) : 1.0;
     return WOS_OK;
 }
 
@@ -591,8 +597,14 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
     if (w->radius_mode != WOS_RADIUS_WOE_BOUND && w->radius_mode != WOS_RADIUS_MAPPED_EXACT &&
         w->radius_mode != WOS_RADIUS_MAPPED_BOUND)
         return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
-    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON)
-        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes and polygons only");
+    const bool curved = g->kind == WOS_DISK || g->kind == WOS_ANNULUS || g->kind == WOS_BALL ||
+                        g->kind == WOS_PERFORATED;
+    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON && !curved)
+        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes, polygons, discs, annuli, balls "
+                                      "and discs / balls with holes only");
+    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && curved && w->precision != WOS_FP64)
+        return set_error(WOS_ENOTSUP, "the mapped-exact radius of circles and spheres (an iterative distance to "
+                                      "an ellipse or ellipsoid) runs with FP64 geometry only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_BOUND && g->kind != WOS_DISK && g->kind != WOS_ANNULUS &&
         g->kind != WOS_BALL && g->kind != WOS_ELLIPSE && g->kind != WOS_PERFORATED && g->kind != WOS_PERFBOX)
         return set_error(WOS_ENOTSUP, "mapped-bound radius is implemented for discs and balls (with or without holes), "
@@ -652,7 +664,7 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         I.pf[6] = static_cast<float>(std::min(g->params[2], g->params[3]));
     }
     double lmax = 0, lmin = 0;
-    wos_status st = conductivity_root(w->K, g->dim, I.S, &lmax, &lmin);
+    wos_status st = conductivity_root(w->K, g->dim, I.S, &lmax, &lmin, I.Sq, I.Se);
     if (st != WOS_OK) return st;
     for (int k = 0; k < 9; ++k) I.Sf[k] = static_cast<float>(I.S[k]);
     if (g->dim == 2) {  // S^{-1} by the 2 x 2 inverse formula
@@ -974,10 +986,13 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
         const wos_measure_job &j = jobs[idx[q]];
         const bool mapped = j.walk.radius_mode == WOS_RADIUS_MAPPED_BOUND ||
                             (j.geom.kind == WOS_POLYGON && j.walk.radius_mode == WOS_RADIUS_MAPPED_EXACT);
+        const bool curved_exact = j.walk.radius_mode == WOS_RADIUS_MAPPED_EXACT && j.geom.kind != WOS_BOX &&
+                                  j.geom.kind != WOS_POLYGON;
+        if (curved_exact) return -1;  // no compiled variant: the kernel reads the radius mode per instance
         return j.geom.kind + (mapped ? kRadiusVariant : 0);
     };
     gl.kind_sel = kernel_kind(0);
-    for (int q = 1; q < n; ++q)
+    for (int q = 1; q < n && gl.kind_sel >= 0; ++q)
         if (kernel_kind(q) != gl.kind_sel) gl.kind_sel = -1;
     const size_t lds = walk_lds_bytes(gl.precision, gl.dim, gl.block, gl.hist_words, gl.seg_bytes, gl.mode);
     if (lds > 160 * 1024) return set_error(WOS_ENOTSUP, "LDS need %zu bytes exceeds 160 KiB", lds);

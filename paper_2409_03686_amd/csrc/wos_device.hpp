@@ -39,6 +39,8 @@ struct alignas(16) DevInst {
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
     double msig2;     // ellipse, mapped bound: |A^{-1} S|^2 (A = diag(a, b))
     double Si[4];     // 2D: S^{-1}, row-major 2x2 (mapped-exact radius of polygons)
+    double Sq[9];     // eigenvectors of S, row-major: column k is the k-th (mapped-exact radius of
+    double Se[3];     // circles and spheres), and the eigenvalues of S
     double cn[3];     // |S e_a|: the half-extent of the unit ellipsoid S B(0,1) along axis a
     double eps;
     double perim;     // polygon perimeter
@@ -380,12 +382,121 @@ constexpr bool mapped_bound_kind(int kind)
 }
 constexpr int kRadiusVariant = 16;
 
+// Distance from y to the ellipsoid sum_i (z_i / e_i)^2 = 1 (y inside or outside), with b_i = e_i^2 and
+// a_i = |y_i| e_i.  The nearest point is z_i = y_i b_i / (b_i + t) for the root t of
+// G(t) = sum_i (a_i / (b_i + t))^2 - 1, which is convex and decreasing on t > -b_min; Newton's method
+// from a point left of the root (G >= 0 there) increases monotonically to it.  When y has no
+// component along the shortest axes (J) and the other terms leave G(-b_min) <= 0, the nearest point
+// has t = -b_min and its J components fill the ellipsoid equation.
+template <int DIM> __device__ __forceinline__ double ellipsoid_dist(const double *e, const double *y)
+{
+#pragma clang fp contract(off)
+    double b[DIM], a[DIM], bmin = __builtin_inf();
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        b[i] = e[i] * e[i];
+        a[i] = __builtin_fabs(y[i]) * e[i];
+        bmin = b[i] < bmin ? b[i] : bmin;
+    }
+    double aj = 0.0, gd = -1.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        if (b[i] == bmin) aj = a[i] > aj ? a[i] : aj;
+        else {
+            const double q = a[i] / (b[i] - bmin);
+            gd += q * q;
+        }
+    }
+    double t;
+    if (aj > 0.0) {
+        t = aj - bmin;
+    } else if (gd > 0.0) {
+        t = -bmin;
+    } else {  // the nearest point leaves the plane of the shortest axes
+        double d2 = 0.0, used = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+            if (b[i] != bmin) {
+                const double z = y[i] * b[i] / (b[i] - bmin);
+                d2 += (y[i] - z) * (y[i] - z);
+                used += z * z / b[i];
+            }
+        const double rest = 1.0 - used;
+        return __builtin_sqrt(d2 + bmin * (rest > 0.0 ? rest : 0.0));
+    }
+    for (int it = 0; it < 64; ++it) {
+        double g = -1.0, dg = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            const double q = a[i] / (b[i] + t);
+            g += q * q;
+            dg += q * q / (b[i] + t);
+        }
+        if (!(g > 0.0)) break;
+        const double tn = t + g / (2.0 * dg);  // G' = -2 dg
+        if (!(tn > t)) break;
+        t = tn;
+    }
+    double d2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const double z = y[i] * b[i] / (b[i] + t);
+        d2 += (y[i] - z) * (y[i] - z);
+    }
+    return __builtin_sqrt(d2);
+}
+
+// Mapped-exact radius of a circle / sphere of centre c and radius R: in the eigenbasis of S
+// (S = Q diag(s) Q^T) the mapped boundary S^{-1}(c + R S^{d-1}) is the ellipsoid with semi-axes R / s_k
+// about S^{-1} c, and the point is w_k = (Q^T (x - c))_k / s_k.
+template <int DIM> __device__ __forceinline__ double mapped_sphere_dist(const DevInst &I, const double *x,
+                                                                        const double *c, double R)
+{
+#pragma clang fp contract(off)
+    double w[DIM], e[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc += I.Sq[a * 3 + k] * (x[a] - c[a]);
+        w[k] = acc / I.Se[k];
+        e[k] = R / I.Se[k];
+    }
+    return ellipsoid_dist<DIM>(e, w);
+}
+
+// Circles and spheres (discs, annuli, balls, discs and balls with holes), mapped exact: the largest r
+// is the distance from S^{-1} x to the mapped boundary, the smallest over its circles / spheres.
+template <int KIND, int DIM> __device__ __forceinline__ double mapped_exact_curved(const DevInst &I, const double *x,
+                                                                                   const PolySeg *segs)
+{
+    const double c[3] = {I.p[0], I.p[1], DIM == 3 ? I.p[2] : 0.0};
+    if constexpr (KIND == kAnnulus) {
+        const double ro = mapped_sphere_dist<2>(I, x, c, I.p[3]), ri = mapped_sphere_dist<2>(I, x, c, I.p[2]);
+        return ro < ri ? ro : ri;
+    } else {
+        double r = mapped_sphere_dist<DIM>(I, x, c, I.p[DIM]);
+        if constexpr (KIND == kPerforated) {
+            for (int l = 0; l < I.n_verts; ++l) {
+                const double h[3] = {segs[l].ax, segs[l].ay, segs[l].ey};
+                const double rl = mapped_sphere_dist<DIM>(I, x, h, segs[l].ex);
+                r = rl < r ? rl : r;
+            }
+        }
+        return r;
+    }
+}
+
 // Polygons (mapped exact): the ellipsoid is { z : |S^{-1}(z - x)| <= r }, so the largest inscribed r is
 // the distance from S^{-1} x to the mapped edges, staged after the edges (segs[n_verts + e]).
 template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(const DevInst &I, const double *x,
                                                                                 double d, const PolySeg *segs)
 {
 #pragma clang fp contract(off)
+    if constexpr ((KIND == kDisk || KIND == kAnnulus || KIND == kBall || KIND == kPerforated) && RV < 0) {
+        // mapped exact for circles and spheres: FP64 only, launched with the per-instance radius mode
+        if (I.radius_mode == 1) return mapped_exact_curved<KIND, DIM>(I, x, segs);
+    }
     if constexpr (KIND == kPolygon && RV != 0) {
         if (RV == 1 || I.radius_mode == 1) {
             const double y0 = I.Si[0] * x[0] + I.Si[1] * x[1], y1 = I.Si[2] * x[0] + I.Si[3] * x[1];

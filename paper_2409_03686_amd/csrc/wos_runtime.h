@@ -58,7 +58,10 @@ wos_status ctx_malloc(wos_ctx *ctx, void **p, size_t bytes);
 void ctx_free(wos_ctx *ctx, void *p, size_t bytes);
 wos_status validate_geometry(const wos_geometry *g, int *n_elem);
 wos_status validate_walk(const wos_geometry *g, const wos_walk_params *w);
-wos_status conductivity_root(const double *K, int d, double S[9], double *lam_max, double *lam_min);
+// S = (K / lambda_max)^{1/2} (symmetric root); optionally its eigenvectors (row-major, column k the
+// k-th) and eigenvalues
+wos_status conductivity_root(const double *K, int d, double S[9], double *lam_max, double *lam_min,
+                             double *evec = nullptr, double *eval = nullptr);
 wos_status fill_inst(const wos_geometry *g, const wos_walk_params *w, int n_elem, DevInst &I,
                      std::vector<PolySeg> &segs);
 wos_tuning get_tuning(wos_ctx *ctx, int dim, int kind, int precision);

@@ -281,6 +281,43 @@ def test_perforated_disc_example(wos, ctx):
     assert rep["ok"]
 
 
+@pytest.mark.parametrize("case", ["disk", "annulus", "ball", "perforated2", "perforated3"])
+def test_curved_mapped_exact_radius_walk_for_walk(wos, ctx, case):
+    """The exact mapped radius of circles and spheres (the distance from S^{-1} x to the mapped
+    ellipses / ellipsoids, Newton on the closest-point equation) with an anisotropic K, FP64: walk for
+    walk against the oracle (which takes S's eigenbasis from its own Jacobi iteration), fewer steps
+    than the WoE chain on the same points, and FP32 geometry refused (WOS_ENOTSUP)."""
+    rng = np.random.default_rng(90)
+    K2 = np.array([[1.0, 0.5], [0.5, 2.0]])
+    Q3 = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    K3 = Q3 @ np.diag([1.0, 0.3, 0.08]) @ Q3.T
+    g, K = {
+        "disk": (wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (48,)), K2),
+        "annulus": (wi.Geometry(2, wi.ANNULUS, (0.0, 0.0, 0.3, 1.0), (40, 24)), K2),
+        "ball": (wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (6, 8)), K3),
+        "perforated2": (wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (24, 8, 3),
+                                    verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]])), K2),
+        "perforated3": (wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (4, 6, 3, 4),
+                                    verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]])), K3),
+    }[case]
+    x = wi.sample_points(g, 29, rng)
+    inst = wi.Instance(g, K, x, 600, eps=1e-5, seed=17, instance_id=1, precision=wi.FP64,
+                       radius_mode=wi.RADIUS_MAPPED_EXACT)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    agree = _agreement(tr, trr)
+    woe = wi.Instance(g, K, x, 600, eps=1e-5, seed=17, instance_id=1, precision=wi.FP64)
+    _, st0, _ = _gpu(wos, ctx, woe)
+    print(f"{case}: mapped exact FP64 walk agreement {agree:.6f}; steps per walk {st['steps'] / st['walks']:.2f} "
+          f"against {st0['steps'] / st0['walks']:.2f} with r = dist")
+    assert np.all(c.sum(1) == 600) and agree >= 0.999
+    assert st["escapes"] == sr["escapes"] == 0 and st["steps"] < 0.9 * st0["steps"]
+    inst32 = wi.Instance(g, K, x, 600, eps=1e-5, seed=17, precision=wi.FP32_GEOM_FP64_EXIT,
+                         radius_mode=wi.RADIUS_MAPPED_EXACT)
+    with pytest.raises(wos.WosError):
+        _gpu(wos, ctx, inst32)
+
+
 @pytest.mark.parametrize("example", [2, 3])
 def test_paper_annulus_examples(wos, ctx, example):
     """The paper's Examples 2 and 3 (Section 5.2): concentric annuli R_0 = 1, R_1 = 0.5 / 0.2 with

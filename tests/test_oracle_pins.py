@@ -559,6 +559,99 @@ def test_perforated_mapped_bound_keeps_the_ellipsoid_inside_and_the_law(dim):
     assert rep["ok"], rep
 
 
+@pytest.mark.parametrize("case", ["disk", "annulus", "ball", "perforated2", "perforated3"])
+def test_curved_mapped_exact_radius_is_the_largest_inscribed(case):
+    """Mapped exact (radius mode 1) on circles and spheres: brute force over the boundary of each step
+    ellipsoid x + r S u, |u| = 1, shows it inside the outer circle / sphere and off every inner circle,
+    sphere or hole when shrunk by 1e-9; the distance from S^{-1} x to the mapped boundary, minimised
+    numerically over the angles of the points c + R u(angles) of every circle / sphere (from the best of
+    dense samples), equals r to 1e-9, so r is the largest inscribed radius; r >= the mapped bound,
+    r = dist when S = I; the chain keeps the WoE chain's exit law with fewer steps (a root of the wrong
+    matrix, S in place of S^{-1}, or a semi-axis R s_k in place of R / s_k fails one of these)."""
+    rng = np.random.default_rng({"disk": 71, "annulus": 72, "ball": 73, "perforated2": 74, "perforated3": 75}[case])
+    if case == "disk":
+        g = wi.Geometry(2, wi.DISK, (0.2, -0.1, 1.3), (8,))
+    elif case == "annulus":
+        g = wi.Geometry(2, wi.ANNULUS, (0.1, 0.2, 0.3, 1.0), (8, 8))
+    elif case == "ball":
+        g = wi.Geometry(3, wi.BALL, (0.1, -0.2, 0.3, 0.9), (4, 4))
+    elif case == "perforated2":
+        g = wi.Geometry(2, wi.PERFORATED, (0.05, 0.0, 1.1), (24, 8, 3),
+                        verts=np.array([[0.4, 0.1, 0.25], [-0.3, -0.35, 0.15], [-0.35, 0.45, 0.2]]))
+    else:
+        g = wi.Geometry(3, wi.PERFORATED, (0.02, 0.0, -0.03, 1.05), (4, 6, 3, 4),
+                        verts=np.array([[0.35, 0.1, -0.05, 0.3], [-0.4, -0.2, 0.25, 0.25]]))
+    dim = g.dim
+    c = np.asarray(g.params[:dim])
+    if g.kind == wi.ANNULUS:
+        R, inner = g.params[3], [(c, g.params[2])]
+    else:
+        R = g.params[dim]
+        inner = [(np.asarray(h[:dim]), h[dim]) for h in np.asarray(g.verts, float).reshape(-1, dim + 1)] \
+            if g.kind == wi.PERFORATED else []
+    x = wi.sample_points(g, 60, rng)
+    U = _sphere_dirs(dim, 4096 if dim == 2 else 12000)
+    Ud = _sphere_dirs(dim, 20_000)  # starting points of the local minimisation
+    pieces = [(c, R)] + inner
+    from scipy import optimize
+
+    def u_of(ang):
+        if dim == 2:
+            return np.array([np.cos(ang[0]), np.sin(ang[0])])
+        return np.array([np.sin(ang[0]) * np.cos(ang[1]), np.sin(ang[0]) * np.sin(ang[1]), np.cos(ang[0])])
+
+    def mapped_distance(z, Si):
+        best = np.inf
+        for pc, pr in pieces:
+            pts = (pc + pr * Ud) @ Si.T
+            k = int(np.argmin(((pts - z) ** 2).sum(1)))
+            u0 = Ud[k]
+            a0 = [np.arctan2(u0[1], u0[0])] if dim == 2 else [np.arccos(np.clip(u0[2], -1, 1)), np.arctan2(u0[1], u0[0])]
+            f = lambda a: np.linalg.norm(Si @ (pc + pr * u_of(a)) - z)
+            if dim == 2:
+                res = optimize.minimize_scalar(lambda t: f([t]), bracket=(a0[0] - 1e-3, a0[0], a0[0] + 1e-3),
+                                               method="brent", tol=1e-14)
+                val = res.fun
+            else:
+                res = optimize.minimize(f, a0, method="Nelder-Mead",
+                                        options={"xatol": 1e-13, "fatol": 1e-16, "maxiter": 4000})
+                val = res.fun
+            best = min(best, val)
+        return best
+
+    def clearance(xi, ri, Sd):
+        """Signed: >= 0 iff the ellipsoid x + ri S B lies in D (smallest margin over its boundary)."""
+        pts = xi + ri * (U @ Sd.T)
+        m = R - np.sqrt(((pts - c) ** 2).sum(1)).max()
+        for hc, hr in inner:
+            m = min(m, np.sqrt(((pts - hc) ** 2).sum(1)).min() - hr)
+        return m
+
+    for cond in (1.0, 6.0, 25.0):
+        K = _random_spd(dim, cond, rng)
+        _, _, S = walks.instance_setup(K, dim)
+        Sd = S[:dim, :dim]
+        r = walks.step_radii(g, S, x, 1)
+        d, _ = walks.geom_eval(g, x)
+        rb = walks.step_radii(g, S, x, 2)
+        assert np.all(r >= rb * (1 - 1e-9)), (cond, (r - rb).min())
+        if cond == 1.0:
+            np.testing.assert_allclose(r, d, rtol=1e-9, atol=1e-13)
+        Si = np.linalg.inv(Sd)
+        for i in range(len(x)):
+            assert clearance(x[i], r[i] * (1 - 1e-9), Sd) >= -1e-13, (cond, i)
+            md = mapped_distance(Si @ x[i], Si)
+            assert abs(r[i] - md) <= 1e-9 * md + 1e-14, (cond, i, r[i], md)
+    xs = wi.sample_points(g, 4, np.random.default_rng(80))
+    N = 10_000
+    K = _random_spd(dim, 10.0, np.random.default_rng(81))
+    c0, s0, _ = walks.build_measure(g, K, xs, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c1, s1, _ = walks.build_measure(g, K, xs, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=1)
+    assert s1["steps"] < 0.9 * s0["steps"] and s1["escapes"] == 0, (s0["steps"], s1["steps"])
+    rep = statutil.two_sample(c0, N, c1, N)
+    assert rep["ok"], rep
+
+
 def test_mapped_bound_radius_same_law_fewer_steps():
     """The mapped-bound chain has the exit law of the WoE-bound chain (the two estimates agree within
     their sampling error) and takes far fewer steps on the anisotropic annulus."""
