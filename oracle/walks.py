@@ -61,7 +61,8 @@ def make_geom(g):
         v = np.ascontiguousarray(np.asarray(g.verts, np.float64).ravel())
         s._verts = v
         s.verts = _ptr(v, C.c_double)
-        s.n_verts = len(v) // (g.dim + 1) if g.kind in (wi.PERFORATED, wi.PERFBOX) else len(v) // 2
+        s.n_verts = (len(v) // (g.dim + 1) if g.kind in (wi.PERFORATED, wi.PERFBOX) else
+                     len(v) // 9 if g.kind == wi.TRIMESH else len(v) // 2)
     return s
 
 
@@ -116,6 +117,10 @@ def element_measures(g) -> np.ndarray:
         return np.full(M, L / M)
     if g.kind == wi.BALL:
         return sphere_cell_measures(g.layout[0], g.layout[1], g.params[3])
+    if g.kind == wi.TRIMESH:  # the areas |(b - a) x (c - a)| / 2 of each element's triangles
+        T = np.asarray(g.verts, float).reshape(-1, 3, 3)
+        area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1)
+        return area.reshape(M, int(g.layout[0])).sum(1)
     if g.kind in (wi.PERFORATED, wi.PERFBOX):
         # the outer boundary's cells, then each hole's: arcs 2 pi r / m, or sphere cells 4 pi r^2 / (nz nphi)
         d = g.dim

@@ -18,7 +18,10 @@
  *   step_radius).  The chain stops at N_eps = min{ n >= 0 : dist(X_n, dD) <= eps } (eq. "N
  *   epsilon x"), tested before each step.  eps = 0 is the fixed-iteration loop of the Remark on
  *   Algorithm MC-REM, item (i): the chain makes exactly max_steps steps (it stops earlier only on
- *   reaching dD, dist <= 0) and its last point is binned.  The stop point is projected onto dD and the element
+ *   reaching dD, dist <= 0) and its last point is binned.  D may also be the interior of a closed
+ *   triangle surface (a mesh; the Remark on Algorithm MC-REM, item (ii), allows other distance
+ *   functions): dist is then the distance to the nearest triangle, and a start point outside the
+ *   surface (by its winding number) is an escape.  The stop point is projected onto dD and the element
  *   that contains the projection receives one count (intrinsic Voronoi weights, Appendix
  *   Ex. A.3; for equally spaced arcs this equals the extrinsic Voronoi cells of Ex. A.2).  So
  *   counts[i, j] / N is the Monte Carlo estimate A_{omega, eps, N} of eq. "WoE_matrix_MC".
@@ -45,6 +48,7 @@
 #define OG_BOX 5
 #define OG_PERFORATED 6
 #define OG_PERFBOX 7
+#define OG_TRIMESH 8
 
 #define OG_TWO_PI 6.283185307179586
 
@@ -54,8 +58,9 @@ typedef struct {
     double p[8];          /* shape parameters, see the geometry table in the docs */
     int32_t layout[4];    /* element layout */
     const double *verts;  /* polygon loop (x0,y0,x1,y1,...), counter-clockwise; for the perforated
-                             domains the holes as (centre, r), dim + 1 numbers each */
-    int32_t n_verts;      /* polygon vertices, or holes of a perforated domain */
+                             domains the holes as (centre, r), dim + 1 numbers each; for a triangle
+                             mesh the corners (a, b, c) of each triangle, 9 numbers each */
+    int32_t n_verts;      /* polygon vertices, holes of a perforated domain, or mesh triangles */
     const double *nodes[2]; /* Bauer-spiral unit vectors (3 per node) of the outer sphere / of the holes
                                when their layout is (n, 0); set by the entry points, not the caller */
 } og_geom;
@@ -182,6 +187,107 @@ static double hole_dist(const og_geom *g, int l, const double *x, double *v)
     return sqrt(s) - h[d];
 }
 
+/* Triangle meshes: D is the interior of a closed surface made of triangles (a, b, c), each
+ * counter-clockwise seen from outside.  Vectors are combined in axis order x, y, z. */
+static double dot3(const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
+
+static void cross3(const double *u, const double *v, double *w)
+{
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+/* Distance from x to the segment p + t e, t in [0, 1], with w = x - p. */
+static double seg3_dist(const double *w, const double *e)
+{
+    double t = dot3(w, e) / dot3(e, e);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double q[3];
+    for (int k = 0; k < 3; ++k) q[k] = w[k] - t * e[k];
+    return sqrt(dot3(q, q));
+}
+
+/* Distance from x to the triangle (a, b, c), from the definition of the distance to a convex set:
+ * when the orthogonal projection of x onto the triangle's plane lies in the triangle (on the inner
+ * side of each edge line within the plane), the projection is the nearest point and the distance is
+ * |n.(x - a)| / |n| (n = (b - a) x (c - b)); otherwise the nearest point lies on the boundary, and
+ * the distance is the smallest of the distances to the three edges. */
+static double tri_dist(const double *T, const double *x)
+{
+    const double *a = T, *b = T + 3, *c = T + 6;
+    double e0[3], e1[3], e2[3], ap[3], bp[3], cp[3], n[3], m[3];
+    for (int k = 0; k < 3; ++k) {
+        e0[k] = b[k] - a[k];
+        e1[k] = c[k] - b[k];
+        e2[k] = a[k] - c[k];
+        ap[k] = x[k] - a[k];
+        bp[k] = x[k] - b[k];
+        cp[k] = x[k] - c[k];
+    }
+    cross3(e0, e1, n);
+    /* n x e points into the triangle from edge e (within the plane) */
+    cross3(n, e0, m);
+    int inside = dot3(m, ap) >= 0.0;
+    cross3(n, e1, m);
+    inside = inside && dot3(m, bp) >= 0.0;
+    cross3(n, e2, m);
+    inside = inside && dot3(m, cp) >= 0.0;
+    if (inside) return fabs(dot3(n, ap)) / sqrt(dot3(n, n));
+    double d = seg3_dist(ap, e0), d1 = seg3_dist(bp, e1), d2 = seg3_dist(cp, e2);
+    if (d1 < d) d = d1;
+    if (d2 < d) d = d2;
+    return d;
+}
+
+/* Distance to the mesh and the nearest triangle (the lowest index among equally near ones). */
+static double mesh_dist(const og_geom *g, const double *x, int *tri_out)
+{
+    double best = INFINITY;
+    int tb = 0;
+    for (int t = 0; t < g->n_verts; ++t) {
+        double d = tri_dist(g->verts + 9 * (size_t)t, x);
+        if (d < best) { best = d; tb = t; }
+    }
+    if (tri_out) *tri_out = tb;
+    return best;
+}
+
+/* Inside test of a start point: the winding number of the surface about x, the sum over the
+ * triangles of the solid angle they subtend at x over 4 pi (Van Oosterom and Strackee: the solid
+ * angle of (A, B, C) seen from the origin is 2 atan2(A.(B x C), |A||B||C| + (A.B)|C| + (A.C)|B| +
+ * (B.C)|A|)), is 1 inside and 0 outside; x counts as inside when it exceeds 1/2. */
+static int mesh_inside(const og_geom *g, const double *x)
+{
+    double total = 0.0;
+    for (int t = 0; t < g->n_verts; ++t) {
+        const double *T = g->verts + 9 * (size_t)t;
+        double A[3], B[3], C[3], bc[3];
+        for (int k = 0; k < 3; ++k) {
+            A[k] = T[k] - x[k];
+            B[k] = T[3 + k] - x[k];
+            C[k] = T[6 + k] - x[k];
+        }
+        double la = sqrt(dot3(A, A)), lb = sqrt(dot3(B, B)), lc = sqrt(dot3(C, C));
+        cross3(B, C, bc);
+        double den = la * lb * lc + dot3(A, B) * lc + dot3(A, C) * lb + dot3(B, C) * la;
+        total += 2.0 * atan2(dot3(A, bc), den);
+    }
+    return total > 0.5 * 2.0 * OG_TWO_PI;
+}
+
+/* Signed distance of a start point: for a mesh the distance carries the sign of the inside test
+ * (the walk never leaves D afterwards, each step staying within the distance, so the distance
+ * along the chain is the unsigned one); for the other kinds the signed distance itself. */
+double oracle_dist(const og_geom *g, const double *x);
+static double start_dist(const og_geom *g, const double *x)
+{
+    if (g->kind != OG_TRIMESH) return oracle_dist(g, x);
+    double d = mesh_dist(g, x, NULL);
+    return mesh_inside(g, x) ? d : -d;
+}
+
 double oracle_dist(const og_geom *g, const double *x)
 {
     switch (g->kind) {
@@ -231,6 +337,8 @@ double oracle_dist(const og_geom *g, const double *x)
         }
         return best;
     }
+    case OG_TRIMESH:
+        return mesh_dist(g, x, NULL);
     case OG_PERFORATED:
     case OG_PERFBOX: {
         /* a disc / ball (the paper's Examples 2-4, 6, 7) or a box (Examples 1, 5) with disjoint
@@ -399,6 +507,12 @@ int oracle_element(const og_geom *g, const double *x)
     }
     case OG_BOX:
         return box_cell(g, x);
+    case OG_TRIMESH: {
+        /* the nearest triangle; layout[0] consecutive triangles form one element */
+        int tb;
+        mesh_dist(g, x, &tb);
+        return tb / g->layout[0];
+    }
     case OG_PERFORATED:
     case OG_PERFBOX: {
         /* the nearest piece of the boundary (ties: the outer boundary, then the lowest hole), then
@@ -769,7 +883,7 @@ static void *run_rows(void *arg)
             int capped = 0;
             double d;
             for (;;) {
-                d = oracle_dist(g, x);
+                d = s == 0 ? start_dist(g, x) : oracle_dist(g, x);
                 if (d <= J->eps) break;
                 if (s >= J->max_steps) { capped = 1; break; }
                 double r = step_radius(g, J->radius_mode, J->S, x, d);
@@ -855,7 +969,7 @@ void oracle_geom_eval(const og_geom *g, const double *x, int32_t n, double *d_ou
     og_geom G = attach_nodes(g);
     for (int32_t i = 0; i < n; ++i) {
         const double *p = x + (size_t)i * G.dim;
-        if (d_out) d_out[i] = oracle_dist(&G, p);
+        if (d_out) d_out[i] = start_dist(&G, p);
         if (e_out) e_out[i] = oracle_element(&G, p);
     }
     detach_nodes(&G);
@@ -883,7 +997,7 @@ int oracle_walk_exits(const og_geom *g, const double *S, double eps, int radius_
         for (int a = 0; a < dim; ++a) x[a] = x0[a];
         uint32_t s = 0;
         for (;;) {
-            double d = oracle_dist(g, x);
+            double d = s == 0 ? start_dist(g, x) : oracle_dist(g, x);
             if (d <= eps || s >= max_steps) break;
             double r = step_radius(g, radius_mode, S, x, d);
             oracle_direction(dim, s, (uint32_t)k, i, inst, seed_lo, seed_hi, U);

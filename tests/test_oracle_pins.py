@@ -996,3 +996,125 @@ def test_perforated_domains_reproduce_paper_solutions():
     assert np.all(_exit_mean_z(g, S2, xh, logc, 20_000, grad_bound=5.0) < 4.5)
     g_nohole = wi.Geometry(2, wi.BOX, g.params, (g.layout[0],))
     assert _exit_mean_z(g_nohole, S2, xh, logc, 20_000, grad_bound=5.0).max() > 8
+
+
+# ------------------------------------------------------------------------------ triangle meshes
+
+def _tri_dist_normal_equations(T, x):
+    """Distance from x to the triangle T = (a, b, c) by another route than the oracle's: the nearest
+    point of the triangle's plane from the 2 x 2 normal equations in the barycentric coordinates
+    (v, w) of a + v (b - a) + w (c - a); if v, w >= 0 and v + w <= 1 it is the nearest point of the
+    triangle, else the nearest point lies on one of the three edges (closed-form clamped projection)."""
+    a, b, c = T
+    e1, e2, r = b - a, c - a, x - a
+    G = np.array([[e1 @ e1, e1 @ e2], [e1 @ e2, e2 @ e2]])
+    v, w = np.linalg.solve(G, np.array([e1 @ r, e2 @ r]))
+    if v >= 0 and w >= 0 and v + w <= 1:
+        return np.linalg.norm(r - v * e1 - w * e2)
+    best = np.inf
+    for p, q in ((a, b), (b, c), (c, a)):
+        e = q - p
+        t = np.clip((x - p) @ e / (e @ e), 0.0, 1.0)
+        best = min(best, np.linalg.norm(x - p - t * e))
+    return best
+
+
+def test_triangle_distance_matches_two_independent_routes():
+    """The oracle's triangle distance (projection inside the triangle by the three in-plane edge
+    normals, else the nearest edge) equals the normal-equation route to 1e-12 on random triangles
+    (from slivers of aspect 1/20 to equilateral) and points near faces, edges, vertices and far away,
+    and lies within the sampling resolution of a dense barycentric sampling of the triangle (and
+    never above it).  A one-triangle mesh gives the unsigned distance."""
+    rng = np.random.default_rng(31)
+    checked = 0
+    for trial in range(60):
+        T = rng.standard_normal((3, 3))
+        if trial % 3 == 0:  # flattened triangles
+            T[2] = T[0] + (T[1] - T[0]) * rng.uniform(0.2, 0.8) + rng.standard_normal(3) * 0.05
+        g = wi.Geometry(3, wi.TRIMESH, (), (1,), verts=T[None])
+        # points: random, near each vertex and edge midpoint, and above the face
+        P = [rng.standard_normal((10, 3)) * 2.0]
+        for p in (T[0], T[1], T[2], 0.5 * (T[0] + T[1]), 0.5 * (T[1] + T[2]), T.mean(0)):
+            P.append(p + rng.standard_normal((4, 3)) * 0.05)
+        P = np.concatenate(P)
+        d, e = walks.geom_eval(g, P)
+        d = np.abs(d)
+        assert np.all(e == 0)
+        ref = np.array([_tri_dist_normal_equations(T, p) for p in P])
+        np.testing.assert_allclose(d, ref, rtol=1e-12, atol=1e-14)
+        s = np.linspace(0, 1, 201)
+        V, W = np.meshgrid(s, s, indexing="ij")
+        m = (V + W) <= 1
+        pts = T[0] + V[m][:, None] * (T[1] - T[0]) + W[m][:, None] * (T[2] - T[0])
+        dense = np.sqrt(((P[:, None, :] - pts[None]) ** 2).sum(2)).min(1)
+        h = 0.5 / 200 * (np.linalg.norm(T[1] - T[0]) + np.linalg.norm(T[2] - T[0]))
+        assert np.all(d <= dense + 1e-12) and np.all(dense <= d + h)
+        checked += len(P)
+    assert checked > 1000
+
+
+def test_mesh_box_is_the_box_kind():
+    """A box as a triangle mesh (two triangles per patch, in the BOX kind's patch order) is the BOX
+    kind: the same distance at interior points (to rounding: the plane distance |n.(x - a)| / |n| and
+    the coordinate difference round differently), the same cells, the same cell measures, and the
+    oracle's walks on both give the same exit cell and step count walk for walk."""
+    g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh([0.1, -0.2, 0.0], [1.1, 0.6, 1.5], 6))
+    gb = wi.Geometry(3, wi.BOX, (0.1, -0.2, 0.0, 1.1, 0.6, 1.5), (6,))
+    rng = np.random.default_rng(32)
+    x = wi.sample_points(gb, 400, rng)
+    d, e = walks.geom_eval(g, x)
+    db, eb = walks.geom_eval(gb, x)
+    np.testing.assert_allclose(d, db, rtol=0, atol=4e-16)
+    assert np.array_equal(e, eb)
+    np.testing.assert_allclose(walks.element_measures(g), walks.element_measures(gb), rtol=1e-14)
+    xo = rng.uniform(-0.5, 2.0, (300, 3))
+    out = ~np.all((xo > [0.1, -0.2, 0.0]) & (xo < [1.1, 0.6, 1.5]), 1)
+    do, _ = walks.geom_eval(g, xo)
+    assert np.all(do[out] < 0) and np.all(do[~out] > 0)
+    K = _random_spd(3, 8.0, np.random.default_rng(33))
+    xs = wi.sample_points(gb, 6, rng)
+    c1, s1, t1 = walks.build_measure(g, K, xs, 1e-4, seed=3, walk_end=400, threads=8, trace=True)
+    c0, s0, t0 = walks.build_measure(gb, K, xs, 1e-4, seed=3, walk_end=400, threads=8, trace=True)
+    assert np.mean(np.all(t1 == t0, axis=2)) >= 0.999 and np.abs(c1 - c0).sum() <= 0.002 * c0.sum()
+
+
+def test_mesh_start_points_outside_are_escapes_and_inside_by_winding():
+    """The winding-number inside test on the non-convex L-prism equals the analytic membership of
+    the prism (points in the notch, beside and above it are outside); walks from outside start points
+    stop at once as escapes in the cell of the nearest triangle, walks from inside never escape."""
+    T = wi.l_prism_mesh(8)
+    g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=T)
+    rng = np.random.default_rng(34)
+    P = rng.uniform(-0.25, 1.25, (3000, 3))
+    ins = (np.all((P > 0) & (P < 1), 1) & ~((P[:, 0] > 0.5) & (P[:, 1] > 0.5)))
+    far = np.abs(walks.geom_eval(g, P)[0]) > 1e-9
+    d, _ = walks.geom_eval(g, P[far])
+    assert np.array_equal(d > 0, ins[far])
+    xo = np.array([[0.75, 0.75, 0.5], [1.2, 0.3, 0.5], [0.3, 0.3, 1.1]])
+    c, st, tr = walks.build_measure(g, np.eye(3), xo, 1e-4, seed=1, walk_end=50, threads=4, trace=True)
+    assert st["escapes"] == 150 and st["steps"] == 0
+    _, e = walks.geom_eval(g, xo)
+    assert np.all(c[np.arange(3), e] == 50)
+    xi = wi.sample_points(g, 5, rng)
+    _, st, _ = walks.build_measure(g, np.eye(3), xi, 1e-4, seed=1, walk_end=500, threads=4)
+    assert st["escapes"] == 0 and st["steps"] > 0
+
+
+def test_mesh_walk_reproduces_harmonic_functions():
+    """E u(X_N) = u(x) for K-harmonic u on the non-convex L-prism with an anisotropic K (u = x^T A x
+    + b.x with tr(K A) = 0); the slip S = Khat in place of Khat^{1/2} fails."""
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.6, -0.2], [0.1, -0.2, 0.4]])
+    A = np.array([[1.0, 0.5, 0.0], [0.5, -0.8, 0.3], [0.0, 0.3, 0.0]])
+    A[2, 2] = -(np.trace(K @ A) - K[2, 2] * A[2, 2]) / K[2, 2]
+    assert abs(np.trace(K @ A)) < 1e-12
+    bvec = np.array([0.3, -0.2, 0.5])
+    u = lambda p: np.einsum("pi,ij,pj->p", p, A, p) + p @ bvec
+    g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.l_prism_mesh(2))  # 44 triangles
+    x = wi.sample_points(g, 6, np.random.default_rng(35))
+    _, Khat, S = walks.instance_setup(K, 3)
+    z = _exit_mean_z(g, S, x, u, 20_000, grad_bound=6.0)
+    assert np.all(z < 4.5), z
+    Sw = np.zeros((3, 3))
+    Sw[:3, :3] = Khat
+    zw = _exit_mean_z(g, Sw, x, u, 20_000, grad_bound=6.0)
+    assert zw.max() > 8, zw

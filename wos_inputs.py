@@ -35,9 +35,10 @@ from typing import Optional
 
 import numpy as np
 
-DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX, PERFORATED, PERFBOX = 0, 1, 2, 3, 4, 5, 6, 7
+DISK, ANNULUS, ELLIPSE, POLYGON, BALL, BOX, PERFORATED, PERFBOX, TRIMESH = 0, 1, 2, 3, 4, 5, 6, 7, 8
 KIND_NAMES = {DISK: "disk", ANNULUS: "annulus", ELLIPSE: "ellipse", POLYGON: "polygon",
-              BALL: "ball", BOX: "box", PERFORATED: "perforated", PERFBOX: "perforated box"}
+              BALL: "ball", BOX: "box", PERFORATED: "perforated", PERFBOX: "perforated box",
+              TRIMESH: "triangle mesh"}
 
 FP64 = 0
 FP32_GEOM_FP64_EXIT = 1
@@ -60,7 +61,14 @@ class Geometry:
         return 0 if self.verts is None else int(np.asarray(self.verts).size // (self.dim + 1))
 
     @property
+    def n_tri(self) -> int:
+        """Triangles of a TRIMESH geometry (verts holds them as (n_tri, 3, 3) corner coordinates)."""
+        return int(np.asarray(self.verts).size // 9)
+
+    @property
     def n_elem(self) -> int:
+        if self.kind == TRIMESH:
+            return self.n_tri // int(self.layout[0])
         return element_count(self.dim, self.kind, self.layout, self.n_holes)
 
 
@@ -176,6 +184,13 @@ def element_ref_points(g: Geometry) -> np.ndarray:
         e = np.searchsorted(cum, s, side="right") - 1
         t = (s - cum[e]) / ln[e]
         return v[e] + t[:, None] * seg[e]
+    if g.kind == TRIMESH:  # area-weighted centroid of each element's triangles
+        T = np.asarray(g.verts, float).reshape(-1, 3, 3)
+        area = 0.5 * np.linalg.norm(np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), axis=1)
+        cen = T.mean(1)
+        gsz = int(g.layout[0])
+        w = area.reshape(-1, gsz)
+        return (cen.reshape(-1, gsz, 3) * w[:, :, None]).sum(1) / w.sum(1)[:, None]
     if g.kind == BALL and g.layout[1] == 0:
         return _sphere_cell_centres(g.params[:3], g.params[3], g.layout[0], 0)
     if g.kind == BALL:
@@ -450,6 +465,102 @@ def cfg3_cube(n_walks: int = 100_000, precision: int = FP32_GEOM_FP64_EXIT,
 L_SHAPE = np.array([[0, 0], [1, 0], [1, 0.5], [0.5, 0.5], [0.5, 1], [0, 1]], float)
 
 
+def mesh_winding(tris: np.ndarray, p: np.ndarray, chunk: int = 4096) -> np.ndarray:
+    """Winding number of a closed triangle surface about each point: the sum of the solid angles
+    of its triangles seen from the point over 4 pi (Van Oosterom and Strackee's formula for the
+    solid angle of a triangle); about 1 inside an outward-oriented surface, 0 outside."""
+    T = np.asarray(tris, float).reshape(-1, 3, 3)
+    p = np.asarray(p, float).reshape(-1, 3)
+    out = np.zeros(p.shape[0])
+    for s in range(0, T.shape[0], chunk):
+        A = T[None, s:s + chunk, 0] - p[:, None]
+        B = T[None, s:s + chunk, 1] - p[:, None]
+        Cc = T[None, s:s + chunk, 2] - p[:, None]
+        la, lb, lc = (np.linalg.norm(v, axis=2) for v in (A, B, Cc))
+        det = np.einsum("ptk,ptk->pt", A, np.cross(B, Cc))
+        den = la * lb * lc + (A * B).sum(2) * lc + (A * Cc).sum(2) * lb + (B * Cc).sum(2) * la
+        out += (2.0 * np.arctan2(det, den)).sum(1)
+    return out / (4.0 * np.pi)
+
+
+def box_mesh(lo, hi, n: int) -> np.ndarray:
+    """The surface of the box [lo, hi] (3D) as triangles, outward-oriented, in the cell order of
+    the BOX kind: faces (x=lo, x=hi, y=lo, y=hi, z=lo, z=hi), n x n patches each (index along the
+    other two axes in increasing axis order), two triangles per patch.  With two triangles per
+    element (layout (2,)) the elements are the BOX kind's patches."""
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    out = []
+    for f in range(6):
+        a, side = f // 2, f % 2
+        b0, b1 = [b for b in range(3) if b != a]
+        # e_b0 x e_b1 is +e_a for a = 0, 2 and -e_a for a = 1; outward is +e_a on the hi side
+        ccw = (1 if a != 1 else -1) * (1 if side else -1) > 0
+        g0 = np.linspace(lo[b0], hi[b0], n + 1)
+        g1 = np.linspace(lo[b1], hi[b1], n + 1)
+        for i0 in range(n):
+            for i1 in range(n):
+                q = np.zeros((4, 3))
+                q[:, a] = hi[a] if side else lo[a]
+                q[:, b0] = [g0[i0], g0[i0 + 1], g0[i0 + 1], g0[i0]]
+                q[:, b1] = [g1[i1], g1[i1], g1[i1 + 1], g1[i1 + 1]]
+                if ccw:
+                    out += [q[[0, 1, 2]], q[[0, 2, 3]]]
+                else:
+                    out += [q[[0, 2, 1]], q[[0, 3, 2]]]
+    return np.array(out)
+
+
+def sphere_mesh(c, R: float, level: int) -> np.ndarray:
+    """An icosahedron subdivided `level` times (each triangle into four) with its vertices on the
+    sphere |x - c| = R: 20 * 4^level outward-oriented triangles."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    tris = [np.array([V[i] for i in f], float) for f in F]
+    tris = [x / np.linalg.norm(x, axis=1, keepdims=True) for x in tris]
+    for _ in range(level):
+        nxt = []
+        for a, b, cc in tris:
+            ab, bc, ca = [(u + v) / np.linalg.norm(u + v) for u, v in ((a, b), (b, cc), (cc, a))]
+            nxt += [np.array([a, ab, ca]), np.array([ab, b, bc]), np.array([ca, bc, cc]), np.array([ab, bc, ca])]
+        tris = nxt
+    T = np.array(tris)
+    flip = np.einsum("tk,tk->t", np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]), T.mean(1)) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return np.asarray(c, float) + R * T
+
+
+def l_prism_mesh(n: int, height: float = 1.0) -> np.ndarray:
+    """The L-shaped prism L x [0, height] (L = the L-shape polygon, a non-convex domain): its six
+    walls split into patches of side about 1/n, the bottom and top L faces into squares of side
+    1/n (n even), two triangles per patch, outward-oriented."""
+    L = L_SHAPE
+    out = []
+    zs = np.linspace(0.0, height, max(1, round(n * height)) + 1)
+    for k in range(len(L)):
+        p, q = L[k], L[(k + 1) % len(L)]
+        m = max(1, round(n * np.linalg.norm(q - p)))
+        s = np.linspace(0.0, 1.0, m + 1)
+        for i in range(m):
+            a, b = p + s[i] * (q - p), p + s[i + 1] * (q - p)
+            for j in range(len(zs) - 1):
+                P = np.array([[*a, zs[j]], [*b, zs[j]], [*b, zs[j + 1]], [*a, zs[j + 1]]])
+                out += [P[[0, 1, 2]], P[[0, 2, 3]]]  # (b - a) x z points out of a CCW loop
+    h = 1.0 / n
+    for (x0, y0) in ((0.0, 0.0), (0.5, 0.0), (0.0, 0.5)):
+        for i in range(n // 2):
+            for j in range(n // 2):
+                xa, ya = x0 + i * h, y0 + j * h
+                sq = np.array([[xa, ya], [xa + h, ya], [xa + h, ya + h], [xa, ya + h]])
+                bot = np.column_stack([sq, np.zeros(4)])
+                top = np.column_stack([sq, np.full(4, height)])
+                out += [bot[[0, 2, 1]], bot[[0, 3, 2]], top[[0, 1, 2]], top[[0, 2, 3]]]
+    return np.array(out)
+
+
 def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
     """Membership of candidate points in the open domain (used to draw points by rejection)."""
     if g.kind == DISK:
@@ -478,6 +589,8 @@ def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
         d = g.dim
         lo, hi = np.array(g.params[:d]), np.array(g.params[d:2 * d])
         return np.all((p > lo) & (p < hi), 1)
+    if g.kind == TRIMESH:
+        return mesh_winding(g.verts, p) > 0.5
     if g.kind in (PERFORATED, PERFBOX):
         d = g.dim
         if g.kind == PERFORATED:
@@ -491,6 +604,9 @@ def _inside(g: Geometry, p: np.ndarray) -> np.ndarray:
 
 
 def _bbox(g: Geometry):
+    if g.kind == TRIMESH:
+        T = np.asarray(g.verts, float).reshape(-1, 3)
+        return T.min(0), T.max(0)
     if g.kind == PERFORATED:
         c, R = np.array(g.params[:g.dim]), g.params[g.dim]
         return c - R, c + R
