@@ -106,12 +106,25 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *   WOS_PERFBOX  a box with k disjoint round holes (the paper's Examples 1 and 5).  params and
  *                face patches as WOS_BOX, holes as for WOS_PERFORATED; layout (n, M_hole) in 2D,
  *                (n, n_z hole, n_phi hole) in 3D: the box's patches first, then each hole's cells.
+ *   WOS_TRIMESH  dim 3, the interior of a closed surface of triangles (general distance functions are
+ *                allowed by the Remark on Algorithm MC-REM, item (ii)).  verts = n_verts triangles
+ *                (a, b, c) as 9 numbers each (host, copied during the call), counter-clockwise seen
+ *                from outside; 4 <= n_verts <= WOS_MAX_TRIANGLES; degenerate triangles are refused.
+ *                layout (g): g consecutive triangles form one cell (g divides n_verts), so M =
+ *                n_verts / g.  dist is the distance to the nearest triangle: the plane distance when
+ *                the point's projection onto the triangle's plane lies in the triangle, else the
+ *                distance to the nearest of its edges.  A stop point goes to the cell of the nearest
+ *                triangle (ties: the lowest triangle index).  A start point whose winding number
+ *                (the triangles' solid angles seen from it over 4 pi) is below 1/2 is outside: its
+ *                walks are escapes.  Step radius r = dist only (WOS_RADIUS_WOE_BOUND).  The triangles
+ *                are searched through a bounding-volume hierarchy in HBM (256 B per triangle plus
+ *                32 B per node, rebuilt on the host for each call).
  * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
  * weights of the paper's appendix, Ex. A.3; for Bauer layouts the extrinsic ones of Ex. A.2, taken
  * on the stop point's nearest sphere); ties go to the lowest face/segment index. */
 typedef enum {
     WOS_DISK = 0, WOS_ANNULUS = 1, WOS_ELLIPSE = 2, WOS_POLYGON = 3, WOS_BALL = 4, WOS_BOX = 5,
-    WOS_PERFORATED = 6, WOS_PERFBOX = 7
+    WOS_PERFORATED = 6, WOS_PERFBOX = 7, WOS_TRIMESH = 8
 } wos_geom_kind;
 
 typedef struct {
@@ -119,12 +132,14 @@ typedef struct {
     int32_t kind;         /* wos_geom_kind */
     double params[8];
     int32_t layout[4];
-    const double *verts;  /* host; polygon vertices or the holes of a perforated domain (copied during the call) */
-    int32_t n_verts;      /* polygon: 3..WOS_MAX_POLY_VERTS vertices; perforated domains: holes */
+    const double *verts;  /* host; polygon vertices, the holes of a perforated domain or the triangles of a
+                             mesh (copied during the call) */
+    int32_t n_verts;      /* polygon: 3..WOS_MAX_POLY_VERTS vertices; perforated domains: holes; mesh: triangles */
 } wos_geometry;
 
 #define WOS_MAX_POLY_VERTS 64
 #define WOS_MAX_HOLES 32
+#define WOS_MAX_TRIANGLES (1 << 20)
 #define WOS_MAX_ELEMENTS 16384  /* one LDS histogram row must fit in 64 KiB */
 
 /* Number of boundary cells M of a geometry. */

@@ -168,8 +168,20 @@ static long long elements_of(const wos_geometry *g)
     case WOS_PERFBOX:
         if (g->dim == 2) return 4 * g->layout[0] + g->n_verts * g->layout[1];
         return 6 * g->layout[0] * g->layout[0] + g->n_verts * sphere_cells(g->layout[1], g->layout[2]);
+    case WOS_TRIMESH: return g->n_verts / g->layout[0];
     }
     return -1;
+}
+
+size_t wos::vertex_doubles(const wos_geometry *g)
+{
+    if (!g->verts || g->n_verts <= 0) return 0;
+    const size_t n = static_cast<size_t>(g->n_verts);
+    switch (g->kind) {
+    case WOS_PERFORATED: case WOS_PERFBOX: return n * (g->dim + 1);
+    case WOS_TRIMESH: return 9 * n;
+    default: return 2 * n;
+    }
 }
 
 // Unit vectors of the n nodes of Bauer's spiral as Section 5.3 gives them: polar angle
@@ -363,6 +375,31 @@ wos_status wos::validate_geometry(const wos_geometry *g, int *n_elem)
         if (st != WOS_OK) return st;
         break;
     }
+    case WOS_TRIMESH: {
+        if (g->dim != 3) return set_error(WOS_EINVAL, "triangle mesh needs dim 3");
+        if (!g->verts || g->n_verts < 4 || g->n_verts > WOS_MAX_TRIANGLES)
+            return set_error(WOS_EINVAL, "triangle mesh needs 4..%d triangles", WOS_MAX_TRIANGLES);
+        if (g->layout[0] < 1 || g->n_verts % g->layout[0] != 0)
+            return set_error(WOS_EINVAL, "triangle mesh layout (g) needs g >= 1 dividing the triangle count");
+        for (int t = 0; t < g->n_verts; ++t) {
+            const double *T = g->verts + 9 * static_cast<size_t>(t);
+            for (int k = 0; k < 9; ++k)
+                if (!std::isfinite(T[k])) return set_error(WOS_EINVAL, "triangle %d has a coordinate that is not finite", t);
+            double e1[3], e2[3], n[3], l1 = 0.0, l2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                e1[k] = T[3 + k] - T[k];
+                e2[k] = T[6 + k] - T[k];
+                l1 += e1[k] * e1[k];
+                l2 += e2[k] * e2[k];
+            }
+            n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            if (!(std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]) > 1e-9 * std::max(l1, l2)))
+                return set_error(WOS_EINVAL, "triangle %d is degenerate", t);
+        }
+        break;
+    }
     case WOS_PERFBOX: {
         if (g->dim != 2 && g->dim != 3) return set_error(WOS_EINVAL, "perforated box needs dim 2 or 3");
         for (int a = 0; a < g->dim; ++a)
@@ -459,6 +496,20 @@ extern "C" wos_status wos_element_measures(const wos_geometry *g, double *sigma)
     }
     case WOS_BALL:
         sphere_measures(g->layout[0], g->layout[1], p[3], sigma);
+        break;
+    case WOS_TRIMESH:  // the areas |(b - a) x (c - a)| / 2 of each element's triangles
+        for (int j = 0; j < M; ++j) sigma[j] = 0.0;
+        for (int t = 0; t < g->n_verts; ++t) {
+            const double *T = g->verts + 9 * static_cast<size_t>(t);
+            double e1[3], e2[3];
+            for (int k = 0; k < 3; ++k) {
+                e1[k] = T[3 + k] - T[k];
+                e2[k] = T[6 + k] - T[k];
+            }
+            const double n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2],
+                         n2 = e1[0] * e2[1] - e1[1] * e2[0];
+            sigma[t / g->layout[0]] += 0.5 * std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        }
         break;
     case WOS_PERFORATED: case WOS_PERFBOX: {
         // outer cells (arcs / equal-area sphere cells of the disc or ball, or box patches), then the
@@ -599,6 +650,8 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
         return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
     const bool curved = g->kind == WOS_DISK || g->kind == WOS_ANNULUS || g->kind == WOS_BALL ||
                         g->kind == WOS_PERFORATED;
+    if (g->kind == WOS_TRIMESH && w->radius_mode != WOS_RADIUS_WOE_BOUND)
+        return set_error(WOS_ENOTSUP, "triangle meshes take the step radius r = dist only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON && !curved)
         return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes, polygons, discs, annuli, balls "
                                       "and discs / balls with holes only");
@@ -632,8 +685,124 @@ static double domain_scale(const wos_geometry *g)
     case WOS_BOX: case WOS_PERFBOX:
         for (int a = 0; a < 2 * g->dim; ++a) s = std::max(s, std::fabs(p[a]));
         break;
+    case WOS_TRIMESH:
+        for (size_t e = 0; e < 9 * static_cast<size_t>(g->n_verts); ++e) s = std::max(s, std::fabs(g->verts[e]));
+        break;
     }
     return std::max(s, 1e-30);
+}
+
+// Bounding-volume hierarchy of a triangle mesh and its device records, appended to segs (read from
+// HBM, not staged in LDS): the nodes depth first (first child next, `skip` past the subtree), leaves of
+// at most 4 triangles split at the median centroid along the longest axis of the centroids' box; FP32
+// boxes rounded outward; then the FP32 and the FP64 triangle records in leaf order.
+namespace {
+struct BvhBuild {
+    const double *v;
+    std::vector<int> idx;
+    std::vector<MeshNode> nodes;
+    double tri_lo(int t, int k) const { return std::min({v[9 * t + k], v[9 * t + 3 + k], v[9 * t + 6 + k]}); }
+    double tri_hi(int t, int k) const { return std::max({v[9 * t + k], v[9 * t + 3 + k], v[9 * t + 6 + k]}); }
+    double cen(int t, int k) const { return (v[9 * t + k] + v[9 * t + 3 + k] + v[9 * t + 6 + k]) / 3.0; }
+    void build(int b, int e)
+    {
+        const int me = static_cast<int>(nodes.size());
+        nodes.push_back(MeshNode{});
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = b; q < e; ++q)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], tri_lo(idx[q], k));
+                hi[k] = std::max(hi[k], tri_hi(idx[q], k));
+                clo[k] = std::min(clo[k], cen(idx[q], k));
+                chi[k] = std::max(chi[k], cen(idx[q], k));
+            }
+        MeshNode nd{};
+        for (int k = 0; k < 3; ++k) {
+            float fl = static_cast<float>(lo[k]), fh = static_cast<float>(hi[k]);
+            if (static_cast<double>(fl) > lo[k]) fl = std::nextafter(fl, -INFINITY);
+            if (static_cast<double>(fh) < hi[k]) fh = std::nextafter(fh, INFINITY);
+            nd.lo[k] = fl;
+            nd.hi[k] = fh;
+        }
+        if (e - b <= 4) {
+            nd.leaf = (b << 3) | (e - b);
+        } else {
+            int ax = 0;
+            for (int k = 1; k < 3; ++k)
+                if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+            const int mid = (b + e) / 2;
+            std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e,
+                             [&](int s, int u) { return cen(s, ax) < cen(u, ax) || (cen(s, ax) == cen(u, ax) && s < u); });
+            nd.leaf = -1;
+            build(b, mid);
+            build(mid, e);
+        }
+        nd.skip = static_cast<int32_t>(nodes.size());
+        nodes[me] = nd;
+    }
+};
+}  // namespace
+
+static void mesh_records(const wos_geometry *g, DevInst &I, std::vector<PolySeg> &segs, double scale)
+{
+    const int nt = g->n_verts;
+    BvhBuild B{g->verts, std::vector<int>(nt), {}};
+    for (int t = 0; t < nt; ++t) B.idx[t] = t;
+    B.build(0, nt);
+    const size_t nn = B.nodes.size();
+    const size_t base = segs.size();
+    I.mesh_off[0] = static_cast<int32_t>(base);
+    I.mesh_off[1] = static_cast<int32_t>(nn);
+    I.mesh_off[2] = static_cast<int32_t>(base + (nn + 1) / 2);
+    I.mesh_off[3] = static_cast<int32_t>(I.mesh_off[2] + 2 * static_cast<size_t>(nt));
+    segs.resize(static_cast<size_t>(I.mesh_off[3]) + 2 * static_cast<size_t>(nt));
+    std::memcpy(segs.data() + base, B.nodes.data(), nn * sizeof(MeshNode));
+    MeshTri32 *t32 = reinterpret_cast<MeshTri32 *>(segs.data() + I.mesh_off[2]);
+    MeshTri64 *t64 = reinterpret_cast<MeshTri64 *>(segs.data() + I.mesh_off[3]);
+    for (int q = 0; q < nt; ++q) {
+        const int t = B.idx[q];
+        const double *a = g->verts + 9 * static_cast<size_t>(t), *b = a + 3, *c = a + 6;
+        MeshTri64 &D = t64[q];
+        std::memset(&D, 0, sizeof D);
+        for (int k = 0; k < 3; ++k) {
+            D.a[k] = a[k];
+            D.b[k] = b[k];
+            D.c[k] = c[k];
+        }
+        D.orig = t;
+        double e[3][3], n[3];
+        for (int k = 0; k < 3; ++k) {
+            e[0][k] = b[k] - a[k];
+            e[1][k] = c[k] - b[k];
+            e[2][k] = a[k] - c[k];
+        }
+        n[0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+        n[1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+        n[2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+        const double nl = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) n[k] /= nl;
+        auto f4 = [](double x, double y, double z, float w) {
+            return float4{static_cast<float>(x), static_cast<float>(y), static_cast<float>(z), w};
+        };
+        MeshTri32 &F = t32[q];
+        F.a = f4(a[0], a[1], a[2], 0.0f);
+        float4 *E[3] = {&F.e0, &F.e1, &F.e2}, *Mv[3] = {&F.m0, &F.m1, &F.m2};
+        for (int s = 0; s < 3; ++s) {
+            const double ll = e[s][0] * e[s][0] + e[s][1] * e[s][1] + e[s][2] * e[s][2];
+            *E[s] = f4(e[s][0], e[s][1], e[s][2], static_cast<float>(1.0 / ll));
+            // n x e: the inward normal of edge s within the plane
+            *Mv[s] = f4(n[1] * e[s][2] - n[2] * e[s][1], n[2] * e[s][0] - n[0] * e[s][2], n[0] * e[s][1] - n[1] * e[s][0], 0.0f);
+        }
+        int32_t ob = t;
+        float ow;
+        std::memcpy(&ow, &ob, 4);
+        F.n = f4(n[0], n[1], n[2], ow);
+    }
+    // pruning margins: far above the rounding of a distance (FP64: some 100 units of 2^-53 of the
+    // coordinate scale; FP32: the box gap's few units of 2^-24)
+    I.mesh_m64 = std::ldexp(scale, -40);
+    I.mesh_m32 = static_cast<float>(std::ldexp(scale, -20));
 }
 
 wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n_elem, DevInst &I,
@@ -686,7 +855,8 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
     // largest coordinate magnitude: differences, squares, one hardware square root (2 ulps) and one
     // subtraction cost at most about 5 such units for circles, spheres and boxes, about 8 for the
     // ellipse gauge and the segment distances of a polygon.
-    const int dexp = (g->kind == WOS_ELLIPSE || g->kind == WOS_POLYGON) ? -19 : -20;
+    // Triangle meshes: 64 units (a CPU replay of the FP32 triangle distance in the tests stays below 8).
+    const int dexp = g->kind == WOS_TRIMESH ? -18 : (g->kind == WOS_ELLIPSE || g->kind == WOS_POLYGON) ? -19 : -20;
     const double delta = std::ldexp(domain_scale(g), dexp);
     I.delta = static_cast<float>(delta);
     I.neg2delta = -2.0f * I.delta;
@@ -839,6 +1009,10 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
         }
     }
     I.n_segs = static_cast<int32_t>(segs.size());
+    if (g->kind == WOS_TRIMESH) {
+        I.n_verts = g->n_verts;
+        mesh_records(g, I, segs, domain_scale(g));
+    }
     // Bauer node tables of the spheres with layout (n, 0), after the staged records (not staged)
     auto add_nodes = [&](int n, int slot) {
         std::vector<double> u;
@@ -889,7 +1063,7 @@ extern "C" wos_status wos_set_tuning(wos_ctx *ctx, int32_t dim, int32_t kind, in
     if (!ctx) return set_error(WOS_EINVAL, "ctx is NULL");
     if (!valid_tuning(t))
         return set_error(WOS_EINVAL, "block must be 64..1024 (power of two), walks_per_lane 1..4096, items a wos_item_mode");
-    if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > WOS_PERFBOX)
+    if ((dim != 2 && dim != 3) || precision < 0 || precision > 1 || kind < -1 || kind > WOS_TRIMESH)
         return set_error(WOS_EINVAL, "bad (dim, kind, precision)");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tuning[tune_key(dim, kind, precision)] = *t;
@@ -1127,7 +1301,8 @@ wos_status wos::group_jobs(const wos_measure_job *jobs, int n, std::vector<std::
         wos_status st = check_job(&jobs[q]);
         if (st != WOS_OK) return set_error(st, "job %d: %s", q, wos_last_error());
         if (jobs[q].n_obs == 0 || jobs[q].walk.walk_end == jobs[q].walk.walk_begin) continue;  // nothing to do
-        by[jobs[q].walk.precision * 4 + jobs[q].geom.dim].push_back(q);
+        // meshes launch on their own (their compiled kernel is not part of the mixed-kind ones)
+        by[jobs[q].walk.precision * 4 + jobs[q].geom.dim + (jobs[q].geom.kind == WOS_TRIMESH ? 16 : 0)].push_back(q);
     }
     for (auto &kv : by) groups.push_back(kv.second);
     return WOS_OK;

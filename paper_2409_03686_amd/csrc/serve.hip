@@ -639,9 +639,8 @@ extern "C" wos_status wos_serve_submit(wos_ctx *ctx, const wos_request *req, uin
     j->req.uD_host = j->uD.data();
     j->req.u0_host = n0 ? j->u0.data() : nullptr;
     j->req.gamma1_mask_host = j->mask.data();
-    if (req->geom.verts && req->geom.n_verts > 0) {  // polygon vertices / holes of a perforated domain
-        const bool holes = req->geom.kind == WOS_PERFORATED || req->geom.kind == WOS_PERFBOX;
-        const size_t nv = static_cast<size_t>(req->geom.n_verts) * (holes ? req->geom.dim + 1 : 2);
+    if (req->geom.verts && req->geom.n_verts > 0) {  // polygon vertices, holes, or mesh triangles
+        const size_t nv = wos::vertex_doubles(&req->geom);
         j->verts.assign(req->geom.verts, req->geom.verts + nv);
         j->req.geom.verts = j->verts.data();
     }

@@ -274,7 +274,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
     double x0d[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) x0d[a] = I.x_obs[static_cast<size_t>(point) * DIM + a];
-    const double d0d = dist64<KIND, DIM>(I, x0d, segs);
+    const double d0d = start_dist64<KIND, DIM>(I, x0d, segs);  // every thread of the block, converged
 
     if (!(d0d > I.eps)) {
         // The start point lies in the eps-shell (or outside D): every walk stops with zero steps
@@ -608,7 +608,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
             double x0d[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) x0d[a] = I.x_obs[static_cast<size_t>(point) * DIM + a];
-            const double d0d = dist64<KIND, DIM>(I, x0d, segs);
+            const double d0d = start_dist64<KIND, DIM>(I, x0d, segs);  // the whole wave, converged
             if (!(d0d > I.eps)) {
                 const int j0 = element64<KIND, DIM>(I, x0d, segs);
                 if (lane == 0) {
@@ -1019,6 +1019,7 @@ template <typename R> static const void *kernel_of(int dim, int ksel, int wave)
     case kPerfBox: return kptr<R, 3, kPerfBox>(wave);
     case kRadiusVariant + kPerfBox: return kptr<R, 3, kRadiusVariant + kPerfBox>(wave);
     case kBox: return kptr<R, 3, kBox>(wave);
+    case kTriMesh: return kptr<R, 3, kTriMesh>(wave);  // meshes always launch on their own
     default: return kptr<R, 3, -1>(wave);
     }
 }

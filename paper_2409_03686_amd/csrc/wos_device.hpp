@@ -12,7 +12,8 @@
 namespace wos {
 
 enum Kind : int32_t {
-    kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5, kPerforated = 6, kPerfBox = 7
+    kDisk = 0, kAnnulus = 1, kEllipse = 2, kPolygon = 3, kBall = 4, kBox = 5, kPerforated = 6, kPerfBox = 7,
+    kTriMesh = 8
 };
 
 constexpr int kMaxPolyVerts = 64;
@@ -35,6 +36,10 @@ struct alignas(16) DevInst {
     int32_t n_segs, pad0;  // PolySeg records to stage in LDS: n_verts, or 2 n_verts with the mapped edges
     int32_t node_off[2];   // record index in segs of the Bauer node table (unit vectors in ax, ay, ey) of
                            // the outer sphere / of the holes, for sphere layouts (n, 0); read from HBM
+    int32_t mesh_off[4];   // triangle meshes (read from HBM): record index in segs of the BVH nodes, the
+                           // node count, record index of the FP32 and of the FP64 triangle records
+    double mesh_m64;       // pruning margin of the FP64 nearest-triangle search (a distance)
+    float mesh_m32;        // the same for the FP32 search
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
     double msig2;     // ellipse, mapped bound: |A^{-1} S|^2 (A = diag(a, b))
@@ -175,6 +180,216 @@ template <> struct RT<float> {
 template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 
 // ------------------------------------------------------------------------------------------
+// Triangle meshes.  The surface's triangles sit in a bounding-volume hierarchy stored depth first:
+// a node's first child follows it, `skip` is the node after its subtree, so a search that drops a
+// subtree jumps to `skip` and needs no stack.  Leaves hold up to 7 consecutive triangles.  Boxes are
+// FP32, rounded outward, so they contain their triangles exactly.
+// ------------------------------------------------------------------------------------------
+struct MeshNode {
+    float lo[3];
+    int32_t skip;
+    float hi[3];
+    int32_t leaf;  // (first triangle << 3) | count for a leaf, -1 for an inner node
+};
+// FP32 record: corner a, edges e0 = b - a, e1 = c - b, e2 = a - c (w: 1 / |e|^2), the unit normal n
+// (w: the triangle's original index as bits), and the in-plane inward edge normals n x e_k.
+struct MeshTri32 {
+    float4 a, e0, e1, e2, n, m0, m1, m2;
+};
+// FP64 record: the corners as given (all derived quantities are computed from them per query).
+struct MeshTri64 {
+    double a[3], b[3], c[3];
+    int32_t orig, pad0;
+    double pad[6];
+};
+static_assert(sizeof(MeshNode) == 32 && sizeof(MeshTri32) == 128 && sizeof(MeshTri64) == 128, "mesh records");
+
+__device__ __forceinline__ double dot3d(const double *u, const double *v)
+{
+#pragma clang fp contract(off)
+    return u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+}
+__device__ __forceinline__ void cross3d(const double *u, const double *v, double *w)
+{
+#pragma clang fp contract(off)
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+// distance from x to the segment p + t e (t in [0, 1]), w = x - p
+__device__ __forceinline__ double seg3_dist64(const double *w, const double *e)
+{
+#pragma clang fp contract(off)
+    double t = dot3d(w, e) / dot3d(e, e);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    double q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[k] = w[k] - t * e[k];
+    return __builtin_sqrt(dot3d(q, q));
+}
+// Distance from x to the triangle (a, b, c): the plane distance |n.(x - a)| / |n|, n = (b - a) x
+// (c - b), when the projection of x onto the plane lies on the inner side of all three edge lines
+// (within the plane the inner side of edge e is where n x e points); else the nearest of the
+// three edges.
+__device__ __forceinline__ double tri_dist64(const MeshTri64 &T, const double *x)
+{
+#pragma clang fp contract(off)
+    double e0[3], e1[3], e2[3], ap[3], bp[3], cp[3], n[3], m[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e0[k] = T.b[k] - T.a[k];
+        e1[k] = T.c[k] - T.b[k];
+        e2[k] = T.a[k] - T.c[k];
+        ap[k] = x[k] - T.a[k];
+        bp[k] = x[k] - T.b[k];
+        cp[k] = x[k] - T.c[k];
+    }
+    cross3d(e0, e1, n);
+    cross3d(n, e0, m);
+    bool inside = dot3d(m, ap) >= 0.0;
+    cross3d(n, e1, m);
+    inside = inside && dot3d(m, bp) >= 0.0;
+    cross3d(n, e2, m);
+    inside = inside && dot3d(m, cp) >= 0.0;
+    if (inside) return __builtin_fabs(dot3d(n, ap)) / __builtin_sqrt(dot3d(n, n));
+    double d = seg3_dist64(ap, e0);
+    const double d1 = seg3_dist64(bp, e1), d2 = seg3_dist64(cp, e2);
+    d = d1 < d ? d1 : d;
+    return d2 < d ? d2 : d;
+}
+
+__device__ __forceinline__ const MeshNode *mesh_nodes(const DevInst &I)
+{
+    return reinterpret_cast<const MeshNode *>(I.segs + I.mesh_off[0]);
+}
+
+// Nearest triangle in FP64: the distance and the original index of the nearest triangle (the lowest
+// among equally near ones, as a scan of all triangles in index order finds).  A subtree is dropped
+// only when its box lies farther than the best distance plus a margin that covers the rounding of
+// both distances, so the search returns exactly what the full scan returns.
+__device__ __forceinline__ double mesh_dist64(const DevInst &I, const double *x, int *orig_out)
+{
+#pragma clang fp contract(off)
+    const MeshNode *nodes = mesh_nodes(I);
+    const MeshTri64 *tris = reinterpret_cast<const MeshTri64 *>(I.segs + I.mesh_off[3]);
+    const int nn = I.mesh_off[1];
+    double best = __builtin_inf(), lim = __builtin_inf();
+    int bo = 0x7FFFFFFF;
+    for (int i = 0; i < nn;) {
+        const MeshNode nd = nodes[i];
+        double g2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double lo = static_cast<double>(nd.lo[k]) - x[k], hi = x[k] - static_cast<double>(nd.hi[k]);
+            const double gk = lo > hi ? lo : hi;
+            if (gk > 0.0) g2 += gk * gk;
+        }
+        if (g2 > lim) {
+            i = nd.skip;
+            continue;
+        }
+        if (nd.leaf >= 0) {
+            const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
+            for (int q = first; q < first + cnt; ++q) {
+                const double d = tri_dist64(tris[q], x);
+                const int o = tris[q].orig;
+                if (d < best || (d == best && o < bo)) {
+                    best = d;
+                    bo = o;
+                    lim = (best + I.mesh_m64) * (best + I.mesh_m64);
+                }
+            }
+            i = nd.skip;
+        } else {
+            ++i;
+        }
+    }
+    if (orig_out) *orig_out = bo;
+    return best;
+}
+
+// Squared distance to a triangle in FP32 (the same definition; the projection test and the edge
+// projections use the record's precomputed normals and inverse squared lengths).
+__device__ __forceinline__ float tri_dist2_32(const MeshTri32 &T, const float *x)
+{
+    const float ap0 = x[0] - T.a.x, ap1 = x[1] - T.a.y, ap2 = x[2] - T.a.z;
+    const float bp0 = ap0 - T.e0.x, bp1 = ap1 - T.e0.y, bp2 = ap2 - T.e0.z;
+    const float cp0 = bp0 - T.e1.x, cp1 = bp1 - T.e1.y, cp2 = bp2 - T.e1.z;
+    const float s0 = __builtin_fmaf(T.m0.z, ap2, __builtin_fmaf(T.m0.y, ap1, T.m0.x * ap0));
+    const float s1 = __builtin_fmaf(T.m1.z, bp2, __builtin_fmaf(T.m1.y, bp1, T.m1.x * bp0));
+    const float s2 = __builtin_fmaf(T.m2.z, cp2, __builtin_fmaf(T.m2.y, cp1, T.m2.x * cp0));
+    const float dp = __builtin_fmaf(T.n.z, ap2, __builtin_fmaf(T.n.y, ap1, T.n.x * ap0));
+    auto seg = [](float w0, float w1, float w2, const float4 &e) {
+        float t = __builtin_fmaf(e.z, w2, __builtin_fmaf(e.y, w1, e.x * w0)) * e.w;
+        t = __builtin_fminf(__builtin_fmaxf(t, 0.0f), 1.0f);
+        const float q0 = __builtin_fmaf(-t, e.x, w0), q1 = __builtin_fmaf(-t, e.y, w1), q2 = __builtin_fmaf(-t, e.z, w2);
+        return __builtin_fmaf(q2, q2, __builtin_fmaf(q1, q1, q0 * q0));
+    };
+    const float de = __builtin_fminf(seg(ap0, ap1, ap2, T.e0), __builtin_fminf(seg(bp0, bp1, bp2, T.e1), seg(cp0, cp1, cp2, T.e2)));
+    const bool inside = s0 >= 0.0f && s1 >= 0.0f && s2 >= 0.0f;
+    return inside ? dp * dp : de;
+}
+
+// Distance to the mesh in FP32 (within the FP32 error bound of the instance).
+__device__ __forceinline__ float mesh_dist32(const DevInst &I, const float *x)
+{
+    const MeshNode *nodes = mesh_nodes(I);
+    const MeshTri32 *tris = reinterpret_cast<const MeshTri32 *>(I.segs + I.mesh_off[2]);
+    const int nn = I.mesh_off[1];
+    float best2 = __builtin_inff(), lim = __builtin_inff();
+    for (int i = 0; i < nn;) {
+        const MeshNode nd = nodes[i];
+        float g2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float gk = __builtin_fmaxf(__builtin_fmaxf(nd.lo[k] - x[k], x[k] - nd.hi[k]), 0.0f);
+            g2 = __builtin_fmaf(gk, gk, g2);
+        }
+        if (g2 > lim) {
+            i = nd.skip;
+            continue;
+        }
+        if (nd.leaf >= 0) {
+            const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
+            for (int q = first; q < first + cnt; ++q) best2 = __builtin_fminf(best2, tri_dist2_32(tris[q], x));
+            const float b = __builtin_amdgcn_sqrtf(best2) + I.mesh_m32;
+            lim = b * b;
+            i = nd.skip;
+        } else {
+            ++i;
+        }
+    }
+    return __builtin_amdgcn_sqrtf(best2);
+}
+
+// Inside test of a start point (all 64 lanes of the wave call it with the same x): the winding
+// number of the surface about x, from the solid angles of the triangles seen from x (Van Oosterom and
+// Strackee: 2 atan2(A.(B x C), |A||B||C| + (A.B)|C| + (A.C)|B| + (B.C)|A|) for corners A, B, C
+// relative to x), lanes taking every 64th triangle; inside when the total exceeds 2 pi (winding 1/2).
+__device__ __forceinline__ bool mesh_inside_wave(const DevInst &I, const double *x)
+{
+#pragma clang fp contract(off)
+    const MeshTri64 *tris = reinterpret_cast<const MeshTri64 *>(I.segs + I.mesh_off[3]);
+    double acc = 0.0;
+    for (int t = static_cast<int>(__lane_id()); t < I.n_verts; t += 64) {
+        double A[3], B[3], C[3], bc[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] = tris[t].a[k] - x[k];
+            B[k] = tris[t].b[k] - x[k];
+            C[k] = tris[t].c[k] - x[k];
+        }
+        const double la = __builtin_sqrt(dot3d(A, A)), lb = __builtin_sqrt(dot3d(B, B)), lc = __builtin_sqrt(dot3d(C, C));
+        cross3d(B, C, bc);
+        const double den = la * lb * lc + dot3d(A, B) * lc + dot3d(A, C) * lb + dot3d(B, C) * la;
+        acc += 2.0 * atan2(dot3d(A, bc), den);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    return acc > kTwoPi;
+}
+
+// ------------------------------------------------------------------------------------------
 // Signed distance to dD, positive inside.  FP64 instantiations keep the evaluation order of the
 // plain definition (no contraction), FP32 ones are the bulk path of the FP32-geometry mode.
 // ------------------------------------------------------------------------------------------
@@ -277,6 +492,10 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += (x[a] - I.p[a]) * (x[a] - I.p[a]);
         return I.p[3] - __builtin_sqrt(s);
+    } else if constexpr (KIND == kTriMesh) {
+        // unsigned: walks start inside (an outside start point is decided by the winding number at
+        // the start) and every step stays within the distance
+        return mesh_dist64(I, x, nullptr);
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
         // the nearest of the outer boundary and the holes
         double best = outer_dist64<KIND, DIM>(I, x), v[DIM];
@@ -332,6 +551,8 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
         return __builtin_amdgcn_sqrtf(best);
     } else if constexpr (KIND == kBall) {
         return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    } else if constexpr (KIND == kTriMesh) {
+        return mesh_dist32(I, x);
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
         float best;
         if constexpr (KIND == kPerforated) {  // centred positions
@@ -940,9 +1161,23 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
         double v[3];
         for (int a = 0; a < 3; ++a) v[a] = x[a] - I.p[a];
         return sphere_cell_of(v, I.layout[0], I.layout[1], I.p[3], I.segs + I.node_off[0]);
+    } else if constexpr (KIND == kTriMesh) {  // the nearest triangle; layout[0] triangles per element
+        int o = 0;
+        (void)mesh_dist64(I, x, &o);
+        return o / I.layout[0];
     } else {  // kBox
         return box_cell<DIM>(I, x);
     }
+}
+
+// Signed distance of a start point.  For a mesh the unsigned distance gets the sign of the winding-number
+// test; all 64 lanes of the wave must call this together (with the same x).
+template <int KIND, int DIM> __device__ __forceinline__ double start_dist64(const DevInst &I, const double *x,
+                                                                           const PolySeg *segs)
+{
+    const double d = dist64<KIND, DIM>(I, x, segs);
+    if constexpr (KIND == kTriMesh) return mesh_inside_wave(I, x) ? d : -d;
+    return d;
 }
 
 }  // namespace wos

@@ -57,6 +57,7 @@ void live_server_stop(wos_ctx *ctx);  // stops and frees the context's live serv
 wos_status ctx_malloc(wos_ctx *ctx, void **p, size_t bytes);
 void ctx_free(wos_ctx *ctx, void *p, size_t bytes);
 wos_status validate_geometry(const wos_geometry *g, int *n_elem);
+size_t vertex_doubles(const wos_geometry *g);  // numbers in g->verts for its kind
 wos_status validate_walk(const wos_geometry *g, const wos_walk_params *w);
 // S = (K / lambda_max)^{1/2} (symmetric root); optionally its eigenvectors (row-major, column k the
 // k-th) and eigenvalues

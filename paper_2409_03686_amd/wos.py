@@ -24,7 +24,7 @@ WOS_RADIUS_WOE_BOUND, WOS_RADIUS_MAPPED_EXACT, WOS_RADIUS_MAPPED_BOUND = 0, 1, 2
 WOS_TSVD_RANK, WOS_TSVD_DISCREPANCY, WOS_TIKHONOV = 0, 1, 2
 WOS_STATS_WORDS = 8
 STAT_NAMES = ["walks", "steps", "max_steps", "cap_hits", "escapes", "fp64_evals", "lane_slots", "reserved"]
-WOS_DISK, WOS_ANNULUS, WOS_ELLIPSE, WOS_POLYGON, WOS_BALL, WOS_BOX, WOS_PERFORATED, WOS_PERFBOX = range(8)
+WOS_DISK, WOS_ANNULUS, WOS_ELLIPSE, WOS_POLYGON, WOS_BALL, WOS_BOX, WOS_PERFORATED, WOS_PERFBOX, WOS_TRIMESH = range(9)
 WOS_MAX_POLY_VERTS = 64
 WOS_MAX_HOLES = 32
 WOS_MAX_ELEMENTS = 16384
@@ -183,7 +183,8 @@ def geometry(g) -> WosGeometry:
         v = np.ascontiguousarray(np.asarray(g.verts, np.float64).ravel())
         s._keep = v
         s.verts = v.ctypes.data_as(C.POINTER(C.c_double))
-        s.n_verts = len(v) // (int(g.dim) + 1) if int(g.kind) in (WOS_PERFORATED, WOS_PERFBOX) else len(v) // 2
+        s.n_verts = (len(v) // (int(g.dim) + 1) if int(g.kind) in (WOS_PERFORATED, WOS_PERFBOX) else
+                     len(v) // 9 if int(g.kind) == WOS_TRIMESH else len(v) // 2)
     return s
 
 

@@ -55,6 +55,9 @@ def _geoms():
         wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 2.0, 1.0), (6, 64, 0),
                     verts=np.array([[0.3, 0.5, 0.5, 0.2], [0.6, 1.4, 0.5, 0.25]])),
         wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.3), (2000, 0)),
+        wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh([0.0, 0.0, 0.0], [1.0, 2.0, 0.5], 5)),
+        wi.Geometry(3, wi.TRIMESH, (), (1,), verts=wi.sphere_mesh([0.1, 0.0, 0.0], 0.7, 2)),
+        wi.Geometry(3, wi.TRIMESH, (), (4,), verts=wi.l_prism_mesh(4)),
     ]
 
 
@@ -105,6 +108,11 @@ def test_invalid_geometries_are_rejected_on_the_host(wos):
         (wi.Geometry(3, wi.PERFBOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (4, 8), verts=np.array([[0.5, 0.5, 0.5, 0.2]])),
          wos.WOS_EINVAL),                                                                      # 3D hole cells missing
         (wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (8, 0)), wos.WOS_EINVAL),                # < 16 Bauer nodes
+        (wi.Geometry(3, wi.TRIMESH, (), (5,), verts=wi.box_mesh([0, 0, 0], [1, 1, 1], 1)), wos.WOS_EINVAL),  # 5 does not divide 12
+        (wi.Geometry(3, wi.TRIMESH, (), (1,), verts=wi.box_mesh([0, 0, 0], [1, 1, 1], 1)[:3]), wos.WOS_EINVAL),  # < 4 triangles
+        (wi.Geometry(3, wi.TRIMESH, (), (1,), verts=np.concatenate(
+            [wi.box_mesh([0, 0, 0], [1, 1, 1], 1), [[[0, 0, 0], [1, 1, 1], [2, 2, 2]]]])), wos.WOS_EINVAL),  # degenerate
+        (wi.Geometry(2, wi.TRIMESH, (), (1,), verts=wi.box_mesh([0, 0, 0], [1, 1, 1], 1)), wos.WOS_EINVAL),  # dim 2
     ]
     for g, code in bad:
         with pytest.raises(wos.WosError) as e:

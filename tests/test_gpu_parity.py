@@ -1514,3 +1514,91 @@ def test_partitioned_streams_give_the_same_results(wos, ctx):
     finally:
         torch.cuda.synchronize()
         wos.wos_streams_destroy(ctx, walk_s, spec_s)
+
+
+# ------------------------------------------------------------------------------ triangle meshes
+
+def _mesh_case(name):
+    if name == "box":
+        return wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh([0.0, 0.0, 0.0], [1.0, 1.0, 1.0], 12))
+    if name == "sphere":
+        return wi.Geometry(3, wi.TRIMESH, (), (1,), verts=wi.sphere_mesh([0.1, -0.1, 0.2], 0.8, 3))
+    return wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.l_prism_mesh(8))
+
+
+@pytest.mark.parametrize("name", ["box", "sphere", "lprism"])
+def test_trimesh_fp64_walk_for_walk(wos, ctx, name):
+    """Closed triangle meshes (a box as 1728 triangles, an icosphere of 1280, the non-convex L-prism of
+    704) with an anisotropic K, FP64: the device's BVH search returns the oracle's brute-force nearest
+    triangle and distance, so exit cells and step counts agree walk for walk."""
+    g = _mesh_case(name)
+    rng = np.random.default_rng(95)
+    x = wi.sample_points(g, 24, rng)
+    Q = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    K = Q @ np.diag([1.0, 0.4, 0.15]) @ Q.T
+    inst = wi.Instance(g, K, x, 500, eps=1e-4, seed=23, instance_id=2, precision=wi.FP64)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    agree = _agreement(tr, trr)
+    print(f"{name}: {g.n_tri} triangles, FP64 walk agreement {agree:.6f}, steps per walk "
+          f"{st['steps'] / st['walks']:.2f}")
+    assert np.all(c.sum(1) == 500) and st["escapes"] == 0 and sr["escapes"] == 0
+    assert agree >= 0.999 and np.abs(c.astype(np.int64) - cr).sum() <= 0.002 * cr.sum()
+
+
+def test_trimesh_box_equals_the_box_kind_on_the_device(wos, ctx):
+    """FP64 walks on the box as a mesh (two triangles per patch, the BOX kind's patch order) and on
+    the BOX kind itself agree walk for walk on the device."""
+    g = _mesh_case("box")
+    gb = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (12,))
+    x = wi.sample_points(gb, 32, np.random.default_rng(96))
+    K = np.array([[1.0, 0.2, 0.0], [0.2, 0.5, 0.1], [0.0, 0.1, 0.3]])
+    c1, s1, t1 = _gpu(wos, ctx, wi.Instance(g, K, x, 400, eps=1e-4, seed=5, precision=wi.FP64), trace=True)
+    c0, s0, t0 = _gpu(wos, ctx, wi.Instance(gb, K, x, 400, eps=1e-4, seed=5, precision=wi.FP64), trace=True)
+    agree = _agreement(t1, t0)
+    print(f"mesh box vs box kind: agreement {agree:.6f}")
+    assert agree >= 0.999
+
+
+@pytest.mark.parametrize("name", ["box", "lprism"])
+def test_trimesh_fp32_geometry_against_fp64_and_oracle(wos, ctx, name):
+    """FP32 mesh geometry (FP32 BVH search with the FP32 error bound subtracted from every radius, FP64
+    exit band and binning): no escapes, the same exit law as the FP64 walks entry by entry and as the
+    oracle's counts on sampled rows."""
+    g = _mesh_case(name)
+    x = wi.sample_points(g, 16, np.random.default_rng(97))
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.6, -0.2], [0.1, -0.2, 0.4]])
+    N = 20_000
+    c32, s32, _ = _gpu(wos, ctx, wi.Instance(g, K, x, N, eps=1e-4, seed=31, precision=wi.FP32_GEOM_FP64_EXIT))
+    c64, s64, _ = _gpu(wos, ctx, wi.Instance(g, K, x, N, eps=1e-4, seed=32, precision=wi.FP64))
+    assert s32["escapes"] == 0 and np.all(c32.sum(1) == N)
+    rep = statutil.two_sample(c32, N, c64, N)
+    print(f"{name} FP32 vs FP64 {rep}; steps per walk {s32['steps'] / s32['walks']:.2f} / {s64['steps'] / s64['walks']:.2f}")
+    assert rep["ok"], rep
+    rows = np.arange(0, 16, 4)
+    cr, _, _ = ow.build_instance(wi.Instance(g, K, x[rows], 4000, eps=1e-4, seed=33))
+    rep2 = statutil.two_sample(c32[rows], N, cr, 4000)
+    assert rep2["ok"], rep2
+    assert abs(s32["steps"] / s32["walks"] - s64["steps"] / s64["walks"]) < 0.05 * s64["steps"] / s64["walks"]
+
+
+def test_trimesh_start_points_outside_are_escapes(wos, ctx):
+    """Start points outside the L-prism (in the notch, beside it, above it) are escapes binned at once
+    in the oracle's cell; points inside walk normally."""
+    g = _mesh_case("lprism")
+    x = np.array([[0.75, 0.75, 0.5], [1.2, 0.3, 0.5], [0.3, 0.3, 1.1], [0.25, 0.25, 0.5]])
+    for prec in (wi.FP64, wi.FP32_GEOM_FP64_EXIT):
+        c, st, tr = _gpu(wos, ctx, wi.Instance(g, np.eye(3), x, 64, eps=1e-4, seed=1, precision=prec), trace=True)
+        cr, sr, trr = ow.build_instance(wi.Instance(g, np.eye(3), x, 64, eps=1e-4, seed=1), trace=True)
+        assert st["escapes"] == sr["escapes"] == 3 * 64
+        assert np.array_equal(c[:3], cr[:3]) and np.all(tr[:3, :, 1] == 0)
+        assert np.all(tr[3, :, 1] > 0)
+
+
+def test_trimesh_rejects_mapped_radii(wos, ctx):
+    g = _mesh_case("lprism")
+    x = wi.sample_points(g, 4, np.random.default_rng(98))
+    for mode in (wi.RADIUS_MAPPED_EXACT, wi.RADIUS_MAPPED_BOUND):
+        with pytest.raises(wos.WosError) as e:
+            _gpu(wos, ctx, wi.Instance(g, np.eye(3), x, 16, radius_mode=mode, precision=wi.FP64))
+        assert e.value.status == wos.WOS_ENOTSUP
