@@ -203,14 +203,14 @@ struct Fold32 {
 // a walk that stops inside it).
 template <typename R, int DIM, int KIND, int PH, bool CAP, int RV>
 __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], const Fold32 &F,
-                                          R *x, R &d, uint32_t &s, uint32_t &n_fp64)
+                                          R *x, R &d, uint32_t &s, uint32_t &n_fp64, int &hint)
 {
     if constexpr (sizeof(R) == 8) {
         R U[DIM];
         Dir<R, DIM>::template get<PH>(w, U);
         const double r = radius64<KIND, DIM, RV>(I, x, d, segs);
         step64<DIM>(I, x, r, U);
-        d = dist64<KIND, DIM>(I, x, segs);
+        d = dist64<KIND, DIM>(I, x, segs, &hint);
         s += 1;
         if (d > I.eps && s >= I.max_steps) {
             d = -1.0;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
             const float r = __builtin_fmaf(rr, I.rshrink, I.neg2delta);
             step32<DIM>(I, x, r, U);
         }
-        d = dist32<KIND, DIM>(I, x, segs);
+        d = dist32<KIND, DIM>(I, x, segs, &hint);
         if constexpr (CAP) s += 1;
         if (d > I.eps_lo && d <= I.eps_hi) {
             // ambiguous band: decide in FP64 at the stored position
@@ -324,6 +324,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         // memory form would cost a compare and a select per phase).
         constexpr R kFree = static_cast<R>(__builtin_inf());
         uint32_t koff = 0, s = 0;
+        int hint = -1;  // meshes: the walk's last nearest triangle
         R x[DIM];
         R d = kFree;
 #pragma unroll
@@ -363,6 +364,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                     if (d == kFree && mine < res_end) {
                         koff = mine;
                         s = 0;
+                        hint = -1;
                         d = d0;
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
@@ -374,6 +376,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                 if (d == kFree && mine < wave_cnt) {
                     koff = k0 + static_cast<uint32_t>(wv) + nw * mine;
                     s = 0;
+                    hint = -1;
                     d = d0;
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) x[a] = x0[a];
@@ -395,7 +398,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
-                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64);
+                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint);
                 const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
                 fph = fin ? static_cast<uint32_t>(PH) : fph;
                 d = fin ? kFree : d;
@@ -639,6 +642,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
     };
 
     uint32_t koff = 0, s = 0, sl = 0;
+    int hint = -1;  // meshes: the walk's last nearest triangle
     R x[DIM];
     R d = kFree;
 #pragma unroll
@@ -653,6 +657,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
             koff = k0c + mine;
             sl = cur;
             s = 0;
+            hint = -1;
             d = d0c;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) x[a] = x0c[a];
@@ -686,7 +691,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
         auto phase = [&](auto ph_tag, auto cap_tag) {
             constexpr int PH = decltype(ph_tag)::value;
             constexpr bool CAP = decltype(cap_tag)::value;
-            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64);
+            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint);
             const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
             fph = fin ? static_cast<uint32_t>(PH) : fph;
             d = fin ? kFree : d;

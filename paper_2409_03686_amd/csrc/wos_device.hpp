@@ -258,54 +258,117 @@ __device__ __forceinline__ double tri_dist64(const MeshTri64 &T, const double *x
     return d2 < d ? d2 : d;
 }
 
-__device__ __forceinline__ const MeshNode *mesh_nodes(const DevInst &I)
+// The records live in global memory: pointers in the global address space let the compiler use
+// global loads (a generic pointer becomes flat loads, which also wait on the LDS counter).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using GPtr = const __attribute__((address_space(1))) T *;
+#else  // the host pass parses these functions but never emits them
+template <typename T> using GPtr = const T *;
+#endif
+template <typename T> __device__ __forceinline__ GPtr<T> mesh_rec(const DevInst &I, int slot)
 {
-    return reinterpret_cast<const MeshNode *>(I.segs + I.mesh_off[0]);
+    return (GPtr<T>)(I.segs + I.mesh_off[slot]);
+}
+
+// Squared distance from x to a node's box (0 inside it).
+template <typename R> __device__ __forceinline__ R box_gap2(const MeshNode &nd, const R *x)
+{
+#pragma clang fp contract(off)
+    R g2 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R lo = static_cast<R>(nd.lo[k]) - x[k], hi = x[k] - static_cast<R>(nd.hi[k]);
+        R gk = lo > hi ? lo : hi;
+        gk = gk > R(0) ? gk : R(0);
+        g2 += gk * gk;
+    }
+    return g2;
+}
+
+// The leaf reached by always stepping into the child whose box is nearer x (the first child on
+// ties): its triangles give the search a first bound close to the final distance, so that the pass
+// over the hierarchy drops most subtrees at their root.
+__device__ __forceinline__ int mesh_greedy_leaf(GPtr<MeshNode> nodes, const float *xf)
+{
+    int i = 0;
+    MeshNode nd = nodes[0];
+    while (nd.leaf < 0) {
+        const MeshNode l = nodes[i + 1], r = nodes[l.skip];
+        const bool left = box_gap2<float>(l, xf) <= box_gap2<float>(r, xf);
+        i = left ? i + 1 : l.skip;
+        nd = left ? l : r;
+    }
+    return i;
 }
 
 // Nearest triangle in FP64: the distance and the original index of the nearest triangle (the lowest
 // among equally near ones, as a scan of all triangles in index order finds).  A subtree is dropped
 // only when its box lies farther than the best distance plus a margin that covers the rounding of
 // both distances, so the search returns exactly what the full scan returns.
-__device__ __forceinline__ double mesh_dist64(const DevInst &I, const double *x, int *orig_out)
+// Result of a nearest-triangle search: the distance, the triangle's original index (FP64 only) and its
+// position in the hierarchy's triangle order (the next search's hint).
+struct MeshHit64 {
+    double d;
+    int orig, q;
+};
+struct MeshHit32 {
+    float d;
+    int q;
+};
+
+// hint >= 0: the triangle (hierarchy position) nearest the walk's previous position, whose distance
+// starts the search in place of the greedy leaf; the result does not depend on it.
+__device__ __attribute__((noinline)) MeshHit64 mesh_dist64(const DevInst &I, double x0, double x1, double x2,
+                                                          int hint)
 {
 #pragma clang fp contract(off)
-    const MeshNode *nodes = mesh_nodes(I);
-    const MeshTri64 *tris = reinterpret_cast<const MeshTri64 *>(I.segs + I.mesh_off[3]);
+    const double x[3] = {x0, x1, x2};
+    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, 0);
+    const GPtr<MeshTri64> tris = mesh_rec<MeshTri64>(I, 3);
     const int nn = I.mesh_off[1];
     double best = __builtin_inf(), lim = __builtin_inf();
-    int bo = 0x7FFFFFFF;
-    for (int i = 0; i < nn;) {
-        const MeshNode nd = nodes[i];
-        double g2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double lo = static_cast<double>(nd.lo[k]) - x[k], hi = x[k] - static_cast<double>(nd.hi[k]);
-            const double gk = lo > hi ? lo : hi;
-            if (gk > 0.0) g2 += gk * gk;
-        }
-        if (g2 > lim) {
-            i = nd.skip;
-            continue;
-        }
-        if (nd.leaf >= 0) {
-            const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
-            for (int q = first; q < first + cnt; ++q) {
-                const double d = tri_dist64(tris[q], x);
-                const int o = tris[q].orig;
-                if (d < best || (d == best && o < bo)) {
-                    best = d;
-                    bo = o;
-                    lim = (best + I.mesh_m64) * (best + I.mesh_m64);
-                }
+    int bo = 0x7FFFFFFF, bq = 0;
+    // One node or one triangle per iteration (lanes of a wave are at different places of the
+    // search, so an iteration costs the larger of the two, not a whole leaf): the hint's triangle or
+    // the greedy leaf's triangles first, then the pass from the root (that skips the greedy leaf).
+    int g = -1, q, qe, i = 0;
+    if (hint >= 0) {
+        q = hint;
+        qe = hint + 1;
+    } else {
+        const float xf[3] = {static_cast<float>(x[0]), static_cast<float>(x[1]), static_cast<float>(x[2])};
+        g = mesh_greedy_leaf(nodes, xf);
+        q = nodes[g].leaf >> 3;
+        qe = q + (nodes[g].leaf & 7);
+    }
+    while (q < qe || i < nn) {
+        if (q < qe) {
+            const MeshTri64 T = tris[q];
+            const double d = tri_dist64(T, x);
+            const int o = T.orig;
+            if (d < best || (d == best && o < bo)) {
+                best = d;
+                bo = o;
+                bq = q;
+                lim = (best + I.mesh_m64) * (best + I.mesh_m64);
             }
-            i = nd.skip;
+            ++q;
         } else {
-            ++i;
+            const MeshNode nd = nodes[i];
+            if (box_gap2<double>(nd, x) > lim) {
+                i = nd.skip;
+            } else if (nd.leaf >= 0) {
+                if (i != g) {
+                    q = nd.leaf >> 3;
+                    qe = q + (nd.leaf & 7);
+                }
+                i = nd.skip;
+            } else {
+                ++i;
+            }
         }
     }
-    if (orig_out) *orig_out = bo;
-    return best;
+    return MeshHit64{best, bo, bq};
 }
 
 // Squared distance to a triangle in FP32 (the same definition; the projection test and the edge
@@ -331,45 +394,63 @@ __device__ __forceinline__ float tri_dist2_32(const MeshTri32 &T, const float *x
 }
 
 // Distance to the mesh in FP32 (within the FP32 error bound of the instance).
-__device__ __forceinline__ float mesh_dist32(const DevInst &I, const float *x)
+__device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, float x0, float x1, float x2, int hint)
 {
-    const MeshNode *nodes = mesh_nodes(I);
-    const MeshTri32 *tris = reinterpret_cast<const MeshTri32 *>(I.segs + I.mesh_off[2]);
+    const float x[3] = {x0, x1, x2};
+    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, 0);
+    const GPtr<MeshTri32> tris = mesh_rec<MeshTri32>(I, 2);
     const int nn = I.mesh_off[1];
     float best2 = __builtin_inff(), lim = __builtin_inff();
-    for (int i = 0; i < nn;) {
-        const MeshNode nd = nodes[i];
-        float g2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float gk = __builtin_fmaxf(__builtin_fmaxf(nd.lo[k] - x[k], x[k] - nd.hi[k]), 0.0f);
-            g2 = __builtin_fmaf(gk, gk, g2);
-        }
-        if (g2 > lim) {
-            i = nd.skip;
-            continue;
-        }
-        if (nd.leaf >= 0) {
-            const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
-            for (int q = first; q < first + cnt; ++q) best2 = __builtin_fminf(best2, tri_dist2_32(tris[q], x));
-            const float b = __builtin_amdgcn_sqrtf(best2) + I.mesh_m32;
-            lim = b * b;
-            i = nd.skip;
+    int bq = 0;
+    // one node or one triangle per iteration, the hint's triangle or the greedy leaf first, as in the
+    // FP64 search
+    int g = -1, q, qe, i = 0;
+    if (hint >= 0) {
+        q = hint;
+        qe = hint + 1;
+    } else {
+        g = mesh_greedy_leaf(nodes, x);
+        q = nodes[g].leaf >> 3;
+        qe = q + (nodes[g].leaf & 7);
+    }
+    while (q < qe || i < nn) {
+        if (q < qe) {
+            const MeshTri32 T = tris[q];
+            const float d2 = tri_dist2_32(T, x);
+            if (d2 < best2) {
+                best2 = d2;
+                bq = q;
+                const float b = __builtin_amdgcn_sqrtf(best2) + I.mesh_m32;
+                lim = b * b;
+            }
+            ++q;
         } else {
-            ++i;
+            const MeshNode nd = nodes[i];
+            if (box_gap2<float>(nd, x) > lim) {
+                i = nd.skip;
+            } else if (nd.leaf >= 0) {
+                if (i != g) {
+                    q = nd.leaf >> 3;
+                    qe = q + (nd.leaf & 7);
+                }
+                i = nd.skip;
+            } else {
+                ++i;
+            }
         }
     }
-    return __builtin_amdgcn_sqrtf(best2);
+    return MeshHit32{__builtin_amdgcn_sqrtf(best2), bq};
 }
 
 // Inside test of a start point (all 64 lanes of the wave call it with the same x): the winding
 // number of the surface about x, from the solid angles of the triangles seen from x (Van Oosterom and
 // Strackee: 2 atan2(A.(B x C), |A||B||C| + (A.B)|C| + (A.C)|B| + (B.C)|A|) for corners A, B, C
 // relative to x), lanes taking every 64th triangle; inside when the total exceeds 2 pi (winding 1/2).
-__device__ __forceinline__ bool mesh_inside_wave(const DevInst &I, const double *x)
+__device__ __attribute__((noinline)) bool mesh_inside_wave(const DevInst &I, double x0, double x1, double x2)
 {
 #pragma clang fp contract(off)
-    const MeshTri64 *tris = reinterpret_cast<const MeshTri64 *>(I.segs + I.mesh_off[3]);
+    const double x[3] = {x0, x1, x2};
+    const GPtr<MeshTri64> tris = mesh_rec<MeshTri64>(I, 3);
     double acc = 0.0;
     for (int t = static_cast<int>(__lane_id()); t < I.n_verts; t += 64) {
         double A[3], B[3], C[3], bc[3];
@@ -452,8 +533,9 @@ template <int DIM> __device__ __forceinline__ double hole_dist64(const PolySeg &
     return __builtin_sqrt(s) - h.ex;
 }
 
+// hint (meshes only, may be null): in, the walk's previous nearest triangle (or -1); out, this one's
 template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevInst &I, const double *x,
-                                                                      const PolySeg *segs)
+                                                                      const PolySeg *segs, int *hint = nullptr)
 {
 #pragma clang fp contract(off)
     if constexpr (KIND == kDisk) {
@@ -495,7 +577,9 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
     } else if constexpr (KIND == kTriMesh) {
         // unsigned: walks start inside (an outside start point is decided by the winding number at
         // the start) and every step stays within the distance
-        return mesh_dist64(I, x, nullptr);
+        const MeshHit64 h = mesh_dist64(I, x[0], x[1], x[2], hint ? *hint : -1);
+        if (hint) *hint = h.q;
+        return h.d;
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
         // the nearest of the outer boundary and the holes
         double best = outer_dist64<KIND, DIM>(I, x), v[DIM];
@@ -529,7 +613,7 @@ template <typename R, int KIND> __device__ __forceinline__ double origin(const D
 }
 
 template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevInst &I, const float *x,
-                                                                     const PolySeg *segs)
+                                                                     const PolySeg *segs, int *hint = nullptr)
 {
     if constexpr (KIND == kDisk) {
         return I.pf[2] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1]);
@@ -552,7 +636,9 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
     } else if constexpr (KIND == kBall) {
         return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     } else if constexpr (KIND == kTriMesh) {
-        return mesh_dist32(I, x);
+        const MeshHit32 h = mesh_dist32(I, x[0], x[1], x[2], hint ? *hint : -1);
+        if (hint) *hint = h.q;
+        return h.d;
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
         float best;
         if constexpr (KIND == kPerforated) {  // centred positions
@@ -1162,9 +1248,7 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
         for (int a = 0; a < 3; ++a) v[a] = x[a] - I.p[a];
         return sphere_cell_of(v, I.layout[0], I.layout[1], I.p[3], I.segs + I.node_off[0]);
     } else if constexpr (KIND == kTriMesh) {  // the nearest triangle; layout[0] triangles per element
-        int o = 0;
-        (void)mesh_dist64(I, x, &o);
-        return o / I.layout[0];
+        return mesh_dist64(I, x[0], x[1], x[2], -1).orig / I.layout[0];
     } else {  // kBox
         return box_cell<DIM>(I, x);
     }
@@ -1176,7 +1260,7 @@ template <int KIND, int DIM> __device__ __forceinline__ double start_dist64(cons
                                                                            const PolySeg *segs)
 {
     const double d = dist64<KIND, DIM>(I, x, segs);
-    if constexpr (KIND == kTriMesh) return mesh_inside_wave(I, x) ? d : -d;
+    if constexpr (KIND == kTriMesh) return mesh_inside_wave(I, x[0], x[1], x[2]) ? d : -d;
     return d;
 }
 
