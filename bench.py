@@ -111,6 +111,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
+    p.add_argument("--no-mesh", action="store_true", help="skip the triangle-mesh measurement")
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1, 2),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping), "
@@ -358,6 +359,46 @@ def bench_batch(ctx, wos, wi, torch, reps=3):
 
 
 # ----------------------------------------------------------------------------------------- cube
+
+def bench_mesh(ctx, wos, wi, torch, box_steps_per_s, walks=10_000, reps=2):
+    """The cube workload's domain as a closed triangle mesh (each of the 3456 patches two triangles:
+    6912 triangles, the same cells), its 4096 points and K, 1e4 walks per point, r = dist: the walk
+    kernel with the BVH nearest-triangle search in FP32 and FP64, beside the box kind's closed-form
+    distance at r = dist (the same chain)."""
+    inst = wi.cfg3_cube(n_walks=walks)
+    g = inst.geom
+    gm = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh(np.array(g.params[:3]), np.array(g.params[3:6]),
+                                                                 g.layout[0]))
+    M = gm.n_elem
+    n_obs = inst.x_obs.shape[0]
+    x = wos.device_inputs(inst)
+    counts = torch.zeros((n_obs, M), dtype=torch.int32, device="cuda")
+    stats = torch.zeros(wos.WOS_STATS_WORDS, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    mi = wi.Instance(gm, inst.K, inst.x_obs, walks, eps=inst.eps, seed=inst.seed)
+    out = {"geometry": f"cube surface as {gm.n_tri} triangles (two per patch, the same {M} cells)",
+           "walks_per_point": walks, "radius": "r = dist"}
+    for name, prec in (("fp32", wi.FP32_GEOM_FP64_EXIT), ("fp64", wi.FP64)):
+        w = wos.walk_params_of(mi, precision=prec)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            counts.zero_()
+            stats.zero_()
+            ev0.record()
+            wos.wos_build_measure(ctx, gm, w, x, n_obs, counts, stats, None, stream)
+            ev1.record()
+            ev1.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        st = wos.stats_dict(stats)
+        t = float(np.mean(ms))
+        out[name] = {"ms": t, "walks_per_s": st["walks"] / (t * 1e-3), "steps_per_s": st["steps"] / (t * 1e-3),
+                     "steps_per_walk": st["steps"] / st["walks"], "escapes": st["escapes"]}
+    out["box_kind_r_dist_fp32_steps_per_s"] = box_steps_per_s
+    out["fp32_step_cost_vs_box_kind"] = box_steps_per_s / out["fp32"]["steps_per_s"]
+    log(f"mesh: FP32 {out['fp32']['ms']:.0f} ms, FP64 {out['fp64']['ms']:.0f} ms for {n_obs} x {walks} walks")
+    return out
+
 
 def bench_cube(a, wos, wi, torch):
     inst = wi.cfg3_cube(precision=wi.FP32_GEOM_FP64_EXIT)
@@ -714,6 +755,11 @@ def main():
     if not a.no_batch:
         log("64-instance batch at full walk budgets")
         out["batch"] = bench_batch(ctx, wos, wi, torch)
+    if not a.no_mesh and a.workload == "cube":
+        log("cube as a triangle mesh")
+        wk = out["walk_kernel"]
+        box_sps = wk["woe_bound_steps_per_walk"] * wk["woe_bound_walks_per_s"]
+        out["mesh"] = bench_mesh(ctx, wos, wi, torch, box_sps)
     if not a.no_serve:
         log(f"serving runs ({a.serve_seconds:.0f} s of arrivals)")
         out["serving"] = serving(ctx, wos, wi, a.serve_seconds, a.serve_rate, a.serve_svd, a.serve_radius)
