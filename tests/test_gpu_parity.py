@@ -815,7 +815,9 @@ def test_invalid_arguments_raise(wos, ctx):
         (g, wos.walk_params(np.array([[1, 2], [2, 1.0]]), 1e-4, 0, 10)),  # not SPD
         (g, wos.walk_params(np.array([[1, 0.5], [0.0, 1.0]]), 1e-4, 0, 10)),  # not symmetric
         (g, wos.walk_params(np.eye(2), 1e-4, 10, 5)),                       # empty range reversed
-        (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=1)),        # mapped-exact on a disk
+        (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=1, precision=1)),  # mapped-exact disk in FP32
+        (wi.Geometry(2, wi.ELLIPSE, (0, 0, 1.0, 0.5), (8,)),
+         wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=1)),             # mapped-exact on an ellipse
         (g, wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=3)),        # unknown radius mode
         (wi.Geometry(2, wi.POLYGON, (), (8,), verts=wi.L_SHAPE.copy()),
          wos.walk_params(np.eye(2), 1e-4, 0, 10, radius_mode=2)),             # mapped-bound on a polygon
