@@ -112,6 +112,7 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     p.add_argument("--no-mesh", action="store_true", help="skip the triangle-mesh measurement")
+    p.add_argument("--mesh-only", action="store_true", help="only the triangle-mesh measurement (for profiling)")
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--serve-svd", type=int, default=1, choices=(0, 1, 2),
                    help="serving SVD: 0 full (cooperative Jacobi), 1 truncated (plain kernels, overlapping), "
@@ -394,8 +395,9 @@ def bench_mesh(ctx, wos, wi, torch, box_steps_per_s, walks=10_000, reps=2):
         t = float(np.mean(ms))
         out[name] = {"ms": t, "walks_per_s": st["walks"] / (t * 1e-3), "steps_per_s": st["steps"] / (t * 1e-3),
                      "steps_per_walk": st["steps"] / st["walks"], "escapes": st["escapes"]}
-    out["box_kind_r_dist_fp32_steps_per_s"] = box_steps_per_s
-    out["fp32_step_cost_vs_box_kind"] = box_steps_per_s / out["fp32"]["steps_per_s"]
+    if box_steps_per_s is not None:
+        out["box_kind_r_dist_fp32_steps_per_s"] = box_steps_per_s
+        out["fp32_step_cost_vs_box_kind"] = box_steps_per_s / out["fp32"]["steps_per_s"]
     log(f"mesh: FP32 {out['fp32']['ms']:.0f} ms, FP64 {out['fp64']['ms']:.0f} ms for {n_obs} x {walks} walks")
     return out
 
@@ -739,6 +741,11 @@ def main():
     from paper_2409_03686_amd import wos
 
     torch.cuda.set_device(0)
+    if a.mesh_only:
+        ctx = wos.wos_create(0)
+        print(json.dumps({"mesh_only": True, "mesh": bench_mesh(ctx, wos, wi, torch, None, reps=1)}))
+        wos.wos_destroy(ctx)
+        return
     if a.serve_only:
         ctx = wos.wos_create(0)
         print(json.dumps({"serve_only": True, "serving": serving(ctx, wos, wi, a.serve_seconds, a.serve_rate,
