@@ -1604,3 +1604,32 @@ def test_trimesh_rejects_mapped_radii(wos, ctx):
         with pytest.raises(wos.WosError) as e:
             _gpu(wos, ctx, wi.Instance(g, np.eye(3), x, 16, radius_mode=mode, precision=wi.FP64))
         assert e.value.status == wos.WOS_ENOTSUP
+
+
+@pytest.mark.parametrize("precision", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
+def test_trimesh_in_a_mixed_batch_launches_on_its_own(wos, ctx, precision):
+    """A batch that mixes meshes with analytic kinds of both dimensions: the meshes form their own
+    launch (their compiled search is not part of the mixed-kind kernels) and every instance's counts
+    equal its separate launch bit for bit."""
+    rng = np.random.default_rng(99)
+    gm1 = _mesh_case("lprism")
+    gm2 = wi.Geometry(3, wi.TRIMESH, (), (1,), verts=wi.sphere_mesh([0.0, 0.0, 0.0], 1.0, 2))
+    gb = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (4,))
+    gball = wi.Geometry(3, wi.BALL, (0.0, 0.0, 0.0, 1.0), (4, 8))
+    gd = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (32,))
+    K3 = np.array([[1.0, 0.2, 0.0], [0.2, 0.6, 0.1], [0.0, 0.1, 0.4]])
+    insts = [wi.Instance(g, K3 if g.dim == 3 else np.eye(2), wi.sample_points(g, 12, rng), 300, eps=1e-4,
+                         seed=40 + k, instance_id=k, precision=precision)
+             for k, g in enumerate((gm1, gb, gm2, gd, gball))]
+    sep = [_gpu(wos, ctx, inst)[0] for inst in insts]
+    jobs, keep = [], []
+    for inst in insts:
+        M = wos.wos_element_count(inst.geom)
+        x = wos.device_inputs(inst)
+        cnt = torch.zeros((x.shape[0], M), dtype=torch.int32, device="cuda")
+        keep += [x, cnt]
+        jobs.append(wos.measure_job(inst.geom, wos.walk_params_of(inst), x, x.shape[0], cnt))
+    wos.wos_build_measure_batch(ctx, jobs)
+    torch.cuda.synchronize()
+    for k, inst in enumerate(insts):
+        assert np.array_equal(_np(keep[2 * k + 1]), sep[k]), (k, inst.geom.kind)
