@@ -758,6 +758,37 @@ static double step_radius(const og_geom *g, int mode, const double *S, const dou
             }
         return r;
     }
+    if (mode == 1 && g->kind == OG_TRIMESH) {
+        /* As for polygons: x + r S B(0,1) lies in D exactly when S^{-1} x + r B(0,1) lies in S^{-1} D,
+         * whose boundary is made of the mapped triangles S^{-1} T (a linear map takes triangles to
+         * triangles), so the largest r is the distance from S^{-1} x to the mapped surface.  S^{-1}
+         * is the adjugate of S over its determinant. */
+        double c[9], Si[9];
+        c[0] = S[4] * S[8] - S[5] * S[7];
+        c[1] = S[5] * S[6] - S[3] * S[8];
+        c[2] = S[3] * S[7] - S[4] * S[6];
+        c[3] = S[2] * S[7] - S[1] * S[8];
+        c[4] = S[0] * S[8] - S[2] * S[6];
+        c[5] = S[1] * S[6] - S[0] * S[7];
+        c[6] = S[1] * S[5] - S[2] * S[4];
+        c[7] = S[2] * S[3] - S[0] * S[5];
+        c[8] = S[0] * S[4] - S[1] * S[3];
+        double det = S[0] * c[0] + S[1] * c[1] + S[2] * c[2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Si[i * 3 + j] = c[j * 3 + i] / det;
+        double y[3], best = INFINITY;
+        for (int i = 0; i < 3; ++i) y[i] = Si[i * 3 + 0] * x[0] + Si[i * 3 + 1] * x[1] + Si[i * 3 + 2] * x[2];
+        for (int t = 0; t < g->n_verts; ++t) {
+            const double *T = g->verts + 9 * (size_t)t;
+            double M[9];
+            for (int v = 0; v < 3; ++v)
+                for (int i = 0; i < 3; ++i)
+                    M[3 * v + i] = Si[i * 3 + 0] * T[3 * v] + Si[i * 3 + 1] * T[3 * v + 1] + Si[i * 3 + 2] * T[3 * v + 2];
+            double dd = tri_dist(M, y);
+            if (dd < best) best = dd;
+        }
+        return best;
+    }
     if (mode == 1 && g->kind == OG_POLYGON) {
         /* The ellipsoid is { z : |S^{-1}(z - x)| <= r }: it misses edge [a, b] exactly while r is
          * below the distance from S^{-1} x to the mapped edge [S^{-1} a, S^{-1} b], and, being
@@ -835,7 +866,7 @@ static int radius_mode_valid(const og_geom *g, int mode)
 {
     if (mode == 0) return 1;
     if (mode == 1)
-        return g->kind == OG_BOX || g->kind == OG_POLYGON || g->kind == OG_DISK || g->kind == OG_ANNULUS ||
+        return g->kind == OG_BOX || g->kind == OG_POLYGON || g->kind == OG_TRIMESH || g->kind == OG_DISK || g->kind == OG_ANNULUS ||
                g->kind == OG_BALL || g->kind == OG_PERFORATED;
     if (mode == 2)
         return g->kind == OG_DISK || g->kind == OG_ANNULUS || g->kind == OG_BALL || g->kind == OG_ELLIPSE ||

@@ -1118,3 +1118,43 @@ def test_mesh_walk_reproduces_harmonic_functions():
     Sw[:3, :3] = Khat
     zw = _exit_mean_z(g, Sw, x, u, 20_000, grad_bound=6.0)
     assert zw.max() > 8, zw
+
+
+def test_mesh_mapped_exact_radius():
+    """Mapped-exact radius of a mesh (the distance from S^{-1} x to the mapped triangles S^{-1} T): on
+    the box as a mesh it equals the BOX kind's exact radius min_a gap_a / |S e_a|; on the non-convex
+    L-prism it equals a numpy route (normal equations on the mapped triangles) to 1e-12 and the step
+    ellipsoid shrunk by 1e-9 lies in the prism (analytic membership of 4096 boundary points each);
+    r = dist for S = I; the chain keeps the WoE chain's exit law with fewer steps (the slips S for
+    S^{-1} or the transposed adjugate fail the first two checks)."""
+    rng = np.random.default_rng(36)
+    K = _random_spd(3, 10.0, np.random.default_rng(37))
+    _, _, S = walks.instance_setup(K, 3)
+    Sd = S[:3, :3]
+    Si = np.linalg.inv(Sd)
+    gm = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh([0.1, -0.2, 0.0], [1.1, 0.6, 1.5], 6))
+    gb = wi.Geometry(3, wi.BOX, (0.1, -0.2, 0.0, 1.1, 0.6, 1.5), (6,))
+    x = wi.sample_points(gb, 300, rng)
+    np.testing.assert_allclose(walks.step_radii(gm, S, x, 1), walks.step_radii(gb, S, x, 1), rtol=1e-12)
+    T = wi.l_prism_mesh(4)
+    g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=T)
+    x = wi.sample_points(g, 60, rng)
+    r = walks.step_radii(g, S, x, 1)
+    MT = T @ Si.T
+    ref = np.array([min(_tri_dist_normal_equations(M, Si @ p) for M in MT) for p in x])
+    np.testing.assert_allclose(r, ref, rtol=1e-12, atol=1e-15)
+    U = _sphere_dirs(3, 4096)
+    for p, rr in zip(x, r):
+        q = p + rr * (1 - 1e-9) * (U @ Sd.T)
+        inside = (np.all((q > -1e-15) & (q < 1 + 1e-15), 1) & ~((q[:, 0] > 0.5 + 1e-15) & (q[:, 1] > 0.5 + 1e-15)))
+        assert inside.all()
+    d, _ = walks.geom_eval(g, x)
+    np.testing.assert_allclose(walks.step_radii(g, np.eye(3), x, 1), d, rtol=1e-12, atol=1e-15)
+    xs = wi.sample_points(wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.l_prism_mesh(2)), 4, rng)
+    g2 = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.l_prism_mesh(2))
+    N = 10_000
+    c0, s0, _ = walks.build_measure(g2, K, xs, 1e-4, seed=5, walk_end=N, threads=8, radius_mode=0)
+    c1, s1, _ = walks.build_measure(g2, K, xs, 1e-4, seed=6, walk_end=N, threads=8, radius_mode=1)
+    assert s1["steps"] < 0.7 * s0["steps"] and s1["escapes"] == 0, (s0["steps"], s1["steps"])
+    rep = statutil.two_sample(c0, N, c1, N)
+    assert rep["ok"], rep
