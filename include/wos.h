@@ -116,9 +116,12 @@ wos_status wos_streams_destroy(wos_ctx *ctx, void *walk_stream, void *spectral_s
  *                distance to the nearest of its edges.  A stop point goes to the cell of the nearest
  *                triangle (ties: the lowest triangle index).  A start point whose winding number
  *                (the triangles' solid angles seen from it over 4 pi) is below 1/2 is outside: its
- *                walks are escapes.  Step radius r = dist only (WOS_RADIUS_WOE_BOUND).  The triangles
- *                are searched through a bounding-volume hierarchy in HBM (256 B per triangle plus
- *                32 B per node, rebuilt on the host for each call).
+ *                walks are escapes.  Step radius r = dist (WOS_RADIUS_WOE_BOUND) or the mapped-exact
+ *                radius (WOS_RADIUS_MAPPED_EXACT: the distance from S^{-1} x to the mapped triangles
+ *                S^{-1} T, searched in a second hierarchy); WOS_RADIUS_MAPPED_BOUND is refused.  The
+ *                triangles are searched through a bounding-volume hierarchy in HBM (256 B per triangle
+ *                plus 32 B per node, twice with the mapped-exact radius, rebuilt on the host for each
+ *                call).
  * A stop point is assigned to the cell containing its projection onto dD (the intrinsic Voronoi
  * weights of the paper's appendix, Ex. A.3; for Bauer layouts the extrinsic ones of Ex. A.2, taken
  * on the stop point's nearest sphere); ties go to the lowest face/segment index. */
@@ -158,7 +161,7 @@ typedef enum { WOS_FP64 = 0, WOS_FP32_GEOM_FP64_EXIT = 1 } wos_precision;
  *   MAPPED_EXACT  the largest inscribed radius, the distance from S^{-1} X to the mapped boundary
  *                 S^{-1} dD (the ellipsoid is the set of z with |S^{-1}(z - X)| <= r): for a box min
  *                 over faces of gap_a / |S e_a|; for a polygon the distance to the mapped edges
- *                 S^{-1}[a, b]; for discs, annuli, balls and discs / balls with holes (FP64 geometry
+ *                 S^{-1}[a, b]; for a mesh the distance to the mapped triangles S^{-1} T; for discs, annuli, balls and discs / balls with holes (FP64 geometry
  *                 only) the distance to the mapped circles / spheres, ellipses / ellipsoids with
  *                 semi-axes R / s_k along the eigenvectors of S (eigenvalues s_k), computed by
  *                 Newton's method on the closest-point equation (§5.1, Remark on Alg. MC-REM,
@@ -186,8 +189,9 @@ typedef struct {
     uint64_t seed;        /* Philox key (low word, high word) */
     uint32_t instance;    /* Philox counter word 3: distinguishes instances sharing a seed */
     int32_t precision;    /* wos_precision */
-    int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes, polygons; MAPPED_BOUND: discs, annuli, balls,
-                             ellipses, perforated discs, balls and boxes) */
+    int32_t radius_mode;  /* wos_radius_mode (MAPPED_EXACT: boxes, polygons, meshes, and in FP64 discs, annuli,
+                             balls, perforated discs and balls; MAPPED_BOUND: discs, annuli, balls, ellipses,
+                             perforated discs, balls and boxes) */
     uint32_t max_steps;   /* step cap S_max (0 -> 10000, must be < 2^31); capped walks are binned where they are */
 } wos_walk_params;
 

@@ -650,11 +650,12 @@ wos_status wos::validate_walk(const wos_geometry *g, const wos_walk_params *w)
         return set_error(WOS_EINVAL, "unknown radius mode %d", w->radius_mode);
     const bool curved = g->kind == WOS_DISK || g->kind == WOS_ANNULUS || g->kind == WOS_BALL ||
                         g->kind == WOS_PERFORATED;
-    if (g->kind == WOS_TRIMESH && w->radius_mode != WOS_RADIUS_WOE_BOUND)
-        return set_error(WOS_ENOTSUP, "triangle meshes take the step radius r = dist only");
-    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON && !curved)
-        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes, polygons, discs, annuli, balls "
-                                      "and discs / balls with holes only");
+    if (g->kind == WOS_TRIMESH && w->radius_mode == WOS_RADIUS_MAPPED_BOUND)
+        return set_error(WOS_ENOTSUP, "triangle meshes take r = dist or the mapped-exact radius");
+    if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && g->kind != WOS_BOX && g->kind != WOS_POLYGON &&
+        g->kind != WOS_TRIMESH && !curved)
+        return set_error(WOS_ENOTSUP, "mapped-exact radius is implemented for boxes, polygons, meshes, discs, annuli, "
+                                      "balls and discs / balls with holes only");
     if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT && curved && w->precision != WOS_FP64)
         return set_error(WOS_ENOTSUP, "the mapped-exact radius of circles and spheres (an iterative distance to "
                                       "an ellipse or ellipsoid) runs with FP64 geometry only");
@@ -744,25 +745,26 @@ struct BvhBuild {
 };
 }  // namespace
 
-static void mesh_records(const wos_geometry *g, DevInst &I, std::vector<PolySeg> &segs, double scale)
+// verts: the triangles (9 numbers each); base: 0 for the surface, 4 for the mapped triangles.
+static void mesh_records(const double *verts, int nt, int base, DevInst &I, std::vector<PolySeg> &segs)
 {
-    const int nt = g->n_verts;
-    BvhBuild B{g->verts, std::vector<int>(nt), {}};
+    BvhBuild B{verts, std::vector<int>(nt), {}};
     for (int t = 0; t < nt; ++t) B.idx[t] = t;
     B.build(0, nt);
     const size_t nn = B.nodes.size();
-    const size_t base = segs.size();
-    I.mesh_off[0] = static_cast<int32_t>(base);
-    I.mesh_off[1] = static_cast<int32_t>(nn);
-    I.mesh_off[2] = static_cast<int32_t>(base + (nn + 1) / 2);
-    I.mesh_off[3] = static_cast<int32_t>(I.mesh_off[2] + 2 * static_cast<size_t>(nt));
-    segs.resize(static_cast<size_t>(I.mesh_off[3]) + 2 * static_cast<size_t>(nt));
-    std::memcpy(segs.data() + base, B.nodes.data(), nn * sizeof(MeshNode));
-    MeshTri32 *t32 = reinterpret_cast<MeshTri32 *>(segs.data() + I.mesh_off[2]);
-    MeshTri64 *t64 = reinterpret_cast<MeshTri64 *>(segs.data() + I.mesh_off[3]);
+    const size_t at = segs.size();
+    int32_t *off = I.mesh_off + base;
+    off[0] = static_cast<int32_t>(at);
+    off[1] = static_cast<int32_t>(nn);
+    off[2] = static_cast<int32_t>(at + (nn + 1) / 2);
+    off[3] = static_cast<int32_t>(off[2] + 2 * static_cast<size_t>(nt));
+    segs.resize(static_cast<size_t>(off[3]) + 2 * static_cast<size_t>(nt));
+    std::memcpy(segs.data() + at, B.nodes.data(), nn * sizeof(MeshNode));
+    MeshTri32 *t32 = reinterpret_cast<MeshTri32 *>(segs.data() + off[2]);
+    MeshTri64 *t64 = reinterpret_cast<MeshTri64 *>(segs.data() + off[3]);
     for (int q = 0; q < nt; ++q) {
         const int t = B.idx[q];
-        const double *a = g->verts + 9 * static_cast<size_t>(t), *b = a + 3, *c = a + 6;
+        const double *a = verts + 9 * static_cast<size_t>(t), *b = a + 3, *c = a + 6;
         MeshTri64 &D = t64[q];
         std::memset(&D, 0, sizeof D);
         for (int k = 0; k < 3; ++k) {
@@ -799,10 +801,6 @@ static void mesh_records(const wos_geometry *g, DevInst &I, std::vector<PolySeg>
         std::memcpy(&ow, &ob, 4);
         F.n = f4(n[0], n[1], n[2], ow);
     }
-    // pruning margins: far above the rounding of a distance (FP64: some 100 units of 2^-53 of the
-    // coordinate scale; FP32: the box gap's few units of 2^-24)
-    I.mesh_m64 = std::ldexp(scale, -40);
-    I.mesh_m32 = static_cast<float>(std::ldexp(scale, -20));
 }
 
 wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n_elem, DevInst &I,
@@ -1011,7 +1009,47 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
     I.n_segs = static_cast<int32_t>(segs.size());
     if (g->kind == WOS_TRIMESH) {
         I.n_verts = g->n_verts;
-        mesh_records(g, I, segs, domain_scale(g));
+        mesh_records(g->verts, g->n_verts, 0, I, segs);
+        double scale = domain_scale(g);
+        if (w->radius_mode == WOS_RADIUS_MAPPED_EXACT) {
+            // S^{-1} (the adjugate over the determinant) and the mapped triangles S^{-1} T, searched for
+            // the distance from S^{-1} x
+            const double *S = I.S;
+            double c[9];
+            c[0] = S[4] * S[8] - S[5] * S[7];
+            c[1] = S[5] * S[6] - S[3] * S[8];
+            c[2] = S[3] * S[7] - S[4] * S[6];
+            c[3] = S[2] * S[7] - S[1] * S[8];
+            c[4] = S[0] * S[8] - S[2] * S[6];
+            c[5] = S[1] * S[6] - S[0] * S[7];
+            c[6] = S[1] * S[5] - S[2] * S[4];
+            c[7] = S[2] * S[3] - S[0] * S[5];
+            c[8] = S[0] * S[4] - S[1] * S[3];
+            const double det = S[0] * c[0] + S[1] * c[1] + S[2] * c[2];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    I.Si3[i * 3 + j] = c[j * 3 + i] / det;
+                    I.Sif3[i * 3 + j] = static_cast<float>(I.Si3[i * 3 + j]);
+                }
+            const size_t nv = 9 * static_cast<size_t>(g->n_verts);
+            std::vector<double> mv(nv);
+            double ms = 0.0;
+            for (size_t v = 0; v < nv; v += 3)
+                for (int i = 0; i < 3; ++i) {
+                    mv[v + i] = I.Si3[i * 3 + 0] * g->verts[v] + I.Si3[i * 3 + 1] * g->verts[v + 1] +
+                                I.Si3[i * 3 + 2] * g->verts[v + 2];
+                    ms = std::max(ms, std::fabs(mv[v + i]));
+                }
+            mesh_records(mv.data(), g->n_verts, 4, I, segs);
+            // FP32 error bound of the mapped distance: the mesh distance's bound (64 units of 2^-24) at
+            // the mapped scale, doubled for the mapping of x and the rounding of the mapped records
+            I.mbf[1] = static_cast<float>(std::ldexp(ms, -17));
+            scale = std::max(scale, ms);
+        }
+        // pruning margins: far above the rounding of a distance (FP64: some 100 units of 2^-53 of the
+        // coordinate scale; FP32: the box gap's few units of 2^-24)
+        I.mesh_m64 = std::ldexp(scale, -40);
+        I.mesh_m32 = static_cast<float>(std::ldexp(scale, -20));
     }
     // Bauer node tables of the spheres with layout (n, 0), after the staged records (not staged)
     auto add_nodes = [&](int n, int slot) {
@@ -1162,6 +1200,7 @@ wos_status wos::prepare_group(wos_ctx *ctx, const wos_measure_job *jobs, const s
                             (j.geom.kind == WOS_POLYGON && j.walk.radius_mode == WOS_RADIUS_MAPPED_EXACT);
         const bool curved_exact = j.walk.radius_mode == WOS_RADIUS_MAPPED_EXACT && j.geom.kind != WOS_BOX &&
                                   j.geom.kind != WOS_POLYGON;
+        if (j.geom.kind == WOS_TRIMESH) return static_cast<int>(kTriMesh);  // reads its radius mode per instance
         if (curved_exact) return -1;  // no compiled variant: the kernel reads the radius mode per instance
         return j.geom.kind + (mapped ? kRadiusVariant : 0);
     };

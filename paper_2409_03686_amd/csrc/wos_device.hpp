@@ -36,14 +36,17 @@ struct alignas(16) DevInst {
     int32_t n_segs, pad0;  // PolySeg records to stage in LDS: n_verts, or 2 n_verts with the mapped edges
     int32_t node_off[2];   // record index in segs of the Bauer node table (unit vectors in ax, ay, ey) of
                            // the outer sphere / of the holes, for sphere layouts (n, 0); read from HBM
-    int32_t mesh_off[4];   // triangle meshes (read from HBM): record index in segs of the BVH nodes, the
-                           // node count, record index of the FP32 and of the FP64 triangle records
+    int32_t mesh_off[8];   // triangle meshes (read from HBM): record index in segs of the BVH nodes, the
+                           // node count, record index of the FP32 and of the FP64 triangle records; then the
+                           // same for the mapped triangles S^{-1} T (mapped-exact radius)
     double mesh_m64;       // pruning margin of the FP64 nearest-triangle search (a distance)
     float mesh_m32;        // the same for the FP32 search
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
     double msig2;     // ellipse, mapped bound: |A^{-1} S|^2 (A = diag(a, b))
     double Si[4];     // 2D: S^{-1}, row-major 2x2 (mapped-exact radius of polygons)
+    double Si3[9];    // 3D: S^{-1}, row-major (mapped-exact radius of meshes)
+    float Sif3[9];
     double Sq[9];     // eigenvectors of S, row-major: column k is the k-th (mapped-exact radius of
     double Se[3];     // circles and spheres), and the eigenvalues of S
     double cn[3];     // |S e_a|: the half-extent of the unit ellipsoid S B(0,1) along axis a
@@ -318,14 +321,15 @@ struct MeshHit32 {
 
 // hint >= 0: the triangle (hierarchy position) nearest the walk's previous position, whose distance
 // starts the search in place of the greedy leaf; the result does not depend on it.
-__device__ __attribute__((noinline)) MeshHit64 mesh_dist64(const DevInst &I, double x0, double x1, double x2,
-                                                          int hint)
+// base: 0 for the surface itself, 4 for the mapped triangles.
+__device__ __attribute__((noinline)) MeshHit64 mesh_dist64(const DevInst &I, int base, double x0, double x1,
+                                                          double x2, int hint)
 {
 #pragma clang fp contract(off)
     const double x[3] = {x0, x1, x2};
-    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, 0);
-    const GPtr<MeshTri64> tris = mesh_rec<MeshTri64>(I, 3);
-    const int nn = I.mesh_off[1];
+    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, base);
+    const GPtr<MeshTri64> tris = mesh_rec<MeshTri64>(I, base + 3);
+    const int nn = I.mesh_off[base + 1];
     double best = __builtin_inf(), lim = __builtin_inf();
     int bo = 0x7FFFFFFF, bq = 0;
     // One node or one triangle per iteration (lanes of a wave are at different places of the
@@ -394,12 +398,13 @@ __device__ __forceinline__ float tri_dist2_32(const MeshTri32 &T, const float *x
 }
 
 // Distance to the mesh in FP32 (within the FP32 error bound of the instance).
-__device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, float x0, float x1, float x2, int hint)
+__device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, int base, float x0, float x1, float x2,
+                                                          int hint)
 {
     const float x[3] = {x0, x1, x2};
-    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, 0);
-    const GPtr<MeshTri32> tris = mesh_rec<MeshTri32>(I, 2);
-    const int nn = I.mesh_off[1];
+    const GPtr<MeshNode> nodes = mesh_rec<MeshNode>(I, base);
+    const GPtr<MeshTri32> tris = mesh_rec<MeshTri32>(I, base + 2);
+    const int nn = I.mesh_off[base + 1];
     float best2 = __builtin_inff(), lim = __builtin_inff();
     int bq = 0;
     // one node or one triangle per iteration, the hint's triangle or the greedy leaf first, as in the
@@ -577,7 +582,7 @@ template <int KIND, int DIM> __device__ __forceinline__ double dist64(const DevI
     } else if constexpr (KIND == kTriMesh) {
         // unsigned: walks start inside (an outside start point is decided by the winding number at
         // the start) and every step stays within the distance
-        const MeshHit64 h = mesh_dist64(I, x[0], x[1], x[2], hint ? *hint : -1);
+        const MeshHit64 h = mesh_dist64(I, 0, x[0], x[1], x[2], hint ? *hint : -1);
         if (hint) *hint = h.q;
         return h.d;
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
@@ -636,7 +641,7 @@ template <int KIND, int DIM> __device__ __forceinline__ float dist32(const DevIn
     } else if constexpr (KIND == kBall) {
         return I.pf[3] - __builtin_amdgcn_sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     } else if constexpr (KIND == kTriMesh) {
-        const MeshHit32 h = mesh_dist32(I, x[0], x[1], x[2], hint ? *hint : -1);
+        const MeshHit32 h = mesh_dist32(I, 0, x[0], x[1], x[2], hint ? *hint : -1);
         if (hint) *hint = h.q;
         return h.d;
     } else if constexpr (KIND == kPerforated || KIND == kPerfBox) {
@@ -902,6 +907,15 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
             }
         }
     }
+    if constexpr (KIND == kTriMesh) {
+        if (I.radius_mode == 1) {  // the distance from S^{-1} x to the mapped triangles
+#pragma clang fp contract(off)
+            double y[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) y[k] = I.Si3[k * 3 + 0] * x[0] + I.Si3[k * 3 + 1] * x[1] + I.Si3[k * 3 + 2] * x[2];
+            return mesh_dist64(I, 4, y[0], y[1], y[2], -1).d;
+        }
+    }
     if constexpr (KIND == kBox) {
         if (I.radius_mode == 1) {
             double best = __builtin_inf();
@@ -1007,6 +1021,15 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
             } else {
                 return s - (__builtin_amdgcn_sqrtf(a2) + I.mbf[1]);
             }
+        }
+    }
+    if constexpr (KIND == kTriMesh) {
+        if (I.radius_mode == 1) {  // mapped triangles, less the FP32 error bound of that distance (mbf[1])
+            float y[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                y[k] = __builtin_fmaf(I.Sif3[k * 3 + 2], x[2], __builtin_fmaf(I.Sif3[k * 3 + 1], x[1], I.Sif3[k * 3] * x[0]));
+            return mesh_dist32(I, 4, y[0], y[1], y[2], -1).d - I.mbf[1];
         }
     }
     if constexpr (KIND == kBox) {
@@ -1248,7 +1271,7 @@ template <int KIND, int DIM> __device__ __forceinline__ int element64(const DevI
         for (int a = 0; a < 3; ++a) v[a] = x[a] - I.p[a];
         return sphere_cell_of(v, I.layout[0], I.layout[1], I.p[3], I.segs + I.node_off[0]);
     } else if constexpr (KIND == kTriMesh) {  // the nearest triangle; layout[0] triangles per element
-        return mesh_dist64(I, x[0], x[1], x[2], -1).orig / I.layout[0];
+        return mesh_dist64(I, 0, x[0], x[1], x[2], -1).orig / I.layout[0];
     } else {  // kBox
         return box_cell<DIM>(I, x);
     }

@@ -1597,13 +1597,48 @@ def test_trimesh_start_points_outside_are_escapes(wos, ctx):
         assert np.all(tr[3, :, 1] > 0)
 
 
-def test_trimesh_rejects_mapped_radii(wos, ctx):
+def test_trimesh_rejects_the_mapped_bound(wos, ctx):
     g = _mesh_case("lprism")
     x = wi.sample_points(g, 4, np.random.default_rng(98))
-    for mode in (wi.RADIUS_MAPPED_EXACT, wi.RADIUS_MAPPED_BOUND):
-        with pytest.raises(wos.WosError) as e:
-            _gpu(wos, ctx, wi.Instance(g, np.eye(3), x, 16, radius_mode=mode, precision=wi.FP64))
-        assert e.value.status == wos.WOS_ENOTSUP
+    with pytest.raises(wos.WosError) as e:
+        _gpu(wos, ctx, wi.Instance(g, np.eye(3), x, 16, radius_mode=wi.RADIUS_MAPPED_BOUND, precision=wi.FP64))
+    assert e.value.status == wos.WOS_ENOTSUP
+
+
+@pytest.mark.parametrize("name", ["box", "lprism"])
+def test_trimesh_mapped_exact_radius(wos, ctx, name):
+    """Mapped-exact radius of a mesh (the distance from S^{-1} x to the mapped triangles, a second
+    hierarchy): FP64 walk for walk against the oracle, fewer steps than r = dist; FP32 against FP64
+    entry by entry with no escapes; on the box as a mesh the same walks as the BOX kind's exact radius."""
+    g = _mesh_case(name)
+    rng = np.random.default_rng(100)
+    x = wi.sample_points(g, 16, rng)
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.5, -0.2], [0.1, -0.2, 0.25]])
+    inst = wi.Instance(g, K, x, 400, eps=1e-4, seed=51, instance_id=3, precision=wi.FP64,
+                       radius_mode=wi.RADIUS_MAPPED_EXACT)
+    c, st, tr = _gpu(wos, ctx, inst, trace=True)
+    cr, sr, trr = ow.build_instance(inst, trace=True)
+    agree = _agreement(tr, trr)
+    woe = wi.Instance(g, K, x, 400, eps=1e-4, seed=51, instance_id=3, precision=wi.FP64)
+    _, st0, _ = _gpu(wos, ctx, woe)
+    print(f"{name}: mapped exact FP64 agreement {agree:.6f}, steps per walk {st['steps'] / st['walks']:.2f} "
+          f"against {st0['steps'] / st0['walks']:.2f} with r = dist")
+    assert agree >= 0.999 and st["escapes"] == 0 and st["steps"] < 0.8 * st0["steps"]
+    if name == "box":
+        gb = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (12,))
+        _, _, tb = _gpu(wos, ctx, wi.Instance(gb, K, x, 400, eps=1e-4, seed=51, instance_id=3, precision=wi.FP64,
+                                              radius_mode=wi.RADIUS_MAPPED_EXACT), trace=True)
+        ab = _agreement(tr, tb)
+        print(f"box mesh vs box kind, mapped exact: agreement {ab:.6f}")
+        assert ab >= 0.999
+    N = 20_000
+    c32, s32, _ = _gpu(wos, ctx, wi.Instance(g, K, x, N, eps=1e-4, seed=52, precision=wi.FP32_GEOM_FP64_EXIT,
+                                             radius_mode=wi.RADIUS_MAPPED_EXACT))
+    c64, s64, _ = _gpu(wos, ctx, wi.Instance(g, K, x, N, eps=1e-4, seed=53, precision=wi.FP64,
+                                             radius_mode=wi.RADIUS_MAPPED_EXACT))
+    rep = statutil.two_sample(c32, N, c64, N)
+    print(f"{name} mapped exact FP32 vs FP64 {rep}")
+    assert s32["escapes"] == 0 and rep["ok"], rep
 
 
 @pytest.mark.parametrize("precision", [wi.FP64, wi.FP32_GEOM_FP64_EXIT])
