@@ -363,9 +363,10 @@ def bench_batch(ctx, wos, wi, torch, reps=3):
 
 def bench_mesh(ctx, wos, wi, torch, box_steps_per_s, walks=10_000, reps=2):
     """The cube workload's domain as a closed triangle mesh (each of the 3456 patches two triangles:
-    6912 triangles, the same cells), its 4096 points and K, 1e4 walks per point, r = dist: the walk
-    kernel with the BVH nearest-triangle search in FP32 and FP64, beside the box kind's closed-form
-    distance at r = dist (the same chain)."""
+    6912 triangles, the same cells), its 4096 points and K, 1e4 walks per point: the walk kernel with
+    the BVH nearest-triangle search at r = dist in FP32 and FP64, beside the box kind's closed-form
+    distance at r = dist (the same chain), and in FP32 with the mapped-exact radius (a second search
+    over the mapped triangles each step)."""
     inst = wi.cfg3_cube(n_walks=walks)
     g = inst.geom
     gm = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.box_mesh(np.array(g.params[:3]), np.array(g.params[3:6]),
@@ -378,9 +379,11 @@ def bench_mesh(ctx, wos, wi, torch, box_steps_per_s, walks=10_000, reps=2):
     stream = torch.cuda.current_stream().cuda_stream
     mi = wi.Instance(gm, inst.K, inst.x_obs, walks, eps=inst.eps, seed=inst.seed)
     out = {"geometry": f"cube surface as {gm.n_tri} triangles (two per patch, the same {M} cells)",
-           "walks_per_point": walks, "radius": "r = dist"}
-    for name, prec in (("fp32", wi.FP32_GEOM_FP64_EXIT), ("fp64", wi.FP64)):
-        w = wos.walk_params_of(mi, precision=prec)
+           "walks_per_point": walks, "radius": "r = dist (fp32, fp64); mapped exact (fp32_mapped_exact)"}
+    for name, prec, rm in (("fp32", wi.FP32_GEOM_FP64_EXIT, wos.WOS_RADIUS_WOE_BOUND),
+                           ("fp64", wi.FP64, wos.WOS_RADIUS_WOE_BOUND),
+                           ("fp32_mapped_exact", wi.FP32_GEOM_FP64_EXIT, wos.WOS_RADIUS_MAPPED_EXACT)):
+        w = wos.walk_params_of(mi, precision=prec, radius_mode=rm)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ms = []
         for _ in range(reps):
@@ -398,7 +401,8 @@ def bench_mesh(ctx, wos, wi, torch, box_steps_per_s, walks=10_000, reps=2):
     if box_steps_per_s is not None:
         out["box_kind_r_dist_fp32_steps_per_s"] = box_steps_per_s
         out["fp32_step_cost_vs_box_kind"] = box_steps_per_s / out["fp32"]["steps_per_s"]
-    log(f"mesh: FP32 {out['fp32']['ms']:.0f} ms, FP64 {out['fp64']['ms']:.0f} ms for {n_obs} x {walks} walks")
+    log(f"mesh: FP32 {out['fp32']['ms']:.0f} ms, FP64 {out['fp64']['ms']:.0f} ms, FP32 mapped exact "
+        f"{out['fp32_mapped_exact']['ms']:.0f} ms for {n_obs} x {walks} walks")
     return out
 
 

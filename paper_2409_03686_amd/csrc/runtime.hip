@@ -1045,6 +1045,10 @@ wos_status wos::fill_inst(const wos_geometry *g, const wos_walk_params *w, int n
             // the mapped scale, doubled for the mapping of x and the rounding of the mapped records
             I.mbf[1] = static_cast<float>(std::ldexp(ms, -17));
             scale = std::max(scale, ms);
+            // sigma_min(S), shrunk below its rounding so that sigma_min r stays below dist
+            const double sg = std::sqrt(lmin / lmax);
+            I.mesh_sig64 = sg * (1.0 - 0x1.0p-40);
+            I.mesh_sig32 = static_cast<float>(sg * (1.0 - 0x1.0p-18));
         }
         // pruning margins: far above the rounding of a distance (FP64: some 100 units of 2^-53 of the
         // coordinate scale; FP32: the box gap's few units of 2^-24)

@@ -203,14 +203,26 @@ struct Fold32 {
 // a walk that stops inside it).
 template <typename R, int DIM, int KIND, int PH, bool CAP, int RV>
 __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs, const uint32_t w[4], const Fold32 &F,
-                                          R *x, R &d, uint32_t &s, uint32_t &n_fp64, int &hint)
+                                          R *x, R &d, uint32_t &s, uint32_t &n_fp64, int &hint, R &rnext)
 {
+    // Meshes with the mapped-exact radius: the radius at the new position is computed right after the
+    // step (rnext, used by the next step), and since the step ellipsoid holds the ball of radius
+    // sigma_min r and touches dD, sigma_min r <= dist <= r: while sigma_min r is above the exit
+    // threshold the walk certainly goes on and the search of the surface itself is skipped.
+    constexpr bool kMeshMapped = KIND == kTriMesh;
+    const bool mapped = kMeshMapped && I.radius_mode == 1;
     if constexpr (sizeof(R) == 8) {
         R U[DIM];
         Dir<R, DIM>::template get<PH>(w, U);
-        const double r = radius64<KIND, DIM, RV>(I, x, d, segs);
+        const double r = (mapped && rnext >= 0.0) ? static_cast<double>(rnext) : radius64<KIND, DIM, RV>(I, x, d, segs);
         step64<DIM>(I, x, r, U);
-        d = dist64<KIND, DIM>(I, x, segs, &hint);
+        if (mapped) {
+            rnext = radius64<KIND, DIM, RV>(I, x, d, segs);
+            const double lb = rnext * I.mesh_sig64;
+            d = lb > I.eps ? lb : dist64<KIND, DIM>(I, x, segs, &hint);
+        } else {
+            d = dist64<KIND, DIM>(I, x, segs, &hint);
+        }
         s += 1;
         if (d > I.eps && s >= I.max_steps) {
             d = -1.0;
@@ -219,7 +231,7 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
     } else {
         // conservative radius: below the true distance by more than the FP32 distance error
         // (2 delta) and the direction's error (the relative shrink 1 - rshrink)
-        const float rr = radius32<KIND, DIM, RV>(I, x, d, segs);
+        const float rr = (mapped && rnext >= 0.0f) ? static_cast<float>(rnext) : radius32<KIND, DIM, RV>(I, x, d, segs);
         if constexpr (DIM == 2) {
             const float t = static_cast<float>(w[PH] >> 8);
             const float c0 = __builtin_amdgcn_cosf(__builtin_fmaf(t, 0x1.0p-24f, F.off0));
@@ -232,9 +244,17 @@ __device__ __forceinline__ void walk_step(const DevInst &I, const PolySeg *segs,
             const float r = __builtin_fmaf(rr, I.rshrink, I.neg2delta);
             step32<DIM>(I, x, r, U);
         }
-        d = dist32<KIND, DIM>(I, x, segs, &hint);
+        bool certain = false;
+        if (mapped) {
+            rnext = radius32<KIND, DIM, RV>(I, x, d, segs);  // below the mapped distance (its error bound is off)
+            const float lb = rnext * I.mesh_sig32;
+            certain = lb > I.eps_hi;
+            d = certain ? lb : dist32<KIND, DIM>(I, x, segs, &hint);
+        } else {
+            d = dist32<KIND, DIM>(I, x, segs, &hint);
+        }
         if constexpr (CAP) s += 1;
-        if (d > I.eps_lo && d <= I.eps_hi) {
+        if (!certain && d > I.eps_lo && d <= I.eps_hi) {
             // ambiguous band: decide in FP64 at the stored position
             double xd[DIM];
 #pragma unroll
@@ -324,7 +344,8 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
         // memory form would cost a compare and a select per phase).
         constexpr R kFree = static_cast<R>(__builtin_inf());
         uint32_t koff = 0, s = 0;
-        int hint = -1;  // meshes: the walk's last nearest triangle
+        int hint = -1;       // meshes: the walk's last nearest triangle
+        R rnext = R(-1);     // meshes, mapped-exact radius: the radius at the walk's position (-1: unknown)
         R x[DIM];
         R d = kFree;
 #pragma unroll
@@ -365,6 +386,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                         koff = mine;
                         s = 0;
                         hint = -1;
+                        rnext = R(-1);
                         d = d0;
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) x[a] = x0[a];
@@ -377,6 +399,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
                     koff = k0 + static_cast<uint32_t>(wv) + nw * mine;
                     s = 0;
                     hint = -1;
+                    rnext = R(-1);
                     d = d0;
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) x[a] = x0[a];
@@ -398,7 +421,7 @@ __device__ __forceinline__ void run_item(const DevInst &I, uint32_t point, uint3
             auto phase = [&](auto ph_tag, auto cap_tag) {
                 constexpr int PH = decltype(ph_tag)::value;
                 constexpr bool CAP = decltype(cap_tag)::value;
-                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint);
+                if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint, rnext);
                 const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
                 fph = fin ? static_cast<uint32_t>(PH) : fph;
                 d = fin ? kFree : d;
@@ -642,7 +665,8 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
     };
 
     uint32_t koff = 0, s = 0, sl = 0;
-    int hint = -1;  // meshes: the walk's last nearest triangle
+    int hint = -1;       // meshes: the walk's last nearest triangle
+    R rnext = R(-1);     // meshes, mapped-exact radius: the radius at the walk's position (-1: unknown)
     R x[DIM];
     R d = kFree;
 #pragma unroll
@@ -658,6 +682,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
             sl = cur;
             s = 0;
             hint = -1;
+            rnext = R(-1);
             d = d0c;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) x[a] = x0c[a];
@@ -691,7 +716,7 @@ __device__ __forceinline__ uint64_t run_chain(const DevInst &I, uint64_t item, u
         auto phase = [&](auto ph_tag, auto cap_tag) {
             constexpr int PH = decltype(ph_tag)::value;
             constexpr bool CAP = decltype(cap_tag)::value;
-            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint);
+            if (d != kFree) walk_step<R, DIM, KIND, PH, CAP, RV>(I, segs, w, F, x, d, s, n_fp64, hint, rnext);
             const bool fin = !(d > (sizeof(R) == 8 ? static_cast<R>(I.eps) : static_cast<R>(I.eps_lo)));
             fph = fin ? static_cast<uint32_t>(PH) : fph;
             d = fin ? kFree : d;

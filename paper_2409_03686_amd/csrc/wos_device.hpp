@@ -41,6 +41,8 @@ struct alignas(16) DevInst {
                            // same for the mapped triangles S^{-1} T (mapped-exact radius)
     double mesh_m64;       // pruning margin of the FP64 nearest-triangle search (a distance)
     float mesh_m32;        // the same for the FP32 search
+    float mesh_sig32;      // mapped-exact radius of meshes: sigma_min(S), rounded down (FP32 and FP64 use
+    double mesh_sig64;     // sigma_min r <= dist <= r to skip the surface search away from the boundary)
     double p[8];
     double S[9];      // Khat^{1/2}, Khat = K / lambda_max(K), row-major 3x3
     double msig2;     // ellipse, mapped bound: |A^{-1} S|^2 (A = diag(a, b))
