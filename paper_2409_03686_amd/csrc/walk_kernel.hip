@@ -177,9 +177,11 @@ __device__ __forceinline__ void flush_queue(const DevInst &I, const StopQueue<R,
         ls.steps += st;
         ls.max_s = max(ls.max_s, st);
         ls.cap += sw >> 31;
-        // escape (stop outside D): certain "no" when the FP32 distance exceeds its error bound
-        bool maybe_out = true;
-        if constexpr (sizeof(R) == 4 && KIND != kPolygon) maybe_out = !(dist32<KIND, DIM>(I, xs, segs) > I.delta);
+        // escape (stop outside D): certain "no" when the FP32 distance exceeds its error bound; a mesh's
+        // walk distance is unsigned, its escapes are decided at the start point
+        bool maybe_out = KIND != kTriMesh;
+        if constexpr (sizeof(R) == 4 && KIND != kPolygon && KIND != kTriMesh)
+            maybe_out = !(dist32<KIND, DIM>(I, xs, segs) > I.delta);
         if (maybe_out && dist64<KIND, DIM>(I, x, segs) < 0.0) ls.esc += 1;
         if (I.trace) {
             const size_t t = (static_cast<size_t>(point) * I.n_walks + q.koff[lane]) * 2;
