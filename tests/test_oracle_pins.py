@@ -1158,3 +1158,41 @@ def test_mesh_mapped_exact_radius():
     assert s1["steps"] < 0.7 * s0["steps"] and s1["escapes"] == 0, (s0["steps"], s1["steps"])
     rep = statutil.two_sample(c0, N, c1, N)
     assert rep["ok"], rep
+
+
+def test_shell_bias_is_first_order_in_eps():
+    """The eps-shell bias is O(eps) (the order the shell-bias allowances of the parity rules assume):
+    for a harmonic u, E u(X_N) = u(x) exactly (optional stopping), so the bias of binning at the
+    projection, E u(pi(X_N)) - u(x), equals E[u(pi(X_N)) - u(X_N)], whose per-walk terms are O(eps) and
+    make a precise mean (standard error about 1 % of it).  Over eps = 0.04 -> 0.005 (three halvings)
+    the bias divided by eps stays within 8 % of its mean on the unit disc (u = x^2 - y^2, pi(X) =
+    X / |X|) and on the unit cube (u = x^2 - z^2, pi onto the nearest face): first order, not
+    eps log(1/eps) (which would grow by 1.25-1.5 per halving here) nor sqrt(eps).  A projection
+    skipped (binning X_N itself) makes the bias vanish and fails the nonzero check."""
+    eps_list = [0.04, 0.02, 0.01, 0.005]
+    n = 120_000
+
+    def ratios(g, x0, u, proj):
+        out = []
+        for e in eps_list:
+            X = walks.walk_exits(g, np.eye(3), x0, e, n, seed=21)
+            out.append(np.mean(u(proj(X)) - u(X)) / e)
+        return np.array(out)
+
+    disk = wi.Geometry(2, wi.DISK, (0.0, 0.0, 1.0), (16,))
+    r_disk = ratios(disk, np.array([0.6, 0.1]), lambda p: p[:, 0] ** 2 - p[:, 1] ** 2,
+                    lambda X: X / np.linalg.norm(X, axis=1, keepdims=True))
+
+    def cube_proj(X):
+        P = X.copy()
+        gaps = np.concatenate([X, 1 - X], 1)
+        k = np.argmin(gaps, 1)
+        rows = np.arange(len(X))
+        P[rows, k % 3] = np.where(k < 3, 0.0, 1.0)
+        return P
+
+    cube = wi.Geometry(3, wi.BOX, (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), (4,))
+    r_cube = ratios(cube, np.array([0.3, 0.55, 0.7]), lambda p: p[:, 0] ** 2 - p[:, 2] ** 2, cube_proj)
+    for r in (r_disk, r_cube):
+        assert np.all(np.abs(r - r.mean()) <= 0.08 * abs(r.mean())), r
+        assert abs(r.mean()) > 0.1, r
