@@ -1668,3 +1668,43 @@ def test_trimesh_in_a_mixed_batch_launches_on_its_own(wos, ctx, precision):
     torch.cuda.synchronize()
     for k, inst in enumerate(insts):
         assert np.array_equal(_np(keep[2 * k + 1]), sep[k]), (k, inst.geom.kind)
+
+
+def test_served_mesh_requests_match_the_oracles_reconstruction(wos, ctx):
+    """Mesh requests through the serving engine (the request's triangles are copied at submission):
+    the L-prism in FP32 with the mapped-exact radius and the icosphere in FP64 at r = dist, served
+    with the full SVD beside an analytic request; each served u1 equals the oracle's LAPACK TSVD
+    reconstruction (discrepancy rule) on the same device counts, rank for rank, to 1e-6."""
+    rng = np.random.default_rng(101)
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.6, -0.2], [0.1, -0.2, 0.4]])
+    insts = []
+    for k, (g, prec, rm) in enumerate(((_mesh_case("lprism"), wi.FP32_GEOM_FP64_EXIT, wi.RADIUS_MAPPED_EXACT),
+                                       (wi.Geometry(3, wi.TRIMESH, (), (1,), verts=wi.sphere_mesh([0, 0, 0], 1.0, 2)),
+                                        wi.FP64, wi.RADIUS_WOE_BOUND))):
+        ref = wi.element_ref_points(g)
+        g.gamma1_mask = (ref[:, 2] > np.median(ref[:, 2])).astype(np.uint8)
+        x = wi.sample_points(g, 200, rng)
+        inst = wi.Instance(g, K, x, 3000, eps=1e-4, seed=70 + k, instance_id=k, precision=prec, radius_mode=rm,
+                           name=f"mesh{k}")
+        u = wi.random_harmonic_poly(3, K, 3, rng)
+        uD, u0, scale = wi.add_noise(u(x), u(ref[g.gamma1_mask == 0]), 0.02, rng)
+        inst.uD, inst.u0, inst.noise_delta = uD, u0, scale
+        inst.u_exact_g1 = u(ref[g.gamma1_mask == 1])
+        insts.append(inst)
+    box = wi.random_instance(rng, 2, kind_name="cube", walk_scale=0.05)
+    box.x_obs, box.uD = box.x_obs[:200], box.uD[:200]
+    insts.append(box)
+    reqs, res, keep = _requests(wos, insts, np.zeros(len(insts)))
+    out = wos.wos_serve(ctx, reqs, res, max_inflight=3, svd_mode=0)
+    for k, (inst, o) in enumerate(zip(insts, out)):
+        g1 = inst.geom.gamma1_mask.astype(bool)
+        assert o.status == 0 and o.walks == inst.x_obs.shape[0] * inst.n_walks, inst.name
+        counts, _, _ = _gpu(wos, ctx, inst)
+        sigma = ow.element_measures(inst.geom)
+        a = ol.assemble(counts, inst.n_walks, inst.geom.gamma1_mask, sigma, uD=inst.uD, u0=inst.u0)
+        U, s, Vt = ol.svd(a["B"])
+        u1r, rr, _ = ol.reconstruct(U, s, Vt, sigma[g1], a["q"], kind=ol.TSVD_DISCREPANCY,
+                                    delta=inst.noise_delta, tau=1.1)
+        rel = float(np.linalg.norm(keep[6 * k + 5] - u1r) / np.linalg.norm(u1r))
+        print(f"{inst.name}: rank served {o.rank_used} oracle {rr}, u1 rel diff {rel:.2e}")
+        assert o.rank_used == rr and rel <= 1e-6, inst.name
