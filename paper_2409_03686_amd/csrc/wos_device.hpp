@@ -187,7 +187,8 @@ template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b
 // ------------------------------------------------------------------------------------------
 // Triangle meshes.  The surface's triangles sit in a bounding-volume hierarchy stored depth first:
 // a node's first child follows it, `skip` is the node after its subtree, so a search that drops a
-// subtree jumps to `skip` and needs no stack.  Leaves hold up to 7 consecutive triangles.  Boxes are
+// subtree jumps to `skip` and needs no stack.  Leaves hold up to 7 consecutive triangles (the host
+// builds leaves of at most 4).  Boxes are
 // FP32, rounded outward, so they contain their triangles exactly.
 // ------------------------------------------------------------------------------------------
 struct MeshNode {
@@ -306,10 +307,6 @@ __device__ __forceinline__ int mesh_greedy_leaf(GPtr<MeshNode> nodes, const floa
     return i;
 }
 
-// Nearest triangle in FP64: the distance and the original index of the nearest triangle (the lowest
-// among equally near ones, as a scan of all triangles in index order finds).  A subtree is dropped
-// only when its box lies farther than the best distance plus a margin that covers the rounding of
-// both distances, so the search returns exactly what the full scan returns.
 // Result of a nearest-triangle search: the distance, the triangle's original index (FP64 only) and its
 // position in the hierarchy's triangle order (the next search's hint).
 struct MeshHit64 {
@@ -321,10 +318,14 @@ struct MeshHit32 {
     int q;
 };
 
+// Nearest triangle in FP64: the distance and the original index of the nearest triangle (the lowest
+// among equally near ones, as a scan of all triangles in index order finds).  A subtree is dropped
+// only when its box lies farther than the best distance plus a margin that covers the rounding of
+// both distances, so the search returns exactly what the full scan returns.
 // hint >= 0: the triangle (hierarchy position) nearest the walk's previous position, whose distance
 // starts the search in place of the greedy leaf; the result does not depend on it.
 // base: 0 for the surface itself, 4 for the mapped triangles.
-__device__ __attribute__((noinline)) MeshHit64 mesh_dist64(const DevInst &I, int base, double x0, double x1,
+static __device__ __attribute__((noinline)) MeshHit64 mesh_dist64(const DevInst &I, int base, double x0, double x1,
                                                           double x2, int hint)
 {
 #pragma clang fp contract(off)
@@ -400,7 +401,7 @@ __device__ __forceinline__ float tri_dist2_32(const MeshTri32 &T, const float *x
 }
 
 // Distance to the mesh in FP32 (within the FP32 error bound of the instance).
-__device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, int base, float x0, float x1, float x2,
+static __device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, int base, float x0, float x1, float x2,
                                                           int hint)
 {
     const float x[3] = {x0, x1, x2};
@@ -453,7 +454,7 @@ __device__ __attribute__((noinline)) MeshHit32 mesh_dist32(const DevInst &I, int
 // number of the surface about x, from the solid angles of the triangles seen from x (Van Oosterom and
 // Strackee: 2 atan2(A.(B x C), |A||B||C| + (A.B)|C| + (A.C)|B| + (B.C)|A|) for corners A, B, C
 // relative to x), lanes taking every 64th triangle; inside when the total exceeds 2 pi (winding 1/2).
-__device__ __attribute__((noinline)) bool mesh_inside_wave(const DevInst &I, double x0, double x1, double x2)
+static __device__ __attribute__((noinline)) bool mesh_inside_wave(const DevInst &I, double x0, double x1, double x2)
 {
 #pragma clang fp contract(off)
     const double x[3] = {x0, x1, x2};
