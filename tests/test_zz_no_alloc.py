@@ -79,3 +79,19 @@ def test_noalloc_refuses_oversized_descriptor(wos, ctx):
         wos.wos_build_measure_noalloc(ctx, g, w, x, 4, counts)
     torch.cuda.synchronize()
     assert int(counts.sum()) == 0
+
+
+def test_noalloc_small_mesh_matches_allocating_launch(wos, ctx):
+    """A small triangle mesh (the L-prism of 44 triangles) with the mapped-exact radius in FP32: both
+    hierarchies (about 24 KB of records) fit the descriptor, and the allocation-free launch equals the
+    allocating one bit for bit, counts, statistics and traces."""
+    rng = np.random.default_rng(12)
+    g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=wi.l_prism_mesh(2))
+    x = wi.sample_points(g, 24, rng)
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.6, -0.2], [0.1, -0.2, 0.4]])
+    inst = wi.Instance(g, K, x, 800, eps=1e-4, seed=4, precision=wi.FP32_GEOM_FP64_EXIT,
+                       radius_mode=wi.RADIUS_MAPPED_EXACT, name="lprism")
+    ref = _run(wos, ctx, inst, False, wi.FP32_GEOM_FP64_EXIT, True)
+    got = _run(wos, ctx, inst, True, wi.FP32_GEOM_FP64_EXIT, True)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+    assert np.all(got[0].sum(1) == 800)
