@@ -695,8 +695,8 @@ static double domain_scale(const wos_geometry *g)
 
 // Bounding-volume hierarchy of a triangle mesh and its device records, appended to segs (read from
 // HBM, not staged in LDS): the nodes depth first (first child next, `skip` past the subtree), leaves of
-// at most 4 triangles split at the median centroid along the longest axis of the centroids' box; FP32
-// boxes rounded outward; then the FP32 and the FP64 triangle records in leaf order.
+// at most 4 triangles, inner nodes split by the surface-area heuristic; FP32 boxes rounded outward;
+// then the FP32 and the FP64 triangle records in leaf order.
 namespace {
 struct BvhBuild {
     const double *v;
@@ -705,6 +705,82 @@ struct BvhBuild {
     double tri_lo(int t, int k) const { return std::min({v[9 * t + k], v[9 * t + 3 + k], v[9 * t + 6 + k]}); }
     double tri_hi(int t, int k) const { return std::max({v[9 * t + k], v[9 * t + 3 + k], v[9 * t + 6 + k]}); }
     double cen(int t, int k) const { return (v[9 * t + k] + v[9 * t + 3 + k] + v[9 * t + 6 + k]) / 3.0; }
+    // Split of idx[b, e) by the surface-area heuristic over 16 centroid bins per axis: the plane
+    // between bins that minimises area(left box) x count(left) + area(right box) x count(right), the
+    // expected cost of searching the two children; triangles are partitioned by bin (stable, so the
+    // tree does not depend on anything but the input order).  Falls back to the median centroid
+    // along the longest axis when the centroids do not spread.  Returns the first index on the right.
+    int split(int b, int e, const double *clo, const double *chi)
+    {
+        constexpr int kBins = 16;
+        double best = INFINITY;
+        int bax = -1, bcut = 0;
+        auto area = [](const double *lo, const double *hi) {
+            const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+            return dx * dy + dy * dz + dz * dx;
+        };
+        auto bin_of = [&](int t, int ax) {
+            const int bb = static_cast<int>(kBins * (cen(t, ax) - clo[ax]) / (chi[ax] - clo[ax]));
+            return bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
+        };
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!(chi[ax] > clo[ax])) continue;
+            double blo[kBins][3], bhi[kBins][3];
+            int cnt[kBins] = {};
+            for (int q = 0; q < kBins; ++q)
+                for (int k = 0; k < 3; ++k) {
+                    blo[q][k] = INFINITY;
+                    bhi[q][k] = -INFINITY;
+                }
+            for (int q = b; q < e; ++q) {
+                const int t = idx[q], bb = bin_of(t, ax);
+                ++cnt[bb];
+                for (int k = 0; k < 3; ++k) {
+                    blo[bb][k] = std::min(blo[bb][k], tri_lo(t, k));
+                    bhi[bb][k] = std::max(bhi[bb][k], tri_hi(t, k));
+                }
+            }
+            // right-hand boxes and counts for every cut, then a sweep from the left
+            double rlo[kBins][3], rhi[kBins][3];
+            int rc[kBins];
+            for (int q = kBins - 1; q >= 0; --q) {
+                rc[q] = cnt[q] + (q + 1 < kBins ? rc[q + 1] : 0);
+                for (int k = 0; k < 3; ++k) {
+                    rlo[q][k] = std::min(blo[q][k], q + 1 < kBins ? rlo[q + 1][k] : INFINITY);
+                    rhi[q][k] = std::max(bhi[q][k], q + 1 < kBins ? rhi[q + 1][k] : -INFINITY);
+                }
+            }
+            double llo[3] = {INFINITY, INFINITY, INFINITY}, lhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            int lc = 0;
+            for (int cut = 1; cut < kBins; ++cut) {  // bins [0, cut) left, [cut, kBins) right
+                lc += cnt[cut - 1];
+                for (int k = 0; k < 3; ++k) {
+                    llo[k] = std::min(llo[k], blo[cut - 1][k]);
+                    lhi[k] = std::max(lhi[k], bhi[cut - 1][k]);
+                }
+                const int nr = rc[cut];
+                if (lc == 0 || nr == 0) continue;
+                const double cost = area(llo, lhi) * lc + area(rlo[cut], rhi[cut]) * nr;
+                if (cost < best) {
+                    best = cost;
+                    bax = ax;
+                    bcut = cut;
+                }
+            }
+        }
+        if (bax >= 0) {
+            const auto it = std::stable_partition(idx.begin() + b, idx.begin() + e,
+                                                  [&](int t) { return bin_of(t, bax) < bcut; });
+            return static_cast<int>(it - idx.begin());
+        }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+        const int mid = (b + e) / 2;
+        std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e,
+                         [&](int s, int u) { return cen(s, ax) < cen(u, ax) || (cen(s, ax) == cen(u, ax) && s < u); });
+        return mid;
+    }
     void build(int b, int e)
     {
         const int me = static_cast<int>(nodes.size());
@@ -729,12 +805,7 @@ struct BvhBuild {
         if (e - b <= 4) {
             nd.leaf = (b << 3) | (e - b);
         } else {
-            int ax = 0;
-            for (int k = 1; k < 3; ++k)
-                if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
-            const int mid = (b + e) / 2;
-            std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e,
-                             [&](int s, int u) { return cen(s, ax) < cen(u, ax) || (cen(s, ax) == cen(u, ax) && s < u); });
+            const int mid = split(b, e, clo, chi);
             nd.leaf = -1;
             build(b, mid);
             build(mid, e);
