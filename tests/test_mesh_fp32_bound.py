@@ -1,4 +1,4 @@
-"""The FP32 error bound of the triangle-mesh distance: a CPU replay of the device's FP32 operation
+"""The FP32 error bounds of the triangle-mesh distance and mapped-exact radius: a CPU replay of the device's FP32 operation
 sequence (the record's corner, edges, inverse squared lengths, unit normal and in-plane edge normals
 rounded to FP32, fused multiply-adds rounded once) against the oracle's FP64 distance.  The library
 subtracts 2 delta = 2 * 2^-18 L (L the largest coordinate magnitude) from every FP32 radius and
@@ -76,3 +76,30 @@ def test_fp32_mesh_distance_stays_within_its_bound():
         worst = max(worst, err)
     print(f"largest FP32 mesh-distance error: {worst:.2f} units of 2^-24 L")
     assert worst <= 8.0, worst
+
+
+def test_fp32_mapped_mesh_radius_stays_within_its_bound():
+    """The FP32 mapped-exact radius of a mesh: S^{-1} x formed in FP32 (fused multiply-adds on the
+    rounded S^{-1}) and the FP32 distance to the FP32 records of the mapped triangles, against the
+    oracle's FP64 mapped radius.  The library subtracts 2^-17 L_m (L_m the largest mapped coordinate
+    magnitude, 128 units of 2^-24 L_m); the replayed error must stay far below it."""
+    rng = np.random.default_rng(42)
+    K = np.array([[1.0, 0.3, 0.1], [0.3, 0.5, -0.2], [0.1, -0.2, 0.25]])
+    _, _, S = walks.instance_setup(K, 3)
+    Si = np.linalg.inv(S[:3, :3])
+    Sif = Si.astype(f32)
+    worst = 0.0
+    for T in (wi.l_prism_mesh(4), wi.box_mesh([0, 0, 0], [1, 1, 1], 6) + 2.5):
+        g = wi.Geometry(3, wi.TRIMESH, (), (2,), verts=T)
+        MT = T @ Si.T
+        Lm = np.abs(MT).max()
+        x = wi.sample_points(g, 1200, rng)
+        xf = x.astype(f32)
+        y = np.stack([_fma(np.full(len(x), Sif[k, 2]), xf[:, 2],
+                           _fma(np.full(len(x), Sif[k, 1]), xf[:, 1], (Sif[k, 0] * xf[:, 0]).astype(f32)))
+                      for k in range(3)], 1)
+        r32 = _dist32(_records(MT), y)
+        r64 = walks.step_radii(g, S, x, 1)
+        worst = max(worst, np.abs(r32 - r64).max() / (Lm * 2.0 ** -24))
+    print(f"largest FP32 mapped mesh radius error: {worst:.2f} units of 2^-24 L_m")
+    assert worst <= 16.0, worst
