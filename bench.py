@@ -737,7 +737,7 @@ def bench_annulus(a, wos, wi, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
 

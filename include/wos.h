@@ -44,7 +44,7 @@ typedef enum {
     WOS_EDEVICE = 3,    /* a HIP call failed; the context is unusable afterwards */
     WOS_EBUSY = 4,      /* the serving queue is full */
     WOS_ETIMEOUT = 5,   /* a serving request exceeded its time limit */
-    WOS_ENOTSUP = 6,    /* valid request outside what this build supports */
+    WOS_ENOTSUP = 6,    /* valid request outside what the library supports */
     WOS_ECANCELLED = 7  /* a serving request was cancelled */
 } wos_status;
 
