@@ -41,9 +41,10 @@ METRIC = "walks/s & sphere-steps/s (FP32 vs FP64 WoS, ε=1e-4); p50/p99 solve la
 OPS_PER_STEP_2D_FP32 = 20 + 3 + 2 + 1 + 6 + 8 + 4
 # 3D FP32 box with the exact mapped radius: Philox 80 ops per block, one block per 2 steps -> 40;
 # two uniforms (shift, convert, scale) 6; direction z = 1 - 2 u, (1 - z)(1 + z), clamp, sqrt, cos,
-# sin, two products 10; mapped radius min_a min(x_a - lo_a, hi_a - x_a) / |S e_a| 18; shrink 1;
-# x += r S U 12; distance to the six faces 11; exit / band tests and step count 5.
-OPS_PER_STEP_3D_FP32 = 40 + 6 + 10 + 18 + 1 + 12 + 11 + 5
+# sin, two products 10; mapped radius min_a min(x_a - lo_a, hi_a - x_a) / |S e_a|, per axis two
+# differences, their min, one product and the running min: 15; shrink 1; x += r S U 12; distance to
+# the six faces 11; exit / band tests and step count 5.
+OPS_PER_STEP_3D_FP32 = 40 + 6 + 10 + 15 + 1 + 12 + 11 + 5
 # Per walk: FP64 projection onto the boundary, cell index and LDS histogram (2D arc 30; 3D box
 # face selection and patch index 40).
 OPS_PER_WALK_2D, OPS_PER_WALK_3D = 30, 40

@@ -842,10 +842,10 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
             double r_out, r_in = __builtin_inf();
             if constexpr (KIND == kPerfBox) {
                 r_out = __builtin_inf();
-                for (int a = 0; a < DIM; ++a) {
-                    const double lo = (x[a] - I.p[a]) / I.cn[a], hi = (I.p[DIM + a] - x[a]) / I.cn[a];
-                    r_out = lo < r_out ? lo : r_out;
-                    r_out = hi < r_out ? hi : r_out;
+                for (int a = 0; a < DIM; ++a) {  // min of the two gaps first: the same as min of the quotients
+                    const double lo = x[a] - I.p[a], hi = I.p[DIM + a] - x[a];
+                    const double g = (hi < lo ? hi : lo) / I.cn[a];
+                    r_out = g < r_out ? g : r_out;
                 }
             } else {
                 double q = 0.0, a2 = 0.0, v[DIM];
@@ -921,11 +921,14 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ double radius64(
     }
     if constexpr (KIND == kBox) {
         if (I.radius_mode == 1) {
+            // min over axes of min(lo gap, hi gap) / |S e_a|: a correctly rounded division by a positive
+            // number is monotone, so dividing the smaller gap gives min of the two quotients bit for bit
+            // with one division per axis in place of two
             double best = __builtin_inf();
             for (int a = 0; a < DIM; ++a) {
-                const double lo = (x[a] - I.p[a]) / I.cn[a], hi = (I.p[DIM + a] - x[a]) / I.cn[a];
-                best = lo < best ? lo : best;
-                best = hi < best ? hi : best;
+                const double lo = x[a] - I.p[a], hi = I.p[DIM + a] - x[a];
+                const double g = (hi < lo ? hi : lo) / I.cn[a];
+                best = g < best ? g : best;
             }
             return best;
         }
@@ -1002,8 +1005,7 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
                 r_out = __builtin_inff();
 #pragma unroll
                 for (int a = 0; a < DIM; ++a)
-                    r_out = __builtin_fminf(r_out, __builtin_fminf((x[a] - I.pf[a]) * I.icnf[a],
-                                                                   (I.pf[DIM + a] - x[a]) * I.icnf[a]));
+                    r_out = __builtin_fminf(r_out, __builtin_fminf(x[a] - I.pf[a], I.pf[DIM + a] - x[a]) * I.icnf[a]);
             } else {
                 float q, a2;
                 centred_norms32<DIM>(I, x, q, a2);
@@ -1040,8 +1042,8 @@ template <int KIND, int DIM, int RV> __device__ __forceinline__ float radius32(c
             float best = __builtin_inff();
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
-                best = __builtin_fminf(best, __builtin_fminf((x[a] - I.pf[a]) * I.icnf[a],
-                                                             (I.pf[DIM + a] - x[a]) * I.icnf[a]));
+                // the smaller gap times 1 / |S e_a| (rounding is monotone: the same as the smaller product)
+                best = __builtin_fminf(best, __builtin_fminf(x[a] - I.pf[a], I.pf[DIM + a] - x[a]) * I.icnf[a]);
             return best;
         }
     }
